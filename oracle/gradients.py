@@ -1,0 +1,65 @@
+"""Gradients of QAOA <C> for the oracle (test infrastructure).
+
+Two routes:
+  * central finite differences, (f(x+h) - f(x-h)) / 2h in FP64; its
+    truncation error is O(h^2) times the third derivative;
+  * the parameter-shift rule: for a gate exp(-i theta G) with G^2 = I,
+    d/dtheta <O> = <O>(theta + pi/4) - <O>(theta - pi/4) exactly; a QAOA angle
+    enters every ZZ phase (gamma_k) or every X rotation (beta_k) of its layer,
+    so its derivative is the sum of the shifts of each occurrence.
+Both evaluate <C> by brute-force state vectors (statevector.run).
+"""
+import numpy as np
+
+from . import gates, statevector
+
+
+def _cost_from_gates(n, edges, gl):
+    prob = np.abs(statevector.run(n, gl)) ** 2
+    sign = np.array([1.0, -1.0])
+    tot = 0.0
+    for (u, v) in edges:
+        marg = np.moveaxis(prob, [u, v], [0, 1]).reshape(2, 2, -1).sum(axis=2)
+        tot += (1.0 - sign @ marg @ sign) / 2.0
+    return float(tot)
+
+
+def cost(n, edges, params):
+    """<C> for params = (gamma_1..gamma_p, beta_1..beta_p)."""
+    p = len(params) // 2
+    return _cost_from_gates(n, edges, gates.qaoa_gate_list(n, edges, params[:p], params[p:]))
+
+
+def finite_difference(n, edges, params, h=1e-4):
+    params = np.asarray(params, dtype=np.float64)
+    g = np.zeros_like(params)
+    for i in range(len(params)):
+        e = np.zeros_like(params)
+        e[i] = h
+        g[i] = (cost(n, edges, params + e) - cost(n, edges, params - e)) / (2 * h)
+    return g
+
+
+def parameter_shift(n, edges, params):
+    """d<C>/d(gamma_k, beta_k) by shifting every gate occurrence by +-pi/4.
+
+    A gate exp(-i a G) appears in the gate list as ZZ(2a) or R_X(2a), so a
+    shift of a by pi/4 is a shift of the listed angle by pi/2.
+    """
+    p = len(params) // 2
+    base = gates.qaoa_gate_list(n, edges, params[:p], params[p:])
+    g = np.zeros(2 * p)
+    # layer k of the gate list: n H gates, then per layer |E| ZZ and n RX
+    per_layer = len(edges) + n
+    for k in range(p):
+        start = n + k * per_layer
+        for idx in range(start, start + per_layer):
+            kind = base[idx][0]
+            slot = k if kind == "ZZ" else p + k
+            plus = list(base)
+            minus = list(base)
+            kd, q0, q1, th = base[idx]
+            plus[idx] = (kd, q0, q1, th + np.pi / 2)
+            minus[idx] = (kd, q0, q1, th - np.pi / 2)
+            g[slot] += _cost_from_gates(n, edges, plus) - _cost_from_gates(n, edges, minus)
+    return g
