@@ -1,0 +1,217 @@
+/*
+ * qtn.h - C ABI of the MI355X tensor-network contraction library.
+ *
+ * The library contracts the closed tensor network of a quantum circuit (the
+ * method of "qTorch: The quantum tensor contraction handler", Fried, Sawaya
+ * et al.) to one scalar: an output amplitude, an output probability or the
+ * expectation value of a Pauli string. Every pairwise contraction of a fixed
+ * contraction order runs in hand-written gfx950 HIP kernels.
+ *
+ * Conventions used throughout:
+ *  - Complex numbers are interleaved (re, im) doubles on the host.
+ *  - Qubits are numbered 0..n_qubits-1. A two-qubit gate matrix has basis
+ *    index 2*x_q0 + x_q1 (q0 is the most significant bit).
+ *  - Rotations are R_P(theta) = exp(-i theta P / 2), and
+ *    TN_ZZ(theta) = exp(-i theta Z(x)Z / 2). A gate's angle is
+ *    theta = coeff * params[param], or theta = coeff when param == -1.
+ *  - Every function returns TN_OK (0) or a negative error code and leaves the
+ *    object unchanged on error; tn_last_error() then gives a message (per
+ *    thread). No C++ exception crosses this boundary.
+ *  - Ownership: inputs are copied during the call; a tn_net / tn_batch is
+ *    owned by the caller and released with tn_free / tn_batch_free.
+ *  - Host-only functions (build, orders, plan, info) never touch the GPU, so
+ *    they work on machines without one.
+ */
+#ifndef QTN_H
+#define QTN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tn_net tn_net;
+typedef struct tn_batch tn_batch;
+
+/* Error codes. */
+enum {
+  TN_OK = 0,
+  TN_EINVAL = -1,  /* bad argument: qubit out of range, q0 == q1, bad kind, bad param index */
+  TN_ENOMEM = -2,  /* plan exceeds the memory limit, or a device allocation failed; checked before any launch */
+  TN_EORDER = -3,  /* the contraction order is not a permutation of the wire ids, or none is set */
+  TN_EDEVICE = -4, /* a HIP call failed; the object is poisoned afterwards */
+  TN_ESTATE = -5   /* object poisoned by an earlier device error, or used in the wrong state */
+};
+
+/* Gate kinds. */
+enum {
+  TN_H = 0, TN_X = 1, TN_Y = 2, TN_Z = 3,
+  TN_RX = 4, TN_RY = 5, TN_RZ = 6,
+  TN_ZZ = 7,   /* exp(-i theta Z(x)Z / 2), a diagonal 4x4 gate */
+  TN_CNOT = 8, /* control q0, target q1 */
+  TN_CZ = 9,
+  TN_U1 = 10,  /* custom 2x2 matrix (row-major, interleaved re/im) */
+  TN_U2 = 11   /* custom 4x4 matrix (row-major, interleaved re/im) */
+};
+
+typedef struct {
+  int32_t kind;
+  int32_t q0, q1;        /* q1 = -1 for one-qubit gates */
+  int32_t param;         /* index into params[], or -1 for a fixed angle */
+  double coeff;          /* theta = coeff * params[param] (or coeff when param == -1) */
+  const double *matrix;  /* TN_U1 / TN_U2 only: 8 or 32 doubles; copied */
+} tn_gate;
+
+/* What the network computes (Sec. Preliminaries and Sec. "Estimating the
+ * answer string" of the paper: the closed network contracts to one scalar). */
+enum {
+  TN_AMPLITUDE = 0,    /* <x| C |psi0>: single-layer network with dimension-2 wires */
+  TN_PROBABILITY = 1,  /* Tr(Pi rho_out), Pi = (x)_q Pi_q; bits[q] = 0 or 1 projects, 2 traces */
+  TN_EXPECTATION = 2   /* Tr(P rho_out) for the Pauli string pauli[] (0=I 1=X 2=Y 3=Z) */
+};
+
+typedef struct {
+  int32_t mode;
+  const uint8_t *bits;   /* AMPLITUDE / PROBABILITY: one entry per qubit */
+  const uint8_t *pauli;  /* EXPECTATION: one entry per qubit */
+  int32_t lightcone;     /* PROBABILITY / EXPECTATION: 1 = drop gates outside the backward
+                            light cone of the measured qubits (exact for unitary gates) */
+} tn_target;
+
+enum { TN_C64 = 0, TN_C128 = 1 };
+
+/* Build the closed network of a circuit (Sec. Preliminaries: one node per
+ * initial state, gate and measurement; gates in superoperator form, wires of
+ * dimension 4, in PROBABILITY/EXPECTATION mode; gate matrices and
+ * dimension-2 wires in AMPLITUDE mode).
+ *  gates/n_gates: circuit in time order.  init: n_qubits x 2 complex
+ *  (interleaved, 4 doubles per qubit) initial product state, or NULL for |0>.
+ *  n_params: length of the params vector later passed to the contract calls.
+ *  dtype: TN_C64 (complex64 contraction, FP64 final scalars) or TN_C128.
+ *  *out receives a new network without an order. */
+int tn_build(const tn_gate *gates, int32_t n_gates, int32_t n_qubits, const double *init,
+             const tn_target *target, int32_t n_params, int32_t dtype, tn_net **out);
+
+/* Network shape: number of wires and tensors; wire w joins tensors
+ * endpoints[2w] and endpoints[2w+1] (endpoints may be NULL). */
+int tn_wires(const tn_net *net, int32_t *n_wires, int32_t *n_tensors, int32_t *endpoints);
+
+/* Stochastic order (Algorithm 2 of the paper): pick a random remaining wire,
+ * accept it if rank(C) - max(rank(A), rank(B)) <= threshold (ranks in
+ * wires), else count a rejection; after more than max_rej rejections raise
+ * the threshold by one; reset threshold to -1 after each acceptance.
+ * max_rej <= 0 means "number of remaining wires". SplitMix64 seeded by seed.
+ * pi receives n_wires wire ids (wires contracted together with the chosen
+ * one follow it). Host only. */
+int tn_order_stochastic(const tn_net *net, uint64_t seed, int32_t max_rej, int32_t *pi);
+
+/* Line-graph order (Algorithm 1 of the paper): build the line graph L(G) of
+ * the network (wires are vertices, adjacent when they share a tensor) and
+ * eliminate its vertices greedily by minimum fill-in with random
+ * tie-breaks; keep the best of `trials` restarts (or restarts until
+ * budget_s seconds when trials <= 0) by (peak tensor size, flops). Host only. */
+int tn_order_linegraph(const tn_net *net, int32_t trials, double budget_s, uint64_t seed, int32_t *pi);
+
+/* Fix the contraction order: pi must be a permutation of 0..n_wires-1
+ * (TN_EORDER otherwise). Wire pi[i] merges its two end tensors, contracting
+ * every wire they share (eq. (1)); a wire whose ends were already merged is
+ * skipped; scalars of disconnected pieces are multiplied at the end.
+ * Compiles the plan; TN_ENOMEM if its peak exceeds the memory limit. */
+int tn_set_order(tn_net *net, const int32_t *pi, int32_t n);
+
+/* Device-memory limit for one network and one angle set (default 64 GiB). */
+int tn_set_memory_limit(tn_net *net, uint64_t bytes);
+
+typedef struct {
+  int32_t n_steps;          /* pairwise contractions */
+  int32_t n_tensors;        /* leaf tensors */
+  int32_t n_wires;
+  int32_t peak_bits;        /* largest intermediate: log2(entries) */
+  int32_t max_rank_wires;   /* largest intermediate rank counted in wires */
+  int32_t n_components;     /* disconnected pieces (scalars multiplied at the end) */
+  int32_t fused;            /* 1: the whole network runs inside one workgroup (LDS resident) */
+  int32_t lds_bytes;        /* fused executor: LDS bytes per workgroup (forward) */
+  double flops;             /* algorithmic: 8 * 2^(|F_A|+|S|+|F_B|) per step, one angle set */
+  double bytes;             /* algorithmic: e*(|A|+|B|+|C|) per step, one angle set */
+  double peak_live_bytes;   /* largest sum of live intermediates, one angle set */
+} tn_plan_stats;
+
+int tn_plan_info(const tn_net *net, tn_plan_stats *out);
+
+/* Per-step shapes: for step s, dims[3s..3s+2] = (|F_A|, |S|, |F_B|) in bits. */
+int tn_plan_steps(const tn_net *net, int32_t *dims);
+
+/* Contract one network for one parameter vector (host params, n_params
+ * doubles) on the given HIP stream (NULL = default); writes the complex
+ * scalar to out[0..1] (host) and synchronises the stream. One network per
+ * launch sequence: the plain path. */
+int tn_contract(tn_net *net, const double *params, double *out, void *stream);
+
+/* Value and gradient of Re(scalar) with respect to params (host buffers;
+ * grad has n_params entries) by reverse-mode (adjoint) contraction. */
+int tn_grad(tn_net *net, const double *params, double *value, double *grad, void *stream);
+
+/* Batched execution of many networks (each with an order set) over many
+ * parameter vectors. All networks must share n_params and dtype.
+ * coef[i] weights network i in the combined objective
+ *   obj[s] = offset + sum_i coef[i] * Re(scalar_i(params_s))
+ * (QAOA Max-Cut: coef = -1/2, offset = |E|/2). coef may be NULL (all 0).
+ * max_sets bounds n_sets of later calls. */
+int tn_batch_create(tn_net *const *nets, int32_t n_nets, const double *coef, double offset,
+                    int32_t max_sets, tn_batch **out);
+
+/* Forward pass over n_sets parameter vectors. Device pointers:
+ *   params: n_sets x n_params doubles;
+ *   out:    n_nets x n_sets complex scalars (2 doubles each, network-major), may be NULL;
+ *   obj:    n_sets doubles (combined objective), may be NULL.
+ * Asynchronous on `stream`; capturable in a HIP graph. */
+int tn_batch_contract(tn_batch *b, const double *params, int32_t n_sets, double *out, double *obj,
+                      void *stream);
+
+/* Forward plus adjoint gradient (reverse-mode contraction over the same
+ * order, forward intermediates kept as checkpoints): as tn_batch_contract, and
+ *   grad:     n_sets x n_params doubles, d obj[s] / d params[s], may be NULL;
+ *   grad_net: n_nets x n_sets x n_params doubles, d Re(scalar_i) / d params, may be NULL.
+ * The gradient sums run in FP64. */
+int tn_batch_grad(tn_batch *b, const double *params, int32_t n_sets, double *out, double *obj,
+                  double *grad, double *grad_net, void *stream);
+
+/* Replay the forward (with_grad = 0) or forward+gradient (1) pass through a
+ * HIP graph captured on first use for these exact pointers and n_sets. */
+int tn_batch_run_graph(tn_batch *b, int32_t with_grad, const double *params, int32_t n_sets,
+                       double *out, double *obj, double *grad, void *stream);
+
+typedef struct {
+  int32_t n_nets, n_fused, n_level;   /* networks on the fused and the level-synchronous path */
+  int32_t n_levels;                   /* level launches per pass */
+  int32_t lds_bytes_fwd, lds_bytes_grad;
+  double flops_fwd, bytes_fwd;        /* algorithmic, one parameter vector, all networks */
+  double flops_grad, bytes_grad;      /* algorithmic, adjoint sweep only */
+} tn_batch_stats;
+
+int tn_batch_info(const tn_batch *b, tn_batch_stats *out);
+
+/* One-shot conveniences: create a transient batch, run, free. Device pointers. */
+int tn_contract_batch(tn_net *const *nets, int32_t n_nets, const double *params, int32_t n_sets,
+                      double *out, void *stream);
+int tn_grad_batch(tn_net *const *nets, int32_t n_nets, const double *params, int32_t n_sets,
+                  double *out, double *grad_net, void *stream);
+
+/* Fill the parametric superoperator tensors for n_sets parameter vectors
+ * (angle binding) into a device buffer: for each set s and each distinct
+ * parametric tensor t of the network, its entries in canonical wire order.
+ * Returns the number of complex entries per set in *per_set when dst is NULL.
+ * Exposed for testing the binding kernel on its own. */
+int tn_bind_params(tn_net *net, const double *params, int32_t n_sets, void *dst, int64_t *per_set,
+                   void *stream);
+
+void tn_free(tn_net *net);
+void tn_batch_free(tn_batch *b);
+const char *tn_last_error(void);
+const char *tn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -90,21 +90,35 @@ PROJ = {0: np.array([[1, 0], [0, 0]], dtype=np.complex128),
 
 # --- light cone -------------------------------------------------------------
 
+DIAGONAL = {"Z", "RZ", "ZZ", "CZ"}
+
+
 def light_cone(n, gate_list, support):
     """Gates that can influence observables on `support` (a set of qubits).
 
     Walking backwards, a gate with no qubit in the current support is dropped
     (for a unitary gate its superoperator meets trace vectors only and
     contracts to trace vectors); a kept two-qubit gate adds both qubits.
+    Gates diagonal in the computational basis commute, so a run of them is
+    one layer: each is tested against the support at the run's late end.
     Returns (kept gates in circuit order, final support).
     """
     sup = set(support)
     kept = []
-    for g in reversed(gate_list):
-        qs = [g[1]] + ([g[2]] if g[2] >= 0 else [])
-        if any(q in sup for q in qs):
-            kept.append(g)
-            sup.update(qs)
+    i = len(gate_list) - 1
+    while i >= 0:
+        j = i
+        if gate_list[i][0] in DIAGONAL:
+            while j - 1 >= 0 and gate_list[j - 1][0] in DIAGONAL:
+                j -= 1
+        grow = set()
+        for g in reversed(gate_list[j:i + 1]):
+            qs = [g[1]] + ([g[2]] if g[2] >= 0 else [])
+            if any(q in sup for q in qs):
+                kept.append(g)
+                grow.update(qs)
+        sup |= grow
+        i = j - 1
     return kept[::-1], sup
 
 

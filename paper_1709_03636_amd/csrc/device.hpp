@@ -1,0 +1,54 @@
+// Device-side program format shared by the runtime and the kernels.
+#pragma once
+#include <cstdint>
+
+namespace qtn {
+
+// One op of a compiled network program, as the kernels read it (48 bytes).
+// Offsets are in complex elements of the executor's memory (LDS for the
+// fused executor, a per-set global arena for the level executor).
+struct DOp {
+  int32_t type;      // OpType
+  int32_t x, y, z;   // operand / result offsets (OP_SCALAR: z = scalar slot)
+  int32_t nFX, nS, nFY;
+  uint32_t maskX, maskY;
+  int32_t tab;       // offset into the int32 table array
+  int32_t aux0, aux1;
+};
+
+// A parametric tensor to bind: entries of exp(-i theta P / 2) (folded:
+// its superoperator) with theta = coeff * params[param], written at `off`.
+struct DParam {
+  int32_t kind, param, folded, bits;
+  int32_t off, pad;
+  double coeff;
+};
+
+// One network program (forward, or forward + adjoint).
+struct DNet {
+  int32_t op_begin, n_ops;      // into the op array
+  int32_t n_comp;               // component scalars
+  int32_t mem_elems;            // executor memory (elements) incl. leaves
+  int32_t const_begin, n_const; // constant leaf values: global -> [0, n_const)
+  int32_t ptens_begin, n_ptens; // DParam range
+};
+
+
+// Arguments of the fused executor kernel.
+struct FusedArgs {
+  const DNet *nets;
+  const DOp *ops;
+  const int32_t *tabs;
+  const void *consts;
+  const DParam *ptens;
+  const double *params;
+  const int32_t *task_net;  // queue position -> network index (cost order)
+  int *counter;             // work counter, reset before every launch
+  double *out_val;          // [net][set][2]
+  double *out_grad;         // [net][set][n_params] (adjoint programs)
+  int n_params, n_sets, n_tasks;
+  int scratch_off, scal_off, gacc_off, red_off;  // LDS byte offsets
+  int with_grad;
+};
+
+}  // namespace qtn

@@ -1,0 +1,366 @@
+// HIP kernels for gfx950: angle binding, the fused per-workgroup network
+// executor (forward and adjoint), and the FP64 objective combine.
+//
+// Fused executor: one workgroup runs one (network, parameter vector) task
+// at a time from a device work counter (persistent grid). All tensors of the
+// task live in LDS: constant leaves are copied in, parametric leaves are
+// bound from the angles in place, and every pairwise contraction (eq. (1))
+// reads its operands through per-op address maps and writes its result into
+// the LDS arena. Rank-0 results (the last contraction of each component)
+// are accumulated in FP64 with a fixed reduction tree, so results are
+// deterministic.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace qtn {
+
+template <typename T> struct Cplx;
+template <> struct Cplx<float> { using type = float2; };
+template <> struct Cplx<double> { using type = double2; };
+
+__device__ __forceinline__ float2 cmul_add(float2 acc, float2 a, float2 b) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(-a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(a.y, b.x, acc.y);
+  return acc;
+}
+__device__ __forceinline__ double2 cmul_add(double2 acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+template <typename V> __device__ __forceinline__ V from_d2(double2 v);
+template <> __device__ __forceinline__ float2 from_d2<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+template <> __device__ __forceinline__ double2 from_d2<double2>(double2 v) { return v; }
+template <typename V> __device__ __forceinline__ V czero();
+template <> __device__ __forceinline__ float2 czero<float2>() { return make_float2(0.f, 0.f); }
+template <> __device__ __forceinline__ double2 czero<double2>() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// Deposit the low bits of v at the set positions of mask (lowest first).
+__device__ __forceinline__ uint32_t pdep32(uint32_t v, uint32_t mask) {
+  uint32_t r = 0;
+  while (mask) {
+    uint32_t low = mask & (0u - mask);
+    if (v & 1u) r |= low;
+    v >>= 1;
+    mask ^= low;
+  }
+  return r;
+}
+
+// --- parametric tensors ---------------------------------------------------------
+// U(theta) = exp(-i theta P / 2) = c I - i s P with c = cos(theta/2),
+// s = sin(theta/2); dU/dtheta has the same form with (c, s) -> (-s/2, c/2).
+
+// Entry (r, col) of the Pauli (product) of a parametric gate kind.
+__device__ __forceinline__ double2 pauli_rc(int kind, int r, int col) {
+  if (kind == TN_RX) return make_double2(r != col ? 1.0 : 0.0, 0.0);
+  if (kind == TN_RY) return make_double2(0.0, r == col ? 0.0 : (r == 0 ? -1.0 : 1.0));
+  if (kind == TN_RZ) return make_double2(r == col ? (r == 0 ? 1.0 : -1.0) : 0.0, 0.0);
+  // Z(x)Z = diag(1, -1, -1, 1): sign is the parity of the two bits
+  return make_double2(r == col ? (((r ^ (r >> 1)) & 1) ? -1.0 : 1.0) : 0.0, 0.0);
+}
+
+__device__ __forceinline__ double2 u_rc(int kind, int r, int col, double c, double s) {
+  double2 p = pauli_rc(kind, r, col);
+  // c*delta - i*s*(p.x + i p.y) = (c*delta + s*p.y) + i(-s*p.x)
+  return make_double2((r == col ? c : 0.0) + s * p.y, -s * p.x);
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
+
+// Entry `idx` (canonical wire order) of the tensor of a parametric gate:
+// unfolded U, or folded U (x) conj(U) with wires (out..., in...), each wire
+// (ket bit, bra bit). deriv selects d/dtheta.
+__device__ double2 param_entry(int kind, int folded, int idx, double c, double s, bool deriv) {
+  const int nq = kind == TN_ZZ ? 2 : 1;
+  const double dc = -0.5 * s, ds = 0.5 * c;
+  if (!folded) {
+    int r = idx >> nq, col = idx & ((1 << nq) - 1);
+    return deriv ? u_rc(kind, r, col, dc, ds) : u_rc(kind, r, col, c, s);
+  }
+  int rk, rb, ck, cb;  // ket row, bra row, ket col, bra col
+  if (nq == 1) {
+    rk = (idx >> 3) & 1; rb = (idx >> 2) & 1; ck = (idx >> 1) & 1; cb = idx & 1;
+  } else {
+    int a0 = (idx >> 7) & 1, b0 = (idx >> 6) & 1, a1 = (idx >> 5) & 1, b1 = (idx >> 4) & 1;
+    int c0 = (idx >> 3) & 1, d0 = (idx >> 2) & 1, c1 = (idx >> 1) & 1, d1 = idx & 1;
+    rk = 2 * a0 + a1; rb = 2 * b0 + b1; ck = 2 * c0 + c1; cb = 2 * d0 + d1;
+  }
+  double2 uk = u_rc(kind, rk, ck, c, s), ub = conj2(u_rc(kind, rb, cb, c, s));
+  if (!deriv) return cmul(uk, ub);
+  double2 duk = u_rc(kind, rk, ck, dc, ds), dub = conj2(u_rc(kind, rb, cb, dc, ds));
+  double2 t1 = cmul(duk, ub), t2 = cmul(uk, dub);
+  return make_double2(t1.x + t2.x, t1.y + t2.y);
+}
+
+// Angle binding on its own: dst[s][t][e] for every set s and parametric
+// tensor t of one network (entries at ptens[t].off within a set's slice).
+template <typename V>
+__global__ void bind_params_kernel(const DParam *__restrict__ ptens, int n_ptens, const double *__restrict__ params,
+                                   int n_params, int n_sets, int per_set, V *__restrict__ dst) {
+  const int s = blockIdx.y;
+  if (s >= n_sets) return;
+  for (int t = 0; t < n_ptens; ++t) {
+    const DParam d = ptens[t];
+    const double th = d.coeff * params[(size_t)s * n_params + d.param];
+    double sn, cs;
+    sincos(0.5 * th, &sn, &cs);
+    const int ne = 1 << d.bits;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x)
+      dst[(size_t)s * per_set + d.off + e] = from_d2<V>(param_entry(d.kind, d.folded, e, cs, sn, false));
+  }
+}
+
+// --- reductions -------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Fixed-tree block sum; the result is valid in thread 0. red: BLOCK/64 doubles.
+template <int BLOCK>
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  if (BLOCK == 64) return v;
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < BLOCK / 64; ++i) r += red[i];
+  __syncthreads();
+  return r;
+}
+
+// --- fused executor ------------------------------------------------------------------
+
+template <typename T, int BLOCK>
+__device__ __forceinline__ void op_contract(typename Cplx<T>::type *mem, const DOp &op, const int32_t *__restrict__ tb,
+                                            typename Cplx<T>::type *scratch) {
+  using V = typename Cplx<T>::type;
+  const int tid = threadIdx.x;
+  const int lgOut = op.nFX + op.nFY;
+  const int nOut = 1 << lgOut;
+  const int K = 1 << op.nS;
+  const int maskJ = (1 << op.nFY) - 1;
+  const V *X = mem + op.x;
+  const V *Y = mem + op.y;
+  V *Z = mem + op.z;
+  if (nOut >= BLOCK || op.nS == 0) {
+    for (int c = tid; c < nOut; c += BLOCK) {
+      const uint32_t fx = pdep32((uint32_t)c >> op.nFY, op.maskX);
+      const uint32_t fy = pdep32((uint32_t)c & maskJ, op.maskY);
+      V acc = czero<V>();
+      for (int k = 0; k < K; ++k) acc = cmul_add(acc, X[fx + tb[2 * k]], Y[fy + tb[2 * k + 1]]);
+      Z[c] = acc;
+    }
+  } else {
+    // fewer outputs than threads: split the summed index over G groups
+    int lgG = 0;
+    while ((nOut << (lgG + 1)) <= BLOCK && lgG < op.nS) ++lgG;
+    const int G = 1 << lgG;
+    const int c = tid & (nOut - 1);
+    const int g = tid >> lgOut;
+    V acc = czero<V>();
+    if (g < G) {
+      const uint32_t fx = pdep32((uint32_t)c >> op.nFY, op.maskX);
+      const uint32_t fy = pdep32((uint32_t)c & maskJ, op.maskY);
+      for (int k = g; k < K; k += G) acc = cmul_add(acc, X[fx + tb[2 * k]], Y[fy + tb[2 * k + 1]]);
+      scratch[tid] = acc;
+    }
+    __syncthreads();
+    if (tid < nOut) {
+      V s = scratch[tid];
+      for (int gg = 1; gg < G; ++gg) s = cadd(s, scratch[gg * nOut + tid]);
+      Z[tid] = s;
+    }
+  }
+}
+
+template <typename T, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void fused_exec_kernel(FusedArgs a) {
+  using V = typename Cplx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  V *mem = reinterpret_cast<V *>(smem);
+  V *scratch = reinterpret_cast<V *>(smem + a.scratch_off);
+  double2 *scal = reinterpret_cast<double2 *>(smem + a.scal_off);
+  double *gacc = reinterpret_cast<double *>(smem + a.gacc_off);
+  double *red = reinterpret_cast<double *>(smem + a.red_off);
+  __shared__ int s_task;
+  const int tid = threadIdx.x;
+  const V *consts = reinterpret_cast<const V *>(a.consts);
+
+  for (;;) {
+    if (tid == 0) s_task = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int task = __builtin_amdgcn_readfirstlane(s_task);
+    if (task >= a.n_tasks) break;
+    const int ni = __builtin_amdgcn_readfirstlane(a.task_net[task / a.n_sets]);
+    const int set = task % a.n_sets;
+    const DNet net = a.nets[ni];
+
+    for (int e = tid; e < net.n_const; e += BLOCK) mem[e] = consts[net.const_begin + e];
+    const double *prm = a.params + (size_t)set * a.n_params;
+    for (int t = 0; t < net.n_ptens; ++t) {
+      const DParam d = a.ptens[net.ptens_begin + t];
+      const double th = d.coeff * prm[d.param];
+      double sn, cs;
+      sincos(0.5 * th, &sn, &cs);
+      for (int e = tid; e < (1 << d.bits); e += BLOCK) mem[d.off + e] = from_d2<V>(param_entry(d.kind, d.folded, e, cs, sn, false));
+    }
+    if (a.with_grad)
+      for (int p = tid; p < a.n_params; p += BLOCK) gacc[p] = 0.0;
+    __syncthreads();
+
+    for (int o = 0; o < net.n_ops; ++o) {
+      const DOp op = a.ops[net.op_begin + o];
+      const int32_t *tb = a.tabs + op.tab;
+      if (op.type == OP_CONTRACT) {
+        op_contract<T, BLOCK>(mem, op, tb, scratch);
+      } else if (op.type == OP_SCALAR) {
+        const int K = 1 << op.nS;
+        double re = 0.0, im = 0.0;
+        for (int k = tid; k < K; k += BLOCK) {
+          const double2 x = to_d2(mem[op.x + tb[2 * k]]);
+          const double2 y = to_d2(mem[op.y + tb[2 * k + 1]]);
+          re += x.x * y.x - x.y * y.y;
+          im += x.x * y.y + x.y * y.x;
+        }
+        re = block_sum<BLOCK>(re, red);
+        im = block_sum<BLOCK>(im, red);
+        if (tid == 0) scal[op.z] = make_double2(re, im);
+      } else if (op.type == OP_SEED) {
+        if (tid == 0) {
+          double2 p = make_double2(1.0, 0.0);
+          for (int j = 0; j < net.n_comp; ++j)
+            if (j != op.aux0) p = cmul(p, scal[j]);
+          mem[op.z] = from_d2<V>(p);
+        }
+      } else {  // OP_LEAFGRAD
+        const DParam d = a.ptens[op.aux0];
+        const double th = d.coeff * prm[d.param];
+        double sn, cs;
+        sincos(0.5 * th, &sn, &cs);
+        double acc = 0.0;
+        for (int i = tid; i < (1 << op.nFX); i += BLOCK) {
+          const double2 g = to_d2(mem[op.x + i]);
+          const double2 dv = param_entry(d.kind, d.folded, tb[i], cs, sn, true);
+          acc += g.x * dv.x - g.y * dv.y;
+        }
+        acc = block_sum<BLOCK>(acc, red);
+        if (tid == 0) gacc[d.param] += d.coeff * acc;
+      }
+      __syncthreads();
+    }
+
+    if (tid == 0) {
+      double2 p = make_double2(1.0, 0.0);
+      for (int j = 0; j < net.n_comp; ++j) p = cmul(p, scal[j]);
+      double *ov = a.out_val + ((size_t)ni * a.n_sets + set) * 2;
+      ov[0] = p.x;
+      ov[1] = p.y;
+    }
+    if (a.with_grad)
+      for (int p = tid; p < a.n_params; p += BLOCK) a.out_grad[((size_t)ni * a.n_sets + set) * a.n_params + p] = gacc[p];
+    __syncthreads();
+  }
+}
+
+__global__ void reset_counter_kernel(int *c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
+}
+
+// obj[s] = offset + sum_i coef[i] Re(val[i][s]); grad[s][p] = sum_i coef[i] gnet[i][s][p].
+// One workgroup per set, fixed-order FP64 tree.
+__global__ __launch_bounds__(256) void combine_kernel(const double *__restrict__ val, const double *__restrict__ gnet,
+                                                      const double *__restrict__ coef, double offset, int n_nets,
+                                                      int n_sets, int n_params, double *obj, double *grad) {
+  __shared__ double red[4];
+  const int s = blockIdx.x;
+  for (int q = -1; q < n_params; ++q) {
+    if (q < 0 && !obj) continue;
+    if (q >= 0 && !grad) break;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n_nets; i += 256)
+      acc += coef[i] * (q < 0 ? val[((size_t)i * n_sets + s) * 2] : gnet[((size_t)i * n_sets + s) * n_params + q]);
+    acc = block_sum<256>(acc, red);
+    if (threadIdx.x == 0) {
+      if (q < 0) obj[s] = offset + acc;
+      else grad[(size_t)s * n_params + q] = acc;
+    }
+  }
+}
+
+// --- launch helpers (host) ----------------------------------------------------------------
+template <typename T, int BLOCK>
+static hipError_t launch_fused_t(const FusedArgs &a, int grid, int lds_bytes, hipStream_t st) {
+  auto kern = fused_exec_kernel<T, BLOCK>;
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, a.counter);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds_bytes, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(int dtype, int block, const FusedArgs &a, int grid, int lds_bytes, hipStream_t st) {
+  if (dtype == TN_C128) {
+    switch (block) {
+      case 64: return launch_fused_t<double, 64>(a, grid, lds_bytes, st);
+      case 128: return launch_fused_t<double, 128>(a, grid, lds_bytes, st);
+      default: return launch_fused_t<double, 256>(a, grid, lds_bytes, st);
+    }
+  }
+  switch (block) {
+    case 64: return launch_fused_t<float, 64>(a, grid, lds_bytes, st);
+    case 128: return launch_fused_t<float, 128>(a, grid, lds_bytes, st);
+    default: return launch_fused_t<float, 256>(a, grid, lds_bytes, st);
+  }
+}
+
+const void *fused_kernel_ptr(int dtype, int block) {
+  if (dtype == TN_C128) {
+    switch (block) {
+      case 64: return (const void *)fused_exec_kernel<double, 64>;
+      case 128: return (const void *)fused_exec_kernel<double, 128>;
+      default: return (const void *)fused_exec_kernel<double, 256>;
+    }
+  }
+  switch (block) {
+    case 64: return (const void *)fused_exec_kernel<float, 64>;
+    case 128: return (const void *)fused_exec_kernel<float, 128>;
+    default: return (const void *)fused_exec_kernel<float, 256>;
+  }
+}
+
+hipError_t launch_combine(const double *val, const double *gnet, const double *coef, double offset, int n_nets,
+                          int n_sets, int n_params, double *obj, double *grad, hipStream_t st) {
+  hipLaunchKernelGGL(combine_kernel, dim3(n_sets), dim3(256), 0, st, val, gnet, coef, offset, n_nets, n_sets, n_params,
+                     obj, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_bind(int dtype, const DParam *ptens, int n_ptens, const double *params, int n_params, int n_sets,
+                       int per_set, void *dst, hipStream_t st) {
+  dim3 grid(1, n_sets);
+  if (dtype == TN_C128)
+    hipLaunchKernelGGL(bind_params_kernel<double2>, grid, dim3(256), 0, st, ptens, n_ptens, params, n_params, n_sets,
+                       per_set, (double2 *)dst);
+  else
+    hipLaunchKernelGGL(bind_params_kernel<float2>, grid, dim3(256), 0, st, ptens, n_ptens, params, n_params, n_sets,
+                       per_set, (float2 *)dst);
+  return hipGetLastError();
+}
+
+}  // namespace qtn

@@ -1,0 +1,283 @@
+// Plan compiler: a contraction order -> a linear program of pairwise
+// contractions (eq. (1) of the paper) and, for gradients, the reverse-mode
+// (adjoint) program over the same steps.
+//
+// Forward: wire pi[i] merges the two tensors at its ends and sums every
+// label they share; the result keeps the free labels of X (in X's order)
+// followed by the free labels of Y (in Y's order), X being the larger
+// operand. A result without labels is a component scalar, accumulated in
+// FP64. Adjoint: for Z = X . Y with upstream Zbar = d s / d Z (no complex
+// conjugation: the network value is a polynomial in the tensor entries),
+//   Xbar = Zbar . Y  (sums the free labels of Y),
+//   Ybar = X . Zbar  (sums the free labels of X),
+// and at a parametric leaf G, d s / d theta += sum Gbar * dG/dtheta.
+#include <algorithm>
+#include <map>
+
+#include "internal.hpp"
+
+namespace qtn {
+
+namespace {
+
+int find_label(const std::vector<int> &l, int x) {
+  for (size_t i = 0; i < l.size(); ++i)
+    if (l[i] == x) return (int)i;
+  return -1;
+}
+
+// Address bit position of list index i in a tensor of rank r (first = MSB).
+inline int pos_of(int i, int r) { return r - 1 - i; }
+
+struct Emitter {
+  Plan &p;
+  const Net &net;
+  int eb;
+  explicit Emitter(Plan &pl, const Net &n) : p(pl), net(n), eb(n.elem_bytes()) {}
+
+  int new_buf(const std::vector<int> &labels) {
+    p.labels.push_back(labels);
+    p.buf_bits.push_back((int)labels.size());
+    return (int)p.labels.size() - 1;
+  }
+
+  // Emit Z = X . Y summing all shared labels. Returns the new buffer, or -1
+  // for a rank-0 result stored in scalar slot `slot` (when slot >= 0).
+  int contract(int x, int y, bool fwd, int slot_if_scalar, double &flops, double &bytes) {
+    const auto &lx = p.labels[x];
+    const auto &ly = p.labels[y];
+    const int rx = (int)lx.size(), ry = (int)ly.size();
+    std::vector<int> S, FX, FY;
+    for (int l : lx) (find_label(ly, l) >= 0 ? S : FX).push_back(l);
+    for (int l : ly)
+      if (find_label(lx, l) < 0) FY.push_back(l);
+    Op op;
+    op.x = x;
+    op.y = y;
+    op.nFX = (int)FX.size();
+    op.nS = (int)S.size();
+    op.nFY = (int)FY.size();
+    op.fwd = fwd;
+    for (int l : FX) op.maskX_F |= 1u << pos_of(find_label(lx, l), rx);
+    for (int l : FY) op.maskY_F |= 1u << pos_of(find_label(ly, l), ry);
+    // summed index k: bit t is the t-th lowest summed position in X
+    std::sort(S.begin(), S.end(), [&](int a, int b) {
+      return pos_of(find_label(lx, a), rx) < pos_of(find_label(lx, b), rx);
+    });
+    const int K = 1 << op.nS;
+    op.tab.resize(2 * (size_t)K);
+    for (int k = 0; k < K; ++k) {
+      int32_t ox = 0, oy = 0;
+      for (int t = 0; t < op.nS; ++t)
+        if ((k >> t) & 1) {
+          ox |= 1 << pos_of(find_label(lx, S[t]), rx);
+          oy |= 1 << pos_of(find_label(ly, S[t]), ry);
+        }
+      op.tab[2 * k] = ox;
+      op.tab[2 * k + 1] = oy;
+    }
+    std::vector<int> lz = FX;
+    lz.insert(lz.end(), FY.begin(), FY.end());
+    const double e = eb;
+    flops += 8.0 * std::ldexp(1.0, op.nFX + op.nS + op.nFY);
+    bytes += e * (std::ldexp(1.0, op.nFX + op.nS) + std::ldexp(1.0, op.nS + op.nFY) + std::ldexp(1.0, op.nFX + op.nFY));
+    int z;
+    if (lz.empty() && slot_if_scalar >= 0) {
+      op.type = OP_SCALAR;
+      op.z = slot_if_scalar;
+      z = -1;
+    } else {
+      op.type = OP_CONTRACT;
+      z = new_buf(lz);
+      op.z = z;
+    }
+    p.ops.push_back(std::move(op));
+    return z;
+  }
+};
+
+}  // namespace
+
+OrderCost order_cost(const Net &net, const std::vector<int> &pi) {
+  OrderCost c;
+  std::vector<std::vector<int>> tw;
+  for (auto &l : net.leaves) tw.push_back(l.wires);
+  auto ends = net.wire_ends;
+  const int wb = net.wire_bits;
+  for (int w : pi) {
+    int a = ends[w][0], b = ends[w][1];
+    if (a == b) continue;
+    int shared = 0;
+    std::vector<int> cw;
+    for (int x : tw[a]) {
+      if (std::find(tw[b].begin(), tw[b].end(), x) != tw[b].end()) ++shared;
+      else cw.push_back(x);
+    }
+    for (int x : tw[b])
+      if (std::find(tw[a].begin(), tw[a].end(), x) == tw[a].end()) cw.push_back(x);
+    int id = (int)tw.size();
+    int rank = (int)cw.size();
+    c.max_rank_wires = std::max(c.max_rank_wires, rank);
+    c.peak_bits = std::max(c.peak_bits, rank * wb);
+    c.flops += 8.0 * std::ldexp(1.0, wb * ((int)tw[a].size() + (int)tw[b].size() - shared));
+    for (int v : {a, b})
+      for (int x : tw[v])
+        for (int k = 0; k < 2; ++k)
+          if (ends[x][k] == a || ends[x][k] == b) ends[x][k] = id;
+    tw.push_back(std::move(cw));
+  }
+  return c;
+}
+
+int compile_plan(const Net &net, const std::vector<int> &pi, bool with_grad, Plan &plan) {
+  const int W = (int)net.wire_ends.size();
+  if ((int)pi.size() != W) {
+    set_error("tn_set_order: order has " + std::to_string(pi.size()) + " entries, network has " + std::to_string(W) + " wires");
+    return TN_EORDER;
+  }
+  std::vector<char> seen(W, 0);
+  for (int w : pi) {
+    if (w < 0 || w >= W || seen[w]) {
+      set_error("tn_set_order: order is not a permutation of the wire ids");
+      return TN_EORDER;
+    }
+    seen[w] = 1;
+  }
+  plan = Plan();
+  Emitter em(plan, net);
+  const int wb = net.wire_bits;
+  const int L = (int)net.leaves.size();
+  plan.n_leaves = L;
+  for (auto &leaf : net.leaves) {
+    std::vector<int> lab;
+    for (int w : leaf.wires)
+      for (int j = 0; j < wb; ++j) lab.push_back(w * wb + j);
+    em.new_buf(lab);
+  }
+  auto ends = net.wire_ends;
+  double flops = 0, bytes = 0;
+  int n_comp = 0;
+  for (int w : pi) {
+    int a = ends[w][0], b = ends[w][1];
+    if (a == b) continue;
+    int x = a, y = b;
+    if (plan.buf_bits[b] > plan.buf_bits[a]) std::swap(x, y);
+    // every wire of both operands (shared ones included) now ends at the
+    // result, so later entries of pi for the shared wires are skipped
+    std::vector<int> touched;
+    for (int v : {a, b})
+      for (int l : plan.labels[v]) touched.push_back(l / wb);
+    int z = em.contract(x, y, true, n_comp, flops, bytes);
+    const Op &op = plan.ops.back();
+    plan.step_dims.push_back({op.nFX, op.nS, op.nFY});
+    int zid = z;
+    if (z < 0) {
+      plan.comp_root_step.push_back((int)plan.ops.size() - 1);
+      zid = -2 - n_comp;  // component marker: never a buffer id
+      ++n_comp;
+    } else {
+      plan.peak_bits = std::max(plan.peak_bits, plan.buf_bits[z]);
+    }
+    for (int wire : touched)
+      for (int k = 0; k < 2; ++k)
+        if (ends[wire][k] == a || ends[wire][k] == b) ends[wire][k] = zid;
+  }
+  if (n_comp == 0 && L > 0) {
+    set_error("tn_set_order: order leaves no scalar (internal)");
+    return TN_EORDER;
+  }
+  plan.n_components = n_comp;
+  plan.n_fwd_ops = (int)plan.ops.size();
+  plan.n_steps = plan.n_fwd_ops;
+  plan.flops = flops;
+  plan.bytes = bytes;
+  plan.max_rank_wires = plan.peak_bits / wb;
+
+  // peak of live intermediates (forward): freed after their consumer
+  {
+    std::vector<int> last(plan.labels.size(), -1);
+    for (int i = 0; i < plan.n_fwd_ops; ++i) {
+      last[plan.ops[i].x] = i;
+      last[plan.ops[i].y] = i;
+    }
+    double live = 0, peak = 0;
+    const double e = net.elem_bytes();
+    for (int i = 0; i < plan.n_fwd_ops; ++i) {
+      const Op &op = plan.ops[i];
+      if (op.type == OP_CONTRACT) live += e * std::ldexp(1.0, plan.buf_bits[op.z]);
+      peak = std::max(peak, live);
+      for (int v : {op.x, op.y})
+        if (v >= L && last[v] == i) live -= e * std::ldexp(1.0, plan.buf_bits[v]);
+    }
+    plan.peak_live_bytes = peak;
+  }
+
+  if (!with_grad) return TN_OK;
+
+  // --- adjoint program ---------------------------------------------------------
+  const int NB = (int)plan.labels.size();
+  std::vector<char> needs(NB, 0);
+  for (int v = 0; v < L; ++v) needs[v] = net.leaves[v].src < 0;
+  for (int i = 0; i < plan.n_fwd_ops; ++i) {
+    const Op &op = plan.ops[i];
+    if (op.type == OP_CONTRACT) needs[op.z] = needs[op.x] || needs[op.y];
+  }
+  // seeds: d(prod_j s_j)/d s_j = prod_{i != j} s_i, one rank-0 buffer each
+  for (int j = 0; j < n_comp; ++j) {
+    Op op;
+    op.type = OP_SEED;
+    op.x = op.y = -1;
+    op.nFX = op.nS = op.nFY = 0;
+    op.aux0 = j;
+    op.fwd = false;
+    op.z = em.new_buf({});
+    plan.seed_buf.push_back(op.z);
+    plan.ops.push_back(op);
+  }
+  std::map<int, int> adj;  // forward buffer -> its adjoint buffer
+  double gflops = 0, gbytes = 0;
+  auto leafgrad = [&](int leaf, int gbar) {
+    const Leaf &lf = net.leaves[leaf];
+    const auto &canon = plan.labels[leaf];
+    const auto &lg = plan.labels[gbar];
+    const int r = (int)canon.size();
+    Op op;
+    op.type = OP_LEAFGRAD;
+    op.x = gbar;
+    op.y = leaf;
+    op.z = -1;
+    op.nFX = r;
+    op.nS = op.nFY = 0;
+    op.aux0 = -lf.src - 1;
+    op.aux1 = leaf;
+    op.fwd = false;
+    op.tab.resize((size_t)1 << r);
+    for (int idx = 0; idx < (1 << r); ++idx) {
+      int ci = 0;
+      for (int i = 0; i < r; ++i)
+        if ((idx >> pos_of(i, r)) & 1) ci |= 1 << pos_of(find_label(canon, lg[i]), r);
+      op.tab[idx] = ci;
+    }
+    plan.ops.push_back(std::move(op));
+  };
+  for (int i = plan.n_fwd_ops - 1; i >= 0; --i) {
+    const Op fop = plan.ops[i];  // copy: ops grows below
+    if (fop.type == OP_CONTRACT && !needs[fop.z]) continue;  // no parameter below this result
+    int zbar = fop.type == OP_SCALAR ? plan.seed_buf[fop.z] : adj.at(fop.z);
+    if (needs[fop.x]) {
+      int xb = em.contract(zbar, fop.y, false, -1, gflops, gbytes);
+      adj[fop.x] = xb;
+      if (fop.x < L) leafgrad(fop.x, xb);
+    }
+    if (needs[fop.y]) {
+      int yb = em.contract(fop.x, zbar, false, -1, gflops, gbytes);
+      adj[fop.y] = yb;
+      if (fop.y < L) leafgrad(fop.y, yb);
+    }
+  }
+  plan.flops_grad = gflops;
+  plan.bytes_grad = gbytes;
+  return TN_OK;
+}
+
+}  // namespace qtn

@@ -1,0 +1,237 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: complex128 path vs the oracle 1e-12 (values) and 1e-10
+(gradients); complex64 path (FP32 contraction, FP64 final scalars and
+gradient sums) 1e-5 absolute for <Z_u Z_v>, probabilities and amplitudes
+(scaled by the largest magnitude), 1e-5 relative for <C>, and
+1e-4 * max(1, |g|) for gradients.
+"""
+import itertools
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from helpers import random_param_circuit
+from oracle import closed_form, gradients, statevector
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1709_03636_amd import qtn
+    qtn.lib()  # loud failure when the library is not built
+
+
+def _qtn():
+    from paper_1709_03636_amd import qtn
+    return qtn
+
+
+def _qaoa():
+    from paper_1709_03636_amd import qaoa
+    return qaoa
+
+
+# --- the 12-vertex 3-regular p=1 instance at gamma=0.4, beta=0.3 --------------------
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-12), ("c64", 1e-5)])
+def test_config1_per_edge(dtype, tol):
+    qtn, qaoa = _qtn(), _qaoa()
+    dt = qtn.TN_C128 if dtype == "c128" else qtn.TN_C64
+    e = workloads.random_regular_graph(3, 12, 0)
+    ref = statevector.qaoa_zz(12, e, [0.4], [0.3])
+    nets = qaoa.edge_networks(12, e, 1, dt, order="stochastic", seed=0)
+    got = []
+    for i, net in enumerate(nets):
+        _say(f"config1 {dtype} edge {i} {e[i]}")
+        z = net.contract([0.4, 0.3])
+        got.append(z)
+    got = np.array(got)
+    assert np.max(np.abs(got.real - ref)) < tol
+    assert np.max(np.abs(got.imag)) < tol
+    c_gpu = float(np.sum((1 - got.real) / 2))
+    c_ref = float(np.sum((1 - ref) / 2))
+    assert abs(c_gpu - c_ref) <= tol * max(1.0, abs(c_ref))
+
+
+# --- random circuits in all three modes ---------------------------------------------------
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-12), ("c64", 2e-5)])
+@pytest.mark.parametrize("seed", range(4))
+def test_random_circuit_expectation(dtype, tol, seed):
+    qtn = _qtn()
+    dt = qtn.TN_C128 if dtype == "c128" else qtn.TN_C64
+    n = 5
+    prod, og, prm = random_param_circuit(n, 18, seed)
+    psi = statevector.run(n, og(prm))
+    rng = workloads.SplitMix64(seed)
+    for t in range(3):
+        pauli = [rng.below(4) for _ in range(n)]
+        if not any(pauli):
+            pauli[0] = 3
+        ref = statevector.expect_pauli(psi, pauli)
+        for lc in (True, False):
+            _say(f"expect {dtype} seed {seed} pauli {pauli} lc {lc}")
+            net = qtn.Network(n, prod, qtn.TN_EXPECTATION, pauli, n_params=len(prm), dtype=dt, lightcone=lc)
+            net.set_order(net.order_stochastic(seed + t))
+            got = net.contract(prm)
+            assert abs(got - ref) < tol, (got, ref)
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-12), ("c64", 2e-5)])
+@pytest.mark.parametrize("seed", range(3))
+def test_random_circuit_amplitude_probability(dtype, tol, seed):
+    qtn = _qtn()
+    dt = qtn.TN_C128 if dtype == "c128" else qtn.TN_C64
+    n = 4
+    prod, og, prm = random_param_circuit(n, 14, 100 + seed)
+    init = [np.array(workloads.random_unitary(2, 50 + q))[:, 0] for q in range(n)]
+    psi = statevector.run(n, og(prm), statevector.product_state(init))
+    scale = np.abs(psi).max()
+    for bits in itertools.product(range(2), repeat=n):
+        _say(f"amp/prob {dtype} seed {seed} bits {bits}")
+        na = qtn.Network(n, prod, qtn.TN_AMPLITUDE, bits, n_params=len(prm), init=np.concatenate(init), dtype=dt)
+        na.set_order(na.order_linegraph(trials=2, seed=seed))
+        a = na.contract(prm)
+        assert abs(a - psi[bits]) < tol * max(1.0, scale), (a, psi[bits])
+        npb = qtn.Network(n, prod, qtn.TN_PROBABILITY, bits, n_params=len(prm), init=np.concatenate(init), dtype=dt)
+        npb.set_order(npb.order_stochastic(seed))
+        pr = npb.contract(prm)
+        assert abs(pr - abs(psi[bits]) ** 2) < tol
+    # marginal of qubit 1 (others traced)
+    for b in range(2):
+        bits = [2, b, 2, 2]
+        net = qtn.Network(n, prod, qtn.TN_PROBABILITY, bits, n_params=len(prm), init=np.concatenate(init), dtype=dt)
+        net.set_order(net.order_stochastic(1))
+        ref = float(np.sum(np.abs(psi[:, b]) ** 2))
+        assert abs(net.contract(prm) - ref) < tol
+
+
+# --- gradients ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_grad_p1_vs_parameter_shift(dtype):
+    qtn, qaoa = _qtn(), _qaoa()
+    dt = qtn.TN_C128 if dtype == "c128" else qtn.TN_C64
+    e = workloads.random_regular_graph(3, 10, 4)
+    params = [0.37, 0.81]
+    ps = gradients.parameter_shift(10, e, params)
+    c_ref = gradients.cost(10, e, params)
+    nets = qaoa.edge_networks(10, e, 1, dt, order="linegraph")
+    tot_v, tot_g = 0.0, np.zeros(2)
+    for i, net in enumerate(nets):
+        _say(f"grad p1 {dtype} edge {i}")
+        v, g = net.grad(params)
+        tot_v += (1 - v) / 2
+        tot_g += -0.5 * g
+    vt, gt = (1e-12, 1e-10) if dtype == "c128" else (1e-5, 1e-4)
+    assert abs(tot_v - c_ref) <= vt * max(1, abs(c_ref))
+    assert np.max(np.abs(tot_g - ps)) <= gt * max(1, np.abs(ps).max())
+
+
+def test_grad_p2_vs_parameter_shift_c128():
+    qtn, qaoa = _qtn(), _qaoa()
+    e = workloads.random_regular_graph(3, 8, 6)
+    params = workloads.qaoa_angles(6, 1, 2)[0]
+    ps = gradients.parameter_shift(8, e, params)
+    nets = qaoa.edge_networks(8, e, 2, qtn.TN_C128, order="stochastic", seed=3)
+    tot_g = np.zeros(4)
+    for i, net in enumerate(nets):
+        _say(f"grad p2 c128 edge {i}")
+        _, g = net.grad(params)
+        tot_g += -0.5 * g
+    assert np.max(np.abs(tot_g - ps)) <= 1e-10 * max(1, np.abs(ps).max())
+
+
+# --- batched path --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_p1_closed_form(dtype):
+    qtn, qaoa = _qtn(), _qaoa()
+    dt = qtn.TN_C128 if dtype == "c128" else qtn.TN_C64
+    n, d = 30, 4
+    e = workloads.random_regular_graph(d, n, 2)
+    S = 16
+    ang = np.array(workloads.qaoa_angles(9, S, 1))
+    _say(f"batch p1 {dtype} n={n} d={d} S={S}")
+    model = qaoa.MaxCut(n, e, 1, dt, order="linegraph", max_sets=S)
+    out = torch.empty((len(e), S, 2), dtype=torch.float64, device="cuda")
+    obj, grad = model.value_and_grad(torch.tensor(ang, device="cuda"), out=out)
+    torch.cuda.synchronize()
+    out, obj, grad = out.cpu().numpy(), obj.cpu().numpy(), grad.cpu().numpy()
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    for s in range(S):
+        zz = closed_form.zz_p1(n, e, ang[s, 0], ang[s, 1])
+        assert np.max(np.abs(out[:, s, 0] - zz)) < tol
+        c_ref = float(np.sum((1 - zz) / 2))
+        assert abs(obj[s] - c_ref) <= tol * max(1, c_ref)
+        dg, db = closed_form.zz_p1_grad(n, e, ang[s, 0], ang[s, 1])
+        g_ref = np.array([-0.5 * dg.sum(), -0.5 * db.sum()])
+        gt = 1e-10 if dtype == "c128" else 1e-4
+        assert np.max(np.abs(grad[s] - g_ref)) <= gt * max(1, np.abs(g_ref).max())
+
+
+def test_batch_forward_matches_grad_pass_and_graph_replay():
+    qtn, qaoa = _qtn(), _qaoa()
+    n = 16
+    e = workloads.random_regular_graph(3, n, 5)
+    S = 8
+    ang = torch.tensor(workloads.qaoa_angles(5, S, 2), device="cuda", dtype=torch.float64)
+    model = qaoa.MaxCut(n, e, 2, qtn.TN_C64, order="stochastic", max_sets=S)
+    _say("batch eager fwd / grad")
+    obj_f = model.expectation(ang)
+    obj_g, grad_g = model.value_and_grad(ang)
+    torch.cuda.synchronize()
+    ref = np.array([gradients.cost(n, e, list(a)) for a in ang.cpu().numpy()])
+    assert np.max(np.abs(obj_f.cpu().numpy() - ref)) <= 1e-5 * max(1, np.abs(ref).max())
+    assert np.max(np.abs(obj_g.cpu().numpy() - ref)) <= 1e-5 * max(1, np.abs(ref).max())
+    st = torch.cuda.Stream()
+    obj = torch.empty(S, dtype=torch.float64, device="cuda")
+    grad = torch.empty((S, 4), dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        _say(f"graph replay {rep}")
+        obj.zero_()
+        grad.zero_()
+        st.wait_stream(torch.cuda.current_stream())
+        model.batch.run_graph(True, ang, obj=obj, grad=grad, stream=st)
+        st.synchronize()
+        torch.cuda.synchronize()
+        assert np.max(np.abs(obj.cpu().numpy() - ref)) <= 1e-5 * max(1, np.abs(ref).max())
+        assert np.max(np.abs(grad.cpu().numpy() - grad_g.cpu().numpy())) <= 1e-6
+        _ = (ang * 2).sum().item()  # eager work between replays
+
+
+def test_bind_params_kernel():
+    """Angle binding on its own: RX and ZZ superoperators vs their definitions."""
+    qtn, qaoa = _qtn(), _qaoa()
+    e = [(0, 1)]
+    net = qaoa.edge_network(2, e, 1, e[0], dtype=qtn.TN_C128)
+    per = net.bind_params(None, 0)
+    S = 3
+    ang = torch.tensor([[0.3, 0.7], [1.1, -0.4], [2.0, 0.25]], dtype=torch.float64, device="cuda")
+    out = torch.zeros((S, per, 2), dtype=torch.float64, device="cuda")
+    _say("bind params")
+    net.bind_params(ang, S, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    got = got[..., 0] + 1j * got[..., 1]
+    from oracle import gates as og, tensornet as tn
+    for s in range(S):
+        g, b = ang[s].cpu().numpy()
+        zz = tn.superop_2q(og.zz(2 * g)).ravel()
+        rx = tn.superop_1q(og.rot(og.X, 2 * b)).ravel()
+        np.testing.assert_allclose(got[s][:256], zz, atol=1e-14)
+        np.testing.assert_allclose(got[s][256:], rx, atol=1e-14)

@@ -1,0 +1,179 @@
+"""Host-side logic of the C-ABI library (no GPU calls): exports, network
+construction, light cone, orders (Algorithms 1 and 2), plan shapes and
+error paths."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def qtn():
+    from paper_1709_03636_amd import qtn as q
+    q.lib()
+    return q
+
+
+@pytest.fixture(scope="module")
+def qaoa():
+    from paper_1709_03636_amd import qaoa as m
+    return m
+
+
+def test_library_exports_every_declared_symbol(qtn):
+    hdr = open(os.path.join(ROOT, "include", "qtn.h")).read()
+    names = set(re.findall(r"^\s*(?:int|void|const char \*)\s*(tn_\w+)\s*\(", hdr, re.M))
+    assert len(names) >= 20
+    L = qtn.lib()
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    assert b"gfx950" in L.tn_version()
+
+
+def test_qaoa_p1_network_shape(qtn, qaoa):
+    # triangle-free edge of a 3-regular graph: 6 boundary vectors, 5 ZZ, 2 RX, 6 measurements
+    e = workloads.random_regular_graph(3, 100, 0)
+    net = qaoa.edge_network(100, e, 1, e[0])
+    nw, nt, ends = net.wires()
+    assert (nt, nw) == (19, 18)
+    # closed network: every wire joins two distinct tensors
+    assert np.all(ends >= 0) and np.all(ends[:, 0] != ends[:, 1])
+
+
+def test_lightcone_off_keeps_everything(qtn, qaoa):
+    e = workloads.random_regular_graph(3, 8, 1)
+    net = qaoa.edge_network(8, e, 1, e[0], lightcone=False)
+    nw, nt, _ = net.wires()
+    assert nt == 8 + len(e) + 8 + 8
+
+
+def test_stochastic_order_is_permutation_and_deterministic(qtn, qaoa):
+    e = workloads.random_regular_graph(3, 20, 3)
+    net = qaoa.edge_network(20, e, 2, e[4])
+    a = net.order_stochastic(7)
+    b = net.order_stochastic(7)
+    c = net.order_stochastic(8)
+    assert sorted(a) == list(range(net.n_wires))
+    assert np.array_equal(a, b)
+    assert not np.array_equal(a, c)
+
+
+def _simulate_alg2_costs(ends, n_tensors, pi):
+    """Replays an order at the wire level and returns the cost of each merge."""
+    tw = [set() for _ in range(n_tensors)]
+    for w, (x, y) in enumerate(ends):
+        tw[x].add(w)
+        tw[y].add(w)
+    owner = {w: [x, y] for w, (x, y) in enumerate(ends)}
+    costs = []
+    for w in pi:
+        a, b = owner[w]
+        if a == b:
+            continue
+        sh = tw[a] & tw[b]
+        rc = len(tw[a]) + len(tw[b]) - 2 * len(sh)
+        costs.append(rc - max(len(tw[a]), len(tw[b])))
+        new = (tw[a] | tw[b]) - sh
+        tw.append(new)
+        nid = len(tw) - 1
+        for x in tw[a] | tw[b]:
+            owner[x] = [nid if t in (a, b) else t for t in owner[x]]
+    return costs
+
+
+def test_stochastic_order_prefers_cheap_merges(qtn, qaoa):
+    """Alg. 2 accepts a merge only when its cost is <= the threshold, which
+    restarts at -1 after every acceptance: the first merge must have cost -1
+    (a boundary vector absorbed), and most merges are non-increasing."""
+    e = workloads.random_regular_graph(4, 20, 2)
+    net = qaoa.edge_network(20, e, 2, e[0])
+    nw, nt, ends = net.wires()
+    pi = net.order_stochastic(0)
+    costs = _simulate_alg2_costs(ends, nt, pi)
+    assert costs[0] == -1
+    assert sum(c <= 0 for c in costs) >= 0.7 * len(costs)
+
+
+def test_linegraph_order_quality(qtn, qaoa):
+    e = workloads.random_regular_graph(5, 50, 0)
+    net = qaoa.edge_network(50, e, 2, e[0])
+    pi = net.order_linegraph(trials=4, seed=1)
+    assert sorted(pi) == list(range(net.n_wires))
+    net.set_order(pi)
+    lg = net.plan_info()
+    # min-fill on the line graph keeps the peak far below the full light cone
+    assert lg["peak_bits"] <= 20
+    assert lg["n_steps"] == lg["n_tensors"] - lg["n_components"]
+
+
+def test_plan_shapes_and_flops(qtn, qaoa):
+    """Eq. (1): C has rank x+z and costs m^(x+y+z) multiply-adds (m = 4 per wire = 2 bits)."""
+    e = workloads.random_regular_graph(3, 12, 0)
+    net = qaoa.edge_network(12, e, 1, e[0])
+    net.set_order(net.order_stochastic(0))
+    info = net.plan_info()
+    dims = net.plan_steps()
+    assert len(dims) == info["n_steps"] == 18
+    flops = sum(8.0 * 2 ** int(d.sum()) for d in dims)
+    assert flops == info["flops"]
+    byts = sum(8.0 * (2 ** int(d[0] + d[1]) + 2 ** int(d[1] + d[2]) + 2 ** int(d[0] + d[2])) for d in dims)
+    assert byts == info["bytes"]
+    assert info["peak_bits"] == max(int(d[0] + d[2]) for d in dims)
+    assert np.all(dims % 2 == 0)  # folded network: whole wires only
+    assert dims[-1][0] == 0 and dims[-1][2] == 0  # last step: scalar
+
+
+def test_error_paths(qtn):
+    with pytest.raises(qtn.QtnError) as ei:
+        qtn.Network(2, [("ZZ", 0, 0, -1, 0.3)], qtn.TN_EXPECTATION, [3, 3])
+    assert ei.value.code == qtn.TN_EINVAL
+    with pytest.raises(qtn.QtnError) as ei:
+        qtn.Network(2, [("RX", 5, -1, -1, 0.3)], qtn.TN_EXPECTATION, [3, 3])
+    assert ei.value.code == qtn.TN_EINVAL
+    with pytest.raises(qtn.QtnError) as ei:
+        qtn.Network(2, [("RX", 0, -1, 3, 0.3)], qtn.TN_EXPECTATION, [3, 3], n_params=2)
+    assert ei.value.code == qtn.TN_EINVAL
+    net = qtn.Network(2, [("H", 0, -1, -1, 0.0), ("CNOT", 0, 1, -1, 0.0)], qtn.TN_EXPECTATION, [3, 3])
+    nw = net.n_wires
+    with pytest.raises(qtn.QtnError) as ei:
+        net.set_order([0] * nw)
+    assert ei.value.code == qtn.TN_EORDER
+    with pytest.raises(qtn.QtnError) as ei:
+        net.set_order(list(range(nw - 1)))
+    assert ei.value.code == qtn.TN_EORDER
+    with pytest.raises(qtn.QtnError) as ei:
+        net.plan_info()
+    assert ei.value.code == qtn.TN_EORDER
+    net.set_memory_limit(16)
+    with pytest.raises(qtn.QtnError) as ei:
+        net.set_order(net.order_stochastic(0))
+    assert ei.value.code == qtn.TN_ENOMEM
+    net.set_memory_limit(1 << 30)
+    net.set_order(net.order_stochastic(0))
+    assert net.plan_info()["n_steps"] > 0
+
+
+def test_parallel_wires_are_contracted_once(qtn):
+    # two gates on the same pair of qubits create tensors joined by two wires
+    gates = [("CNOT", 0, 1, -1, 0.0), ("CZ", 0, 1, -1, 0.0), ("H", 0, -1, -1, 0.0)]
+    net = qtn.Network(2, gates, qtn.TN_EXPECTATION, [3, 1], lightcone=False)
+    nw, nt, _ = net.wires()
+    for seed in range(5):
+        net.set_order(net.order_stochastic(seed))
+        info = net.plan_info()
+        assert info["n_steps"] == nt - info["n_components"]
+    net.set_order(list(range(nw))[::-1])
+    assert net.plan_info()["n_steps"] == nt - net.plan_info()["n_components"]
+
+
+def test_disconnected_components(qtn):
+    # no two-qubit gates: every qubit is its own component
+    gates = [("RX", q, -1, -1, 0.1 * (q + 1)) for q in range(3)]
+    net = qtn.Network(3, gates, qtn.TN_EXPECTATION, [3, 0, 1], lightcone=False)
+    net.set_order(net.order_linegraph(trials=1))
+    assert net.plan_info()["n_components"] == 3
