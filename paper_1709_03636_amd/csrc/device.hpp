@@ -43,7 +43,7 @@ struct FusedArgs {
   const DParam *ptens;
   const double *params;
   const int32_t *task_net;  // queue position -> network index (cost order)
-  int *counter;             // work counter, reset before every launch
+  int *counter;             // [2]: work counter, exit counter (zero between launches)
   double *out_val;          // [net][set][2]
   double *out_grad;         // [net][set][n_params] (adjoint programs)
   int n_params, n_sets, n_tasks;

@@ -278,10 +278,17 @@ __global__ __launch_bounds__(BLOCK) void fused_exec_kernel(FusedArgs a) {
       for (int p = tid; p < a.n_params; p += BLOCK) a.out_grad[((size_t)ni * a.n_sets + set) * a.n_params + p] = gacc[p];
     __syncthreads();
   }
-}
-
-__global__ void reset_counter_kernel(int *c) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
+  // The last workgroup to leave returns both counters to zero for the next
+  // launch: every workgroup has made its final claim on counter[0] before it
+  // counts itself out on counter[1].
+  if (tid == 0) {
+    __threadfence();
+    const int done = atomicAdd(a.counter + 1, 1);
+    if (done == (int)gridDim.x - 1) {
+      atomicExch(a.counter, 0);
+      atomicExch(a.counter + 1, 0);
+    }
+  }
 }
 
 // obj[s] = offset + sum_i coef[i] Re(val[i][s]); grad[s][p] = sum_i coef[i] gnet[i][s][p].
@@ -309,7 +316,6 @@ __global__ __launch_bounds__(256) void combine_kernel(const double *__restrict__
 template <typename T, int BLOCK>
 static hipError_t launch_fused_t(const FusedArgs &a, int grid, int lds_bytes, hipStream_t st) {
   auto kern = fused_exec_kernel<T, BLOCK>;
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, a.counter);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds_bytes, st, a);
   return hipGetLastError();
 }

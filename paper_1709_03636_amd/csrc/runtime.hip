@@ -353,7 +353,8 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   if ((e = dalloc(&b->d_task_net, b->task_net.size())) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc((char **)&b->d_consts, hp.consts.size() / 2 * eb)) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_ptens, hp.ptens.size())) != hipSuccess) return fail(e, "hipMalloc");
-  if ((e = dalloc(&b->d_counter, 1)) != hipSuccess) return fail(e, "hipMalloc");
+  if ((e = dalloc(&b->d_counter, 2)) != hipSuccess) return fail(e, "hipMalloc");
+  if ((e = hipMemset(b->d_counter, 0, 2 * sizeof(int))) != hipSuccess) return fail(e, "hipMemset");
   if ((e = dalloc(&b->d_val, (size_t)n_nets * max_sets * 2)) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_gnet, (size_t)n_nets * max_sets * std::max(1, b->n_params))) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_coef, (size_t)n_nets)) != hipSuccess) return fail(e, "hipMalloc");
