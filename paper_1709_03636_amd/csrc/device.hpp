@@ -16,11 +16,15 @@ struct DOp {
   int32_t aux0, aux1;
 };
 
-// A parametric tensor to bind: entries of exp(-i theta P / 2) (folded:
-// its superoperator) with theta = coeff * params[param], written at `off`.
+// A parametric tensor: entries of exp(-i theta P / 2) (folded: its
+// superoperator) with theta = coeff * params[param]. In the binding kernel
+// `off` is its offset in a parameter vector's slice of the bound-tensor
+// buffer; in a network program `off` is its place in executor memory,
+// `goff` that of its adjoint accumulator and `slot` its offset in the
+// bound-tensor slice.
 struct DParam {
   int32_t kind, param, folded, bits;
-  int32_t off, pad;
+  int32_t off, goff, slot, pad;
   double coeff;
 };
 
@@ -41,14 +45,22 @@ struct FusedArgs {
   const int32_t *tabs;
   const void *consts;
   const DParam *ptens;
-  const double *params;
+  const void *bound;        // [set][per_set] parametric tensors (binding kernel output)
+  const void *dbound;       // [set][per_set] their angle derivatives (adjoint programs)
   const int32_t *task_net;  // queue position -> network index (cost order)
-  int *counter;             // [2]: work counter, exit counter (zero between launches)
   double *out_val;          // [net][set][2]
   double *out_grad;         // [net][set][n_params] (adjoint programs)
-  int n_params, n_sets, n_tasks;
-  int scratch_off, scal_off, gacc_off, red_off;  // LDS byte offsets
-  int with_grad;
+  int n_params, n_sets, n_tasks, per_set;
+  int scratch_off, scal_off, gacc_off, red_off, gbar_off;  // LDS byte offsets
+};
+
+// Arguments of the level executor kernels (one chunk of parameter vectors).
+struct LevelArgs {
+  void *arena;     // [set][stride] elements
+  int64_t stride;  // elements per parameter vector
+  int n_sets;      // parameter vectors in this chunk
+  double *scal;    // [set][n_comp] component scalars (complex, FP64)
+  int n_comp;
 };
 
 }  // namespace qtn

@@ -1,10 +1,11 @@
 // HIP kernels for gfx950: angle binding, the fused per-workgroup network
 // executor (forward and adjoint), and the FP64 objective combine.
 //
-// Fused executor: one workgroup runs one (network, parameter vector) task
-// at a time from a device work counter (persistent grid). All tensors of the
-// task live in LDS: constant leaves are copied in, parametric leaves are
-// bound from the angles in place, and every pairwise contraction (eq. (1))
+// Fused executor: one workgroup runs one (network, parameter vector) task at
+// a time (persistent grid, static striding over tasks sorted by cost). All
+// tensors of the task live in LDS: constant leaves and the parametric leaves
+// bound for its parameter vector are copied in, and every pairwise
+// contraction (eq. (1))
 // reads its operands through per-op address maps and writes its result into
 // the LDS arena. Rank-0 results (the last contraction of each component)
 // are accumulated in FP64 with a fixed reduction tree, so results are
@@ -44,6 +45,26 @@ template <> __device__ __forceinline__ float2 czero<float2>() { return make_floa
 template <> __device__ __forceinline__ double2 czero<double2>() { return make_double2(0.0, 0.0); }
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// Read-only data read with workgroup-uniform addresses (op descriptors,
+// offset tables) goes through the constant address space so the compiler
+// can use scalar loads for it. Nothing the kernels write is read this way.
+#define QTN_CONST __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const QTN_CONST T *cptr(const T *p) {
+  return (const QTN_CONST T *)(p);
+}
+// Word-wise load of a descriptor struct through the constant address space.
+template <typename S>
+__device__ __forceinline__ S cload(const S *p) {
+  static_assert(sizeof(S) % 4 == 0, "descriptor size");
+  S r;
+  const QTN_CONST int32_t *src = (const QTN_CONST int32_t *)(p);
+  int32_t *dst = reinterpret_cast<int32_t *>(&r);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(S) / 4); ++i) dst[i] = src[i];
+  return r;
+}
 
 // Deposit the low bits of v at the set positions of mask (lowest first).
 __device__ __forceinline__ uint32_t pdep32(uint32_t v, uint32_t mask) {
@@ -106,21 +127,23 @@ __device__ double2 param_entry(int kind, int folded, int idx, double c, double s
   return make_double2(t1.x + t2.x, t1.y + t2.y);
 }
 
-// Angle binding on its own: dst[s][t][e] for every set s and parametric
-// tensor t of one network (entries at ptens[t].off within a set's slice).
+// Angle binding (one workgroup per parametric tensor and parameter vector):
+// G[s][off + e] = entry e of the tensor at angle coeff * params[s][param], and
+// optionally dG[s][off + e] = its derivative with respect to that angle.
 template <typename V>
-__global__ void bind_params_kernel(const DParam *__restrict__ ptens, int n_ptens, const double *__restrict__ params,
-                                   int n_params, int n_sets, int per_set, V *__restrict__ dst) {
+__global__ __launch_bounds__(256) void bind_params_kernel(const DParam *__restrict__ slots,
+                                                          const double *__restrict__ params, int n_params,
+                                                          int per_set, V *__restrict__ G, V *__restrict__ dG) {
   const int s = blockIdx.y;
-  if (s >= n_sets) return;
-  for (int t = 0; t < n_ptens; ++t) {
-    const DParam d = ptens[t];
-    const double th = d.coeff * params[(size_t)s * n_params + d.param];
-    double sn, cs;
-    sincos(0.5 * th, &sn, &cs);
-    const int ne = 1 << d.bits;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x)
-      dst[(size_t)s * per_set + d.off + e] = from_d2<V>(param_entry(d.kind, d.folded, e, cs, sn, false));
+  const DParam d = slots[blockIdx.x];
+  const double th = d.coeff * params[(size_t)s * n_params + d.param];
+  double sn, cs;
+  sincos(0.5 * th, &sn, &cs);
+  V *g = G + (size_t)s * per_set + d.off;
+  V *dg = dG ? dG + (size_t)s * per_set + d.off : nullptr;
+  for (int e = threadIdx.x; e < (1 << d.bits); e += blockDim.x) {
+    g[e] = from_d2<V>(param_entry(d.kind, d.folded, e, cs, sn, false));
+    if (dg) dg[e] = from_d2<V>(param_entry(d.kind, d.folded, e, cs, sn, true));
   }
 }
 
@@ -148,19 +171,58 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 
 // --- fused executor ------------------------------------------------------------------
 
-template <typename T, int BLOCK>
-__device__ __forceinline__ void op_contract(typename Cplx<T>::type *mem, const DOp &op, const int32_t *__restrict__ tb,
-                                            typename Cplx<T>::type *scratch) {
-  using V = typename Cplx<T>::type;
+// Contraction with a compile-time number of summed entries K = 2^LGK: the
+// op's offset table (2K ints, uniform across the workgroup) is held in
+// scalar registers and the K loop is unrolled, so all operand reads of an
+// output are in flight together. One output per lane.
+template <typename V, int BLOCK, int LGK>
+__device__ __forceinline__ void contract_small_k(V *mem, const DOp &op, const int32_t *__restrict__ tb) {
+  constexpr int K = 1 << LGK;
+  int32_t t[2 * K];
+  const QTN_CONST int32_t *tc = cptr(tb);
+#pragma unroll
+  for (int i = 0; i < 2 * K; ++i) t[i] = tc[i];
+  const int nOut = 1 << (op.nFX + op.nFY);
+  const uint32_t maskJ = (1u << op.nFY) - 1u;
+  const V *X = mem + op.x;
+  const V *Y = mem + op.y;
+  V *Z = mem + op.z;
+  for (int c = threadIdx.x; c < nOut; c += BLOCK) {
+    const uint32_t fx = pdep32((uint32_t)c >> op.nFY, op.maskX);
+    const uint32_t fy = pdep32((uint32_t)c & maskJ, op.maskY);
+    // operand reads in chunks of up to 8 entries, all issued before the
+    // multiply-adds that consume them
+    constexpr int CH = K < 8 ? K : 8;
+    V acc = czero<V>();
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += CH) {
+      V xv[CH], yv[CH];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        xv[k] = X[fx + t[2 * (k0 + k)]];
+        yv[k] = Y[fy + t[2 * (k0 + k) + 1]];
+      }
+#pragma unroll
+      for (int k = 0; k < CH; ++k) acc = cmul_add(acc, xv[k], yv[k]);
+    }
+    Z[c] = acc;
+  }
+}
+
+// General contraction (any K); with fewer outputs than lanes the summed
+// index is split over lane groups and the partial sums are added in a fixed
+// order through `scratch`.
+template <typename V, int BLOCK>
+__device__ __forceinline__ void contract_general(V *mem, const DOp &op, const int32_t *__restrict__ tb, V *scratch) {
   const int tid = threadIdx.x;
   const int lgOut = op.nFX + op.nFY;
   const int nOut = 1 << lgOut;
   const int K = 1 << op.nS;
-  const int maskJ = (1 << op.nFY) - 1;
+  const uint32_t maskJ = (1u << op.nFY) - 1u;
   const V *X = mem + op.x;
   const V *Y = mem + op.y;
   V *Z = mem + op.z;
-  if (nOut >= BLOCK || op.nS == 0) {
+  if (nOut >= BLOCK) {
     for (int c = tid; c < nOut; c += BLOCK) {
       const uint32_t fx = pdep32((uint32_t)c >> op.nFY, op.maskX);
       const uint32_t fy = pdep32((uint32_t)c & maskJ, op.maskY);
@@ -169,16 +231,15 @@ __device__ __forceinline__ void op_contract(typename Cplx<T>::type *mem, const D
       Z[c] = acc;
     }
   } else {
-    // fewer outputs than threads: split the summed index over G groups
     int lgG = 0;
     while ((nOut << (lgG + 1)) <= BLOCK && lgG < op.nS) ++lgG;
     const int G = 1 << lgG;
     const int c = tid & (nOut - 1);
     const int g = tid >> lgOut;
-    V acc = czero<V>();
     if (g < G) {
       const uint32_t fx = pdep32((uint32_t)c >> op.nFY, op.maskX);
       const uint32_t fy = pdep32((uint32_t)c & maskJ, op.maskY);
+      V acc = czero<V>();
       for (int k = g; k < K; k += G) acc = cmul_add(acc, X[fx + tb[2 * k]], Y[fy + tb[2 * k + 1]]);
       scratch[tid] = acc;
     }
@@ -191,7 +252,23 @@ __device__ __forceinline__ void op_contract(typename Cplx<T>::type *mem, const D
   }
 }
 
-template <typename T, int BLOCK>
+template <typename V, int BLOCK>
+__device__ __forceinline__ void op_contract(V *mem, const DOp &op, const int32_t *__restrict__ tb, V *scratch) {
+  switch (op.nS) {
+    case 0: contract_small_k<V, BLOCK, 0>(mem, op, tb); break;
+    case 1: contract_small_k<V, BLOCK, 1>(mem, op, tb); break;
+    case 2: contract_small_k<V, BLOCK, 2>(mem, op, tb); break;
+    case 3: contract_small_k<V, BLOCK, 3>(mem, op, tb); break;
+    case 4: contract_small_k<V, BLOCK, 4>(mem, op, tb); break;
+    default: contract_general<V, BLOCK>(mem, op, tb, scratch); break;
+  }
+}
+
+// Fused executor. GRAD selects the forward+adjoint program: adjoints of
+// parametric leaves are accumulated, in canonical layout, per distinct
+// parametric tensor (several gates share one angle), and contracted with
+// dG/dtheta once per task, in FP64.
+template <typename T, int BLOCK, bool GRAD>
 __global__ __launch_bounds__(BLOCK) void fused_exec_kernel(FusedArgs a) {
   using V = typename Cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -200,37 +277,37 @@ __global__ __launch_bounds__(BLOCK) void fused_exec_kernel(FusedArgs a) {
   double2 *scal = reinterpret_cast<double2 *>(smem + a.scal_off);
   double *gacc = reinterpret_cast<double *>(smem + a.gacc_off);
   double *red = reinterpret_cast<double *>(smem + a.red_off);
-  __shared__ int s_task;
+  V *gbar = reinterpret_cast<V *>(smem + a.gbar_off);
   const int tid = threadIdx.x;
   const V *consts = reinterpret_cast<const V *>(a.consts);
+  const V *bound = reinterpret_cast<const V *>(a.bound);
+  const V *dbound = reinterpret_cast<const V *>(a.dbound);
 
-  for (;;) {
-    if (tid == 0) s_task = atomicAdd(a.counter, 1);
-    __syncthreads();
-    const int task = __builtin_amdgcn_readfirstlane(s_task);
-    if (task >= a.n_tasks) break;
-    const int ni = __builtin_amdgcn_readfirstlane(a.task_net[task / a.n_sets]);
+  // tasks are ordered by decreasing cost; workgroup b takes b, b + grid, ...
+  for (int task = blockIdx.x; task < a.n_tasks; task += gridDim.x) {
+    const int ni = cptr(a.task_net)[task / a.n_sets];
     const int set = task % a.n_sets;
-    const DNet net = a.nets[ni];
+    const DNet net = cload(a.nets + ni);
 
     for (int e = tid; e < net.n_const; e += BLOCK) mem[e] = consts[net.const_begin + e];
-    const double *prm = a.params + (size_t)set * a.n_params;
+    const V *bset = bound + (size_t)set * a.per_set;
     for (int t = 0; t < net.n_ptens; ++t) {
-      const DParam d = a.ptens[net.ptens_begin + t];
-      const double th = d.coeff * prm[d.param];
-      double sn, cs;
-      sincos(0.5 * th, &sn, &cs);
-      for (int e = tid; e < (1 << d.bits); e += BLOCK) mem[d.off + e] = from_d2<V>(param_entry(d.kind, d.folded, e, cs, sn, false));
+      const DParam d = cload(a.ptens + net.ptens_begin + t);
+      for (int e = tid; e < (1 << d.bits); e += BLOCK) {
+        mem[d.off + e] = bset[d.slot + e];
+        if (GRAD) gbar[d.goff + e] = czero<V>();
+      }
     }
-    if (a.with_grad)
-      for (int p = tid; p < a.n_params; p += BLOCK) gacc[p] = 0.0;
     __syncthreads();
 
+    const DOp *ops = a.ops + net.op_begin;
+    DOp nxt = cload(ops);
     for (int o = 0; o < net.n_ops; ++o) {
-      const DOp op = a.ops[net.op_begin + o];
+      const DOp op = nxt;
+      if (o + 1 < net.n_ops) nxt = cload(ops + o + 1);  // next descriptor in flight during this op
       const int32_t *tb = a.tabs + op.tab;
       if (op.type == OP_CONTRACT) {
-        op_contract<T, BLOCK>(mem, op, tb, scratch);
+        op_contract<V, BLOCK>(mem, op, tb, scratch);
       } else if (op.type == OP_SCALAR) {
         const int K = 1 << op.nS;
         double re = 0.0, im = 0.0;
@@ -243,26 +320,17 @@ __global__ __launch_bounds__(BLOCK) void fused_exec_kernel(FusedArgs a) {
         re = block_sum<BLOCK>(re, red);
         im = block_sum<BLOCK>(im, red);
         if (tid == 0) scal[op.z] = make_double2(re, im);
-      } else if (op.type == OP_SEED) {
+      } else if (GRAD && op.type == OP_SEED) {
         if (tid == 0) {
           double2 p = make_double2(1.0, 0.0);
           for (int j = 0; j < net.n_comp; ++j)
             if (j != op.aux0) p = cmul(p, scal[j]);
           mem[op.z] = from_d2<V>(p);
         }
-      } else {  // OP_LEAFGRAD
-        const DParam d = a.ptens[op.aux0];
-        const double th = d.coeff * prm[d.param];
-        double sn, cs;
-        sincos(0.5 * th, &sn, &cs);
-        double acc = 0.0;
-        for (int i = tid; i < (1 << op.nFX); i += BLOCK) {
-          const double2 g = to_d2(mem[op.x + i]);
-          const double2 dv = param_entry(d.kind, d.folded, tb[i], cs, sn, true);
-          acc += g.x * dv.x - g.y * dv.y;
-        }
-        acc = block_sum<BLOCK>(acc, red);
-        if (tid == 0) gacc[d.param] += d.coeff * acc;
+      } else if (GRAD) {  // OP_LEAFGRAD: add the leaf adjoint into its tensor's accumulator
+        const DParam d = cload(a.ptens + op.aux0);
+        V *acc = gbar + d.goff;
+        for (int i = tid; i < (1 << op.nFX); i += BLOCK) acc[tb[i]] = cadd(acc[tb[i]], mem[op.x + i]);
       }
       __syncthreads();
     }
@@ -274,20 +342,26 @@ __global__ __launch_bounds__(BLOCK) void fused_exec_kernel(FusedArgs a) {
       ov[0] = p.x;
       ov[1] = p.y;
     }
-    if (a.with_grad)
+    if (GRAD) {
+      for (int p = tid; p < a.n_params; p += BLOCK) gacc[p] = 0.0;
+      __syncthreads();
+      // d Re(s) / d theta_p = sum over tensors t with param p of coeff_t * Re <Gbar_t, dG_t/dtheta>
+      const V *dset = dbound + (size_t)set * a.per_set;
+      for (int t = 0; t < net.n_ptens; ++t) {
+        const DParam d = cload(a.ptens + net.ptens_begin + t);
+        double acc = 0.0;
+        for (int e = tid; e < (1 << d.bits); e += BLOCK) {
+          const double2 g = to_d2(gbar[d.goff + e]);
+          const double2 dv = to_d2(dset[d.slot + e]);
+          acc += g.x * dv.x - g.y * dv.y;
+        }
+        acc = block_sum<BLOCK>(acc, red);
+        if (tid == 0) gacc[d.param] += d.coeff * acc;
+      }
+      __syncthreads();
       for (int p = tid; p < a.n_params; p += BLOCK) a.out_grad[((size_t)ni * a.n_sets + set) * a.n_params + p] = gacc[p];
-    __syncthreads();
-  }
-  // The last workgroup to leave returns both counters to zero for the next
-  // launch: every workgroup has made its final claim on counter[0] before it
-  // counts itself out on counter[1].
-  if (tid == 0) {
-    __threadfence();
-    const int done = atomicAdd(a.counter + 1, 1);
-    if (done == (int)gridDim.x - 1) {
-      atomicExch(a.counter, 0);
-      atomicExch(a.counter + 1, 0);
     }
+    __syncthreads();
   }
 }
 
@@ -313,41 +387,25 @@ __global__ __launch_bounds__(256) void combine_kernel(const double *__restrict__
 }
 
 // --- launch helpers (host) ----------------------------------------------------------------
-template <typename T, int BLOCK>
-static hipError_t launch_fused_t(const FusedArgs &a, int grid, int lds_bytes, hipStream_t st) {
-  auto kern = fused_exec_kernel<T, BLOCK>;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds_bytes, st, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_fused(int dtype, int block, const FusedArgs &a, int grid, int lds_bytes, hipStream_t st) {
-  if (dtype == TN_C128) {
-    switch (block) {
-      case 64: return launch_fused_t<double, 64>(a, grid, lds_bytes, st);
-      case 128: return launch_fused_t<double, 128>(a, grid, lds_bytes, st);
-      default: return launch_fused_t<double, 256>(a, grid, lds_bytes, st);
-    }
-  }
+template <typename T, bool G>
+static const void *fused_ptr_t(int block) {
   switch (block) {
-    case 64: return launch_fused_t<float, 64>(a, grid, lds_bytes, st);
-    case 128: return launch_fused_t<float, 128>(a, grid, lds_bytes, st);
-    default: return launch_fused_t<float, 256>(a, grid, lds_bytes, st);
+    case 64: return (const void *)fused_exec_kernel<T, 64, G>;
+    case 128: return (const void *)fused_exec_kernel<T, 128, G>;
+    default: return (const void *)fused_exec_kernel<T, 256, G>;
   }
 }
 
-const void *fused_kernel_ptr(int dtype, int block) {
-  if (dtype == TN_C128) {
-    switch (block) {
-      case 64: return (const void *)fused_exec_kernel<double, 64>;
-      case 128: return (const void *)fused_exec_kernel<double, 128>;
-      default: return (const void *)fused_exec_kernel<double, 256>;
-    }
-  }
-  switch (block) {
-    case 64: return (const void *)fused_exec_kernel<float, 64>;
-    case 128: return (const void *)fused_exec_kernel<float, 128>;
-    default: return (const void *)fused_exec_kernel<float, 256>;
-  }
+const void *fused_kernel_ptr(int dtype, int block, bool grad) {
+  if (dtype == TN_C128) return grad ? fused_ptr_t<double, true>(block) : fused_ptr_t<double, false>(block);
+  return grad ? fused_ptr_t<float, true>(block) : fused_ptr_t<float, false>(block);
+}
+
+hipError_t launch_fused(int dtype, int block, bool grad, const FusedArgs &a, int grid, int lds_bytes,
+                        hipStream_t st) {
+  const void *k = fused_kernel_ptr(dtype, block, grad);
+  void *args[] = {(void *)&a};
+  return hipLaunchKernel(k, dim3(grid), dim3(block), args, lds_bytes, st);
 }
 
 hipError_t launch_combine(const double *val, const double *gnet, const double *coef, double offset, int n_nets,
@@ -357,15 +415,16 @@ hipError_t launch_combine(const double *val, const double *gnet, const double *c
   return hipGetLastError();
 }
 
-hipError_t launch_bind(int dtype, const DParam *ptens, int n_ptens, const double *params, int n_params, int n_sets,
-                       int per_set, void *dst, hipStream_t st) {
-  dim3 grid(1, n_sets);
+hipError_t launch_bind(int dtype, const DParam *slots, int n_slots, const double *params, int n_params, int n_sets,
+                       int per_set, void *G, void *dG, hipStream_t st) {
+  if (n_slots == 0) return hipSuccess;
+  dim3 grid(n_slots, n_sets);
   if (dtype == TN_C128)
-    hipLaunchKernelGGL(bind_params_kernel<double2>, grid, dim3(256), 0, st, ptens, n_ptens, params, n_params, n_sets,
-                       per_set, (double2 *)dst);
+    hipLaunchKernelGGL(bind_params_kernel<double2>, grid, dim3(256), 0, st, slots, params, n_params, per_set,
+                       (double2 *)G, (double2 *)dG);
   else
-    hipLaunchKernelGGL(bind_params_kernel<float2>, grid, dim3(256), 0, st, ptens, n_ptens, params, n_params, n_sets,
-                       per_set, (float2 *)dst);
+    hipLaunchKernelGGL(bind_params_kernel<float2>, grid, dim3(256), 0, st, slots, params, n_params, per_set,
+                       (float2 *)G, (float2 *)dG);
   return hipGetLastError();
 }
 

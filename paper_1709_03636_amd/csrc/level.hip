@@ -1,0 +1,282 @@
+// Level executor: runs network programs whose tensors do not fit in one
+// workgroup's LDS. Every buffer of a (network, parameter vector) pair lives
+// in a global-memory arena slice; each op of the program is one launch that
+// covers all parameter vectors of the chunk at once (the batch dimension),
+// with the same addressing as the fused executor (free-index deposit plus
+// a per-op offset table for the summed index, eq. (1)).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace qtn {
+
+template <typename T> struct LCplx;
+template <> struct LCplx<float> { using type = float2; };
+template <> struct LCplx<double> { using type = double2; };
+
+__device__ __forceinline__ float2 l_fma(float2 acc, float2 a, float2 b) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(-a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(a.y, b.x, acc.y);
+  return acc;
+}
+__device__ __forceinline__ double2 l_fma(double2 acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+__device__ __forceinline__ double2 l_d2(float2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ double2 l_d2(double2 v) { return v; }
+template <typename V> __device__ __forceinline__ V l_from(double2 v);
+template <> __device__ __forceinline__ float2 l_from<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+template <> __device__ __forceinline__ double2 l_from<double2>(double2 v) { return v; }
+
+#define QTN_LCONST __attribute__((address_space(4)))
+
+__device__ __forceinline__ uint32_t l_pdep(uint32_t v, uint32_t mask) {
+  uint32_t r = 0;
+  while (mask) {
+    uint32_t low = mask & (0u - mask);
+    if (v & 1u) r |= low;
+    v >>= 1;
+    mask ^= low;
+  }
+  return r;
+}
+
+
+// Z[set][c] = sum_k X[set][fx(c) + tx(k)] * Y[set][fy(c) + ty(k)]; one output per thread.
+template <typename V>
+__global__ __launch_bounds__(256) void level_contract_kernel(LevelArgs a, DOp op, const int32_t *__restrict__ tab) {
+  const int lgOut = op.nFX + op.nFY;
+  const int64_t nOut = (int64_t)1 << lgOut;
+  const int64_t total = nOut * a.n_sets;
+  const int K = 1 << op.nS;
+  const uint32_t maskJ = (1u << op.nFY) - 1u;
+  const QTN_LCONST int32_t *tb = (const QTN_LCONST int32_t *)tab;
+  V *arena = reinterpret_cast<V *>(a.arena);
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t set = g >> lgOut;
+    const uint32_t c = (uint32_t)(g & (nOut - 1));
+    V *base = arena + set * a.stride;
+    const V *X = base + op.x + l_pdep(c >> op.nFY, op.maskX);
+    const V *Y = base + op.y + l_pdep(c & maskJ, op.maskY);
+    V acc;
+    acc.x = 0;
+    acc.y = 0;
+    for (int k = 0; k < K; ++k) acc = l_fma(acc, X[tb[2 * k]], Y[tb[2 * k + 1]]);
+    base[op.z + c] = acc;
+  }
+}
+
+// Rank-0 result: one workgroup per parameter vector, FP64 fixed-tree sum.
+template <typename V>
+__global__ __launch_bounds__(256) void level_scalar_kernel(LevelArgs a, DOp op, const int32_t *__restrict__ tab) {
+  __shared__ double red[2][4];
+  const int set = blockIdx.x;
+  const V *base = reinterpret_cast<const V *>(a.arena) + set * a.stride;
+  const int K = 1 << op.nS;
+  double re = 0.0, im = 0.0;
+  for (int k = threadIdx.x; k < K; k += 256) {
+    const double2 x = l_d2(base[op.x + tab[2 * k]]);
+    const double2 y = l_d2(base[op.y + tab[2 * k + 1]]);
+    re += x.x * y.x - x.y * y.y;
+    im += x.x * y.y + x.y * y.x;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    re += __shfl_xor(re, o, 64);
+    im += __shfl_xor(im, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = re;
+    red[1][threadIdx.x >> 6] = im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0, i = 0.0;
+    for (int w = 0; w < 4; ++w) {
+      r += red[0][w];
+      i += red[1][w];
+    }
+    a.scal[((size_t)set * a.n_comp + op.z) * 2] = r;
+    a.scal[((size_t)set * a.n_comp + op.z) * 2 + 1] = i;
+  }
+}
+
+// Adjoint seed of component aux0: product of the other component scalars.
+template <typename V>
+__global__ void level_seed_kernel(LevelArgs a, DOp op) {
+  const int set = blockIdx.x * blockDim.x + threadIdx.x;
+  if (set >= a.n_sets) return;
+  double pr = 1.0, pi = 0.0;
+  for (int j = 0; j < a.n_comp; ++j) {
+    if (j == op.aux0) continue;
+    const double sr = a.scal[((size_t)set * a.n_comp + j) * 2], si = a.scal[((size_t)set * a.n_comp + j) * 2 + 1];
+    const double nr = pr * sr - pi * si, ni = pr * si + pi * sr;
+    pr = nr;
+    pi = ni;
+  }
+  V *base = reinterpret_cast<V *>(a.arena) + set * a.stride;
+  base[op.z] = l_from<V>(make_double2(pr, pi));
+}
+
+// Leaf adjoint added into its tensor's canonical-layout accumulator at y.
+template <typename V>
+__global__ __launch_bounds__(256) void level_leafgrad_kernel(LevelArgs a, DOp op, const int32_t *__restrict__ tab) {
+  const int n = 1 << op.nFX;
+  const int64_t total = (int64_t)n * a.n_sets;
+  V *arena = reinterpret_cast<V *>(a.arena);
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t set = g / n;
+    const int i = (int)(g - set * n);
+    V *base = arena + set * a.stride;
+    V v = base[op.y + tab[i]];
+    const V x = base[op.x + i];
+    v.x += x.x;
+    v.y += x.y;
+    base[op.y + tab[i]] = v;
+  }
+}
+
+// Set-up of a chunk: constants and bound parametric tensors into every
+// slice, adjoint accumulators cleared. Entries of one slice: `n_copy`
+// from consts, then per tensor from the bound-tensor buffer.
+template <typename V>
+__global__ __launch_bounds__(256) void level_setup_kernel(LevelArgs a, const V *__restrict__ consts, int n_const,
+                                                          const DParam *__restrict__ pt, int n_pt,
+                                                          const V *__restrict__ bound, int per_set, int set0,
+                                                          int zero_begin, int zero_n) {
+  const int set = blockIdx.y;
+  V *base = reinterpret_cast<V *>(a.arena) + set * a.stride;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n_const; e += gridDim.x * blockDim.x) base[e] = consts[e];
+  const V *bs = bound + (size_t)(set0 + set) * per_set;
+  for (int t = 0; t < n_pt; ++t) {
+    const DParam d = pt[t];
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < (1 << d.bits); e += gridDim.x * blockDim.x)
+      base[d.off + e] = bs[d.slot + e];
+  }
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < zero_n; e += gridDim.x * blockDim.x) {
+    V z;
+    z.x = 0;
+    z.y = 0;
+    base[zero_begin + e] = z;
+  }
+}
+
+// Outputs of a chunk: value = product of component scalars; gradient =
+// sum over parametric tensors of coeff * Re <Gbar, dG/dtheta> in FP64.
+template <typename V>
+__global__ __launch_bounds__(256) void level_finish_kernel(LevelArgs a, const DParam *__restrict__ pt, int n_pt,
+                                                           const V *__restrict__ dbound, int per_set, int set0,
+                                                           int net, int n_sets_total, int n_params,
+                                                           double *__restrict__ out_val, double *__restrict__ out_grad,
+                                                           int with_grad) {
+  __shared__ double red[4];
+  __shared__ double gacc[64];
+  const int set = blockIdx.x;
+  const V *base = reinterpret_cast<const V *>(a.arena) + set * a.stride;
+  const int gs = set0 + set;
+  if (threadIdx.x == 0) {
+    double pr = 1.0, pi = 0.0;
+    for (int j = 0; j < a.n_comp; ++j) {
+      const double sr = a.scal[((size_t)set * a.n_comp + j) * 2], si = a.scal[((size_t)set * a.n_comp + j) * 2 + 1];
+      const double nr = pr * sr - pi * si, ni = pr * si + pi * sr;
+      pr = nr;
+      pi = ni;
+    }
+    out_val[((size_t)net * n_sets_total + gs) * 2] = pr;
+    out_val[((size_t)net * n_sets_total + gs) * 2 + 1] = pi;
+  }
+  if (!with_grad) return;
+  for (int p0 = 0; p0 < n_params; p0 += 64) {
+    for (int p = threadIdx.x; p < 64; p += blockDim.x) gacc[p] = 0.0;
+    __syncthreads();
+    const V *dset = dbound + (size_t)gs * per_set;
+    for (int t = 0; t < n_pt; ++t) {
+      const DParam d = pt[t];
+      if (d.param < p0 || d.param >= p0 + 64) continue;
+      double acc = 0.0;
+      for (int e = threadIdx.x; e < (1 << d.bits); e += 256) {
+        const double2 g = l_d2(base[d.goff + e]);
+        const double2 dv = l_d2(dset[d.slot + e]);
+        acc += g.x * dv.x - g.y * dv.y;
+      }
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+      __syncthreads();
+      if (threadIdx.x == 0) gacc[d.param - p0] += d.coeff * (red[0] + red[1] + red[2] + red[3]);
+      __syncthreads();
+    }
+    for (int p = threadIdx.x; p < 64 && p0 + p < n_params; p += blockDim.x)
+      out_grad[((size_t)net * n_sets_total + gs) * n_params + p0 + p] = gacc[p];
+    __syncthreads();
+  }
+}
+
+// --- host launchers ------------------------------------------------------------------------
+static inline int grid_for(int64_t total) {
+  int64_t g = (total + 255) / 256;
+  return (int)(g < 65536 ? (g < 1 ? 1 : g) : 65536);
+}
+
+template <typename V>
+static hipError_t level_op_t(const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream_t st) {
+  switch (op.type) {
+    case OP_CONTRACT: {
+      int64_t total = ((int64_t)1 << (op.nFX + op.nFY)) * a.n_sets;
+      hipLaunchKernelGGL(level_contract_kernel<V>, dim3(grid_for(total)), dim3(256), 0, st, a, op, tab);
+      break;
+    }
+    case OP_SCALAR:
+      hipLaunchKernelGGL(level_scalar_kernel<V>, dim3(a.n_sets), dim3(256), 0, st, a, op, tab);
+      break;
+    case OP_SEED:
+      hipLaunchKernelGGL(level_seed_kernel<V>, dim3((a.n_sets + 63) / 64), dim3(64), 0, st, a, op);
+      break;
+    default: {
+      int64_t total = ((int64_t)1 << op.nFX) * a.n_sets;
+      hipLaunchKernelGGL(level_leafgrad_kernel<V>, dim3(grid_for(total)), dim3(256), 0, st, a, op, tab);
+      break;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream_t st) {
+  return dtype == TN_C128 ? level_op_t<double2>(a, op, tab, st) : level_op_t<float2>(a, op, tab, st);
+}
+
+hipError_t level_setup(int dtype, const LevelArgs &a, const void *consts, int n_const, const DParam *pt, int n_pt,
+                       const void *bound, int per_set, int set0, int zero_begin, int zero_n, hipStream_t st) {
+  int64_t per = n_const;
+  dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (per + zero_n + 255) / 256 + 1)), a.n_sets);
+  if (dtype == TN_C128)
+    hipLaunchKernelGGL(level_setup_kernel<double2>, grid, dim3(256), 0, st, a, (const double2 *)consts, n_const, pt,
+                       n_pt, (const double2 *)bound, per_set, set0, zero_begin, zero_n);
+  else
+    hipLaunchKernelGGL(level_setup_kernel<float2>, grid, dim3(256), 0, st, a, (const float2 *)consts, n_const, pt, n_pt,
+                       (const float2 *)bound, per_set, set0, zero_begin, zero_n);
+  return hipGetLastError();
+}
+
+hipError_t level_finish(int dtype, const LevelArgs &a, const DParam *pt, int n_pt, const void *dbound, int per_set,
+                        int set0, int net, int n_sets_total, int n_params, double *out_val, double *out_grad,
+                        int with_grad, hipStream_t st) {
+  if (dtype == TN_C128)
+    hipLaunchKernelGGL(level_finish_kernel<double2>, dim3(a.n_sets), dim3(256), 0, st, a, pt, n_pt,
+                       (const double2 *)dbound, per_set, set0, net, n_sets_total, n_params, out_val, out_grad,
+                       with_grad);
+  else
+    hipLaunchKernelGGL(level_finish_kernel<float2>, dim3(a.n_sets), dim3(256), 0, st, a, pt, n_pt,
+                       (const float2 *)dbound, per_set, set0, net, n_sets_total, n_params, out_val, out_grad,
+                       with_grad);
+  return hipGetLastError();
+}
+
+}  // namespace qtn

@@ -3,24 +3,40 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <map>
 #include <numeric>
+#include <tuple>
 
 #include "device.hpp"
 #include "internal.hpp"
 
 namespace qtn {
 
-hipError_t launch_fused(int dtype, int block, const FusedArgs &a, int grid, int lds_bytes, hipStream_t st);
-const void *fused_kernel_ptr(int dtype, int block);
+hipError_t launch_fused(int dtype, int block, bool grad, const FusedArgs &a, int grid, int lds_bytes,
+                        hipStream_t st);
+const void *fused_kernel_ptr(int dtype, int block, bool grad);
 hipError_t launch_combine(const double *val, const double *gnet, const double *coef, double offset, int n_nets,
                           int n_sets, int n_params, double *obj, double *grad, hipStream_t st);
-hipError_t launch_bind(int dtype, const DParam *ptens, int n_ptens, const double *params, int n_params, int n_sets,
-                       int per_set, void *dst, hipStream_t st);
+hipError_t launch_bind(int dtype, const DParam *slots, int n_slots, const double *params, int n_params, int n_sets,
+                       int per_set, void *G, void *dG, hipStream_t st);
+hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream_t st);
+hipError_t level_setup(int dtype, const LevelArgs &a, const void *consts, int n_const, const DParam *pt, int n_pt,
+                       const void *bound, int per_set, int set0, int zero_begin, int zero_n, hipStream_t st);
+hipError_t level_finish(int dtype, const LevelArgs &a, const DParam *pt, int n_pt, const void *dbound, int per_set,
+                        int set0, int net, int n_sets_total, int n_params, double *out_val, double *out_grad,
+                        int with_grad, hipStream_t st);
 
 
 static constexpr int kLdsCap = 160 * 1024;
+// Networks whose fused adjoint program needs more LDS than this run on the
+// level executor, so one large network does not lower the occupancy of all.
+static constexpr int64_t kFusedLdsMax = 64 * 1024;
+// Global-memory arena budget of the level executor (parameter vectors are
+// processed in chunks that fit).
+static constexpr int64_t kLevelBudget = 8ll << 30;
 
 // First-fit arena allocator over element offsets.
 struct Arena {
@@ -91,105 +107,227 @@ static int64_t layout_buffers(const Plan &p, int n_ops, std::vector<int64_t> &of
   return ar.top;
 }
 
+// Layout of one network's buffers in executor memory: constant leaves,
+// parametric leaves, then the arena of intermediates/adjoints for each
+// program variant (0 = forward, 1 = forward + adjoint).
+struct NetLayout {
+  std::vector<int64_t> coff, poff;
+  int64_t n_const = 0, leaf_region = 0, ptens_elems = 0;
+  std::vector<int64_t> off[2];
+  int64_t arena[2] = {0, 0};
+};
+
+static NetLayout make_layout(const Net &net) {
+  NetLayout lay;
+  lay.coff.resize(net.consts.size());
+  lay.poff.resize(net.ptensors.size());
+  int64_t pos = 0;
+  for (size_t c = 0; c < net.consts.size(); ++c) {
+    lay.coff[c] = pos;
+    pos += (int64_t)net.consts[c].size();
+  }
+  lay.n_const = pos;
+  for (size_t t = 0; t < net.ptensors.size(); ++t) {
+    lay.poff[t] = pos;
+    pos += (int64_t)1 << net.ptensors[t].bits;
+  }
+  lay.leaf_region = pos;
+  lay.ptens_elems = pos - lay.n_const;
+  const Plan &p = net.gplan;
+  lay.arena[0] = layout_buffers(p, p.n_fwd_ops, lay.off[0]);
+  lay.arena[1] = layout_buffers(p, (int)p.ops.size(), lay.off[1]);
+  return lay;
+}
+
+static int64_t abs_off(const Net &net, const NetLayout &lay, int variant, int v) {
+  if (v < net.gplan.n_leaves) {
+    int src = net.leaves[v].src;
+    return src >= 0 ? lay.coff[src] : lay.poff[-src - 1];
+  }
+  return lay.leaf_region + lay.off[variant][v];
+}
+
+// Program arrays shared by the fused executor (LDS offsets) and the level
+// executor (global arena offsets).
 struct HostProgram {
-  std::vector<DNet> nets_fwd, nets_grad;
+  std::vector<DNet> nets_fwd, nets_grad;  // fused: one entry per batch network (level ones empty)
   std::vector<DOp> ops;
   std::vector<int32_t> tabs;
   std::vector<double> consts;  // interleaved, converted to the dtype at upload
   std::vector<DParam> ptens;
-  int max_mem_fwd = 0, max_mem_grad = 0, max_comp = 0;
+  // distinct parametric tensors of the whole batch (bound once per parameter vector)
+  std::vector<DParam> slots;
+  std::map<std::tuple<int, int, double, int>, int> slot_of;
+  int per_set = 0;
+  int max_mem_fwd = 0, max_mem_grad = 0, max_comp = 0, max_ptens_elems = 0;
 };
 
-// Append the fused programs (forward and forward+adjoint) of one network.
-static int append_fused(const Net &net, HostProgram &hp, std::string &why) {
-  const Plan &p = net.gplan;
-  const int L = p.n_leaves;
-  // leaf region: constants then parametric tensors
-  std::vector<int64_t> coff(net.consts.size()), poff(net.ptensors.size());
-  int64_t pos = 0;
-  const int const_begin = (int)(hp.consts.size() / 2);
-  for (size_t c = 0; c < net.consts.size(); ++c) {
-    coff[c] = pos;
-    for (auto &z : net.consts[c]) {
+struct LevelNet {
+  int net = 0;
+  int n_comp = 0;
+  int op_begin[2] = {0, 0}, n_ops[2] = {0, 0};  // into HostProgram::ops
+  int64_t stride[2] = {0, 0};                   // elements per parameter vector
+  int const_begin = 0, n_const = 0;             // into HostProgram::consts (elements)
+  int ptens_begin = 0, n_ptens = 0;             // into HostProgram::ptens (absolute offsets)
+  int64_t gbar_begin = 0, ptens_elems = 0;      // adjoint accumulators (variant 1)
+  int chunk = 1;                                // parameter vectors per pass
+};
+
+static int slot_for(HostProgram &hp, const ParamTensor &pt) {
+  auto key = std::make_tuple(pt.kind, pt.param, pt.coeff, pt.folded);
+  auto it = hp.slot_of.find(key);
+  if (it != hp.slot_of.end()) return it->second;
+  DParam s{};
+  s.kind = pt.kind;
+  s.param = pt.param;
+  s.folded = pt.folded;
+  s.bits = pt.bits;
+  s.off = hp.per_set;
+  s.coeff = pt.coeff;
+  hp.slots.push_back(s);
+  hp.slot_of.emplace(key, hp.per_set);
+  int r = hp.per_set;
+  hp.per_set += 1 << pt.bits;
+  return r;
+}
+
+static int append_consts(const Net &net, HostProgram &hp) {
+  const int begin = (int)(hp.consts.size() / 2);
+  for (auto &c : net.consts)
+    for (auto &z : c) {
       hp.consts.push_back(z.real());
       hp.consts.push_back(z.imag());
     }
-    pos += (int64_t)net.consts[c].size();
+  return begin;
+}
+
+// Emit the ops of one variant with offsets from `boff`; LEAFGRAD targets
+// are resolved by `leafgrad`.
+template <typename BOff, typename LG>
+static void emit_ops(const Plan &p, int n_ops, HostProgram &hp, BOff boff, LG leafgrad) {
+  for (int i = 0; i < n_ops; ++i) {
+    const Op &op = p.ops[i];
+    DOp d{};
+    d.type = op.type;
+    d.nFX = op.nFX;
+    d.nS = op.nS;
+    d.nFY = op.nFY;
+    d.maskX = op.maskX_F;
+    d.maskY = op.maskY_F;
+    d.tab = (int32_t)hp.tabs.size();
+    hp.tabs.insert(hp.tabs.end(), op.tab.begin(), op.tab.end());
+    if (op.type == OP_CONTRACT) {
+      d.x = boff(op.x);
+      d.y = boff(op.y);
+      d.z = boff(op.z);
+    } else if (op.type == OP_SCALAR) {
+      d.x = boff(op.x);
+      d.y = boff(op.y);
+      d.z = op.z;
+    } else if (op.type == OP_SEED) {
+      d.z = boff(op.z);
+      d.aux0 = op.aux0;
+    } else {
+      d.x = boff(op.x);
+      leafgrad(op, d);
+    }
+    hp.ops.push_back(d);
   }
-  const int n_const = (int)pos;
+}
+
+// LDS bytes the fused adjoint program of a network needs.
+static int64_t fused_lds_need(const Net &net, const NetLayout &lay, int eb, int n_params) {
+  int64_t mem = lay.leaf_region + std::max(lay.arena[0], lay.arena[1]);
+  return mem * eb + 256 * eb + (int64_t)std::max(1, net.gplan.n_components) * 16 + (int64_t)n_params * 8 + 256 +
+         lay.ptens_elems * eb + 64;
+}
+
+static void append_fused(const Net &net, const NetLayout &lay, HostProgram &hp) {
+  const Plan &p = net.gplan;
+  const int const_begin = append_consts(net, hp);
   const int ptens_begin = (int)hp.ptens.size();
   for (size_t t = 0; t < net.ptensors.size(); ++t) {
     const ParamTensor &pt = net.ptensors[t];
-    poff[t] = pos;
     DParam d{};
     d.kind = pt.kind;
     d.param = pt.param;
     d.folded = pt.folded;
     d.bits = pt.bits;
-    d.off = (int32_t)pos;
+    d.off = (int32_t)lay.poff[t];
+    d.goff = (int32_t)(lay.poff[t] - lay.n_const);
     d.coeff = pt.coeff;
+    d.slot = slot_for(hp, pt);
     hp.ptens.push_back(d);
-    pos += (int64_t)1 << pt.bits;
   }
-  const int64_t leaf_region = pos;
-  auto leaf_off = [&](int v) -> int64_t {
-    int src = net.leaves[v].src;
-    return src >= 0 ? coff[src] : poff[-src - 1];
-  };
+  hp.max_ptens_elems = std::max(hp.max_ptens_elems, (int)lay.ptens_elems);
   for (int variant = 0; variant < 2; ++variant) {
     const int n_ops = variant == 0 ? p.n_fwd_ops : (int)p.ops.size();
-    std::vector<int64_t> off;
-    int64_t arena = layout_buffers(p, n_ops, off);
-    int64_t mem = leaf_region + arena;
-    if (mem * net.elem_bytes() > kLdsCap) {
-      why = "needs " + std::to_string(mem * net.elem_bytes()) + " bytes of LDS";
-      return TN_ENOMEM;
-    }
-    auto boff = [&](int v) -> int32_t { return (int32_t)(v < L ? leaf_off(v) : leaf_region + off[v]); };
     DNet dn{};
     dn.op_begin = (int32_t)hp.ops.size();
     dn.n_ops = n_ops;
     dn.n_comp = p.n_components;
-    dn.mem_elems = (int32_t)mem;
+    dn.mem_elems = (int32_t)(lay.leaf_region + lay.arena[variant]);
     dn.const_begin = const_begin;
-    dn.n_const = n_const;
+    dn.n_const = (int32_t)lay.n_const;
     dn.ptens_begin = ptens_begin;
     dn.n_ptens = (int32_t)net.ptensors.size();
-    for (int i = 0; i < n_ops; ++i) {
-      const Op &op = p.ops[i];
-      DOp d{};
-      d.type = op.type;
-      d.nFX = op.nFX;
-      d.nS = op.nS;
-      d.nFY = op.nFY;
-      d.maskX = op.maskX_F;
-      d.maskY = op.maskY_F;
-      d.tab = (int32_t)hp.tabs.size();
-      hp.tabs.insert(hp.tabs.end(), op.tab.begin(), op.tab.end());
-      if (op.type == OP_CONTRACT) {
-        d.x = boff(op.x);
-        d.y = boff(op.y);
-        d.z = boff(op.z);
-      } else if (op.type == OP_SCALAR) {
-        d.x = boff(op.x);
-        d.y = boff(op.y);
-        d.z = op.z;
-      } else if (op.type == OP_SEED) {
-        d.z = boff(op.z);
-        d.aux0 = op.aux0;
-      } else {
-        d.x = boff(op.x);
-        d.aux0 = ptens_begin + op.aux0;
-        d.aux1 = op.aux1;
-      }
-      hp.ops.push_back(d);
-    }
+    emit_ops(
+        p, n_ops, hp, [&](int v) { return (int32_t)abs_off(net, lay, variant, v); },
+        [&](const Op &op, DOp &d) {
+          d.aux0 = ptens_begin + op.aux0;
+          d.aux1 = op.aux1;
+        });
     (variant == 0 ? hp.nets_fwd : hp.nets_grad).push_back(dn);
     int &mx = variant == 0 ? hp.max_mem_fwd : hp.max_mem_grad;
-    mx = std::max(mx, (int)mem);
+    mx = std::max(mx, dn.mem_elems);
   }
   hp.max_comp = std::max(hp.max_comp, p.n_components);
-  return TN_OK;
+}
+
+// A network on the level executor: buffers in a global arena slice per
+// parameter vector; adjoint accumulators after the arena.
+static LevelNet append_level(const Net &net, const NetLayout &lay, HostProgram &hp, int index, int eb,
+                             int64_t budget_bytes, int max_sets) {
+  const Plan &p = net.gplan;
+  LevelNet ln;
+  ln.net = index;
+  ln.n_comp = p.n_components;
+  ln.const_begin = append_consts(net, hp);
+  ln.n_const = (int)lay.n_const;
+  ln.stride[0] = lay.leaf_region + lay.arena[0];
+  ln.gbar_begin = lay.leaf_region + lay.arena[1];
+  ln.ptens_elems = lay.ptens_elems;
+  ln.stride[1] = ln.gbar_begin + lay.ptens_elems;
+  for (int v = 0; v < 2; ++v) ln.stride[v] = (ln.stride[v] + 63) & ~int64_t(63);
+  ln.ptens_begin = (int)hp.ptens.size();
+  ln.n_ptens = (int)net.ptensors.size();
+  for (size_t t = 0; t < net.ptensors.size(); ++t) {
+    const ParamTensor &pt = net.ptensors[t];
+    DParam d{};
+    d.kind = pt.kind;
+    d.param = pt.param;
+    d.folded = pt.folded;
+    d.bits = pt.bits;
+    d.off = (int32_t)lay.poff[t];
+    d.goff = (int32_t)(ln.gbar_begin + lay.poff[t] - lay.n_const);
+    d.coeff = pt.coeff;
+    d.slot = slot_for(hp, pt);
+    hp.ptens.push_back(d);
+  }
+  for (int variant = 0; variant < 2; ++variant) {
+    ln.op_begin[variant] = (int)hp.ops.size();
+    ln.n_ops[variant] = variant == 0 ? p.n_fwd_ops : (int)p.ops.size();
+    emit_ops(
+        p, ln.n_ops[variant], hp, [&](int v) { return (int32_t)abs_off(net, lay, variant, v); },
+        [&](const Op &op, DOp &d) {
+          d.y = (int32_t)(ln.gbar_begin + lay.poff[op.aux0] - lay.n_const);
+          d.aux0 = ln.ptens_begin + op.aux0;
+          d.aux1 = op.aux1;
+        });
+  }
+  int64_t per = ln.stride[1] * eb;
+  ln.chunk = (int)std::max<int64_t>(1, std::min<int64_t>(max_sets, budget_bytes / std::max<int64_t>(1, per)));
+  return ln;
 }
 
 template <typename T>
@@ -220,18 +358,22 @@ struct tn_batch {
   double offset = 0;
   std::vector<double> coef;
   qtn::HostProgram hp;
-  std::vector<int32_t> task_net;
+  std::vector<int32_t> task_net;       // fused networks, in cost order
+  std::vector<qtn::LevelNet> level;    // networks on the level executor
   // device
   qtn::DNet *d_nets_fwd = nullptr, *d_nets_grad = nullptr;
   qtn::DOp *d_ops = nullptr;
   int32_t *d_tabs = nullptr, *d_task_net = nullptr;
   void *d_consts = nullptr;
-  qtn::DParam *d_ptens = nullptr;
-  int *d_counter = nullptr;
+  qtn::DParam *d_ptens = nullptr, *d_slots = nullptr;
+  void *d_bound = nullptr, *d_dbound = nullptr;
   double *d_val = nullptr, *d_gnet = nullptr, *d_coef = nullptr;
+  void *d_larena = nullptr;            // level executor arena
+  double *d_lscal = nullptr;           // level executor component scalars
   int lds_fwd = 0, lds_grad = 0, grid_fwd = 0, grid_grad = 0;
-  int scratch_off[2], scal_off[2], gacc_off[2], red_off[2];
+  int scratch_off[2], scal_off[2], gacc_off[2], red_off[2], gbar_off[2];
   double flops_fwd = 0, bytes_fwd = 0, flops_grad = 0, bytes_grad = 0;
+  int64_t level_bytes = 0;
   bool poisoned = false;
   qtn::GraphCache gc;
 };
@@ -251,8 +393,8 @@ static int hip_fail(hipError_t e, const char *what) {
 
 static void free_batch_dev(tn_batch *b) {
   b->gc.clear();
-  void *ptrs[] = {b->d_nets_fwd, b->d_nets_grad, b->d_ops, b->d_tabs, b->d_task_net, b->d_consts,
-                  b->d_ptens, b->d_counter, b->d_val, b->d_gnet, b->d_coef};
+  void *ptrs[] = {b->d_nets_fwd, b->d_nets_grad, b->d_ops, b->d_tabs, b->d_task_net, b->d_consts, b->d_ptens,
+                  b->d_slots, b->d_bound, b->d_dbound, b->d_val, b->d_gnet, b->d_coef, b->d_larena, b->d_lscal};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -270,13 +412,15 @@ static int layout_lds(tn_batch *b, int variant) {
   o = al(o + std::max(1, b->n_params) * 8);
   b->red_off[variant] = o;
   o = al(o + 16 * 8);
+  b->gbar_off[variant] = o;
+  if (variant == 1) o = al(o + b->hp.max_ptens_elems * eb);
   if (o > kLdsCap) {
     set_error("fused executor: LDS layout of " + std::to_string(o) + " bytes exceeds 160 KiB");
     return TN_ENOMEM;
   }
   (variant == 0 ? b->lds_fwd : b->lds_grad) = o;
   int per_cu = 0;
-  const void *k = fused_kernel_ptr(b->dtype, b->block);
+  const void *k = fused_kernel_ptr(b->dtype, b->block, variant == 1);
   if (o > 64 * 1024) HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, o));
   HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, b->block, o));
   int dev = 0, cus = 0;
@@ -311,28 +455,36 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   b->offset = offset;
   b->coef.assign(n_nets, 0.0);
   if (coef) std::copy(coef, coef + n_nets, b->coef.begin());
+  const int eb = b->dtype == TN_C128 ? 16 : 8;
+  // QTN_FUSED_LDS_MAX (bytes) overrides the fused/level split, e.g. 0 sends
+  // every network to the level executor
+  int64_t fused_max = kFusedLdsMax;
+  if (const char *env = std::getenv("QTN_FUSED_LDS_MAX")) fused_max = std::atoll(env);
   std::vector<double> cost(n_nets);
+  std::vector<int> fused_ids;
+  int maxbits = 0;
   for (int i = 0; i < n_nets; ++i) {
     const Net *n = reinterpret_cast<const Net *>(nets[i]);
-    std::string why;
-    int rc = append_fused(*n, b->hp, why);
-    if (rc != TN_OK) {
-      set_error("tn_batch_create: network " + std::to_string(i) + " does not fit the fused executor (" + why + ")");
-      return rc;
-    }
+    NetLayout lay = make_layout(*n);
     cost[i] = n->gplan.flops + n->gplan.flops_grad + 1e3 * n->gplan.ops.size();
     b->flops_fwd += n->gplan.flops;
     b->bytes_fwd += n->gplan.bytes;
     b->flops_grad += n->gplan.flops_grad;
     b->bytes_grad += n->gplan.bytes_grad;
+    if (fused_lds_need(*n, lay, eb, b->n_params) <= fused_max) {
+      append_fused(*n, lay, b->hp);
+      fused_ids.push_back(i);
+      maxbits = std::max(maxbits, n->gplan.peak_bits);
+    } else {
+      b->hp.nets_fwd.push_back(DNet{});
+      b->hp.nets_grad.push_back(DNet{});
+      b->level.push_back(append_level(*n, lay, b->hp, i, eb, kLevelBudget, max_sets));
+    }
   }
-  // expensive networks first (longest-processing-time order for the work queue)
-  b->task_net.resize(n_nets);
-  std::iota(b->task_net.begin(), b->task_net.end(), 0);
+  // fused networks, expensive first (longest processing time first)
+  b->task_net = fused_ids;
   std::stable_sort(b->task_net.begin(), b->task_net.end(), [&](int x, int y) { return cost[x] > cost[y]; });
   // block size: enough threads for the typical op, few idle lanes
-  int maxbits = 0;
-  for (int i = 0; i < n_nets; ++i) maxbits = std::max(maxbits, reinterpret_cast<const Net *>(nets[i])->gplan.peak_bits);
   b->block = maxbits <= 6 ? 64 : (maxbits <= 9 ? 128 : 256);
   int rc;
   if ((rc = layout_lds(b.get(), 0)) != TN_OK) return rc;
@@ -345,7 +497,6 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   };
   hipError_t e;
   const HostProgram &hp = b->hp;
-  const int eb = b->dtype == TN_C128 ? 16 : 8;
   if ((e = dalloc(&b->d_nets_fwd, hp.nets_fwd.size())) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_nets_grad, hp.nets_grad.size())) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_ops, hp.ops.size())) != hipSuccess) return fail(e, "hipMalloc");
@@ -353,11 +504,26 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   if ((e = dalloc(&b->d_task_net, b->task_net.size())) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc((char **)&b->d_consts, hp.consts.size() / 2 * eb)) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_ptens, hp.ptens.size())) != hipSuccess) return fail(e, "hipMalloc");
-  if ((e = dalloc(&b->d_counter, 2)) != hipSuccess) return fail(e, "hipMalloc");
-  if ((e = hipMemset(b->d_counter, 0, 2 * sizeof(int))) != hipSuccess) return fail(e, "hipMemset");
+  if ((e = dalloc(&b->d_slots, hp.slots.size())) != hipSuccess) return fail(e, "hipMalloc");
+  if ((e = dalloc((char **)&b->d_bound, (size_t)max_sets * std::max(1, hp.per_set) * eb)) != hipSuccess)
+    return fail(e, "hipMalloc");
+  if ((e = dalloc((char **)&b->d_dbound, (size_t)max_sets * std::max(1, hp.per_set) * eb)) != hipSuccess)
+    return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_val, (size_t)n_nets * max_sets * 2)) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_gnet, (size_t)n_nets * max_sets * std::max(1, b->n_params))) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_coef, (size_t)n_nets)) != hipSuccess) return fail(e, "hipMalloc");
+  {
+    int64_t arena = 0, scal = 0;
+    for (auto &ln : b->level) {
+      arena = std::max(arena, ln.stride[1] * ln.chunk * eb);
+      scal = std::max(scal, (int64_t)ln.chunk * std::max(1, ln.n_comp) * 2);
+    }
+    b->level_bytes = arena;
+    if (!b->level.empty()) {
+      if ((e = dalloc((char **)&b->d_larena, (size_t)arena)) != hipSuccess) return fail(e, "hipMalloc (level arena)");
+      if ((e = dalloc(&b->d_lscal, (size_t)scal)) != hipSuccess) return fail(e, "hipMalloc");
+    }
+  }
   std::vector<float> cf;
   const void *csrc = hp.consts.data();
   if (b->dtype == TN_C64) {
@@ -372,6 +538,7 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
       {b->d_task_net, b->task_net.data(), b->task_net.size() * sizeof(int32_t)},
       {b->d_consts, csrc, hp.consts.size() / 2 * eb},
       {b->d_ptens, hp.ptens.data(), hp.ptens.size() * sizeof(DParam)},
+      {b->d_slots, hp.slots.data(), hp.slots.size() * sizeof(DParam)},
       {b->d_coef, b->coef.data(), b->coef.size() * sizeof(double)},
   };
   for (auto &u : ups)
@@ -397,26 +564,63 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
   a.tabs = b->d_tabs;
   a.consts = b->d_consts;
   a.ptens = b->d_ptens;
-  a.params = params;
+  a.bound = b->d_bound;
+  a.dbound = b->d_dbound;
+  a.per_set = b->hp.per_set;
   a.task_net = b->d_task_net;
-  a.counter = b->d_counter;
   // network-major output; the internal buffer is used when the caller's
   // layout would not match or no pointer is given
   a.out_val = out ? out : b->d_val;
   a.out_grad = gnet_out ? gnet_out : b->d_gnet;
   a.n_params = b->n_params;
   a.n_sets = n_sets;
-  a.n_tasks = b->n_nets * n_sets;
+  a.n_tasks = (int)b->task_net.size() * n_sets;
   a.scratch_off = b->scratch_off[v];
   a.scal_off = b->scal_off[v];
   a.gacc_off = b->gacc_off[v];
   a.red_off = b->red_off[v];
-  a.with_grad = grad ? 1 : 0;
-  const int grid = std::min(grad ? b->grid_grad : b->grid_fwd, a.n_tasks);
-  hipError_t e = launch_fused(b->dtype, b->block, a, grid, grad ? b->lds_grad : b->lds_fwd, st);
+  a.gbar_off = b->gbar_off[v];
+  hipError_t e = launch_bind(b->dtype, b->d_slots, (int)b->hp.slots.size(), params, b->n_params, n_sets,
+                             b->hp.per_set, b->d_bound, grad ? b->d_dbound : nullptr, st);
   if (e != hipSuccess) {
     b->poisoned = true;
-    return hip_fail(e, "fused executor launch");
+    return hip_fail(e, "binding launch");
+  }
+  if (a.n_tasks > 0) {
+    // resident workgroups, balanced so every one runs the same number of tasks
+    const int cap = std::max(1, std::min(grad ? b->grid_grad : b->grid_fwd, a.n_tasks));
+    const int rounds = (a.n_tasks + cap - 1) / cap;
+    const int grid = (a.n_tasks + rounds - 1) / rounds;
+    e = launch_fused(b->dtype, b->block, grad, a, grid, grad ? b->lds_grad : b->lds_fwd, st);
+    if (e != hipSuccess) {
+      b->poisoned = true;
+      return hip_fail(e, "fused executor launch");
+    }
+  }
+  const int eb = b->dtype == TN_C128 ? 16 : 8;
+  for (const LevelNet &ln : b->level) {
+    for (int s0 = 0; s0 < n_sets; s0 += ln.chunk) {
+      LevelArgs la{};
+      la.arena = b->d_larena;
+      la.stride = ln.stride[v];
+      la.n_sets = std::min(ln.chunk, n_sets - s0);
+      la.scal = b->d_lscal;
+      la.n_comp = ln.n_comp;
+      e = level_setup(b->dtype, la, (const char *)b->d_consts + (size_t)ln.const_begin * eb, ln.n_const,
+                      b->d_ptens + ln.ptens_begin, ln.n_ptens, b->d_bound, b->hp.per_set, s0, (int)ln.gbar_begin,
+                      grad ? (int)ln.ptens_elems : 0, st);
+      for (int o = 0; o < ln.n_ops[v] && e == hipSuccess; ++o) {
+        const DOp &op = b->hp.ops[ln.op_begin[v] + o];
+        e = level_op(b->dtype, la, op, b->d_tabs + op.tab, st);
+      }
+      if (e == hipSuccess)
+        e = level_finish(b->dtype, la, b->d_ptens + ln.ptens_begin, ln.n_ptens, b->d_dbound, b->hp.per_set, s0, ln.net,
+                         n_sets, b->n_params, a.out_val, a.out_grad, grad ? 1 : 0, st);
+      if (e != hipSuccess) {
+        b->poisoned = true;
+        return hip_fail(e, "level executor launch");
+      }
+    }
   }
   if (obj || (grad && gobj)) {
     e = launch_combine(a.out_val, a.out_grad, b->d_coef, b->offset, b->n_nets, n_sets, b->n_params, obj,
@@ -480,9 +684,11 @@ int batch_run_graph(tn_batch *b, int with_grad, const double *params, int n_sets
 int batch_info(const tn_batch *b, tn_batch_stats *s) {
   std::memset(s, 0, sizeof(*s));
   s->n_nets = b->n_nets;
-  s->n_fused = b->n_nets;
-  s->n_level = 0;
-  s->n_levels = 0;
+  s->n_fused = (int32_t)b->task_net.size();
+  s->n_level = (int32_t)b->level.size();
+  int levels = 0;
+  for (auto &ln : b->level) levels = std::max(levels, ln.n_ops[1]);
+  s->n_levels = levels;
   s->lds_bytes_fwd = b->lds_fwd;
   s->lds_bytes_grad = b->lds_grad;
   s->flops_fwd = b->flops_fwd;
@@ -609,7 +815,8 @@ int net_bind(Net &net, const double *params, int n_sets, void *dst, int64_t *per
   HIPCHK(dalloc(&d_dp, dp.size()));
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync(d_dp, dp.data(), dp.size() * sizeof(DParam), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = launch_bind(net.dtype, d_dp, (int)dp.size(), params, net.n_params, n_sets, (int)total, dst, st);
+  if (e == hipSuccess)
+    e = launch_bind(net.dtype, d_dp, (int)dp.size(), params, net.n_params, n_sets, (int)total, dst, nullptr, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(d_dp);
   if (e != hipSuccess) return hip_fail(e, "tn_bind_params");

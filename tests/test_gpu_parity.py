@@ -235,3 +235,30 @@ def test_bind_params_kernel():
         rx = tn.superop_1q(og.rot(og.X, 2 * b)).ravel()
         np.testing.assert_allclose(got[s][:256], zz, atol=1e-14)
         np.testing.assert_allclose(got[s][256:], rx, atol=1e-14)
+
+
+def test_level_executor_matches_fused(monkeypatch):
+    """The same batch on the level (global-memory) executor and on the fused one."""
+    qtn, qaoa = _qtn(), _qaoa()
+    n = 14
+    e = workloads.random_regular_graph(3, n, 8)
+    S = 5
+    ang = torch.tensor(workloads.qaoa_angles(8, S, 2), device="cuda", dtype=torch.float64)
+    ref = np.array([gradients.cost(n, e, list(a)) for a in ang.cpu().numpy()])
+    ps = np.array([gradients.parameter_shift(n, e, list(a)) for a in ang.cpu().numpy()])
+    res = {}
+    for mode, lim in (("fused", None), ("level", "0")):
+        if lim is None:
+            monkeypatch.delenv("QTN_FUSED_LDS_MAX", raising=False)
+        else:
+            monkeypatch.setenv("QTN_FUSED_LDS_MAX", lim)
+        model = qaoa.MaxCut(n, e, 2, qtn.TN_C128, order="linegraph", max_sets=S)
+        info = model.batch.info()
+        if mode == "level":
+            assert info["n_level"] == len(e) and info["n_fused"] == 0
+        _say(f"executor {mode} n_fused={info['n_fused']} n_level={info['n_level']}")
+        obj, grad = model.value_and_grad(ang)
+        torch.cuda.synchronize()
+        res[mode] = (obj.cpu().numpy(), grad.cpu().numpy())
+        assert np.max(np.abs(res[mode][0] - ref)) <= 1e-12 * max(1, np.abs(ref).max())
+        assert np.max(np.abs(res[mode][1] - ps)) <= 1e-10 * max(1, np.abs(ps).max())
