@@ -78,6 +78,23 @@ def cpu_baseline(edges, angles, budget_s=12.0):
                       f"finite-difference gradient (5 FP64 contractions each), {workers} processes"}
 
 
+def traffic_from_profile():
+    """HBM bytes per launch of the fused adjoint kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.fused_exec_grad.json")
+    src = os.path.join(ROOT, "paper_1709_03636_amd", "csrc", "kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_src_sha256_prefix") != sha:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def copy_calibration(steps):
     """A plain device copy of known size, for scaling HBM traffic counters."""
     import torch
@@ -235,7 +252,7 @@ def main():
         "plain_one_network_per_launch": plain,
         "error_vs_fp64_oracle": {"max_abs_zz": err_zz, "max_rel_cost": err_c, "max_rel_grad": err_g},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK, "traffic": None,
+                     "frac": achieved / HBM_PEAK, "traffic": traffic_from_profile(),
                      "kernel": "fused_exec_kernel (adjoint program)", "kernel_us": k_ms * 1e3,
                      "algorithmic_bytes_per_launch": alg_bytes, "algorithmic_flops_per_launch": alg_flops},
         "cpu_baseline": cpu,

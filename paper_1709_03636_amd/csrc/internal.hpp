@@ -24,6 +24,12 @@ namespace qtn {
 
 using cd = std::complex<double>;
 
+// Summed-index offset tables are split in a low part of at most this many
+// bits and a high part (see Op::tab).
+constexpr int kTabLoBits = 12;
+// Largest intermediate (log2 entries) a plan may create: 32-bit addressing.
+constexpr int kMaxTensorBits = 31;
+
 // Op types of the compiled program.
 enum OpType : int32_t {
   OP_CONTRACT = 0,  // Z[F_X, F_Y] = sum_S X[F_X, S] Y[S, F_Y]   (eq. (1))
@@ -54,7 +60,9 @@ struct Op {
   int x, y, z;            // buffer ids (z: scalar slot for OP_SCALAR; component for OP_SEED)
   int nFX, nS, nFY;       // bits: free of X, summed, free of Y
   uint32_t maskX_F = 0, maskY_F = 0;  // address positions of the free bits in X / Y
-  std::vector<int32_t> tab;  // OP_CONTRACT/OP_SCALAR: 2*2^nS offsets (X, Y) per summed index k
+  std::vector<int32_t> tab;  // OP_CONTRACT/OP_SCALAR: (X, Y) offset pairs of the summed index k:
+                             //   2^min(nS,12) pairs for the low bits of k, then (nS > 12)
+                             //   2^(nS-12) pairs for the high bits; offsets add
                              // OP_LEAFGRAD: 2^bits canonical index per buffer index
   int aux0 = 0, aux1 = 0; // OP_LEAFGRAD: param tensor id, leaf id; OP_SEED: component
   bool fwd = true;        // part of the forward pass

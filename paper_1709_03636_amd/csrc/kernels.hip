@@ -66,6 +66,15 @@ __device__ __forceinline__ S cload(const S *p) {
   return r;
 }
 
+// (X, Y) offsets of summed index k from an op's table (low/high split
+// beyond kTabLoBits summed bits).
+__device__ __forceinline__ int2 tab_at(const int32_t *__restrict__ tb, int nS, int k) {
+  if (nS <= kTabLoBits) return make_int2(tb[2 * k], tb[2 * k + 1]);
+  const int lo = k & ((1 << kTabLoBits) - 1), hi = k >> kTabLoBits;
+  const int32_t *h = tb + (2 << kTabLoBits);
+  return make_int2(tb[2 * lo] + h[2 * hi], tb[2 * lo + 1] + h[2 * hi + 1]);
+}
+
 // Deposit the low bits of v at the set positions of mask (lowest first).
 __device__ __forceinline__ uint32_t pdep32(uint32_t v, uint32_t mask) {
   uint32_t r = 0;
@@ -227,7 +236,10 @@ __device__ __forceinline__ void contract_general(V *mem, const DOp &op, const in
       const uint32_t fx = pdep32((uint32_t)c >> op.nFY, op.maskX);
       const uint32_t fy = pdep32((uint32_t)c & maskJ, op.maskY);
       V acc = czero<V>();
-      for (int k = 0; k < K; ++k) acc = cmul_add(acc, X[fx + tb[2 * k]], Y[fy + tb[2 * k + 1]]);
+      for (int k = 0; k < K; ++k) {
+        const int2 o = tab_at(tb, op.nS, k);
+        acc = cmul_add(acc, X[fx + o.x], Y[fy + o.y]);
+      }
       Z[c] = acc;
     }
   } else {
@@ -240,7 +252,10 @@ __device__ __forceinline__ void contract_general(V *mem, const DOp &op, const in
       const uint32_t fx = pdep32((uint32_t)c >> op.nFY, op.maskX);
       const uint32_t fy = pdep32((uint32_t)c & maskJ, op.maskY);
       V acc = czero<V>();
-      for (int k = g; k < K; k += G) acc = cmul_add(acc, X[fx + tb[2 * k]], Y[fy + tb[2 * k + 1]]);
+      for (int k = g; k < K; k += G) {
+        const int2 o = tab_at(tb, op.nS, k);
+        acc = cmul_add(acc, X[fx + o.x], Y[fy + o.y]);
+      }
       scratch[tid] = acc;
     }
     __syncthreads();
@@ -312,8 +327,9 @@ __global__ __launch_bounds__(BLOCK) void fused_exec_kernel(FusedArgs a) {
         const int K = 1 << op.nS;
         double re = 0.0, im = 0.0;
         for (int k = tid; k < K; k += BLOCK) {
-          const double2 x = to_d2(mem[op.x + tb[2 * k]]);
-          const double2 y = to_d2(mem[op.y + tb[2 * k + 1]]);
+          const int2 o = tab_at(tb, op.nS, k);
+          const double2 x = to_d2(mem[op.x + o.x]);
+          const double2 y = to_d2(mem[op.y + o.y]);
           re += x.x * y.x - x.y * y.y;
           im += x.x * y.y + x.y * y.x;
         }

@@ -37,7 +37,13 @@ template <typename V> __device__ __forceinline__ V l_from(double2 v);
 template <> __device__ __forceinline__ float2 l_from<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
 template <> __device__ __forceinline__ double2 l_from<double2>(double2 v) { return v; }
 
-#define QTN_LCONST __attribute__((address_space(4)))
+
+__device__ __forceinline__ int2 l_tab(const int32_t *__restrict__ tb, int nS, int k) {
+  if (nS <= kTabLoBits) return make_int2(tb[2 * k], tb[2 * k + 1]);
+  const int lo = k & ((1 << kTabLoBits) - 1), hi = k >> kTabLoBits;
+  const int32_t *h = tb + (2 << kTabLoBits);
+  return make_int2(tb[2 * lo] + h[2 * hi], tb[2 * lo + 1] + h[2 * hi + 1]);
+}
 
 __device__ __forceinline__ uint32_t l_pdep(uint32_t v, uint32_t mask) {
   uint32_t r = 0;
@@ -59,7 +65,6 @@ __global__ __launch_bounds__(256) void level_contract_kernel(LevelArgs a, DOp op
   const int64_t total = nOut * a.n_sets;
   const int K = 1 << op.nS;
   const uint32_t maskJ = (1u << op.nFY) - 1u;
-  const QTN_LCONST int32_t *tb = (const QTN_LCONST int32_t *)tab;
   V *arena = reinterpret_cast<V *>(a.arena);
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
     const int64_t set = g >> lgOut;
@@ -70,7 +75,10 @@ __global__ __launch_bounds__(256) void level_contract_kernel(LevelArgs a, DOp op
     V acc;
     acc.x = 0;
     acc.y = 0;
-    for (int k = 0; k < K; ++k) acc = l_fma(acc, X[tb[2 * k]], Y[tb[2 * k + 1]]);
+    for (int k = 0; k < K; ++k) {
+      const int2 o = l_tab(tab, op.nS, k);
+      acc = l_fma(acc, X[o.x], Y[o.y]);
+    }
     base[op.z + c] = acc;
   }
 }
@@ -84,8 +92,9 @@ __global__ __launch_bounds__(256) void level_scalar_kernel(LevelArgs a, DOp op, 
   const int K = 1 << op.nS;
   double re = 0.0, im = 0.0;
   for (int k = threadIdx.x; k < K; k += 256) {
-    const double2 x = l_d2(base[op.x + tab[2 * k]]);
-    const double2 y = l_d2(base[op.y + tab[2 * k + 1]]);
+    const int2 o = l_tab(tab, op.nS, k);
+    const double2 x = l_d2(base[op.x + o.x]);
+    const double2 y = l_d2(base[op.y + o.y]);
     re += x.x * y.x - x.y * y.y;
     im += x.x * y.y + x.y * y.x;
   }

@@ -64,17 +64,24 @@ struct Emitter {
     std::sort(S.begin(), S.end(), [&](int a, int b) {
       return pos_of(find_label(lx, a), rx) < pos_of(find_label(lx, b), rx);
     });
-    const int K = 1 << op.nS;
-    op.tab.resize(2 * (size_t)K);
-    for (int k = 0; k < K; ++k) {
-      int32_t ox = 0, oy = 0;
-      for (int t = 0; t < op.nS; ++t)
-        if ((k >> t) & 1) {
+    // offsets of the summed index k: one (X, Y) pair per k, or, for more
+    // than kTabLoBits summed bits, a table for the low bits of k plus one
+    // for the high bits (offsets add over disjoint bit sets)
+    auto offs = [&](int t0, int t1, int32_t kk, int32_t &ox, int32_t &oy) {
+      ox = oy = 0;
+      for (int t = t0; t < t1; ++t)
+        if ((kk >> (t - t0)) & 1) {
           ox |= 1 << pos_of(find_label(lx, S[t]), rx);
           oy |= 1 << pos_of(find_label(ly, S[t]), ry);
         }
-      op.tab[2 * k] = ox;
-      op.tab[2 * k + 1] = oy;
+    };
+    const int lo = std::min(op.nS, kTabLoBits);
+    const int hi = op.nS - lo;
+    op.tab.resize(2 * ((size_t)1 << lo) + (hi > 0 ? 2 * ((size_t)1 << hi) : 0));
+    for (int32_t k = 0; k < (1 << lo); ++k) offs(0, lo, k, op.tab[2 * k], op.tab[2 * k + 1]);
+    if (hi > 0) {
+      int32_t *h = op.tab.data() + 2 * ((size_t)1 << lo);
+      for (int32_t k = 0; k < (1 << hi); ++k) offs(lo, op.nS, k, h[2 * k], h[2 * k + 1]);
     }
     std::vector<int> lz = FX;
     lz.insert(lz.end(), FY.begin(), FY.end());
@@ -142,6 +149,14 @@ int compile_plan(const Net &net, const std::vector<int> &pi, bool with_grad, Pla
       return TN_EORDER;
     }
     seen[w] = 1;
+  }
+  {
+    OrderCost c = order_cost(net, pi);
+    if (c.peak_bits > kMaxTensorBits) {
+      set_error("tn_set_order: order creates an intermediate of 2^" + std::to_string(c.peak_bits) +
+                " entries (limit 2^" + std::to_string(kMaxTensorBits) + ")");
+      return TN_ENOMEM;
+    }
   }
   plan = Plan();
   Emitter em(plan, net);
