@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 D, N_VERT, P_LAYERS, N_SETS, GRAPH_SEED, ANGLE_SEED = 3, 100, 1, 64, 0, 0
 HBM_PEAK = 8.0e12
+FP32_MFMA_PEAK = 157.3e12
 
 
 def log(msg):
@@ -115,6 +116,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -224,6 +226,35 @@ def main():
                        "max_abs_err_zz": float(np.max(np.abs(np.array(vals).real - zz)))}
         log(f"plain {name}: {plain[name]}")
 
+    # dense regime (MFMA path): whole-circuit network of one edge, 6-regular n=20, p=1
+    mfma = None
+    if not args.no_dense:
+        dd, dn = 6, 20
+        de = workloads.random_regular_graph(dd, dn, GRAPH_SEED)
+        dnet = qaoa.edge_network(dn, de, 1, de[0], dtype=qtn.TN_C64, lightcone=False)
+        dnet.set_order(dnet.order_linegraph(trials=8, seed=0))
+        dinfo = dnet.plan_info()
+        dbatch = qtn.Batch([dnet], max_sets=1)
+        dpar = torch.tensor([angles[0]], dtype=torch.float64, device=dev)
+        dout = torch.empty((1, 1, 2), dtype=torch.float64, device=dev)
+        dbatch.contract(dpar, out=dout, stream=st)
+        st.synchronize()
+        reps = 5
+        ev0.record(st)
+        for _ in range(reps):
+            dbatch.contract(dpar, out=dout, stream=st)
+        ev1.record(st)
+        torch.cuda.synchronize()
+        d_ms = ev0.elapsed_time(ev1) / reps
+        zz_ref = closed_form.zz_p1(dn, de, angles[0, 0], angles[0, 1])[0]
+        mfma = {"workload": f"whole-circuit folded network of one edge, QAOA p=1, {dd}-regular n={dn} "
+                            f"(no light cone), line-graph order, complex64, 4M FP32 MFMA",
+                "peak_bits": dinfo["peak_bits"], "flops_per_pass": dinfo["flops"], "pass_ms": d_ms,
+                "tflops": dinfo["flops"] / (d_ms * 1e-3) / 1e12,
+                "frac_of_fp32_matrix_peak": dinfo["flops"] / (d_ms * 1e-3) / FP32_MFMA_PEAK,
+                "abs_err_zz_vs_closed_form": abs(dout[0, 0, 0].item() - zz_ref)}
+        log(f"dense/MFMA: {mfma}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle) ...")
@@ -255,6 +286,7 @@ def main():
                      "frac": achieved / HBM_PEAK, "traffic": traffic_from_profile(),
                      "kernel": "fused_exec_kernel (adjoint program)", "kernel_us": k_ms * 1e3,
                      "algorithmic_bytes_per_launch": alg_bytes, "algorithmic_flops_per_launch": alg_flops},
+        "mfma_path": mfma,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -61,6 +61,10 @@ struct LevelArgs {
   int n_sets;      // parameter vectors in this chunk
   double *scal;    // [set][n_comp] component scalars (complex, FP64)
   int n_comp;
+  double *part;    // [set][kScalarParts] partial sums of a large rank-0 contraction
 };
+
+// Workgroups per parameter vector for a large rank-0 contraction.
+constexpr int kScalarParts = 256;
 
 }  // namespace qtn

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "device.hpp"
 #include "internal.hpp"
@@ -83,16 +84,21 @@ __global__ __launch_bounds__(256) void level_contract_kernel(LevelArgs a, DOp op
   }
 }
 
-// Rank-0 result: one workgroup per parameter vector, FP64 fixed-tree sum.
+// Rank-0 result, FP64: workgroup g of parameter vector s sums the summed
+// entries g, g + G*256, ... into part[s][g]; a second kernel adds the G
+// partial sums in index order (a fixed tree: results do not depend on
+// scheduling).
 template <typename V>
-__global__ __launch_bounds__(256) void level_scalar_kernel(LevelArgs a, DOp op, const int32_t *__restrict__ tab) {
+__global__ __launch_bounds__(256) void level_scalar_part_kernel(LevelArgs a, DOp op, const int32_t *__restrict__ tab,
+                                                                double *__restrict__ part) {
   __shared__ double red[2][4];
-  const int set = blockIdx.x;
+  const int set = blockIdx.y;
+  const int G = gridDim.x;
   const V *base = reinterpret_cast<const V *>(a.arena) + set * a.stride;
-  const int K = 1 << op.nS;
+  const int64_t K = (int64_t)1 << op.nS;
   double re = 0.0, im = 0.0;
-  for (int k = threadIdx.x; k < K; k += 256) {
-    const int2 o = l_tab(tab, op.nS, k);
+  for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < K; k += (int64_t)G * 256) {
+    const int2 o = l_tab(tab, op.nS, (int)k);
     const double2 x = l_d2(base[op.x + o.x]);
     const double2 y = l_d2(base[op.y + o.y]);
     re += x.x * y.x - x.y * y.y;
@@ -108,14 +114,21 @@ __global__ __launch_bounds__(256) void level_scalar_kernel(LevelArgs a, DOp op, 
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double r = 0.0, i = 0.0;
-    for (int w = 0; w < 4; ++w) {
-      r += red[0][w];
-      i += red[1][w];
-    }
-    a.scal[((size_t)set * a.n_comp + op.z) * 2] = r;
-    a.scal[((size_t)set * a.n_comp + op.z) * 2 + 1] = i;
+    part[((size_t)set * G + blockIdx.x) * 2] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    part[((size_t)set * G + blockIdx.x) * 2 + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
   }
+}
+
+__global__ void level_scalar_final_kernel(LevelArgs a, DOp op, const double *__restrict__ part, int G) {
+  const int set = blockIdx.x * blockDim.x + threadIdx.x;
+  if (set >= a.n_sets) return;
+  double re = 0.0, im = 0.0;
+  for (int g = 0; g < G; ++g) {
+    re += part[((size_t)set * G + g) * 2];
+    im += part[((size_t)set * G + g) * 2 + 1];
+  }
+  a.scal[((size_t)set * a.n_comp + op.z) * 2] = re;
+  a.scal[((size_t)set * a.n_comp + op.z) * 2 + 1] = im;
 }
 
 // Adjoint seed of component aux0: product of the other component scalars.
@@ -229,6 +242,9 @@ __global__ __launch_bounds__(256) void level_finish_kernel(LevelArgs a, const DP
 }
 
 // --- host launchers ------------------------------------------------------------------------
+bool mfma_eligible(int dtype, const DOp &op);
+hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream_t st);
+
 static inline int grid_for(int64_t total) {
   int64_t g = (total + 255) / 256;
   return (int)(g < 65536 ? (g < 1 ? 1 : g) : 65536);
@@ -242,9 +258,14 @@ static hipError_t level_op_t(const LevelArgs &a, const DOp &op, const int32_t *t
       hipLaunchKernelGGL(level_contract_kernel<V>, dim3(grid_for(total)), dim3(256), 0, st, a, op, tab);
       break;
     }
-    case OP_SCALAR:
-      hipLaunchKernelGGL(level_scalar_kernel<V>, dim3(a.n_sets), dim3(256), 0, st, a, op, tab);
+    case OP_SCALAR: {
+      // enough workgroups for large sums, at most kScalarParts per set
+      const int64_t K = (int64_t)1 << op.nS;
+      const int G = (int)std::min<int64_t>(kScalarParts, std::max<int64_t>(1, K / 4096));
+      hipLaunchKernelGGL(level_scalar_part_kernel<V>, dim3(G, a.n_sets), dim3(256), 0, st, a, op, tab, a.part);
+      hipLaunchKernelGGL(level_scalar_final_kernel, dim3((a.n_sets + 63) / 64), dim3(64), 0, st, a, op, a.part, G);
       break;
+    }
     case OP_SEED:
       hipLaunchKernelGGL(level_seed_kernel<V>, dim3((a.n_sets + 63) / 64), dim3(64), 0, st, a, op);
       break;
@@ -258,6 +279,7 @@ static hipError_t level_op_t(const LevelArgs &a, const DOp &op, const int32_t *t
 }
 
 hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream_t st) {
+  if (mfma_eligible(dtype, op) && !std::getenv("QTN_NO_MFMA")) return mfma_contract(a, op, tab, st);
   return dtype == TN_C128 ? level_op_t<double2>(a, op, tab, st) : level_op_t<float2>(a, op, tab, st);
 }
 

@@ -370,6 +370,7 @@ struct tn_batch {
   double *d_val = nullptr, *d_gnet = nullptr, *d_coef = nullptr;
   void *d_larena = nullptr;            // level executor arena
   double *d_lscal = nullptr;           // level executor component scalars
+  double *d_lpart = nullptr;           // level executor partial sums
   int lds_fwd = 0, lds_grad = 0, grid_fwd = 0, grid_grad = 0;
   int scratch_off[2], scal_off[2], gacc_off[2], red_off[2], gbar_off[2];
   double flops_fwd = 0, bytes_fwd = 0, flops_grad = 0, bytes_grad = 0;
@@ -394,7 +395,8 @@ static int hip_fail(hipError_t e, const char *what) {
 static void free_batch_dev(tn_batch *b) {
   b->gc.clear();
   void *ptrs[] = {b->d_nets_fwd, b->d_nets_grad, b->d_ops, b->d_tabs, b->d_task_net, b->d_consts, b->d_ptens,
-                  b->d_slots, b->d_bound, b->d_dbound, b->d_val, b->d_gnet, b->d_coef, b->d_larena, b->d_lscal};
+                  b->d_slots, b->d_bound, b->d_dbound, b->d_val, b->d_gnet, b->d_coef, b->d_larena, b->d_lscal,
+                  b->d_lpart};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -513,15 +515,17 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   if ((e = dalloc(&b->d_gnet, (size_t)n_nets * max_sets * std::max(1, b->n_params))) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_coef, (size_t)n_nets)) != hipSuccess) return fail(e, "hipMalloc");
   {
-    int64_t arena = 0, scal = 0;
+    int64_t arena = 0, scal = 0, part = 0;
     for (auto &ln : b->level) {
       arena = std::max(arena, ln.stride[1] * ln.chunk * eb);
       scal = std::max(scal, (int64_t)ln.chunk * std::max(1, ln.n_comp) * 2);
+      part = std::max(part, (int64_t)ln.chunk * kScalarParts * 2);
     }
     b->level_bytes = arena;
     if (!b->level.empty()) {
       if ((e = dalloc((char **)&b->d_larena, (size_t)arena)) != hipSuccess) return fail(e, "hipMalloc (level arena)");
       if ((e = dalloc(&b->d_lscal, (size_t)scal)) != hipSuccess) return fail(e, "hipMalloc");
+      if ((e = dalloc(&b->d_lpart, (size_t)part)) != hipSuccess) return fail(e, "hipMalloc");
     }
   }
   std::vector<float> cf;
@@ -606,6 +610,7 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
       la.n_sets = std::min(ln.chunk, n_sets - s0);
       la.scal = b->d_lscal;
       la.n_comp = ln.n_comp;
+      la.part = b->d_lpart;
       e = level_setup(b->dtype, la, (const char *)b->d_consts + (size_t)ln.const_begin * eb, ln.n_const,
                       b->d_ptens + ln.ptens_begin, ln.n_ptens, b->d_bound, b->hp.per_set, s0, (int)ln.gbar_begin,
                       grad ? (int)ln.ptens_elems : 0, st);

@@ -262,3 +262,36 @@ def test_level_executor_matches_fused(monkeypatch):
         res[mode] = (obj.cpu().numpy(), grad.cpu().numpy())
         assert np.max(np.abs(res[mode][0] - ref)) <= 1e-12 * max(1, np.abs(ref).max())
         assert np.max(np.abs(res[mode][1] - ps)) <= 1e-10 * max(1, np.abs(ps).max())
+
+
+# --- dense regime: whole-circuit networks, large steps on the matrix cores -----------------
+
+@pytest.mark.parametrize("d,n", [(6, 12), (5, 14)])
+def test_dense_whole_circuit_mfma(d, n, monkeypatch):
+    """Whole-circuit folded networks (trace on every other qubit, no light cone):
+    large intermediates, complex GEMM steps on MFMA (complex64) vs the state vector."""
+    qtn, qaoa = _qtn(), _qaoa()
+    e = workloads.random_regular_graph(d, n, 0)
+    ang = np.array(workloads.qaoa_angles(3, 2, 1))
+    S = len(ang)
+    edges = e[:3]
+    ref = np.array([statevector.qaoa_zz(n, e, [a[0]], [a[1]]) for a in ang])  # [set][edge]
+    for dtype, tol in (("c64", 2e-5), ("c128", 1e-12)):
+        dt = qtn.TN_C64 if dtype == "c64" else qtn.TN_C128
+        nets = []
+        for ed in edges:
+            net = qaoa.edge_network(n, e, 1, ed, dtype=dt, lightcone=False)
+            net.set_order(net.order_linegraph(trials=4, seed=0))
+            dims = net.plan_steps()
+            assert any(fx >= 6 and s >= 4 and fy >= 6 for fx, s, fy in dims), "no MFMA-sized step"
+            nets.append(net)
+        batch = qtn.Batch(nets, max_sets=S)
+        info = batch.info()
+        _say(f"dense d={d} n={n} {dtype} n_level={info['n_level']} peak={max(x.plan_info()['peak_bits'] for x in nets)}")
+        out = torch.empty((len(nets), S, 2), dtype=torch.float64, device="cuda")
+        batch.contract(torch.tensor(ang, device="cuda"), out=out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        for s in range(S):
+            assert np.max(np.abs(got[:, s, 0] - ref[s, :3])) < tol, (dtype, got[:, s, 0], ref[s, :3])
+            assert np.max(np.abs(got[:, s, 1])) < tol
