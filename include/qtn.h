@@ -186,6 +186,8 @@ typedef struct {
   int32_t n_nets, n_fused, n_level;   /* networks on the fused and the level-synchronous path */
   int32_t n_levels;                   /* level launches per pass */
   int32_t lds_bytes_fwd, lds_bytes_grad;
+  int32_t n_programs;                 /* distinct fused programs (identical networks share one) */
+  int32_t reserved;
   double flops_fwd, bytes_fwd;        /* algorithmic, one parameter vector, all networks */
   double flops_grad, bytes_grad;      /* algorithmic, adjoint sweep only */
 } tn_batch_stats;

@@ -16,6 +16,32 @@ struct DOp {
   int32_t aux0, aux1;
 };
 
+// The free-bit masks of an op as runs of consecutive address bits, lowest
+// first, packed (shift | len << 8 | pos << 16): deposit(v) = OR over runs of
+// bits [shift, shift+len) of v moved to [pos, pos+len). Unused runs have
+// len 0; runsX[0] == -1 when the mask has more than kMaxRuns runs. Passed to
+// the level executor's kernels with each launch.
+struct DRuns {
+  int32_t runsX[4], runsY[4];
+};
+constexpr int kMaxRuns = 4;
+
+// Runs of a bit mask in the DOp encoding (host and device).
+inline void pack_runs(uint32_t mask, int32_t out[4]) {
+  int n = 0, shift = 0;
+  for (int j = 0; j < 4; ++j) out[j] = 0;
+  int p = 0;
+  while (p < 32) {
+    if (!((mask >> p) & 1u)) { ++p; continue; }
+    int q = p;
+    while (q < 32 && ((mask >> q) & 1u)) ++q;
+    if (n == 4) { out[0] = -1; return; }
+    out[n++] = shift | ((q - p) << 8) | (p << 16);
+    shift += q - p;
+    p = q;
+  }
+}
+
 // A parametric tensor: entries of exp(-i theta P / 2) (folded: its
 // superoperator) with theta = coeff * params[param]. In the binding kernel
 // `off` is its offset in a parameter vector's slice of the bound-tensor
@@ -51,6 +77,7 @@ struct FusedArgs {
   double *out_val;          // [net][set][2]
   double *out_grad;         // [net][set][n_params] (adjoint programs)
   int n_params, n_sets, n_tasks, per_set;
+  int per_block;            // workgroup b runs tasks [b*per_block, (b+1)*per_block)
   int scratch_off, scal_off, gacc_off, red_off, gbar_off;  // LDS byte offsets
 };
 

@@ -2,7 +2,7 @@
 // executor (forward and adjoint), and the FP64 objective combine.
 //
 // Fused executor: one workgroup runs one (network, parameter vector) task at
-// a time (persistent grid, static striding over tasks sorted by cost). All
+// a time (persistent grid, contiguous runs of tasks sorted by cost). All
 // tensors of the task live in LDS: constant leaves and the parametric leaves
 // bound for its parameter vector are copied in, and every pairwise
 // contraction (eq. (1))
@@ -201,7 +201,11 @@ __device__ __forceinline__ void contract_small_k(V *mem, const DOp &op, const in
     const uint32_t fy = pdep32((uint32_t)c & maskJ, op.maskY);
     // operand reads in chunks of up to 8 entries, all issued before the
     // multiply-adds that consume them
+#ifdef QTN_CHUNK
+    constexpr int CH = K < QTN_CHUNK ? K : QTN_CHUNK;
+#else
     constexpr int CH = K < 8 ? K : 8;
+#endif
     V acc = czero<V>();
 #pragma unroll
     for (int k0 = 0; k0 < K; k0 += CH) {
@@ -279,12 +283,16 @@ __device__ __forceinline__ void op_contract(V *mem, const DOp &op, const int32_t
   }
 }
 
-// Fused executor. GRAD selects the forward+adjoint program: adjoints of
-// parametric leaves are accumulated, in canonical layout, per distinct
-// parametric tensor (several gates share one angle), and contracted with
-// dG/dtheta once per task, in FP64.
+// Fused executor. GRAD selects the forward+adjoint program: the adjoint of
+// each parametric leaf is contracted with the leaf's angle derivative (bound
+// by the binding kernel) as soon as it is formed, and summed per parameter in
+// FP64.
 template <typename T, int BLOCK, bool GRAD>
-__global__ __launch_bounds__(BLOCK) void fused_exec_kernel(FusedArgs a) {
+__global__ __launch_bounds__(BLOCK)
+#ifdef QTN_WAVES
+__attribute__((amdgpu_waves_per_eu(QTN_WAVES, QTN_WAVES)))
+#endif
+void fused_exec_kernel(FusedArgs a) {
   using V = typename Cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   V *mem = reinterpret_cast<V *>(smem);
@@ -292,14 +300,15 @@ __global__ __launch_bounds__(BLOCK) void fused_exec_kernel(FusedArgs a) {
   double2 *scal = reinterpret_cast<double2 *>(smem + a.scal_off);
   double *gacc = reinterpret_cast<double *>(smem + a.gacc_off);
   double *red = reinterpret_cast<double *>(smem + a.red_off);
-  V *gbar = reinterpret_cast<V *>(smem + a.gbar_off);
   const int tid = threadIdx.x;
   const V *consts = reinterpret_cast<const V *>(a.consts);
   const V *bound = reinterpret_cast<const V *>(a.bound);
   const V *dbound = reinterpret_cast<const V *>(a.dbound);
 
-  // tasks are ordered by decreasing cost; workgroup b takes b, b + grid, ...
-  for (int task = blockIdx.x; task < a.n_tasks; task += gridDim.x) {
+  // tasks are ordered by decreasing network cost, network-major; workgroup b
+  // takes a contiguous run, so its consecutive tasks mostly share one program
+  const int t_end = min(a.n_tasks, ((int)blockIdx.x + 1) * a.per_block);
+  for (int task = blockIdx.x * a.per_block; task < t_end; ++task) {
     const int ni = cptr(a.task_net)[task / a.n_sets];
     const int set = task % a.n_sets;
     const DNet net = cload(a.nets + ni);
@@ -308,18 +317,18 @@ __global__ __launch_bounds__(BLOCK) void fused_exec_kernel(FusedArgs a) {
     const V *bset = bound + (size_t)set * a.per_set;
     for (int t = 0; t < net.n_ptens; ++t) {
       const DParam d = cload(a.ptens + net.ptens_begin + t);
-      for (int e = tid; e < (1 << d.bits); e += BLOCK) {
-        mem[d.off + e] = bset[d.slot + e];
-        if (GRAD) gbar[d.goff + e] = czero<V>();
-      }
+      for (int e = tid; e < (1 << d.bits); e += BLOCK) mem[d.off + e] = bset[d.slot + e];
     }
+    if (GRAD)
+      for (int p = tid; p < a.n_params; p += BLOCK) gacc[p] = 0.0;
     __syncthreads();
 
+    // Descriptors are read when needed, not prefetched: scalar and LDS
+    // loads share one wait counter, so an outstanding descriptor load would
+    // delay every LDS wait of the current op.
     const DOp *ops = a.ops + net.op_begin;
-    DOp nxt = cload(ops);
     for (int o = 0; o < net.n_ops; ++o) {
-      const DOp op = nxt;
-      if (o + 1 < net.n_ops) nxt = cload(ops + o + 1);  // next descriptor in flight during this op
+      const DOp op = cload(ops + o);
       const int32_t *tb = a.tabs + op.tab;
       if (op.type == OP_CONTRACT) {
         op_contract<V, BLOCK>(mem, op, tb, scratch);
@@ -343,10 +352,17 @@ __global__ __launch_bounds__(BLOCK) void fused_exec_kernel(FusedArgs a) {
             if (j != op.aux0) p = cmul(p, scal[j]);
           mem[op.z] = from_d2<V>(p);
         }
-      } else if (GRAD) {  // OP_LEAFGRAD: add the leaf adjoint into its tensor's accumulator
+      } else if (GRAD) {  // OP_LEAFGRAD: theta-derivative of the leaf, contracted with its adjoint
         const DParam d = cload(a.ptens + op.aux0);
-        V *acc = gbar + d.goff;
-        for (int i = tid; i < (1 << op.nFX); i += BLOCK) acc[tb[i]] = cadd(acc[tb[i]], mem[op.x + i]);
+        const V *dv = dbound + (size_t)set * a.per_set + d.slot;
+        double acc = 0.0;
+        for (int i = tid; i < (1 << op.nFX); i += BLOCK) {
+          const double2 g = to_d2(mem[op.x + i]);
+          const double2 w = to_d2(dv[tb[i]]);
+          acc += g.x * w.x - g.y * w.y;
+        }
+        acc = block_sum<BLOCK>(acc, red);
+        if (tid == 0) gacc[d.param] += d.coeff * acc;
       }
       __syncthreads();
     }
@@ -358,25 +374,8 @@ __global__ __launch_bounds__(BLOCK) void fused_exec_kernel(FusedArgs a) {
       ov[0] = p.x;
       ov[1] = p.y;
     }
-    if (GRAD) {
-      for (int p = tid; p < a.n_params; p += BLOCK) gacc[p] = 0.0;
-      __syncthreads();
-      // d Re(s) / d theta_p = sum over tensors t with param p of coeff_t * Re <Gbar_t, dG_t/dtheta>
-      const V *dset = dbound + (size_t)set * a.per_set;
-      for (int t = 0; t < net.n_ptens; ++t) {
-        const DParam d = cload(a.ptens + net.ptens_begin + t);
-        double acc = 0.0;
-        for (int e = tid; e < (1 << d.bits); e += BLOCK) {
-          const double2 g = to_d2(gbar[d.goff + e]);
-          const double2 dv = to_d2(dset[d.slot + e]);
-          acc += g.x * dv.x - g.y * dv.y;
-        }
-        acc = block_sum<BLOCK>(acc, red);
-        if (tid == 0) gacc[d.param] += d.coeff * acc;
-      }
-      __syncthreads();
+    if (GRAD)
       for (int p = tid; p < a.n_params; p += BLOCK) a.out_grad[((size_t)ni * a.n_sets + set) * a.n_params + p] = gacc[p];
-    }
     __syncthreads();
   }
 }

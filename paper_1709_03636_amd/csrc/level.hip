@@ -58,9 +58,21 @@ __device__ __forceinline__ uint32_t l_pdep(uint32_t v, uint32_t mask) {
 }
 
 
+__device__ __forceinline__ uint32_t l_deposit(uint32_t v, const int32_t runs[4], uint32_t mask) {
+  if (runs[0] < 0) return l_pdep(v, mask);
+  uint32_t r = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t shift = runs[j] & 0xff, len = (runs[j] >> 8) & 0xff, pos = (uint32_t)runs[j] >> 16;
+    r |= __builtin_amdgcn_ubfe(v, shift, len) << pos;
+  }
+  return r;
+}
+
 // Z[set][c] = sum_k X[set][fx(c) + tx(k)] * Y[set][fy(c) + ty(k)]; one output per thread.
 template <typename V>
-__global__ __launch_bounds__(256) void level_contract_kernel(LevelArgs a, DOp op, const int32_t *__restrict__ tab) {
+__global__ __launch_bounds__(256) void level_contract_kernel(LevelArgs a, DOp op, DRuns ru,
+                                                             const int32_t *__restrict__ tab) {
   const int lgOut = op.nFX + op.nFY;
   const int64_t nOut = (int64_t)1 << lgOut;
   const int64_t total = nOut * a.n_sets;
@@ -71,8 +83,8 @@ __global__ __launch_bounds__(256) void level_contract_kernel(LevelArgs a, DOp op
     const int64_t set = g >> lgOut;
     const uint32_t c = (uint32_t)(g & (nOut - 1));
     V *base = arena + set * a.stride;
-    const V *X = base + op.x + l_pdep(c >> op.nFY, op.maskX);
-    const V *Y = base + op.y + l_pdep(c & maskJ, op.maskY);
+    const V *X = base + op.x + l_deposit(c >> op.nFY, ru.runsX, op.maskX);
+    const V *Y = base + op.y + l_deposit(c & maskJ, ru.runsY, op.maskY);
     V acc;
     acc.x = 0;
     acc.y = 0;
@@ -255,7 +267,10 @@ static hipError_t level_op_t(const LevelArgs &a, const DOp &op, const int32_t *t
   switch (op.type) {
     case OP_CONTRACT: {
       int64_t total = ((int64_t)1 << (op.nFX + op.nFY)) * a.n_sets;
-      hipLaunchKernelGGL(level_contract_kernel<V>, dim3(grid_for(total)), dim3(256), 0, st, a, op, tab);
+      DRuns ru;
+      pack_runs(op.maskX, ru.runsX);
+      pack_runs(op.maskY, ru.runsY);
+      hipLaunchKernelGGL(level_contract_kernel<V>, dim3(grid_for(total)), dim3(256), 0, st, a, op, ru, tab);
       break;
     }
     case OP_SCALAR: {

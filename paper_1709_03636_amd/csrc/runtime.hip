@@ -160,6 +160,8 @@ struct HostProgram {
   std::map<std::tuple<int, int, double, int>, int> slot_of;
   int per_set = 0;
   int max_mem_fwd = 0, max_mem_grad = 0, max_comp = 0, max_ptens_elems = 0;
+  std::map<std::string, int> program_of;  // fused program signature -> first network using it
+  int n_programs = 0;
 };
 
 struct LevelNet {
@@ -238,14 +240,18 @@ static void emit_ops(const Plan &p, int n_ops, HostProgram &hp, BOff boff, LG le
 // LDS bytes the fused adjoint program of a network needs.
 static int64_t fused_lds_need(const Net &net, const NetLayout &lay, int eb, int n_params) {
   int64_t mem = lay.leaf_region + std::max(lay.arena[0], lay.arena[1]);
-  return mem * eb + 256 * eb + (int64_t)std::max(1, net.gplan.n_components) * 16 + (int64_t)n_params * 8 + 256 +
-         lay.ptens_elems * eb + 64;
+  return mem * eb + 256 * eb + (int64_t)std::max(1, net.gplan.n_components) * 16 + (int64_t)n_params * 8 + 256 + 64;
 }
 
+// Append the fused programs (forward, forward+adjoint) of one network.
+// Networks whose programs are identical (same ops, offset tables, constants
+// and parametric tensors: e.g. isomorphic light cones contracted in the same
+// order) share one copy, which keeps the descriptors of a batch small enough
+// to stay in the scalar cache.
 static void append_fused(const Net &net, const NetLayout &lay, HostProgram &hp) {
   const Plan &p = net.gplan;
-  const int const_begin = append_consts(net, hp);
-  const int ptens_begin = (int)hp.ptens.size();
+  HostProgram loc;  // this network's program with local indices
+  std::vector<DParam> lptens;
   for (size_t t = 0; t < net.ptensors.size(); ++t) {
     const ParamTensor &pt = net.ptensors[t];
     DParam d{};
@@ -257,30 +263,57 @@ static void append_fused(const Net &net, const NetLayout &lay, HostProgram &hp) 
     d.goff = (int32_t)(lay.poff[t] - lay.n_const);
     d.coeff = pt.coeff;
     d.slot = slot_for(hp, pt);
-    hp.ptens.push_back(d);
+    lptens.push_back(d);
   }
+  int op_begin[2], n_ops[2];
+  for (int variant = 0; variant < 2; ++variant) {
+    op_begin[variant] = (int)loc.ops.size();
+    n_ops[variant] = variant == 0 ? p.n_fwd_ops : (int)p.ops.size();
+    emit_ops(
+        p, n_ops[variant], loc, [&](int v) { return (int32_t)abs_off(net, lay, variant, v); },
+        [&](const Op &op, DOp &d) { d.aux0 = op.aux0; });
+  }
+  append_consts(net, loc);
+  std::string sig;
+  auto put = [&](const void *q, size_t n) { sig.append(reinterpret_cast<const char *>(q), n); };
+  put(loc.ops.data(), loc.ops.size() * sizeof(DOp));
+  put(loc.tabs.data(), loc.tabs.size() * sizeof(int32_t));
+  put(loc.consts.data(), loc.consts.size() * sizeof(double));
+  put(lptens.data(), lptens.size() * sizeof(DParam));
+  put(n_ops, sizeof(n_ops));
+  auto it = hp.program_of.find(sig);
+  if (it != hp.program_of.end()) {
+    hp.nets_fwd.push_back(hp.nets_fwd[it->second]);
+    hp.nets_grad.push_back(hp.nets_grad[it->second]);
+    return;
+  }
+  const int tab0 = (int)hp.tabs.size(), op0 = (int)hp.ops.size(), ptens_begin = (int)hp.ptens.size();
+  const int const_begin = (int)(hp.consts.size() / 2);
+  for (DOp d : loc.ops) {
+    d.tab += tab0;
+    if (d.type == OP_LEAFGRAD) d.aux0 += ptens_begin;
+    hp.ops.push_back(d);
+  }
+  hp.tabs.insert(hp.tabs.end(), loc.tabs.begin(), loc.tabs.end());
+  hp.consts.insert(hp.consts.end(), loc.consts.begin(), loc.consts.end());
+  hp.ptens.insert(hp.ptens.end(), lptens.begin(), lptens.end());
   hp.max_ptens_elems = std::max(hp.max_ptens_elems, (int)lay.ptens_elems);
   for (int variant = 0; variant < 2; ++variant) {
-    const int n_ops = variant == 0 ? p.n_fwd_ops : (int)p.ops.size();
     DNet dn{};
-    dn.op_begin = (int32_t)hp.ops.size();
-    dn.n_ops = n_ops;
+    dn.op_begin = op0 + op_begin[variant];
+    dn.n_ops = n_ops[variant];
     dn.n_comp = p.n_components;
     dn.mem_elems = (int32_t)(lay.leaf_region + lay.arena[variant]);
     dn.const_begin = const_begin;
     dn.n_const = (int32_t)lay.n_const;
     dn.ptens_begin = ptens_begin;
     dn.n_ptens = (int32_t)net.ptensors.size();
-    emit_ops(
-        p, n_ops, hp, [&](int v) { return (int32_t)abs_off(net, lay, variant, v); },
-        [&](const Op &op, DOp &d) {
-          d.aux0 = ptens_begin + op.aux0;
-          d.aux1 = op.aux1;
-        });
     (variant == 0 ? hp.nets_fwd : hp.nets_grad).push_back(dn);
     int &mx = variant == 0 ? hp.max_mem_fwd : hp.max_mem_grad;
     mx = std::max(mx, dn.mem_elems);
   }
+  hp.program_of.emplace(sig, (int)hp.nets_fwd.size() - 1);
+  hp.n_programs++;
   hp.max_comp = std::max(hp.max_comp, p.n_components);
 }
 
@@ -415,7 +448,6 @@ static int layout_lds(tn_batch *b, int variant) {
   b->red_off[variant] = o;
   o = al(o + 16 * 8);
   b->gbar_off[variant] = o;
-  if (variant == 1) o = al(o + b->hp.max_ptens_elems * eb);
   if (o > kLdsCap) {
     set_error("fused executor: LDS layout of " + std::to_string(o) + " bytes exceeds 160 KiB");
     return TN_ENOMEM;
@@ -488,6 +520,10 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   std::stable_sort(b->task_net.begin(), b->task_net.end(), [&](int x, int y) { return cost[x] > cost[y]; });
   // block size: enough threads for the typical op, few idle lanes
   b->block = maxbits <= 6 ? 64 : (maxbits <= 9 ? 128 : 256);
+  if (const char *env = std::getenv("QTN_FUSED_BLOCK")) {
+    int v = std::atoi(env);
+    if (v == 64 || v == 128 || v == 256) b->block = v;
+  }
   int rc;
   if ((rc = layout_lds(b.get(), 0)) != TN_OK) return rc;
   if ((rc = layout_lds(b.get(), 1)) != TN_OK) return rc;
@@ -595,6 +631,7 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     const int cap = std::max(1, std::min(grad ? b->grid_grad : b->grid_fwd, a.n_tasks));
     const int rounds = (a.n_tasks + cap - 1) / cap;
     const int grid = (a.n_tasks + rounds - 1) / rounds;
+    a.per_block = rounds;
     e = launch_fused(b->dtype, b->block, grad, a, grid, grad ? b->lds_grad : b->lds_fwd, st);
     if (e != hipSuccess) {
       b->poisoned = true;
@@ -694,6 +731,7 @@ int batch_info(const tn_batch *b, tn_batch_stats *s) {
   int levels = 0;
   for (auto &ln : b->level) levels = std::max(levels, ln.n_ops[1]);
   s->n_levels = levels;
+  s->n_programs = b->hp.n_programs;
   s->lds_bytes_fwd = b->lds_fwd;
   s->lds_bytes_grad = b->lds_grad;
   s->flops_fwd = b->flops_fwd;

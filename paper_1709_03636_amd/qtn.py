@@ -11,7 +11,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqtn.so")
+LIB_PATH = os.environ.get("QTN_LIB", os.path.join(HERE, "libqtn.so"))
 
 TN_OK, TN_EINVAL, TN_ENOMEM, TN_EORDER, TN_EDEVICE, TN_ESTATE = 0, -1, -2, -3, -4, -5
 TN_H, TN_X, TN_Y, TN_Z, TN_RX, TN_RY, TN_RZ, TN_ZZ, TN_CNOT, TN_CZ, TN_U1, TN_U2 = range(12)
@@ -47,7 +47,7 @@ class tn_plan_stats(ctypes.Structure):
 
 class tn_batch_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("n_nets", "n_fused", "n_level", "n_levels", "lds_bytes_fwd",
-                                               "lds_bytes_grad")] + \
+                                               "lds_bytes_grad", "n_programs", "reserved")] + \
                [(n, ctypes.c_double) for n in ("flops_fwd", "bytes_fwd", "flops_grad", "bytes_grad")]
 
 
