@@ -194,6 +194,18 @@ typedef struct {
 
 int tn_batch_info(const tn_batch *b, tn_batch_stats *out);
 
+/* Autotuner (project-written; not in the paper). Times, on this batch and
+ * these device parameters, (1) each workgroup size of the fused executor and
+ * (2) for each shape class of large contractions on the level executor, the
+ * matrix-core kernel against the thin kernel, and keeps the fastest.
+ * Synchronous. cache_path (may be NULL): decisions are merged into this text
+ * file ("key value" lines). Plan-time work: run it before timing. */
+int tn_batch_autotune(tn_batch *b, const double *params, int32_t n_sets, int32_t reps, const char *cache_path,
+                      void *stream);
+
+/* Apply decisions from an autotuner cache file without timing. */
+int tn_batch_apply_tuning(tn_batch *b, const char *cache_path);
+
 /* One-shot conveniences: create a transient batch, run, free. Device pointers. */
 int tn_contract_batch(tn_net *const *nets, int32_t n_nets, const double *params, int32_t n_sets,
                       double *out, void *stream);

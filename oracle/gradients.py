@@ -63,3 +63,23 @@ def parameter_shift(n, edges, params):
             minus[idx] = (kd, q0, q1, th - np.pi / 2)
             g[slot] += _cost_from_gates(n, edges, plus) - _cost_from_gates(n, edges, minus)
     return g
+
+
+def parameter_shift_edge(n, edges, params, edge):
+    """d<Z_u Z_v>/d(gamma_k, beta_k) for one edge, by the shift rule on the
+    edge's light-cone circuit (state vector over the light cone only)."""
+    p = len(params) // 2
+    m, sub, uv, pos = statevector.qaoa_edge_lightcone_circuit(n, edges, params[:p], params[p:], edge,
+                                                              with_index=True)
+    per_layer = len(edges) + n
+    g = np.zeros(2 * p)
+    for idx, ((kd, q0, q1, th), full) in enumerate(zip(sub, pos)):
+        if kd == "H":
+            continue
+        k = (full - n) // per_layer
+        slot = k if kd == "ZZ" else p + k
+        plus, minus = list(sub), list(sub)
+        plus[idx] = (kd, q0, q1, th + np.pi / 2)
+        minus[idx] = (kd, q0, q1, th - np.pi / 2)
+        g[slot] += statevector.zz_of(m, plus, uv) - statevector.zz_of(m, minus, uv)
+    return g

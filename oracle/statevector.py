@@ -74,3 +74,37 @@ def qaoa_zz(n, edges, gammas, betas):
 def qaoa_cost(n, edges, gammas, betas):
     """<C> = sum over edges of (1 - <Z_u Z_v>)/2 (Sec. QAOA / Max-Cut)."""
     return float(np.sum((1.0 - qaoa_zz(n, edges, gammas, betas)) / 2.0))
+
+
+def qaoa_edge_lightcone_circuit(n, edges, gammas, betas, edge, with_index=False):
+    """(qubit count, gate list, (u', v')) of the backward light cone of one edge.
+
+    Gates outside the light cone of Z_u Z_v do not change <Z_u Z_v>
+    (unitarity); the kept gates act only on the support, relabelled 0..m-1.
+    with_index also returns each kept gate's position in the full QAOA gate
+    list (H layer first, then per layer |E| ZZ gates and n X rotations).
+    """
+    from .tensornet import light_cone
+    u, v = edge
+    gl = gates.qaoa_gate_list(n, edges, gammas, betas)
+    tagged = [g + (i,) for i, g in enumerate(gl)]
+    kept, sup = light_cone(n, tagged, {u, v})
+    qubits = sorted(sup)
+    idx = {q: i for i, q in enumerate(qubits)}
+    sub = [(g[0], idx[g[1]], idx[g[2]] if g[2] >= 0 else -1, g[3]) for g in kept]
+    if with_index:
+        return len(qubits), sub, (idx[u], idx[v]), [g[4] for g in kept]
+    return len(qubits), sub, (idx[u], idx[v])
+
+
+def zz_of(m, gate_list, uv):
+    prob = np.abs(run(m, gate_list)) ** 2
+    marg = np.moveaxis(prob, list(uv), [0, 1]).reshape(2, 2, -1).sum(axis=2)
+    sign = np.array([1.0, -1.0])
+    return float(sign @ marg @ sign)
+
+
+def qaoa_zz_edge(n, edges, gammas, betas, edge):
+    """<Z_u Z_v> of one edge from a state vector over its light cone only."""
+    m, sub, uv = qaoa_edge_lightcone_circuit(n, edges, gammas, betas, edge)
+    return zz_of(m, sub, uv)

@@ -21,6 +21,8 @@ int batch_grad(tn_batch *b, const double *params, int n_sets, double *out, doubl
 int batch_run_graph(tn_batch *b, int with_grad, const double *params, int n_sets, double *out, double *obj,
                     double *grad, void *stream);
 int batch_info(const tn_batch *b, tn_batch_stats *s);
+int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, const char *cache_path, void *stream);
+int batch_apply_cache(tn_batch *b, const char *cache_path);
 void batch_free(tn_batch *b);
 int net_contract(Net &net, const double *params, double *out, double *value, double *grad, void *stream);
 int net_bind(Net &net, const double *params, int n_sets, void *dst, int64_t *per_set, void *stream);
@@ -235,6 +237,23 @@ int tn_batch_run_graph(tn_batch *b, int32_t with_grad, const double *params, int
     return TN_EINVAL;
   }
   GUARD({ return qtn::batch_run_graph(b, with_grad, params, n_sets, out, obj, grad, stream); })
+}
+
+int tn_batch_autotune(tn_batch *b, const double *params, int32_t n_sets, int32_t reps, const char *cache_path,
+                      void *stream) {
+  if (!b) {
+    qtn::set_error("tn_batch_autotune: NULL batch");
+    return TN_EINVAL;
+  }
+  GUARD({ return qtn::batch_autotune(b, params, n_sets, reps, cache_path, stream); })
+}
+
+int tn_batch_apply_tuning(tn_batch *b, const char *cache_path) {
+  if (!b || !cache_path) {
+    qtn::set_error("tn_batch_apply_tuning: NULL argument");
+    return TN_EINVAL;
+  }
+  GUARD({ return qtn::batch_apply_cache(b, cache_path); })
 }
 
 int tn_batch_info(const tn_batch *b, tn_batch_stats *out) {

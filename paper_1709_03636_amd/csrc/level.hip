@@ -7,7 +7,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cstdlib>
 
 #include "device.hpp"
 #include "internal.hpp"
@@ -293,8 +292,10 @@ static hipError_t level_op_t(const LevelArgs &a, const DOp &op, const int32_t *t
   return hipGetLastError();
 }
 
-hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream_t st) {
-  if (mfma_eligible(dtype, op) && !std::getenv("QTN_NO_MFMA")) return mfma_contract(a, op, tab, st);
+// use_mfma: take the matrix-core kernel when the op is eligible (the
+// autotuner may decide against it for a shape class).
+hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tab, bool use_mfma, hipStream_t st) {
+  if (use_mfma && mfma_eligible(dtype, op)) return mfma_contract(a, op, tab, st);
   return dtype == TN_C128 ? level_op_t<double2>(a, op, tab, st) : level_op_t<float2>(a, op, tab, st);
 }
 

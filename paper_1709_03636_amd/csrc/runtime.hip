@@ -4,7 +4,9 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <map>
 #include <numeric>
@@ -22,7 +24,9 @@ hipError_t launch_combine(const double *val, const double *gnet, const double *c
                           int n_sets, int n_params, double *obj, double *grad, hipStream_t st);
 hipError_t launch_bind(int dtype, const DParam *slots, int n_slots, const double *params, int n_params, int n_sets,
                        int per_set, void *G, void *dG, hipStream_t st);
-hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream_t st);
+hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tab, bool use_mfma, hipStream_t st);
+bool mfma_eligible(int dtype, const DOp &op);
+hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream_t st);
 hipError_t level_setup(int dtype, const LevelArgs &a, const void *consts, int n_const, const DParam *pt, int n_pt,
                        const void *bound, int per_set, int set0, int zero_begin, int zero_n, hipStream_t st);
 hipError_t level_finish(int dtype, const LevelArgs &a, const DParam *pt, int n_pt, const void *dbound, int per_set,
@@ -408,6 +412,7 @@ struct tn_batch {
   int scratch_off[2], scal_off[2], gacc_off[2], red_off[2], gbar_off[2];
   double flops_fwd = 0, bytes_fwd = 0, flops_grad = 0, bytes_grad = 0;
   int64_t level_bytes = 0;
+  std::map<std::string, int> use_mfma;  // autotuner: shape class of a large op -> 1 MFMA, 0 thin
   bool poisoned = false;
   qtn::GraphCache gc;
 };
@@ -587,6 +592,13 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   return TN_OK;
 }
 
+// Key of a large op for the autotuner: dtype, free/summed bit counts and
+// which operands are read with the summed index contiguous.
+static std::string shape_class(int dtype, const DOp &op) {
+  return std::to_string(dtype) + ":" + std::to_string(op.nFX) + "," + std::to_string(op.nS) + "," +
+         std::to_string(op.nFY) + ":" + std::to_string(!(op.maskX & 1u)) + std::to_string(!(op.maskY & 1u));
+}
+
 static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, double *out, double *obj, double *gobj,
                      double *gnet_out, hipStream_t st) {
   if (b->poisoned) {
@@ -653,7 +665,8 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
                       grad ? (int)ln.ptens_elems : 0, st);
       for (int o = 0; o < ln.n_ops[v] && e == hipSuccess; ++o) {
         const DOp &op = b->hp.ops[ln.op_begin[v] + o];
-        e = level_op(b->dtype, la, op, b->d_tabs + op.tab, st);
+        auto it = b->use_mfma.find(shape_class(b->dtype, op));
+        e = level_op(b->dtype, la, op, b->d_tabs + op.tab, it == b->use_mfma.end() || it->second, st);
       }
       if (e == hipSuccess)
         e = level_finish(b->dtype, la, b->d_ptens + ln.ptens_begin, ln.n_ptens, b->d_dbound, b->hp.per_set, s0, ln.net,
@@ -720,6 +733,149 @@ int batch_run_graph(tn_batch *b, int with_grad, const double *params, int n_sets
     b->poisoned = true;
     return hip_fail(e, "hipGraphLaunch");
   }
+  return TN_OK;
+}
+
+// Autotuner. (1) Fused executor: time the forward+adjoint pass with each
+// workgroup size and keep the fastest. (2) Level executor: for every shape
+// class of MFMA-eligible ops, time the matrix-core kernel against the thin
+// kernel on scratch operands of that shape and keep the faster. Decisions
+// live in the batch (and, with cache_path, in a text file of
+// "key value" lines that later batches read first).
+static float time_ms(hipStream_t st, int reps, const std::function<int()> &fn, int &rc) {
+  hipEvent_t e0, e1;
+  rc = TN_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    rc = TN_EDEVICE;
+    return 0.f;
+  }
+  if ((rc = fn()) == TN_OK) {  // warm-up
+    (void)hipEventRecord(e0, st);
+    for (int i = 0; i < reps && rc == TN_OK; ++i) rc = fn();
+    (void)hipEventRecord(e1, st);
+    (void)hipEventSynchronize(e1);
+  }
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / std::max(1, reps);
+}
+
+static std::map<std::string, int> read_cache(const char *path) {
+  std::map<std::string, int> m;
+  if (!path) return m;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return m;
+  char key[256];
+  int v;
+  while (std::fscanf(f, "%255s %d", key, &v) == 2) m[key] = v;
+  std::fclose(f);
+  return m;
+}
+
+static void write_cache(const char *path, const std::map<std::string, int> &add) {
+  if (!path) return;
+  auto m = read_cache(path);
+  for (auto &kv : add) m[kv.first] = kv.second;
+  FILE *f = std::fopen(path, "w");
+  if (!f) return;
+  for (auto &kv : m) std::fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+  std::fclose(f);
+}
+
+static std::string fused_key(const tn_batch *b) {
+  return "fused_block:" + std::to_string(b->dtype) + ":" + std::to_string(b->hp.n_programs) + ":" +
+         std::to_string(b->hp.ops.size()) + ":" + std::to_string(b->task_net.size());
+}
+
+int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, const char *cache_path, void *stream) {
+  if (b->poisoned) {
+    set_error("batch poisoned by an earlier device error");
+    return TN_ESTATE;
+  }
+  if (!params || n_sets < 1 || n_sets > b->max_sets) {
+    set_error("tn_batch_autotune: n_sets out of range or params NULL");
+    return TN_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  reps = std::max(1, reps);
+  std::map<std::string, int> found;
+  int rc = TN_OK;
+  b->gc.clear();
+  // (1) fused workgroup size
+  if (!b->task_net.empty()) {
+    float best = 0.f;
+    int best_block = b->block;
+    for (int blk : {64, 128, 256}) {
+      b->block = blk;
+      if ((rc = layout_lds(b, 0)) != TN_OK || (rc = layout_lds(b, 1)) != TN_OK) return rc;
+      float ms = time_ms(st, reps, [&] { return run_batch(b, true, params, n_sets, nullptr, nullptr, nullptr, nullptr, st); },
+                         rc);
+      if (rc != TN_OK) return rc;
+      if (best == 0.f || ms < best) {
+        best = ms;
+        best_block = blk;
+      }
+    }
+    b->block = best_block;
+    if ((rc = layout_lds(b, 0)) != TN_OK || (rc = layout_lds(b, 1)) != TN_OK) return rc;
+    found[fused_key(b)] = best_block;
+  }
+  // (2) large level ops: MFMA vs thin per shape class
+  std::map<std::string, const DOp *> classes;
+  for (const LevelNet &ln : b->level)
+    for (int v = 0; v < 2; ++v)
+      for (int o = 0; o < ln.n_ops[v]; ++o) {
+        const DOp &op = b->hp.ops[ln.op_begin[v] + o];
+        if (mfma_eligible(b->dtype, op)) classes.emplace(shape_class(b->dtype, op), &op);
+      }
+  const int eb = b->dtype == TN_C128 ? 16 : 8;
+  for (auto &kv : classes) {
+    DOp op = *kv.second;
+    const int64_t nx = (int64_t)1 << (op.nFX + op.nS), ny = (int64_t)1 << (op.nS + op.nFY);
+    const int64_t nz = (int64_t)1 << (op.nFX + op.nFY);
+    void *buf = nullptr;
+    if (hipMalloc(&buf, (size_t)(nx + ny + nz) * eb) != hipSuccess) {
+      (void)hipGetLastError();
+      continue;  // no room to tune this class: keep the default
+    }
+    HIPCHK(hipMemset(buf, 0, (size_t)(nx + ny + nz) * eb));
+    op.x = 0;
+    op.y = (int32_t)nx;
+    op.z = (int32_t)(nx + ny);
+    LevelArgs la{};
+    la.arena = buf;
+    la.stride = nx + ny + nz;
+    la.n_sets = 1;
+    int rc1 = TN_OK, rc2 = TN_OK;
+    float t_mfma = time_ms(st, reps, [&] { return mfma_contract(la, op, b->d_tabs + op.tab, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rc1);
+    float t_thin = time_ms(st, reps, [&] { return level_op(b->dtype, la, op, b->d_tabs + op.tab, false, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rc2);
+    (void)hipFree(buf);
+    if (rc1 != TN_OK || rc2 != TN_OK) {
+      b->poisoned = true;
+      set_error("tn_batch_autotune: launch failed");
+      return TN_EDEVICE;
+    }
+    b->use_mfma[kv.first] = t_mfma <= t_thin ? 1 : 0;
+    found["mfma:" + kv.first] = b->use_mfma[kv.first];
+  }
+  write_cache(cache_path, found);
+  return TN_OK;
+}
+
+// Apply cached autotuner decisions (no timing).
+int batch_apply_cache(tn_batch *b, const char *cache_path) {
+  auto m = read_cache(cache_path);
+  auto it = m.find(fused_key(b));
+  if (it != m.end() && (it->second == 64 || it->second == 128 || it->second == 256) && !b->task_net.empty()) {
+    b->block = it->second;
+    int rc;
+    if ((rc = layout_lds(b, 0)) != TN_OK || (rc = layout_lds(b, 1)) != TN_OK) return rc;
+  }
+  for (auto &kv : m)
+    if (kv.first.rfind("mfma:", 0) == 0) b->use_mfma[kv.first.substr(5)] = kv.second;
+  b->gc.clear();
   return TN_OK;
 }
 

@@ -74,6 +74,8 @@ _SIGS = {
     "tn_batch_grad": (_I, [_P, _P, _I, _P, _P, _P, _P, _P]),
     "tn_batch_run_graph": (_I, [_P, _I, _P, _I, _P, _P, _P, _P]),
     "tn_batch_info": (_I, [_P, ctypes.POINTER(tn_batch_stats)]),
+    "tn_batch_autotune": (_I, [_P, _P, _I, _I, ctypes.c_char_p, _P]),
+    "tn_batch_apply_tuning": (_I, [_P, ctypes.c_char_p]),
     "tn_contract_batch": (_I, [ctypes.POINTER(_P), _I, _P, _I, _P, _P]),
     "tn_grad_batch": (_I, [ctypes.POINTER(_P), _I, _P, _I, _P, _P, _P]),
     "tn_bind_params": (_I, [_P, _P, _I, _P, ctypes.POINTER(ctypes.c_int64), _P]),
@@ -249,6 +251,14 @@ class Batch:
         s = tn_batch_stats()
         _check(lib().tn_batch_info(self.h, ctypes.byref(s)))
         return {n: getattr(s, n) for n, _ in s._fields_}
+
+    def autotune(self, params, reps=3, cache_path=None, stream=None):
+        """Pick fused workgroup size and MFMA/thin per large-op shape (tn_batch_autotune)."""
+        cp = cache_path.encode() if cache_path else None
+        _check(lib().tn_batch_autotune(self.h, _dptr(params), params.shape[0], reps, cp, _stream(stream)))
+
+    def apply_tuning(self, cache_path):
+        _check(lib().tn_batch_apply_tuning(self.h, cache_path.encode()))
 
     def contract(self, params, out=None, obj=None, stream=None):
         """params: cuda float64 [n_sets, n_params]; out: [n_nets, n_sets, 2]; obj: [n_sets]."""

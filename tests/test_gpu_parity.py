@@ -295,3 +295,42 @@ def test_dense_whole_circuit_mfma(d, n, monkeypatch):
         for s in range(S):
             assert np.max(np.abs(got[:, s, 0] - ref[s, :3])) < tol, (dtype, got[:, s, 0], ref[s, :3])
             assert np.max(np.abs(got[:, s, 1])) < tol
+
+
+def test_autotune_keeps_results(tmp_path):
+    """The autotuner changes only kernel choices: results before and after
+    tuning agree, and the decisions are written to and read from its cache."""
+    qtn, qaoa = _qtn(), _qaoa()
+    e = workloads.random_regular_graph(6, 12, 0)
+    ang = torch.tensor(workloads.qaoa_angles(4, 2, 1), device="cuda", dtype=torch.float64)
+    nets = []
+    for ed in e[:2]:
+        net = qaoa.edge_network(12, e, 1, ed, dtype=qtn.TN_C64, lightcone=False)
+        net.set_order(net.order_linegraph(trials=4, seed=0))
+        nets.append(net)
+    for ed in e[2:4]:
+        net = qaoa.edge_network(12, e, 1, ed, dtype=qtn.TN_C64, lightcone=True)
+        net.set_order(net.order_linegraph(trials=4, seed=0))
+        nets.append(net)
+    batch = qtn.Batch(nets, max_sets=2)
+    out0 = torch.empty((len(nets), 2, 2), dtype=torch.float64, device="cuda")
+    out1 = torch.empty_like(out0)
+    g0 = torch.empty((len(nets), 2, 2), dtype=torch.float64, device="cuda")
+    g1 = torch.empty_like(g0)
+    _say("autotune before")
+    batch.grad(ang, out=out0, grad_net=g0)
+    torch.cuda.synchronize()
+    cache = str(tmp_path / "tune.txt")
+    _say("autotune run")
+    batch.autotune(ang, reps=2, cache_path=cache)
+    batch.grad(ang, out=out1, grad_net=g1)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(out0.cpu().numpy() - out1.cpu().numpy())) < 2e-5
+    assert np.max(np.abs(g0.cpu().numpy() - g1.cpu().numpy())) < 2e-4
+    text = open(cache).read()
+    assert "fused_block:" in text and "mfma:" in text
+    batch2 = qtn.Batch(nets, max_sets=2)
+    batch2.apply_tuning(cache)
+    batch2.contract(ang, out=out1)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(out0.cpu().numpy() - out1.cpu().numpy())) < 2e-5

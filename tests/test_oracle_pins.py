@@ -274,3 +274,24 @@ def test_finite_difference_vs_parameter_shift_p2():
     fd = gradients.finite_difference(8, e, params)
     ps = gradients.parameter_shift(8, e, params)
     np.testing.assert_allclose(fd, ps, atol=1e-5 * max(1, np.abs(ps).max()))
+
+
+# --- light-cone state vectors (the route for graphs too large for a full state vector) ----------
+
+@pytest.mark.parametrize("d,n,p,seed", [(3, 12, 1, 0), (3, 10, 2, 1), (4, 10, 2, 3)])
+def test_lightcone_statevector_matches_full(d, n, p, seed):
+    e = workloads.random_regular_graph(d, n, seed)
+    ang = workloads.qaoa_angles(seed, 1, p)[0]
+    full = statevector.qaoa_zz(n, e, ang[:p], ang[p:])
+    lc = np.array([statevector.qaoa_zz_edge(n, e, ang[:p], ang[p:], ed) for ed in e])
+    np.testing.assert_allclose(lc, full, atol=1e-13)
+    m, _, _ = statevector.qaoa_edge_lightcone_circuit(n, e, ang[:p], ang[p:], e[0])
+    assert m <= n
+
+
+def test_edge_parameter_shift_sums_to_full_gradient():
+    e = workloads.random_regular_graph(3, 8, 6)
+    params = workloads.qaoa_angles(6, 1, 2)[0]
+    full = gradients.parameter_shift(8, e, params)
+    per_edge = sum(-0.5 * gradients.parameter_shift_edge(8, e, params, ed) for ed in e)
+    np.testing.assert_allclose(per_edge, full, atol=1e-12)
