@@ -23,6 +23,7 @@ int batch_run_graph(tn_batch *b, int with_grad, const double *params, int n_sets
 int batch_info(const tn_batch *b, tn_batch_stats *s);
 int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, const char *cache_path, void *stream);
 int batch_apply_cache(tn_batch *b, const char *cache_path);
+int batch_set_precision(tn_batch *b, int prec);
 void batch_free(tn_batch *b);
 int net_contract(Net &net, const double *params, double *out, double *value, double *grad, void *stream);
 int net_bind(Net &net, const double *params, int n_sets, void *dst, int64_t *per_set, void *stream);
@@ -246,6 +247,14 @@ int tn_batch_autotune(tn_batch *b, const double *params, int32_t n_sets, int32_t
     return TN_EINVAL;
   }
   GUARD({ return qtn::batch_autotune(b, params, n_sets, reps, cache_path, stream); })
+}
+
+int tn_batch_set_precision(tn_batch *b, int32_t mfma_precision) {
+  if (!b) {
+    qtn::set_error("tn_batch_set_precision: NULL batch");
+    return TN_EINVAL;
+  }
+  return qtn::batch_set_precision(b, mfma_precision);
 }
 
 int tn_batch_apply_tuning(tn_batch *b, const char *cache_path) {

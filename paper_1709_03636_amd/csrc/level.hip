@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void level_finish_kernel(LevelArgs a, const DP
 
 // --- host launchers ------------------------------------------------------------------------
 bool mfma_eligible(int dtype, const DOp &op);
-hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream_t st);
+hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, int prec, hipStream_t st);
 
 static inline int grid_for(int64_t total) {
   int64_t g = (total + 255) / 256;
@@ -292,10 +292,10 @@ static hipError_t level_op_t(const LevelArgs &a, const DOp &op, const int32_t *t
   return hipGetLastError();
 }
 
-// use_mfma: take the matrix-core kernel when the op is eligible (the
-// autotuner may decide against it for a shape class).
-hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tab, bool use_mfma, hipStream_t st) {
-  if (use_mfma && mfma_eligible(dtype, op)) return mfma_contract(a, op, tab, st);
+// mfma: 0 = thin kernel, else the matrix-core precision (TN_MFMA_*) used
+// when the op is eligible (the autotuner may choose thin for a shape class).
+hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tab, int mfma, hipStream_t st) {
+  if (mfma && mfma_eligible(dtype, op)) return mfma_contract(a, op, tab, mfma, st);
   return dtype == TN_C128 ? level_op_t<double2>(a, op, tab, st) : level_op_t<float2>(a, op, tab, st);
 }
 

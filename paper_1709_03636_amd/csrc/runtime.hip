@@ -24,9 +24,9 @@ hipError_t launch_combine(const double *val, const double *gnet, const double *c
                           int n_sets, int n_params, double *obj, double *grad, hipStream_t st);
 hipError_t launch_bind(int dtype, const DParam *slots, int n_slots, const double *params, int n_params, int n_sets,
                        int per_set, void *G, void *dG, hipStream_t st);
-hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tab, bool use_mfma, hipStream_t st);
+hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tab, int mfma, hipStream_t st);
 bool mfma_eligible(int dtype, const DOp &op);
-hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream_t st);
+hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, int prec, hipStream_t st);
 hipError_t level_setup(int dtype, const LevelArgs &a, const void *consts, int n_const, const DParam *pt, int n_pt,
                        const void *bound, int per_set, int set0, int zero_begin, int zero_n, hipStream_t st);
 hipError_t level_finish(int dtype, const LevelArgs &a, const DParam *pt, int n_pt, const void *dbound, int per_set,
@@ -413,6 +413,7 @@ struct tn_batch {
   double flops_fwd = 0, bytes_fwd = 0, flops_grad = 0, bytes_grad = 0;
   int64_t level_bytes = 0;
   std::map<std::string, int> use_mfma;  // autotuner: shape class of a large op -> 1 MFMA, 0 thin
+  int mfma_prec = TN_MFMA_FP32;          // matrix-core precision of large complex64 steps
   bool poisoned = false;
   qtn::GraphCache gc;
 };
@@ -594,8 +595,8 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
 
 // Key of a large op for the autotuner: dtype, free/summed bit counts and
 // which operands are read with the summed index contiguous.
-static std::string shape_class(int dtype, const DOp &op) {
-  return std::to_string(dtype) + ":" + std::to_string(op.nFX) + "," + std::to_string(op.nS) + "," +
+static std::string shape_class(int dtype, const DOp &op, int prec) {
+  return std::to_string(dtype) + "p" + std::to_string(prec) + ":" + std::to_string(op.nFX) + "," + std::to_string(op.nS) + "," +
          std::to_string(op.nFY) + ":" + std::to_string(!(op.maskX & 1u)) + std::to_string(!(op.maskY & 1u));
 }
 
@@ -665,8 +666,9 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
                       grad ? (int)ln.ptens_elems : 0, st);
       for (int o = 0; o < ln.n_ops[v] && e == hipSuccess; ++o) {
         const DOp &op = b->hp.ops[ln.op_begin[v] + o];
-        auto it = b->use_mfma.find(shape_class(b->dtype, op));
-        e = level_op(b->dtype, la, op, b->d_tabs + op.tab, it == b->use_mfma.end() || it->second, st);
+        auto it = b->use_mfma.find(shape_class(b->dtype, op, b->mfma_prec));
+        const bool mf = it == b->use_mfma.end() || it->second;
+        e = level_op(b->dtype, la, op, b->d_tabs + op.tab, mf ? b->mfma_prec : 0, st);
       }
       if (e == hipSuccess)
         e = level_finish(b->dtype, la, b->d_ptens + ln.ptens_begin, ln.n_ptens, b->d_dbound, b->hp.per_set, s0, ln.net,
@@ -828,7 +830,7 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
     for (int v = 0; v < 2; ++v)
       for (int o = 0; o < ln.n_ops[v]; ++o) {
         const DOp &op = b->hp.ops[ln.op_begin[v] + o];
-        if (mfma_eligible(b->dtype, op)) classes.emplace(shape_class(b->dtype, op), &op);
+        if (mfma_eligible(b->dtype, op)) classes.emplace(shape_class(b->dtype, op, b->mfma_prec), &op);
       }
   const int eb = b->dtype == TN_C128 ? 16 : 8;
   for (auto &kv : classes) {
@@ -849,8 +851,8 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
     la.stride = nx + ny + nz;
     la.n_sets = 1;
     int rc1 = TN_OK, rc2 = TN_OK;
-    float t_mfma = time_ms(st, reps, [&] { return mfma_contract(la, op, b->d_tabs + op.tab, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rc1);
-    float t_thin = time_ms(st, reps, [&] { return level_op(b->dtype, la, op, b->d_tabs + op.tab, false, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rc2);
+    float t_mfma = time_ms(st, reps, [&] { return mfma_contract(la, op, b->d_tabs + op.tab, b->mfma_prec, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rc1);
+    float t_thin = time_ms(st, reps, [&] { return level_op(b->dtype, la, op, b->d_tabs + op.tab, 0, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rc2);
     (void)hipFree(buf);
     if (rc1 != TN_OK || rc2 != TN_OK) {
       b->poisoned = true;
@@ -861,6 +863,16 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
     found["mfma:" + kv.first] = b->use_mfma[kv.first];
   }
   write_cache(cache_path, found);
+  return TN_OK;
+}
+
+int batch_set_precision(tn_batch *b, int prec) {
+  if (prec != TN_MFMA_FP32 && prec != TN_MFMA_BF16X3) {
+    set_error("tn_batch_set_precision: unknown precision");
+    return TN_EINVAL;
+  }
+  b->mfma_prec = prec;
+  b->gc.clear();
   return TN_OK;
 }
 

@@ -17,6 +17,7 @@ TN_OK, TN_EINVAL, TN_ENOMEM, TN_EORDER, TN_EDEVICE, TN_ESTATE = 0, -1, -2, -3, -
 TN_H, TN_X, TN_Y, TN_Z, TN_RX, TN_RY, TN_RZ, TN_ZZ, TN_CNOT, TN_CZ, TN_U1, TN_U2 = range(12)
 TN_AMPLITUDE, TN_PROBABILITY, TN_EXPECTATION = 0, 1, 2
 TN_C64, TN_C128 = 0, 1
+TN_MFMA_FP32, TN_MFMA_BF16X3 = 1, 2
 GATE_KINDS = {"H": TN_H, "X": TN_X, "Y": TN_Y, "Z": TN_Z, "RX": TN_RX, "RY": TN_RY, "RZ": TN_RZ, "ZZ": TN_ZZ,
               "CNOT": TN_CNOT, "CZ": TN_CZ, "U1": TN_U1, "U2": TN_U2}
 ERR_NAMES = {TN_EINVAL: "TN_EINVAL", TN_ENOMEM: "TN_ENOMEM", TN_EORDER: "TN_EORDER", TN_EDEVICE: "TN_EDEVICE",
@@ -76,6 +77,7 @@ _SIGS = {
     "tn_batch_info": (_I, [_P, ctypes.POINTER(tn_batch_stats)]),
     "tn_batch_autotune": (_I, [_P, _P, _I, _I, ctypes.c_char_p, _P]),
     "tn_batch_apply_tuning": (_I, [_P, ctypes.c_char_p]),
+    "tn_batch_set_precision": (_I, [_P, _I]),
     "tn_contract_batch": (_I, [ctypes.POINTER(_P), _I, _P, _I, _P, _P]),
     "tn_grad_batch": (_I, [ctypes.POINTER(_P), _I, _P, _I, _P, _P, _P]),
     "tn_bind_params": (_I, [_P, _P, _I, _P, ctypes.POINTER(ctypes.c_int64), _P]),
@@ -256,6 +258,10 @@ class Batch:
         """Pick fused workgroup size and MFMA/thin per large-op shape (tn_batch_autotune)."""
         cp = cache_path.encode() if cache_path else None
         _check(lib().tn_batch_autotune(self.h, _dptr(params), params.shape[0], reps, cp, _stream(stream)))
+
+    def set_precision(self, mfma_precision):
+        """TN_MFMA_FP32 or TN_MFMA_BF16X3 for the large complex64 steps."""
+        _check(lib().tn_batch_set_precision(self.h, mfma_precision))
 
     def apply_tuning(self, cache_path):
         _check(lib().tn_batch_apply_tuning(self.h, cache_path.encode()))

@@ -334,3 +334,31 @@ def test_autotune_keeps_results(tmp_path):
     batch2.contract(ang, out=out1)
     torch.cuda.synchronize()
     assert np.max(np.abs(out0.cpu().numpy() - out1.cpu().numpy())) < 2e-5
+
+
+def test_dense_split_bf16_precision():
+    """Split-BF16 MFMA products on the dense whole-circuit networks: error
+    against the state vector within the split's bound (relative 2^-16 per
+    product, summed over the contraction: 2e-4 absolute on <ZZ>)."""
+    qtn, qaoa = _qtn(), _qaoa()
+    d, n = 6, 12
+    e = workloads.random_regular_graph(d, n, 0)
+    ang = np.array(workloads.qaoa_angles(3, 2, 1))
+    ref = np.array([statevector.qaoa_zz(n, e, [a[0]], [a[1]]) for a in ang])
+    nets = []
+    for ed in e[:3]:
+        net = qaoa.edge_network(n, e, 1, ed, dtype=qtn.TN_C64, lightcone=False)
+        net.set_order(net.order_linegraph(trials=4, seed=0))
+        nets.append(net)
+    errs = {}
+    for prec in (qtn.TN_MFMA_FP32, qtn.TN_MFMA_BF16X3):
+        batch = qtn.Batch(nets, max_sets=2)
+        batch.set_precision(prec)
+        out = torch.empty((len(nets), 2, 2), dtype=torch.float64, device="cuda")
+        _say(f"dense precision {prec}")
+        batch.contract(torch.tensor(ang, device="cuda"), out=out)
+        torch.cuda.synchronize()
+        errs[prec] = float(np.max(np.abs(out.cpu().numpy()[:, :, 0] - ref[:, :3].T)))
+    _say(f"errors {errs}")
+    assert errs[qtn.TN_MFMA_FP32] < 2e-5
+    assert errs[qtn.TN_MFMA_BF16X3] < 2e-4
