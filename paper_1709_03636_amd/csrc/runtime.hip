@@ -852,7 +852,11 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
     la.n_sets = 1;
     int rc1 = TN_OK, rc2 = TN_OK;
     float t_mfma = time_ms(st, reps, [&] { return mfma_contract(la, op, b->d_tabs + op.tab, b->mfma_prec, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rc1);
-    float t_thin = time_ms(st, reps, [&] { return level_op(b->dtype, la, op, b->d_tabs + op.tab, 0, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rc2);
+    // the thin kernel is not a candidate for very large products (2^30 and
+    // more complex multiply-adds): the matrix cores win by orders of magnitude
+    float t_thin = 1e30f;
+    if (op.nFX + op.nS + op.nFY < 30)
+      t_thin = time_ms(st, reps, [&] { return level_op(b->dtype, la, op, b->d_tabs + op.tab, 0, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rc2);
     (void)hipFree(buf);
     if (rc1 != TN_OK || rc2 != TN_OK) {
       b->poisoned = true;
