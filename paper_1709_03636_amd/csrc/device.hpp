@@ -57,6 +57,7 @@ struct DParam {
 // One network program (forward, or forward + adjoint).
 struct DNet {
   int32_t op_begin, n_ops;      // into the op array
+  int32_t rec_begin;            // lane records of op o at (rec_begin + o) * 64
   int32_t n_comp;               // component scalars
   int32_t mem_elems;            // executor memory (elements) incl. leaves
   int32_t const_begin, n_const; // constant leaf values: global -> [0, n_const)
@@ -64,10 +65,20 @@ struct DNet {
 };
 
 
+// Lane record of an op of the fused executor (64 lanes per op, one int4
+// each). For a small contraction (at most 64 outputs, at most 16 summed
+// entries) lane l holds the LDS offsets of its output's X and Y rows, the
+// (X, Y) offsets of summed entry k = l packed as two 16-bit halves, and a
+// workgroup-uniform header: bit 0 set, bits 1-3 log2 K, bits 4-10 the
+// number of outputs, bits 12.. the result offset. Any other op has header 0
+// and runs from its DOp descriptor.
+constexpr int kRecLanes = 64;
+
 // Arguments of the fused executor kernel.
 struct FusedArgs {
   const DNet *nets;
   const DOp *ops;
+  const int4 *recs;
   const int32_t *tabs;
   const void *consts;
   const DParam *ptens;

@@ -283,6 +283,35 @@ __device__ __forceinline__ void op_contract(V *mem, const DOp &op, const int32_t
   }
 }
 
+// Small contraction from a lane record (64-lane workgroups): the lane's
+// operand offsets and the summed-index table come precomputed, the table is
+// read out of the record lanes into scalar registers.
+template <typename V, int LGK>
+__device__ __forceinline__ void contract_lite(V *mem, const int4 &rec, uint32_t hdr) {
+  constexpr int K = 1 << LGK;
+  const int nOut = (hdr >> 4) & 127;
+  const int z = (int)(hdr >> 12);
+  int32_t tx[K], ty[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t t = (uint32_t)__builtin_amdgcn_readlane(rec.z, k);
+    tx[k] = (int32_t)(t & 0xffffu);
+    ty[k] = (int32_t)(t >> 16);
+  }
+  if ((int)threadIdx.x < nOut) {
+    V xv[K], yv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      xv[k] = mem[rec.x + tx[k]];
+      yv[k] = mem[rec.y + ty[k]];
+    }
+    V acc = czero<V>();
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc = cmul_add(acc, xv[k], yv[k]);
+    mem[z + threadIdx.x] = acc;
+  }
+}
+
 // Fused executor. GRAD selects the forward+adjoint program: the adjoint of
 // each parametric leaf is contracted with the leaf's angle derivative (bound
 // by the binding kernel) as soon as it is formed, and summed per parameter in
@@ -327,7 +356,30 @@ void fused_exec_kernel(FusedArgs a) {
     // loads share one wait counter, so an outstanding descriptor load would
     // delay every LDS wait of the current op.
     const DOp *ops = a.ops + net.op_begin;
+    // lane records (64-lane workgroups): the next op's record is loaded
+    // while the current op runs (vector loads: their wait counter is not
+    // the LDS one)
+    const int4 *recs = a.recs + (size_t)net.rec_begin * kRecLanes + (tid & (kRecLanes - 1));
+    int4 rec = make_int4(0, 0, 0, 0);
+    if (BLOCK == kRecLanes && net.n_ops > 0) rec = recs[0];
     for (int o = 0; o < net.n_ops; ++o) {
+      int4 nrec = make_int4(0, 0, 0, 0);
+      if (BLOCK == kRecLanes) {
+        if (o + 1 < net.n_ops) nrec = recs[(size_t)(o + 1) * kRecLanes];
+        const uint32_t hdr = (uint32_t)__builtin_amdgcn_readfirstlane(rec.w);
+        if (hdr & 1u) {
+          switch ((hdr >> 1) & 7u) {
+            case 0: contract_lite<V, 0>(mem, rec, hdr); break;
+            case 1: contract_lite<V, 1>(mem, rec, hdr); break;
+            case 2: contract_lite<V, 2>(mem, rec, hdr); break;
+            case 3: contract_lite<V, 3>(mem, rec, hdr); break;
+            default: contract_lite<V, 4>(mem, rec, hdr); break;
+          }
+          __syncthreads();
+          rec = nrec;
+          continue;
+        }
+      }
       const DOp op = cload(ops + o);
       const int32_t *tb = a.tabs + op.tab;
       if (op.type == OP_CONTRACT) {
@@ -365,6 +417,7 @@ void fused_exec_kernel(FusedArgs a) {
         if (tid == 0) gacc[d.param] += d.coeff * acc;
       }
       __syncthreads();
+      rec = nrec;
     }
 
     if (tid == 0) {

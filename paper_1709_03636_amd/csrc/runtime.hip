@@ -157,6 +157,7 @@ struct HostProgram {
   std::vector<DNet> nets_fwd, nets_grad;  // fused: one entry per batch network (level ones empty)
   std::vector<DOp> ops;
   std::vector<int32_t> tabs;
+  std::vector<int32_t> recs;   // fused lane records, 4 ints x 64 lanes per op
   std::vector<double> consts;  // interleaved, converted to the dtype at upload
   std::vector<DParam> ptens;
   // distinct parametric tensors of the whole batch (bound once per parameter vector)
@@ -247,6 +248,41 @@ static int64_t fused_lds_need(const Net &net, const NetLayout &lay, int eb, int 
   return mem * eb + 256 * eb + (int64_t)std::max(1, net.gplan.n_components) * 16 + (int64_t)n_params * 8 + 256 + 64;
 }
 
+static uint32_t host_pdep(uint32_t v, uint32_t mask) {
+  uint32_t out = 0;
+  while (mask) {
+    uint32_t low = mask & (0u - mask);
+    if (v & 1u) out |= low;
+    v >>= 1;
+    mask ^= low;
+  }
+  return out;
+}
+
+// Lane records (see kRecLanes) of ops [first, first + n) of `loc`.
+static void build_records(const HostProgram &loc, int first, int n, std::vector<int32_t> &recs) {
+  for (int o = first; o < first + n; ++o) {
+    const DOp &op = loc.ops[o];
+    const int nOut = 1 << (op.nFX + op.nFY);
+    const bool lite = op.type == OP_CONTRACT && nOut <= kRecLanes && op.nS <= 4 && op.z < (1 << 19);
+    for (int l = 0; l < kRecLanes; ++l) {
+      int32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+      if (lite) {
+        if (l < nOut) {
+          a0 = op.x + (int32_t)host_pdep((uint32_t)l >> op.nFY, op.maskX);
+          a1 = op.y + (int32_t)host_pdep((uint32_t)l & ((1u << op.nFY) - 1u), op.maskY);
+        }
+        if (l < (1 << op.nS)) a2 = (loc.tabs[op.tab + 2 * l] & 0xffff) | (loc.tabs[op.tab + 2 * l + 1] << 16);
+        a3 = 1 | (op.nS << 1) | (nOut << 4) | (op.z << 12);
+      }
+      recs.push_back(a0);
+      recs.push_back(a1);
+      recs.push_back(a2);
+      recs.push_back(a3);
+    }
+  }
+}
+
 // Append the fused programs (forward, forward+adjoint) of one network.
 // Networks whose programs are identical (same ops, offset tables, constants
 // and parametric tensors: e.g. isomorphic light cones contracted in the same
@@ -292,6 +328,8 @@ static void append_fused(const Net &net, const NetLayout &lay, HostProgram &hp) 
     return;
   }
   const int tab0 = (int)hp.tabs.size(), op0 = (int)hp.ops.size(), ptens_begin = (int)hp.ptens.size();
+  const int rec0 = (int)(hp.recs.size() / (4 * kRecLanes));
+  build_records(loc, 0, (int)loc.ops.size(), hp.recs);
   const int const_begin = (int)(hp.consts.size() / 2);
   for (DOp d : loc.ops) {
     d.tab += tab0;
@@ -305,6 +343,7 @@ static void append_fused(const Net &net, const NetLayout &lay, HostProgram &hp) 
   for (int variant = 0; variant < 2; ++variant) {
     DNet dn{};
     dn.op_begin = op0 + op_begin[variant];
+    dn.rec_begin = rec0 + op_begin[variant];
     dn.n_ops = n_ops[variant];
     dn.n_comp = p.n_components;
     dn.mem_elems = (int32_t)(lay.leaf_region + lay.arena[variant]);
@@ -400,6 +439,7 @@ struct tn_batch {
   // device
   qtn::DNet *d_nets_fwd = nullptr, *d_nets_grad = nullptr;
   qtn::DOp *d_ops = nullptr;
+  int4 *d_recs = nullptr;
   int32_t *d_tabs = nullptr, *d_task_net = nullptr;
   void *d_consts = nullptr;
   qtn::DParam *d_ptens = nullptr, *d_slots = nullptr;
@@ -433,7 +473,7 @@ static int hip_fail(hipError_t e, const char *what) {
 
 static void free_batch_dev(tn_batch *b) {
   b->gc.clear();
-  void *ptrs[] = {b->d_nets_fwd, b->d_nets_grad, b->d_ops, b->d_tabs, b->d_task_net, b->d_consts, b->d_ptens,
+  void *ptrs[] = {b->d_nets_fwd, b->d_nets_grad, b->d_ops, b->d_recs, b->d_tabs, b->d_task_net, b->d_consts, b->d_ptens,
                   b->d_slots, b->d_bound, b->d_dbound, b->d_val, b->d_gnet, b->d_coef, b->d_larena, b->d_lscal,
                   b->d_lpart};
   for (void *p : ptrs)
@@ -545,6 +585,7 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   if ((e = dalloc(&b->d_nets_grad, hp.nets_grad.size())) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_ops, hp.ops.size())) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_tabs, hp.tabs.size())) != hipSuccess) return fail(e, "hipMalloc");
+  if ((e = dalloc(&b->d_recs, hp.recs.size() / 4)) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_task_net, b->task_net.size())) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc((char **)&b->d_consts, hp.consts.size() / 2 * eb)) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_ptens, hp.ptens.size())) != hipSuccess) return fail(e, "hipMalloc");
@@ -581,6 +622,7 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
       {b->d_nets_grad, hp.nets_grad.data(), hp.nets_grad.size() * sizeof(DNet)},
       {b->d_ops, hp.ops.data(), hp.ops.size() * sizeof(DOp)},
       {b->d_tabs, hp.tabs.data(), hp.tabs.size() * sizeof(int32_t)},
+      {b->d_recs, hp.recs.data(), hp.recs.size() * sizeof(int32_t)},
       {b->d_task_net, b->task_net.data(), b->task_net.size() * sizeof(int32_t)},
       {b->d_consts, csrc, hp.consts.size() / 2 * eb},
       {b->d_ptens, hp.ptens.data(), hp.ptens.size() * sizeof(DParam)},
@@ -614,6 +656,7 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
   FusedArgs a{};
   a.nets = grad ? b->d_nets_grad : b->d_nets_fwd;
   a.ops = b->d_ops;
+  a.recs = b->d_recs;
   a.tabs = b->d_tabs;
   a.consts = b->d_consts;
   a.ptens = b->d_ptens;

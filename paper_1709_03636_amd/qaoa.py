@@ -26,13 +26,59 @@ def qaoa_gates(n, edges, p):
     return gates
 
 
+def edge_lightcone_circuit(n, edges, p, edge):
+    """The gates that can reach <Z_u Z_v>, on the light-cone qubits only,
+    relabelled canonically: u -> 0, v -> 1, then breadth-first over the kept
+    ZZ gates with ties broken by already-assigned neighbour labels. Isomorphic
+    light cones thus give identical circuits (hence identical contraction
+    programs, which the batch stores once). Returns (m qubits, gates)."""
+    adj = {}
+    for a, b in edges:
+        adj.setdefault(a, set()).add(b)
+        adj.setdefault(b, set()).add(a)
+    sup = {edge[0], edge[1]}
+    layers = []
+    for _ in range(p):  # backwards: a ZZ layer is kept where it touches the support
+        zz = [(a, b) for (a, b) in edges if a in sup or b in sup]
+        layers.append(zz)
+        sup = sup | {q for e in zz for q in e}
+    layers.reverse()
+    kadj = {}
+    for zz in layers:
+        for a, b in zz:
+            kadj.setdefault(a, set()).add(b)
+            kadj.setdefault(b, set()).add(a)
+    lab = {edge[0]: 0, edge[1]: 1}
+    frontier = [edge[0], edge[1]]
+    while frontier:
+        cand = {w for q in frontier for w in kadj.get(q, ()) if w not in lab}
+        cand = sorted(cand, key=lambda w: (sorted(lab[x] for x in kadj[w] if x in lab), len(kadj[w])))
+        for w in cand:
+            lab[w] = len(lab)
+        frontier = cand
+    m = len(lab)
+    gates = []
+    for k, zz in enumerate(layers):
+        ren = sorted(tuple(sorted((lab[a], lab[b]))) for a, b in zz)
+        gates += [("ZZ", a, b, k, 2.0) for a, b in ren]
+        gates += [("RX", q, -1, p + k, 2.0) for q in range(m)]
+    return m, gates
+
+
 def edge_network(n, edges, p, edge, dtype=qtn.TN_C64, lightcone=True):
-    u, v = edge
-    pauli = [0] * n
-    pauli[u] = pauli[v] = 3
-    init = np.array([complex(PLUS[0], PLUS[1]), complex(PLUS[2], PLUS[3])] * n)
-    return qtn.Network(n, qaoa_gates(n, edges, p), qtn.TN_EXPECTATION, pauli, n_params=2 * p, init=init,
-                       dtype=dtype, lightcone=lightcone)
+    """Folded network of <Z_u Z_v>. With lightcone=True it is built on the
+    edge's canonically relabelled light-cone circuit; with lightcone=False it
+    is the whole circuit (trace on every other qubit)."""
+    if lightcone:
+        m, gates = edge_lightcone_circuit(n, edges, p, edge)
+        pauli = [3, 3] + [0] * (m - 2)
+    else:
+        m, gates = n, qaoa_gates(n, edges, p)
+        pauli = [0] * n
+        pauli[edge[0]] = pauli[edge[1]] = 3
+    init = np.array([complex(PLUS[0], PLUS[1]), complex(PLUS[2], PLUS[3])] * m)
+    return qtn.Network(m, gates, qtn.TN_EXPECTATION, pauli, n_params=2 * p, init=init, dtype=dtype,
+                       lightcone=lightcone)
 
 
 def edge_networks(n, edges, p, dtype=qtn.TN_C64, order="stochastic", seed=0, trials=8, lightcone=True):
