@@ -66,12 +66,31 @@ struct DNet {
 
 
 // Lane record of an op of the fused executor (64 lanes per op, one int4
-// each). For a small contraction (at most 64 outputs, at most 16 summed
-// entries) lane l holds the LDS offsets of its output's X and Y rows, the
-// (X, Y) offsets of summed entry k = l packed as two 16-bit halves, and a
-// workgroup-uniform header: bit 0 set, bits 1-3 log2 K, bits 4-10 the
-// number of outputs, bits 12.. the result offset. Any other op has header 0
-// and runs from its DOp descriptor.
+// each, lane l holding (x, y, z, w)). w of lane 0 is a workgroup-uniform
+// header: bits 0-2 the record type, three 4-bit fields A (bits 3-6), B
+// (7-10), C (11-14), and bits 15.. the result offset (leaf gradients: the
+// parameter index). Offsets are LDS element offsets; "packed" means an
+// (X, Y) pair as two 16-bit halves. Types:
+//  kRecLite     contraction, 2^B <= 64 outputs, K = 2^A <= 16 summed
+//               entries: x, y = offsets of output l's X and Y rows, z =
+//               packed offsets of summed entry l;
+//  kRecWide     outer product (K = 1), 2^B <= 256 outputs: x, y for output
+//               l; w of lanes 1-3 = packed offset steps of outputs 64 l
+//               (offsets add over disjoint index bits);
+//  kRecNarrow   contraction, 2^B <= 64 outputs, K = G R with G = 2^A lanes
+//               per output and R = 2^C entries per lane: lane l serves
+//               output l / G, its x, y include the offsets of entry l mod G,
+//               z of lane i = packed offsets of entry G i; the G partial
+//               sums are reduced across lanes;
+//  kRecScalar   rank-0 result, K = 2^A <= 64: x, y = offsets of entry l;
+//               FP64 products and sum;
+//  kRecSeed     adjoint seed: x of lane 0 = the component left out;
+//  kRecLeafGrad adjoint of a parametric leaf, 2^B <= 256 entries: x =
+//               offset of entry l, y = canonical indices of entries
+//               l + 64 q (8 bits each), z of lane 0 the bound-tensor slot,
+//               of lanes 1-2 the FP64 coefficient.
+// Type 0: the op runs from its DOp descriptor.
+constexpr int kRecLite = 1, kRecWide = 2, kRecNarrow = 3, kRecScalar = 4, kRecSeed = 5, kRecLeafGrad = 6;
 constexpr int kRecLanes = 64;
 
 // Arguments of the fused executor kernel.

@@ -289,8 +289,8 @@ __device__ __forceinline__ void op_contract(V *mem, const DOp &op, const int32_t
 template <typename V, int LGK>
 __device__ __forceinline__ void contract_lite(V *mem, const int4 &rec, uint32_t hdr) {
   constexpr int K = 1 << LGK;
-  const int nOut = (hdr >> 4) & 127;
-  const int z = (int)(hdr >> 12);
+  const int nOut = 1 << ((hdr >> 7) & 15u);
+  const int z = (int)(hdr >> 15);
   int32_t tx[K], ty[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -310,6 +310,86 @@ __device__ __forceinline__ void contract_lite(V *mem, const int4 &rec, uint32_t 
     for (int k = 0; k < K; ++k) acc = cmul_add(acc, xv[k], yv[k]);
     mem[z + threadIdx.x] = acc;
   }
+}
+
+// Outer product (no summed index) with up to 256 outputs from a lane
+// record: lane l forms outputs l + 64 r, whose operand offsets differ from
+// output l's by the uniform steps held in the record.
+template <typename V>
+__device__ __forceinline__ void contract_wide(V *mem, const int4 &rec, uint32_t hdr) {
+  const int R = 1 << (((hdr >> 7) & 15u) - 6);
+  const int z = (int)(hdr >> 15) + (int)threadIdx.x;
+  int32_t dx[4], dy[4];
+#pragma unroll
+  for (int r = 1; r < 4; ++r) {
+    const uint32_t t = (uint32_t)__builtin_amdgcn_readlane(rec.w, r);
+    dx[r] = (int32_t)(t & 0xffffu);
+    dy[r] = (int32_t)(t >> 16);
+  }
+  V xv[4], yv[4];
+  xv[0] = mem[rec.x];
+  yv[0] = mem[rec.y];
+#pragma unroll
+  for (int r = 1; r < 4; ++r)
+    if (r < R) {
+      xv[r] = mem[rec.x + dx[r]];
+      yv[r] = mem[rec.y + dy[r]];
+    }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (r < R) mem[z + 64 * r] = cmul_add(czero<V>(), xv[r], yv[r]);
+}
+
+template <typename V>
+__device__ __forceinline__ V shfl_xor_c(V v, int m) {
+  V r;
+  r.x = __shfl_xor(v.x, m, 64);
+  r.y = __shfl_xor(v.y, m, 64);
+  return r;
+}
+
+// Contraction with few outputs and many summed entries from a lane record:
+// G lanes per output each sum R entries (uniform offset steps), then the G
+// partial sums are reduced across lanes in a fixed order.
+template <typename V>
+__device__ __forceinline__ void contract_narrow(V *mem, const int4 &rec, uint32_t hdr) {
+  const int lgG = (int)((hdr >> 3) & 15u);
+  const int nOut = 1 << ((hdr >> 7) & 15u);
+  const int R = 1 << ((hdr >> 11) & 15u);
+  const int z = (int)(hdr >> 15);
+  V acc = czero<V>();
+  for (int i = 0; i < R; i += 4) {
+    V xv[4], yv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u < R) {
+        const uint32_t t = (uint32_t)__builtin_amdgcn_readlane(rec.z, i + u);
+        xv[u] = mem[rec.x + (int32_t)(t & 0xffffu)];
+        yv[u] = mem[rec.y + (int32_t)(t >> 16)];
+      }
+  #pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u < R) acc = cmul_add(acc, xv[u], yv[u]);
+  }
+  for (int m = 1; m < (1 << lgG); m <<= 1) acc = cadd(acc, shfl_xor_c(acc, m));
+  const int l = (int)threadIdx.x;
+  if ((l & ((1 << lgG) - 1)) == 0 && (l >> lgG) < nOut) mem[z + (l >> lgG)] = acc;
+}
+
+// Rank-0 contraction from a lane record, in FP64.
+template <typename V>
+__device__ __forceinline__ void scalar_rec(const V *mem, double2 *scal, const int4 &rec, uint32_t hdr) {
+  const int K = 1 << ((hdr >> 3) & 15u);
+  double re = 0.0, im = 0.0;
+  if ((int)threadIdx.x < K) {
+    const double2 x = to_d2(mem[rec.x]);
+    const double2 y = to_d2(mem[rec.y]);
+    re = x.x * y.x - x.y * y.y;
+    im = x.x * y.y + x.y * y.x;
+  }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (threadIdx.x == 0) scal[hdr >> 15] = make_double2(re, im);
 }
 
 // Fused executor. GRAD selects the forward+adjoint program: the adjoint of
@@ -367,14 +447,49 @@ void fused_exec_kernel(FusedArgs a) {
       if (BLOCK == kRecLanes) {
         if (o + 1 < net.n_ops) nrec = recs[(size_t)(o + 1) * kRecLanes];
         const uint32_t hdr = (uint32_t)__builtin_amdgcn_readfirstlane(rec.w);
-        if (hdr & 1u) {
-          switch ((hdr >> 1) & 7u) {
+        const uint32_t type = hdr & 7u;
+        if (type == kRecLite) {
+          switch ((hdr >> 3) & 15u) {
             case 0: contract_lite<V, 0>(mem, rec, hdr); break;
             case 1: contract_lite<V, 1>(mem, rec, hdr); break;
             case 2: contract_lite<V, 2>(mem, rec, hdr); break;
             case 3: contract_lite<V, 3>(mem, rec, hdr); break;
             default: contract_lite<V, 4>(mem, rec, hdr); break;
           }
+        } else if (type == kRecWide) {
+          contract_wide<V>(mem, rec, hdr);
+        } else if (type == kRecNarrow) {
+          contract_narrow<V>(mem, rec, hdr);
+        } else if (type == kRecScalar) {
+          scalar_rec<V>(mem, scal, rec, hdr);
+        } else if (GRAD && type == kRecSeed) {
+          if (tid == 0) {
+            const int skip = rec.x;
+            double2 p = make_double2(1.0, 0.0);
+            for (int j = 0; j < net.n_comp; ++j)
+              if (j != skip) p = cmul(p, scal[j]);
+            mem[hdr >> 15] = from_d2<V>(p);
+          }
+        } else if (GRAD && type == kRecLeafGrad) {
+          // entries l + 64 q: adjoint times the bound angle derivative
+          const int cnt = 1 << ((hdr >> 7) & 15u);
+          const int slot = __builtin_amdgcn_readlane(rec.z, 0);
+          const uint32_t clo = (uint32_t)__builtin_amdgcn_readlane(rec.z, 1);
+          const uint32_t chi = (uint32_t)__builtin_amdgcn_readlane(rec.z, 2);
+          const double coeff = __hiloint2double((int)chi, (int)clo);
+          const V *dv = dbound + (size_t)set * a.per_set + slot;
+          double acc = 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (tid + 64 * q < cnt) {
+              const double2 g = to_d2(mem[rec.x + 64 * q]);
+              const double2 w = to_d2(dv[((uint32_t)rec.y >> (8 * q)) & 0xffu]);
+              acc += g.x * w.x - g.y * w.y;
+            }
+          acc = wave_sum(acc);
+          if (tid == 0) gacc[hdr >> 15] += coeff * acc;
+        }
+        if (type != 0) {
           __syncthreads();
           rec = nrec;
           continue;

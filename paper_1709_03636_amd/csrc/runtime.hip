@@ -259,22 +259,121 @@ static uint32_t host_pdep(uint32_t v, uint32_t mask) {
   return out;
 }
 
-// Lane records (see kRecLanes) of ops [first, first + n) of `loc`.
-static void build_records(const HostProgram &loc, int first, int n, std::vector<int32_t> &recs) {
+// Lane records (see kRecLanes) of ops [first, first + n) of `loc`;
+// `pt` are the network's parametric tensors (for leaf-gradient ops).
+static void build_records(const HostProgram &loc, const std::vector<DParam> &pt, int first, int n,
+                          std::vector<int32_t> &recs) {
+  auto pack = [](int32_t a, int32_t b) { return (a & 0xffff) | (b << 16); };
   for (int o = first; o < first + n; ++o) {
     const DOp &op = loc.ops[o];
-    const int nOut = 1 << (op.nFX + op.nFY);
-    const bool lite = op.type == OP_CONTRACT && nOut <= kRecLanes && op.nS <= 4 && op.z < (1 << 19);
+    const int lgOut = op.nFX + op.nFY;
+    const uint32_t maskJ = (1u << op.nFY) - 1u;
+    // LDS offsets of output c's X and Y rows
+    auto offs = [&](uint32_t c, int32_t &ox, int32_t &oy) {
+      ox = op.x + (int32_t)host_pdep(c >> op.nFY, op.maskX);
+      oy = op.y + (int32_t)host_pdep(c & maskJ, op.maskY);
+    };
+    // (X, Y) offsets of summed entry k (tables of at most 2^12 entries)
+    auto tab = [&](int k, int32_t &tx, int32_t &ty) {
+      tx = loc.tabs[op.tab + 2 * k];
+      ty = loc.tabs[op.tab + 2 * k + 1];
+    };
+    int type = 0, A = 0, B = 0, C = 0, zf = 0;
+    int lgG = 0;
+    if (op.type == OP_CONTRACT) {
+      zf = op.z;
+      if (lgOut <= 6 && op.nS <= 4) {
+        type = kRecLite;
+        A = op.nS;
+        B = lgOut;
+      } else if (op.nS == 0 && lgOut <= 8) {
+        type = kRecWide;
+        B = lgOut;
+      } else if (lgOut <= 6 && op.nS <= 12) {
+        lgG = std::min(6 - lgOut, op.nS);
+        const int lgR = op.nS - lgG;
+        bool additive = lgR <= 6;
+        // entry k = g + G i must sit at t(g) + t(G i)
+        for (int k = 0; additive && k < (1 << op.nS); ++k) {
+          int32_t ax, ay, bx, by, cx, cy;
+          tab(k, ax, ay);
+          tab(k & ((1 << lgG) - 1), bx, by);
+          tab(k & ~((1 << lgG) - 1), cx, cy);
+          additive = ax == bx + cx && ay == by + cy;
+        }
+        if (additive) {
+          type = kRecNarrow;
+          A = lgG;
+          B = lgOut;
+          C = lgR;
+        }
+      }
+    } else if (op.type == OP_SCALAR && op.nS <= 6) {
+      type = kRecScalar;
+      A = op.nS;
+      zf = op.z;
+    } else if (op.type == OP_SEED) {
+      type = kRecSeed;
+      zf = op.z;
+    } else if (op.type == OP_LEAFGRAD && op.nFX <= 8) {
+      type = kRecLeafGrad;
+      B = op.nFX;
+      zf = pt[op.aux0].param;
+    }
+    if (zf >= (1 << 17)) type = 0;
     for (int l = 0; l < kRecLanes; ++l) {
       int32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-      if (lite) {
-        if (l < nOut) {
-          a0 = op.x + (int32_t)host_pdep((uint32_t)l >> op.nFY, op.maskX);
-          a1 = op.y + (int32_t)host_pdep((uint32_t)l & ((1u << op.nFY) - 1u), op.maskY);
+      if (type == kRecLite) {
+        if (l < (1 << lgOut)) offs((uint32_t)l, a0, a1);
+        if (l < (1 << op.nS)) {
+          int32_t tx, ty;
+          tab(l, tx, ty);
+          a2 = pack(tx, ty);
         }
-        if (l < (1 << op.nS)) a2 = (loc.tabs[op.tab + 2 * l] & 0xffff) | (loc.tabs[op.tab + 2 * l + 1] << 16);
-        a3 = 1 | (op.nS << 1) | (nOut << 4) | (op.z << 12);
+      } else if (type == kRecWide) {
+        offs((uint32_t)l, a0, a1);
+        if (l >= 1 && (l << 6) < (1 << lgOut)) {  // offset steps of outputs 64 l
+          int32_t dx, dy;
+          offs((uint32_t)(l << 6), dx, dy);
+          a3 = pack(dx - op.x, dy - op.y);
+        }
+      } else if (type == kRecNarrow) {
+        // lane l sums entries g + G i (g = l mod G) of output l / G
+        const int j = l >> lgG, g = l & ((1 << lgG) - 1);
+        if (j < (1 << lgOut)) {
+          int32_t tx, ty;
+          offs((uint32_t)j, a0, a1);
+          tab(g, tx, ty);
+          a0 += tx;
+          a1 += ty;
+        } else {
+          a0 = op.x;
+          a1 = op.y;
+        }
+        if (l < (1 << C)) {
+          int32_t tx, ty;
+          tab(l << lgG, tx, ty);
+          a2 = pack(tx, ty);
+        }
+      } else if (type == kRecScalar) {
+        int32_t tx = 0, ty = 0;
+        if (l < (1 << op.nS)) tab(l, tx, ty);
+        a0 = op.x + tx;
+        a1 = op.y + ty;
+      } else if (type == kRecSeed) {
+        if (l == 0) a0 = op.aux0;
+      } else if (type == kRecLeafGrad) {
+        a0 = op.x + l;
+        for (int q = 0; q < 4; ++q)
+          if (l + (q << 6) < (1 << op.nFX)) a1 |= (loc.tabs[op.tab + l + (q << 6)] & 0xff) << (8 * q);
+        const DParam &d = pt[op.aux0];
+        int64_t bits;
+        std::memcpy(&bits, &d.coeff, sizeof(bits));
+        if (l == 0) a2 = d.slot;
+        if (l == 1) a2 = (int32_t)(bits & 0xffffffff);
+        if (l == 2) a2 = (int32_t)(bits >> 32);
       }
+      if (l == 0) a3 = type ? (type | (A << 3) | (B << 7) | (C << 11) | (zf << 15)) : 0;
       recs.push_back(a0);
       recs.push_back(a1);
       recs.push_back(a2);
@@ -329,7 +428,7 @@ static void append_fused(const Net &net, const NetLayout &lay, HostProgram &hp) 
   }
   const int tab0 = (int)hp.tabs.size(), op0 = (int)hp.ops.size(), ptens_begin = (int)hp.ptens.size();
   const int rec0 = (int)(hp.recs.size() / (4 * kRecLanes));
-  build_records(loc, 0, (int)loc.ops.size(), hp.recs);
+  build_records(loc, lptens, 0, (int)loc.ops.size(), hp.recs);
   const int const_begin = (int)(hp.consts.size() / 2);
   for (DOp d : loc.ops) {
     d.tab += tab0;
