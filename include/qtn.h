@@ -193,6 +193,9 @@ typedef struct {
   int32_t n_levels;                   /* level launches per pass */
   int32_t lds_bytes_fwd, lds_bytes_grad;
   int32_t n_programs;                 /* distinct fused programs (identical networks share one) */
+  int32_t fused_block;                /* workgroup size of the fused executor */
+  int32_t rec_only;                   /* bit 0 / 1: the forward / adjoint fused programs have a lane
+                                         record for every op (kernel without the descriptor path) */
   int32_t reserved;
   double flops_fwd, bytes_fwd;        /* algorithmic, one parameter vector, all networks */
   double flops_grad, bytes_grad;      /* algorithmic, adjoint sweep only */

@@ -395,8 +395,9 @@ __device__ __forceinline__ void scalar_rec(const V *mem, double2 *scal, const in
 // Fused executor. GRAD selects the forward+adjoint program: the adjoint of
 // each parametric leaf is contracted with the leaf's angle derivative (bound
 // by the binding kernel) as soon as it is formed, and summed per parameter in
-// FP64.
-template <typename T, int BLOCK, bool GRAD>
+// FP64. RONLY (64-lane workgroups): every op has a lane record, the
+// descriptor path is left out.
+template <typename T, int BLOCK, bool GRAD, bool RONLY>
 __global__ __launch_bounds__(BLOCK)
 #ifdef QTN_WAVES
 __attribute__((amdgpu_waves_per_eu(QTN_WAVES, QTN_WAVES)))
@@ -489,7 +490,7 @@ void fused_exec_kernel(FusedArgs a) {
           acc = wave_sum(acc);
           if (tid == 0) gacc[hdr >> 15] += coeff * acc;
         }
-        if (type != 0) {
+        if (RONLY || type != 0) {
           __syncthreads();
           rec = nrec;
           continue;
@@ -571,22 +572,23 @@ __global__ __launch_bounds__(256) void combine_kernel(const double *__restrict__
 
 // --- launch helpers (host) ----------------------------------------------------------------
 template <typename T, bool G>
-static const void *fused_ptr_t(int block) {
+static const void *fused_ptr_t(int block, bool rec_only) {
   switch (block) {
-    case 64: return (const void *)fused_exec_kernel<T, 64, G>;
-    case 128: return (const void *)fused_exec_kernel<T, 128, G>;
-    default: return (const void *)fused_exec_kernel<T, 256, G>;
+    case 64: return rec_only ? (const void *)fused_exec_kernel<T, 64, G, true> : (const void *)fused_exec_kernel<T, 64, G, false>;
+    case 128: return (const void *)fused_exec_kernel<T, 128, G, false>;
+    default: return (const void *)fused_exec_kernel<T, 256, G, false>;
   }
 }
 
-const void *fused_kernel_ptr(int dtype, int block, bool grad) {
-  if (dtype == TN_C128) return grad ? fused_ptr_t<double, true>(block) : fused_ptr_t<double, false>(block);
-  return grad ? fused_ptr_t<float, true>(block) : fused_ptr_t<float, false>(block);
+const void *fused_kernel_ptr(int dtype, int block, bool grad, bool rec_only) {
+  if (dtype == TN_C128)
+    return grad ? fused_ptr_t<double, true>(block, rec_only) : fused_ptr_t<double, false>(block, rec_only);
+  return grad ? fused_ptr_t<float, true>(block, rec_only) : fused_ptr_t<float, false>(block, rec_only);
 }
 
-hipError_t launch_fused(int dtype, int block, bool grad, const FusedArgs &a, int grid, int lds_bytes,
+hipError_t launch_fused(int dtype, int block, bool grad, bool rec_only, const FusedArgs &a, int grid, int lds_bytes,
                         hipStream_t st) {
-  const void *k = fused_kernel_ptr(dtype, block, grad);
+  const void *k = fused_kernel_ptr(dtype, block, grad, rec_only);
   void *args[] = {(void *)&a};
   return hipLaunchKernel(k, dim3(grid), dim3(block), args, lds_bytes, st);
 }

@@ -17,9 +17,9 @@
 
 namespace qtn {
 
-hipError_t launch_fused(int dtype, int block, bool grad, const FusedArgs &a, int grid, int lds_bytes,
+hipError_t launch_fused(int dtype, int block, bool grad, bool rec_only, const FusedArgs &a, int grid, int lds_bytes,
                         hipStream_t st);
-const void *fused_kernel_ptr(int dtype, int block, bool grad);
+const void *fused_kernel_ptr(int dtype, int block, bool grad, bool rec_only);
 hipError_t launch_combine(const double *val, const double *gnet, const double *coef, double offset, int n_nets,
                           int n_sets, int n_params, double *obj, double *grad, hipStream_t st);
 hipError_t launch_bind(int dtype, const DParam *slots, int n_slots, const double *params, int n_params, int n_sets,
@@ -167,6 +167,7 @@ struct HostProgram {
   int max_mem_fwd = 0, max_mem_grad = 0, max_comp = 0, max_ptens_elems = 0;
   std::map<std::string, int> program_of;  // fused program signature -> first network using it
   int n_programs = 0;
+  bool generic[2] = {false, false};  // some op of a forward / adjoint program has no lane record
 };
 
 struct LevelNet {
@@ -429,6 +430,9 @@ static void append_fused(const Net &net, const NetLayout &lay, HostProgram &hp) 
   const int tab0 = (int)hp.tabs.size(), op0 = (int)hp.ops.size(), ptens_begin = (int)hp.ptens.size();
   const int rec0 = (int)(hp.recs.size() / (4 * kRecLanes));
   build_records(loc, lptens, 0, (int)loc.ops.size(), hp.recs);
+  for (int variant = 0; variant < 2; ++variant)
+    for (int o = op_begin[variant]; o < op_begin[variant] + n_ops[variant]; ++o)
+      if (hp.recs[((size_t)(rec0 + o) * kRecLanes) * 4 + 3] == 0) hp.generic[variant] = true;
   const int const_begin = (int)(hp.consts.size() / 2);
   for (DOp d : loc.ops) {
     d.tab += tab0;
@@ -579,6 +583,11 @@ static void free_batch_dev(tn_batch *b) {
     if (p) (void)hipFree(p);
 }
 
+// 64-lane workgroups whose programs have a lane record for every op run a
+// kernel instance without the descriptor path (fewer registers live across
+// the op loop).
+static bool rec_only(const tn_batch *b, int variant) { return b->block == kRecLanes && !b->hp.generic[variant]; }
+
 static int layout_lds(tn_batch *b, int variant) {
   const int eb = b->dtype == TN_C128 ? 16 : 8;
   const int mem = variant == 0 ? b->hp.max_mem_fwd : b->hp.max_mem_grad;
@@ -599,7 +608,7 @@ static int layout_lds(tn_batch *b, int variant) {
   }
   (variant == 0 ? b->lds_fwd : b->lds_grad) = o;
   int per_cu = 0;
-  const void *k = fused_kernel_ptr(b->dtype, b->block, variant == 1);
+  const void *k = fused_kernel_ptr(b->dtype, b->block, variant == 1, rec_only(b, variant));
   if (o > 64 * 1024) HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, o));
   HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, b->block, o));
   int dev = 0, cus = 0;
@@ -787,7 +796,7 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     const int rounds = (a.n_tasks + cap - 1) / cap;
     const int grid = (a.n_tasks + rounds - 1) / rounds;
     a.per_block = rounds;
-    e = launch_fused(b->dtype, b->block, grad, a, grid, grad ? b->lds_grad : b->lds_fwd, st);
+    e = launch_fused(b->dtype, b->block, grad, rec_only(b, v), a, grid, grad ? b->lds_grad : b->lds_fwd, st);
     if (e != hipSuccess) {
       b->poisoned = true;
       return hip_fail(e, "fused executor launch");
@@ -1046,6 +1055,8 @@ int batch_info(const tn_batch *b, tn_batch_stats *s) {
   for (auto &ln : b->level) levels = std::max(levels, ln.n_ops[1]);
   s->n_levels = levels;
   s->n_programs = b->hp.n_programs;
+  s->fused_block = b->block;
+  s->rec_only = (rec_only(b, 0) ? 1 : 0) | (rec_only(b, 1) ? 2 : 0);
   s->lds_bytes_fwd = b->lds_fwd;
   s->lds_bytes_grad = b->lds_grad;
   s->flops_fwd = b->flops_fwd;

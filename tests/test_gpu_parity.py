@@ -264,6 +264,39 @@ def test_level_executor_matches_fused(monkeypatch):
         assert np.max(np.abs(res[mode][1] - ps)) <= 1e-10 * max(1, np.abs(ps).max())
 
 
+@pytest.mark.parametrize("p", [1, 2])
+def test_fused_workgroup_sizes_and_record_kernels(p, monkeypatch):
+    """Every fused workgroup size gives the oracle's cost and gradient. At 64
+    lanes the p=1 light cones run on the records-only kernel; the p=2 ones
+    (intermediates of 2^12 entries, too large for a lane record) also need
+    the descriptor path."""
+    qtn, qaoa = _qtn(), _qaoa()
+    n = 14
+    e = workloads.random_regular_graph(3, n, 8)
+    S = 3
+    ang = torch.tensor(workloads.qaoa_angles(11, S, p), device="cuda", dtype=torch.float64)
+    ref = np.array([gradients.cost(n, e, list(a)) for a in ang.cpu().numpy()])
+    ps = np.array([gradients.parameter_shift(n, e, list(a)) for a in ang.cpu().numpy()])
+    for blk in (64, 128, 256):
+        monkeypatch.setenv("QTN_FUSED_BLOCK", str(blk))
+        model = qaoa.MaxCut(n, e, p, qtn.TN_C64, order="linegraph", max_sets=S)
+        info = model.batch.info()
+        _say(f"fused block {blk} p={p} rec_only={info['rec_only']} n_fused={info['n_fused']}")
+        assert info["fused_block"] == blk and info["n_fused"] > 0
+        assert info["n_fused"] + info["n_level"] == len(e)
+        if blk == 64 and p == 1:
+            assert info["rec_only"] == 3
+        elif blk == 64:
+            assert info["rec_only"] & 2 == 0
+        else:
+            assert info["rec_only"] == 0
+        obj, grad = model.value_and_grad(ang)
+        torch.cuda.synchronize()
+        obj, grad = obj.cpu().numpy(), grad.cpu().numpy()
+        assert np.max(np.abs(obj - ref)) <= 1e-5 * max(1, np.abs(ref).max()), blk
+        assert np.max(np.abs(grad - ps)) <= 1e-4 * max(1, np.abs(ps).max()), blk
+
+
 # --- dense regime: whole-circuit networks, large steps on the matrix cores -----------------
 
 @pytest.mark.parametrize("d,n", [(6, 12), (5, 14)])

@@ -35,6 +35,31 @@ def test_library_exports_every_declared_symbol(qtn):
     assert b"gfx950" in L.tn_version()
 
 
+def test_binding_structs_match_header(qtn):
+    """Every struct the header declares has a ctypes twin with the same
+    fields in the same order, of the same C types (so the same layout)."""
+    import ctypes
+    hdr = open(os.path.join(ROOT, "include", "qtn.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    cmap = {"int32_t": ctypes.c_int32, "double": ctypes.c_double, "uint64_t": ctypes.c_uint64}
+    structs = re.findall(r"typedef struct \{(.*?)\}\s*(\w+);", hdr, re.S)
+    assert {n for _, n in structs} >= {"tn_gate", "tn_target", "tn_plan_stats", "tn_batch_stats"}
+    for body, name in structs:
+        fields = []
+        for decl in filter(None, (d.strip() for d in body.split(";"))):
+            m = re.match(r"(const\s+)?(\w+)\s*(\*?)\s*(.*)", decl)
+            ctype, ptr = m.group(2), m.group(3)
+            for nm in (x.strip().lstrip("*").strip() for x in m.group(4).split(",")):
+                fields.append((nm, ctype, bool(ptr) or m.group(4).lstrip().startswith("*")))
+        py = getattr(qtn, name)._fields_
+        assert [f[0] for f in fields] == [f[0] for f in py], name
+        for (nm, ctype, ptr), (_, pt) in zip(fields, py):
+            if ptr:
+                assert issubclass(pt, ctypes._Pointer), (name, nm)
+            else:
+                assert pt is cmap[ctype], (name, nm)
+
+
 def test_qaoa_p1_network_shape(qtn, qaoa):
     # triangle-free edge of a 3-regular graph: 6 boundary vectors, 5 ZZ, 2 RX, 6 measurements
     e = workloads.random_regular_graph(3, 100, 0)
