@@ -71,8 +71,9 @@ struct DNet {
 // (7-10), C (11-14), and bits 15.. the result offset (leaf gradients: the
 // parameter index). Offsets are LDS element offsets; "packed" means an
 // (X, Y) pair as two 16-bit halves. Types:
-//  kRecLite     contraction, 2^B <= 64 outputs, K = 2^A <= 16 summed
-//               entries: x, y = offsets of output l's X and Y rows, z =
+//  kRecLite     contraction, 2^B <= 64 outputs, K = 2^A <= 4 summed
+//               entries (larger K go to kRecNarrow, which needs fewer
+//               registers): x, y = offsets of output l's X and Y rows, z =
 //               packed offsets of summed entry l;
 //  kRecWide     outer product (K = 1), 2^B <= 256 outputs: x, y for output
 //               l; w of lanes 1-3 = packed offset steps of outputs 64 l

@@ -437,25 +437,25 @@ void fused_exec_kernel(FusedArgs a) {
     // loads share one wait counter, so an outstanding descriptor load would
     // delay every LDS wait of the current op.
     const DOp *ops = a.ops + net.op_begin;
-    // lane records (64-lane workgroups): the next op's record is loaded
-    // while the current op runs (vector loads: their wait counter is not
-    // the LDS one)
+    // lane records (64-lane workgroups): the records of the next two ops are
+    // in flight while the current op runs (vector loads: their wait counter
+    // is not the LDS one; two hide an L2 hit, more cost occupancy)
     const int4 *recs = a.recs + (size_t)net.rec_begin * kRecLanes + (tid & (kRecLanes - 1));
     int4 rec = make_int4(0, 0, 0, 0);
+    int4 rec1 = make_int4(0, 0, 0, 0);
     if (BLOCK == kRecLanes && net.n_ops > 0) rec = recs[0];
+    if (BLOCK == kRecLanes && net.n_ops > 1) rec1 = recs[kRecLanes];
     for (int o = 0; o < net.n_ops; ++o) {
       int4 nrec = make_int4(0, 0, 0, 0);
       if (BLOCK == kRecLanes) {
-        if (o + 1 < net.n_ops) nrec = recs[(size_t)(o + 1) * kRecLanes];
+        if (o + 2 < net.n_ops) nrec = recs[(size_t)(o + 2) * kRecLanes];
         const uint32_t hdr = (uint32_t)__builtin_amdgcn_readfirstlane(rec.w);
         const uint32_t type = hdr & 7u;
         if (type == kRecLite) {
           switch ((hdr >> 3) & 15u) {
             case 0: contract_lite<V, 0>(mem, rec, hdr); break;
             case 1: contract_lite<V, 1>(mem, rec, hdr); break;
-            case 2: contract_lite<V, 2>(mem, rec, hdr); break;
-            case 3: contract_lite<V, 3>(mem, rec, hdr); break;
-            default: contract_lite<V, 4>(mem, rec, hdr); break;
+            default: contract_lite<V, 2>(mem, rec, hdr); break;
           }
         } else if (type == kRecWide) {
           contract_wide<V>(mem, rec, hdr);
@@ -492,7 +492,8 @@ void fused_exec_kernel(FusedArgs a) {
         }
         if (RONLY || type != 0) {
           __syncthreads();
-          rec = nrec;
+          rec = rec1;
+          rec1 = nrec;
           continue;
         }
       }
@@ -533,7 +534,8 @@ void fused_exec_kernel(FusedArgs a) {
         if (tid == 0) gacc[d.param] += d.coeff * acc;
       }
       __syncthreads();
-      rec = nrec;
+      rec = rec1;
+      rec1 = nrec;
     }
 
     if (tid == 0) {

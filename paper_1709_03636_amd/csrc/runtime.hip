@@ -283,7 +283,7 @@ static void build_records(const HostProgram &loc, const std::vector<DParam> &pt,
     int lgG = 0;
     if (op.type == OP_CONTRACT) {
       zf = op.z;
-      if (lgOut <= 6 && op.nS <= 4) {
+      if (lgOut <= 6 && op.nS <= 2) {
         type = kRecLite;
         A = op.nS;
         B = lgOut;
