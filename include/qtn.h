@@ -196,6 +196,8 @@ typedef struct {
   int32_t fused_block;                /* workgroup size of the fused executor */
   int32_t rec_only;                   /* bit 0 / 1: the forward / adjoint fused programs have a lane
                                          record for every op (kernel without the descriptor path) */
+  int32_t sets_per_wave_fwd;          /* angle sets one 64-lane wave of the fused executor runs at once: */
+  int32_t sets_per_wave_grad;         /* forward / adjoint programs (1, 2 or 4) */
   int32_t reserved;
   double flops_fwd, bytes_fwd;        /* algorithmic, one parameter vector, all networks */
   double flops_grad, bytes_grad;      /* algorithmic, adjoint sweep only */

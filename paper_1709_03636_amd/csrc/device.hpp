@@ -94,6 +94,32 @@ struct DNet {
 constexpr int kRecLite = 1, kRecWide = 2, kRecNarrow = 3, kRecScalar = 4, kRecSeed = 5, kRecLeafGrad = 6;
 constexpr int kRecLanes = 64;
 
+// Set-packed records: one 64-lane wave runs S = 2 or 4 angle sets of one
+// network at once, W = 64 / S lanes per set, each set in its own LDS region
+// of set_stride elements. A record is W int4 (lane w: x, y, z, w); lane w of
+// every set reads lane w of the record. Header (w of lane 0): bits 0-2
+// type, 3-5 log2 G, 6-8 log2 Q, 9-11 log2 R, 12-15 log2 of the number of
+// outputs, 16.. the result offset (leaf gradient: parameter index).
+// "Packed" = two 16-bit offsets (X, Y). G <= kMaxGroupLanes keeps every
+// cross-lane sum inside one row of 16 lanes.
+//  kSetContract  lane w serves outputs w / G + (W / G) q (q < Q) and summed
+//                entries w mod G + G i (i < R): x, y = operand offsets of
+//                its first output and entry; z of lane i = packed offset
+//                step of entry G i; w of lane q >= 1 = packed offset step of
+//                output W q (Q > 1 only when G = 1). The G partial sums of
+//                an output are reduced across lanes.
+//  kSetScalar    rank-0 result in FP64 over entries w + G i; x, y, z as
+//                above.
+//  kSetSeed      adjoint seed; x of lane 0 = the component left out.
+//  kSetLeafGrad  adjoint of a parametric leaf against the bound angle
+//                derivative, FP64, entries w + G i: x = adjoint offset of
+//                entry w, y = derivative index of entry w, z of lane i =
+//                index step of entry G i, w of lane 1 = bound-tensor slot,
+//                of lanes 2-3 = FP64 coefficient.
+// Offsets add over disjoint index bits, which the host checks per op.
+constexpr int kMaxGroupLanes = 16, kLgMaxGroupLanes = 4;
+constexpr int kSetContract = 1, kSetScalar = 2, kSetSeed = 3, kSetLeafGrad = 4;
+
 // Arguments of the fused executor kernel.
 struct FusedArgs {
   const DNet *nets;
@@ -108,6 +134,7 @@ struct FusedArgs {
   double *out_val;          // [net][set][2]
   double *out_grad;         // [net][set][n_params] (adjoint programs)
   int n_params, n_sets, n_tasks, per_set;
+  int set_stride, n_groups, max_comp;  // set-packed executor: LDS elements per set, set groups, scalars per set
   int per_block;            // workgroup b runs tasks [b*per_block, (b+1)*per_block)
   int scratch_off, scal_off, gacc_off, red_off, gbar_off;  // LDS byte offsets
 };

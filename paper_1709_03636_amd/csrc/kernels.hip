@@ -157,10 +157,60 @@ __global__ __launch_bounds__(256) void bind_params_kernel(const DParam *__restri
 }
 
 // --- reductions -------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Cross-lane moves with DPP (no LDS traffic). Inside a row of 16 lanes the
+// controls used are permutations of the row; row_bcast15 / row_bcast31 add
+// the last lane of a row into the rows selected by the row mask (the other
+// rows receive 0).
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float2 dpp_c(float2 v) {
+  return make_float2(dpp_f32<CTRL, ROWS>(v.x), dpp_f32<CTRL, ROWS>(v.y));
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double2 dpp_c(double2 v) {
+  return make_double2(dpp_f64<CTRL, ROWS>(v.x), dpp_f64<CTRL, ROWS>(v.y));
+}
+
+// Sum over aligned groups of 2^lg lanes (lg <= 6), fixed order: lanes 1
+// apart, 2 apart (quad permutations), the mirrored half-row and row, then
+// rows pairwise and the two row pairs. For lg <= 4 every lane of a group
+// holds the group's sum afterwards; in any case its last lane does. All 64
+// lanes must be active.
+template <typename V>
+__device__ __forceinline__ V group_sum(V v, int lg) {
+  if (lg > 0) v = cadd(v, dpp_c<0xB1>(v));        // quad_perm [1,0,3,2]
+  if (lg > 1) v = cadd(v, dpp_c<0x4E>(v));        // quad_perm [2,3,0,1]
+  if (lg > 2) v = cadd(v, dpp_c<0x141>(v));       // row_half_mirror
+  if (lg > 3) v = cadd(v, dpp_c<0x140>(v));       // row_mirror
+  if (lg > 4) v = cadd(v, dpp_c<0x142, 0xA>(v));  // row_bcast15 into rows 1, 3
+  if (lg > 5) v = cadd(v, dpp_c<0x143, 0xC>(v));  // row_bcast31 into rows 2, 3
   return v;
+}
+
+__device__ __forceinline__ double group_sum_f64(double v, int lg) {
+  if (lg > 0) v += dpp_f64<0xB1>(v);
+  if (lg > 1) v += dpp_f64<0x4E>(v);
+  if (lg > 2) v += dpp_f64<0x141>(v);
+  if (lg > 3) v += dpp_f64<0x140>(v);
+  if (lg > 4) v += dpp_f64<0x142, 0xA>(v);
+  if (lg > 5) v += dpp_f64<0x143, 0xC>(v);
+  return v;
+}
+
+// Sum over the wave, returned to every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = group_sum_f64(v, 6);
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                          __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
 
 // Fixed-tree block sum; the result is valid in thread 0. red: BLOCK/64 doubles.
@@ -340,13 +390,6 @@ __device__ __forceinline__ void contract_wide(V *mem, const int4 &rec, uint32_t 
     if (r < R) mem[z + 64 * r] = cmul_add(czero<V>(), xv[r], yv[r]);
 }
 
-template <typename V>
-__device__ __forceinline__ V shfl_xor_c(V v, int m) {
-  V r;
-  r.x = __shfl_xor(v.x, m, 64);
-  r.y = __shfl_xor(v.y, m, 64);
-  return r;
-}
 
 // Contraction with few outputs and many summed entries from a lane record:
 // G lanes per output each sum R entries (uniform offset steps), then the G
@@ -371,9 +414,9 @@ __device__ __forceinline__ void contract_narrow(V *mem, const int4 &rec, uint32_
     for (int u = 0; u < 4; ++u)
       if (i + u < R) acc = cmul_add(acc, xv[u], yv[u]);
   }
-  for (int m = 1; m < (1 << lgG); m <<= 1) acc = cadd(acc, shfl_xor_c(acc, m));
-  const int l = (int)threadIdx.x;
-  if ((l & ((1 << lgG) - 1)) == 0 && (l >> lgG) < nOut) mem[z + (l >> lgG)] = acc;
+  acc = group_sum(acc, lgG);  // valid in the last lane of each group
+  const int l = (int)threadIdx.x, g1 = (1 << lgG) - 1;
+  if ((l & g1) == g1 && (l >> lgG) < nOut) mem[z + (l >> lgG)] = acc;
 }
 
 // Rank-0 contraction from a lane record, in FP64.
@@ -387,9 +430,8 @@ __device__ __forceinline__ void scalar_rec(const V *mem, double2 *scal, const in
     re = x.x * y.x - x.y * y.y;
     im = x.x * y.y + x.y * y.x;
   }
-  re = wave_sum(re);
-  im = wave_sum(im);
-  if (threadIdx.x == 0) scal[hdr >> 15] = make_double2(re, im);
+  const double2 v = group_sum(make_double2(re, im), 6);
+  if (threadIdx.x == 63) scal[hdr >> 15] = v;
 }
 
 // Fused executor. GRAD selects the forward+adjoint program: the adjoint of
@@ -487,8 +529,8 @@ void fused_exec_kernel(FusedArgs a) {
               const double2 w = to_d2(dv[((uint32_t)rec.y >> (8 * q)) & 0xffu]);
               acc += g.x * w.x - g.y * w.y;
             }
-          acc = wave_sum(acc);
-          if (tid == 0) gacc[hdr >> 15] += coeff * acc;
+          acc = group_sum_f64(acc, 6);
+          if (tid == 63) gacc[hdr >> 15] += coeff * acc;
         }
         if (RONLY || type != 0) {
           __syncthreads();
@@ -551,6 +593,211 @@ void fused_exec_kernel(FusedArgs a) {
   }
 }
 
+// --- set-packed fused executor ----------------------------------------------------------
+// One 64-lane wave runs S = 2 or 4 angle sets of one network: lane
+// l = s * W + w (W = 64 / S) serves set s. Small steps (4 to 16 products per
+// set) then fill the wave instead of leaving most lanes idle, and the
+// per-op decode is shared by the sets.
+
+__device__ __forceinline__ int2 unpack16(uint32_t t) { return make_int2((int)(t & 0xffffu), (int)(t >> 16)); }
+
+// kSetContract (see device.hpp); 2^LGW lanes per set.
+template <typename V, int LGW>
+__device__ __forceinline__ void set_contract(V *m, const int4 &rec, uint32_t hdr, int w) {
+  const int lgG = (hdr >> 3) & 7, lgQ = (hdr >> 6) & 7, lgR = (hdr >> 9) & 7, lgOut = (hdr >> 12) & 15;
+  const int z = (int)(hdr >> 16);
+  const int R = 1 << lgR;
+  if (lgQ == 0) {
+    V acc = czero<V>();
+    for (int i = 0; i < R; i += 4) {
+      V xv[4], yv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i + u < R) {
+          const int2 t = unpack16((uint32_t)__builtin_amdgcn_readlane(rec.z, i + u));
+          xv[u] = m[rec.x + t.x];
+          yv[u] = m[rec.y + t.y];
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i + u < R) acc = cmul_add(acc, xv[u], yv[u]);
+    }
+    acc = group_sum(acc, lgG);
+    const int j = w >> lgG;
+    if ((w & ((1 << lgG) - 1)) == 0 && j < (1 << lgOut)) m[z + j] = acc;
+  } else {  // G = 1: outputs w + W q, four at a time
+    const int Q = 1 << lgQ;
+    for (int q0 = 0; q0 < Q; q0 += 4) {
+      int2 d[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        d[u] = (q0 + u == 0 || q0 + u >= Q) ? make_int2(0, 0)
+                                            : unpack16((uint32_t)__builtin_amdgcn_readlane(rec.w, q0 + u));
+      V acc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = czero<V>();
+      for (int i = 0; i < R; ++i) {
+        const int2 t = unpack16((uint32_t)__builtin_amdgcn_readlane(rec.z, i));
+        V xv[4], yv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (q0 + u < Q) {
+            xv[u] = m[rec.x + d[u].x + t.x];
+            yv[u] = m[rec.y + d[u].y + t.y];
+          }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (q0 + u < Q) acc[u] = cmul_add(acc[u], xv[u], yv[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (q0 + u < Q) m[z + w + ((q0 + u) << LGW)] = acc[u];
+    }
+  }
+}
+
+// kSetScalar: FP64 products and sums.
+template <typename V>
+__device__ __forceinline__ void set_scalar(const V *m, double2 *scal, const int4 &rec, uint32_t hdr, int w) {
+  const int lgG = (hdr >> 3) & 7, lgR = (hdr >> 9) & 7;
+  const int R = 1 << lgR;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int i = 0; i < R; ++i) {
+    const int2 t = unpack16((uint32_t)__builtin_amdgcn_readlane(rec.z, i));
+    const double2 x = to_d2(m[rec.x + t.x]);
+    const double2 y = to_d2(m[rec.y + t.y]);
+    acc.x += x.x * y.x - x.y * y.y;
+    acc.y += x.x * y.y + x.y * y.x;
+  }
+  acc = group_sum(acc, lgG);
+  if (w == 0) scal[hdr >> 16] = acc;
+}
+
+// kSetLeafGrad: Re(sum_e adjoint[e] * dU[index(e)]) in FP64, added to the
+// parameter's accumulator.
+template <typename V>
+__device__ __forceinline__ void set_leafgrad(const V *m, const V *dv, double *gacc, const int4 &rec, uint32_t hdr,
+                                             int w) {
+  const int lgG = (hdr >> 3) & 7, lgR = (hdr >> 9) & 7;
+  const int R = 1 << lgR;
+  const int slot = __builtin_amdgcn_readlane(rec.w, 1);
+  const double coeff = __hiloint2double(__builtin_amdgcn_readlane(rec.w, 3), __builtin_amdgcn_readlane(rec.w, 2));
+  dv += slot;
+  double acc = 0.0;
+  constexpr int U = 4;
+  for (int i = 0; i < R; i += U) {
+    V gv[U], dvv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i + u < R) {
+        const int t = __builtin_amdgcn_readlane(rec.z, i + u);
+        gv[u] = m[rec.x + ((i + u) << lgG)];
+        dvv[u] = dv[rec.y + t];
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i + u < R) {
+        const double2 g = to_d2(gv[u]), d = to_d2(dvv[u]);
+        acc += g.x * d.x - g.y * d.y;
+      }
+  }
+  acc = group_sum_f64(acc, lgG);
+  if (w == 0) gacc[hdr >> 16] += coeff * acc;
+}
+
+// n elements src -> dst by the W lanes of one set, four loads in flight.
+template <typename V, int W>
+__device__ __forceinline__ void set_copy(V *dst, const V *src, int n, int w) {
+  int e = w;
+  for (; e + 3 * W < n; e += 4 * W) {
+    const V a0 = src[e], a1 = src[e + W], a2 = src[e + 2 * W], a3 = src[e + 3 * W];
+    dst[e] = a0;
+    dst[e + W] = a1;
+    dst[e + 2 * W] = a2;
+    dst[e + 3 * W] = a3;
+  }
+  for (; e < n; e += W) dst[e] = src[e];
+}
+
+// Set-packed fused executor: a task is (network, group of 64 / 2^LGW angle
+// sets, 2^LGW lanes each); every op of every program has a set-packed
+// record. Sets past n_sets in the last group recompute the last set and
+// write nothing.
+template <typename T, bool GRAD, int LGW>
+__global__ __launch_bounds__(64) void fused_sets_kernel(FusedArgs a) {
+  using V = typename Cplx<T>::type;
+  constexpr int W = 1 << LGW, S = 64 >> LGW;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x, s = lane >> LGW, w = lane & (W - 1);
+  V *m = reinterpret_cast<V *>(smem) + (size_t)s * a.set_stride;
+  double2 *scal = reinterpret_cast<double2 *>(smem + a.scal_off) + s * a.max_comp;
+  double *gacc = reinterpret_cast<double *>(smem + a.gacc_off) + s * a.n_params;
+  const V *consts = reinterpret_cast<const V *>(a.consts);
+  const V *bound = reinterpret_cast<const V *>(a.bound);
+  const V *dbound = reinterpret_cast<const V *>(a.dbound);
+
+  const int t_end = min(a.n_tasks, ((int)blockIdx.x + 1) * a.per_block);
+  for (int task = blockIdx.x * a.per_block; task < t_end; ++task) {
+    const int ni = cptr(a.task_net)[task / a.n_groups];
+    const int set = (task % a.n_groups) * S + s;
+    const bool valid = set < a.n_sets;
+    const int setc = valid ? set : a.n_sets - 1;
+    const DNet net = cload(a.nets + ni);
+
+    set_copy<V, W>(m, consts + net.const_begin, net.n_const, w);
+    const V *bset = bound + (size_t)setc * a.per_set;
+    for (int t = 0; t < net.n_ptens; ++t) {
+      const DParam d = cload(a.ptens + net.ptens_begin + t);
+      set_copy<V, W>(m + d.off, bset + d.slot, 1 << d.bits, w);
+    }
+    if (GRAD)
+      for (int p = w; p < a.n_params; p += W) gacc[p] = 0.0;
+    __syncthreads();
+
+    const V *dv = dbound + (size_t)setc * a.per_set;
+    const int4 *recs = a.recs + (size_t)net.rec_begin * W + w;
+    int4 rec = make_int4(0, 0, 0, 0), rec1 = make_int4(0, 0, 0, 0);
+    if (net.n_ops > 0) rec = recs[0];
+    if (net.n_ops > 1) rec1 = recs[W];
+    for (int o = 0; o < net.n_ops; ++o) {
+      int4 nrec = make_int4(0, 0, 0, 0);
+      if (o + 2 < net.n_ops) nrec = recs[(size_t)(o + 2) * W];
+      const uint32_t hdr = (uint32_t)__builtin_amdgcn_readfirstlane(rec.w);
+      const uint32_t type = hdr & 7u;
+      if (type == kSetContract) {
+        set_contract<V, LGW>(m, rec, hdr, w);
+      } else if (type == kSetScalar) {
+        set_scalar<V>(m, scal, rec, hdr, w);
+      } else if (GRAD && type == kSetSeed) {
+        const int skip = __builtin_amdgcn_readlane(rec.x, 0);
+        if (w == 0) {
+          double2 p = make_double2(1.0, 0.0);
+          for (int j = 0; j < net.n_comp; ++j)
+            if (j != skip) p = cmul(p, scal[j]);
+          m[hdr >> 16] = from_d2<V>(p);
+        }
+      } else if (GRAD && type == kSetLeafGrad) {
+        set_leafgrad<V>(m, dv, gacc, rec, hdr, w);
+      }
+      __syncthreads();
+      rec = rec1;
+      rec1 = nrec;
+    }
+
+    if (valid && w == 0) {
+      double2 p = make_double2(1.0, 0.0);
+      for (int j = 0; j < net.n_comp; ++j) p = cmul(p, scal[j]);
+      double *ov = a.out_val + ((size_t)ni * a.n_sets + set) * 2;
+      ov[0] = p.x;
+      ov[1] = p.y;
+    }
+    if (GRAD && valid)
+      for (int p = w; p < a.n_params; p += W)
+        a.out_grad[((size_t)ni * a.n_sets + set) * a.n_params + p] = gacc[p];
+    __syncthreads();
+  }
+}
+
 // obj[s] = offset + sum_i coef[i] Re(val[i][s]); grad[s][p] = sum_i coef[i] gnet[i][s][p].
 // One workgroup per set, fixed-order FP64 tree.
 __global__ __launch_bounds__(256) void combine_kernel(const double *__restrict__ val, const double *__restrict__ gnet,
@@ -586,6 +833,23 @@ const void *fused_kernel_ptr(int dtype, int block, bool grad, bool rec_only) {
   if (dtype == TN_C128)
     return grad ? fused_ptr_t<double, true>(block, rec_only) : fused_ptr_t<double, false>(block, rec_only);
   return grad ? fused_ptr_t<float, true>(block, rec_only) : fused_ptr_t<float, false>(block, rec_only);
+}
+
+template <typename T, bool G>
+static const void *fused_sets_ptr_t(int sets) {
+  return sets == 2 ? (const void *)fused_sets_kernel<T, G, 5> : (const void *)fused_sets_kernel<T, G, 4>;
+}
+
+// sets: angle sets per wave (2 or 4)
+const void *fused_sets_kernel_ptr(int dtype, bool grad, int sets) {
+  if (dtype == TN_C128) return grad ? fused_sets_ptr_t<double, true>(sets) : fused_sets_ptr_t<double, false>(sets);
+  return grad ? fused_sets_ptr_t<float, true>(sets) : fused_sets_ptr_t<float, false>(sets);
+}
+
+hipError_t launch_fused_sets(int dtype, bool grad, int sets, const FusedArgs &a, int grid, int lds_bytes, hipStream_t st) {
+  const void *k = fused_sets_kernel_ptr(dtype, grad, sets);
+  void *args[] = {(void *)&a};
+  return hipLaunchKernel(k, dim3(grid), dim3(64), args, lds_bytes, st);
 }
 
 hipError_t launch_fused(int dtype, int block, bool grad, bool rec_only, const FusedArgs &a, int grid, int lds_bytes,

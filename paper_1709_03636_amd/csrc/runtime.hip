@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstdio>
+#include <array>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -17,6 +18,8 @@
 
 namespace qtn {
 
+hipError_t launch_fused_sets(int dtype, bool grad, int sets, const FusedArgs &a, int grid, int lds_bytes, hipStream_t st);
+const void *fused_sets_kernel_ptr(int dtype, bool grad, int sets);
 hipError_t launch_fused(int dtype, int block, bool grad, bool rec_only, const FusedArgs &a, int grid, int lds_bytes,
                         hipStream_t st);
 const void *fused_kernel_ptr(int dtype, int block, bool grad, bool rec_only);
@@ -168,6 +171,10 @@ struct HostProgram {
   std::map<std::string, int> program_of;  // fused program signature -> first network using it
   int n_programs = 0;
   bool generic[2] = {false, false};  // some op of a forward / adjoint program has no lane record
+  // set-packed records for 4 and 2 sets per wave (index 0, 1): 4 ints x
+  // W lanes per op; sets_ok: every op of every program has one
+  std::vector<int32_t> srecs[2];
+  bool sets_ok[2] = {true, true};
 };
 
 struct LevelNet {
@@ -383,6 +390,127 @@ static void build_records(const HostProgram &loc, const std::vector<DParam> &pt,
   }
 }
 
+// Set-packed records (see kSetContract), 2^lgW lanes per set, of the ops of
+// `loc`; false when some op has no set-packed form (its record is then
+// left empty).
+static bool build_set_records(const HostProgram &loc, const std::vector<DParam> &pt, int lgW,
+                              std::vector<int32_t> &recs) {
+  const int W = 1 << lgW, lgGmax = std::min(lgW, kLgMaxGroupLanes);
+  auto pack = [](int32_t a, int32_t b) { return (a & 0xffff) | (b << 16); };
+  bool all = true;
+  for (const DOp &op : loc.ops) {
+    std::vector<std::array<int32_t, 4>> f(W, std::array<int32_t, 4>{0, 0, 0, 0});
+    const uint32_t maskJ = (1u << op.nFY) - 1u;
+    auto offs = [&](uint32_t c, int32_t &ox, int32_t &oy) {
+      ox = op.x + (int32_t)host_pdep(c >> op.nFY, op.maskX);
+      oy = op.y + (int32_t)host_pdep(c & maskJ, op.maskY);
+    };
+    auto tab = [&](int k, int32_t &tx, int32_t &ty) {
+      tx = loc.tabs[op.tab + 2 * k];
+      ty = loc.tabs[op.tab + 2 * k + 1];
+    };
+    // entry k = g + G i must sit at t(g) + t(G i)
+    auto additive = [&](int nS, int lgG) {
+      const int lo = (1 << lgG) - 1;
+      for (int k = 0; k < (1 << nS); ++k) {
+        int32_t ax, ay, bx, by, cx, cy;
+        tab(k, ax, ay);
+        tab(k & lo, bx, by);
+        tab(k & ~lo, cx, cy);
+        if (ax != bx + cx || ay != by + cy) return false;
+      }
+      return true;
+    };
+    int type = 0, lgG = 0, lgQ = 0, lgR = 0, lgOut = 0, zf = 0;
+    if (op.type == OP_CONTRACT && op.nS <= 12) {
+      lgOut = op.nFX + op.nFY;
+      lgG = lgOut >= lgW ? 0 : std::min(std::min(lgW - lgOut, op.nS), lgGmax);
+      lgQ = std::max(0, lgOut - lgW);
+      lgR = op.nS - lgG;
+      // outputs w / G + (W / G) q must cover all outputs once
+      if (lgQ > 0 && lgG > 0) lgQ = 99;
+      if (lgOut < lgW && lgOut + lgG > lgW) lgQ = 99;
+      if (lgQ <= std::min(lgW, 7) && lgR <= std::min(lgW, 7) && additive(op.nS, lgG)) {
+        type = kSetContract;
+        zf = op.z;
+        for (int w = 0; w < W; ++w) {
+          const int j = w >> lgG, g = w & ((1 << lgG) - 1);
+          int32_t tx, ty;
+          if (j < (1 << lgOut)) {
+            offs((uint32_t)j, f[w][0], f[w][1]);
+            tab(g, tx, ty);
+            f[w][0] += tx;
+            f[w][1] += ty;
+          } else {
+            f[w][0] = op.x;
+            f[w][1] = op.y;
+          }
+          if (w < (1 << lgR)) {
+            tab(w << lgG, tx, ty);
+            f[w][2] = pack(tx, ty);
+          }
+          if (w >= 1 && w < (1 << lgQ)) {
+            offs((uint32_t)(w * W), tx, ty);
+            f[w][3] = pack(tx - op.x, ty - op.y);
+          }
+        }
+      }
+    } else if (op.type == OP_SCALAR && op.nS <= 12) {
+      lgG = std::min(lgGmax, op.nS);
+      lgR = op.nS - lgG;
+      if (lgR <= std::min(lgW, 7) && additive(op.nS, lgG)) {
+        type = kSetScalar;
+        zf = op.z;
+        for (int w = 0; w < W; ++w) {
+          int32_t tx = 0, ty = 0;
+          if (w < (1 << lgG)) tab(w, tx, ty);
+          f[w][0] = op.x + tx;
+          f[w][1] = op.y + ty;
+          if (w < (1 << lgR)) {
+            tab(w << lgG, tx, ty);
+            f[w][2] = pack(tx, ty);
+          }
+        }
+      }
+    } else if (op.type == OP_SEED) {
+      type = kSetSeed;
+      zf = op.z;
+      f[0][0] = op.aux0;
+    } else if (op.type == OP_LEAFGRAD && op.nFX <= 8) {
+      lgG = std::min(lgGmax, op.nFX);
+      lgR = op.nFX - lgG;
+      auto perm = [&](int e) { return loc.tabs[op.tab + e]; };
+      bool add = lgR <= std::min(lgW, 7);
+      for (int e = 0; add && e < (1 << op.nFX); ++e)
+        add = perm(e) == perm(e & ((1 << lgG) - 1)) + perm(e & ~((1 << lgG) - 1));
+      if (add) {
+        type = kSetLeafGrad;
+        const DParam &d = pt[op.aux0];
+        zf = d.param;
+        int64_t bits;
+        std::memcpy(&bits, &d.coeff, sizeof(bits));
+        for (int w = 0; w < W; ++w) {
+          const bool act = w < (1 << lgG);
+          f[w][0] = op.x + (act ? w : 0);
+          f[w][1] = act ? perm(w) : 0;
+          if (w < (1 << lgR)) f[w][2] = perm(w << lgG);
+        }
+        f[1][3] = d.slot;
+        f[2][3] = (int32_t)(bits & 0xffffffff);
+        f[3][3] = (int32_t)(bits >> 32);
+      }
+    }
+    if (zf >= (1 << 16)) type = 0;
+    if (type == 0) all = false;
+    f[0][3] = type ? (int32_t)((uint32_t)type | (lgG << 3) | (lgQ << 6) | (lgR << 9) | (lgOut << 12) |
+                               ((uint32_t)zf << 16))
+                   : 0;
+    for (int w = 0; w < W; ++w)
+      for (int c = 0; c < 4; ++c) recs.push_back(f[w][c]);
+  }
+  return all;
+}
+
 // Append the fused programs (forward, forward+adjoint) of one network.
 // Networks whose programs are identical (same ops, offset tables, constants
 // and parametric tensors: e.g. isomorphic light cones contracted in the same
@@ -433,6 +561,8 @@ static void append_fused(const Net &net, const NetLayout &lay, HostProgram &hp) 
   for (int variant = 0; variant < 2; ++variant)
     for (int o = op_begin[variant]; o < op_begin[variant] + n_ops[variant]; ++o)
       if (hp.recs[((size_t)(rec0 + o) * kRecLanes) * 4 + 3] == 0) hp.generic[variant] = true;
+  for (int i = 0; i < 2; ++i)
+    if (!build_set_records(loc, lptens, i == 0 ? 4 : 5, hp.srecs[i])) hp.sets_ok[i] = false;
   const int const_begin = (int)(hp.consts.size() / 2);
   for (DOp d : loc.ops) {
     d.tab += tab0;
@@ -534,6 +664,8 @@ struct GraphCache {
 
 struct tn_batch {
   int dtype = 0, n_nets = 0, n_params = 0, max_sets = 0, block = 128;
+  int spw[2] = {1, 1};                 // angle sets per wave of the fused executor (1, 2 or 4), forward / adjoint
+  int64_t fused_budget = 0;            // LDS bytes a fused workgroup may use
   double offset = 0;
   std::vector<double> coef;
   qtn::HostProgram hp;
@@ -542,7 +674,7 @@ struct tn_batch {
   // device
   qtn::DNet *d_nets_fwd = nullptr, *d_nets_grad = nullptr;
   qtn::DOp *d_ops = nullptr;
-  int4 *d_recs = nullptr;
+  int4 *d_recs = nullptr, *d_srecs[2] = {nullptr, nullptr};
   int32_t *d_tabs = nullptr, *d_task_net = nullptr;
   void *d_consts = nullptr;
   qtn::DParam *d_ptens = nullptr, *d_slots = nullptr;
@@ -552,7 +684,7 @@ struct tn_batch {
   double *d_lscal = nullptr;           // level executor component scalars
   double *d_lpart = nullptr;           // level executor partial sums
   int lds_fwd = 0, lds_grad = 0, grid_fwd = 0, grid_grad = 0;
-  int scratch_off[2], scal_off[2], gacc_off[2], red_off[2], gbar_off[2];
+  int scratch_off[2], scal_off[2], gacc_off[2], red_off[2], gbar_off[2], set_stride[2];
   double flops_fwd = 0, bytes_fwd = 0, flops_grad = 0, bytes_grad = 0;
   int64_t level_bytes = 0;
   std::map<std::string, int> use_mfma;  // autotuner: shape class of a large op -> 1 MFMA, 0 thin
@@ -576,7 +708,7 @@ static int hip_fail(hipError_t e, const char *what) {
 
 static void free_batch_dev(tn_batch *b) {
   b->gc.clear();
-  void *ptrs[] = {b->d_nets_fwd, b->d_nets_grad, b->d_ops, b->d_recs, b->d_tabs, b->d_task_net, b->d_consts, b->d_ptens,
+  void *ptrs[] = {b->d_nets_fwd, b->d_nets_grad, b->d_ops, b->d_recs, b->d_srecs[0], b->d_srecs[1], b->d_tabs, b->d_task_net, b->d_consts, b->d_ptens,
                   b->d_slots, b->d_bound, b->d_dbound, b->d_val, b->d_gnet, b->d_coef, b->d_larena, b->d_lscal,
                   b->d_lpart};
   for (void *p : ptrs)
@@ -588,10 +720,54 @@ static void free_batch_dev(tn_batch *b) {
 // the op loop).
 static bool rec_only(const tn_batch *b, int variant) { return b->block == kRecLanes && !b->hp.generic[variant]; }
 
+// LDS bytes of the set-packed layout with S sets per wave: per set its
+// memory, component scalars and gradient sums. The sets' regions start 64
+// bytes apart modulo the 256-byte bank cycle, so the same lane of different
+// sets reads different banks.
+static int set_lds_layout(const tn_batch *b, int S, int variant, int *stride, int *scal_off, int *gacc_off) {
+  const int eb = b->dtype == TN_C128 ? 16 : 8;
+  const int mem = variant == 0 ? b->hp.max_mem_fwd : b->hp.max_mem_grad;
+  auto al = [](int x) { return (x + 15) & ~15; };
+  const int unit = 256 / eb, shift = 64 / eb;
+  const int base = (mem + 1) & ~1;
+  *stride = base + ((shift - base % unit) % unit + unit) % unit;
+  int o = al(S * *stride * eb);
+  *scal_off = o;
+  o = al(o + S * std::max(1, b->hp.max_comp) * 16);
+  *gacc_off = o;
+  return al(o + S * std::max(1, b->n_params) * 8);
+}
+
+// Set-packed form with S sets per wave available for a program variant and
+// within the fused LDS budget.
+static bool sets_fit(const tn_batch *b, int S, int64_t budget, int variant) {
+  if (b->task_net.empty() || !b->hp.sets_ok[S == 4 ? 0 : 1]) return false;
+  int st, so, go;
+  return set_lds_layout(b, S, variant, &st, &so, &go) <= std::min<int64_t>(budget, 64 * 1024);
+}
+
 static int layout_lds(tn_batch *b, int variant) {
   const int eb = b->dtype == TN_C128 ? 16 : 8;
   const int mem = variant == 0 ? b->hp.max_mem_fwd : b->hp.max_mem_grad;
   auto al = [](int x) { return (x + 15) & ~15; };
+  int dev = 0, cus = 0, per_cu = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (b->spw[variant] > 1) {
+    const int o = set_lds_layout(b, b->spw[variant], variant, &b->set_stride[variant], &b->scal_off[variant], &b->gacc_off[variant]);
+    b->scratch_off[variant] = b->red_off[variant] = b->gbar_off[variant] = 0;
+    if (o > kLdsCap) {
+      set_error("fused executor: LDS layout of " + std::to_string(o) + " bytes exceeds 160 KiB");
+      return TN_ENOMEM;
+    }
+    (variant == 0 ? b->lds_fwd : b->lds_grad) = o;
+    const void *k = fused_sets_kernel_ptr(b->dtype, variant == 1, b->spw[variant]);
+    if (o > 64 * 1024) HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, o));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64, o));
+    (variant == 0 ? b->grid_fwd : b->grid_grad) = std::max(1, per_cu) * std::max(1, cus);
+    return TN_OK;
+  }
+  b->set_stride[variant] = 0;
   int o = al(mem * eb);
   b->scratch_off[variant] = o;
   o = al(o + b->block * eb);
@@ -607,13 +783,9 @@ static int layout_lds(tn_batch *b, int variant) {
     return TN_ENOMEM;
   }
   (variant == 0 ? b->lds_fwd : b->lds_grad) = o;
-  int per_cu = 0;
   const void *k = fused_kernel_ptr(b->dtype, b->block, variant == 1, rec_only(b, variant));
   if (o > 64 * 1024) HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, o));
   HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, b->block, o));
-  int dev = 0, cus = 0;
-  HIPCHK(hipGetDevice(&dev));
-  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   int grid = std::max(1, per_cu) * std::max(1, cus);
   (variant == 0 ? b->grid_fwd : b->grid_grad) = grid;
   return TN_OK;
@@ -679,6 +851,18 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
     if (v == 64 || v == 128 || v == 256) b->block = v;
   }
   int rc;
+  // several angle sets per wave when every op has a set-packed record and
+  // their memory stays within the fused budget. Measured default: four for
+  // forward programs (many small steps), one for adjoint programs (their
+  // larger LDS need leaves too few waves to hide latency). QTN_SETS_PER_WAVE
+  // (1, 2, 4) asks for a count for both; the autotuner compares them.
+  b->fused_budget = fused_max;
+  int want[2] = {4, 1};
+  if (const char *env = std::getenv("QTN_SETS_PER_WAVE")) want[0] = want[1] = std::atoi(env);
+  for (int v = 0; v < 2; ++v) {
+    if (want[v] == 4 && sets_fit(b.get(), 4, fused_max, v)) b->spw[v] = 4;
+    else if (want[v] >= 2 && sets_fit(b.get(), 2, fused_max, v)) b->spw[v] = 2;
+  }
   if ((rc = layout_lds(b.get(), 0)) != TN_OK) return rc;
   if ((rc = layout_lds(b.get(), 1)) != TN_OK) return rc;
 
@@ -694,6 +878,8 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   if ((e = dalloc(&b->d_ops, hp.ops.size())) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_tabs, hp.tabs.size())) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_recs, hp.recs.size() / 4)) != hipSuccess) return fail(e, "hipMalloc");
+  for (int i = 0; i < 2; ++i)
+    if ((e = dalloc(&b->d_srecs[i], hp.srecs[i].size() / 4)) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_task_net, b->task_net.size())) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc((char **)&b->d_consts, hp.consts.size() / 2 * eb)) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_ptens, hp.ptens.size())) != hipSuccess) return fail(e, "hipMalloc");
@@ -731,6 +917,8 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
       {b->d_ops, hp.ops.data(), hp.ops.size() * sizeof(DOp)},
       {b->d_tabs, hp.tabs.data(), hp.tabs.size() * sizeof(int32_t)},
       {b->d_recs, hp.recs.data(), hp.recs.size() * sizeof(int32_t)},
+      {b->d_srecs[0], hp.srecs[0].data(), hp.srecs[0].size() * sizeof(int32_t)},
+      {b->d_srecs[1], hp.srecs[1].data(), hp.srecs[1].size() * sizeof(int32_t)},
       {b->d_task_net, b->task_net.data(), b->task_net.size() * sizeof(int32_t)},
       {b->d_consts, csrc, hp.consts.size() / 2 * eb},
       {b->d_ptens, hp.ptens.data(), hp.ptens.size() * sizeof(DParam)},
@@ -790,13 +978,24 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     b->poisoned = true;
     return hip_fail(e, "binding launch");
   }
+  const int spw = b->spw[v];
+  if (spw > 1) {
+    a.recs = b->d_srecs[spw == 4 ? 0 : 1];
+    a.set_stride = b->set_stride[v];
+    a.max_comp = std::max(1, b->hp.max_comp);
+    a.n_groups = (n_sets + spw - 1) / spw;
+    a.n_tasks = (int)b->task_net.size() * a.n_groups;
+  }
   if (a.n_tasks > 0) {
     // resident workgroups, balanced so every one runs the same number of tasks
     const int cap = std::max(1, std::min(grad ? b->grid_grad : b->grid_fwd, a.n_tasks));
     const int rounds = (a.n_tasks + cap - 1) / cap;
     const int grid = (a.n_tasks + rounds - 1) / rounds;
     a.per_block = rounds;
-    e = launch_fused(b->dtype, b->block, grad, rec_only(b, v), a, grid, grad ? b->lds_grad : b->lds_fwd, st);
+    if (spw > 1)
+      e = launch_fused_sets(b->dtype, grad, spw, a, grid, grad ? b->lds_grad : b->lds_fwd, st);
+    else
+      e = launch_fused(b->dtype, b->block, grad, rec_only(b, v), a, grid, grad ? b->lds_grad : b->lds_fwd, st);
     if (e != hipSuccess) {
       b->poisoned = true;
       return hip_fail(e, "fused executor launch");
@@ -956,24 +1155,52 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
   std::map<std::string, int> found;
   int rc = TN_OK;
   b->gc.clear();
-  // (1) fused workgroup size
+  // (1) fused executor: adjoint programs by workgroup size or sets per wave,
+  // then forward programs by sets per wave
   if (!b->task_net.empty()) {
-    float best = 0.f;
-    int best_block = b->block;
-    for (int blk : {64, 128, 256}) {
-      b->block = blk;
-      if ((rc = layout_lds(b, 0)) != TN_OK || (rc = layout_lds(b, 1)) != TN_OK) return rc;
+    auto relayout = [&] { return (rc = layout_lds(b, 0)) == TN_OK && (rc = layout_lds(b, 1)) == TN_OK; };
+    float best = 0.f, best_single = 0.f;
+    int best_spw = b->spw[1], best_block = b->block, single_block = b->block;
+    for (int cand : {64, 128, 256, -2, -4}) {
+      if (cand < 0 && !sets_fit(b, -cand, b->fused_budget, 1)) continue;
+      b->spw[1] = cand < 0 ? -cand : 1;
+      if (cand > 0) b->block = cand;
+      if (!relayout()) return rc;
       float ms = time_ms(st, reps, [&] { return run_batch(b, true, params, n_sets, nullptr, nullptr, nullptr, nullptr, st); },
                          rc);
       if (rc != TN_OK) return rc;
       if (best == 0.f || ms < best) {
         best = ms;
-        best_block = blk;
+        best_spw = b->spw[1];
+        best_block = b->block;
+      }
+      if (cand > 0 && (best_single == 0.f || ms < best_single)) {
+        best_single = ms;
+        single_block = cand;
       }
     }
-    b->block = best_block;
-    if ((rc = layout_lds(b, 0)) != TN_OK || (rc = layout_lds(b, 1)) != TN_OK) return rc;
-    found[fused_key(b)] = best_block;
+    b->spw[1] = best_spw;
+    b->block = best_spw > 1 ? single_block : best_block;
+    best = 0.f;
+    int best_fwd = b->spw[0];
+    for (int S : {1, 2, 4}) {
+      if (S > 1 && !sets_fit(b, S, b->fused_budget, 0)) continue;
+      b->spw[0] = S;
+      if (!relayout()) return rc;
+      float ms = time_ms(st, reps, [&] { return run_batch(b, false, params, n_sets, nullptr, nullptr, nullptr, nullptr, st); },
+                         rc);
+      if (rc != TN_OK) return rc;
+      if (best == 0.f || ms < best) {
+        best = ms;
+        best_fwd = S;
+      }
+    }
+    b->spw[0] = best_fwd;
+    if (!relayout()) return rc;
+    const std::string suffix = fused_key(b).substr(12);
+    found[fused_key(b)] = b->block;
+    found["sets_per_wave:" + suffix] = b->spw[1];
+    found["sets_per_wave_fwd:" + suffix] = b->spw[0];
   }
   // (2) large level ops: MFMA vs thin per shape class
   std::map<std::string, const DOp *> classes;
@@ -1037,6 +1264,13 @@ int batch_apply_cache(tn_batch *b, const char *cache_path) {
   auto it = m.find(fused_key(b));
   if (it != m.end() && (it->second == 64 || it->second == 128 || it->second == 256) && !b->task_net.empty()) {
     b->block = it->second;
+    const std::string suffix = fused_key(b).substr(12);
+    for (int v = 0; v < 2; ++v) {
+      auto is = m.find((v == 0 ? "sets_per_wave_fwd:" : "sets_per_wave:") + suffix);
+      if (is != m.end() &&
+          (is->second == 1 || ((is->second == 2 || is->second == 4) && sets_fit(b, is->second, b->fused_budget, v))))
+        b->spw[v] = is->second;
+    }
     int rc;
     if ((rc = layout_lds(b, 0)) != TN_OK || (rc = layout_lds(b, 1)) != TN_OK) return rc;
   }
@@ -1056,6 +1290,8 @@ int batch_info(const tn_batch *b, tn_batch_stats *s) {
   s->n_levels = levels;
   s->n_programs = b->hp.n_programs;
   s->fused_block = b->block;
+  s->sets_per_wave_fwd = b->spw[0];
+  s->sets_per_wave_grad = b->spw[1];
   s->rec_only = (rec_only(b, 0) ? 1 : 0) | (rec_only(b, 1) ? 2 : 0);
   s->lds_bytes_fwd = b->lds_fwd;
   s->lds_bytes_grad = b->lds_grad;

@@ -266,35 +266,42 @@ def test_level_executor_matches_fused(monkeypatch):
 
 @pytest.mark.parametrize("p", [1, 2])
 def test_fused_workgroup_sizes_and_record_kernels(p, monkeypatch):
-    """Every fused workgroup size gives the oracle's cost and gradient. At 64
-    lanes the p=1 light cones run on the records-only kernel; the p=2 ones
-    (intermediates of 2^12 entries, too large for a lane record) also need
-    the descriptor path."""
+    """Every fused executor configuration gives the oracle's cost and
+    gradient: one angle set per workgroup at 64, 128 and 256 lanes, and four
+    angle sets per 64-lane wave. At 64 lanes the p=1 light cones run on the
+    records-only kernel; the p=2 ones (intermediates of 2^12 entries, too
+    large for a lane record) also need the descriptor path and have no
+    set-packed form. S = 7 leaves the last group of four sets partly empty."""
     qtn, qaoa = _qtn(), _qaoa()
     n = 14
     e = workloads.random_regular_graph(3, n, 8)
-    S = 3
+    S = 7
     ang = torch.tensor(workloads.qaoa_angles(11, S, p), device="cuda", dtype=torch.float64)
     ref = np.array([gradients.cost(n, e, list(a)) for a in ang.cpu().numpy()])
     ps = np.array([gradients.parameter_shift(n, e, list(a)) for a in ang.cpu().numpy()])
-    for blk in (64, 128, 256):
+    for blk, spw in ((64, 1), (128, 1), (256, 1), (64, 4)):
         monkeypatch.setenv("QTN_FUSED_BLOCK", str(blk))
+        monkeypatch.setenv("QTN_SETS_PER_WAVE", str(spw))
         model = qaoa.MaxCut(n, e, p, qtn.TN_C64, order="linegraph", max_sets=S)
         info = model.batch.info()
-        _say(f"fused block {blk} p={p} rec_only={info['rec_only']} n_fused={info['n_fused']}")
+        _say(f"fused block {blk} spw {spw} p={p} rec_only={info['rec_only']} "
+             f"sets={info['sets_per_wave_fwd']},{info['sets_per_wave_grad']} n_fused={info['n_fused']}")
         assert info["fused_block"] == blk and info["n_fused"] > 0
         assert info["n_fused"] + info["n_level"] == len(e)
+        assert info["sets_per_wave_fwd"] == info["sets_per_wave_grad"] == (spw if p == 1 else 1)
         if blk == 64 and p == 1:
             assert info["rec_only"] == 3
         elif blk == 64:
             assert info["rec_only"] & 2 == 0
         else:
             assert info["rec_only"] == 0
+        obj_f = model.expectation(ang)
         obj, grad = model.value_and_grad(ang)
         torch.cuda.synchronize()
-        obj, grad = obj.cpu().numpy(), grad.cpu().numpy()
-        assert np.max(np.abs(obj - ref)) <= 1e-5 * max(1, np.abs(ref).max()), blk
-        assert np.max(np.abs(grad - ps)) <= 1e-4 * max(1, np.abs(ps).max()), blk
+        obj_f, obj, grad = obj_f.cpu().numpy(), obj.cpu().numpy(), grad.cpu().numpy()
+        assert np.max(np.abs(obj_f - ref)) <= 1e-5 * max(1, np.abs(ref).max()), (blk, spw)
+        assert np.max(np.abs(obj - ref)) <= 1e-5 * max(1, np.abs(ref).max()), (blk, spw)
+        assert np.max(np.abs(grad - ps)) <= 1e-4 * max(1, np.abs(ps).max()), (blk, spw)
 
 
 # --- dense regime: whole-circuit networks, large steps on the matrix cores -----------------
