@@ -221,6 +221,16 @@ int tn_batch_set_precision(tn_batch *b, int32_t mfma_precision);
 /* Apply decisions from an autotuner cache file without timing. */
 int tn_batch_apply_tuning(tn_batch *b, const char *cache_path);
 
+/* Kernel timing (profiling aid, not in the paper). With enable = 1, every
+ * later eager tn_batch_contract / tn_batch_grad records a pair of HIP events
+ * on its stream around the fused-executor launch (at most 4096 pending
+ * pairs; graph captures record none). tn_batch_kernel_time waits for those
+ * events, returns how many launches were timed and their summed duration in
+ * milliseconds, and forgets them. enable = 0 stops recording and drops
+ * pending pairs. */
+int tn_batch_kernel_timing(tn_batch *b, int32_t enable);
+int tn_batch_kernel_time(tn_batch *b, int32_t *n_launches, double *total_ms);
+
 /* One-shot conveniences: create a transient batch, run, free. Device pointers. */
 int tn_contract_batch(tn_net *const *nets, int32_t n_nets, const double *params, int32_t n_sets,
                       double *out, void *stream);

@@ -691,6 +691,9 @@ struct tn_batch {
   int mfma_prec = TN_MFMA_FP32;          // matrix-core precision of large complex64 steps
   bool poisoned = false;
   qtn::GraphCache gc;
+  // kernel timing (tn_batch_kernel_timing): event pairs around fused launches
+  bool timing = false, capturing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
 };
 
 namespace qtn {
@@ -706,8 +709,17 @@ static int hip_fail(hipError_t e, const char *what) {
     if (_e != hipSuccess) return hip_fail(_e, #call);   \
   } while (0)
 
+static void drop_timing_events(tn_batch *b) {
+  for (auto &pr : b->tev) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  b->tev.clear();
+}
+
 static void free_batch_dev(tn_batch *b) {
   b->gc.clear();
+  drop_timing_events(b);
   void *ptrs[] = {b->d_nets_fwd, b->d_nets_grad, b->d_ops, b->d_recs, b->d_srecs[0], b->d_srecs[1], b->d_tabs, b->d_task_net, b->d_consts, b->d_ptens,
                   b->d_slots, b->d_bound, b->d_dbound, b->d_val, b->d_gnet, b->d_coef, b->d_larena, b->d_lscal,
                   b->d_lpart};
@@ -859,6 +871,7 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   b->fused_budget = fused_max;
   int want[2] = {4, 1};
   if (const char *env = std::getenv("QTN_SETS_PER_WAVE")) want[0] = want[1] = std::atoi(env);
+  if (max_sets == 1) want[0] = want[1] = 1;  // one angle set: nothing to pack
   for (int v = 0; v < 2; ++v) {
     if (want[v] == 4 && sets_fit(b.get(), 4, fused_max, v)) b->spw[v] = 4;
     else if (want[v] >= 2 && sets_fit(b.get(), 2, fused_max, v)) b->spw[v] = 2;
@@ -992,10 +1005,26 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     const int rounds = (a.n_tasks + cap - 1) / cap;
     const int grid = (a.n_tasks + rounds - 1) / rounds;
     a.per_block = rounds;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (b->timing && !b->capturing && b->tev.size() < 4096 && hipEventCreate(&t0) == hipSuccess) {
+      if (hipEventCreate(&t1) != hipSuccess || hipEventRecord(t0, st) != hipSuccess) {
+        (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
+        t0 = t1 = nullptr;
+      }
+    }
     if (spw > 1)
       e = launch_fused_sets(b->dtype, grad, spw, a, grid, grad ? b->lds_grad : b->lds_fwd, st);
     else
       e = launch_fused(b->dtype, b->block, grad, rec_only(b, v), a, grid, grad ? b->lds_grad : b->lds_fwd, st);
+    if (t0) {
+      if (e == hipSuccess && hipEventRecord(t1, st) == hipSuccess) {
+        b->tev.emplace_back(t0, t1);
+      } else {
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+      }
+    }
     if (e != hipSuccess) {
       b->poisoned = true;
       return hip_fail(e, "fused executor launch");
@@ -1062,7 +1091,9 @@ int batch_run_graph(tn_batch *b, int with_grad, const double *params, int n_sets
   if (!hit) {
     g.clear();
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    b->capturing = true;
     int rc = run_batch(b, with_grad != 0, params, n_sets, out, obj, grad, nullptr, st);
+    b->capturing = false;
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(st, &graph);
     if (rc != TN_OK) {
@@ -1094,24 +1125,31 @@ int batch_run_graph(tn_batch *b, int with_grad, const double *params, int n_sets
 // kernel on scratch operands of that shape and keep the faster. Decisions
 // live in the batch (and, with cache_path, in a text file of
 // "key value" lines that later batches read first).
+// Shortest of `reps` runs of fn (after one warm-up run), each between its
+// own pair of events: robust to the occasional delayed launch.
 static float time_ms(hipStream_t st, int reps, const std::function<int()> &fn, int &rc) {
-  hipEvent_t e0, e1;
+  reps = std::max(1, reps);
+  std::vector<hipEvent_t> ev(2 * reps, nullptr);
   rc = TN_OK;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-    rc = TN_EDEVICE;
-    return 0.f;
+  for (auto &e : ev)
+    if (hipEventCreate(&e) != hipSuccess) rc = TN_EDEVICE;
+  float best = 0.f;
+  if (rc == TN_OK && (rc = fn()) == TN_OK) {  // warm-up
+    for (int i = 0; i < reps && rc == TN_OK; ++i) {
+      (void)hipEventRecord(ev[2 * i], st);
+      rc = fn();
+      (void)hipEventRecord(ev[2 * i + 1], st);
+    }
+    if (rc == TN_OK && hipEventSynchronize(ev[2 * reps - 1]) == hipSuccess) {
+      for (int i = 0; i < reps; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess && (i == 0 || ms < best)) best = ms;
+      }
+    }
   }
-  if ((rc = fn()) == TN_OK) {  // warm-up
-    (void)hipEventRecord(e0, st);
-    for (int i = 0; i < reps && rc == TN_OK; ++i) rc = fn();
-    (void)hipEventRecord(e1, st);
-    (void)hipEventSynchronize(e1);
-  }
-  float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  return ms / std::max(1, reps);
+  for (auto &e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return best;
 }
 
 static std::map<std::string, int> read_cache(const char *path) {
@@ -1162,7 +1200,7 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
     float best = 0.f, best_single = 0.f;
     int best_spw = b->spw[1], best_block = b->block, single_block = b->block;
     for (int cand : {64, 128, 256, -2, -4}) {
-      if (cand < 0 && !sets_fit(b, -cand, b->fused_budget, 1)) continue;
+      if (cand < 0 && (b->max_sets == 1 || !sets_fit(b, -cand, b->fused_budget, 1))) continue;
       b->spw[1] = cand < 0 ? -cand : 1;
       if (cand > 0) b->block = cand;
       if (!relayout()) return rc;
@@ -1184,7 +1222,7 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
     best = 0.f;
     int best_fwd = b->spw[0];
     for (int S : {1, 2, 4}) {
-      if (S > 1 && !sets_fit(b, S, b->fused_budget, 0)) continue;
+      if (S > 1 && (b->max_sets == 1 || !sets_fit(b, S, b->fused_budget, 0))) continue;
       b->spw[0] = S;
       if (!relayout()) return rc;
       float ms = time_ms(st, reps, [&] { return run_batch(b, false, params, n_sets, nullptr, nullptr, nullptr, nullptr, st); },
@@ -1245,6 +1283,32 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
     found["mfma:" + kv.first] = b->use_mfma[kv.first];
   }
   write_cache(cache_path, found);
+  return TN_OK;
+}
+
+int batch_kernel_timing(tn_batch *b, int enable) {
+  b->timing = enable != 0;
+  if (!b->timing) drop_timing_events(b);
+  return TN_OK;
+}
+
+int batch_kernel_time(tn_batch *b, int *n, double *total_ms) {
+  double sum = 0.0;
+  int cnt = 0;
+  hipError_t e = hipSuccess;
+  for (auto &pr : b->tev) {
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventSynchronize(pr.second);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+    if (e == hipSuccess) {
+      sum += ms;
+      ++cnt;
+    }
+  }
+  drop_timing_events(b);
+  if (e != hipSuccess) return hip_fail(e, "tn_batch_kernel_time");
+  *n = cnt;
+  *total_ms = sum;
   return TN_OK;
 }
 

@@ -79,6 +79,8 @@ _SIGS = {
     "tn_batch_autotune": (_I, [_P, _P, _I, _I, ctypes.c_char_p, _P]),
     "tn_batch_apply_tuning": (_I, [_P, ctypes.c_char_p]),
     "tn_batch_set_precision": (_I, [_P, _I]),
+    "tn_batch_kernel_timing": (_I, [_P, _I]),
+    "tn_batch_kernel_time": (_I, [_P, _PI, _PD]),
     "tn_contract_batch": (_I, [ctypes.POINTER(_P), _I, _P, _I, _P, _P]),
     "tn_grad_batch": (_I, [ctypes.POINTER(_P), _I, _P, _I, _P, _P, _P]),
     "tn_bind_params": (_I, [_P, _P, _I, _P, ctypes.POINTER(ctypes.c_int64), _P]),
@@ -263,6 +265,16 @@ class Batch:
     def set_precision(self, mfma_precision):
         """TN_MFMA_FP32 or TN_MFMA_BF16X3 for the large complex64 steps."""
         _check(lib().tn_batch_set_precision(self.h, mfma_precision))
+
+    def kernel_timing(self, enable=True):
+        """Record HIP events around later eager fused launches (tn_batch_kernel_timing)."""
+        _check(lib().tn_batch_kernel_timing(self.h, 1 if enable else 0))
+
+    def kernel_time(self):
+        """(launches timed, summed milliseconds) since the last call (tn_batch_kernel_time)."""
+        n, ms = ctypes.c_int32(), ctypes.c_double()
+        _check(lib().tn_batch_kernel_time(self.h, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
 
     def apply_tuning(self, cache_path):
         _check(lib().tn_batch_apply_tuning(self.h, cache_path.encode()))

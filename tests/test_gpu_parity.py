@@ -214,6 +214,37 @@ def test_batch_forward_matches_grad_pass_and_graph_replay():
         _ = (ang * 2).sum().item()  # eager work between replays
 
 
+def test_kernel_timing_hook():
+    """tn_batch_kernel_timing records one event pair per eager fused launch
+    and none inside graph captures; the results are unchanged."""
+    qtn, qaoa = _qtn(), _qaoa()
+    n = 12
+    e = workloads.random_regular_graph(3, n, 3)
+    S = 4
+    ang = torch.tensor(workloads.qaoa_angles(3, S, 1), device="cuda", dtype=torch.float64)
+    model = qaoa.MaxCut(n, e, 1, qtn.TN_C64, max_sets=S)
+    obj0, grad0 = model.value_and_grad(ang)
+    st = torch.cuda.Stream()
+    model.batch.kernel_timing(True)
+    for _ in range(3):
+        model.batch.grad(ang, stream=st)
+    model.batch.contract(ang, stream=st)
+    obj = torch.empty(S, dtype=torch.float64, device="cuda")
+    st.wait_stream(torch.cuda.current_stream())
+    model.batch.run_graph(False, ang, obj=obj, stream=st)
+    st.synchronize()
+    n_timed, ms = model.batch.kernel_time()
+    assert n_timed == 4 and 0.0 < ms < 1e3
+    assert model.batch.kernel_time() == (0, 0.0)
+    model.batch.kernel_timing(False)
+    obj1, grad1 = model.value_and_grad(ang)
+    torch.cuda.synchronize()
+    assert np.array_equal(obj0.cpu().numpy(), obj1.cpu().numpy())
+    assert np.array_equal(grad0.cpu().numpy(), grad1.cpu().numpy())
+    # forward-only graph vs the adjoint pass's value: different kernels, c64 tolerance
+    assert np.max(np.abs(obj.cpu().numpy() - obj0.cpu().numpy())) <= 1e-5 * max(1.0, float(obj0.abs().max()))
+
+
 def test_bind_params_kernel():
     """Angle binding on its own: RX and ZZ superoperators vs their definitions."""
     qtn, qaoa = _qtn(), _qaoa()
