@@ -111,6 +111,97 @@ def copy_calibration(steps):
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": steps}))
 
 
+def max_cut_brute_force(n, edges):
+    """Exact Max-Cut by enumerating every cut with vertex n-1 on side 0."""
+    x = np.arange(1 << (n - 1), dtype=np.int64)
+    cut = np.zeros(x.shape, dtype=np.int64)
+    for u, v in edges:
+        cut += ((x >> u) ^ (x >> v)) & 1
+    return int(cut.max())
+
+
+def next_rows(model, params, edges, st, dev):
+    """Rows past the hot path: angle optimisation on the adjoint gradient,
+    answer-string estimation, and the batched pass with noise channels."""
+    import torch
+    import workloads
+    from paper_1709_03636_amd import answer, noise, optimize, qaoa, qtn
+    res = {}
+    # angle optimisation: Adam on the batched fwd+grad pass, all 64 starts at once
+    steps = 100
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xb, fb, trace = optimize.adam_maximize(lambda x: model.value_and_grad(x), params, steps=steps, lr=0.05)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k = int(fb.argmax())
+    best = xb[k].cpu().numpy()
+    res["angle_optimisation"] = {
+        "workload": f"Adam ascent of <C>, QAOA p={P_LAYERS} on the headline graph, {params.shape[0]} starts at once",
+        "steps": steps, "ms_per_iteration": dt / (steps + 1) * 1e3, "start_best_cost": float(trace[0]),
+        "final_best_cost": float(fb[k]), "edges": len(edges), "best_angles": best.tolist()}
+    log(f"optimisation: {res['angle_optimisation']}")
+
+    # answer strings: the paper's 30-vertex 3-regular setting (timed) and n=20 graphs against brute force
+    def plus(n):
+        return np.array([complex(qaoa.PLUS[0], qaoa.PLUS[1]), complex(qaoa.PLUS[2], qaoa.PLUS[3])] * n)
+
+    def opt_angles(n, e):
+        m = qaoa.MaxCut(n, e, 1, qtn.TN_C64, order="linegraph", max_sets=16, trials=4)
+        x0 = torch.tensor(workloads.qaoa_angles(11, 16, 1), dtype=torch.float64, device=dev)
+        xb, fb, _ = optimize.adam_maximize(m.value_and_grad, x0, steps=150, lr=0.05)
+        j = int(fb.argmax())
+        return xb[j].cpu().numpy(), float(fb[j])
+
+    n30 = 30
+    e30 = workloads.random_regular_graph(3, n30, GRAPH_SEED)
+    ang30, c30 = opt_angles(n30, e30)
+    t0 = time.perf_counter()
+    bits, _ = answer.answer_string(n30, qaoa.qaoa_gates(n30, e30, 1), init=plus(n30), n_params=2, params=ang30,
+                                   dtype=qtn.TN_C64, tie_tol=1e-4)
+    dt30 = time.perf_counter() - t0
+    ratios = []
+    for seed in range(5):
+        e20 = workloads.random_regular_graph(3, 20, seed)
+        a20, _ = opt_angles(20, e20)
+        b20, _ = answer.answer_string(20, qaoa.qaoa_gates(20, e20, 1), init=plus(20), n_params=2, params=a20,
+                                      dtype=qtn.TN_C64, tie_tol=1e-4)
+        ratios.append(answer.cut_value(e20, b20) / max_cut_brute_force(20, e20))
+    res["answer_string"] = {
+        "workload": "qubit-by-qubit projection (one PROBABILITY contraction per qubit, plain path), QAOA p=1 at "
+                    "optimised angles, complex64",
+        "n30": {"edges": len(e30), "contractions": n30, "seconds": dt30, "cut": answer.cut_value(e30, bits),
+                "expected_cut_at_angles": c30},
+        "n20_approx_ratio_vs_brute_force": {"graphs": 5, "mean": float(np.mean(ratios)), "min": float(min(ratios))}}
+    log(f"answer string: {res['answer_string']}")
+
+    # noise: depolarizing channel after every gate, same batch shape, fwd+grad
+    nm = qaoa.MaxCut(N_VERT, edges, P_LAYERS, qtn.TN_C64, order="linegraph", max_sets=N_SETS, trials=4,
+                     noise=noise.depolarizing(0.01))
+    nm.batch.autotune(params, reps=10, stream=st)
+    for _ in range(5):
+        nm.batch.grad(params, stream=st)
+    nm.batch.kernel_timing(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    ev0.record(st)
+    for _ in range(reps):
+        nm.batch.grad(params, stream=st)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    n_t, k_ms = nm.batch.kernel_time()
+    nm.batch.kernel_timing(False)
+    ms = ev0.elapsed_time(ev1) / reps
+    ninfo = nm.batch.info()
+    res["noise"] = {
+        "workload": "headline batch with a depolarizing channel (p = 0.01) after every gate on each of its qubits "
+                    "(folded superoperator tensors, light cone kept: trace preserving)",
+        "fwd_grad_networks_per_s": len(edges) * N_SETS / (ms * 1e-3), "ms_per_pass": ms,
+        "fused_kernel_us": k_ms / max(1, n_t) * 1e3, "n_programs": ninfo["n_programs"]}
+    log(f"noise: {res['noise']}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +210,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-next", action="store_true", help="skip the optimisation / answer-string / noise lines")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note "
@@ -281,6 +373,8 @@ def main():
                                "abs_err_zz_vs_closed_form": abs(dout2[0, 0, 0].item() - zz_ref)}}
         log(f"dense/MFMA: {mfma}")
 
+    nxt = None if args.no_next else next_rows(model, params, edges, st, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle) ...")
@@ -313,6 +407,7 @@ def main():
                      "kernel": kname, "kernel_us": k_ms * 1e3, "kernel_launches_timed": n_timed,
                      "algorithmic_bytes_per_launch": alg_bytes, "algorithmic_flops_per_launch": alg_flops},
         "mfma_path": mfma,
+        "next_rows": nxt,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -52,7 +52,18 @@ enum {
   TN_CNOT = 8, /* control q0, target q1 */
   TN_CZ = 9,
   TN_U1 = 10,  /* custom 2x2 matrix (row-major, interleaved re/im) */
-  TN_U2 = 11   /* custom 4x4 matrix (row-major, interleaved re/im) */
+  TN_U2 = 11,  /* custom 4x4 matrix (row-major, interleaved re/im) */
+  /* Quantum channel rho -> sum_k E_k rho E_k^dagger (e.g. noise, Sec. on
+   * noise: Kraus operators as superoperators), given as its folded
+   * superoperator S: entry [(2a+b)*4 + (2c+d)] maps rho_cd to rho'_ab, i.e.
+   * sum_k E_k[a][c] conj(E_k[b][d]) (16 entries, 32 doubles); for two qubits
+   * entry [((2a0+b0)*4 + (2a1+b1))*16 + (2c0+d0)*4 + (2c1+d1)] with qubit q0
+   * first (256 entries, 512 doubles). Folded modes only (PROBABILITY,
+   * EXPECTATION). A channel that is not trace preserving turns the light
+   * cone off for the network (it does not reduce to the identity outside
+   * the cone). */
+  TN_SUPER1 = 12,
+  TN_SUPER2 = 13
 };
 
 typedef struct {
@@ -60,7 +71,7 @@ typedef struct {
   int32_t q0, q1;        /* q1 = -1 for one-qubit gates */
   int32_t param;         /* index into params[], or -1 for a fixed angle */
   double coeff;          /* theta = coeff * params[param] (or coeff when param == -1) */
-  const double *matrix;  /* TN_U1 / TN_U2 only: 8 or 32 doubles; copied */
+  const double *matrix;  /* TN_U1 / TN_U2: 8 or 32 doubles; TN_SUPER1 / TN_SUPER2: 32 or 512 doubles; copied */
 } tn_gate;
 
 /* What the network computes (Sec. Preliminaries and Sec. "Estimating the

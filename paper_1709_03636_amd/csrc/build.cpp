@@ -61,7 +61,8 @@ const Mat &pauli_of_kind(int kind, int &dim) {
   }
 }
 
-bool gate_is_2q(int kind) { return kind == TN_ZZ || kind == TN_CNOT || kind == TN_CZ || kind == TN_U2; }
+bool gate_is_2q(int kind) { return kind == TN_ZZ || kind == TN_CNOT || kind == TN_CZ || kind == TN_U2 || kind == TN_SUPER2; }
+bool gate_is_super(int kind) { return kind == TN_SUPER1 || kind == TN_SUPER2; }
 bool gate_is_param(int kind) { return kind == TN_RX || kind == TN_RY || kind == TN_RZ || kind == TN_ZZ; }
 
 // Fixed matrix of a gate (parametric kinds evaluated at theta).
@@ -75,8 +76,10 @@ Mat gate_matrix(const tn_gate &g, double theta) {
     case TN_CNOT: return {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 0, 1, 0, 0, 1, 0};
     case TN_CZ: return {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, -1};
     case TN_U1:
-    case TN_U2: {
-      int dim = g.kind == TN_U1 ? 2 : 4;
+    case TN_U2:
+    case TN_SUPER1:
+    case TN_SUPER2: {
+      int dim = g.kind == TN_U1 ? 2 : (g.kind == TN_U2 ? 4 : (g.kind == TN_SUPER1 ? 4 : 16));
       Mat m((size_t)dim * dim);
       for (int i = 0; i < dim * dim; ++i) m[i] = cd(g.matrix[2 * i], g.matrix[2 * i + 1]);
       return m;
@@ -113,6 +116,24 @@ bool is_unitary(const Mat &m, int dim) {
       for (int k = 0; k < dim; ++k) s += m[i * dim + k] * std::conj(m[j * dim + k]);
       if (std::abs(s - (i == j ? 1.0 : 0.0)) > 1e-10) return false;
     }
+  return true;
+}
+
+// A folded superoperator preserves the trace: summing its output over the
+// diagonal (a = b on every qubit) leaves the trace functional of the input.
+bool is_trace_preserving(const Mat &S, int qubits) {
+  const int nin = qubits == 1 ? 4 : 16;
+  for (int in = 0; in < nin; ++in) {
+    cd s = 0;
+    if (qubits == 1) {
+      for (int a = 0; a < 2; ++a) s += S[(3 * a) * 4 + in];
+    } else {
+      for (int a0 = 0; a0 < 2; ++a0)
+        for (int a1 = 0; a1 < 2; ++a1) s += S[((3 * a0) * 4 + 3 * a1) * 16 + in];
+    }
+    const bool diag = qubits == 1 ? (in == 0 || in == 3) : ((in >> 2) == 0 || (in >> 2) == 3) && ((in & 3) == 0 || (in & 3) == 3);
+    if (std::abs(s - (diag ? 1.0 : 0.0)) > 1e-10) return false;
+  }
   return true;
 }
 
@@ -211,7 +232,7 @@ int build_network(const tn_gate *gates, int n_gates, int n_qubits, const double 
   bool all_unitary = true;
   for (int i = 0; i < n_gates; ++i) {
     const tn_gate &g = gates[i];
-    if (g.kind < TN_H || g.kind > TN_U2) { set_error("tn_build: bad gate kind at gate " + std::to_string(i)); return TN_EINVAL; }
+    if (g.kind < TN_H || g.kind > TN_SUPER2) { set_error("tn_build: bad gate kind at gate " + std::to_string(i)); return TN_EINVAL; }
     bool two = gate_is_2q(g.kind);
     if (g.q0 < 0 || g.q0 >= n_qubits || (two && (g.q1 < 0 || g.q1 >= n_qubits || g.q1 == g.q0)) || (!two && g.q1 != -1)) {
       set_error("tn_build: bad qubits at gate " + std::to_string(i));
@@ -221,11 +242,17 @@ int build_network(const tn_gate *gates, int n_gates, int n_qubits, const double 
       set_error("tn_build: bad param index at gate " + std::to_string(i));
       return TN_EINVAL;
     }
-    if ((g.kind == TN_U1 || g.kind == TN_U2) && !g.matrix) {
+    if ((g.kind == TN_U1 || g.kind == TN_U2 || gate_is_super(g.kind)) && !g.matrix) {
       set_error("tn_build: custom gate without matrix at gate " + std::to_string(i));
       return TN_EINVAL;
     }
+    if (gate_is_super(g.kind) && mode == TN_AMPLITUDE) {
+      set_error("tn_build: a channel (superoperator) needs a folded mode, at gate " + std::to_string(i));
+      return TN_EINVAL;
+    }
     if ((g.kind == TN_U1 || g.kind == TN_U2) && !is_unitary(gate_matrix(g, 0.0), g.kind == TN_U1 ? 2 : 4))
+      all_unitary = false;
+    if (gate_is_super(g.kind) && !is_trace_preserving(gate_matrix(g, 0.0), g.kind == TN_SUPER1 ? 1 : 2))
       all_unitary = false;
   }
 
@@ -238,8 +265,9 @@ int build_network(const tn_gate *gates, int n_gates, int n_qubits, const double 
   net.wire_bits = folded ? 2 : 1;
 
   // Backward light cone of the measured qubits: a gate none of whose qubits
-  // is in the current support meets only trace vectors and, being unitary,
-  // contracts to trace vectors; it is dropped. Kept gates add their qubits.
+  // is in the current support meets only trace vectors and, being unitary
+  // (or a trace-preserving channel), contracts to trace vectors; it is
+  // dropped. Kept gates add their qubits.
   // Consecutive diagonal gates commute, so a run of them is treated as one
   // layer: its gates are tested against the support at the run's late end.
   std::vector<char> keep(n_gates, 1), in_net(n_qubits, 1);
@@ -288,7 +316,7 @@ int build_network(const tn_gate *gates, int n_gates, int n_qubits, const double 
     } else {
       Mat U = gate_matrix(g, g.coeff);
       bool two = gate_is_2q(g.kind);
-      src = B.add_const(folded ? (two ? superop_2q(U) : superop_1q(U)) : U);
+      src = B.add_const(gate_is_super(g.kind) ? U : (folded ? (two ? superop_2q(U) : superop_1q(U)) : U));
     }
     if (g.q1 < 0) {
       int w = B.new_wire();

@@ -12,26 +12,85 @@ import math
 
 import numpy as np
 
+from . import noise as noise_mod
 from . import qtn
 
 PLUS = [1 / math.sqrt(2), 0.0, 1 / math.sqrt(2), 0.0]
 
 
-def qaoa_gates(n, edges, p):
+def _zz_layer(edges, k, chan):
+    out = []
+    for u, v in edges:
+        out.append(("ZZ", u, v, k, 2.0))
+        if chan is not None:
+            out += [chan(u), chan(v)]
+    return out
+
+
+def _rx_layer(qubits, p, k, chan):
+    out = []
+    for q in qubits:
+        out.append(("RX", q, -1, p + k, 2.0))
+        if chan is not None:
+            out.append(chan(q))
+    return out
+
+
+def _channel(noise):
+    """noise: None or the Kraus operators of a one-qubit channel applied
+    after every gate, on each qubit the gate acts on."""
+    if noise is None:
+        return None
+    S = noise_mod.superop(noise)
+    return lambda q: ("SUPER1", q, -1, -1, 0.0, S)
+
+
+def qaoa_gates(n, edges, p, noise=None):
     """Gate tuples of the QAOA circuit without the Hadamard layer."""
+    chan = _channel(noise)
     gates = []
     for k in range(p):
-        gates += [("ZZ", u, v, k, 2.0) for (u, v) in edges]
-        gates += [("RX", q, -1, p + k, 2.0) for q in range(n)]
+        gates += _zz_layer(edges, k, chan)
+        gates += _rx_layer(range(n), p, k, chan)
     return gates
 
 
-def edge_lightcone_circuit(n, edges, p, edge):
+def _lightcone_in_sequence(n, edges, p, edge, noise):
+    """With channels between the ZZ gates the ZZ layer no longer commutes as
+    a block: walk the gate sequence backwards, keeping a gate when it touches
+    the support (which then takes its qubits). Kept qubits are relabelled
+    u -> 0, v -> 1, then in order of their last appearance."""
+    full = qaoa_gates(n, edges, p, noise)
+    sup = {edge[0], edge[1]}
+    kept = []
+    for g in reversed(full):
+        qs = [g[1]] + ([g[2]] if g[2] >= 0 else [])
+        if any(q in sup for q in qs):
+            kept.append(g)
+            sup.update(qs)
+    kept.reverse()
+    lab = {edge[0]: 0, edge[1]: 1}
+    for g in reversed(kept):
+        for q in (g[1], g[2]):
+            if q >= 0 and q not in lab:
+                lab[q] = len(lab)
+    gates = []
+    for g in kept:
+        q0, q1 = lab[g[1]], (lab[g[2]] if g[2] >= 0 else -1)
+        gates.append((g[0], q0, q1) + tuple(g[3:]))
+    return len(lab), gates
+
+
+def edge_lightcone_circuit(n, edges, p, edge, noise=None):
     """The gates that can reach <Z_u Z_v>, on the light-cone qubits only,
     relabelled canonically: u -> 0, v -> 1, then breadth-first over the kept
     ZZ gates with ties broken by already-assigned neighbour labels. Isomorphic
     light cones thus give identical circuits (hence identical contraction
-    programs, which the batch stores once). Returns (m qubits, gates)."""
+    programs, which the batch stores once). Returns (m qubits, gates).
+    With noise the cone follows the gate sequence instead (see
+    _lightcone_in_sequence)."""
+    if noise is not None:
+        return _lightcone_in_sequence(n, edges, p, edge, noise)
     adj = {}
     for a, b in edges:
         adj.setdefault(a, set()).add(b)
@@ -60,20 +119,21 @@ def edge_lightcone_circuit(n, edges, p, edge):
     gates = []
     for k, zz in enumerate(layers):
         ren = sorted(tuple(sorted((lab[a], lab[b]))) for a, b in zz)
-        gates += [("ZZ", a, b, k, 2.0) for a, b in ren]
-        gates += [("RX", q, -1, p + k, 2.0) for q in range(m)]
+        gates += _zz_layer(ren, k, None)
+        gates += _rx_layer(range(m), p, k, None)
     return m, gates
 
 
-def edge_network(n, edges, p, edge, dtype=qtn.TN_C64, lightcone=True):
+def edge_network(n, edges, p, edge, dtype=qtn.TN_C64, lightcone=True, noise=None):
     """Folded network of <Z_u Z_v>. With lightcone=True it is built on the
     edge's canonically relabelled light-cone circuit; with lightcone=False it
-    is the whole circuit (trace on every other qubit)."""
+    is the whole circuit (trace on every other qubit). noise: Kraus operators
+    of a trace-preserving one-qubit channel after every gate (or None)."""
     if lightcone:
-        m, gates = edge_lightcone_circuit(n, edges, p, edge)
+        m, gates = edge_lightcone_circuit(n, edges, p, edge, noise)
         pauli = [3, 3] + [0] * (m - 2)
     else:
-        m, gates = n, qaoa_gates(n, edges, p)
+        m, gates = n, qaoa_gates(n, edges, p, noise)
         pauli = [0] * n
         pauli[edge[0]] = pauli[edge[1]] = 3
     init = np.array([complex(PLUS[0], PLUS[1]), complex(PLUS[2], PLUS[3])] * m)
@@ -81,11 +141,11 @@ def edge_network(n, edges, p, edge, dtype=qtn.TN_C64, lightcone=True):
                        lightcone=lightcone)
 
 
-def edge_networks(n, edges, p, dtype=qtn.TN_C64, order="stochastic", seed=0, trials=8, lightcone=True):
+def edge_networks(n, edges, p, dtype=qtn.TN_C64, order="stochastic", seed=0, trials=8, lightcone=True, noise=None):
     """One network per edge with its contraction order set."""
     nets = []
     for e in edges:
-        net = edge_network(n, edges, p, e, dtype, lightcone)
+        net = edge_network(n, edges, p, e, dtype, lightcone, noise)
         if order == "stochastic":
             pi = net.order_stochastic(seed)
         elif order == "linegraph":
@@ -100,9 +160,9 @@ def edge_networks(n, edges, p, dtype=qtn.TN_C64, order="stochastic", seed=0, tri
 class MaxCut:
     """<C>(params) and its gradient for many parameter vectors at once."""
 
-    def __init__(self, n, edges, p, dtype=qtn.TN_C64, order="stochastic", seed=0, max_sets=64, trials=8):
+    def __init__(self, n, edges, p, dtype=qtn.TN_C64, order="stochastic", seed=0, max_sets=64, trials=8, noise=None):
         self.n, self.edges, self.p = n, list(edges), p
-        self.nets = edge_networks(n, edges, p, dtype, order, seed, trials)
+        self.nets = edge_networks(n, edges, p, dtype, order, seed, trials, noise=noise)
         m = len(self.edges)
         self.batch = qtn.Batch(self.nets, coef=[-0.5] * m, offset=0.5 * m, max_sets=max_sets)
 

@@ -1,0 +1,259 @@
+"""GPU checks of the rows built past the hot path: the angle-optimisation
+loop on the adjoint gradient, answer-string estimation and noise channels,
+each against the FP64 oracle (complex64 tolerances as in test_gpu_parity)."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import gradients
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CUBE = [(0, 1), (0, 2), (0, 4), (1, 3), (1, 5), (2, 3), (2, 6), (3, 7), (4, 5), (4, 6), (5, 7), (6, 7)]
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1709_03636_amd import qtn
+    qtn.lib()
+
+
+def _mods():
+    from paper_1709_03636_amd import optimize, qaoa, qtn
+    return optimize, qaoa, qtn
+
+
+# --- angle optimisation (Adam on tn_batch_grad) ------------------------------------------
+
+def test_angle_optimisation_reaches_p1_optimum_on_the_3cube():
+    optimize, qaoa, qtn = _mods()
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "qaoa_p1_known_values.json")))
+    best = len(CUBE) * gold["triangle_free_3regular_max_edge_cost"]["value"]
+    _say("optimise p=1 3-cube, 8 starts")
+    model = qaoa.MaxCut(8, CUBE, 1, qtn.TN_C64, max_sets=8)
+    xb, fb, trace = optimize.maxcut_optimize(model, workloads.qaoa_angles(3, 8, 1), steps=400, lr=0.05)
+    torch.cuda.synchronize()
+    fmax = float(fb.max())
+    assert fmax <= best * (1 + 1e-5) and fmax >= best * (1 - 1e-5)
+    x = xb[int(fb.argmax())].cpu().tolist()
+    assert abs(gradients.cost(8, CUBE, x) - fmax) <= 1e-5 * best
+    assert float(trace[-1]) >= float(trace[0])
+
+
+def test_angle_optimisation_p2_beats_p1():
+    optimize, qaoa, qtn = _mods()
+    n = 10
+    e = workloads.random_regular_graph(3, n, 4)
+    res = {}
+    for p in (1, 2):
+        _say(f"optimise p={p} n={n}")
+        model = qaoa.MaxCut(n, e, p, qtn.TN_C64, max_sets=8)
+        xb, fb, _ = optimize.maxcut_optimize(model, workloads.qaoa_angles(7, 8, p), steps=300, lr=0.05)
+        torch.cuda.synchronize()
+        k = int(fb.argmax())
+        res[p] = (float(fb[k]), xb[k].cpu().tolist())
+        ref = gradients.cost(n, e, res[p][1])
+        assert abs(ref - res[p][0]) <= 1e-5 * max(1.0, abs(ref))
+    assert res[2][0] >= res[1][0] - 1e-5
+
+
+# --- answer-string estimation (Sec. "Estimating the answer string") -------------------------
+
+def test_answer_string_random_circuit_matches_oracle():
+    from helpers import random_param_circuit
+    from oracle import answer as oracle_answer, statevector
+    _, _, qtn = _mods()
+    from paper_1709_03636_amd import answer
+    n = 7
+    prod, ogates, params = random_param_circuit(n, 30, 21)
+    draws = [k % 2 for k in range(n)]
+    _say("answer string random circuit n=7 c128")
+    bits, probs = answer.answer_string(n, prod, n_params=3, params=params, dtype=qtn.TN_C128, tie_tol=1e-9,
+                                       tie_draws=draws)
+    psi = statevector.run(n, ogates(params))
+    rbits, rprobs = oracle_answer.answer_string(psi, 1e-9, draws)
+    assert bits == rbits
+    np.testing.assert_allclose(np.array(probs), np.array(rprobs), atol=1e-12)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_answer_string_qaoa_matches_oracle(dtype):
+    from oracle import answer as oracle_answer, statevector
+    _, qaoa, qtn = _mods()
+    from paper_1709_03636_amd import answer
+    n = 12
+    e = workloads.random_regular_graph(3, n, 0)
+    gam, bet = -0.35, 0.42
+    gates_ = qaoa.qaoa_gates(n, e, 1)
+    init = np.array([complex(qaoa.PLUS[0], qaoa.PLUS[1]), complex(qaoa.PLUS[2], qaoa.PLUS[3])] * n)
+    draws = [1] + [0] * (n - 1)
+    dt, tol, ptol = (qtn.TN_C128, 1e-9, 1e-12) if dtype == "c128" else (qtn.TN_C64, 1e-4, 1e-6)
+    _say(f"answer string QAOA n={n} {dtype}")
+    bits, probs = answer.answer_string(n, gates_, init=init, n_params=2, params=[gam, bet], dtype=dt, tie_tol=tol,
+                                       tie_draws=draws)
+    psi = statevector.qaoa_state(n, e, [gam], [bet])
+    rbits, rprobs = oracle_answer.answer_string(psi, tol, draws)
+    # the cost is symmetric under flipping every bit: qubit 0 is an exact tie and takes the draw
+    assert abs(probs[0][0] - probs[0][1]) <= ptol and bits[0] == 1
+    assert bits == rbits
+    np.testing.assert_allclose(np.array(probs), np.array(rprobs), atol=ptol)
+    assert answer.cut_value(e, bits) == sum(1 for u, v in e if rbits[u] != rbits[v])
+
+
+# --- noise channels as superoperators -----------------------------------------------------
+
+def _noisy_circuit(n, seed, non_tp=False):
+    """(product gates, oracle ops factory, params): a seeded circuit with
+    channels after some gates: depolarizing, amplitude damping, dephasing,
+    and a two-qubit channel from a random isometry (all trace preserving),
+    optionally one projection (not trace preserving)."""
+    from helpers import random_param_circuit
+    from oracle import gates as ogates_mod
+    from paper_1709_03636_amd import noise
+    prod, ogates, params = random_param_circuit(n, 18, seed)
+    rng = np.random.default_rng(seed + 1000)
+    chans = []  # (position after gate i, kraus, qubits)
+    for i in range(len(prod)):
+        r = rng.integers(0, 6)
+        q = int(rng.integers(0, n))
+        if r == 0:
+            chans.append((i, noise.depolarizing(float(rng.uniform(0, 0.3))), [q]))
+        elif r == 1:
+            chans.append((i, noise.amplitude_damping(float(rng.uniform(0, 0.5))), [q]))
+        elif r == 2:
+            chans.append((i, noise.dephasing(float(rng.uniform(0, 0.4))), [q]))
+        elif r == 3:
+            q1 = (q + 1 + int(rng.integers(0, n - 1))) % n
+            z = rng.normal(size=(16, 4)) + 1j * rng.normal(size=(16, 4))
+            V, _ = np.linalg.qr(z)
+            chans.append((i, [_kraus_of(V, k) for k in range(4)], [q, q1]))
+    if non_tp:
+        chans.append((len(prod) // 2, [np.diag([0.0, 1.0])], [1]))
+    prod_n, layout = [], []
+    for i, g in enumerate(prod):
+        prod_n.append(g)
+        layout.append(("g", i))
+        for pos, kraus, qs in chans:
+            if pos == i:
+                prod_n.append(noise.channel_gate(kraus, qs[0], qs[1] if len(qs) > 1 else -1))
+                layout.append(("c", kraus, qs))
+
+    def oracle_ops(prm):
+        og = ogates(prm)
+        ops = []
+        for item in layout:
+            if item[0] == "g":
+                k, q0, q1, th, ms = og[item[1]]
+                ops.append(([ogates_mod.gate_matrix(k, th, ms)], [q0] if q1 < 0 else [q0, q1]))
+            else:
+                ops.append((item[1], item[2]))
+        return ops
+
+    return prod_n, oracle_ops, params
+
+
+def _kraus_of(V, k):
+    # rows 4k..4k+3 of a 16 x 4 isometry: four 4 x 4 Kraus operators with sum E^dagger E = I
+    return V[4 * k:4 * k + 4, :]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_noisy_circuits_match_density_oracle(seed, dtype):
+    from oracle import density, statevector
+    _, _, qtn = _mods()
+    n = 5
+    prod, oracle_ops, params = _noisy_circuit(n, seed)
+    rho = density.run(n, oracle_ops(params), density.pure(statevector.zero_state(n)))
+    dt, tol = (qtn.TN_C128, 1e-12) if dtype == "c128" else (qtn.TN_C64, 1e-5)
+    rng = np.random.default_rng(seed + 5)
+    for case in range(4):
+        pauli = [int(x) for x in rng.integers(0, 4, size=n)]
+        bits = [int(x) for x in rng.integers(0, 3, size=n)]
+        for mode, target, ref in ((qtn.TN_EXPECTATION, pauli, density.expect_pauli(rho, pauli)),
+                                  (qtn.TN_PROBABILITY, bits, density.probability(rho, bits))):
+            vals = []
+            for lc in (True, False):
+                _say(f"noisy seed={seed} {dtype} case={case} mode={mode} lightcone={lc}")
+                net = qtn.Network(n, prod, mode, target, n_params=3, dtype=dt, lightcone=lc)
+                net.set_order(net.order_linegraph(trials=4, seed=0))
+                vals.append(net.contract(params))
+            for v in vals:
+                assert abs(v - ref) <= tol, (mode, target, v, ref)
+
+
+def test_noisy_gradient_matches_finite_differences():
+    from oracle import density, statevector
+    _, _, qtn = _mods()
+    n = 4
+    prod, oracle_ops, params = _noisy_circuit(n, 3)
+    pauli = [3, 1, 0, 3]
+    net = qtn.Network(n, prod, qtn.TN_EXPECTATION, pauli, n_params=3, dtype=qtn.TN_C128)
+    net.set_order(net.order_linegraph(trials=4, seed=0))
+    _say("noisy gradient c128")
+    val, g = net.grad(params)
+
+    def f(prm):
+        rho = density.run(n, oracle_ops(prm), density.pure(statevector.zero_state(n)))
+        return density.expect_pauli(rho, pauli).real
+
+    h = 1e-5
+    fd = np.array([(f(params + h * np.eye(3)[i]) - f(params - h * np.eye(3)[i])) / (2 * h) for i in range(3)])
+    assert abs(val - f(params)) < 1e-12
+    np.testing.assert_allclose(g, fd, atol=1e-8)
+
+
+def test_non_trace_preserving_map_turns_the_light_cone_off():
+    from oracle import density, statevector
+    _, _, qtn = _mods()
+    n = 5
+    prod, oracle_ops, params = _noisy_circuit(n, 4, non_tp=True)
+    rho = density.run(n, oracle_ops(params), density.pure(statevector.zero_state(n)))
+    bits = [0, 2, 2, 2, 2]
+    on = qtn.Network(n, prod, qtn.TN_PROBABILITY, bits, n_params=3, dtype=qtn.TN_C128, lightcone=True)
+    off = qtn.Network(n, prod, qtn.TN_PROBABILITY, bits, n_params=3, dtype=qtn.TN_C128, lightcone=False)
+    assert on.wires()[1] == off.wires()[1]
+    on.set_order(on.order_linegraph(trials=4, seed=0))
+    _say("non-trace-preserving map")
+    v = on.contract(params)
+    assert abs(v - density.probability(rho, bits)) < 1e-12
+    assert abs(density.probability(rho, [2] * n).real - 1.0) > 1e-3  # the projection removed weight
+
+
+def test_noisy_qaoa_maxcut_matches_density_oracle():
+    from oracle import density, gates as og, statevector
+    from paper_1709_03636_amd import noise
+    _, qaoa, qtn = _mods()
+    n = 8
+    e = workloads.random_regular_graph(3, n, 2)
+    K = noise.depolarizing(0.05)
+    S = 3
+    ang = workloads.qaoa_angles(6, S, 1)
+    _say("noisy QAOA MaxCut n=8")
+    model = qaoa.MaxCut(n, e, 1, qtn.TN_C128, order="linegraph", max_sets=S, noise=K)
+    obj, grad = model.value_and_grad(torch.tensor(ang, dtype=torch.float64, device="cuda"))
+    obj = obj.cpu().numpy()
+    for s in range(S):
+        gam, bet = ang[s]
+        ops = [([og.gate_matrix("H")], [q]) for q in range(n)]
+        for u, v in e:
+            ops += [([og.zz(2 * gam)], [u, v]), (K, [u]), (K, [v])]
+        for q in range(n):
+            ops += [([og.rot(og.X, 2 * bet)], [q]), (K, [q])]
+        rho = density.run(n, ops, density.pure(statevector.zero_state(n)))
+        ref = sum((1 - density.expect_pauli(rho, [3 if q in (u, v) else 0 for q in range(n)]).real) / 2
+                  for u, v in e)
+        assert abs(obj[s] - ref) < 1e-10 * len(e)

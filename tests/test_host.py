@@ -1,6 +1,7 @@
 """Host-side logic of the C-ABI library (no GPU calls): exports, network
 construction, light cone, orders (Algorithms 1 and 2), plan shapes and
 error paths."""
+import itertools
 import os
 import re
 
@@ -202,3 +203,82 @@ def test_disconnected_components(qtn):
     net = qtn.Network(3, gates, qtn.TN_EXPECTATION, [3, 0, 1], lightcone=False)
     net.set_order(net.order_linegraph(trials=1))
     assert net.plan_info()["n_components"] == 3
+
+
+def test_channel_gates_light_cone_and_errors(qtn):
+    """A trace-preserving channel outside the light cone is dropped like a
+    unitary gate; a map that is not trace preserving turns the cone off;
+    channels are rejected in the (unfolded) amplitude mode."""
+    from paper_1709_03636_amd import noise
+    base = [("H", 0, -1, -1, 0.0), ("CNOT", 0, 1, -1, 0.0), ("H", 2, -1, -1, 0.0)]
+    tp = base + [noise.channel_gate(noise.depolarizing(0.1), 2)]
+    ntp = base + [noise.channel_gate([np.diag([1.0, 0.0])], 2)]
+    pauli = [3, 3, 0]
+
+    def tensors(gates, lc):
+        return qtn.Network(3, gates, qtn.TN_EXPECTATION, pauli, lightcone=lc).wires()[1]
+
+    assert tensors(tp, True) < tensors(tp, False)
+    assert tensors(tp, True) == tensors(base, True)
+    assert tensors(ntp, True) == tensors(ntp, False)
+    two = base + [noise.channel_gate([np.kron(E, F) for E in noise.dephasing(0.2) for F in noise.dephasing(0.1)], 1, 2)]
+    # the two-qubit channel touches qubit 1 (in the cone), so it stays and pulls qubit 2's past in
+    assert tensors(two, True) == tensors(two, False) == tensors(base, True) + 4
+    with pytest.raises(qtn.QtnError) as ei:
+        qtn.Network(3, tp, qtn.TN_AMPLITUDE, [0, 0, 0])
+    assert ei.value.code == qtn.TN_EINVAL
+    with pytest.raises(qtn.QtnError):
+        qtn.Network(3, base + [("SUPER1", 1, -1, -1, 0.0)], qtn.TN_EXPECTATION, pauli)
+
+
+def test_superoperator_layout(qtn):
+    """noise.superop follows the documented folded layout: for one Kraus
+    operator E, entry (2a+b, 2c+d) is E[a, c] conj(E[b, d]); two-qubit
+    entries are indexed (q0 out, q1 out, q0 in, q1 in)."""
+    from paper_1709_03636_amd import noise
+    rng = np.random.default_rng(1)
+    E = rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2))
+    S = noise.superop([E])
+    for a, b, c, d in itertools.product((0, 1), repeat=4):
+        assert S[2 * a + b, 2 * c + d] == E[a, c] * np.conj(E[b, d])
+    F = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+    S2 = noise.superop([F])
+    for a0, b0, a1, b1, c0, d0, c1, d1 in itertools.product((0, 1), repeat=8):
+        row, col = (2 * a0 + b0) * 4 + 2 * a1 + b1, (2 * c0 + d0) * 4 + 2 * c1 + d1
+        assert S2[row, col] == F[2 * a0 + a1, 2 * c0 + c1] * np.conj(F[2 * b0 + b1, 2 * d0 + d1])
+
+
+@pytest.mark.parametrize("noisy", [False, True])
+def test_qaoa_edge_lightcone_circuits_are_exact(qaoa, noisy):
+    """The relabelled light-cone circuit of every edge gives the same <Z_u Z_v>
+    as the whole circuit (density-matrix oracle), with and without a channel
+    after every gate (which stops the ZZ layer from commuting as a block)."""
+    from oracle import density, gates as og, statevector
+    from paper_1709_03636_amd import noise
+    n = 8
+    e = workloads.random_regular_graph(3, n, 2)
+    K = noise.depolarizing(0.05) if noisy else None
+    p = 2
+    ang = [0.37, -0.2, -0.61, 0.45]
+
+    def ops_of(gl):
+        ops = []
+        for g in gl:
+            kind, q0, q1, prm = g[0], g[1], g[2], g[3]
+            if kind == "ZZ":
+                ops.append(([og.zz(2 * ang[prm])], [q0, q1]))
+            elif kind == "RX":
+                ops.append(([og.rot(og.X, 2 * ang[prm])], [q0]))
+            else:
+                ops.append((K, [q0]))
+        return ops
+
+    def plus(m):
+        return density.pure(statevector.product_state([[2 ** -0.5, 2 ** -0.5]] * m))
+
+    rho = density.run(n, ops_of(qaoa.qaoa_gates(n, e, p, K)), plus(n))
+    for u, v in e:
+        full = density.expect_pauli(rho, [3 if q in (u, v) else 0 for q in range(n)]).real
+        m, g = qaoa.edge_lightcone_circuit(n, e, p, (u, v), K)
+        lc = density.expect_pauli(density.run(m, ops_of(g), plus(m)), [3, 3] + [0] * (m - 2)).real
+        assert abs(full - lc) < 1e-13
