@@ -88,6 +88,13 @@ typedef struct {
   const uint8_t *pauli;  /* EXPECTATION: one entry per qubit */
   int32_t lightcone;     /* PROBABILITY / EXPECTATION: 1 = drop gates outside the backward
                             light cone of the measured qubits (exact for unitary gates) */
+  int32_t diagonal;      /* 1 = gates diagonal in the computational basis (Z, RZ, ZZ, CZ,
+                            diagonal custom gates) keep their wires and become tensors of
+                            their diagonal on them (4 or 16 entries folded; 2 or 4 unfolded):
+                            those wires are hyperedges, and a contraction keeps (does not sum)
+                            a shared index that another live tensor still holds. Exact; the
+                            paper keeps every gate dense (sparsity is its future work).
+                            0 = dense gates, the paper's network. */
 } tn_target;
 
 enum { TN_C64 = 0, TN_C128 = 1 };
@@ -111,7 +118,8 @@ int tn_build(const tn_gate *gates, int32_t n_gates, int32_t n_qubits, const doub
              const tn_target *target, int32_t n_params, int32_t dtype, tn_net **out);
 
 /* Network shape: number of wires and tensors; wire w joins tensors
- * endpoints[2w] and endpoints[2w+1] (endpoints may be NULL). */
+ * endpoints[2w] and endpoints[2w+1] (endpoints may be NULL). A hyperedge
+ * (diagonal mode) reports its first and last holder. */
 int tn_wires(const tn_net *net, int32_t *n_wires, int32_t *n_tensors, int32_t *endpoints);
 
 /* Stochastic order (Algorithm 2 of the paper): pick a random remaining wire,

@@ -74,12 +74,13 @@ int tn_wires(const tn_net *net, int32_t *n_wires, int32_t *n_tensors, int32_t *e
     qtn::set_error("tn_wires: NULL network");
     return TN_EINVAL;
   }
-  if (n_wires) *n_wires = (int32_t)net->wire_ends.size();
+  if (n_wires) *n_wires = (int32_t)net->wire_holders.size();
   if (n_tensors) *n_tensors = (int32_t)net->leaves.size();
   if (endpoints)
-    for (size_t w = 0; w < net->wire_ends.size(); ++w) {
-      endpoints[2 * w] = net->wire_ends[w][0];
-      endpoints[2 * w + 1] = net->wire_ends[w][1];
+    for (size_t w = 0; w < net->wire_holders.size(); ++w) {
+      const auto &h = net->wire_holders[w];
+      endpoints[2 * w] = h.empty() ? -1 : h.front();
+      endpoints[2 * w + 1] = h.size() < 2 ? -1 : h.back();
     }
   return TN_OK;
 }
@@ -160,7 +161,7 @@ int tn_plan_info(const tn_net *net, tn_plan_stats *out) {
   std::memset(out, 0, sizeof(*out));
   out->n_steps = p.n_steps;
   out->n_tensors = (int32_t)net->leaves.size();
-  out->n_wires = (int32_t)net->wire_ends.size();
+  out->n_wires = (int32_t)net->wire_holders.size();
   out->peak_bits = p.peak_bits;
   out->max_rank_wires = p.max_rank_wires;
   out->n_components = p.n_components;

@@ -161,6 +161,31 @@ Mat superop_2q(const Mat &U) {
   return S;
 }
 
+// Diagonal of a gate that is diagonal in the computational basis, as a
+// tensor over its (input = output) wires: folded, entry 2a+b (one qubit) or
+// (2a0+b0)*4 + (2a1+b1) (two) holds U_aa conj(U_bb); unfolded, entry a
+// (or 2a0+a1) holds U_aa.
+Mat diag_entries(const Mat &U, bool two, bool folded) {
+  const int dim = two ? 4 : 2;
+  Mat d;
+  if (!folded) {
+    for (int a = 0; a < dim; ++a) d.push_back(U[a * dim + a]);
+    return d;
+  }
+  if (!two) {
+    for (int a = 0; a < 2; ++a)
+      for (int bb = 0; bb < 2; ++bb) d.push_back(U[a * 2 + a] * std::conj(U[bb * 2 + bb]));
+    return d;
+  }
+  d.resize(16);
+  for (int e = 0; e < 16; ++e) {
+    const int a0 = (e >> 3) & 1, b0 = (e >> 2) & 1, a1 = (e >> 1) & 1, b1 = e & 1;
+    const int ka = 2 * a0 + a1, kb = 2 * b0 + b1;
+    d[e] = U[ka * 4 + ka] * std::conj(U[kb * 4 + kb]);
+  }
+  return d;
+}
+
 struct Builder {
   Net &net;
   std::map<std::vector<double>, int> const_ids;
@@ -168,8 +193,8 @@ struct Builder {
   explicit Builder(Net &n) : net(n) {}
 
   int new_wire() {
-    net.wire_ends.push_back({-1, -1});
-    return (int)net.wire_ends.size() - 1;
+    net.wire_holders.emplace_back();
+    return (int)net.wire_holders.size() - 1;
   }
   int add_const(const Mat &m) {
     std::vector<double> key;
@@ -185,13 +210,13 @@ struct Builder {
     const_ids[key] = id;
     return id;
   }
-  int add_ptensor(int kind, int param, double coeff, int folded) {
-    auto key = std::make_tuple(kind, param, coeff, folded);
+  int add_ptensor(int kind, int param, double coeff, int folded, int diag) {
+    auto key = std::make_tuple(kind, param, coeff, folded + 2 * diag);
     auto it = ptensor_ids.find(key);
     if (it != ptensor_ids.end()) return it->second;
     int nq = kind == TN_ZZ ? 2 : 1;
-    int bits = (folded ? 2 : 1) * 2 * nq;
-    net.ptensors.push_back({kind, param, coeff, folded, bits});
+    int bits = (folded ? 2 : 1) * (diag ? 1 : 2) * nq;
+    net.ptensors.push_back({kind, param, coeff, folded, bits, diag});
     int id = (int)net.ptensors.size() - 1;
     ptensor_ids[key] = id;
     return id;
@@ -199,10 +224,7 @@ struct Builder {
   void add_leaf(const std::vector<int> &wires, int src) {
     int id = (int)net.leaves.size();
     net.leaves.push_back({wires, src});
-    for (int w : wires) {
-      auto &e = net.wire_ends[w];
-      if (e[0] < 0) e[0] = id; else e[1] = id;
-    }
+    for (int w : wires) net.wire_holders[w].push_back(id);
   }
 };
 
@@ -307,12 +329,24 @@ int build_network(const tn_gate *gates, int n_gates, int n_qubits, const double 
     B.add_leaf({w}, B.add_const(v));
     cur[q] = w;
   }
+  // diagonal mode: a gate diagonal in the computational basis keeps its
+  // wires (input = output) and becomes a tensor of its diagonal on them;
+  // those wires become hyperedges held by more than two tensors
+  const bool diag_mode = target->diagonal != 0;
   for (int i = 0; i < n_gates; ++i) {
     if (!keep[i]) continue;
     const tn_gate &g = gates[i];
+    if (diag_mode && gate_is_diagonal(g)) {
+      const bool two = gate_is_2q(g.kind);
+      int src = g.param >= 0 ? -B.add_ptensor(g.kind, g.param, g.coeff, folded, 1) - 1
+                             : B.add_const(diag_entries(gate_matrix(g, g.coeff), two, folded));
+      if (two) B.add_leaf({cur[g.q0], cur[g.q1]}, src);
+      else B.add_leaf({cur[g.q0]}, src);
+      continue;
+    }
     int src;
     if (g.param >= 0) {
-      src = -B.add_ptensor(g.kind, g.param, g.coeff, folded) - 1;
+      src = -B.add_ptensor(g.kind, g.param, g.coeff, folded, 0) - 1;
     } else {
       Mat U = gate_matrix(g, g.coeff);
       bool two = gate_is_2q(g.kind);

@@ -4,16 +4,20 @@
 
 namespace qtn {
 
-// One op of a compiled network program, as the kernels read it (48 bytes).
+// One op of a compiled network program, as the kernels read it (56 bytes).
 // Offsets are in complex elements of the executor's memory (LDS for the
-// fused executor, a per-set global arena for the level executor).
+// fused executor, a per-set global arena for the level executor). Output
+// index c = (i, b, j): i the nFX X-only bits (deposited at maskX in X), b
+// the nB batch bits (offsets from the table at tabB), j the nFY Y-only bits
+// (deposited at maskY in Y).
 struct DOp {
   int32_t type;      // OpType
   int32_t x, y, z;   // operand / result offsets (OP_SCALAR: z = scalar slot)
   int32_t nFX, nS, nFY;
   uint32_t maskX, maskY;
-  int32_t tab;       // offset into the int32 table array
+  int32_t tab;       // offset into the int32 table array (summed index)
   int32_t aux0, aux1;
+  int32_t nB, tabB;  // batch bits and their (X, Y) offset table
 };
 
 // The free-bit masks of an op as runs of consecutive address bits, lowest
@@ -50,7 +54,7 @@ inline void pack_runs(uint32_t mask, int32_t out[4]) {
 // bound-tensor slice.
 struct DParam {
   int32_t kind, param, folded, bits;
-  int32_t off, goff, slot, pad;
+  int32_t off, goff, slot, diag;  // diag: only the diagonal of the gate (2^bits entries)
   double coeff;
 };
 

@@ -46,6 +46,7 @@ struct ParamTensor {
   double coeff;
   int folded;    // 1: superoperator U (x) conj(U); 0: the matrix U
   int bits;      // log2(entries)
+  int diag = 0;  // 1: only the diagonal (a gate diagonal in the computational basis on hyperedge wires)
 };
 
 struct Leaf {
@@ -58,8 +59,10 @@ struct Leaf {
 struct Op {
   OpType type;
   int x, y, z;            // buffer ids (z: scalar slot for OP_SCALAR; component for OP_SEED)
-  int nFX, nS, nFY;       // bits: free of X, summed, free of Y
-  uint32_t maskX_F = 0, maskY_F = 0;  // address positions of the free bits in X / Y
+  int nFX, nS, nFY;       // bits: free of X only, summed, free of Y only
+  int nB = 0;             // batch bits: shared by X and Y and kept in Z (hyperedges)
+  uint32_t maskX_F = 0, maskY_F = 0;  // address positions of the X-only / Y-only free bits
+  std::vector<int32_t> tabB;  // (X, Y) offset pairs of the batch index b (2^nB pairs; empty if nB = 0)
   std::vector<int32_t> tab;  // OP_CONTRACT/OP_SCALAR: (X, Y) offset pairs of the summed index k:
                              //   2^min(nS,12) pairs for the low bits of k, then (nS > 12)
                              //   2^(nS-12) pairs for the high bits; offsets add
@@ -88,7 +91,7 @@ struct Plan {
 struct Net {
   int n_qubits = 0, mode = 0, dtype = 0, n_params = 0, wire_bits = 2;
   std::vector<Leaf> leaves;
-  std::vector<std::array<int, 2>> wire_ends;  // leaf ids
+  std::vector<std::vector<int>> wire_holders; // leaf ids holding each wire (2, or more for a hyperedge)
   std::vector<std::vector<cd>> consts;        // distinct constant tensors
   std::vector<ParamTensor> ptensors;          // distinct parametric tensors
   uint64_t mem_limit = 64ull << 30;

@@ -87,6 +87,19 @@ __device__ __forceinline__ uint32_t pdep32(uint32_t v, uint32_t mask) {
   return r;
 }
 
+// Operand offsets (X, Y) of output c of an op (see DOp: c = (i, b, j)).
+__device__ __forceinline__ void out_addr(const DOp &op, const int32_t *__restrict__ tbB, uint32_t c, uint32_t &fx,
+                                         uint32_t &fy) {
+  const uint32_t rest = c >> op.nFY;
+  fy = pdep32(c & ((1u << op.nFY) - 1u), op.maskY);
+  fx = pdep32(rest >> op.nB, op.maskX);
+  if (op.nB) {
+    const uint32_t b = rest & ((1u << op.nB) - 1u);
+    fx += tbB[2 * b];
+    fy += tbB[2 * b + 1];
+  }
+}
+
 // --- parametric tensors ---------------------------------------------------------
 // U(theta) = exp(-i theta P / 2) = c I - i s P with c = cos(theta/2),
 // s = sin(theta/2); dU/dtheta has the same form with (c, s) -> (-s/2, c/2).
@@ -150,9 +163,11 @@ __global__ __launch_bounds__(256) void bind_params_kernel(const DParam *__restri
   sincos(0.5 * th, &sn, &cs);
   V *g = G + (size_t)s * per_set + d.off;
   V *dg = dG ? dG + (size_t)s * per_set + d.off : nullptr;
+  // a diagonal tensor holds entries (e, e) of the full one: index e (2^bits + 1)
+  const int stride = d.diag ? (1 << d.bits) + 1 : 1;
   for (int e = threadIdx.x; e < (1 << d.bits); e += blockDim.x) {
-    g[e] = from_d2<V>(param_entry(d.kind, d.folded, e, cs, sn, false));
-    if (dg) dg[e] = from_d2<V>(param_entry(d.kind, d.folded, e, cs, sn, true));
+    g[e] = from_d2<V>(param_entry(d.kind, d.folded, e * stride, cs, sn, false));
+    if (dg) dg[e] = from_d2<V>(param_entry(d.kind, d.folded, e * stride, cs, sn, true));
   }
 }
 
@@ -235,20 +250,20 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 // scalar registers and the K loop is unrolled, so all operand reads of an
 // output are in flight together. One output per lane.
 template <typename V, int BLOCK, int LGK>
-__device__ __forceinline__ void contract_small_k(V *mem, const DOp &op, const int32_t *__restrict__ tb) {
+__device__ __forceinline__ void contract_small_k(V *mem, const DOp &op, const int32_t *__restrict__ tb,
+                                                 const int32_t *__restrict__ tbB) {
   constexpr int K = 1 << LGK;
   int32_t t[2 * K];
   const QTN_CONST int32_t *tc = cptr(tb);
 #pragma unroll
   for (int i = 0; i < 2 * K; ++i) t[i] = tc[i];
-  const int nOut = 1 << (op.nFX + op.nFY);
-  const uint32_t maskJ = (1u << op.nFY) - 1u;
+  const int nOut = 1 << (op.nFX + op.nB + op.nFY);
   const V *X = mem + op.x;
   const V *Y = mem + op.y;
   V *Z = mem + op.z;
   for (int c = threadIdx.x; c < nOut; c += BLOCK) {
-    const uint32_t fx = pdep32((uint32_t)c >> op.nFY, op.maskX);
-    const uint32_t fy = pdep32((uint32_t)c & maskJ, op.maskY);
+    uint32_t fx, fy;
+    out_addr(op, tbB, (uint32_t)c, fx, fy);
     // operand reads in chunks of up to 8 entries, all issued before the
     // multiply-adds that consume them
 #ifdef QTN_CHUNK
@@ -276,19 +291,19 @@ __device__ __forceinline__ void contract_small_k(V *mem, const DOp &op, const in
 // index is split over lane groups and the partial sums are added in a fixed
 // order through `scratch`.
 template <typename V, int BLOCK>
-__device__ __forceinline__ void contract_general(V *mem, const DOp &op, const int32_t *__restrict__ tb, V *scratch) {
+__device__ __forceinline__ void contract_general(V *mem, const DOp &op, const int32_t *__restrict__ tb,
+                                                 const int32_t *__restrict__ tbB, V *scratch) {
   const int tid = threadIdx.x;
-  const int lgOut = op.nFX + op.nFY;
+  const int lgOut = op.nFX + op.nB + op.nFY;
   const int nOut = 1 << lgOut;
   const int K = 1 << op.nS;
-  const uint32_t maskJ = (1u << op.nFY) - 1u;
   const V *X = mem + op.x;
   const V *Y = mem + op.y;
   V *Z = mem + op.z;
   if (nOut >= BLOCK) {
     for (int c = tid; c < nOut; c += BLOCK) {
-      const uint32_t fx = pdep32((uint32_t)c >> op.nFY, op.maskX);
-      const uint32_t fy = pdep32((uint32_t)c & maskJ, op.maskY);
+      uint32_t fx, fy;
+      out_addr(op, tbB, (uint32_t)c, fx, fy);
       V acc = czero<V>();
       for (int k = 0; k < K; ++k) {
         const int2 o = tab_at(tb, op.nS, k);
@@ -303,8 +318,8 @@ __device__ __forceinline__ void contract_general(V *mem, const DOp &op, const in
     const int c = tid & (nOut - 1);
     const int g = tid >> lgOut;
     if (g < G) {
-      const uint32_t fx = pdep32((uint32_t)c >> op.nFY, op.maskX);
-      const uint32_t fy = pdep32((uint32_t)c & maskJ, op.maskY);
+      uint32_t fx, fy;
+      out_addr(op, tbB, (uint32_t)c, fx, fy);
       V acc = czero<V>();
       for (int k = g; k < K; k += G) {
         const int2 o = tab_at(tb, op.nS, k);
@@ -322,14 +337,15 @@ __device__ __forceinline__ void contract_general(V *mem, const DOp &op, const in
 }
 
 template <typename V, int BLOCK>
-__device__ __forceinline__ void op_contract(V *mem, const DOp &op, const int32_t *__restrict__ tb, V *scratch) {
+__device__ __forceinline__ void op_contract(V *mem, const DOp &op, const int32_t *__restrict__ tb,
+                                            const int32_t *__restrict__ tbB, V *scratch) {
   switch (op.nS) {
-    case 0: contract_small_k<V, BLOCK, 0>(mem, op, tb); break;
-    case 1: contract_small_k<V, BLOCK, 1>(mem, op, tb); break;
-    case 2: contract_small_k<V, BLOCK, 2>(mem, op, tb); break;
-    case 3: contract_small_k<V, BLOCK, 3>(mem, op, tb); break;
-    case 4: contract_small_k<V, BLOCK, 4>(mem, op, tb); break;
-    default: contract_general<V, BLOCK>(mem, op, tb, scratch); break;
+    case 0: contract_small_k<V, BLOCK, 0>(mem, op, tb, tbB); break;
+    case 1: contract_small_k<V, BLOCK, 1>(mem, op, tb, tbB); break;
+    case 2: contract_small_k<V, BLOCK, 2>(mem, op, tb, tbB); break;
+    case 3: contract_small_k<V, BLOCK, 3>(mem, op, tb, tbB); break;
+    case 4: contract_small_k<V, BLOCK, 4>(mem, op, tb, tbB); break;
+    default: contract_general<V, BLOCK>(mem, op, tb, tbB, scratch); break;
   }
 }
 
@@ -542,7 +558,7 @@ void fused_exec_kernel(FusedArgs a) {
       const DOp op = cload(ops + o);
       const int32_t *tb = a.tabs + op.tab;
       if (op.type == OP_CONTRACT) {
-        op_contract<V, BLOCK>(mem, op, tb, scratch);
+        op_contract<V, BLOCK>(mem, op, tb, a.tabs + op.tabB, scratch);
       } else if (op.type == OP_SCALAR) {
         const int K = 1 << op.nS;
         double re = 0.0, im = 0.0;

@@ -71,8 +71,9 @@ __device__ __forceinline__ uint32_t l_deposit(uint32_t v, const int32_t runs[4],
 // Z[set][c] = sum_k X[set][fx(c) + tx(k)] * Y[set][fy(c) + ty(k)]; one output per thread.
 template <typename V>
 __global__ __launch_bounds__(256) void level_contract_kernel(LevelArgs a, DOp op, DRuns ru,
-                                                             const int32_t *__restrict__ tab) {
-  const int lgOut = op.nFX + op.nFY;
+                                                             const int32_t *__restrict__ tab,
+                                                             const int32_t *__restrict__ tabB) {
+  const int lgOut = op.nFX + op.nB + op.nFY;
   const int64_t nOut = (int64_t)1 << lgOut;
   const int64_t total = nOut * a.n_sets;
   const int K = 1 << op.nS;
@@ -82,8 +83,16 @@ __global__ __launch_bounds__(256) void level_contract_kernel(LevelArgs a, DOp op
     const int64_t set = g >> lgOut;
     const uint32_t c = (uint32_t)(g & (nOut - 1));
     V *base = arena + set * a.stride;
-    const V *X = base + op.x + l_deposit(c >> op.nFY, ru.runsX, op.maskX);
-    const V *Y = base + op.y + l_deposit(c & maskJ, ru.runsY, op.maskY);
+    // output c = (i, b, j): X-only bits, batch bits (table), Y-only bits
+    const uint32_t rest = c >> op.nFY;
+    uint32_t bx = 0, by = 0;
+    if (op.nB) {
+      const uint32_t b = rest & ((1u << op.nB) - 1u);
+      bx = tabB[2 * b];
+      by = tabB[2 * b + 1];
+    }
+    const V *X = base + op.x + l_deposit(rest >> op.nB, ru.runsX, op.maskX) + bx;
+    const V *Y = base + op.y + l_deposit(c & maskJ, ru.runsY, op.maskY) + by;
     V acc;
     acc.x = 0;
     acc.y = 0;
@@ -262,14 +271,16 @@ static inline int grid_for(int64_t total) {
 }
 
 template <typename V>
-static hipError_t level_op_t(const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream_t st) {
+static hipError_t level_op_t(const LevelArgs &a, const DOp &op, const int32_t *tabs, hipStream_t st) {
+  const int32_t *tab = tabs + op.tab;
   switch (op.type) {
     case OP_CONTRACT: {
-      int64_t total = ((int64_t)1 << (op.nFX + op.nFY)) * a.n_sets;
+      int64_t total = ((int64_t)1 << (op.nFX + op.nB + op.nFY)) * a.n_sets;
       DRuns ru;
       pack_runs(op.maskX, ru.runsX);
       pack_runs(op.maskY, ru.runsY);
-      hipLaunchKernelGGL(level_contract_kernel<V>, dim3(grid_for(total)), dim3(256), 0, st, a, op, ru, tab);
+      hipLaunchKernelGGL(level_contract_kernel<V>, dim3(grid_for(total)), dim3(256), 0, st, a, op, ru, tab,
+                         tabs + op.tabB);
       break;
     }
     case OP_SCALAR: {
@@ -294,9 +305,10 @@ static hipError_t level_op_t(const LevelArgs &a, const DOp &op, const int32_t *t
 
 // mfma: 0 = thin kernel, else the matrix-core precision (TN_MFMA_*) used
 // when the op is eligible (the autotuner may choose thin for a shape class).
-hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tab, int mfma, hipStream_t st) {
-  if (mfma && mfma_eligible(dtype, op)) return mfma_contract(a, op, tab, mfma, st);
-  return dtype == TN_C128 ? level_op_t<double2>(a, op, tab, st) : level_op_t<float2>(a, op, tab, st);
+// tabs: the batch's table array (the op's tables at op.tab / op.tabB).
+hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tabs, int mfma, hipStream_t st) {
+  if (mfma && mfma_eligible(dtype, op)) return mfma_contract(a, op, tabs + op.tab, mfma, st);
+  return dtype == TN_C128 ? level_op_t<double2>(a, op, tabs, st) : level_op_t<float2>(a, op, tabs, st);
 }
 
 hipError_t level_setup(int dtype, const LevelArgs &a, const void *consts, int n_const, const DParam *pt, int n_pt,

@@ -300,7 +300,7 @@ __global__ __launch_bounds__(256) void mfma_cgemm_bf16x3_kernel(LevelArgs a, DOp
 
 // True when the MFMA path takes this op (complex64, tiles divide the shape).
 bool mfma_eligible(int dtype, const DOp &op) {
-  return dtype == TN_C64 && op.type == OP_CONTRACT && op.nFX >= 6 && op.nFY >= 6 && op.nS >= 4;
+  return dtype == TN_C64 && op.type == OP_CONTRACT && op.nB == 0 && op.nFX >= 6 && op.nFY >= 6 && op.nS >= 4;
 }
 
 // prec: TN_MFMA_FP32 (4M FP32 products) or TN_MFMA_BF16X3 (split-BF16 products).

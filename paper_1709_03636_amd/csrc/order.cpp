@@ -5,7 +5,8 @@
 //    of the merged tensor minus the larger rank of its two ends (ranks in
 //    wires); accept when the cost is at most the threshold, which starts at
 //    -1, rises by one after more than MaxRejections consecutive rejections
-//    and returns to -1 after every acceptance.
+//    and returns to -1 after every acceptance. A hyperedge (diagonal mode)
+//    merges all of its holders.
 //  * Line-graph scheme (Algorithm 1): build the line graph L(G) (one vertex
 //    per wire, adjacent when the wires meet at a tensor), find an elimination
 //    ordering of L(G) and eliminate the wires of G in that order. The paper
@@ -25,39 +26,60 @@ namespace qtn {
 namespace {
 
 // Wire-level state of a network being contracted: each live tensor is a set
-// of wire ids; wire ends point at live tensor ids.
+// of wire ids; each wire lists the live tensors holding it (two, or more
+// for a hyperedge of diagonal gates).
 struct WireGraph {
   std::vector<std::vector<int>> tw;   // wires of each tensor (live or dead)
   std::vector<char> live;
-  std::vector<std::array<int, 2>> ends;
+  std::vector<std::vector<int>> hold;
 
   explicit WireGraph(const Net &net) {
     for (auto &l : net.leaves) tw.push_back(l.wires);
     live.assign(tw.size(), 1);
-    ends = net.wire_ends;
+    hold = net.wire_holders;
   }
-  // Wires shared by the two ends of wire w.
-  std::vector<int> shared(int a, int b) const {
-    std::vector<int> s;
-    for (int x : tw[a])
-      if (std::find(tw[b].begin(), tw[b].end(), x) != tw[b].end()) s.push_back(x);
-    return s;
+  // A wire of the merge of tensors `grp` survives when some tensor outside
+  // the group still holds it.
+  bool internal(int w, const std::vector<int> &grp) const {
+    for (int h : hold[w])
+      if (std::find(grp.begin(), grp.end(), h) == grp.end()) return false;
+    return true;
+  }
+  // Wires of the merge of `grp` (first-seen order).
+  std::vector<int> merged_wires(const std::vector<int> &grp) const {
+    std::vector<int> c;
+    for (int t : grp)
+      for (int x : tw[t])
+        if (!internal(x, grp) && std::find(c.begin(), c.end(), x) == c.end()) c.push_back(x);
+    return c;
   }
   // Merge tensors a and b; returns the new tensor id.
-  int merge(int a, int b, const std::vector<int> &sh) {
-    std::vector<int> c;
-    for (int x : tw[a])
-      if (std::find(sh.begin(), sh.end(), x) == sh.end()) c.push_back(x);
-    for (int x : tw[b])
-      if (std::find(sh.begin(), sh.end(), x) == sh.end()) c.push_back(x);
+  int merge(int a, int b) {
+    const std::vector<int> grp{a, b};
+    std::vector<int> c = merged_wires(grp);
+    std::vector<int> touched = tw[a];
+    touched.insert(touched.end(), tw[b].begin(), tw[b].end());
     int id = (int)tw.size();
     tw.push_back(c);
     live.push_back(1);
     live[a] = live[b] = 0;
-    for (int v : {a, b})
-      for (int x : tw[v])
-        for (int k = 0; k < 2; ++k)
-          if (ends[x][k] == a || ends[x][k] == b) ends[x][k] = id;
+    for (int x : touched) {
+      auto &h = hold[x];
+      const bool keep = std::find(c.begin(), c.end(), x) != c.end();
+      bool placed = false;
+      for (size_t i = 0; i < h.size();) {
+        if (h[i] == a || h[i] == b) {
+          if (keep && !placed) {
+            h[i++] = id;
+            placed = true;
+          } else {
+            h.erase(h.begin() + (long)i);
+          }
+        } else {
+          ++i;
+        }
+      }
+    }
     return id;
   }
 };
@@ -65,15 +87,16 @@ struct WireGraph {
 }  // namespace
 
 int order_stochastic(const Net &net, uint64_t seed, int max_rej, std::vector<int> &pi) {
-  const int W = (int)net.wire_ends.size();
+  const int W = (int)net.wire_holders.size();
   pi.clear();
   WireGraph g(net);
   SplitMix64 rng(seed);
-  // remaining wires (ends on distinct tensors), with O(1) removal
+  // remaining wires (held by two or more live tensors), with O(1) removal
   std::vector<int> rem(W), where(W);
   for (int w = 0; w < W; ++w) rem[w] = where[w] = w;
   auto remove = [&](int w) {
     int i = where[w];
+    if (i < 0) return;
     int last = rem.back();
     rem[i] = last;
     where[last] = i;
@@ -84,17 +107,33 @@ int order_stochastic(const Net &net, uint64_t seed, int max_rej, std::vector<int
   while (!rem.empty()) {
     int limit = max_rej > 0 ? max_rej : (int)rem.size();
     int w = rem[rng.below((uint32_t)rem.size())];
-    int a = g.ends[w][0], b = g.ends[w][1];
-    std::vector<int> sh = g.shared(a, b);
-    int ra = (int)g.tw[a].size(), rb = (int)g.tw[b].size();
-    int rc = ra + rb - 2 * (int)sh.size();
-    int cost = rc - std::max(ra, rb);
-    if (cost <= threshold) {
+    // contracting a wire merges every tensor holding it (two for an ordinary wire)
+    const std::vector<int> grp = g.hold[w];
+    if (grp.size() < 2) {  // a dangling wire: nothing to merge
       pi.push_back(w);
-      for (int x : sh)
+      remove(w);
+      continue;
+    }
+    int rmax = 0;
+    for (int t : grp) rmax = std::max(rmax, (int)g.tw[t].size());
+    int rc = (int)g.merged_wires(grp).size();
+    int cost = rc - rmax;
+    if (cost <= threshold) {
+      std::vector<int> before;
+      for (int t : grp)
+        for (int x : g.tw[t])
+          if (std::find(before.begin(), before.end(), x) == before.end()) before.push_back(x);
+      int cur = grp[0];
+      for (size_t i = 1; i < grp.size(); ++i) cur = g.merge(cur, grp[i]);
+      // the drawn wire first, then every other wire the merge made internal
+      // (removed from the remaining set in first-seen order)
+      std::vector<int> done_now;
+      for (int x : before)
+        if (where[x] >= 0 && g.hold[x].size() < 2) done_now.push_back(x);
+      pi.push_back(w);
+      for (int x : done_now)
         if (x != w) pi.push_back(x);
-      for (int x : sh) remove(x);
-      g.merge(a, b, sh);
+      for (int x : done_now) remove(x);
       rejections = 0;
       threshold = -1;
     } else {
@@ -157,7 +196,7 @@ std::vector<int> min_fill_order(const std::vector<std::vector<int>> &adj0, Split
 }  // namespace
 
 int order_linegraph(const Net &net, int trials, double budget_s, uint64_t seed, std::vector<int> &pi) {
-  const int W = (int)net.wire_ends.size();
+  const int W = (int)net.wire_holders.size();
   // line graph: wires adjacent when they meet at a tensor
   std::vector<std::vector<int>> adj(W);
   for (auto &l : net.leaves)

@@ -2,14 +2,17 @@
 // contractions (eq. (1) of the paper) and, for gradients, the reverse-mode
 // (adjoint) program over the same steps.
 //
-// Forward: wire pi[i] merges the two tensors at its ends and sums every
-// label they share; the result keeps the free labels of X (in X's order)
-// followed by the free labels of Y (in Y's order), X being the larger
-// operand. A result without labels is a component scalar, accumulated in
-// FP64. Adjoint: for Z = X . Y with upstream Zbar = d s / d Z (no complex
-// conjugation: the network value is a polynomial in the tensor entries),
-//   Xbar = Zbar . Y  (sums the free labels of Y),
-//   Ybar = X . Zbar  (sums the free labels of X),
+// Forward: wire pi[i] merges the tensors holding it (two, or more for a
+// hyperedge of diagonal gates, merged pairwise) and sums every label they
+// share that no other live tensor holds; shared labels still held elsewhere
+// are batch labels, kept in the result. The result keeps the free labels of
+// X (in X's order), then the batch labels (in X's order), then the free
+// labels of Y (in Y's order), X being the larger operand. A result without
+// labels is a component scalar, accumulated in FP64. Adjoint: for
+// Z = X . Y with upstream Zbar = d s / d Z (no complex conjugation: the
+// network value is a polynomial in the tensor entries),
+//   Xbar = Zbar . Y  (sums the free labels of Y, keeps the batch labels),
+//   Ybar = X . Zbar  (sums the free labels of X, keeps the batch labels),
 // and at a parametric leaf G, d s / d theta += sum Gbar * dG/dtheta.
 #include <algorithm>
 #include <map>
@@ -41,14 +44,20 @@ struct Emitter {
     return (int)p.labels.size() - 1;
   }
 
-  // Emit Z = X . Y summing all shared labels. Returns the new buffer, or -1
-  // for a rank-0 result stored in scalar slot `slot` (when slot >= 0).
-  int contract(int x, int y, bool fwd, int slot_if_scalar, double &flops, double &bytes) {
-    const auto &lx = p.labels[x];
-    const auto &ly = p.labels[y];
+  // Emit Z = X . Y summing the shared labels for which keep(label) is false
+  // (keep(label) true: a batch label). Returns the new buffer, or -1 for a
+  // rank-0 result stored in scalar slot `slot` (when slot >= 0).
+  template <typename Keep>
+  int contract(int x, int y, bool fwd, int slot_if_scalar, double &flops, double &bytes, Keep keep) {
+    const auto lx = p.labels[x];
+    const auto ly = p.labels[y];
     const int rx = (int)lx.size(), ry = (int)ly.size();
-    std::vector<int> S, FX, FY;
-    for (int l : lx) (find_label(ly, l) >= 0 ? S : FX).push_back(l);
+    std::vector<int> S, FX, FY, B;
+    for (int l : lx) {
+      if (find_label(ly, l) < 0) FX.push_back(l);
+      else if (keep(l)) B.push_back(l);
+      else S.push_back(l);
+    }
     for (int l : ly)
       if (find_label(lx, l) < 0) FY.push_back(l);
     Op op;
@@ -57,9 +66,25 @@ struct Emitter {
     op.nFX = (int)FX.size();
     op.nS = (int)S.size();
     op.nFY = (int)FY.size();
+    op.nB = (int)B.size();
     op.fwd = fwd;
     for (int l : FX) op.maskX_F |= 1u << pos_of(find_label(lx, l), rx);
     for (int l : FY) op.maskY_F |= 1u << pos_of(find_label(ly, l), ry);
+    // batch index b: bit nB-1-t is batch label B[t] (the result keeps B in
+    // this order between the X-only and the Y-only labels)
+    if (op.nB > 0) {
+      op.tabB.resize(2 * ((size_t)1 << op.nB));
+      for (int32_t bb = 0; bb < (1 << op.nB); ++bb) {
+        int32_t ox = 0, oy = 0;
+        for (int t = 0; t < op.nB; ++t)
+          if ((bb >> (op.nB - 1 - t)) & 1) {
+            ox |= 1 << pos_of(find_label(lx, B[t]), rx);
+            oy |= 1 << pos_of(find_label(ly, B[t]), ry);
+          }
+        op.tabB[2 * bb] = ox;
+        op.tabB[2 * bb + 1] = oy;
+      }
+    }
     // summed index k: bit t is the t-th lowest summed position in X
     std::sort(S.begin(), S.end(), [&](int a, int b) {
       return pos_of(find_label(lx, a), rx) < pos_of(find_label(lx, b), rx);
@@ -84,10 +109,11 @@ struct Emitter {
       for (int32_t k = 0; k < (1 << hi); ++k) offs(lo, op.nS, k, h[2 * k], h[2 * k + 1]);
     }
     std::vector<int> lz = FX;
+    lz.insert(lz.end(), B.begin(), B.end());
     lz.insert(lz.end(), FY.begin(), FY.end());
     const double e = eb;
-    flops += 8.0 * std::ldexp(1.0, op.nFX + op.nS + op.nFY);
-    bytes += e * (std::ldexp(1.0, op.nFX + op.nS) + std::ldexp(1.0, op.nS + op.nFY) + std::ldexp(1.0, op.nFX + op.nFY));
+    flops += 8.0 * std::ldexp(1.0, op.nFX + op.nB + op.nS + op.nFY);
+    bytes += e * (std::ldexp(1.0, rx) + std::ldexp(1.0, ry) + std::ldexp(1.0, (int)lz.size()));
     int z;
     if (lz.empty() && slot_if_scalar >= 0) {
       op.type = OP_SCALAR;
@@ -105,39 +131,70 @@ struct Emitter {
 
 }  // namespace
 
+// Holders of each wire while tensors merge (leaf ids, then new ids): merging
+// a and b replaces them by the result on every wire the result keeps.
+struct Holders {
+  std::vector<std::vector<int>> h;
+  explicit Holders(const Net &net) : h(net.wire_holders) {}
+  bool held_elsewhere(int w, int a, int b) const {
+    for (int t : h[w])
+      if (t != a && t != b) return true;
+    return false;
+  }
+  // the result takes the place of the first of a, b (dense networks then
+  // keep the endpoint order of an in-place update)
+  void replace(int w, int a, int b, int id, bool keep) {
+    auto &v = h[w];
+    bool placed = false;
+    for (size_t i = 0; i < v.size();) {
+      if (v[i] == a || v[i] == b) {
+        if (keep && !placed) {
+          v[i++] = id;
+          placed = true;
+        } else {
+          v.erase(v.begin() + (long)i);
+        }
+      } else {
+        ++i;
+      }
+    }
+  }
+};
+
 OrderCost order_cost(const Net &net, const std::vector<int> &pi) {
   OrderCost c;
   std::vector<std::vector<int>> tw;
   for (auto &l : net.leaves) tw.push_back(l.wires);
-  auto ends = net.wire_ends;
+  Holders H(net);
   const int wb = net.wire_bits;
   for (int w : pi) {
-    int a = ends[w][0], b = ends[w][1];
-    if (a == b) continue;
-    int shared = 0;
-    std::vector<int> cw;
-    for (int x : tw[a]) {
-      if (std::find(tw[b].begin(), tw[b].end(), x) != tw[b].end()) ++shared;
-      else cw.push_back(x);
+    while (H.h[w].size() >= 2) {
+      const int a = H.h[w][0], b = H.h[w][1];
+      std::vector<int> cw, all;
+      int summed = 0;
+      for (int v : {a, b})
+        for (int x : tw[v]) {
+          if (std::find(all.begin(), all.end(), x) != all.end()) continue;
+          all.push_back(x);
+          const bool shared = std::find(tw[a].begin(), tw[a].end(), x) != tw[a].end() &&
+                              std::find(tw[b].begin(), tw[b].end(), x) != tw[b].end();
+          if (shared && !H.held_elsewhere(x, a, b)) ++summed;
+          else cw.push_back(x);
+        }
+      const int id = (int)tw.size();
+      const int rank = (int)cw.size();
+      c.max_rank_wires = std::max(c.max_rank_wires, rank);
+      c.peak_bits = std::max(c.peak_bits, rank * wb);
+      c.flops += 8.0 * std::ldexp(1.0, wb * (rank + summed));
+      for (int x : all) H.replace(x, a, b, id, std::find(cw.begin(), cw.end(), x) != cw.end());
+      tw.push_back(std::move(cw));
     }
-    for (int x : tw[b])
-      if (std::find(tw[a].begin(), tw[a].end(), x) == tw[a].end()) cw.push_back(x);
-    int id = (int)tw.size();
-    int rank = (int)cw.size();
-    c.max_rank_wires = std::max(c.max_rank_wires, rank);
-    c.peak_bits = std::max(c.peak_bits, rank * wb);
-    c.flops += 8.0 * std::ldexp(1.0, wb * ((int)tw[a].size() + (int)tw[b].size() - shared));
-    for (int v : {a, b})
-      for (int x : tw[v])
-        for (int k = 0; k < 2; ++k)
-          if (ends[x][k] == a || ends[x][k] == b) ends[x][k] = id;
-    tw.push_back(std::move(cw));
   }
   return c;
 }
 
 int compile_plan(const Net &net, const std::vector<int> &pi, bool with_grad, Plan &plan) {
-  const int W = (int)net.wire_ends.size();
+  const int W = (int)net.wire_holders.size();
   if ((int)pi.size() != W) {
     set_error("tn_set_order: order has " + std::to_string(pi.size()) + " entries, network has " + std::to_string(W) + " wires");
     return TN_EORDER;
@@ -169,33 +226,38 @@ int compile_plan(const Net &net, const std::vector<int> &pi, bool with_grad, Pla
       for (int j = 0; j < wb; ++j) lab.push_back(w * wb + j);
     em.new_buf(lab);
   }
-  auto ends = net.wire_ends;
+  Holders H(net);
   double flops = 0, bytes = 0;
   int n_comp = 0;
   for (int w : pi) {
-    int a = ends[w][0], b = ends[w][1];
-    if (a == b) continue;
-    int x = a, y = b;
-    if (plan.buf_bits[b] > plan.buf_bits[a]) std::swap(x, y);
-    // every wire of both operands (shared ones included) now ends at the
-    // result, so later entries of pi for the shared wires are skipped
-    std::vector<int> touched;
-    for (int v : {a, b})
-      for (int l : plan.labels[v]) touched.push_back(l / wb);
-    int z = em.contract(x, y, true, n_comp, flops, bytes);
-    const Op &op = plan.ops.back();
-    plan.step_dims.push_back({op.nFX, op.nS, op.nFY});
-    int zid = z;
-    if (z < 0) {
-      plan.comp_root_step.push_back((int)plan.ops.size() - 1);
-      zid = -2 - n_comp;  // component marker: never a buffer id
-      ++n_comp;
-    } else {
-      plan.peak_bits = std::max(plan.peak_bits, plan.buf_bits[z]);
+    while (H.h[w].size() >= 2) {
+      const int a = H.h[w][0], b = H.h[w][1];
+      int x = a, y = b;
+      if (plan.buf_bits[b] > plan.buf_bits[a]) std::swap(x, y);
+      std::vector<int> touched;
+      for (int v : {a, b})
+        for (int l : plan.labels[v])
+          if (std::find(touched.begin(), touched.end(), l / wb) == touched.end()) touched.push_back(l / wb);
+      // a shared label stays (batch) while another live tensor holds its wire
+      int z = em.contract(x, y, true, n_comp, flops, bytes, [&](int l) { return H.held_elsewhere(l / wb, a, b); });
+      const Op &op = plan.ops.back();
+      plan.step_dims.push_back({op.nFX + op.nB, op.nS, op.nFY});
+      int zid = z;
+      if (z < 0) {
+        plan.comp_root_step.push_back((int)plan.ops.size() - 1);
+        zid = -2 - n_comp;  // component marker: never a buffer id
+        ++n_comp;
+      } else {
+        plan.peak_bits = std::max(plan.peak_bits, plan.buf_bits[z]);
+      }
+      for (int wire : touched) {
+        bool kept = false;
+        if (z >= 0)
+          for (int l : plan.labels[z])
+            if (l / wb == wire) kept = true;
+        H.replace(wire, a, b, zid, kept);
+      }
     }
-    for (int wire : touched)
-      for (int k = 0; k < 2; ++k)
-        if (ends[wire][k] == a || ends[wire][k] == b) ends[wire][k] = zid;
   }
   if (n_comp == 0 && L > 0) {
     set_error("tn_set_order: order leaves no scalar (internal)");
@@ -279,13 +341,16 @@ int compile_plan(const Net &net, const std::vector<int> &pi, bool with_grad, Pla
     const Op fop = plan.ops[i];  // copy: ops grows below
     if (fop.type == OP_CONTRACT && !needs[fop.z]) continue;  // no parameter below this result
     int zbar = fop.type == OP_SCALAR ? plan.seed_buf[fop.z] : adj.at(fop.z);
+    // adjoints keep the batch labels of the forward step: exactly the shared
+    // labels that belong to the operand whose adjoint is formed
+    const std::vector<int> lx = plan.labels[fop.x], ly = plan.labels[fop.y];
     if (needs[fop.x]) {
-      int xb = em.contract(zbar, fop.y, false, -1, gflops, gbytes);
+      int xb = em.contract(zbar, fop.y, false, -1, gflops, gbytes, [&](int l) { return find_label(lx, l) >= 0; });
       adj[fop.x] = xb;
       if (fop.x < L) leafgrad(fop.x, xb);
     }
     if (needs[fop.y]) {
-      int yb = em.contract(fop.x, zbar, false, -1, gflops, gbytes);
+      int yb = em.contract(fop.x, zbar, false, -1, gflops, gbytes, [&](int l) { return find_label(ly, l) >= 0; });
       adj[fop.y] = yb;
       if (fop.y < L) leafgrad(fop.y, yb);
     }

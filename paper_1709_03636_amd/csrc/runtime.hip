@@ -27,7 +27,7 @@ hipError_t launch_combine(const double *val, const double *gnet, const double *c
                           int n_sets, int n_params, double *obj, double *grad, hipStream_t st);
 hipError_t launch_bind(int dtype, const DParam *slots, int n_slots, const double *params, int n_params, int n_sets,
                        int per_set, void *G, void *dG, hipStream_t st);
-hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tab, int mfma, hipStream_t st);
+hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tabs, int mfma, hipStream_t st);
 bool mfma_eligible(int dtype, const DOp &op);
 hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, int prec, hipStream_t st);
 hipError_t level_setup(int dtype, const LevelArgs &a, const void *consts, int n_const, const DParam *pt, int n_pt,
@@ -189,13 +189,14 @@ struct LevelNet {
 };
 
 static int slot_for(HostProgram &hp, const ParamTensor &pt) {
-  auto key = std::make_tuple(pt.kind, pt.param, pt.coeff, pt.folded);
+  auto key = std::make_tuple(pt.kind, pt.param, pt.coeff, pt.folded + 2 * pt.diag);
   auto it = hp.slot_of.find(key);
   if (it != hp.slot_of.end()) return it->second;
   DParam s{};
   s.kind = pt.kind;
   s.param = pt.param;
   s.folded = pt.folded;
+  s.diag = pt.diag;
   s.bits = pt.bits;
   s.off = hp.per_set;
   s.coeff = pt.coeff;
@@ -229,8 +230,11 @@ static void emit_ops(const Plan &p, int n_ops, HostProgram &hp, BOff boff, LG le
     d.nFY = op.nFY;
     d.maskX = op.maskX_F;
     d.maskY = op.maskY_F;
+    d.nB = op.nB;
     d.tab = (int32_t)hp.tabs.size();
     hp.tabs.insert(hp.tabs.end(), op.tab.begin(), op.tab.end());
+    d.tabB = (int32_t)hp.tabs.size();
+    hp.tabs.insert(hp.tabs.end(), op.tabB.begin(), op.tabB.end());
     if (op.type == OP_CONTRACT) {
       d.x = boff(op.x);
       d.y = boff(op.y);
@@ -267,6 +271,19 @@ static uint32_t host_pdep(uint32_t v, uint32_t mask) {
   return out;
 }
 
+// Operand offsets (X, Y) of output c of a contraction: c = (i, b, j) with i
+// the X-only bits, b the batch bits (offset table), j the Y-only bits.
+static void out_offsets(const HostProgram &loc, const DOp &op, uint32_t c, int32_t &ox, int32_t &oy) {
+  const uint32_t rest = c >> op.nFY;
+  ox = op.x + (int32_t)host_pdep(rest >> op.nB, op.maskX);
+  oy = op.y + (int32_t)host_pdep(c & ((1u << op.nFY) - 1u), op.maskY);
+  if (op.nB) {
+    const uint32_t b = rest & ((1u << op.nB) - 1u);
+    ox += loc.tabs[op.tabB + 2 * b];
+    oy += loc.tabs[op.tabB + 2 * b + 1];
+  }
+}
+
 // Lane records (see kRecLanes) of ops [first, first + n) of `loc`;
 // `pt` are the network's parametric tensors (for leaf-gradient ops).
 static void build_records(const HostProgram &loc, const std::vector<DParam> &pt, int first, int n,
@@ -274,13 +291,9 @@ static void build_records(const HostProgram &loc, const std::vector<DParam> &pt,
   auto pack = [](int32_t a, int32_t b) { return (a & 0xffff) | (b << 16); };
   for (int o = first; o < first + n; ++o) {
     const DOp &op = loc.ops[o];
-    const int lgOut = op.nFX + op.nFY;
-    const uint32_t maskJ = (1u << op.nFY) - 1u;
+    const int lgOut = op.nFX + op.nB + op.nFY;
     // LDS offsets of output c's X and Y rows
-    auto offs = [&](uint32_t c, int32_t &ox, int32_t &oy) {
-      ox = op.x + (int32_t)host_pdep(c >> op.nFY, op.maskX);
-      oy = op.y + (int32_t)host_pdep(c & maskJ, op.maskY);
-    };
+    auto offs = [&](uint32_t c, int32_t &ox, int32_t &oy) { out_offsets(loc, op, c, ox, oy); };
     // (X, Y) offsets of summed entry k (tables of at most 2^12 entries)
     auto tab = [&](int k, int32_t &tx, int32_t &ty) {
       tx = loc.tabs[op.tab + 2 * k];
@@ -400,11 +413,7 @@ static bool build_set_records(const HostProgram &loc, const std::vector<DParam> 
   bool all = true;
   for (const DOp &op : loc.ops) {
     std::vector<std::array<int32_t, 4>> f(W, std::array<int32_t, 4>{0, 0, 0, 0});
-    const uint32_t maskJ = (1u << op.nFY) - 1u;
-    auto offs = [&](uint32_t c, int32_t &ox, int32_t &oy) {
-      ox = op.x + (int32_t)host_pdep(c >> op.nFY, op.maskX);
-      oy = op.y + (int32_t)host_pdep(c & maskJ, op.maskY);
-    };
+    auto offs = [&](uint32_t c, int32_t &ox, int32_t &oy) { out_offsets(loc, op, c, ox, oy); };
     auto tab = [&](int k, int32_t &tx, int32_t &ty) {
       tx = loc.tabs[op.tab + 2 * k];
       ty = loc.tabs[op.tab + 2 * k + 1];
@@ -423,7 +432,7 @@ static bool build_set_records(const HostProgram &loc, const std::vector<DParam> 
     };
     int type = 0, lgG = 0, lgQ = 0, lgR = 0, lgOut = 0, zf = 0;
     if (op.type == OP_CONTRACT && op.nS <= 12) {
-      lgOut = op.nFX + op.nFY;
+      lgOut = op.nFX + op.nB + op.nFY;
       lgG = lgOut >= lgW ? 0 : std::min(std::min(lgW - lgOut, op.nS), lgGmax);
       lgQ = std::max(0, lgOut - lgW);
       lgR = op.nS - lgG;
@@ -526,6 +535,7 @@ static void append_fused(const Net &net, const NetLayout &lay, HostProgram &hp) 
     d.kind = pt.kind;
     d.param = pt.param;
     d.folded = pt.folded;
+    d.diag = pt.diag;
     d.bits = pt.bits;
     d.off = (int32_t)lay.poff[t];
     d.goff = (int32_t)(lay.poff[t] - lay.n_const);
@@ -566,6 +576,7 @@ static void append_fused(const Net &net, const NetLayout &lay, HostProgram &hp) 
   const int const_begin = (int)(hp.consts.size() / 2);
   for (DOp d : loc.ops) {
     d.tab += tab0;
+    d.tabB += tab0;
     if (d.type == OP_LEAFGRAD) d.aux0 += ptens_begin;
     hp.ops.push_back(d);
   }
@@ -616,6 +627,7 @@ static LevelNet append_level(const Net &net, const NetLayout &lay, HostProgram &
     d.kind = pt.kind;
     d.param = pt.param;
     d.folded = pt.folded;
+    d.diag = pt.diag;
     d.bits = pt.bits;
     d.off = (int32_t)lay.poff[t];
     d.goff = (int32_t)(ln.gbar_begin + lay.poff[t] - lay.n_const);
@@ -1047,7 +1059,7 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
         const DOp &op = b->hp.ops[ln.op_begin[v] + o];
         auto it = b->use_mfma.find(shape_class(b->dtype, op, b->mfma_prec));
         const bool mf = it == b->use_mfma.end() || it->second;
-        e = level_op(b->dtype, la, op, b->d_tabs + op.tab, mf ? b->mfma_prec : 0, st);
+        e = level_op(b->dtype, la, op, b->d_tabs, mf ? b->mfma_prec : 0, st);
       }
       if (e == hipSuccess)
         e = level_finish(b->dtype, la, b->d_ptens + ln.ptens_begin, ln.n_ptens, b->d_dbound, b->hp.per_set, s0, ln.net,
@@ -1272,7 +1284,7 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
     // more complex multiply-adds): the matrix cores win by orders of magnitude
     float t_thin = 1e30f;
     if (op.nFX + op.nS + op.nFY < 30)
-      t_thin = time_ms(st, reps, [&] { return level_op(b->dtype, la, op, b->d_tabs + op.tab, 0, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rc2);
+      t_thin = time_ms(st, reps, [&] { return level_op(b->dtype, la, op, b->d_tabs, 0, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rc2);
     (void)hipFree(buf);
     if (rc1 != TN_OK || rc2 != TN_OK) {
       b->poisoned = true;
@@ -1466,6 +1478,7 @@ int net_bind(Net &net, const double *params, int n_sets, void *dst, int64_t *per
     d.kind = pt.kind;
     d.param = pt.param;
     d.folded = pt.folded;
+    d.diag = pt.diag;
     d.bits = pt.bits;
     d.off = (int32_t)total;
     d.coeff = pt.coeff;

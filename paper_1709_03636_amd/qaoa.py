@@ -124,11 +124,13 @@ def edge_lightcone_circuit(n, edges, p, edge, noise=None):
     return m, gates
 
 
-def edge_network(n, edges, p, edge, dtype=qtn.TN_C64, lightcone=True, noise=None):
+def edge_network(n, edges, p, edge, dtype=qtn.TN_C64, lightcone=True, noise=None, diagonal=False):
     """Folded network of <Z_u Z_v>. With lightcone=True it is built on the
     edge's canonically relabelled light-cone circuit; with lightcone=False it
     is the whole circuit (trace on every other qubit). noise: Kraus operators
-    of a trace-preserving one-qubit channel after every gate (or None)."""
+    of a trace-preserving one-qubit channel after every gate (or None).
+    diagonal: the ZZ gates become 16-entry tensors on hyperedge wires
+    (tn_target.diagonal) instead of dense 256-entry superoperators."""
     if lightcone:
         m, gates = edge_lightcone_circuit(n, edges, p, edge, noise)
         pauli = [3, 3] + [0] * (m - 2)
@@ -138,14 +140,15 @@ def edge_network(n, edges, p, edge, dtype=qtn.TN_C64, lightcone=True, noise=None
         pauli[edge[0]] = pauli[edge[1]] = 3
     init = np.array([complex(PLUS[0], PLUS[1]), complex(PLUS[2], PLUS[3])] * m)
     return qtn.Network(m, gates, qtn.TN_EXPECTATION, pauli, n_params=2 * p, init=init, dtype=dtype,
-                       lightcone=lightcone)
+                       lightcone=lightcone, diagonal=diagonal)
 
 
-def edge_networks(n, edges, p, dtype=qtn.TN_C64, order="stochastic", seed=0, trials=8, lightcone=True, noise=None):
+def edge_networks(n, edges, p, dtype=qtn.TN_C64, order="stochastic", seed=0, trials=8, lightcone=True, noise=None,
+                  diagonal=False):
     """One network per edge with its contraction order set."""
     nets = []
     for e in edges:
-        net = edge_network(n, edges, p, e, dtype, lightcone, noise)
+        net = edge_network(n, edges, p, e, dtype, lightcone, noise, diagonal)
         if order == "stochastic":
             pi = net.order_stochastic(seed)
         elif order == "linegraph":
@@ -160,9 +163,10 @@ def edge_networks(n, edges, p, dtype=qtn.TN_C64, order="stochastic", seed=0, tri
 class MaxCut:
     """<C>(params) and its gradient for many parameter vectors at once."""
 
-    def __init__(self, n, edges, p, dtype=qtn.TN_C64, order="stochastic", seed=0, max_sets=64, trials=8, noise=None):
+    def __init__(self, n, edges, p, dtype=qtn.TN_C64, order="stochastic", seed=0, max_sets=64, trials=8, noise=None,
+                 diagonal=False):
         self.n, self.edges, self.p = n, list(edges), p
-        self.nets = edge_networks(n, edges, p, dtype, order, seed, trials, noise=noise)
+        self.nets = edge_networks(n, edges, p, dtype, order, seed, trials, noise=noise, diagonal=diagonal)
         m = len(self.edges)
         self.batch = qtn.Batch(self.nets, coef=[-0.5] * m, offset=0.5 * m, max_sets=max_sets)
 

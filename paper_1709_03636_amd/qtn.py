@@ -37,7 +37,8 @@ class tn_gate(ctypes.Structure):
 
 class tn_target(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("bits", ctypes.POINTER(ctypes.c_uint8)),
-                ("pauli", ctypes.POINTER(ctypes.c_uint8)), ("lightcone", ctypes.c_int32)]
+                ("pauli", ctypes.POINTER(ctypes.c_uint8)), ("lightcone", ctypes.c_int32),
+                ("diagonal", ctypes.c_int32)]
 
 
 class tn_plan_stats(ctypes.Structure):
@@ -143,10 +144,11 @@ def make_gates(gates):
 class Network:
     """A built network (tn_build) with an optional order (tn_set_order)."""
 
-    def __init__(self, n_qubits, gates, mode, target, n_params=0, init=None, dtype=TN_C64, lightcone=True):
+    def __init__(self, n_qubits, gates, mode, target, n_params=0, init=None, dtype=TN_C64, lightcone=True,
+                 diagonal=False):
         garr, keep = make_gates(gates)
         tv = np.ascontiguousarray(np.asarray(target, dtype=np.uint8))
-        t = tn_target(mode, None, None, 1 if lightcone else 0)
+        t = tn_target(mode, None, None, 1 if lightcone else 0, 1 if diagonal else 0)
         if mode == TN_EXPECTATION:
             t.pauli = tv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
         else:

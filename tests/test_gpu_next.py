@@ -257,3 +257,170 @@ def test_noisy_qaoa_maxcut_matches_density_oracle():
         ref = sum((1 - density.expect_pauli(rho, [3 if q in (u, v) else 0 for q in range(n)]).real) / 2
                   for u, v in e)
         assert abs(obj[s] - ref) < 1e-10 * len(e)
+
+
+# --- diagonal gates as hyperedge tensors (tn_target.diagonal) --------------------------------
+
+def _diag_circuit(n, seed):
+    """Seeded circuit (RZ, ZZ, CZ, Z among the generic gates) plus explicit
+    diagonal one- and two-qubit custom gates; returns (product gates, oracle
+    apply(params) -> state, params)."""
+    from helpers import random_param_circuit
+    from oracle import gates as og, statevector
+    prod, ogates, params = random_param_circuit(n, 36, seed)
+    rng = np.random.default_rng(seed + 300)
+    extra = []
+    for _ in range(4):
+        q = int(rng.integers(0, n))
+        extra.append(("U1", q, -1, np.diag(np.exp(1j * rng.uniform(0, 2 * np.pi, 2)))))
+        q0, q1 = rng.choice(n, 2, replace=False)
+        extra.append(("U2", int(q0), int(q1), np.diag(np.exp(1j * rng.uniform(0, 2 * np.pi, 4)))))
+    # interleave: one extra gate after every 4 generic gates
+    prod_all, order = [], []
+    for i, g in enumerate(prod):
+        prod_all.append(g)
+        order.append(("g", i))
+        if i % 4 == 3 and i // 4 < len(extra):
+            k, q0, q1, M = extra[i // 4]
+            prod_all.append((k, q0, q1, -1, 0.0, M))
+            order.append(("x", i // 4))
+
+    def state(prm):
+        gl = ogates(prm)
+        psi = statevector.zero_state(n)
+        for kind, idx in order:
+            if kind == "g":
+                k, q0, q1, th, ms = gl[idx]
+                U = og.gate_matrix(k, th, ms)
+            else:
+                k, q0, q1, U = extra[idx]
+            psi = statevector.apply_1q(psi, U, q0) if q1 < 0 else statevector.apply_2q(psi, U, q0, q1)
+        return psi
+
+    return prod_all, state, params
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_diagonal_mode_random_circuits_all_modes(seed):
+    from oracle import statevector
+    _, _, qtn = _mods()
+    n = 6
+    prod, state, params = _diag_circuit(n, seed)
+    psi = state(params)
+    rng = np.random.default_rng(seed + 7)
+    pauli = [int(x) for x in rng.integers(0, 4, size=n)]
+    bits_p = [int(x) for x in rng.integers(0, 3, size=n)]
+    bits_a = [int(x) for x in rng.integers(0, 2, size=n)]
+    prob = np.abs(psi) ** 2
+    for q in reversed(range(n)):
+        prob = prob.sum(axis=q) if bits_p[q] == 2 else np.take(prob, bits_p[q], axis=q)
+    cases = ((qtn.TN_EXPECTATION, pauli, statevector.expect_pauli(psi, pauli)),
+             (qtn.TN_PROBABILITY, bits_p, float(prob)),
+             (qtn.TN_AMPLITUDE, bits_a, psi[tuple(bits_a)]))
+    for mode, target, ref in cases:
+        dense = qtn.Network(n, prod, mode, target, n_params=3, dtype=qtn.TN_C128)
+        diag = qtn.Network(n, prod, mode, target, n_params=3, dtype=qtn.TN_C128, diagonal=True)
+        assert diag.wires()[0] < dense.wires()[0]  # diagonal gates add no wires
+        for net in (diag,):
+            for pi in (net.order_stochastic(seed), net.order_linegraph(trials=4, seed=seed)):
+                _say(f"diagonal seed={seed} mode={mode}")
+                net.set_order(pi)
+                v = net.contract(params)
+                assert abs(v - ref) <= 1e-12 * max(1.0, abs(ref)), (mode, v, ref)
+
+
+def test_diagonal_mode_gradient_matches_finite_differences():
+    from oracle import statevector
+    _, _, qtn = _mods()
+    n = 6
+    prod, state, params = _diag_circuit(n, 5)
+    pauli = [3, 0, 1, 3, 2, 0]
+    net = qtn.Network(n, prod, qtn.TN_EXPECTATION, pauli, n_params=3, dtype=qtn.TN_C128, diagonal=True)
+    net.set_order(net.order_linegraph(trials=4, seed=0))
+    _say("diagonal gradient c128")
+    val, g = net.grad(params)
+
+    def f(prm):
+        return statevector.expect_pauli(state(prm), pauli).real
+
+    h = 1e-5
+    fd = np.array([(f(params + h * np.eye(3)[i]) - f(params - h * np.eye(3)[i])) / (2 * h) for i in range(3)])
+    assert abs(val - f(params)) < 1e-12
+    np.testing.assert_allclose(g, fd, atol=1e-8)
+
+
+@pytest.mark.parametrize("cfg", ["records", "sets", "block128", "block256", "level"])
+def test_diagonal_qaoa_batch_every_executor(cfg, monkeypatch):
+    """Hyperedge (batch-label) steps through every executor: 64-lane lane
+    records, set-packed records, the descriptor path at 128/256 lanes and the
+    level executor; p=1 values and gradients against the closed form."""
+    from oracle import closed_form
+    _, qaoa, qtn = _mods()
+    env = {"records": {"QTN_SETS_PER_WAVE": "1", "QTN_FUSED_BLOCK": "64"},
+           "sets": {"QTN_SETS_PER_WAVE": "4", "QTN_FUSED_BLOCK": "64"},
+           "block128": {"QTN_SETS_PER_WAVE": "1", "QTN_FUSED_BLOCK": "128"},
+           "block256": {"QTN_SETS_PER_WAVE": "1", "QTN_FUSED_BLOCK": "256"},
+           "level": {"QTN_FUSED_LDS_MAX": "0"}}[cfg]
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    n, d = 20, 3
+    e = workloads.random_regular_graph(d, n, 3)
+    S = 6
+    ang = workloads.qaoa_angles(4, S, 1)
+    for dt, tol, gtol in ((qtn.TN_C128, 1e-12, 1e-10), (qtn.TN_C64, 1e-5, 1e-4)):
+        _say(f"diagonal QAOA batch {cfg} dtype={dt}")
+        model = qaoa.MaxCut(n, e, 1, dt, order="linegraph", max_sets=S, diagonal=True)
+        info = model.batch.info()
+        if cfg == "level":
+            assert info["n_level"] == len(e)
+        out = torch.empty((len(e), S, 2), dtype=torch.float64, device="cuda")
+        obj, grad = model.value_and_grad(torch.tensor(ang, dtype=torch.float64, device="cuda"), out=out)
+        torch.cuda.synchronize()
+        o, grad = out.cpu().numpy(), grad.cpu().numpy()
+        for s in range(S):
+            zz = closed_form.zz_p1(n, e, ang[s][0], ang[s][1])
+            assert np.max(np.abs(o[:, s, 0] - zz)) < tol
+            dg, db = closed_form.zz_p1_grad(n, e, ang[s][0], ang[s][1])
+            g_ref = np.array([-0.5 * dg.sum(), -0.5 * db.sum()])
+            assert np.max(np.abs(grad[s] - g_ref)) <= gtol * max(1, np.abs(g_ref).max())
+
+
+def test_diagonal_qaoa_p2_matches_statevector():
+    _, qaoa, qtn = _mods()
+    n = 12
+    e = workloads.random_regular_graph(3, n, 6)
+    S = 3
+    ang = workloads.qaoa_angles(8, S, 2)
+    _say("diagonal QAOA p=2")
+    model = qaoa.MaxCut(n, e, 2, qtn.TN_C128, order="stochastic", max_sets=S, diagonal=True)
+    obj, grad = model.value_and_grad(torch.tensor(ang, dtype=torch.float64, device="cuda"))
+    obj, grad = obj.cpu().numpy(), grad.cpu().numpy()
+    for s in range(S):
+        ref = gradients.cost(n, e, list(ang[s]))
+        ps = gradients.parameter_shift(n, e, list(ang[s]))
+        assert abs(obj[s] - ref) < 1e-11
+        np.testing.assert_allclose(grad[s], ps, atol=1e-10)
+
+
+def test_diagonal_mode_with_noise():
+    from oracle import density, gates as og, statevector
+    from paper_1709_03636_amd import noise
+    _, qaoa, qtn = _mods()
+    n = 8
+    e = workloads.random_regular_graph(3, n, 2)
+    K = noise.amplitude_damping(0.07)
+    ang = workloads.qaoa_angles(9, 2, 1)
+    _say("diagonal + noise")
+    model = qaoa.MaxCut(n, e, 1, qtn.TN_C128, order="linegraph", max_sets=2, noise=K, diagonal=True)
+    obj = model.expectation(torch.tensor(ang, dtype=torch.float64, device="cuda")).cpu().numpy()
+    for s in range(2):
+        gam, bet = ang[s]
+        ops = [([og.gate_matrix("H")], [q]) for q in range(n)]
+        for u, v in e:
+            ops += [([og.zz(2 * gam)], [u, v]), (K, [u]), (K, [v])]
+        for q in range(n):
+            ops += [([og.rot(og.X, 2 * bet)], [q]), (K, [q])]
+        rho = density.run(n, ops, density.pure(statevector.zero_state(n)))
+        ref = sum((1 - density.expect_pauli(rho, [3 if q in (u, v) else 0 for q in range(n)]).real) / 2
+                  for u, v in e)
+        assert abs(obj[s] - ref) < 1e-10 * len(e)

@@ -282,3 +282,26 @@ def test_qaoa_edge_lightcone_circuits_are_exact(qaoa, noisy):
         m, g = qaoa.edge_lightcone_circuit(n, e, p, (u, v), K)
         lc = density.expect_pauli(density.run(m, ops_of(g), plus(m)), [3, 3] + [0] * (m - 2)).real
         assert abs(full - lc) < 1e-13
+
+
+def test_diagonal_mode_hyperedges_and_orders(qtn, qaoa):
+    """Diagonal gates keep their wires: fewer wires, some held by more than
+    two tensors; both order schemes return permutations, plans compile
+    (forward and adjoint) and need fewer flops than the dense network."""
+    e = workloads.random_regular_graph(3, 16, 1)
+    dense = qaoa.edge_network(16, e, 2, e[0])
+    diag = qaoa.edge_network(16, e, 2, e[0], diagonal=True)
+    nw_d, nt_d, _ = dense.wires()
+    nw, nt, ends = diag.wires()
+    assert nt == nt_d and nw < nw_d
+    for net in (dense, diag):
+        for pi in (net.order_stochastic(3), net.order_linegraph(trials=3, seed=3)):
+            assert sorted(pi.tolist()) == list(range(net.n_wires))
+    dense.set_order(dense.order_linegraph(trials=4, seed=0))
+    diag.set_order(diag.order_linegraph(trials=4, seed=0))
+    a, b = dense.plan_info(), diag.plan_info()
+    assert b["flops"] < a["flops"] / 4 and b["peak_bits"] <= a["peak_bits"]
+    # ZZ leaves are 16-entry diagonals on existing wires: every wire of a ZZ leaf
+    # also belongs to at least two other tensors
+    steps = diag.plan_steps()
+    assert len(steps) == b["n_steps"]
