@@ -199,6 +199,62 @@ def next_rows(model, params, edges, st, dev):
         "fwd_grad_networks_per_s": len(edges) * N_SETS / (ms * 1e-3), "ms_per_pass": ms,
         "fused_kernel_us": k_ms / max(1, n_t) * 1e3, "n_programs": ninfo["n_programs"]}
     log(f"noise: {res['noise']}")
+
+    # diagonal gates as hyperedge tensors: the headline batch, and whole-circuit networks
+    from oracle import closed_form
+    dm = qaoa.MaxCut(N_VERT, edges, P_LAYERS, qtn.TN_C64, order="linegraph", max_sets=N_SETS, trials=4,
+                     diagonal=True)
+    dm.batch.autotune(params, reps=10, stream=st)
+    out = torch.empty((len(edges), N_SETS, 2), dtype=torch.float64, device=dev)
+    obj = torch.empty(N_SETS, dtype=torch.float64, device=dev)
+    grad = torch.empty((N_SETS, 2 * P_LAYERS), dtype=torch.float64, device=dev)
+    dm.batch.grad(params, out=out, obj=obj, grad=grad, stream=st)
+    st.synchronize()
+    ang = params.cpu().numpy()
+    err = max(float(np.max(np.abs(out[:, s, 0].cpu().numpy() - closed_form.zz_p1(N_VERT, edges, *ang[s]))))
+              for s in range(N_SETS))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    timed = {}
+    for wg in (True, False):
+        for _ in range(5):
+            dm.batch.run_graph(wg, params, obj=obj, grad=grad if wg else None, stream=st)
+        ev0.record(st)
+        for _ in range(50):
+            dm.batch.run_graph(wg, params, obj=obj, grad=grad if wg else None, stream=st)
+        ev1.record(st)
+        torch.cuda.synchronize()
+        timed[wg] = ev0.elapsed_time(ev1) / 50
+    dm.batch.kernel_timing(True)
+    for _ in range(20):
+        dm.batch.grad(params, stream=st)
+    n_t, k_ms = dm.batch.kernel_time()
+    dm.batch.kernel_timing(False)
+    dinfo = dm.batch.info()
+    whole = {}
+    for dd, dn in ((6, 20), (6, 30)):
+        de = workloads.random_regular_graph(dd, dn, GRAPH_SEED)
+        net = qaoa.edge_network(dn, de, 1, de[0], dtype=qtn.TN_C64, lightcone=False, diagonal=True)
+        net.set_order(net.order_linegraph(trials=8, seed=0))
+        pinfo = net.plan_info()
+        a0 = ang[0]
+        v = net.contract(a0, stream=st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            v = net.contract(a0, stream=st)
+        ms = (time.perf_counter() - t0) / 3 * 1e3
+        whole[f"d{dd}_n{dn}"] = {"peak_bits": pinfo["peak_bits"], "flops": pinfo["flops"], "bytes": pinfo["bytes"],
+                                 "ms_per_contraction": ms,
+                                 "abs_err_zz_vs_closed_form": abs(v.real - closed_form.zz_p1(dn, de, *a0)[0])}
+    res["diagonal"] = {
+        "workload": "the headline batch with ZZ gates as 16-entry diagonal tensors on hyperedge wires "
+                    "(exact; the paper keeps gates dense), complex64",
+        "fwd_grad_networks_per_s": len(edges) * N_SETS / (timed[True] * 1e-3), "ms_per_step": timed[True],
+        "fwd_networks_per_s": len(edges) * N_SETS / (timed[False] * 1e-3), "ms_per_step_fwd": timed[False],
+        "fused_kernel_us": k_ms / max(1, n_t) * 1e3, "max_abs_err_zz": err,
+        "flops_fwd_per_set": dinfo["flops_fwd"], "bytes_fwd_per_set": dinfo["bytes_fwd"],
+        "whole_circuit_one_edge": whole}
+    log(f"diagonal: {res['diagonal']}")
     return res
 
 

@@ -44,6 +44,7 @@ static constexpr int64_t kFusedLdsMax = 64 * 1024;
 // Global-memory arena budget of the level executor (parameter vectors are
 // processed in chunks that fit).
 static constexpr int64_t kLevelBudget = 8ll << 30;
+static constexpr int64_t kMaxArenaElems = int64_t(1) << 31;  // 32-bit element offsets per set
 
 // First-fit arena allocator over element offsets.
 struct Arena {
@@ -186,6 +187,7 @@ struct LevelNet {
   int ptens_begin = 0, n_ptens = 0;             // into HostProgram::ptens (absolute offsets)
   int64_t gbar_begin = 0, ptens_elems = 0;      // adjoint accumulators (variant 1)
   int chunk = 1;                                // parameter vectors per pass
+  bool grad_ok = true;                          // the adjoint arena is addressable (< 2^31 elements)
 };
 
 static int slot_for(HostProgram &hp, const ParamTensor &pt) {
@@ -646,7 +648,10 @@ static LevelNet append_level(const Net &net, const NetLayout &lay, HostProgram &
           d.aux1 = op.aux1;
         });
   }
-  int64_t per = ln.stride[1] * eb;
+  // element offsets inside a set's arena are 32-bit: an adjoint arena past
+  // 2^31 elements leaves the network usable for forward passes only
+  ln.grad_ok = ln.stride[1] < kMaxArenaElems;
+  int64_t per = ln.stride[ln.grad_ok ? 1 : 0] * eb;
   ln.chunk = (int)std::max<int64_t>(1, std::min<int64_t>(max_sets, budget_bytes / std::max<int64_t>(1, per)));
   return ln;
 }
@@ -863,6 +868,11 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
       b->hp.nets_fwd.push_back(DNet{});
       b->hp.nets_grad.push_back(DNet{});
       b->level.push_back(append_level(*n, lay, b->hp, i, eb, kLevelBudget, max_sets));
+      if (b->level.back().stride[0] >= kMaxArenaElems) {
+        set_error("tn_batch_create: network " + std::to_string(i) + " needs " + std::to_string(b->level.back().stride[0]) +
+                  " elements of working memory per parameter vector; the executor addresses at most 2^31");
+        return TN_ENOMEM;
+      }
     }
   }
   // fused networks, expensive first (longest processing time first)
@@ -919,7 +929,7 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   {
     int64_t arena = 0, scal = 0, part = 0;
     for (auto &ln : b->level) {
-      arena = std::max(arena, ln.stride[1] * ln.chunk * eb);
+      arena = std::max(arena, ln.stride[ln.grad_ok ? 1 : 0] * ln.chunk * eb);
       scal = std::max(scal, (int64_t)ln.chunk * std::max(1, ln.n_comp) * 2);
       part = std::max(part, (int64_t)ln.chunk * kScalarParts * 2);
     }
@@ -973,6 +983,13 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     set_error("batch run: n_sets out of range or params NULL");
     return TN_EINVAL;
   }
+  if (grad)
+    for (const LevelNet &ln : b->level)
+      if (!ln.grad_ok) {
+        set_error("batch gradient: network " + std::to_string(ln.net) +
+                  " needs more than 2^31 elements of adjoint working memory per parameter vector");
+        return TN_ENOMEM;
+      }
   const int v = grad ? 1 : 0;
   FusedArgs a{};
   a.nets = grad ? b->d_nets_grad : b->d_nets_fwd;

@@ -424,3 +424,22 @@ def test_diagonal_mode_with_noise():
         ref = sum((1 - density.expect_pauli(rho, [3 if q in (u, v) else 0 for q in range(n)]).real) / 2
                   for u, v in e)
         assert abs(obj[s] - ref) < 1e-10 * len(e)
+
+
+def test_diagonal_whole_circuit_6regular_n30():
+    """The dense regime's whole-circuit network of one edge (6-regular, n=30,
+    p=1, trace on every other qubit): with dense gates its orders need
+    intermediates of 2^42 entries or more; in diagonal mode the line-graph
+    order peaks at 2^28. Its value against the p=1 closed form."""
+    from oracle import closed_form
+    _, qaoa, qtn = _mods()
+    n = 30
+    e = workloads.random_regular_graph(6, n, 0)
+    net = qaoa.edge_network(n, e, 1, e[0], dtype=qtn.TN_C64, lightcone=False, diagonal=True)
+    net.set_order(net.order_linegraph(trials=8, seed=0))
+    assert net.plan_info()["peak_bits"] <= 28
+    gam, bet = 0.31, -0.52
+    _say("whole circuit 6-regular n=30 diagonal")
+    v = net.contract([gam, bet])
+    ref = closed_form.zz_p1(n, e, gam, bet)[0]
+    assert abs(v.real - ref) < 1e-5 and abs(v.imag) < 1e-5
