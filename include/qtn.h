@@ -187,7 +187,7 @@ int tn_batch_create(tn_net *const *nets, int32_t n_nets, const double *coef, dou
                     int32_t max_sets, tn_batch **out);
 
 /* Forward pass over n_sets parameter vectors. Device pointers:
- *   params: n_sets x n_params doubles;
+ *   params: n_sets x n_params doubles (may be NULL when n_params = 0);
  *   out:    n_nets x n_sets complex scalars (2 doubles each, network-major), may be NULL;
  *   obj:    n_sets doubles (combined objective), may be NULL.
  * Asynchronous on `stream`; capturable in a HIP graph. */

@@ -979,7 +979,7 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     set_error("batch poisoned by an earlier device error");
     return TN_ESTATE;
   }
-  if (!params || n_sets < 1 || n_sets > b->max_sets) {
+  if ((!params && b->n_params > 0) || n_sets < 1 || n_sets > b->max_sets) {
     set_error("batch run: n_sets out of range or params NULL");
     return TN_EINVAL;
   }
@@ -1213,7 +1213,7 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
     set_error("batch poisoned by an earlier device error");
     return TN_ESTATE;
   }
-  if (!params || n_sets < 1 || n_sets > b->max_sets) {
+  if ((!params && b->n_params > 0) || n_sets < 1 || n_sets > b->max_sets) {
     set_error("tn_batch_autotune: n_sets out of range or params NULL");
     return TN_EINVAL;
   }

@@ -443,3 +443,91 @@ def test_diagonal_whole_circuit_6regular_n30():
     v = net.contract([gam, bet])
     ref = closed_form.zz_p1(n, e, gam, bet)[0]
     assert abs(v.real - ref) < 1e-5 and abs(v.imag) < 1e-5
+
+
+# --- degenerate cases ----------------------------------------------------------------------
+
+def test_circuits_without_gates_and_single_qubits():
+    """No gates at all (the network is the initial state against the
+    measurement) and one-qubit circuits, in every mode and both orders."""
+    _, _, qtn = _mods()
+    rng = np.random.default_rng(11)
+    for n in (1, 3):
+        v = rng.normal(size=(n, 2)) + 1j * rng.normal(size=(n, 2))
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        init = v.reshape(-1)
+        for gates_ in ([], [("H", 0, -1, -1, 0.0), ("RY", 0, -1, 0, 0.7)]):
+            psi = v[0]
+            if gates_:
+                from oracle import gates as og
+                psi = og.rot(og.Y, 0.7 * 0.3) @ (og.H @ v[0])
+            full = [psi] + [v[q] for q in range(1, n)]
+            X = np.array([[0, 1], [1, 0]])
+            Z = np.diag([1.0, -1.0])
+            exp_ref = np.prod([np.vdot(full[q], (Z if q == 0 else X) @ full[q]) for q in range(n)])
+            prob_ref = abs(full[0][1]) ** 2 * np.prod([abs(full[q][0]) ** 2 for q in range(1, n)])
+            amp_ref = full[0][1] * np.prod([full[q][0] for q in range(1, n)])
+            cases = ((qtn.TN_EXPECTATION, [3] + [1] * (n - 1), exp_ref), (qtn.TN_PROBABILITY, [1] + [0] * (n - 1), prob_ref),
+                     (qtn.TN_AMPLITUDE, [1] + [0] * (n - 1), amp_ref))
+            for mode, target, ref in cases:
+                net = qtn.Network(n, gates_, mode, target, n_params=1, init=init, dtype=qtn.TN_C128)
+                for pi in (net.order_stochastic(1), net.order_linegraph(trials=2, seed=1)):
+                    net.set_order(pi)
+                    _say(f"degenerate n={n} gates={len(gates_)} mode={mode}")
+                    val = net.contract([0.3])
+                    assert abs(val - ref) < 1e-12, (n, len(gates_), mode, val, ref)
+
+
+def test_disconnected_components_in_a_batch_with_gradient():
+    """Qubit pairs that never interact: the network falls apart into
+    components whose scalars multiply; values and gradients in a batch
+    against the state vector and parameter shift."""
+    from oracle import statevector
+    _, _, qtn = _mods()
+    gates_ = [("H", 0, -1, -1, 0.0), ("ZZ", 0, 1, 0, 1.0), ("RX", 1, -1, 1, 1.0),
+              ("H", 2, -1, -1, 0.0), ("ZZ", 2, 3, 1, 0.5), ("RY", 3, -1, 0, 1.0)]
+    pauli = [3, 3, 1, 3]
+    nets = []
+    for diag in (False, True):
+        net = qtn.Network(4, gates_, qtn.TN_EXPECTATION, pauli, n_params=2, dtype=qtn.TN_C128, diagonal=diag)
+        net.set_order(net.order_linegraph(trials=2, seed=0))
+        nets.append(net)
+    assert nets[0].plan_info()["n_components"] == 2
+    ang = np.array([[0.4, -0.7], [1.1, 0.2], [-0.3, 0.9]])
+    batch = qtn.Batch(nets, coef=[1.0, 0.0], max_sets=3)
+    out = torch.empty((2, 3, 2), dtype=torch.float64, device="cuda")
+    gnet = torch.empty((2, 3, 2), dtype=torch.float64, device="cuda")
+    _say("disconnected components batch")
+    batch.grad(torch.tensor(ang, device="cuda"), out=out, grad_net=gnet)
+    torch.cuda.synchronize()
+    out, gnet = out.cpu().numpy(), gnet.cpu().numpy()
+
+    def f(prm):
+        gl = [("H", 0, -1, 0.0), ("ZZ", 0, 1, prm[0]), ("RX", 1, -1, prm[1]), ("H", 2, -1, 0.0),
+              ("ZZ", 2, 3, 0.5 * prm[1]), ("RY", 3, -1, prm[0])]
+        return statevector.expect_pauli(statevector.run(4, gl), pauli).real
+
+    for s in range(3):
+        ref = f(ang[s])
+        h = 1e-5
+        fd = [(f(ang[s] + h * np.eye(2)[i]) - f(ang[s] - h * np.eye(2)[i])) / (2 * h) for i in range(2)]
+        for k in range(2):
+            assert abs(out[k, s, 0] - ref) < 1e-12
+            np.testing.assert_allclose(gnet[k, s], fd, atol=1e-8)
+
+
+def test_batch_without_parameters_and_set_bounds():
+    _, _, qtn = _mods()
+    gates_ = [("H", 0, -1, -1, 0.0), ("CNOT", 0, 1, -1, 0.0)]
+    net = qtn.Network(2, gates_, qtn.TN_EXPECTATION, [3, 3], n_params=0, dtype=qtn.TN_C64)
+    net.set_order(net.order_stochastic(0))
+    batch = qtn.Batch([net], coef=[2.0], offset=1.0, max_sets=2)
+    params = torch.empty((2, 0), dtype=torch.float64, device="cuda")
+    out = torch.empty((1, 2, 2), dtype=torch.float64, device="cuda")
+    obj = torch.empty(2, dtype=torch.float64, device="cuda")
+    batch.contract(params, out=out, obj=obj)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(out[0, :, 0].cpu().numpy(), [1.0, 1.0], atol=1e-6)  # Bell state: <ZZ> = 1
+    np.testing.assert_allclose(obj.cpu().numpy(), [3.0, 3.0], atol=1e-6)
+    with pytest.raises(qtn.QtnError):
+        batch.contract(torch.empty((3, 0), dtype=torch.float64, device="cuda"))  # more sets than max_sets
