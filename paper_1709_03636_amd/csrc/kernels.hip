@@ -815,23 +815,21 @@ __global__ __launch_bounds__(64) void fused_sets_kernel(FusedArgs a) {
 }
 
 // obj[s] = offset + sum_i coef[i] Re(val[i][s]); grad[s][p] = sum_i coef[i] gnet[i][s][p].
-// One workgroup per set, fixed-order FP64 tree.
-__global__ __launch_bounds__(256) void combine_kernel(const double *__restrict__ val, const double *__restrict__ gnet,
-                                                      const double *__restrict__ coef, double offset, int n_nets,
-                                                      int n_sets, int n_params, double *obj, double *grad) {
-  __shared__ double red[4];
-  const int s = blockIdx.x;
-  for (int q = -1; q < n_params; ++q) {
-    if (q < 0 && !obj) continue;
-    if (q >= 0 && !grad) break;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < n_nets; i += 256)
-      acc += coef[i] * (q < 0 ? val[((size_t)i * n_sets + s) * 2] : gnet[((size_t)i * n_sets + s) * n_params + q]);
-    acc = block_sum<256>(acc, red);
-    if (threadIdx.x == 0) {
-      if (q < 0) obj[s] = offset + acc;
-      else grad[(size_t)s * n_params + q] = acc;
-    }
+// One 64-lane wave per (set, quantity): lane partial sums in network order,
+// then the fixed DPP tree; FP64 throughout.
+__global__ __launch_bounds__(64) void combine_kernel(const double *__restrict__ val, const double *__restrict__ gnet,
+                                                     const double *__restrict__ coef, double offset, int n_nets,
+                                                     int n_sets, int n_params, double *obj, double *grad) {
+  const int nq = n_params + 1;
+  const int s = blockIdx.x / nq, q = (int)(blockIdx.x % nq) - 1;
+  if ((q < 0 && !obj) || (q >= 0 && !grad)) return;  // uniform over the wave
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n_nets; i += 64)
+    acc += coef[i] * (q < 0 ? val[((size_t)i * n_sets + s) * 2] : gnet[((size_t)i * n_sets + s) * n_params + q]);
+  acc = wave_sum(acc);
+  if (threadIdx.x == 0) {
+    if (q < 0) obj[s] = offset + acc;
+    else grad[(size_t)s * n_params + q] = acc;
   }
 }
 
@@ -877,8 +875,8 @@ hipError_t launch_fused(int dtype, int block, bool grad, bool rec_only, const Fu
 
 hipError_t launch_combine(const double *val, const double *gnet, const double *coef, double offset, int n_nets,
                           int n_sets, int n_params, double *obj, double *grad, hipStream_t st) {
-  hipLaunchKernelGGL(combine_kernel, dim3(n_sets), dim3(256), 0, st, val, gnet, coef, offset, n_nets, n_sets, n_params,
-                     obj, grad);
+  hipLaunchKernelGGL(combine_kernel, dim3(n_sets * (n_params + 1)), dim3(64), 0, st, val, gnet, coef, offset, n_nets,
+                     n_sets, n_params, obj, grad);
   return hipGetLastError();
 }
 
