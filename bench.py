@@ -74,9 +74,17 @@ def cpu_baseline(edges, angles, budget_s=12.0):
         t0 = time.perf_counter()
         pool.map(_oracle_worker, sample, chunksize=max(1, n_sample // (4 * workers)))
         dt = time.perf_counter() - t0
+    # one core: a short sample in this process
+    n1 = int(max(4, min(len(tasks), 2.0 / max(one, 1e-4))))
+    t0 = time.perf_counter()
+    for t in tasks[:n1]:
+        _oracle_worker(t)
+    dt1 = time.perf_counter() - t0
     return {"value": n_sample / dt, "unit": "networks/s (fwd+grad)", "cores": workers, "kind": "oracle",
+            "value_1core": n1 / dt1,
             "sample": f"{n_sample} (edge, angle-set) networks of the same workload, forward plus central "
-                      f"finite-difference gradient (5 FP64 contractions each), {workers} processes"}
+                      f"finite-difference gradient (5 FP64 contractions each), {workers} processes; "
+                      f"1-core figure from {n1} networks in one process"}
 
 
 def traffic_from_profile(kernel):
@@ -382,8 +390,15 @@ def main():
         vals = [net.contract(a0, stream=st) for net in nets]
         dtp = time.perf_counter() - t0
         zz = closed_form.zz_p1(N_VERT, edges, a0[0], a0[1])
+        # forward plus adjoint gradient, one network per call (tn_grad)
+        t0 = time.perf_counter()
+        grads = [net.grad(a0, stream=st) for net in nets]
+        dtg = time.perf_counter() - t0
+        dg, db = closed_form.zz_p1_grad(N_VERT, edges, a0[0], a0[1])
+        gerr = max(float(np.max(np.abs(g - np.array([dg[i], db[i]])))) for i, (_, g) in enumerate(grads))
         plain[name] = {"networks_per_s": len(nets) / dtp,
-                       "max_abs_err_zz": float(np.max(np.abs(np.array(vals).real - zz)))}
+                       "max_abs_err_zz": float(np.max(np.abs(np.array(vals).real - zz))),
+                       "fwd_grad_networks_per_s": len(nets) / dtg, "max_abs_err_grad": gerr}
         log(f"plain {name}: {plain[name]}")
 
     # dense regime (MFMA path): whole-circuit network of one edge, 6-regular n=20, p=1

@@ -208,7 +208,7 @@ int tn_batch_run_graph(tn_batch *b, int32_t with_grad, const double *params, int
                        double *out, double *obj, double *grad, void *stream);
 
 typedef struct {
-  int32_t n_nets, n_fused, n_level;   /* networks on the fused and the level-synchronous path */
+  int32_t n_nets, n_fused, n_level;   /* networks on the LDS fused and the level-synchronous path */
   int32_t n_levels;                   /* level launches per pass */
   int32_t lds_bytes_fwd, lds_bytes_grad;
   int32_t n_programs;                 /* distinct fused programs (identical networks share one) */
@@ -217,7 +217,8 @@ typedef struct {
                                          record for every op (kernel without the descriptor path) */
   int32_t sets_per_wave_fwd;          /* angle sets one 64-lane wave of the fused executor runs at once: */
   int32_t sets_per_wave_grad;         /* forward / adjoint programs (1, 2 or 4) */
-  int32_t reserved;
+  int32_t n_global;                   /* networks on the global-arena fused executor (too large for
+                                         LDS, steps small enough for one workgroup) */
   double flops_fwd, bytes_fwd;        /* algorithmic, one parameter vector, all networks */
   double flops_grad, bytes_grad;      /* algorithmic, adjoint sweep only */
 } tn_batch_stats;

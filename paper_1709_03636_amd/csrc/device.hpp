@@ -124,6 +124,15 @@ constexpr int kRecLanes = 64;
 constexpr int kMaxGroupLanes = 16, kLgMaxGroupLanes = 4;
 constexpr int kSetContract = 1, kSetScalar = 2, kSetSeed = 3, kSetLeafGrad = 4;
 
+// One step of one network for the grouped level launches: every network
+// works in its own region of the level arena (`base` elements from its
+// start, `stride` elements per parameter vector).
+struct LItem {
+  DOp op;
+  DRuns ru;
+  int64_t base, stride;
+};
+
 // Arguments of the fused executor kernel.
 struct FusedArgs {
   const DNet *nets;
@@ -140,6 +149,8 @@ struct FusedArgs {
   int n_params, n_sets, n_tasks, per_set;
   int set_stride, n_groups, max_comp;  // set-packed executor: LDS elements per set, set groups, scalars per set
   int per_block;            // workgroup b runs tasks [b*per_block, (b+1)*per_block)
+  void *garena;             // global-arena executor: workgroup b works in garena + b * garena_stride
+  int64_t garena_stride;    // (elements)
   int scratch_off, scal_off, gacc_off, red_off, gbar_off;  // LDS byte offsets
 };
 

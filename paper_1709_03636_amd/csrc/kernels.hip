@@ -454,8 +454,11 @@ __device__ __forceinline__ void scalar_rec(const V *mem, double2 *scal, const in
 // each parametric leaf is contracted with the leaf's angle derivative (bound
 // by the binding kernel) as soon as it is formed, and summed per parameter in
 // FP64. RONLY (64-lane workgroups): every op has a lane record, the
-// descriptor path is left out.
-template <typename T, int BLOCK, bool GRAD, bool RONLY>
+// descriptor path is left out. GMEM: the network's memory is not LDS but the
+// workgroup's slot of a global arena (networks too large for LDS whose
+// steps are still small: no launch per step, the slot stays in L2/MALL);
+// scratch, scalars and gradient sums stay in LDS.
+template <typename T, int BLOCK, bool GRAD, bool RONLY, bool GMEM>
 __global__ __launch_bounds__(BLOCK)
 #ifdef QTN_WAVES
 __attribute__((amdgpu_waves_per_eu(QTN_WAVES, QTN_WAVES)))
@@ -463,7 +466,7 @@ __attribute__((amdgpu_waves_per_eu(QTN_WAVES, QTN_WAVES)))
 void fused_exec_kernel(FusedArgs a) {
   using V = typename Cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
-  V *mem = reinterpret_cast<V *>(smem);
+  V *mem = GMEM ? reinterpret_cast<V *>(a.garena) + (size_t)blockIdx.x * a.garena_stride : reinterpret_cast<V *>(smem);
   V *scratch = reinterpret_cast<V *>(smem + a.scratch_off);
   double2 *scal = reinterpret_cast<double2 *>(smem + a.scal_off);
   double *gacc = reinterpret_cast<double *>(smem + a.gacc_off);
@@ -835,18 +838,29 @@ __global__ __launch_bounds__(64) void combine_kernel(const double *__restrict__ 
 
 // --- launch helpers (host) ----------------------------------------------------------------
 template <typename T, bool G>
-static const void *fused_ptr_t(int block, bool rec_only) {
+static const void *fused_ptr_t(int block, bool rec_only, bool gmem) {
+  if (gmem) return (const void *)fused_exec_kernel<T, 256, G, false, true>;
   switch (block) {
-    case 64: return rec_only ? (const void *)fused_exec_kernel<T, 64, G, true> : (const void *)fused_exec_kernel<T, 64, G, false>;
-    case 128: return (const void *)fused_exec_kernel<T, 128, G, false>;
-    default: return (const void *)fused_exec_kernel<T, 256, G, false>;
+    case 64:
+      return rec_only ? (const void *)fused_exec_kernel<T, 64, G, true, false>
+                      : (const void *)fused_exec_kernel<T, 64, G, false, false>;
+    case 128: return (const void *)fused_exec_kernel<T, 128, G, false, false>;
+    default: return (const void *)fused_exec_kernel<T, 256, G, false, false>;
   }
 }
 
-const void *fused_kernel_ptr(int dtype, int block, bool grad, bool rec_only) {
+// gmem: the global-arena instance (256 lanes)
+const void *fused_kernel_ptr(int dtype, int block, bool grad, bool rec_only, bool gmem) {
   if (dtype == TN_C128)
-    return grad ? fused_ptr_t<double, true>(block, rec_only) : fused_ptr_t<double, false>(block, rec_only);
-  return grad ? fused_ptr_t<float, true>(block, rec_only) : fused_ptr_t<float, false>(block, rec_only);
+    return grad ? fused_ptr_t<double, true>(block, rec_only, gmem) : fused_ptr_t<double, false>(block, rec_only, gmem);
+  return grad ? fused_ptr_t<float, true>(block, rec_only, gmem) : fused_ptr_t<float, false>(block, rec_only, gmem);
+}
+
+hipError_t launch_fused(int dtype, int block, bool grad, bool rec_only, bool gmem, const FusedArgs &a, int grid,
+                        int lds_bytes, hipStream_t st) {
+  const void *k = fused_kernel_ptr(dtype, block, grad, rec_only, gmem);
+  void *args[] = {(void *)&a};
+  return hipLaunchKernel(k, dim3(grid), dim3(gmem ? 256 : block), args, lds_bytes, st);
 }
 
 template <typename T, bool G>
@@ -864,13 +878,6 @@ hipError_t launch_fused_sets(int dtype, bool grad, int sets, const FusedArgs &a,
   const void *k = fused_sets_kernel_ptr(dtype, grad, sets);
   void *args[] = {(void *)&a};
   return hipLaunchKernel(k, dim3(grid), dim3(64), args, lds_bytes, st);
-}
-
-hipError_t launch_fused(int dtype, int block, bool grad, bool rec_only, const FusedArgs &a, int grid, int lds_bytes,
-                        hipStream_t st) {
-  const void *k = fused_kernel_ptr(dtype, block, grad, rec_only);
-  void *args[] = {(void *)&a};
-  return hipLaunchKernel(k, dim3(grid), dim3(block), args, lds_bytes, st);
 }
 
 hipError_t launch_combine(const double *val, const double *gnet, const double *coef, double offset, int n_nets,

@@ -261,6 +261,70 @@ __global__ __launch_bounds__(256) void level_finish_kernel(LevelArgs a, const DP
   }
 }
 
+// --- grouped launches: one step of many networks ---------------------------------------------
+
+// Thin contractions of several networks at once: workgroup row y serves item
+// y (its own arena region and op), with the addressing of
+// level_contract_kernel.
+template <typename V>
+__global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *__restrict__ items, V *arena, int n_sets,
+                                                                   const int32_t *__restrict__ tabs) {
+  const LItem &it = items[blockIdx.y];
+  const DOp op = it.op;
+  const int lgOut = op.nFX + op.nB + op.nFY;
+  const int64_t nOut = (int64_t)1 << lgOut;
+  const int64_t total = nOut * n_sets;
+  const int K = 1 << op.nS;
+  const uint32_t maskJ = (1u << op.nFY) - 1u;
+  const int32_t *tab = tabs + op.tab;
+  const int32_t *tabB = tabs + op.tabB;
+  V *reg = arena + it.base;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t set = g >> lgOut;
+    const uint32_t c = (uint32_t)(g & (nOut - 1));
+    V *base = reg + set * it.stride;
+    const uint32_t rest = c >> op.nFY;
+    uint32_t bx = 0, by = 0;
+    if (op.nB) {
+      const uint32_t b = rest & ((1u << op.nB) - 1u);
+      bx = tabB[2 * b];
+      by = tabB[2 * b + 1];
+    }
+    const V *X = base + op.x + l_deposit(rest >> op.nB, it.ru.runsX, op.maskX) + bx;
+    const V *Y = base + op.y + l_deposit(c & maskJ, it.ru.runsY, op.maskY) + by;
+    V acc;
+    acc.x = 0;
+    acc.y = 0;
+    for (int k = 0; k < K; ++k) {
+      const int2 o = l_tab(tab, op.nS, k);
+      acc = l_fma(acc, X[o.x], Y[o.y]);
+    }
+    base[op.z + c] = acc;
+  }
+}
+
+// Leaf adjoints of several networks at once (level_leafgrad_kernel per item).
+template <typename V>
+__global__ __launch_bounds__(256) void level_group_leafgrad_kernel(const LItem *__restrict__ items, V *arena, int n_sets,
+                                                                   const int32_t *__restrict__ tabs) {
+  const LItem &it = items[blockIdx.y];
+  const DOp op = it.op;
+  const int n = 1 << op.nFX;
+  const int64_t total = (int64_t)n * n_sets;
+  const int32_t *tab = tabs + op.tab;
+  V *reg = arena + it.base;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t set = g / n;
+    const int i = (int)(g - set * n);
+    V *base = reg + set * it.stride;
+    V v = base[op.y + tab[i]];
+    const V x = base[op.x + i];
+    v.x += x.x;
+    v.y += x.y;
+    base[op.y + tab[i]] = v;
+  }
+}
+
 // --- host launchers ------------------------------------------------------------------------
 bool mfma_eligible(int dtype, const DOp &op);
 hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, int prec, hipStream_t st);
@@ -309,6 +373,26 @@ static hipError_t level_op_t(const LevelArgs &a, const DOp &op, const int32_t *t
 hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tabs, int mfma, hipStream_t st) {
   if (mfma && mfma_eligible(dtype, op)) return mfma_contract(a, op, tabs + op.tab, mfma, st);
   return dtype == TN_C128 ? level_op_t<double2>(a, op, tabs, st) : level_op_t<float2>(a, op, tabs, st);
+}
+
+// n items of one step (device array), the largest output count among them
+// (outputs or leaf entries per parameter vector); leafgrad selects the kind.
+hipError_t level_group(int dtype, bool leafgrad, const LItem *items, int n, void *arena, int n_sets, int64_t max_out,
+                       const int32_t *tabs, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (max_out * n_sets + 255) / 256)), (unsigned)n);
+  if (dtype == TN_C128) {
+    if (leafgrad)
+      hipLaunchKernelGGL(level_group_leafgrad_kernel<double2>, grid, dim3(256), 0, st, items, (double2 *)arena, n_sets, tabs);
+    else
+      hipLaunchKernelGGL(level_group_contract_kernel<double2>, grid, dim3(256), 0, st, items, (double2 *)arena, n_sets, tabs);
+  } else {
+    if (leafgrad)
+      hipLaunchKernelGGL(level_group_leafgrad_kernel<float2>, grid, dim3(256), 0, st, items, (float2 *)arena, n_sets, tabs);
+    else
+      hipLaunchKernelGGL(level_group_contract_kernel<float2>, grid, dim3(256), 0, st, items, (float2 *)arena, n_sets, tabs);
+  }
+  return hipGetLastError();
 }
 
 hipError_t level_setup(int dtype, const LevelArgs &a, const void *consts, int n_const, const DParam *pt, int n_pt,

@@ -20,9 +20,9 @@ namespace qtn {
 
 hipError_t launch_fused_sets(int dtype, bool grad, int sets, const FusedArgs &a, int grid, int lds_bytes, hipStream_t st);
 const void *fused_sets_kernel_ptr(int dtype, bool grad, int sets);
-hipError_t launch_fused(int dtype, int block, bool grad, bool rec_only, const FusedArgs &a, int grid, int lds_bytes,
+hipError_t launch_fused(int dtype, int block, bool grad, bool rec_only, bool gmem, const FusedArgs &a, int grid, int lds_bytes,
                         hipStream_t st);
-const void *fused_kernel_ptr(int dtype, int block, bool grad, bool rec_only);
+const void *fused_kernel_ptr(int dtype, int block, bool grad, bool rec_only, bool gmem);
 hipError_t launch_combine(const double *val, const double *gnet, const double *coef, double offset, int n_nets,
                           int n_sets, int n_params, double *obj, double *grad, hipStream_t st);
 hipError_t launch_bind(int dtype, const DParam *slots, int n_slots, const double *params, int n_params, int n_sets,
@@ -45,6 +45,13 @@ static constexpr int64_t kFusedLdsMax = 64 * 1024;
 // processed in chunks that fit).
 static constexpr int64_t kLevelBudget = 8ll << 30;
 static constexpr int64_t kMaxArenaElems = int64_t(1) << 31;  // 32-bit element offsets per set
+// Global-arena fused executor: networks too large for LDS whose whole task
+// (forward + adjoint program of one parameter vector) has at most this many
+// complex multiply-adds, and no step above a sixteenth of it, run one
+// workgroup per task. Heavier tasks need whole-GPU launches per step (level
+// executor, matrix cores): one workgroup would serialise them.
+static constexpr int64_t kGmemMaxMacs = int64_t(1) << 20;
+static constexpr int64_t kGmemBudget = 16ll << 30;  // bytes of arena slots
 
 // First-fit arena allocator over element offsets.
 struct Arena {
@@ -169,6 +176,7 @@ struct HostProgram {
   std::map<std::tuple<int, int, double, int>, int> slot_of;
   int per_set = 0;
   int max_mem_fwd = 0, max_mem_grad = 0, max_comp = 0, max_ptens_elems = 0;
+  int64_t max_mem_g[2] = {0, 0};  // global-arena programs: memory (elements), forward / adjoint
   std::map<std::string, int> program_of;  // fused program signature -> first network using it
   int n_programs = 0;
   bool generic[2] = {false, false};  // some op of a forward / adjoint program has no lane record
@@ -527,7 +535,7 @@ static bool build_set_records(const HostProgram &loc, const std::vector<DParam> 
 // and parametric tensors: e.g. isomorphic light cones contracted in the same
 // order) share one copy, which keeps the descriptors of a batch small enough
 // to stay in the scalar cache.
-static void append_fused(const Net &net, const NetLayout &lay, HostProgram &hp) {
+static void append_fused(const Net &net, const NetLayout &lay, HostProgram &hp, bool gmem) {
   const Plan &p = net.gplan;
   HostProgram loc;  // this network's program with local indices
   std::vector<DParam> lptens;
@@ -572,9 +580,9 @@ static void append_fused(const Net &net, const NetLayout &lay, HostProgram &hp) 
   build_records(loc, lptens, 0, (int)loc.ops.size(), hp.recs);
   for (int variant = 0; variant < 2; ++variant)
     for (int o = op_begin[variant]; o < op_begin[variant] + n_ops[variant]; ++o)
-      if (hp.recs[((size_t)(rec0 + o) * kRecLanes) * 4 + 3] == 0) hp.generic[variant] = true;
+      if (hp.recs[((size_t)(rec0 + o) * kRecLanes) * 4 + 3] == 0 && !gmem) hp.generic[variant] = true;
   for (int i = 0; i < 2; ++i)
-    if (!build_set_records(loc, lptens, i == 0 ? 4 : 5, hp.srecs[i])) hp.sets_ok[i] = false;
+    if (!build_set_records(loc, lptens, i == 0 ? 4 : 5, hp.srecs[i]) && !gmem) hp.sets_ok[i] = false;
   const int const_begin = (int)(hp.consts.size() / 2);
   for (DOp d : loc.ops) {
     d.tab += tab0;
@@ -598,8 +606,12 @@ static void append_fused(const Net &net, const NetLayout &lay, HostProgram &hp) 
     dn.ptens_begin = ptens_begin;
     dn.n_ptens = (int32_t)net.ptensors.size();
     (variant == 0 ? hp.nets_fwd : hp.nets_grad).push_back(dn);
-    int &mx = variant == 0 ? hp.max_mem_fwd : hp.max_mem_grad;
-    mx = std::max(mx, dn.mem_elems);
+    if (gmem) {
+      hp.max_mem_g[variant] = std::max<int64_t>(hp.max_mem_g[variant], dn.mem_elems);
+    } else {
+      int &mx = variant == 0 ? hp.max_mem_fwd : hp.max_mem_grad;
+      mx = std::max(mx, dn.mem_elems);
+    }
   }
   hp.program_of.emplace(sig, (int)hp.nets_fwd.size() - 1);
   hp.n_programs++;
@@ -687,12 +699,17 @@ struct tn_batch {
   std::vector<double> coef;
   qtn::HostProgram hp;
   std::vector<int32_t> task_net;       // fused networks, in cost order
+  std::vector<int32_t> gtask_net;      // networks on the global-arena fused executor, in cost order
+  struct GLayout { int lds = 0, grid = 0, scratch_off = 0, scal_off = 0, gacc_off = 0, red_off = 0; } gl[2];
+  int64_t gstride = 0;                 // elements per global-arena slot
+  int gslots = 0;                      // slots (= most workgroups of one launch)
   std::vector<qtn::LevelNet> level;    // networks on the level executor
   // device
   qtn::DNet *d_nets_fwd = nullptr, *d_nets_grad = nullptr;
   qtn::DOp *d_ops = nullptr;
   int4 *d_recs = nullptr, *d_srecs[2] = {nullptr, nullptr};
-  int32_t *d_tabs = nullptr, *d_task_net = nullptr;
+  int32_t *d_tabs = nullptr, *d_task_net = nullptr, *d_gtask_net = nullptr;
+  void *d_garena = nullptr;            // global-arena slots
   void *d_consts = nullptr;
   qtn::DParam *d_ptens = nullptr, *d_slots = nullptr;
   void *d_bound = nullptr, *d_dbound = nullptr;
@@ -737,7 +754,7 @@ static void drop_timing_events(tn_batch *b) {
 static void free_batch_dev(tn_batch *b) {
   b->gc.clear();
   drop_timing_events(b);
-  void *ptrs[] = {b->d_nets_fwd, b->d_nets_grad, b->d_ops, b->d_recs, b->d_srecs[0], b->d_srecs[1], b->d_tabs, b->d_task_net, b->d_consts, b->d_ptens,
+  void *ptrs[] = {b->d_nets_fwd, b->d_nets_grad, b->d_ops, b->d_recs, b->d_srecs[0], b->d_srecs[1], b->d_tabs, b->d_task_net, b->d_gtask_net, b->d_garena, b->d_consts, b->d_ptens,
                   b->d_slots, b->d_bound, b->d_dbound, b->d_val, b->d_gnet, b->d_coef, b->d_larena, b->d_lscal,
                   b->d_lpart};
   for (void *p : ptrs)
@@ -812,11 +829,43 @@ static int layout_lds(tn_batch *b, int variant) {
     return TN_ENOMEM;
   }
   (variant == 0 ? b->lds_fwd : b->lds_grad) = o;
-  const void *k = fused_kernel_ptr(b->dtype, b->block, variant == 1, rec_only(b, variant));
+  const void *k = fused_kernel_ptr(b->dtype, b->block, variant == 1, rec_only(b, variant), false);
   if (o > 64 * 1024) HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, o));
   HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, b->block, o));
   int grid = std::max(1, per_cu) * std::max(1, cus);
   (variant == 0 ? b->grid_fwd : b->grid_grad) = grid;
+  return TN_OK;
+}
+
+// Global-arena fused executor: LDS holds only the scratch, the component
+// scalars, the gradient sums and the reduction slots; the arena has one slot
+// of `gstride` elements per workgroup.
+static int layout_gmem(tn_batch *b) {
+  if (b->gtask_net.empty()) return TN_OK;
+  const int eb = b->dtype == TN_C128 ? 16 : 8;
+  auto al = [](int x) { return (x + 15) & ~15; };
+  int dev = 0, cus = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  int grid_max = 0;
+  for (int v = 0; v < 2; ++v) {
+    tn_batch::GLayout &g = b->gl[v];
+    g.scratch_off = 0;
+    int o = al(256 * eb);
+    g.scal_off = o;
+    o = al(o + std::max(1, b->hp.max_comp) * 16);
+    g.gacc_off = o;
+    o = al(o + std::max(1, b->n_params) * 8);
+    g.red_off = o;
+    o = al(o + 16 * 8);
+    g.lds = o;
+    int per_cu = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_kernel_ptr(b->dtype, 256, v == 1, false, true), 256, o));
+    g.grid = std::max(1, per_cu) * std::max(1, cus);
+    grid_max = std::max(grid_max, g.grid);
+  }
+  b->gstride = (std::max(b->hp.max_mem_g[0], b->hp.max_mem_g[1]) + 63) & ~int64_t(63);
+  b->gslots = (int)std::max<int64_t>(1, std::min<int64_t>(grid_max, kGmemBudget / (b->gstride * eb)));
   return TN_OK;
 }
 
@@ -849,8 +898,10 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   // every network to the level executor
   int64_t fused_max = kFusedLdsMax;
   if (const char *env = std::getenv("QTN_FUSED_LDS_MAX")) fused_max = std::atoll(env);
+  int64_t gmem_max = kGmemMaxMacs;  // QTN_GMEM_MAX_MACS=0 turns the global-arena executor off
+  if (const char *env = std::getenv("QTN_GMEM_MAX_MACS")) gmem_max = std::atoll(env);
   std::vector<double> cost(n_nets);
-  std::vector<int> fused_ids;
+  std::vector<int> fused_ids, gmem_ids;
   int maxbits = 0;
   for (int i = 0; i < n_nets; ++i) {
     const Net *n = reinterpret_cast<const Net *>(nets[i]);
@@ -860,10 +911,22 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
     b->bytes_fwd += n->gplan.bytes;
     b->flops_grad += n->gplan.flops_grad;
     b->bytes_grad += n->gplan.bytes_grad;
+    double max_macs = 0, tot_macs = 0;
+    for (const Op &op : n->gplan.ops)
+      if (op.type == OP_CONTRACT || op.type == OP_SCALAR) {
+        const double m = std::ldexp(1.0, op.nFX + op.nB + op.nS + op.nFY);
+        max_macs = std::max(max_macs, m);
+        tot_macs += m;
+      }
+    const int64_t mem_elems = lay.leaf_region + std::max(lay.arena[0], lay.arena[1]);
     if (fused_lds_need(*n, lay, eb, b->n_params) <= fused_max) {
-      append_fused(*n, lay, b->hp);
+      append_fused(*n, lay, b->hp, false);
       fused_ids.push_back(i);
       maxbits = std::max(maxbits, n->gplan.peak_bits);
+    } else if (tot_macs <= (double)gmem_max && max_macs <= (double)gmem_max / 16 && mem_elems < kMaxArenaElems &&
+               mem_elems * eb <= kGmemBudget / 256) {
+      append_fused(*n, lay, b->hp, true);
+      gmem_ids.push_back(i);
     } else {
       b->hp.nets_fwd.push_back(DNet{});
       b->hp.nets_grad.push_back(DNet{});
@@ -878,6 +941,8 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   // fused networks, expensive first (longest processing time first)
   b->task_net = fused_ids;
   std::stable_sort(b->task_net.begin(), b->task_net.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  b->gtask_net = gmem_ids;
+  std::stable_sort(b->gtask_net.begin(), b->gtask_net.end(), [&](int x, int y) { return cost[x] > cost[y]; });
   // block size: enough threads for the typical op, few idle lanes
   b->block = maxbits <= 6 ? 64 : (maxbits <= 9 ? 128 : 256);
   if (const char *env = std::getenv("QTN_FUSED_BLOCK")) {
@@ -900,6 +965,7 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   }
   if ((rc = layout_lds(b.get(), 0)) != TN_OK) return rc;
   if ((rc = layout_lds(b.get(), 1)) != TN_OK) return rc;
+  if ((rc = layout_gmem(b.get())) != TN_OK) return rc;
 
   tn_batch *B = b.get();
   auto fail = [&](hipError_t e, const char *w) {
@@ -916,6 +982,10 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   for (int i = 0; i < 2; ++i)
     if ((e = dalloc(&b->d_srecs[i], hp.srecs[i].size() / 4)) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_task_net, b->task_net.size())) != hipSuccess) return fail(e, "hipMalloc");
+  if ((e = dalloc(&b->d_gtask_net, b->gtask_net.size())) != hipSuccess) return fail(e, "hipMalloc");
+  if (!b->gtask_net.empty() &&
+      (e = dalloc((char **)&b->d_garena, (size_t)b->gslots * b->gstride * eb)) != hipSuccess)
+    return fail(e, "hipMalloc (global arena)");
   if ((e = dalloc((char **)&b->d_consts, hp.consts.size() / 2 * eb)) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_ptens, hp.ptens.size())) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_slots, hp.slots.size())) != hipSuccess) return fail(e, "hipMalloc");
@@ -955,6 +1025,7 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
       {b->d_srecs[0], hp.srecs[0].data(), hp.srecs[0].size() * sizeof(int32_t)},
       {b->d_srecs[1], hp.srecs[1].data(), hp.srecs[1].size() * sizeof(int32_t)},
       {b->d_task_net, b->task_net.data(), b->task_net.size() * sizeof(int32_t)},
+      {b->d_gtask_net, b->gtask_net.data(), b->gtask_net.size() * sizeof(int32_t)},
       {b->d_consts, csrc, hp.consts.size() / 2 * eb},
       {b->d_ptens, hp.ptens.data(), hp.ptens.size() * sizeof(DParam)},
       {b->d_slots, hp.slots.data(), hp.slots.size() * sizeof(DParam)},
@@ -1045,7 +1116,7 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     if (spw > 1)
       e = launch_fused_sets(b->dtype, grad, spw, a, grid, grad ? b->lds_grad : b->lds_fwd, st);
     else
-      e = launch_fused(b->dtype, b->block, grad, rec_only(b, v), a, grid, grad ? b->lds_grad : b->lds_fwd, st);
+      e = launch_fused(b->dtype, b->block, grad, rec_only(b, v), false, a, grid, grad ? b->lds_grad : b->lds_fwd, st);
     if (t0) {
       if (e == hipSuccess && hipEventRecord(t1, st) == hipSuccess) {
         b->tev.emplace_back(t0, t1);
@@ -1057,6 +1128,27 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     if (e != hipSuccess) {
       b->poisoned = true;
       return hip_fail(e, "fused executor launch");
+    }
+  }
+  if (!b->gtask_net.empty()) {
+    const tn_batch::GLayout &gl = b->gl[v];
+    FusedArgs g = a;
+    g.recs = b->d_recs;
+    g.task_net = b->d_gtask_net;
+    g.n_tasks = (int)b->gtask_net.size() * n_sets;
+    g.scratch_off = gl.scratch_off;
+    g.scal_off = gl.scal_off;
+    g.gacc_off = gl.gacc_off;
+    g.red_off = gl.red_off;
+    g.garena = b->d_garena;
+    g.garena_stride = b->gstride;
+    const int cap = std::max(1, std::min(std::min(gl.grid, b->gslots), g.n_tasks));
+    const int rounds = (g.n_tasks + cap - 1) / cap;
+    g.per_block = rounds;
+    e = launch_fused(b->dtype, 256, grad, false, true, g, (g.n_tasks + rounds - 1) / rounds, gl.lds, st);
+    if (e != hipSuccess) {
+      b->poisoned = true;
+      return hip_fail(e, "global-arena executor launch");
     }
   }
   const int eb = b->dtype == TN_C128 ? 16 : 8;
@@ -1377,6 +1469,7 @@ int batch_info(const tn_batch *b, tn_batch_stats *s) {
   std::memset(s, 0, sizeof(*s));
   s->n_nets = b->n_nets;
   s->n_fused = (int32_t)b->task_net.size();
+  s->n_global = (int32_t)b->gtask_net.size();
   s->n_level = (int32_t)b->level.size();
   int levels = 0;
   for (auto &ln : b->level) levels = std::max(levels, ln.n_ops[1]);

@@ -49,7 +49,7 @@ def test_config3_batched_graphs(d, n, p):
     ang = np.array(workloads.qaoa_angles(0, S, p))
     model = qaoa.MaxCut(n, e, p, qtn.TN_C64, order="linegraph", max_sets=S, trials=4)
     info = model.batch.info()
-    _say(f"config3 d={d} n={n} p={p} nets={len(e)} fused={info['n_fused']} level={info['n_level']}")
+    _say(f"config3 d={d} n={n} p={p} nets={len(e)} fused={info['n_fused']} global={info['n_global']} level={info['n_level']}")
     out = torch.empty((len(e), S, 2), dtype=torch.float64, device="cuda")
     obj = model.expectation(torch.tensor(ang, device="cuda"), out=out)
     torch.cuda.synchronize()

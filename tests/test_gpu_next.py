@@ -349,18 +349,20 @@ def test_diagonal_mode_gradient_matches_finite_differences():
     np.testing.assert_allclose(g, fd, atol=1e-8)
 
 
-@pytest.mark.parametrize("cfg", ["records", "sets", "block128", "block256", "level"])
+@pytest.mark.parametrize("cfg", ["records", "sets", "block128", "block256", "global", "level"])
 def test_diagonal_qaoa_batch_every_executor(cfg, monkeypatch):
     """Hyperedge (batch-label) steps through every executor: 64-lane lane
-    records, set-packed records, the descriptor path at 128/256 lanes and the
-    level executor; p=1 values and gradients against the closed form."""
+    records, set-packed records, the descriptor path at 128/256 lanes, the
+    global-arena fused executor and the level executor; p=1 values and
+    gradients against the closed form."""
     from oracle import closed_form
     _, qaoa, qtn = _mods()
     env = {"records": {"QTN_SETS_PER_WAVE": "1", "QTN_FUSED_BLOCK": "64"},
            "sets": {"QTN_SETS_PER_WAVE": "4", "QTN_FUSED_BLOCK": "64"},
            "block128": {"QTN_SETS_PER_WAVE": "1", "QTN_FUSED_BLOCK": "128"},
            "block256": {"QTN_SETS_PER_WAVE": "1", "QTN_FUSED_BLOCK": "256"},
-           "level": {"QTN_FUSED_LDS_MAX": "0"}}[cfg]
+           "global": {"QTN_FUSED_LDS_MAX": "0"},
+           "level": {"QTN_FUSED_LDS_MAX": "0", "QTN_GMEM_MAX_MACS": "0"}}[cfg]
     for k, v in env.items():
         monkeypatch.setenv(k, v)
     n, d = 20, 3
@@ -373,6 +375,8 @@ def test_diagonal_qaoa_batch_every_executor(cfg, monkeypatch):
         info = model.batch.info()
         if cfg == "level":
             assert info["n_level"] == len(e)
+        if cfg == "global":
+            assert info["n_global"] == len(e)
         out = torch.empty((len(e), S, 2), dtype=torch.float64, device="cuda")
         obj, grad = model.value_and_grad(torch.tensor(ang, dtype=torch.float64, device="cuda"), out=out)
         torch.cuda.synchronize()

@@ -269,7 +269,8 @@ def test_bind_params_kernel():
 
 
 def test_level_executor_matches_fused(monkeypatch):
-    """The same batch on the level (global-memory) executor and on the fused one."""
+    """The same batch on the LDS fused executor, on the global-arena fused
+    executor and on the level (one launch per step) executor."""
     qtn, qaoa = _qtn(), _qaoa()
     n = 14
     e = workloads.random_regular_graph(3, n, 8)
@@ -278,16 +279,19 @@ def test_level_executor_matches_fused(monkeypatch):
     ref = np.array([gradients.cost(n, e, list(a)) for a in ang.cpu().numpy()])
     ps = np.array([gradients.parameter_shift(n, e, list(a)) for a in ang.cpu().numpy()])
     res = {}
-    for mode, lim in (("fused", None), ("level", "0")):
-        if lim is None:
-            monkeypatch.delenv("QTN_FUSED_LDS_MAX", raising=False)
-        else:
-            monkeypatch.setenv("QTN_FUSED_LDS_MAX", lim)
+    for mode, lim, gmem in (("fused", None, None), ("global", "0", None), ("level", "0", "0")):
+        for var, val in (("QTN_FUSED_LDS_MAX", lim), ("QTN_GMEM_MAX_MACS", gmem)):
+            if val is None:
+                monkeypatch.delenv(var, raising=False)
+            else:
+                monkeypatch.setenv(var, val)
         model = qaoa.MaxCut(n, e, 2, qtn.TN_C128, order="linegraph", max_sets=S)
         info = model.batch.info()
         if mode == "level":
-            assert info["n_level"] == len(e) and info["n_fused"] == 0
-        _say(f"executor {mode} n_fused={info['n_fused']} n_level={info['n_level']}")
+            assert info["n_level"] == len(e) and info["n_fused"] == 0 and info["n_global"] == 0
+        if mode == "global":
+            assert info["n_global"] == len(e) and info["n_fused"] == 0 and info["n_level"] == 0
+        _say(f"executor {mode} n_fused={info['n_fused']} n_global={info['n_global']} n_level={info['n_level']}")
         obj, grad = model.value_and_grad(ang)
         torch.cuda.synchronize()
         res[mode] = (obj.cpu().numpy(), grad.cpu().numpy())
@@ -318,7 +322,7 @@ def test_fused_workgroup_sizes_and_record_kernels(p, monkeypatch):
         _say(f"fused block {blk} spw {spw} p={p} rec_only={info['rec_only']} "
              f"sets={info['sets_per_wave_fwd']},{info['sets_per_wave_grad']} n_fused={info['n_fused']}")
         assert info["fused_block"] == blk and info["n_fused"] > 0
-        assert info["n_fused"] + info["n_level"] == len(e)
+        assert info["n_fused"] + info["n_global"] + info["n_level"] == len(e)
         assert info["sets_per_wave_fwd"] == info["sets_per_wave_grad"] == (spw if p == 1 else 1)
         if blk == 64 and p == 1:
             assert info["rec_only"] == 3
@@ -342,6 +346,7 @@ def test_dense_whole_circuit_mfma(d, n, monkeypatch):
     """Whole-circuit folded networks (trace on every other qubit, no light cone):
     large intermediates, complex GEMM steps on MFMA (complex64) vs the state vector."""
     qtn, qaoa = _qtn(), _qaoa()
+    monkeypatch.setenv("QTN_GMEM_MAX_MACS", "0")  # keep these networks on the level executor
     e = workloads.random_regular_graph(d, n, 0)
     ang = np.array(workloads.qaoa_angles(3, 2, 1))
     S = len(ang)
