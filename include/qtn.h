@@ -209,7 +209,7 @@ int tn_batch_run_graph(tn_batch *b, int32_t with_grad, const double *params, int
 
 typedef struct {
   int32_t n_nets, n_fused, n_level;   /* networks on the LDS fused and the level-synchronous path */
-  int32_t n_levels;                   /* level launches per pass */
+  int32_t n_levels;                   /* steps of the longest level-executor program (adjoint) */
   int32_t lds_bytes_fwd, lds_bytes_grad;
   int32_t n_programs;                 /* distinct fused programs (identical networks share one) */
   int32_t fused_block;                /* workgroup size of the fused executor */
@@ -219,6 +219,11 @@ typedef struct {
   int32_t sets_per_wave_grad;         /* forward / adjoint programs (1, 2 or 4) */
   int32_t n_global;                   /* networks on the global-arena fused executor (too large for
                                          LDS, steps small enough for one workgroup) */
+  int32_t n_level_bins;               /* groups of level networks stepped together (one launch per
+                                         step and kind for the whole group) */
+  int32_t n_level_chunked;            /* level networks run alone, in chunks of parameter vectors */
+  int32_t level_launches_fwd;         /* kernel launches of the level executor per pass with all */
+  int32_t level_launches_grad;        /* parameter vectors: forward / forward+adjoint */
   double flops_fwd, bytes_fwd;        /* algorithmic, one parameter vector, all networks */
   double flops_grad, bytes_grad;      /* algorithmic, adjoint sweep only */
 } tn_batch_stats;

@@ -263,13 +263,30 @@ __global__ __launch_bounds__(256) void level_finish_kernel(LevelArgs a, const DP
 
 // --- grouped launches: one step of many networks ---------------------------------------------
 
-// Thin contractions of several networks at once: workgroup row y serves item
-// y (its own arena region and op), with the addressing of
-// level_contract_kernel.
+// Item of workgroup blockIdx.x (the last with blk0 <= blockIdx.x) and the
+// workgroup's rank / count within it.
+__device__ __forceinline__ int l_item(const LItem *__restrict__ items, int n, int *rank, int *count) {
+  int lo = 0, hi = n - 1;
+  const int b = (int)blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].blk0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int end = lo + 1 < n ? items[lo + 1].blk0 : (int)gridDim.x;
+  *rank = b - items[lo].blk0;
+  *count = end - items[lo].blk0;
+  return lo;
+}
+
+// Thin contractions of several networks at once: each item is one op of one
+// network, with the addressing of level_contract_kernel inside the
+// network's own arena region.
 template <typename V>
-__global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *__restrict__ items, V *arena, int n_sets,
-                                                                   const int32_t *__restrict__ tabs) {
-  const LItem &it = items[blockIdx.y];
+__global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *__restrict__ items, int n, V *arena,
+                                                                   int n_sets, const int32_t *__restrict__ tabs) {
+  int rank, count;
+  const LItem &it = items[l_item(items, n, &rank, &count)];
   const DOp op = it.op;
   const int lgOut = op.nFX + op.nB + op.nFY;
   const int64_t nOut = (int64_t)1 << lgOut;
@@ -279,16 +296,16 @@ __global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *
   const int32_t *tab = tabs + op.tab;
   const int32_t *tabB = tabs + op.tabB;
   V *reg = arena + it.base;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t g = rank * (int64_t)256 + threadIdx.x; g < total; g += (int64_t)count * 256) {
     const int64_t set = g >> lgOut;
     const uint32_t c = (uint32_t)(g & (nOut - 1));
     V *base = reg + set * it.stride;
     const uint32_t rest = c >> op.nFY;
     uint32_t bx = 0, by = 0;
     if (op.nB) {
-      const uint32_t b = rest & ((1u << op.nB) - 1u);
-      bx = tabB[2 * b];
-      by = tabB[2 * b + 1];
+      const uint32_t bb = rest & ((1u << op.nB) - 1u);
+      bx = tabB[2 * bb];
+      by = tabB[2 * bb + 1];
     }
     const V *X = base + op.x + l_deposit(rest >> op.nB, it.ru.runsX, op.maskX) + bx;
     const V *Y = base + op.y + l_deposit(c & maskJ, it.ru.runsY, op.maskY) + by;
@@ -305,17 +322,18 @@ __global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *
 
 // Leaf adjoints of several networks at once (level_leafgrad_kernel per item).
 template <typename V>
-__global__ __launch_bounds__(256) void level_group_leafgrad_kernel(const LItem *__restrict__ items, V *arena, int n_sets,
-                                                                   const int32_t *__restrict__ tabs) {
-  const LItem &it = items[blockIdx.y];
+__global__ __launch_bounds__(256) void level_group_leafgrad_kernel(const LItem *__restrict__ items, int n, V *arena,
+                                                                   int n_sets, const int32_t *__restrict__ tabs) {
+  int rank, count;
+  const LItem &it = items[l_item(items, n, &rank, &count)];
   const DOp op = it.op;
-  const int n = 1 << op.nFX;
-  const int64_t total = (int64_t)n * n_sets;
+  const int m = 1 << op.nFX;
+  const int64_t total = (int64_t)m * n_sets;
   const int32_t *tab = tabs + op.tab;
   V *reg = arena + it.base;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t set = g / n;
-    const int i = (int)(g - set * n);
+  for (int64_t g = rank * (int64_t)256 + threadIdx.x; g < total; g += (int64_t)count * 256) {
+    const int64_t set = g / m;
+    const int i = (int)(g - set * m);
     V *base = reg + set * it.stride;
     V v = base[op.y + tab[i]];
     const V x = base[op.x + i];
@@ -375,22 +393,25 @@ hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t 
   return dtype == TN_C128 ? level_op_t<double2>(a, op, tabs, st) : level_op_t<float2>(a, op, tabs, st);
 }
 
-// n items of one step (device array), the largest output count among them
-// (outputs or leaf entries per parameter vector); leafgrad selects the kind.
-hipError_t level_group(int dtype, bool leafgrad, const LItem *items, int n, void *arena, int n_sets, int64_t max_out,
+// One grouped launch: n items (device array, blk0 ascending from 0) on
+// `blocks` workgroups; leafgrad selects the kind of every item.
+hipError_t level_group(int dtype, bool leafgrad, const LItem *items, int n, int blocks, void *arena, int n_sets,
                        const int32_t *tabs, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (max_out * n_sets + 255) / 256)), (unsigned)n);
   if (dtype == TN_C128) {
     if (leafgrad)
-      hipLaunchKernelGGL(level_group_leafgrad_kernel<double2>, grid, dim3(256), 0, st, items, (double2 *)arena, n_sets, tabs);
+      hipLaunchKernelGGL(level_group_leafgrad_kernel<double2>, dim3(blocks), dim3(256), 0, st, items, n, (double2 *)arena,
+                         n_sets, tabs);
     else
-      hipLaunchKernelGGL(level_group_contract_kernel<double2>, grid, dim3(256), 0, st, items, (double2 *)arena, n_sets, tabs);
+      hipLaunchKernelGGL(level_group_contract_kernel<double2>, dim3(blocks), dim3(256), 0, st, items, n, (double2 *)arena,
+                         n_sets, tabs);
   } else {
     if (leafgrad)
-      hipLaunchKernelGGL(level_group_leafgrad_kernel<float2>, grid, dim3(256), 0, st, items, (float2 *)arena, n_sets, tabs);
+      hipLaunchKernelGGL(level_group_leafgrad_kernel<float2>, dim3(blocks), dim3(256), 0, st, items, n, (float2 *)arena,
+                         n_sets, tabs);
     else
-      hipLaunchKernelGGL(level_group_contract_kernel<float2>, grid, dim3(256), 0, st, items, (float2 *)arena, n_sets, tabs);
+      hipLaunchKernelGGL(level_group_contract_kernel<float2>, dim3(blocks), dim3(256), 0, st, items, n, (float2 *)arena,
+                         n_sets, tabs);
   }
   return hipGetLastError();
 }

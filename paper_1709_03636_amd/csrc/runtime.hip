@@ -28,6 +28,8 @@ hipError_t launch_combine(const double *val, const double *gnet, const double *c
 hipError_t launch_bind(int dtype, const DParam *slots, int n_slots, const double *params, int n_params, int n_sets,
                        int per_set, void *G, void *dG, hipStream_t st);
 hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tabs, int mfma, hipStream_t st);
+hipError_t level_group(int dtype, bool leafgrad, const LItem *items, int n, int blocks, void *arena, int n_sets,
+                       const int32_t *tabs, hipStream_t st);
 bool mfma_eligible(int dtype, const DOp &op);
 hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, int prec, hipStream_t st);
 hipError_t level_setup(int dtype, const LevelArgs &a, const void *consts, int n_const, const DParam *pt, int n_pt,
@@ -197,6 +199,28 @@ struct LevelNet {
   int chunk = 1;                                // parameter vectors per pass
   bool grad_ok = true;                          // the adjoint arena is addressable (< 2^31 elements)
 };
+
+// Level networks whose parameter vectors all fit in the arena at once run
+// in bins: each network of a bin owns an arena region (and a region of
+// component scalars), and step k of every network of the bin is one grouped
+// launch per kind (thin contractions, leaf adjoints). Matrix-core, rank-0
+// and seed steps keep launches of their own.
+struct LevelBin {
+  std::vector<int> lv;         // indices into tn_batch::level
+  std::vector<int64_t> abase;  // arena region start (elements)
+  std::vector<int64_t> sbase;  // component-scalar region start (doubles)
+  // per step: thin items [t0, t0+nt) on tb workgroups, leaf items [l0,
+  // l0+nl) on lb workgroups (into the variant's item array), separately
+  // launched ops [o0, o0+no) of `other`
+  struct Step {
+    int t0 = 0, nt = 0, tb = 0, l0 = 0, nl = 0, lb = 0, o0 = 0, no = 0;
+  };
+  std::vector<Step> steps[2];
+  std::vector<int2> other[2];  // (member, matrix-core precision or 0)
+};
+
+// Most workgroups one item of a grouped launch takes.
+static constexpr int64_t kGroupItemBlocks = 2048;
 
 static int slot_for(HostProgram &hp, const ParamTensor &pt) {
   auto key = std::make_tuple(pt.kind, pt.param, pt.coeff, pt.folded + 2 * pt.diag);
@@ -704,6 +728,10 @@ struct tn_batch {
   int64_t gstride = 0;                 // elements per global-arena slot
   int gslots = 0;                      // slots (= most workgroups of one launch)
   std::vector<qtn::LevelNet> level;    // networks on the level executor
+  std::vector<qtn::LevelBin> lbins;    // level networks run with grouped launches
+  std::vector<int> lsolo;              // level networks run one by one, in chunks of parameter vectors
+  qtn::LItem *d_litems[2] = {nullptr, nullptr};
+  size_t litem_cap[2] = {0, 0};
   // device
   qtn::DNet *d_nets_fwd = nullptr, *d_nets_grad = nullptr;
   qtn::DOp *d_ops = nullptr;
@@ -756,9 +784,90 @@ static void free_batch_dev(tn_batch *b) {
   drop_timing_events(b);
   void *ptrs[] = {b->d_nets_fwd, b->d_nets_grad, b->d_ops, b->d_recs, b->d_srecs[0], b->d_srecs[1], b->d_tabs, b->d_task_net, b->d_gtask_net, b->d_garena, b->d_consts, b->d_ptens,
                   b->d_slots, b->d_bound, b->d_dbound, b->d_val, b->d_gnet, b->d_coef, b->d_larena, b->d_lscal,
-                  b->d_lpart};
+                  b->d_lpart, b->d_litems[0], b->d_litems[1]};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+}
+
+static std::string shape_class(int dtype, const DOp &op, int prec);
+
+// Matrix-core precision a level op runs with (0: a thin kernel).
+static int level_prec(const tn_batch *b, const DOp &op) {
+  if (!mfma_eligible(b->dtype, op)) return 0;
+  auto it = b->use_mfma.find(shape_class(b->dtype, op, b->mfma_prec));
+  return it == b->use_mfma.end() || it->second ? b->mfma_prec : 0;
+}
+
+// Item lists of the level bins for the current matrix-core choices,
+// uploaded to the device. Runs after every change of those choices, never
+// under capture.
+static int build_level_items(tn_batch *b) {
+  for (int v = 0; v < 2; ++v) {
+    std::vector<LItem> items;
+    for (LevelBin &bn : b->lbins) {
+      bn.steps[v].clear();
+      bn.other[v].clear();
+      int n_steps = 0;
+      for (int l : bn.lv) n_steps = std::max(n_steps, b->level[l].n_ops[v]);
+      for (int k = 0; k < n_steps; ++k) {
+        LevelBin::Step stp;
+        for (int kind = 0; kind < 2; ++kind) {
+          const int first = (int)items.size();
+          int blocks = 0;
+          for (size_t j = 0; j < bn.lv.size(); ++j) {
+            const LevelNet &ln = b->level[bn.lv[j]];
+            if (k >= ln.n_ops[v]) continue;
+            const DOp &op = b->hp.ops[ln.op_begin[v] + k];
+            const bool thin = op.type == OP_CONTRACT && level_prec(b, op) == 0;
+            if (kind == 0 ? !thin : op.type != OP_LEAFGRAD) continue;
+            const int lg = kind == 0 ? op.nFX + op.nB + op.nFY : op.nFX;
+            const int64_t work = ((int64_t)1 << lg) * b->max_sets;
+            LItem it{};
+            it.op = op;
+            pack_runs(op.maskX, it.ru.runsX);
+            pack_runs(op.maskY, it.ru.runsY);
+            it.base = bn.abase[j];
+            it.stride = ln.stride[v];
+            it.blk0 = blocks;
+            blocks += (int)std::max<int64_t>(1, std::min<int64_t>(kGroupItemBlocks, (work + 255) / 256));
+            items.push_back(it);
+          }
+          if (kind == 0) {
+            stp.t0 = first;
+            stp.nt = (int)items.size() - first;
+            stp.tb = blocks;
+          } else {
+            stp.l0 = first;
+            stp.nl = (int)items.size() - first;
+            stp.lb = blocks;
+          }
+        }
+        stp.o0 = (int)bn.other[v].size();
+        for (size_t j = 0; j < bn.lv.size(); ++j) {
+          const LevelNet &ln = b->level[bn.lv[j]];
+          if (k >= ln.n_ops[v]) continue;
+          const DOp &op = b->hp.ops[ln.op_begin[v] + k];
+          const int prec = level_prec(b, op);
+          if ((op.type == OP_CONTRACT && prec == 0) || op.type == OP_LEAFGRAD) continue;
+          bn.other[v].push_back(make_int2((int)j, prec));
+        }
+        stp.no = (int)bn.other[v].size() - stp.o0;
+        bn.steps[v].push_back(stp);
+      }
+    }
+    if (items.empty()) continue;
+    if (items.size() > b->litem_cap[v]) {
+      if (b->d_litems[v]) HIPCHK(hipFree(b->d_litems[v]));
+      b->d_litems[v] = nullptr;
+      HIPCHK(hipMalloc((void **)&b->d_litems[v], items.size() * sizeof(LItem)));
+      b->litem_cap[v] = items.size();
+    }
+    // earlier launches may still read the old lists
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(b->d_litems[v], items.data(), items.size() * sizeof(LItem), hipMemcpyHostToDevice));
+  }
+  b->gc.clear();
+  return TN_OK;
 }
 
 // 64-lane workgroups whose programs have a lane record for every op run a
@@ -900,6 +1009,8 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   if (const char *env = std::getenv("QTN_FUSED_LDS_MAX")) fused_max = std::atoll(env);
   int64_t gmem_max = kGmemMaxMacs;  // QTN_GMEM_MAX_MACS=0 turns the global-arena executor off
   if (const char *env = std::getenv("QTN_GMEM_MAX_MACS")) gmem_max = std::atoll(env);
+  int64_t level_budget = kLevelBudget;  // QTN_LEVEL_BUDGET (bytes): level arena limit
+  if (const char *env = std::getenv("QTN_LEVEL_BUDGET")) level_budget = std::max<int64_t>(1, std::atoll(env));
   std::vector<double> cost(n_nets);
   std::vector<int> fused_ids, gmem_ids;
   int maxbits = 0;
@@ -930,7 +1041,7 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
     } else {
       b->hp.nets_fwd.push_back(DNet{});
       b->hp.nets_grad.push_back(DNet{});
-      b->level.push_back(append_level(*n, lay, b->hp, i, eb, kLevelBudget, max_sets));
+      b->level.push_back(append_level(*n, lay, b->hp, i, eb, level_budget, max_sets));
       if (b->level.back().stride[0] >= kMaxArenaElems) {
         set_error("tn_batch_create: network " + std::to_string(i) + " needs " + std::to_string(b->level.back().stride[0]) +
                   " elements of working memory per parameter vector; the executor addresses at most 2^31");
@@ -997,11 +1108,32 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   if ((e = dalloc(&b->d_gnet, (size_t)n_nets * max_sets * std::max(1, b->n_params))) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_coef, (size_t)n_nets)) != hipSuccess) return fail(e, "hipMalloc");
   {
-    int64_t arena = 0, scal = 0, part = 0;
-    for (auto &ln : b->level) {
-      arena = std::max(arena, ln.stride[ln.grad_ok ? 1 : 0] * ln.chunk * eb);
-      scal = std::max(scal, (int64_t)ln.chunk * std::max(1, ln.n_comp) * 2);
+    // bins: level networks that take every parameter vector at once, packed
+    // in order while their regions fit the level budget together
+    int64_t arena = 0, scal = 0, part = 0, bin_elems = 0, bin_scal = 0;
+    for (int l = 0; l < (int)b->level.size(); ++l) {
+      const LevelNet &ln = b->level[l];
+      const int64_t per = ln.stride[ln.grad_ok ? 1 : 0];
       part = std::max(part, (int64_t)ln.chunk * kScalarParts * 2);
+      if (ln.chunk < max_sets) {
+        b->lsolo.push_back(l);
+        arena = std::max(arena, per * ln.chunk * eb);
+        scal = std::max(scal, (int64_t)ln.chunk * std::max(1, ln.n_comp) * 2);
+        continue;
+      }
+      const int64_t need = (per * max_sets + 63) / 64 * 64;
+      if (b->lbins.empty() || (bin_elems + need) * eb > level_budget) {
+        b->lbins.emplace_back();
+        bin_elems = bin_scal = 0;
+      }
+      LevelBin &bn = b->lbins.back();
+      bn.lv.push_back(l);
+      bn.abase.push_back(bin_elems);
+      bn.sbase.push_back(bin_scal);
+      bin_elems += need;
+      bin_scal += (int64_t)max_sets * std::max(1, ln.n_comp) * 2;
+      arena = std::max(arena, bin_elems * eb);
+      scal = std::max(scal, bin_scal);
     }
     b->level_bytes = arena;
     if (!b->level.empty()) {
@@ -1033,6 +1165,10 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   };
   for (auto &u : ups)
     if (u.n && (e = hipMemcpy(u.d, u.h, u.n, hipMemcpyHostToDevice)) != hipSuccess) return fail(e, "hipMemcpy");
+  if ((rc = build_level_items(B)) != TN_OK) {
+    free_batch_dev(B);
+    return rc;
+  }
   *out = b.release();
   return TN_OK;
 }
@@ -1152,7 +1288,48 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     }
   }
   const int eb = b->dtype == TN_C128 ? 16 : 8;
-  for (const LevelNet &ln : b->level) {
+  for (const LevelBin &bn : b->lbins) {
+    auto args = [&](size_t j) {
+      const LevelNet &ln = b->level[bn.lv[j]];
+      LevelArgs la{};
+      la.arena = (char *)b->d_larena + bn.abase[j] * eb;
+      la.stride = ln.stride[v];
+      la.n_sets = n_sets;
+      la.scal = b->d_lscal + bn.sbase[j];
+      la.n_comp = ln.n_comp;
+      la.part = b->d_lpart;
+      return la;
+    };
+    for (size_t j = 0; j < bn.lv.size() && e == hipSuccess; ++j) {
+      const LevelNet &ln = b->level[bn.lv[j]];
+      e = level_setup(b->dtype, args(j), (const char *)b->d_consts + (size_t)ln.const_begin * eb, ln.n_const,
+                      b->d_ptens + ln.ptens_begin, ln.n_ptens, b->d_bound, b->hp.per_set, 0, (int)ln.gbar_begin,
+                      grad ? (int)ln.ptens_elems : 0, st);
+    }
+    for (const LevelBin::Step &stp : bn.steps[v]) {
+      if (e == hipSuccess)
+        e = level_group(b->dtype, false, b->d_litems[v] + stp.t0, stp.nt, stp.tb, b->d_larena, n_sets, b->d_tabs, st);
+      if (e == hipSuccess)
+        e = level_group(b->dtype, true, b->d_litems[v] + stp.l0, stp.nl, stp.lb, b->d_larena, n_sets, b->d_tabs, st);
+      for (int q = stp.o0; q < stp.o0 + stp.no && e == hipSuccess; ++q) {
+        const int2 oj = bn.other[v][q];
+        const LevelNet &ln = b->level[bn.lv[oj.x]];
+        const DOp &op = b->hp.ops[ln.op_begin[v] + (int)(&stp - bn.steps[v].data())];
+        e = level_op(b->dtype, args(oj.x), op, b->d_tabs, oj.y, st);
+      }
+    }
+    for (size_t j = 0; j < bn.lv.size() && e == hipSuccess; ++j) {
+      const LevelNet &ln = b->level[bn.lv[j]];
+      e = level_finish(b->dtype, args(j), b->d_ptens + ln.ptens_begin, ln.n_ptens, b->d_dbound, b->hp.per_set, 0, ln.net,
+                       n_sets, b->n_params, a.out_val, a.out_grad, grad ? 1 : 0, st);
+    }
+    if (e != hipSuccess) {
+      b->poisoned = true;
+      return hip_fail(e, "level executor launch");
+    }
+  }
+  for (int l : b->lsolo) {
+    const LevelNet &ln = b->level[l];
     for (int s0 = 0; s0 < n_sets; s0 += ln.chunk) {
       LevelArgs la{};
       la.arena = b->d_larena;
@@ -1166,9 +1343,7 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
                       grad ? (int)ln.ptens_elems : 0, st);
       for (int o = 0; o < ln.n_ops[v] && e == hipSuccess; ++o) {
         const DOp &op = b->hp.ops[ln.op_begin[v] + o];
-        auto it = b->use_mfma.find(shape_class(b->dtype, op, b->mfma_prec));
-        const bool mf = it == b->use_mfma.end() || it->second;
-        e = level_op(b->dtype, la, op, b->d_tabs, mf ? b->mfma_prec : 0, st);
+        e = level_op(b->dtype, la, op, b->d_tabs, level_prec(b, op), st);
       }
       if (e == hipSuccess)
         e = level_finish(b->dtype, la, b->d_ptens + ln.ptens_begin, ln.n_ptens, b->d_dbound, b->hp.per_set, s0, ln.net,
@@ -1404,7 +1579,7 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
     found["mfma:" + kv.first] = b->use_mfma[kv.first];
   }
   write_cache(cache_path, found);
-  return TN_OK;
+  return build_level_items(b);
 }
 
 int batch_kernel_timing(tn_batch *b, int enable) {
@@ -1439,8 +1614,7 @@ int batch_set_precision(tn_batch *b, int prec) {
     return TN_EINVAL;
   }
   b->mfma_prec = prec;
-  b->gc.clear();
-  return TN_OK;
+  return build_level_items(b);
 }
 
 // Apply cached autotuner decisions (no timing).
@@ -1461,8 +1635,7 @@ int batch_apply_cache(tn_batch *b, const char *cache_path) {
   }
   for (auto &kv : m)
     if (kv.first.rfind("mfma:", 0) == 0) b->use_mfma[kv.first.substr(5)] = kv.second;
-  b->gc.clear();
-  return TN_OK;
+  return build_level_items(b);
 }
 
 int batch_info(const tn_batch *b, tn_batch_stats *s) {
@@ -1474,6 +1647,28 @@ int batch_info(const tn_batch *b, tn_batch_stats *s) {
   int levels = 0;
   for (auto &ln : b->level) levels = std::max(levels, ln.n_ops[1]);
   s->n_levels = levels;
+  s->n_level_bins = (int32_t)b->lbins.size();
+  s->n_level_chunked = (int32_t)b->lsolo.size();
+  for (int v = 0; v < 2; ++v) {
+    int64_t n = 0;
+    for (const LevelBin &bn : b->lbins) {
+      n += 2 * (int64_t)bn.lv.size();  // set-up and outputs
+      for (const LevelBin::Step &stp : bn.steps[v]) {
+        n += (stp.nt > 0) + (stp.nl > 0);
+        for (int q = stp.o0; q < stp.o0 + stp.no; ++q) {
+          const LevelNet &ln = b->level[bn.lv[bn.other[v][q].x]];
+          n += b->hp.ops[ln.op_begin[v] + (int)(&stp - bn.steps[v].data())].type == OP_SCALAR ? 2 : 1;
+        }
+      }
+    }
+    for (int l : b->lsolo) {
+      const LevelNet &ln = b->level[l];
+      int64_t per = 2;
+      for (int o = 0; o < ln.n_ops[v]; ++o) per += b->hp.ops[ln.op_begin[v] + o].type == OP_SCALAR ? 2 : 1;
+      n += per * ((b->max_sets + ln.chunk - 1) / ln.chunk);
+    }
+    (v == 0 ? s->level_launches_fwd : s->level_launches_grad) = (int32_t)std::min<int64_t>(n, INT32_MAX);
+  }
   s->n_programs = b->hp.n_programs;
   s->fused_block = b->block;
   s->sets_per_wave_fwd = b->spw[0];

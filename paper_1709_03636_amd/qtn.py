@@ -50,7 +50,9 @@ class tn_plan_stats(ctypes.Structure):
 class tn_batch_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("n_nets", "n_fused", "n_level", "n_levels", "lds_bytes_fwd",
                                                "lds_bytes_grad", "n_programs", "fused_block", "rec_only",
-                                               "sets_per_wave_fwd", "sets_per_wave_grad", "n_global")] + \
+                                               "sets_per_wave_fwd", "sets_per_wave_grad", "n_global",
+                                               "n_level_bins", "n_level_chunked", "level_launches_fwd",
+                                               "level_launches_grad")] + \
                [(n, ctypes.c_double) for n in ("flops_fwd", "bytes_fwd", "flops_grad", "bytes_grad")]
 
 

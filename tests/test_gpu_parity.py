@@ -268,9 +268,26 @@ def test_bind_params_kernel():
         np.testing.assert_allclose(got[s][256:], rx, atol=1e-14)
 
 
+def _mixed_level_budget(qtn, qaoa, n, e, S, monkeypatch):
+    """A level-arena budget (bytes) under which the level networks split into
+    several groups and, where the sizes allow, some run alone in chunks."""
+    best = None
+    for k in range(30, 8, -1):
+        monkeypatch.setenv("QTN_LEVEL_BUDGET", str(1 << k))
+        info = qaoa.MaxCut(n, e, 2, qtn.TN_C128, order="linegraph", max_sets=S).batch.info()
+        if info["n_level_bins"] >= 2 and best is None:
+            best = 1 << k
+        if info["n_level_bins"] >= 2 and info["n_level_chunked"] >= 1:
+            return 1 << k
+    return best
+
+
 def test_level_executor_matches_fused(monkeypatch):
     """The same batch on the LDS fused executor, on the global-arena fused
-    executor and on the level (one launch per step) executor."""
+    executor and on the level executor: all networks stepped together in one
+    group (one launch per step and kind), in several groups with some
+    networks run alone (arena budget lowered), and every network alone in
+    chunks of one parameter vector."""
     qtn, qaoa = _qtn(), _qaoa()
     n = 14
     e = workloads.random_regular_graph(3, n, 8)
@@ -279,19 +296,32 @@ def test_level_executor_matches_fused(monkeypatch):
     ref = np.array([gradients.cost(n, e, list(a)) for a in ang.cpu().numpy()])
     ps = np.array([gradients.parameter_shift(n, e, list(a)) for a in ang.cpu().numpy()])
     res = {}
-    for mode, lim, gmem in (("fused", None, None), ("global", "0", None), ("level", "0", "0")):
-        for var, val in (("QTN_FUSED_LDS_MAX", lim), ("QTN_GMEM_MAX_MACS", gmem)):
+    monkeypatch.setenv("QTN_FUSED_LDS_MAX", "0")
+    monkeypatch.setenv("QTN_GMEM_MAX_MACS", "0")
+    mixed = _mixed_level_budget(qtn, qaoa, n, e, S, monkeypatch)
+    assert mixed is not None
+    for mode, lim, gmem, budget in (("fused", None, None, None), ("global", "0", None, None),
+                                    ("level", "0", "0", None), ("level-mixed", "0", "0", str(mixed)),
+                                    ("level-chunked", "0", "0", "1")):
+        for var, val in (("QTN_FUSED_LDS_MAX", lim), ("QTN_GMEM_MAX_MACS", gmem), ("QTN_LEVEL_BUDGET", budget)):
             if val is None:
                 monkeypatch.delenv(var, raising=False)
             else:
                 monkeypatch.setenv(var, val)
         model = qaoa.MaxCut(n, e, 2, qtn.TN_C128, order="linegraph", max_sets=S)
         info = model.batch.info()
-        if mode == "level":
+        if mode.startswith("level"):
             assert info["n_level"] == len(e) and info["n_fused"] == 0 and info["n_global"] == 0
+        if mode == "level":
+            assert info["n_level_bins"] == 1 and info["n_level_chunked"] == 0
+        if mode == "level-mixed":
+            assert info["n_level_bins"] >= 2
+        if mode == "level-chunked":
+            assert info["n_level_bins"] == 0 and info["n_level_chunked"] == len(e)
         if mode == "global":
             assert info["n_global"] == len(e) and info["n_fused"] == 0 and info["n_level"] == 0
-        _say(f"executor {mode} n_fused={info['n_fused']} n_global={info['n_global']} n_level={info['n_level']}")
+        _say(f"executor {mode} n_fused={info['n_fused']} n_global={info['n_global']} n_level={info['n_level']} "
+             f"bins={info['n_level_bins']} chunked={info['n_level_chunked']} launches={info['level_launches_grad']}")
         obj, grad = model.value_and_grad(ang)
         torch.cuda.synchronize()
         res[mode] = (obj.cpu().numpy(), grad.cpu().numpy())
