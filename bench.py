@@ -266,6 +266,77 @@ def next_rows(model, params, edges, st, dev):
     return res
 
 
+def batching_grid(st, dev):
+    """The batching configurations: seeded random 4- and 5-regular graphs with
+    n in {50, 70, 100}, p in {1, 2}; all edge light-cone networks x 64 angle
+    sets per batch, forward + adjoint gradient from a captured graph, complex64
+    with split-BF16 matrix-core products (FP32 accumulation). Also the same
+    batches with the diagonal gates on hyperedge wires. Error against the FP64
+    oracle: closed form for every edge and set at p = 1, the oracle's
+    light-cone contraction on 4 sampled (edge, set) pairs at p = 2."""
+    import torch
+    import workloads
+    from oracle import closed_form, gates, tensornet
+    from paper_1709_03636_amd import qaoa, qtn
+    rows = []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for d in (4, 5):
+        for n in (50, 70, 100):
+            for p in (1, 2):
+                e = workloads.random_regular_graph(d, n, GRAPH_SEED)
+                ang = np.array(workloads.qaoa_angles(ANGLE_SEED, N_SETS, p))
+                prm = torch.tensor(ang, dtype=torch.float64, device=dev)
+                if p == 1:
+                    ref = {(i, s): v for s in range(N_SETS)
+                           for i, v in enumerate(closed_form.zz_p1(n, e, ang[s, 0], ang[s, 1]))}
+                else:
+                    rng = workloads.SplitMix64(d * 1000 + n)
+                    ref = {}
+                    for _ in range(4):
+                        i, s = rng.below(len(e)), rng.below(N_SETS)
+                        gl = gates.qaoa_gate_list(n, e, ang[s, :p], ang[s, p:])[n:]
+                        pauli = [0] * n
+                        pauli[e[i][0]] = pauli[e[i][1]] = 3
+                        ref[(i, s)] = tensornet.expectation(n, gl, pauli, init=[np.array([1.0, 1.0]) / math.sqrt(2)] * n,
+                                                            lightcone=True).real
+                row = {"d": d, "n": n, "p": p, "edges": len(e)}
+                for mode in ("dense", "diagonal"):
+                    m = qaoa.MaxCut(n, e, p, qtn.TN_C64, order="linegraph", max_sets=N_SETS, trials=4,
+                                    diagonal=mode == "diagonal")
+                    m.batch.set_precision(qtn.TN_MFMA_BF16X3)
+                    m.batch.autotune(prm, reps=2, stream=st)
+                    out = torch.empty((len(e), N_SETS, 2), dtype=torch.float64, device=dev)
+                    obj = torch.empty(N_SETS, dtype=torch.float64, device=dev)
+                    grad = torch.empty((N_SETS, 2 * p), dtype=torch.float64, device=dev)
+                    m.batch.grad(prm, out=out, obj=obj, grad=grad, stream=st)
+                    st.synchronize()
+                    o = out.cpu().numpy()
+                    err = max(abs(o[i, s, 0] - v) for (i, s), v in ref.items())
+                    for _ in range(2):
+                        m.batch.run_graph(True, prm, obj=obj, grad=grad, stream=st)
+                    reps = 3
+                    ev0.record(st)
+                    for _ in range(reps):
+                        m.batch.run_graph(True, prm, obj=obj, grad=grad, stream=st)
+                    ev1.record(st)
+                    torch.cuda.synchronize()
+                    ms = ev0.elapsed_time(ev1) / reps
+                    inf = m.batch.info()
+                    row[mode] = {"ms_per_step": ms, "fwd_grad_networks_per_s": len(e) * N_SETS / (ms * 1e-3),
+                                 "max_abs_err_zz": float(err),
+                                 "executors": {"lds_fused": inf["n_fused"], "global_arena": inf["n_global"],
+                                               "level": inf["n_level"]},
+                                 "flops_per_set": inf["flops_fwd"] + inf["flops_grad"]}
+                    del m
+                rows.append(row)
+                log(f"batching grid: {row}")
+    return {"workload": "all edge light-cone networks x 64 angle sets, fwd + adjoint grad, graph replay, complex64 "
+                        "with split-BF16 matrix-core products; diagonal: ZZ gates on hyperedge wires",
+            "oracle_check": "closed form, all edges and sets (p=1); FP64 light-cone contraction, 4 sampled (edge, "
+                            "set) pairs (p=2)",
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +346,7 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-next", action="store_true", help="skip the optimisation / answer-string / noise lines")
+    ap.add_argument("--no-grid", action="store_true", help="skip the 4-/5-regular batching grid")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note "
@@ -445,6 +517,7 @@ def main():
         log(f"dense/MFMA: {mfma}")
 
     nxt = None if args.no_next else next_rows(model, params, edges, st, dev)
+    grid = None if args.no_grid else batching_grid(st, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -479,6 +552,7 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes, "algorithmic_flops_per_launch": alg_flops},
         "mfma_path": mfma,
         "next_rows": nxt,
+        "batching_grid": grid,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
