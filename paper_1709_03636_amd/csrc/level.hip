@@ -9,6 +9,7 @@
 #include <algorithm>
 
 #include "device.hpp"
+#include "group.hpp"
 #include "internal.hpp"
 
 namespace qtn {
@@ -263,22 +264,6 @@ __global__ __launch_bounds__(256) void level_finish_kernel(LevelArgs a, const DP
 
 // --- grouped launches: one step of many networks ---------------------------------------------
 
-// Item of workgroup blockIdx.x (the last with blk0 <= blockIdx.x) and the
-// workgroup's rank / count within it.
-__device__ __forceinline__ int l_item(const LItem *__restrict__ items, int n, int *rank, int *count) {
-  int lo = 0, hi = n - 1;
-  const int b = (int)blockIdx.x;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (items[mid].blk0 <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  const int end = lo + 1 < n ? items[lo + 1].blk0 : (int)gridDim.x;
-  *rank = b - items[lo].blk0;
-  *count = end - items[lo].blk0;
-  return lo;
-}
-
 // Thin contractions of several networks at once: each item is one op of one
 // network, with the addressing of level_contract_kernel inside the
 // network's own arena region.
@@ -286,7 +271,7 @@ template <typename V>
 __global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *__restrict__ items, int n, V *arena,
                                                                    int n_sets, const int32_t *__restrict__ tabs) {
   int rank, count;
-  const LItem &it = items[l_item(items, n, &rank, &count)];
+  const LItem &it = items[group_item(items, n, &rank, &count)];
   const DOp op = it.op;
   const int lgOut = op.nFX + op.nB + op.nFY;
   const int64_t nOut = (int64_t)1 << lgOut;
@@ -325,7 +310,7 @@ template <typename V>
 __global__ __launch_bounds__(256) void level_group_leafgrad_kernel(const LItem *__restrict__ items, int n, V *arena,
                                                                    int n_sets, const int32_t *__restrict__ tabs) {
   int rank, count;
-  const LItem &it = items[l_item(items, n, &rank, &count)];
+  const LItem &it = items[group_item(items, n, &rank, &count)];
   const DOp op = it.op;
   const int m = 1 << op.nFX;
   const int64_t total = (int64_t)m * n_sets;

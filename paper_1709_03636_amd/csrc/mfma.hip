@@ -6,14 +6,17 @@
 // tiles are staged into LDS, so X and Y are read in their stored layout.
 //
 // Complex products use four real products (4M) on v_mfma_f32_16x16x4_f32
-// with FP32 accumulation (or split-BF16 products, below): with the summed index interleaved as
-// (re, im) pairs, Re Z = [Xr, -Xi] . [Yr; Yi] and Im Z = [Xi, Xr] . [Yr; Yi].
-// Tile: 64 x 64 complex outputs per workgroup of four waves (32 x 32 each),
-// 16 complex summed entries per LDS stage, next stage prefetched into
-// registers while the matrix cores work on the current one.
+// with FP32 accumulation (or split-BF16 products, below): with the summed
+// index interleaved as (re, im) pairs, Re Z = [Xr, -Xi] . [Yr; Yi] and
+// Im Z = [Xi, Xr] . [Yr; Yi].
+// Workgroup tile: BM x BN complex outputs (64 x 64, or 16 x 64 / 64 x 16
+// when one free index has only 4 or 5 bits) for four waves; 16 complex
+// summed entries per LDS stage, the next stage prefetched into registers
+// while the matrix cores work on the current one.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
+#include "group.hpp"
 #include "internal.hpp"
 
 namespace qtn {
@@ -22,9 +25,22 @@ typedef float mf4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16;
-constexpr int AS = BK + 1;  // LDS row stride of the X tile (float2), padded against bank conflicts
-constexpr int BS = BN + 2;  // LDS row stride of the Y tile
+constexpr int BK = 16;
+
+// Wave layout of a BM x BN tile: GM x GN waves, each WM x WN MFMA tiles of
+// 16 x 16; NX / NY staged X / Y entries per thread and stage.
+template <int BM, int BN>
+struct TileT {
+  static constexpr int LM = BM == 64 ? 6 : 4, LN = BN == 64 ? 6 : 4;
+  static constexpr int GM = (BM == 64 && BN == 64) ? 2 : BM / 16;
+  static constexpr int GN = 4 / GM;
+  static constexpr int WM = BM / 16 / GM, WN = BN / 16 / GN;
+  static constexpr int NX = BM / 16, NY = BN / 16;
+  static constexpr int AS = BK + 1;  // LDS row stride of the X tile (float2), padded against bank conflicts
+  static constexpr int BS = BN + 2;  // LDS row stride of the Y tile
+  static constexpr int PS = BK + 4;  // packed-tile row stride (dwords), 16-byte aligned rows
+  static_assert(GM * GN == 4 && WM >= 1 && WN >= 1, "tile");
+};
 
 __device__ __forceinline__ uint32_t g_pdep(uint32_t v, uint32_t mask) {
   uint32_t r = 0;
@@ -44,97 +60,96 @@ __device__ __forceinline__ int2 g_tab(const int32_t *__restrict__ tb, int nS, in
   return make_int2(tb[2 * lo] + h[2 * hi], tb[2 * lo + 1] + h[2 * hi + 1]);
 }
 
-}  // namespace
+// Staging assignment: each thread moves NX X and NY Y entries per stage.
+// Summed-index offsets add over disjoint bits, so the offset of k0 + k (k0
+// a multiple of BK, k < BK) is t(k0) + t(k): the per-thread parts t(k) are
+// fixed, and t(k0) is one workgroup-uniform lookup per stage.
+// XK: X's lowest address bit is summed (stage X with k fastest), else m
+// fastest; YK likewise for Y.
+template <bool XK, bool YK, int BM, int BN>
+struct Stager {
+  using T = TileT<BM, BN>;
+  int xr[T::NX], xk[T::NX], yk[T::NY], yn[T::NY];
+  uint32_t xrow[T::NX], ycol[T::NY];
+  float2 xv[T::NX], yv[T::NY];
+  __device__ __forceinline__ Stager(const DOp &op, const int32_t *tab, int m0, int n0) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < T::NX; ++i) {
+      const int e = tid + 256 * i;
+      if (XK) { xk[i] = e & (BK - 1); xr[i] = e >> 4; } else { xr[i] = e & (BM - 1); xk[i] = e >> T::LM; }
+      xrow[i] = g_pdep((uint32_t)(m0 + xr[i]), op.maskX) + (uint32_t)g_tab(tab, op.nS, xk[i]).x;
+    }
+#pragma unroll
+    for (int i = 0; i < T::NY; ++i) {
+      const int e = tid + 256 * i;
+      if (YK) { yk[i] = e & (BK - 1); yn[i] = e >> 4; } else { yn[i] = e & (BN - 1); yk[i] = e >> T::LN; }
+      ycol[i] = g_pdep((uint32_t)(n0 + yn[i]), op.maskY) + (uint32_t)g_tab(tab, op.nS, yk[i]).y;
+    }
+  }
+  __device__ __forceinline__ void fetch(const float2 *X, const float2 *Y, const DOp &op, const int32_t *tab, int k0) {
+    const int2 t0 = g_tab(tab, op.nS, k0);
+    const int bx = __builtin_amdgcn_readfirstlane(t0.x), by = __builtin_amdgcn_readfirstlane(t0.y);
+#pragma unroll
+    for (int i = 0; i < T::NX; ++i) xv[i] = X[xrow[i] + bx];
+#pragma unroll
+    for (int i = 0; i < T::NY; ++i) yv[i] = Y[by + ycol[i]];
+  }
+};
 
-// XK: X's lowest address bit is summed (stage X with k fastest), else m fastest.
-// YK: Y's lowest address bit is summed (stage Y with k fastest), else n fastest.
-template <bool XK, bool YK>
-__global__ __launch_bounds__(256) void mfma_cgemm_kernel(LevelArgs a, DOp op, const int32_t *__restrict__ tab) {
-  __shared__ float2 As[BM * AS];
-  __shared__ float2 Bs[BK * BS];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int nT = 1 << (op.nFY - 6), mT = 1 << (op.nFX - 6);
-  // XCD-aware tile order: consecutive workgroups land on different XCDs, so
-  // give each XCD a contiguous run of tiles (shared X rows stay in its L2)
-  const int nblk = nT * mT;
-  int b = blockIdx.x;
-  if (nblk % 8 == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
-  const int n0 = (b % nT) * BN, m0 = (b / nT) * BM;
-  float2 *base = reinterpret_cast<float2 *>(a.arena) + (int64_t)blockIdx.z * a.stride;
+// Output tile `tile` of the op on one parameter vector's arena slice.
+template <bool XK, bool YK, int BM, int BN>
+__device__ __forceinline__ void f32_tile(float2 *__restrict__ As, float2 *__restrict__ Bs, float2 *base, const DOp &op,
+                                         const int32_t *__restrict__ tab, int tile) {
+  using T = TileT<BM, BN>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nT = 1 << (op.nFY - T::LN);
+  const int n0 = (tile & (nT - 1)) * BN, m0 = (tile >> (op.nFY - T::LN)) * BM;
   const float2 *X = base + op.x;
   const float2 *Y = base + op.y;
   float2 *Z = base + op.z;
   const int K = 1 << op.nS;
-
-  // staging assignment: each thread moves 4 X and 4 Y entries per stage.
-  // Summed-index offsets add over disjoint bits, so the offset of k0 + k
-  // (k0 a multiple of BK, k < BK) is t(k0) + t(k): the per-thread parts
-  // t(k) are fixed, and t(k0) is one workgroup-uniform lookup per stage.
-  int xr[4], xk[4], yk[4], yn[4];
-  uint32_t xrow[4], ycol[4];
+  Stager<XK, YK, BM, BN> sg(op, tab, m0, n0);
+  mf4 cre[T::WM][T::WN], cim[T::WM][T::WN];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int e = tid + 256 * i;
-    if (XK) { xk[i] = e & (BK - 1); xr[i] = e >> 4; } else { xr[i] = e & (BM - 1); xk[i] = e >> 6; }
-    if (YK) { yk[i] = e & (BK - 1); yn[i] = e >> 4; } else { yn[i] = e & (BN - 1); yk[i] = e >> 6; }
-    xrow[i] = g_pdep((uint32_t)(m0 + xr[i]), op.maskX) + (uint32_t)g_tab(tab, op.nS, xk[i]).x;
-    ycol[i] = g_pdep((uint32_t)(n0 + yn[i]), op.maskY) + (uint32_t)g_tab(tab, op.nS, yk[i]).y;
-  }
-  float2 xv[4], yv[4];
-  auto fetch = [&](int k0) {
-    const int2 t0 = g_tab(tab, op.nS, k0);
-    const int bx = __builtin_amdgcn_readfirstlane(t0.x), by = __builtin_amdgcn_readfirstlane(t0.y);
+  for (int i = 0; i < T::WM; ++i)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      xv[i] = X[xrow[i] + bx];
-      yv[i] = Y[by + ycol[i]];
-    }
-  };
-  auto stash = [&]() {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      As[xr[i] * AS + xk[i]] = xv[i];
-      Bs[yk[i] * BS + yn[i]] = yv[i];
-    }
-  };
-  mf4 cre[2][2], cim[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < T::WN; ++j) {
       cre[i][j] = mf4{0.f, 0.f, 0.f, 0.f};
       cim[i][j] = mf4{0.f, 0.f, 0.f, 0.f};
     }
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int wr = (wave / T::GN) * 16 * T::WM, wc = (wave % T::GN) * 16 * T::WN;
   const int lr = lane & 15, lk = lane >> 4;  // MFMA operand row/col and real-k index
   const int part = lk & 1;
 
-  fetch(0);
+  sg.fetch(X, Y, op, tab, 0);
   for (int k0 = 0; k0 < K; k0 += BK) {
     __syncthreads();
-    stash();
+#pragma unroll
+    for (int i = 0; i < T::NX; ++i) As[sg.xr[i] * T::AS + sg.xk[i]] = sg.xv[i];
+#pragma unroll
+    for (int i = 0; i < T::NY; ++i) Bs[sg.yk[i] * T::BS + sg.yn[i]] = sg.yv[i];
     __syncthreads();
-    if (k0 + BK < K) fetch(k0 + BK);
+    if (k0 + BK < K) sg.fetch(X, Y, op, tab, k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 2) {
       const int kc = kk + (lk >> 1);
-      float are[2], aim[2], bv[2];
+      float are[T::WM], aim[T::WM], bv[T::WN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const float2 x = As[(wr + 16 * i + lr) * AS + kc];
+      for (int i = 0; i < T::WM; ++i) {
+        const float2 x = As[(wr + 16 * i + lr) * T::AS + kc];
         are[i] = part ? -x.y : x.x;  // [Xr, -Xi]
         aim[i] = part ? x.x : x.y;   // [Xi,  Xr]
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const float2 y = Bs[kc * BS + wc + 16 * j + lr];
+      for (int j = 0; j < T::WN; ++j) {
+        const float2 y = Bs[kc * T::BS + wc + 16 * j + lr];
         bv[j] = part ? y.y : y.x;  // [Yr; Yi]
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < T::WM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < T::WN; ++j) {
           cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(are[i], bv[j], cre[i][j], 0, 0, 0);
           cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(aim[i], bv[j], cim[i][j], 0, 0, 0);
         }
@@ -143,9 +158,9 @@ __global__ __launch_bounds__(256) void mfma_cgemm_kernel(LevelArgs a, DOp op, co
   // D layout of the 16x16 tile: lane holds rows 4*(lane/16)+r, column lane%16
   const int N = 1 << op.nFY;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < T::WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < T::WN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wr + 16 * i + 4 * lk + r;
@@ -164,8 +179,6 @@ __global__ __launch_bounds__(256) void mfma_cgemm_kernel(LevelArgs a, DOp op, co
 // one 32-deep MFMA per product.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-namespace {
 
 __device__ __forceinline__ uint32_t f2bf(float x) {
   uint32_t u = __float_as_uint(x);
@@ -186,94 +199,68 @@ __device__ __forceinline__ bf16x8 as_bf(u32x4 v) { return __builtin_bit_cast(bf1
 __device__ __forceinline__ u32x4 neg_im(u32x4 v) { return v ^ (u32x4){0x80000000u, 0x80000000u, 0x80000000u, 0x80000000u}; }
 __device__ __forceinline__ u32x4 swap_ri(u32x4 v) { return (v >> 16) | (v << 16); }
 
-constexpr int PS = BK + 4;  // packed-tile row stride (dwords), 16-byte aligned rows
-
-}  // namespace
-
-template <bool XK, bool YK>
-__global__ __launch_bounds__(256) void mfma_cgemm_bf16x3_kernel(LevelArgs a, DOp op, const int32_t *__restrict__ tab) {
-  __shared__ __align__(16) uint32_t Ah[BM * PS], Al[BM * PS];  // [m][k] packed pairs
-  __shared__ __align__(16) uint32_t Bh[BN * PS], Bl[BN * PS];  // [n][k] (transposed) packed pairs
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int nT = 1 << (op.nFY - 6), mT = 1 << (op.nFX - 6);
-  const int nblk = nT * mT;
-  int b = blockIdx.x;
-  if (nblk % 8 == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
-  const int n0 = (b % nT) * BN, m0 = (b / nT) * BM;
-  float2 *base = reinterpret_cast<float2 *>(a.arena) + (int64_t)blockIdx.z * a.stride;
+// LDS of the split-BF16 tile: X as [m][k] and Y as [n][k] (transposed)
+// packed pairs, hi and lo parts.
+template <bool XK, bool YK, int BM, int BN>
+__device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t *__restrict__ Al,
+                                            uint32_t *__restrict__ Bh, uint32_t *__restrict__ Bl, float2 *base,
+                                            const DOp &op, const int32_t *__restrict__ tab, int tile) {
+  using T = TileT<BM, BN>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nT = 1 << (op.nFY - T::LN);
+  const int n0 = (tile & (nT - 1)) * BN, m0 = (tile >> (op.nFY - T::LN)) * BM;
   const float2 *X = base + op.x;
   const float2 *Y = base + op.y;
   float2 *Z = base + op.z;
   const int K = 1 << op.nS;
-
-  int xr[4], xk[4], yk[4], yn[4];
-  uint32_t xrow[4], ycol[4];
+  Stager<XK, YK, BM, BN> sg(op, tab, m0, n0);
+  mf4 cre[T::WM][T::WN], cim[T::WM][T::WN];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int e = tid + 256 * i;
-    if (XK) { xk[i] = e & (BK - 1); xr[i] = e >> 4; } else { xr[i] = e & (BM - 1); xk[i] = e >> 6; }
-    if (YK) { yk[i] = e & (BK - 1); yn[i] = e >> 4; } else { yn[i] = e & (BN - 1); yk[i] = e >> 6; }
-    xrow[i] = g_pdep((uint32_t)(m0 + xr[i]), op.maskX) + (uint32_t)g_tab(tab, op.nS, xk[i]).x;
-    ycol[i] = g_pdep((uint32_t)(n0 + yn[i]), op.maskY) + (uint32_t)g_tab(tab, op.nS, yk[i]).y;
-  }
-  float2 xv[4], yv[4];
-  auto fetch = [&](int k0) {
-    const int2 t0 = g_tab(tab, op.nS, k0);
-    const int bx = __builtin_amdgcn_readfirstlane(t0.x), by = __builtin_amdgcn_readfirstlane(t0.y);
+  for (int i = 0; i < T::WM; ++i)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      xv[i] = X[xrow[i] + bx];
-      yv[i] = Y[by + ycol[i]];
-    }
-  };
-  auto stash = [&]() {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      uint32_t h, l;
-      split_pack(xv[i], h, l);
-      Ah[xr[i] * PS + xk[i]] = h;
-      Al[xr[i] * PS + xk[i]] = l;
-      split_pack(yv[i], h, l);
-      Bh[yn[i] * PS + yk[i]] = h;
-      Bl[yn[i] * PS + yk[i]] = l;
-    }
-  };
-
-  mf4 cre[2][2], cim[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < T::WN; ++j) {
       cre[i][j] = mf4{0.f, 0.f, 0.f, 0.f};
       cim[i][j] = mf4{0.f, 0.f, 0.f, 0.f};
     }
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int wr = (wave / T::GN) * 16 * T::WM, wc = (wave % T::GN) * 16 * T::WN;
   const int lr = lane & 15, lg = lane >> 4;  // operand row/col, group of 4 complex summed entries
 
-  fetch(0);
+  sg.fetch(X, Y, op, tab, 0);
   for (int k0 = 0; k0 < K; k0 += BK) {
     __syncthreads();
-    stash();
+#pragma unroll
+    for (int i = 0; i < T::NX; ++i) {
+      uint32_t h, l;
+      split_pack(sg.xv[i], h, l);
+      Ah[sg.xr[i] * T::PS + sg.xk[i]] = h;
+      Al[sg.xr[i] * T::PS + sg.xk[i]] = l;
+    }
+#pragma unroll
+    for (int i = 0; i < T::NY; ++i) {
+      uint32_t h, l;
+      split_pack(sg.yv[i], h, l);
+      Bh[sg.yn[i] * T::PS + sg.yk[i]] = h;
+      Bl[sg.yn[i] * T::PS + sg.yk[i]] = l;
+    }
     __syncthreads();
-    if (k0 + BK < K) fetch(k0 + BK);
-    u32x4 ah[2], al[2], bh[2], bl[2];
+    if (k0 + BK < K) sg.fetch(X, Y, op, tab, k0 + BK);
+    u32x4 ah[T::WM], al[T::WM], bh[T::WN], bl[T::WN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      ah[i] = *reinterpret_cast<const u32x4 *>(&Ah[(wr + 16 * i + lr) * PS + 4 * lg]);
-      al[i] = *reinterpret_cast<const u32x4 *>(&Al[(wr + 16 * i + lr) * PS + 4 * lg]);
+    for (int i = 0; i < T::WM; ++i) {
+      ah[i] = *reinterpret_cast<const u32x4 *>(&Ah[(wr + 16 * i + lr) * T::PS + 4 * lg]);
+      al[i] = *reinterpret_cast<const u32x4 *>(&Al[(wr + 16 * i + lr) * T::PS + 4 * lg]);
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      bh[j] = *reinterpret_cast<const u32x4 *>(&Bh[(wc + 16 * j + lr) * PS + 4 * lg]);
-      bl[j] = *reinterpret_cast<const u32x4 *>(&Bl[(wc + 16 * j + lr) * PS + 4 * lg]);
+    for (int j = 0; j < T::WN; ++j) {
+      bh[j] = *reinterpret_cast<const u32x4 *>(&Bh[(wc + 16 * j + lr) * T::PS + 4 * lg]);
+      bl[j] = *reinterpret_cast<const u32x4 *>(&Bl[(wc + 16 * j + lr) * T::PS + 4 * lg]);
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < T::WM; ++i) {
       const bf16x8 arh = as_bf(neg_im(ah[i])), arl = as_bf(neg_im(al[i]));
       const bf16x8 aih = as_bf(ah[i]), ail = as_bf(al[i]);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < T::WN; ++j) {
         const bf16x8 brh = as_bf(bh[j]), brl = as_bf(bl[j]);
         const bf16x8 bih = as_bf(swap_ri(bh[j])), bil = as_bf(swap_ri(bl[j]));
         cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brh, cre[i][j], 0, 0, 0);
@@ -287,9 +274,9 @@ __global__ __launch_bounds__(256) void mfma_cgemm_bf16x3_kernel(LevelArgs a, DOp
   }
   const int N = 1 << op.nFY;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < T::WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < T::WN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wr + 16 * i + 4 * lg + r;
@@ -298,27 +285,145 @@ __global__ __launch_bounds__(256) void mfma_cgemm_bf16x3_kernel(LevelArgs a, DOp
       }
 }
 
-// True when the MFMA path takes this op (complex64, tiles divide the shape).
-bool mfma_eligible(int dtype, const DOp &op) {
-  return dtype == TN_C64 && op.type == OP_CONTRACT && op.nB == 0 && op.nFX >= 6 && op.nFY >= 6 && op.nS >= 4;
+// One tile of either precision with its LDS.
+template <int PREC, bool XK, bool YK, int BM, int BN>
+__device__ __forceinline__ void any_tile(float2 *base, const DOp &op, const int32_t *__restrict__ tab, int tile) {
+  using T = TileT<BM, BN>;
+  if constexpr (PREC == TN_MFMA_BF16X3) {
+    __shared__ __align__(16) uint32_t Ah[BM * T::PS], Al[BM * T::PS];
+    __shared__ __align__(16) uint32_t Bh[BN * T::PS], Bl[BN * T::PS];
+    bf16x3_tile<XK, YK, BM, BN>(Ah, Al, Bh, Bl, base, op, tab, tile);
+  } else {
+    __shared__ float2 As[BM * T::AS];
+    __shared__ float2 Bs[BK * T::BS];
+    f32_tile<XK, YK, BM, BN>(As, Bs, base, op, tab, tile);
+  }
 }
+
+// XCD-aware order of a run of `total` workgroups: consecutive workgroups
+// land on different XCDs, so each XCD is given a contiguous run of tiles
+// (shared operand rows stay in its L2).
+__device__ __forceinline__ int xcd_order(int b, int total) {
+  return total % 8 == 0 ? (b & 7) * (total >> 3) + (b >> 3) : b;
+}
+
+}  // namespace
+
+// One op: grid (tiles, 1, parameter vectors).
+template <int PREC, bool XK, bool YK, int BM, int BN>
+__global__ __launch_bounds__(256) void mfma_cgemm_kernel(LevelArgs a, DOp op, const int32_t *__restrict__ tab) {
+  const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
+  float2 *base = reinterpret_cast<float2 *>(a.arena) + (int64_t)blockIdx.z * a.stride;
+  any_tile<PREC, XK, YK, BM, BN>(base, op, tab, b);
+}
+
+// One step of several networks: each item is one op in its network's arena
+// region, on (tiles x parameter vectors) workgroups; the workgroups of
+// parameter vectors past n_sets return at once.
+template <int PREC, bool XK, bool YK, int BM, int BN>
+__global__ __launch_bounds__(256) void mfma_group_kernel(const LItem *__restrict__ items, int n, float2 *arena,
+                                                         int n_sets, const int32_t *__restrict__ tabs) {
+  using T = TileT<BM, BN>;
+  int rank, count;
+  const LItem &it = items[group_item(items, n, &rank, &count)];
+  const DOp op = it.op;
+  const int lt = op.nFX - T::LM + op.nFY - T::LN;  // log2 tiles per parameter vector
+  const int b = xcd_order(rank, count);
+  const int set = b >> lt, tile = b & ((1 << lt) - 1);
+  if (set >= n_sets) return;
+  any_tile<PREC, XK, YK, BM, BN>(arena + it.base + (int64_t)set * it.stride, op, tabs + op.tab, tile);
+}
+
+// True when the MFMA path takes this op: complex64, no batch bits, at least
+// 16 summed entries, both free indices at least 16 wide and one at least 64
+// (tiles 64 x 64, 16 x 64 or 64 x 16 divide the shape).
+bool mfma_eligible(int dtype, const DOp &op) {
+  return dtype == TN_C64 && op.type == OP_CONTRACT && op.nB == 0 && op.nS >= 4 && op.nFX >= 4 && op.nFY >= 4 &&
+         (op.nFX >= 6 || op.nFY >= 6);
+}
+
+// Tile rows / columns of an eligible op.
+static inline int tile_m(const DOp &op) { return op.nFX >= 6 ? 64 : 16; }
+static inline int tile_n(const DOp &op) { return op.nFY >= 6 ? 64 : 16; }
+
+// Workgroups of an eligible op per parameter vector.
+int mfma_tiles(const DOp &op) {
+  return 1 << (op.nFX - (tile_m(op) == 64 ? 6 : 4) + op.nFY - (tile_n(op) == 64 ? 6 : 4));
+}
+
+// Kernel variant of an op: bit 0 XK, bit 1 YK, bit 2 BM = 16, bit 3 BN = 16,
+// bit 4 split-BF16.
+int mfma_variant(const DOp &op, int prec) {
+  return (!(op.maskX & 1u) ? 1 : 0) | (!(op.maskY & 1u) ? 2 : 0) | (tile_m(op) == 16 ? 4 : 0) |
+         (tile_n(op) == 16 ? 8 : 0) | (prec == TN_MFMA_BF16X3 ? 16 : 0);
+}
+
+namespace {
+
+template <int PREC, bool XK, bool YK, int BM, int BN>
+void launch_one(const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream_t st) {
+  hipLaunchKernelGGL((mfma_cgemm_kernel<PREC, XK, YK, BM, BN>), dim3(mfma_tiles(op), 1, a.n_sets), dim3(256), 0, st, a,
+                     op, tab);
+}
+
+template <int PREC, bool XK, bool YK, int BM, int BN>
+void launch_group(const LItem *items, int n, int blocks, void *arena, int n_sets, const int32_t *tabs, hipStream_t st) {
+  hipLaunchKernelGGL((mfma_group_kernel<PREC, XK, YK, BM, BN>), dim3(blocks), dim3(256), 0, st, items, n,
+                     (float2 *)arena, n_sets, tabs);
+}
+
+// Calls F<PREC, XK, YK, BM, BN>::run(args...) for a variant index; false
+// for an index without a kernel.
+template <template <int, bool, bool, int, int> class F, typename... A>
+bool dispatch(int v, A... args) {
+#define QTN_TILE(PREC, XK, YK, BM, BN)              \
+  case (XK ? 1 : 0) | (YK ? 2 : 0) | (BM == 16 ? 4 : 0) | (BN == 16 ? 8 : 0) | (PREC == TN_MFMA_BF16X3 ? 16 : 0): \
+    F<PREC, XK, YK, BM, BN>::run(args...);          \
+    return true;
+#define QTN_TILES(PREC, BM, BN) \
+  QTN_TILE(PREC, false, false, BM, BN) QTN_TILE(PREC, true, false, BM, BN) QTN_TILE(PREC, false, true, BM, BN) \
+  QTN_TILE(PREC, true, true, BM, BN)
+  switch (v) {
+    QTN_TILES(TN_MFMA_FP32, 64, 64)
+    QTN_TILES(TN_MFMA_FP32, 16, 64)
+    QTN_TILES(TN_MFMA_FP32, 64, 16)
+    QTN_TILES(TN_MFMA_BF16X3, 64, 64)
+    QTN_TILES(TN_MFMA_BF16X3, 16, 64)
+    QTN_TILES(TN_MFMA_BF16X3, 64, 16)
+    default:
+      return false;
+  }
+#undef QTN_TILES
+#undef QTN_TILE
+}
+
+template <int PREC, bool XK, bool YK, int BM, int BN>
+struct OneF {
+  static void run(const LevelArgs *a, const DOp *op, const int32_t *tab, hipStream_t st) {
+    launch_one<PREC, XK, YK, BM, BN>(*a, *op, tab, st);
+  }
+};
+template <int PREC, bool XK, bool YK, int BM, int BN>
+struct GroupF {
+  static void run(const LItem *items, int n, int blocks, void *arena, int n_sets, const int32_t *tabs, hipStream_t st) {
+    launch_group<PREC, XK, YK, BM, BN>(items, n, blocks, arena, n_sets, tabs, st);
+  }
+};
+
+}  // namespace
 
 // prec: TN_MFMA_FP32 (4M FP32 products) or TN_MFMA_BF16X3 (split-BF16 products).
 hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, int prec, hipStream_t st) {
-  const int nblk = 1 << (op.nFX - 6 + op.nFY - 6);
-  dim3 grid(nblk, 1, a.n_sets);
-  const bool xk = !(op.maskX & 1u), yk = !(op.maskY & 1u);
-  if (prec == TN_MFMA_BF16X3) {
-    if (xk && yk) hipLaunchKernelGGL((mfma_cgemm_bf16x3_kernel<true, true>), grid, dim3(256), 0, st, a, op, tab);
-    else if (xk) hipLaunchKernelGGL((mfma_cgemm_bf16x3_kernel<true, false>), grid, dim3(256), 0, st, a, op, tab);
-    else if (yk) hipLaunchKernelGGL((mfma_cgemm_bf16x3_kernel<false, true>), grid, dim3(256), 0, st, a, op, tab);
-    else hipLaunchKernelGGL((mfma_cgemm_bf16x3_kernel<false, false>), grid, dim3(256), 0, st, a, op, tab);
-    return hipGetLastError();
-  }
-  if (xk && yk) hipLaunchKernelGGL((mfma_cgemm_kernel<true, true>), grid, dim3(256), 0, st, a, op, tab);
-  else if (xk) hipLaunchKernelGGL((mfma_cgemm_kernel<true, false>), grid, dim3(256), 0, st, a, op, tab);
-  else if (yk) hipLaunchKernelGGL((mfma_cgemm_kernel<false, true>), grid, dim3(256), 0, st, a, op, tab);
-  else hipLaunchKernelGGL((mfma_cgemm_kernel<false, false>), grid, dim3(256), 0, st, a, op, tab);
+  if (!mfma_eligible(TN_C64, op) || !dispatch<OneF>(mfma_variant(op, prec), &a, &op, tab, st)) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// Grouped launch of n items of one kernel variant (mfma_variant) on
+// `blocks` workgroups (per item: mfma_tiles x the batch's parameter vectors).
+hipError_t mfma_group(int variant, const LItem *items, int n, int blocks, void *arena, int n_sets, const int32_t *tabs,
+                      hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (!dispatch<GroupF>(variant, items, n, blocks, arena, n_sets, tabs, st)) return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -32,6 +32,10 @@ hipError_t level_group(int dtype, bool leafgrad, const LItem *items, int n, int 
                        const int32_t *tabs, hipStream_t st);
 bool mfma_eligible(int dtype, const DOp &op);
 hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, int prec, hipStream_t st);
+int mfma_tiles(const DOp &op);
+int mfma_variant(const DOp &op, int prec);
+hipError_t mfma_group(int variant, const LItem *items, int n, int blocks, void *arena, int n_sets, const int32_t *tabs,
+                      hipStream_t st);
 hipError_t level_setup(int dtype, const LevelArgs &a, const void *consts, int n_const, const DParam *pt, int n_pt,
                        const void *bound, int per_set, int set0, int zero_begin, int zero_n, hipStream_t st);
 hipError_t level_finish(int dtype, const LevelArgs &a, const DParam *pt, int n_pt, const void *dbound, int per_set,
@@ -203,20 +207,26 @@ struct LevelNet {
 // Level networks whose parameter vectors all fit in the arena at once run
 // in bins: each network of a bin owns an arena region (and a region of
 // component scalars), and step k of every network of the bin is one grouped
-// launch per kind (thin contractions, leaf adjoints). Matrix-core, rank-0
-// and seed steps keep launches of their own.
+// launch per kind (thin contractions, leaf adjoints, matrix-core products
+// per kernel variant). Rank-0 and seed steps keep launches of their own.
 struct LevelBin {
   std::vector<int> lv;         // indices into tn_batch::level
   std::vector<int64_t> abase;  // arena region start (elements)
   std::vector<int64_t> sbase;  // component-scalar region start (doubles)
+  // Matrix-core items of one kernel variant in a step.
+  struct MGroup {
+    int variant = 0, i0 = 0, n = 0, blocks = 0;
+  };
   // per step: thin items [t0, t0+nt) on tb workgroups, leaf items [l0,
-  // l0+nl) on lb workgroups (into the variant's item array), separately
-  // launched ops [o0, o0+no) of `other`
+  // l0+nl) on lb workgroups (into the variant's item array), matrix-core
+  // groups [g0, g0+ng) of `mg`, separately launched ops [o0, o0+no) of
+  // `other`
   struct Step {
-    int t0 = 0, nt = 0, tb = 0, l0 = 0, nl = 0, lb = 0, o0 = 0, no = 0;
+    int t0 = 0, nt = 0, tb = 0, l0 = 0, nl = 0, lb = 0, g0 = 0, ng = 0, o0 = 0, no = 0;
   };
   std::vector<Step> steps[2];
-  std::vector<int2> other[2];  // (member, matrix-core precision or 0)
+  std::vector<MGroup> mg[2];
+  std::vector<int> other[2];  // members whose op of the step runs on its own
 };
 
 // Most workgroups one item of a grouped launch takes.
@@ -807,6 +817,7 @@ static int build_level_items(tn_batch *b) {
     for (LevelBin &bn : b->lbins) {
       bn.steps[v].clear();
       bn.other[v].clear();
+      bn.mg[v].clear();
       int n_steps = 0;
       for (int l : bn.lv) n_steps = std::max(n_steps, b->level[l].n_ops[v]);
       for (int k = 0; k < n_steps; ++k) {
@@ -842,16 +853,46 @@ static int build_level_items(tn_batch *b) {
             stp.lb = blocks;
           }
         }
+        // matrix-core products, grouped by kernel variant
+        std::vector<std::pair<int, int>> mf;  // (variant, member)
         stp.o0 = (int)bn.other[v].size();
         for (size_t j = 0; j < bn.lv.size(); ++j) {
           const LevelNet &ln = b->level[bn.lv[j]];
           if (k >= ln.n_ops[v]) continue;
           const DOp &op = b->hp.ops[ln.op_begin[v] + k];
-          const int prec = level_prec(b, op);
-          if ((op.type == OP_CONTRACT && prec == 0) || op.type == OP_LEAFGRAD) continue;
-          bn.other[v].push_back(make_int2((int)j, prec));
+          if (op.type == OP_LEAFGRAD) continue;
+          if (op.type == OP_CONTRACT) {
+            const int prec = level_prec(b, op);
+            if (prec) mf.emplace_back(mfma_variant(op, prec), (int)j);
+            continue;
+          }
+          bn.other[v].push_back((int)j);
         }
         stp.no = (int)bn.other[v].size() - stp.o0;
+        std::stable_sort(mf.begin(), mf.end(), [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+          return x.first < y.first;
+        });
+        stp.g0 = (int)bn.mg[v].size();
+        for (size_t q = 0; q < mf.size(); ++q) {
+          if (q == 0 || mf[q].first != mf[q - 1].first) {
+            LevelBin::MGroup g;
+            g.variant = mf[q].first;
+            g.i0 = (int)items.size();
+            bn.mg[v].push_back(g);
+          }
+          LevelBin::MGroup &g = bn.mg[v].back();
+          const int j = mf[q].second;
+          const LevelNet &ln = b->level[bn.lv[j]];
+          LItem it{};
+          it.op = b->hp.ops[ln.op_begin[v] + k];
+          it.base = bn.abase[j];
+          it.stride = ln.stride[v];
+          it.blk0 = g.blocks;
+          g.blocks += mfma_tiles(it.op) * b->max_sets;
+          ++g.n;
+          items.push_back(it);
+        }
+        stp.ng = (int)bn.mg[v].size() - stp.g0;
         bn.steps[v].push_back(stp);
       }
     }
@@ -1311,11 +1352,15 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
         e = level_group(b->dtype, false, b->d_litems[v] + stp.t0, stp.nt, stp.tb, b->d_larena, n_sets, b->d_tabs, st);
       if (e == hipSuccess)
         e = level_group(b->dtype, true, b->d_litems[v] + stp.l0, stp.nl, stp.lb, b->d_larena, n_sets, b->d_tabs, st);
+      for (int g = stp.g0; g < stp.g0 + stp.ng && e == hipSuccess; ++g) {
+        const LevelBin::MGroup &mg = bn.mg[v][g];
+        e = mfma_group(mg.variant, b->d_litems[v] + mg.i0, mg.n, mg.blocks, b->d_larena, n_sets, b->d_tabs, st);
+      }
       for (int q = stp.o0; q < stp.o0 + stp.no && e == hipSuccess; ++q) {
-        const int2 oj = bn.other[v][q];
-        const LevelNet &ln = b->level[bn.lv[oj.x]];
+        const int j = bn.other[v][q];
+        const LevelNet &ln = b->level[bn.lv[j]];
         const DOp &op = b->hp.ops[ln.op_begin[v] + (int)(&stp - bn.steps[v].data())];
-        e = level_op(b->dtype, args(oj.x), op, b->d_tabs, oj.y, st);
+        e = level_op(b->dtype, args(j), op, b->d_tabs, 0, st);
       }
     }
     for (size_t j = 0; j < bn.lv.size() && e == hipSuccess; ++j) {
@@ -1549,19 +1594,22 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
     DOp op = *kv.second;
     const int64_t nx = (int64_t)1 << (op.nFX + op.nS), ny = (int64_t)1 << (op.nS + op.nFY);
     const int64_t nz = (int64_t)1 << (op.nFX + op.nFY);
+    // as many parameter vectors as the pass has (the launch shapes of the
+    // real run), within 2^28 elements of scratch
+    const int sets_t = (int)std::max<int64_t>(1, std::min<int64_t>(n_sets, ((int64_t)1 << 28) / (nx + ny + nz)));
     void *buf = nullptr;
-    if (hipMalloc(&buf, (size_t)(nx + ny + nz) * eb) != hipSuccess) {
+    if (hipMalloc(&buf, (size_t)(nx + ny + nz) * sets_t * eb) != hipSuccess) {
       (void)hipGetLastError();
       continue;  // no room to tune this class: keep the default
     }
-    HIPCHK(hipMemset(buf, 0, (size_t)(nx + ny + nz) * eb));
+    HIPCHK(hipMemset(buf, 0, (size_t)(nx + ny + nz) * sets_t * eb));
     op.x = 0;
     op.y = (int32_t)nx;
     op.z = (int32_t)(nx + ny);
     LevelArgs la{};
     la.arena = buf;
     la.stride = nx + ny + nz;
-    la.n_sets = 1;
+    la.n_sets = sets_t;
     int rc1 = TN_OK, rc2 = TN_OK;
     float t_mfma = time_ms(st, reps, [&] { return mfma_contract(la, op, b->d_tabs + op.tab, b->mfma_prec, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rc1);
     // the thin kernel is not a candidate for very large products (2^30 and
@@ -1654,9 +1702,9 @@ int batch_info(const tn_batch *b, tn_batch_stats *s) {
     for (const LevelBin &bn : b->lbins) {
       n += 2 * (int64_t)bn.lv.size();  // set-up and outputs
       for (const LevelBin::Step &stp : bn.steps[v]) {
-        n += (stp.nt > 0) + (stp.nl > 0);
+        n += (stp.nt > 0) + (stp.nl > 0) + stp.ng;
         for (int q = stp.o0; q < stp.o0 + stp.no; ++q) {
-          const LevelNet &ln = b->level[bn.lv[bn.other[v][q].x]];
+          const LevelNet &ln = b->level[bn.lv[bn.other[v][q]]];
           n += b->hp.ops[ln.op_begin[v] + (int)(&stp - bn.steps[v].data())].type == OP_SCALAR ? 2 : 1;
         }
       }

@@ -468,3 +468,41 @@ def test_dense_split_bf16_precision():
     _say(f"errors {errs}")
     assert errs[qtn.TN_MFMA_FP32] < 2e-5
     assert errs[qtn.TN_MFMA_BF16X3] < 2e-4
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_level_mfma_tile_shapes(prec, monkeypatch):
+    """Matrix-core products of every tile shape (64 x 64, and 16 x 64 / 64 x 16
+    where one free index has 4 or 5 bits), forward and adjoint, launched in
+    groups across the networks of a batch: 4-regular n=14 p=2 light-cone
+    networks on the level executor, complex64, against the state-vector cost
+    and the parameter-shift gradient."""
+    qtn, qaoa = _qtn(), _qaoa()
+    monkeypatch.setenv("QTN_FUSED_LDS_MAX", "0")
+    monkeypatch.setenv("QTN_GMEM_MAX_MACS", "0")
+    n = 14
+    e = workloads.random_regular_graph(4, n, 0)
+    S = 3
+    ang = torch.tensor(workloads.qaoa_angles(5, S, 2), device="cuda", dtype=torch.float64)
+    ref = np.array([gradients.cost(n, e, list(a)) for a in ang.cpu().numpy()])
+    ps = np.array([gradients.parameter_shift(n, e, list(a)) for a in ang.cpu().numpy()])
+    model = qaoa.MaxCut(n, e, 2, qtn.TN_C64, order="linegraph", max_sets=S, trials=4)
+    shapes = set()
+    for net in model.nets:
+        for fx, s, fy in net.plan_steps():
+            for a, ss, c in ((fx, s, fy), (fx, fy, s), (s, fx, fy)):  # the step and its two adjoints
+                if ss >= 4 and min(a, c) >= 4 and max(a, c) >= 6:
+                    shapes.add((64 if a >= 6 else 16, 64 if c >= 6 else 16))
+    assert shapes == {(64, 64), (16, 64), (64, 16)}
+    model.batch.set_precision(qtn.TN_MFMA_FP32 if prec == "fp32" else qtn.TN_MFMA_BF16X3)
+    info = model.batch.info()
+    assert info["n_level"] == len(e) and info["n_level_bins"] == 1
+    _say(f"level mfma tiles {prec} launches fwd={info['level_launches_fwd']} grad={info['level_launches_grad']}")
+    obj, grad = model.value_and_grad(ang)
+    torch.cuda.synchronize()
+    obj, grad = obj.cpu().numpy(), grad.cpu().numpy()
+    err_c = float(np.max(np.abs(obj - ref)) / np.abs(ref).max())
+    err_g = float(np.max(np.abs(grad - ps)) / np.abs(ps).max())
+    _say(f"level mfma tiles {prec}: cost rel {err_c:.2e} grad rel {err_g:.2e}")
+    tol_c, tol_g = (1e-5, 1e-4) if prec == "fp32" else (3e-5, 3e-4)
+    assert err_c <= tol_c and err_g <= tol_g
