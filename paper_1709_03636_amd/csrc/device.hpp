@@ -127,12 +127,13 @@ constexpr int kSetContract = 1, kSetScalar = 2, kSetSeed = 3, kSetLeafGrad = 4;
 // One step of one network for the grouped level launches: every network
 // works in its own region of the level arena (`base` elements from its
 // start, `stride` elements per parameter vector).
-// Workgroups [blk0, next item's blk0) of a grouped launch serve the item.
+// Workgroups [blk0, next item's blk0) of a grouped launch serve the item;
+// a thin contraction sums each output on 2^lgl lanes.
 struct LItem {
   DOp op;
   DRuns ru;
   int64_t base, stride;
-  int32_t blk0, pad;
+  int32_t blk0, lgl;
 };
 
 // Arguments of the fused executor kernel.

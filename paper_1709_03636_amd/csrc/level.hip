@@ -264,9 +264,16 @@ __global__ __launch_bounds__(256) void level_finish_kernel(LevelArgs a, const DP
 
 // --- grouped launches: one step of many networks ---------------------------------------------
 
+__device__ __forceinline__ float l_xor(float v, int m) { return __shfl_xor(v, m, 64); }
+__device__ __forceinline__ double l_xor(double v, int m) { return __shfl_xor(v, m, 64); }
+
 // Thin contractions of several networks at once: each item is one op of one
 // network, with the addressing of level_contract_kernel inside the
-// network's own arena region.
+// network's own arena region. An output is summed by L = 2^lgl adjacent
+// lanes (summed entries k = part, part + L, ...; then a butterfly over the
+// L lanes), so that steps with few outputs and long sums still fill the
+// chip. All L lanes of an output are in the same loop iteration: the
+// stride is a multiple of 256 and the total a multiple of L.
 template <typename V>
 __global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *__restrict__ items, int n, V *arena,
                                                                    int n_sets, const int32_t *__restrict__ tabs) {
@@ -274,16 +281,20 @@ __global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *
   const LItem &it = items[group_item(items, n, &rank, &count)];
   const DOp op = it.op;
   const int lgOut = op.nFX + op.nB + op.nFY;
+  const int lgl = it.lgl;
+  const int L = 1 << lgl;
   const int64_t nOut = (int64_t)1 << lgOut;
-  const int64_t total = nOut * n_sets;
+  const int64_t total = (nOut * n_sets) << lgl;
   const int K = 1 << op.nS;
   const uint32_t maskJ = (1u << op.nFY) - 1u;
   const int32_t *tab = tabs + op.tab;
   const int32_t *tabB = tabs + op.tabB;
   V *reg = arena + it.base;
   for (int64_t g = rank * (int64_t)256 + threadIdx.x; g < total; g += (int64_t)count * 256) {
-    const int64_t set = g >> lgOut;
-    const uint32_t c = (uint32_t)(g & (nOut - 1));
+    const int part = (int)(g & (L - 1));
+    const int64_t o = g >> lgl;
+    const int64_t set = o >> lgOut;
+    const uint32_t c = (uint32_t)(o & (nOut - 1));
     V *base = reg + set * it.stride;
     const uint32_t rest = c >> op.nFY;
     uint32_t bx = 0, by = 0;
@@ -297,11 +308,15 @@ __global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *
     V acc;
     acc.x = 0;
     acc.y = 0;
-    for (int k = 0; k < K; ++k) {
-      const int2 o = l_tab(tab, op.nS, k);
-      acc = l_fma(acc, X[o.x], Y[o.y]);
+    for (int k = part; k < K; k += L) {
+      const int2 t = l_tab(tab, op.nS, k);
+      acc = l_fma(acc, X[t.x], Y[t.y]);
     }
-    base[op.z + c] = acc;
+    for (int m = 1; m < L; m <<= 1) {
+      acc.x += l_xor(acc.x, m);
+      acc.y += l_xor(acc.y, m);
+    }
+    if (part == 0) base[op.z + c] = acc;
   }
 }
 

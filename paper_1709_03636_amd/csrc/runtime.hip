@@ -832,8 +832,16 @@ static int build_level_items(tn_batch *b) {
             const bool thin = op.type == OP_CONTRACT && level_prec(b, op) == 0;
             if (kind == 0 ? !thin : op.type != OP_LEAFGRAD) continue;
             const int lg = kind == 0 ? op.nFX + op.nB + op.nFY : op.nFX;
-            const int64_t work = ((int64_t)1 << lg) * b->max_sets;
+            int64_t work = ((int64_t)1 << lg) * b->max_sets;
             LItem it{};
+            if (kind == 0) {
+              // lanes per output: at least 8 summed entries each, up to 64,
+              // while the step has fewer than 2^20 (output, lane) pairs
+              int lgs = 0;
+              while ((int64_t(1) << lgs) < b->max_sets) ++lgs;
+              it.lgl = std::max(0, std::min({6, op.nS - 3, 20 - lg - lgs}));
+              work <<= it.lgl;
+            }
             it.op = op;
             pack_runs(op.maskX, it.ru.runsX);
             pack_runs(op.maskY, it.ru.runsY);
@@ -1612,10 +1620,10 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
     la.n_sets = sets_t;
     int rc1 = TN_OK, rc2 = TN_OK;
     float t_mfma = time_ms(st, reps, [&] { return mfma_contract(la, op, b->d_tabs + op.tab, b->mfma_prec, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rc1);
-    // the thin kernel is not a candidate for very large products (2^30 and
-    // more complex multiply-adds): the matrix cores win by orders of magnitude
+    // the thin kernel is not a candidate for large products (2^24 and more
+    // complex multiply-adds per parameter vector): the matrix cores win there
     float t_thin = 1e30f;
-    if (op.nFX + op.nS + op.nFY < 30)
+    if (op.nFX + op.nS + op.nFY < 24)
       t_thin = time_ms(st, reps, [&] { return level_op(b->dtype, la, op, b->d_tabs, 0, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rc2);
     (void)hipFree(buf);
     if (rc1 != TN_OK || rc2 != TN_OK) {
