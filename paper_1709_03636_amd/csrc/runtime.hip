@@ -47,9 +47,11 @@ static constexpr int kLdsCap = 160 * 1024;
 // Networks whose fused adjoint program needs more LDS than this run on the
 // level executor, so one large network does not lower the occupancy of all.
 static constexpr int64_t kFusedLdsMax = 64 * 1024;
-// Global-memory arena budget of the level executor (parameter vectors are
-// processed in chunks that fit).
-static constexpr int64_t kLevelBudget = 8ll << 30;
+// Global-memory arena budget of the level executor: networks stepped
+// together share it (more of them per group, fewer groups stepped one after
+// another); a network alone processes its parameter vectors in chunks that
+// fit. 32 GiB of the 288 GB of HBM.
+static constexpr int64_t kLevelBudget = 32ll << 30;
 static constexpr int64_t kMaxArenaElems = int64_t(1) << 31;  // 32-bit element offsets per set
 // Global-arena fused executor: networks too large for LDS whose whole task
 // (forward + adjoint program of one parameter vector) has at most this many
