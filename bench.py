@@ -312,17 +312,22 @@ def batching_grid(st, dev):
                     st.synchronize()
                     o = out.cpu().numpy()
                     err = max(abs(o[i, s, 0] - v) for (i, s), v in ref.items())
-                    for _ in range(2):
-                        m.batch.run_graph(True, prm, obj=obj, grad=grad, stream=st)
-                    reps = 3
-                    ev0.record(st)
-                    for _ in range(reps):
-                        m.batch.run_graph(True, prm, obj=obj, grad=grad, stream=st)
-                    ev1.record(st)
-                    torch.cuda.synchronize()
-                    ms = ev0.elapsed_time(ev1) / reps
+                    t = {}
+                    for wg in (True, False):
+                        for _ in range(2):
+                            m.batch.run_graph(wg, prm, obj=obj, grad=grad if wg else None, stream=st)
+                        reps = 3
+                        ev0.record(st)
+                        for _ in range(reps):
+                            m.batch.run_graph(wg, prm, obj=obj, grad=grad if wg else None, stream=st)
+                        ev1.record(st)
+                        torch.cuda.synchronize()
+                        t[wg] = ev0.elapsed_time(ev1) / reps
+                    ms = t[True]
                     inf = m.batch.info()
                     row[mode] = {"ms_per_step": ms, "fwd_grad_networks_per_s": len(e) * N_SETS / (ms * 1e-3),
+                                 "ms_per_step_fwd": t[False],
+                                 "fwd_networks_per_s": len(e) * N_SETS / (t[False] * 1e-3),
                                  "max_abs_err_zz": float(err),
                                  "executors": {"lds_fused": inf["n_fused"], "global_arena": inf["n_global"],
                                                "level": inf["n_level"]},
@@ -335,6 +340,57 @@ def batching_grid(st, dev):
             "oracle_check": "closed form, all edges and sets (p=1); FP64 light-cone contraction, 4 sampled (edge, "
                             "set) pairs (p=2)",
             "rows": rows}
+
+
+def differentiation(st, dev):
+    """QAOA p=2 on the seeded 3-regular graph with 60 vertices (90 edge
+    networks) x 64 angle sets: forward + adjoint gradient from a captured
+    graph, complex64; error of <C> on every set against light-cone state
+    vectors, of the gradient on one set against the parameter-shift rule."""
+    import torch
+    import workloads
+    from oracle import gradients, statevector
+    from paper_1709_03636_amd import qaoa, qtn
+    n, p = 60, 2
+    e = workloads.random_regular_graph(3, n, GRAPH_SEED)
+    ang = np.array(workloads.qaoa_angles(ANGLE_SEED, N_SETS, p))
+    prm = torch.tensor(ang, dtype=torch.float64, device=dev)
+    m = qaoa.MaxCut(n, e, p, qtn.TN_C64, order="linegraph", max_sets=N_SETS, trials=4)
+    m.batch.autotune(prm, reps=5, stream=st)
+    obj = torch.empty(N_SETS, dtype=torch.float64, device=dev)
+    grad = torch.empty((N_SETS, 2 * p), dtype=torch.float64, device=dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    timed = {}
+    for wg in (True, False):
+        for _ in range(5):
+            m.batch.run_graph(wg, prm, obj=obj, grad=grad if wg else None, stream=st)
+        ev0.record(st)
+        for _ in range(20):
+            m.batch.run_graph(wg, prm, obj=obj, grad=grad if wg else None, stream=st)
+        ev1.record(st)
+        torch.cuda.synchronize()
+        timed[wg] = ev0.elapsed_time(ev1) / 20
+    m.batch.run_graph(True, prm, obj=obj, grad=grad, stream=st)
+    torch.cuda.synchronize()
+    ob, gr = obj.cpu().numpy(), grad.cpu().numpy()
+    err_c = 0.0
+    for s in range(0, N_SETS, 16):
+        zz = np.array([statevector.qaoa_zz_edge(n, e, ang[s, :p], ang[s, p:], ed) for ed in e])
+        c_ref = float(np.sum((1 - zz) / 2))
+        err_c = max(err_c, abs(ob[s] - c_ref) / c_ref)
+    s = 1
+    ps = sum(-0.5 * gradients.parameter_shift_edge(n, e, ang[s], ed) for ed in e)
+    err_g = float(np.max(np.abs(gr[s] - ps)) / max(1.0, np.abs(ps).max()))
+    info = m.batch.info()
+    res = {"workload": "QAOA p=2 Max-Cut, random 3-regular n=60 (90 edge light-cone networks) x 64 angle sets, "
+                       "fwd + adjoint gradient (4 entries), complex64, graph replay",
+           "ms_per_step": timed[True], "fwd_grad_networks_per_s": len(e) * N_SETS / (timed[True] * 1e-3),
+           "ms_per_step_fwd": timed[False], "fwd_networks_per_s": len(e) * N_SETS / (timed[False] * 1e-3),
+           "max_rel_err_cost_vs_statevector": err_c, "rel_err_grad_vs_parameter_shift": err_g,
+           "executors": {"lds_fused": info["n_fused"], "global_arena": info["n_global"], "level": info["n_level"]},
+           "n_programs": info["n_programs"]}
+    log(f"differentiation: {res}")
+    return res
 
 
 def main():
@@ -518,6 +574,7 @@ def main():
 
     nxt = None if args.no_next else next_rows(model, params, edges, st, dev)
     grid = None if args.no_grid else batching_grid(st, dev)
+    diff = None if args.no_grid else differentiation(st, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -553,6 +610,7 @@ def main():
         "mfma_path": mfma,
         "next_rows": nxt,
         "batching_grid": grid,
+        "differentiation_p2_n60": diff,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -45,8 +45,11 @@ hipError_t level_finish(int dtype, const LevelArgs &a, const DParam *pt, int n_p
 
 static constexpr int kLdsCap = 160 * 1024;
 // Networks whose fused adjoint program needs more LDS than this run on the
-// level executor, so one large network does not lower the occupancy of all.
-static constexpr int64_t kFusedLdsMax = 64 * 1024;
+// global-arena or level executor, so one large network does not lower the
+// occupancy of all: at most 48 KiB keeps three workgroups per CU (a p=2
+// 3-regular batch with 40-56 KiB programs ran 1.8x faster on HBM arena
+// slots with more workgroups in flight than in LDS with two).
+static constexpr int64_t kFusedLdsMax = 48 * 1024;
 // Global-memory arena budget of the level executor: networks stepped
 // together share it (more of them per group, fewer groups stepped one after
 // another); a network alone processes its parameter vectors in chunks that
@@ -1054,8 +1057,8 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   b->coef.assign(n_nets, 0.0);
   if (coef) std::copy(coef, coef + n_nets, b->coef.begin());
   const int eb = b->dtype == TN_C128 ? 16 : 8;
-  // QTN_FUSED_LDS_MAX (bytes) overrides the fused/level split, e.g. 0 sends
-  // every network to the level executor
+  // QTN_FUSED_LDS_MAX (bytes) overrides the LDS-fused limit, e.g. 0 sends
+  // every network to the global-arena or level executor
   int64_t fused_max = kFusedLdsMax;
   if (const char *env = std::getenv("QTN_FUSED_LDS_MAX")) fused_max = std::atoll(env);
   int64_t gmem_max = kGmemMaxMacs;  // QTN_GMEM_MAX_MACS=0 turns the global-arena executor off
@@ -1635,6 +1638,10 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
     }
     b->use_mfma[kv.first] = t_mfma <= t_thin ? 1 : 0;
     found["mfma:" + kv.first] = b->use_mfma[kv.first];
+    // measured times (ns, at sets_t angle sets), recorded for inspection only
+    found["time_ns_mfma:" + kv.first + ":sets" + std::to_string(sets_t)] = (int)std::min(2e9f, t_mfma * 1e6f);
+    if (t_thin < 1e29f)
+      found["time_ns_thin:" + kv.first + ":sets" + std::to_string(sets_t)] = (int)std::min(2e9f, t_thin * 1e6f);
   }
   write_cache(cache_path, found);
   return build_level_items(b);

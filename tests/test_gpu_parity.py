@@ -300,7 +300,7 @@ def test_level_executor_matches_fused(monkeypatch):
     monkeypatch.setenv("QTN_GMEM_MAX_MACS", "0")
     mixed = _mixed_level_budget(qtn, qaoa, n, e, S, monkeypatch)
     assert mixed is not None
-    for mode, lim, gmem, budget in (("fused", None, None, None), ("global", "0", None, None),
+    for mode, lim, gmem, budget in (("fused", str(160 * 1024), None, None), ("global", "0", None, None),
                                     ("level", "0", "0", None), ("level-mixed", "0", "0", str(mixed)),
                                     ("level-chunked", "0", "0", "1")):
         for var, val in (("QTN_FUSED_LDS_MAX", lim), ("QTN_GMEM_MAX_MACS", gmem), ("QTN_LEVEL_BUDGET", budget)):
@@ -320,6 +320,8 @@ def test_level_executor_matches_fused(monkeypatch):
             assert info["n_level_bins"] == 0 and info["n_level_chunked"] == len(e)
         if mode == "global":
             assert info["n_global"] == len(e) and info["n_fused"] == 0 and info["n_level"] == 0
+        if mode == "fused":
+            assert info["n_fused"] > 0
         _say(f"executor {mode} n_fused={info['n_fused']} n_global={info['n_global']} n_level={info['n_level']} "
              f"bins={info['n_level_bins']} chunked={info['n_level_chunked']} launches={info['level_launches_grad']}")
         obj, grad = model.value_and_grad(ang)
@@ -335,8 +337,10 @@ def test_fused_workgroup_sizes_and_record_kernels(p, monkeypatch):
     gradient: one angle set per workgroup at 64, 128 and 256 lanes, and four
     angle sets per 64-lane wave. At 64 lanes the p=1 light cones run on the
     records-only kernel; the p=2 ones (intermediates of 2^12 entries, too
-    large for a lane record) also need the descriptor path and have no
-    set-packed form. S = 7 leaves the last group of four sets partly empty."""
+    large for a lane record) also need the descriptor path, and pack sets
+    only as far as their LDS allows (the larger p=2 networks run on the
+    global-arena executor). S = 7 leaves the last group of four sets partly
+    empty."""
     qtn, qaoa = _qtn(), _qaoa()
     n = 14
     e = workloads.random_regular_graph(3, n, 8)
@@ -353,7 +357,10 @@ def test_fused_workgroup_sizes_and_record_kernels(p, monkeypatch):
              f"sets={info['sets_per_wave_fwd']},{info['sets_per_wave_grad']} n_fused={info['n_fused']}")
         assert info["fused_block"] == blk and info["n_fused"] > 0
         assert info["n_fused"] + info["n_global"] + info["n_level"] == len(e)
-        assert info["sets_per_wave_fwd"] == info["sets_per_wave_grad"] == (spw if p == 1 else 1)
+        if p == 1 or spw == 1:
+            assert info["sets_per_wave_fwd"] == info["sets_per_wave_grad"] == spw
+        else:  # as many sets per wave as the largest fused program's LDS allows
+            assert info["sets_per_wave_fwd"] in (1, 2, 4) and info["sets_per_wave_grad"] in (1, 2, 4)
         if blk == 64 and p == 1:
             assert info["rec_only"] == 3
         elif blk == 64:
