@@ -266,7 +266,7 @@ def next_rows(model, params, edges, st, dev):
     return res
 
 
-def batching_grid(st, dev):
+def batching_grid(st, dev, cases=None):
     """The batching configurations: seeded random 4- and 5-regular graphs with
     n in {50, 70, 100}, p in {1, 2}; all edge light-cone networks x 64 angle
     sets per batch, forward + adjoint gradient from a captured graph, complex64
@@ -283,6 +283,8 @@ def batching_grid(st, dev):
     for d in (4, 5):
         for n in (50, 70, 100):
             for p in (1, 2):
+                if cases is not None and (d, n, p) not in cases:
+                    continue
                 e = workloads.random_regular_graph(d, n, GRAPH_SEED)
                 ang = np.array(workloads.qaoa_angles(ANGLE_SEED, N_SETS, p))
                 prm = torch.tensor(ang, dtype=torch.float64, device=dev)
@@ -403,6 +405,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-next", action="store_true", help="skip the optimisation / answer-string / noise lines")
     ap.add_argument("--no-grid", action="store_true", help="skip the 4-/5-regular batching grid")
+    ap.add_argument("--grid-case", default=None,
+                    help="only the batching-grid rows d,n,p (e.g. 5,50,2); prints them as one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note "
@@ -417,6 +421,10 @@ def main():
     from paper_1709_03636_amd import qtn, qaoa
 
     dev = torch.device("cuda:0")
+    if args.grid_case:
+        case = tuple(int(x) for x in args.grid_case.split(","))
+        print(json.dumps(batching_grid(torch.cuda.Stream(), dev, cases={case})), flush=True)
+        return
     edges = workloads.random_regular_graph(D, N_VERT, GRAPH_SEED)
     angles = np.array(workloads.qaoa_angles(ANGLE_SEED, N_SETS, P_LAYERS))
     n_nets = len(edges)
@@ -458,7 +466,8 @@ def main():
     if info["sets_per_wave_grad"] > 1:
         kname = f"fused_sets_kernel<float, true, {6 - info['sets_per_wave_grad'] // 2}>"
     else:
-        kname = f"fused_exec_kernel<float, {info['fused_block']}, true, {'true' if info['rec_only'] & 2 else 'false'}>"
+        kname = (f"fused_exec_kernel<float, {info['fused_block']}, true, "
+                 f"{'true' if info['rec_only'] & 2 else 'false'}, false>")
 
     # --- timed: fwd+grad steps from the captured graph ----------------------------------
     def replay(with_grad):
