@@ -235,7 +235,7 @@ struct LevelBin {
 };
 
 // Most workgroups one item of a grouped launch takes.
-static constexpr int64_t kGroupItemBlocks = 2048;
+static constexpr int64_t kGroupItemBlocks = 65536;
 
 static int slot_for(HostProgram &hp, const ParamTensor &pt) {
   auto key = std::make_tuple(pt.kind, pt.param, pt.coeff, pt.folded + 2 * pt.diag);
