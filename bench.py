@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 D, N_VERT, P_LAYERS, N_SETS, GRAPH_SEED, ANGLE_SEED = 3, 100, 1, 64, 0, 0
 HBM_PEAK = 8.0e12
 FP32_MFMA_PEAK = 157.3e12
+FP64_MFMA_PEAK = 78.6e12
 
 
 def log(msg):
@@ -571,6 +572,19 @@ def main():
         ev1.record(st)
         torch.cuda.synchronize()
         b_ms = ev0.elapsed_time(ev1) / reps
+        # complex128: FP64 matrix-core products on the same network
+        dnet128 = qaoa.edge_network(dn, de, 1, de[0], dtype=qtn.TN_C128, lightcone=False)
+        dnet128.set_order(dnet128.order_linegraph(trials=8, seed=0))
+        dbatch128 = qtn.Batch([dnet128], max_sets=1)
+        dbatch128.autotune(dpar, reps=2, stream=st)
+        dout3 = torch.empty_like(dout)
+        dbatch128.contract(dpar, out=dout3, stream=st)
+        ev0.record(st)
+        for _ in range(reps):
+            dbatch128.contract(dpar, out=dout3, stream=st)
+        ev1.record(st)
+        torch.cuda.synchronize()
+        f_ms = ev0.elapsed_time(ev1) / reps
         mfma = {"workload": f"whole-circuit folded network of one edge, QAOA p=1, {dd}-regular n={dn} "
                             f"(no light cone), line-graph order, complex64, 4M FP32 MFMA",
                 "peak_bits": dinfo["peak_bits"], "flops_per_pass": dinfo["flops"], "pass_ms": d_ms,
@@ -578,7 +592,10 @@ def main():
                 "frac_of_fp32_matrix_peak": dinfo["flops"] / (d_ms * 1e-3) / FP32_MFMA_PEAK,
                 "abs_err_zz_vs_closed_form": abs(dout[0, 0, 0].item() - zz_ref),
                 "split_bf16": {"pass_ms": b_ms, "tflops_fp32_equivalent": dinfo["flops"] / (b_ms * 1e-3) / 1e12,
-                               "abs_err_zz_vs_closed_form": abs(dout2[0, 0, 0].item() - zz_ref)}}
+                               "abs_err_zz_vs_closed_form": abs(dout2[0, 0, 0].item() - zz_ref)},
+                "complex128_fp64": {"pass_ms": f_ms, "tflops": dinfo["flops"] / (f_ms * 1e-3) / 1e12,
+                                    "frac_of_fp64_matrix_peak": dinfo["flops"] / (f_ms * 1e-3) / FP64_MFMA_PEAK,
+                                    "abs_err_zz_vs_closed_form": abs(dout3[0, 0, 0].item() - zz_ref)}}
         log(f"dense/MFMA: {mfma}")
 
     nxt = None if args.no_next else next_rows(model, params, edges, st, dev)

@@ -99,11 +99,12 @@ typedef struct {
 
 enum { TN_C64 = 0, TN_C128 = 1 };
 
-/* Matrix-core precision of large complex64 contractions (complex GEMM steps):
+/* Matrix-core precision of large contractions (complex GEMM steps). complex64:
  * FP32 products (4 real MFMA products per complex product, default) or
  * split-BF16 products (x = hi + lo in bfloat16, hi*hi + hi*lo + lo*hi),
- * both with FP32 accumulation. */
-enum { TN_MFMA_FP32 = 1, TN_MFMA_BF16X3 = 2 };
+ * both with FP32 accumulation. complex128: FP64 products (4 real MFMA
+ * products per complex product) with FP64 accumulation, always. */
+enum { TN_MFMA_FP32 = 1, TN_MFMA_BF16X3 = 2, TN_MFMA_FP64 = 3 };
 
 /* Build the closed network of a circuit (Sec. Preliminaries: one node per
  * initial state, gate and measurement; gates in superoperator form, wires of
@@ -239,8 +240,9 @@ int tn_batch_info(const tn_batch *b, tn_batch_stats *out);
 int tn_batch_autotune(tn_batch *b, const double *params, int32_t n_sets, int32_t reps, const char *cache_path,
                       void *stream);
 
-/* Matrix-core precision for this batch's large complex64 steps
- * (TN_MFMA_FP32 or TN_MFMA_BF16X3). */
+/* Matrix-core precision for this batch's large steps: TN_MFMA_FP32 or
+ * TN_MFMA_BF16X3 for a complex64 batch, TN_MFMA_FP64 (the only one) for a
+ * complex128 batch; TN_EINVAL otherwise. */
 int tn_batch_set_precision(tn_batch *b, int32_t mfma_precision);
 
 /* Apply decisions from an autotuner cache file without timing. */

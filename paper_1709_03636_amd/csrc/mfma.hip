@@ -6,7 +6,8 @@
 // tiles are staged into LDS, so X and Y are read in their stored layout.
 //
 // Complex products use four real products (4M) on v_mfma_f32_16x16x4_f32
-// with FP32 accumulation (or split-BF16 products, below): with the summed
+// with FP32 accumulation for complex64 (or split-BF16 products, below), on
+// v_mfma_f64_16x16x4_f64 with FP64 accumulation for complex128: with the summed
 // index interleaved as (re, im) pairs, Re Z = [Xr, -Xi] . [Yr; Yi] and
 // Im Z = [Xi, Xr] . [Yr; Yi].
 // Workgroup tile: BM x BN complex outputs (64 x 64, or 16 x 64 / 64 x 16
@@ -22,6 +23,27 @@
 namespace qtn {
 
 typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md4 __attribute__((ext_vector_type(4)));
+
+// 16 x 16 x 4 real matrix product, FP32 or FP64: lane l holds A[l % 16][l / 16]
+// and B[l / 16][l % 16]; result entry r < 4 of lane l is D[row(l, r)][l % 16]
+// with row = 4 (l / 16) + r for FP32 and row = l / 16 + 4 r for FP64
+// (measured on gfx950).
+__device__ __forceinline__ mf4 mfma4(float a, float b, mf4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ md4 mfma4(double a, double b, md4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+template <typename V> struct Acc4;
+template <> struct Acc4<float2> {
+  using R = float;
+  using type = mf4;
+  static __device__ __forceinline__ int row(int lg, int r) { return 4 * lg + r; }
+};
+template <> struct Acc4<double2> {
+  using R = double;
+  using type = md4;
+  static __device__ __forceinline__ int row(int lg, int r) { return lg + 4 * r; }
+};
+__device__ __forceinline__ float2 make_c(float r, float i) { return make_float2(r, i); }
+__device__ __forceinline__ double2 make_c(double r, double i) { return make_double2(r, i); }
 
 namespace {
 
@@ -36,7 +58,7 @@ struct TileT {
   static constexpr int GN = 4 / GM;
   static constexpr int WM = BM / 16 / GM, WN = BN / 16 / GN;
   static constexpr int NX = BM / 16, NY = BN / 16;
-  static constexpr int AS = BK + 1;  // LDS row stride of the X tile (float2), padded against bank conflicts
+  static constexpr int AS = BK + 1;  // LDS row stride of the X tile (complex), padded against bank conflicts
   static constexpr int BS = BN + 2;  // LDS row stride of the Y tile
   static constexpr int PS = BK + 4;  // packed-tile row stride (dwords), 16-byte aligned rows
   static_assert(GM * GN == 4 && WM >= 1 && WN >= 1, "tile");
@@ -66,12 +88,12 @@ __device__ __forceinline__ int2 g_tab(const int32_t *__restrict__ tb, int nS, in
 // fixed, and t(k0) is one workgroup-uniform lookup per stage.
 // XK: X's lowest address bit is summed (stage X with k fastest), else m
 // fastest; YK likewise for Y.
-template <bool XK, bool YK, int BM, int BN>
+template <bool XK, bool YK, int BM, int BN, typename V = float2>
 struct Stager {
   using T = TileT<BM, BN>;
   int xr[T::NX], xk[T::NX], yk[T::NY], yn[T::NY];
   uint32_t xrow[T::NX], ycol[T::NY];
-  float2 xv[T::NX], yv[T::NY];
+  V xv[T::NX], yv[T::NY];
   __device__ __forceinline__ Stager(const DOp &op, const int32_t *tab, int m0, int n0) {
     const int tid = threadIdx.x;
 #pragma unroll
@@ -87,7 +109,7 @@ struct Stager {
       ycol[i] = g_pdep((uint32_t)(n0 + yn[i]), op.maskY) + (uint32_t)g_tab(tab, op.nS, yk[i]).y;
     }
   }
-  __device__ __forceinline__ void fetch(const float2 *X, const float2 *Y, const DOp &op, const int32_t *tab, int k0) {
+  __device__ __forceinline__ void fetch(const V *X, const V *Y, const DOp &op, const int32_t *tab, int k0) {
     const int2 t0 = g_tab(tab, op.nS, k0);
     const int bx = __builtin_amdgcn_readfirstlane(t0.x), by = __builtin_amdgcn_readfirstlane(t0.y);
 #pragma unroll
@@ -97,26 +119,29 @@ struct Stager {
   }
 };
 
-// Output tile `tile` of the op on one parameter vector's arena slice.
-template <bool XK, bool YK, int BM, int BN>
-__device__ __forceinline__ void f32_tile(float2 *__restrict__ As, float2 *__restrict__ Bs, float2 *base, const DOp &op,
+// Output tile `tile` of the op on one parameter vector's arena slice, 4M
+// products in the precision of V (complex64: FP32, complex128: FP64).
+template <typename V, bool XK, bool YK, int BM, int BN>
+__device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs, V *base, const DOp &op,
                                          const int32_t *__restrict__ tab, int tile) {
   using T = TileT<BM, BN>;
+  using R = typename Acc4<V>::R;
+  using A4 = typename Acc4<V>::type;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nT = 1 << (op.nFY - T::LN);
   const int n0 = (tile & (nT - 1)) * BN, m0 = (tile >> (op.nFY - T::LN)) * BM;
-  const float2 *X = base + op.x;
-  const float2 *Y = base + op.y;
-  float2 *Z = base + op.z;
+  const V *X = base + op.x;
+  const V *Y = base + op.y;
+  V *Z = base + op.z;
   const int K = 1 << op.nS;
-  Stager<XK, YK, BM, BN> sg(op, tab, m0, n0);
-  mf4 cre[T::WM][T::WN], cim[T::WM][T::WN];
+  Stager<XK, YK, BM, BN, V> sg(op, tab, m0, n0);
+  A4 cre[T::WM][T::WN], cim[T::WM][T::WN];
 #pragma unroll
   for (int i = 0; i < T::WM; ++i)
 #pragma unroll
     for (int j = 0; j < T::WN; ++j) {
-      cre[i][j] = mf4{0.f, 0.f, 0.f, 0.f};
-      cim[i][j] = mf4{0.f, 0.f, 0.f, 0.f};
+      cre[i][j] = A4{0, 0, 0, 0};
+      cim[i][j] = A4{0, 0, 0, 0};
     }
   const int wr = (wave / T::GN) * 16 * T::WM, wc = (wave % T::GN) * 16 * T::WN;
   const int lr = lane & 15, lk = lane >> 4;  // MFMA operand row/col and real-k index
@@ -134,28 +159,28 @@ __device__ __forceinline__ void f32_tile(float2 *__restrict__ As, float2 *__rest
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 2) {
       const int kc = kk + (lk >> 1);
-      float are[T::WM], aim[T::WM], bv[T::WN];
+      R are[T::WM], aim[T::WM], bv[T::WN];
 #pragma unroll
       for (int i = 0; i < T::WM; ++i) {
-        const float2 x = As[(wr + 16 * i + lr) * T::AS + kc];
+        const V x = As[(wr + 16 * i + lr) * T::AS + kc];
         are[i] = part ? -x.y : x.x;  // [Xr, -Xi]
         aim[i] = part ? x.x : x.y;   // [Xi,  Xr]
       }
 #pragma unroll
       for (int j = 0; j < T::WN; ++j) {
-        const float2 y = Bs[kc * T::BS + wc + 16 * j + lr];
+        const V y = Bs[kc * T::BS + wc + 16 * j + lr];
         bv[j] = part ? y.y : y.x;  // [Yr; Yi]
       }
 #pragma unroll
       for (int i = 0; i < T::WM; ++i)
 #pragma unroll
         for (int j = 0; j < T::WN; ++j) {
-          cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(are[i], bv[j], cre[i][j], 0, 0, 0);
-          cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(aim[i], bv[j], cim[i][j], 0, 0, 0);
+          cre[i][j] = mfma4(are[i], bv[j], cre[i][j]);
+          cim[i][j] = mfma4(aim[i], bv[j], cim[i][j]);
         }
     }
   }
-  // D layout of the 16x16 tile: lane holds rows 4*(lane/16)+r, column lane%16
+  // result layout of the 16x16 tile (mfma4): column lane % 16, row per precision
   const int N = 1 << op.nFY;
 #pragma unroll
   for (int i = 0; i < T::WM; ++i)
@@ -163,9 +188,9 @@ __device__ __forceinline__ void f32_tile(float2 *__restrict__ As, float2 *__rest
     for (int j = 0; j < T::WN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wr + 16 * i + 4 * lk + r;
+        const int row = m0 + wr + 16 * i + Acc4<V>::row(lk, r);
         const int col = n0 + wc + 16 * j + lr;
-        Z[(int64_t)row * N + col] = make_float2(cre[i][j][r], cim[i][j][r]);
+        Z[(int64_t)row * N + col] = make_c(cre[i][j][r], cim[i][j][r]);
       }
 }
 
@@ -285,20 +310,28 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
       }
 }
 
-// One tile of either precision with its LDS.
+// One tile of any precision with its LDS; base: the parameter vector's
+// arena slice (complex128 for TN_MFMA_FP64, else complex64).
 template <int PREC, bool XK, bool YK, int BM, int BN>
-__device__ __forceinline__ void any_tile(float2 *base, const DOp &op, const int32_t *__restrict__ tab, int tile) {
+__device__ __forceinline__ void any_tile(void *base, const DOp &op, const int32_t *__restrict__ tab, int tile) {
   using T = TileT<BM, BN>;
   if constexpr (PREC == TN_MFMA_BF16X3) {
     __shared__ __align__(16) uint32_t Ah[BM * T::PS], Al[BM * T::PS];
     __shared__ __align__(16) uint32_t Bh[BN * T::PS], Bl[BN * T::PS];
-    bf16x3_tile<XK, YK, BM, BN>(Ah, Al, Bh, Bl, base, op, tab, tile);
+    bf16x3_tile<XK, YK, BM, BN>(Ah, Al, Bh, Bl, (float2 *)base, op, tab, tile);
+  } else if constexpr (PREC == TN_MFMA_FP64) {
+    __shared__ double2 As[BM * T::AS];
+    __shared__ double2 Bs[BK * T::BS];
+    c4m_tile<double2, XK, YK, BM, BN>(As, Bs, (double2 *)base, op, tab, tile);
   } else {
     __shared__ float2 As[BM * T::AS];
     __shared__ float2 Bs[BK * T::BS];
-    f32_tile<XK, YK, BM, BN>(As, Bs, base, op, tab, tile);
+    c4m_tile<float2, XK, YK, BM, BN>(As, Bs, (float2 *)base, op, tab, tile);
   }
 }
+
+// Bytes of one complex element of a precision's operands.
+constexpr int elem_bytes(int prec) { return prec == TN_MFMA_FP64 ? 16 : 8; }
 
 // XCD-aware order of a run of `total` workgroups: consecutive workgroups
 // land on different XCDs, so each XCD is given a contiguous run of tiles
@@ -313,7 +346,7 @@ __device__ __forceinline__ int xcd_order(int b, int total) {
 template <int PREC, bool XK, bool YK, int BM, int BN>
 __global__ __launch_bounds__(256) void mfma_cgemm_kernel(LevelArgs a, DOp op, const int32_t *__restrict__ tab) {
   const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
-  float2 *base = reinterpret_cast<float2 *>(a.arena) + (int64_t)blockIdx.z * a.stride;
+  char *base = reinterpret_cast<char *>(a.arena) + (int64_t)blockIdx.z * a.stride * elem_bytes(PREC);
   any_tile<PREC, XK, YK, BM, BN>(base, op, tab, b);
 }
 
@@ -321,7 +354,7 @@ __global__ __launch_bounds__(256) void mfma_cgemm_kernel(LevelArgs a, DOp op, co
 // region, on (tiles x parameter vectors) workgroups; the workgroups of
 // parameter vectors past n_sets return at once.
 template <int PREC, bool XK, bool YK, int BM, int BN>
-__global__ __launch_bounds__(256) void mfma_group_kernel(const LItem *__restrict__ items, int n, float2 *arena,
+__global__ __launch_bounds__(256) void mfma_group_kernel(const LItem *__restrict__ items, int n, void *arena,
                                                          int n_sets, const int32_t *__restrict__ tabs) {
   using T = TileT<BM, BN>;
   int rank, count;
@@ -331,15 +364,18 @@ __global__ __launch_bounds__(256) void mfma_group_kernel(const LItem *__restrict
   const int b = xcd_order(rank, count);
   const int set = b >> lt, tile = b & ((1 << lt) - 1);
   if (set >= n_sets) return;
-  any_tile<PREC, XK, YK, BM, BN>(arena + it.base + (int64_t)set * it.stride, op, tabs + op.tab, tile);
+  any_tile<PREC, XK, YK, BM, BN>((char *)arena + (it.base + (int64_t)set * it.stride) * elem_bytes(PREC), op,
+                                 tabs + op.tab, tile);
 }
 
-// True when the MFMA path takes this op: complex64, no batch bits, at least
-// 16 summed entries, both free indices at least 16 wide and one at least 64
-// (tiles 64 x 64, 16 x 64 or 64 x 16 divide the shape).
+// True when the MFMA path takes this op: no batch bits, at least 16 summed
+// entries; complex64: both free indices at least 16 wide and one at least 64
+// (tiles 64 x 64, 16 x 64 or 64 x 16 divide the shape); complex128: both at
+// least 64 wide (64 x 64 tiles only).
 bool mfma_eligible(int dtype, const DOp &op) {
-  return dtype == TN_C64 && op.type == OP_CONTRACT && op.nB == 0 && op.nS >= 4 && op.nFX >= 4 && op.nFY >= 4 &&
-         (op.nFX >= 6 || op.nFY >= 6);
+  if (op.type != OP_CONTRACT || op.nB != 0 || op.nS < 4) return false;
+  if (dtype == TN_C128) return op.nFX >= 6 && op.nFY >= 6;
+  return dtype == TN_C64 && op.nFX >= 4 && op.nFY >= 4 && (op.nFX >= 6 || op.nFY >= 6);
 }
 
 // Tile rows / columns of an eligible op.
@@ -352,10 +388,10 @@ int mfma_tiles(const DOp &op) {
 }
 
 // Kernel variant of an op: bit 0 XK, bit 1 YK, bit 2 BM = 16, bit 3 BN = 16,
-// bit 4 split-BF16.
+// bit 4 split-BF16, bit 5 FP64.
 int mfma_variant(const DOp &op, int prec) {
   return (!(op.maskX & 1u) ? 1 : 0) | (!(op.maskY & 1u) ? 2 : 0) | (tile_m(op) == 16 ? 4 : 0) |
-         (tile_n(op) == 16 ? 8 : 0) | (prec == TN_MFMA_BF16X3 ? 16 : 0);
+         (tile_n(op) == 16 ? 8 : 0) | (prec == TN_MFMA_BF16X3 ? 16 : 0) | (prec == TN_MFMA_FP64 ? 32 : 0);
 }
 
 namespace {
@@ -368,8 +404,8 @@ void launch_one(const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream
 
 template <int PREC, bool XK, bool YK, int BM, int BN>
 void launch_group(const LItem *items, int n, int blocks, void *arena, int n_sets, const int32_t *tabs, hipStream_t st) {
-  hipLaunchKernelGGL((mfma_group_kernel<PREC, XK, YK, BM, BN>), dim3(blocks), dim3(256), 0, st, items, n,
-                     (float2 *)arena, n_sets, tabs);
+  hipLaunchKernelGGL((mfma_group_kernel<PREC, XK, YK, BM, BN>), dim3(blocks), dim3(256), 0, st, items, n, arena,
+                     n_sets, tabs);
 }
 
 // Calls F<PREC, XK, YK, BM, BN>::run(args...) for a variant index; false
@@ -377,7 +413,8 @@ void launch_group(const LItem *items, int n, int blocks, void *arena, int n_sets
 template <template <int, bool, bool, int, int> class F, typename... A>
 bool dispatch(int v, A... args) {
 #define QTN_TILE(PREC, XK, YK, BM, BN)              \
-  case (XK ? 1 : 0) | (YK ? 2 : 0) | (BM == 16 ? 4 : 0) | (BN == 16 ? 8 : 0) | (PREC == TN_MFMA_BF16X3 ? 16 : 0): \
+  case (XK ? 1 : 0) | (YK ? 2 : 0) | (BM == 16 ? 4 : 0) | (BN == 16 ? 8 : 0) | (PREC == TN_MFMA_BF16X3 ? 16 : 0) | \
+      (PREC == TN_MFMA_FP64 ? 32 : 0):              \
     F<PREC, XK, YK, BM, BN>::run(args...);          \
     return true;
 #define QTN_TILES(PREC, BM, BN) \
@@ -390,6 +427,7 @@ bool dispatch(int v, A... args) {
     QTN_TILES(TN_MFMA_BF16X3, 64, 64)
     QTN_TILES(TN_MFMA_BF16X3, 16, 64)
     QTN_TILES(TN_MFMA_BF16X3, 64, 16)
+    QTN_TILES(TN_MFMA_FP64, 64, 64)
     default:
       return false;
   }
@@ -414,7 +452,8 @@ struct GroupF {
 
 // prec: TN_MFMA_FP32 (4M FP32 products) or TN_MFMA_BF16X3 (split-BF16 products).
 hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, int prec, hipStream_t st) {
-  if (!mfma_eligible(TN_C64, op) || !dispatch<OneF>(mfma_variant(op, prec), &a, &op, tab, st)) return hipErrorInvalidValue;
+  if (!mfma_eligible(prec == TN_MFMA_FP64 ? TN_C128 : TN_C64, op) || !dispatch<OneF>(mfma_variant(op, prec), &a, &op, tab, st))
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -765,7 +765,7 @@ struct tn_batch {
   double flops_fwd = 0, bytes_fwd = 0, flops_grad = 0, bytes_grad = 0;
   int64_t level_bytes = 0;
   std::map<std::string, int> use_mfma;  // autotuner: shape class of a large op -> 1 MFMA, 0 thin
-  int mfma_prec = TN_MFMA_FP32;          // matrix-core precision of large complex64 steps
+  int mfma_prec = TN_MFMA_FP32;          // matrix-core precision of large steps (complex128: TN_MFMA_FP64)
   bool poisoned = false;
   qtn::GraphCache gc;
   // kernel timing (tn_batch_kernel_timing): event pairs around fused launches
@@ -1050,6 +1050,7 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   }
   std::unique_ptr<tn_batch> b(new tn_batch());
   b->dtype = n0->dtype;
+  b->mfma_prec = b->dtype == TN_C128 ? TN_MFMA_FP64 : TN_MFMA_FP32;
   b->n_nets = n_nets;
   b->n_params = n0->n_params;
   b->max_sets = max_sets;
@@ -1674,8 +1675,9 @@ int batch_kernel_time(tn_batch *b, int *n, double *total_ms) {
 }
 
 int batch_set_precision(tn_batch *b, int prec) {
-  if (prec != TN_MFMA_FP32 && prec != TN_MFMA_BF16X3) {
-    set_error("tn_batch_set_precision: unknown precision");
+  const bool ok = b->dtype == TN_C128 ? prec == TN_MFMA_FP64 : (prec == TN_MFMA_FP32 || prec == TN_MFMA_BF16X3);
+  if (!ok) {
+    set_error("tn_batch_set_precision: precision not available for this batch's dtype");
     return TN_EINVAL;
   }
   b->mfma_prec = prec;

@@ -17,7 +17,7 @@ TN_OK, TN_EINVAL, TN_ENOMEM, TN_EORDER, TN_EDEVICE, TN_ESTATE = 0, -1, -2, -3, -
 TN_H, TN_X, TN_Y, TN_Z, TN_RX, TN_RY, TN_RZ, TN_ZZ, TN_CNOT, TN_CZ, TN_U1, TN_U2, TN_SUPER1, TN_SUPER2 = range(14)
 TN_AMPLITUDE, TN_PROBABILITY, TN_EXPECTATION = 0, 1, 2
 TN_C64, TN_C128 = 0, 1
-TN_MFMA_FP32, TN_MFMA_BF16X3 = 1, 2
+TN_MFMA_FP32, TN_MFMA_BF16X3, TN_MFMA_FP64 = 1, 2, 3
 GATE_KINDS = {"H": TN_H, "X": TN_X, "Y": TN_Y, "Z": TN_Z, "RX": TN_RX, "RY": TN_RY, "RZ": TN_RZ, "ZZ": TN_ZZ,
               "CNOT": TN_CNOT, "CZ": TN_CZ, "U1": TN_U1, "U2": TN_U2, "SUPER1": TN_SUPER1, "SUPER2": TN_SUPER2}
 ERR_NAMES = {TN_EINVAL: "TN_EINVAL", TN_ENOMEM: "TN_ENOMEM", TN_EORDER: "TN_EORDER", TN_EDEVICE: "TN_EDEVICE",
@@ -267,7 +267,7 @@ class Batch:
         _check(lib().tn_batch_autotune(self.h, _dptr(params), params.shape[0], reps, cp, _stream(stream)))
 
     def set_precision(self, mfma_precision):
-        """TN_MFMA_FP32 or TN_MFMA_BF16X3 for the large complex64 steps."""
+        """TN_MFMA_FP32 or TN_MFMA_BF16X3 (complex64 batch), TN_MFMA_FP64 (complex128 batch)."""
         _check(lib().tn_batch_set_precision(self.h, mfma_precision))
 
     def kernel_timing(self, enable=True):

@@ -513,3 +513,40 @@ def test_level_mfma_tile_shapes(prec, monkeypatch):
     _say(f"level mfma tiles {prec}: cost rel {err_c:.2e} grad rel {err_g:.2e}")
     tol_c, tol_g = (1e-5, 1e-4) if prec == "fp32" else (3e-5, 3e-4)
     assert err_c <= tol_c and err_g <= tol_g
+
+
+def test_level_mfma_fp64(monkeypatch):
+    """complex128 batches take their large steps on FP64 matrix-core products
+    (64 x 64 tiles, FP64 accumulation): 4-regular n=14 p=2 light-cone networks
+    on the level executor, forward and adjoint, against the state-vector cost
+    (1e-12) and the parameter-shift gradient (1e-10). The precision is fixed
+    by the dtype: FP32 / split-BF16 are refused for complex128 and FP64 for
+    complex64."""
+    qtn, qaoa = _qtn(), _qaoa()
+    monkeypatch.setenv("QTN_FUSED_LDS_MAX", "0")
+    monkeypatch.setenv("QTN_GMEM_MAX_MACS", "0")
+    n = 14
+    e = workloads.random_regular_graph(4, n, 0)
+    S = 3
+    ang = torch.tensor(workloads.qaoa_angles(6, S, 2), device="cuda", dtype=torch.float64)
+    ref = np.array([gradients.cost(n, e, list(a)) for a in ang.cpu().numpy()])
+    ps = np.array([gradients.parameter_shift(n, e, list(a)) for a in ang.cpu().numpy()])
+    model = qaoa.MaxCut(n, e, 2, qtn.TN_C128, order="linegraph", max_sets=S, trials=4)
+    big = sum(1 for net in model.nets for fx, s, fy in net.plan_steps()
+              for a, ss, c in ((fx, s, fy), (fx, fy, s), (s, fx, fy)) if ss >= 4 and a >= 6 and c >= 6)
+    assert big > 0
+    for bad in (qtn.TN_MFMA_FP32, qtn.TN_MFMA_BF16X3):
+        with pytest.raises(qtn.QtnError):
+            model.batch.set_precision(bad)
+    model.batch.set_precision(qtn.TN_MFMA_FP64)
+    _say(f"level mfma fp64: {big} matrix-core steps (forward and adjoint shapes)")
+    obj, grad = model.value_and_grad(ang)
+    torch.cuda.synchronize()
+    obj, grad = obj.cpu().numpy(), grad.cpu().numpy()
+    err_c = float(np.max(np.abs(obj - ref)) / np.abs(ref).max())
+    err_g = float(np.max(np.abs(grad - ps)) / np.abs(ps).max())
+    _say(f"level mfma fp64: cost rel {err_c:.2e} grad rel {err_g:.2e}")
+    assert err_c <= 1e-12 and err_g <= 1e-10
+    m64 = qaoa.MaxCut(n, e[:4], 1, qtn.TN_C64, order="linegraph", max_sets=1, trials=2)
+    with pytest.raises(qtn.QtnError):
+        m64.batch.set_precision(qtn.TN_MFMA_FP64)
