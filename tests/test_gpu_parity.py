@@ -550,3 +550,48 @@ def test_level_mfma_fp64(monkeypatch):
     m64 = qaoa.MaxCut(n, e[:4], 1, qtn.TN_C64, order="linegraph", max_sets=1, trials=2)
     with pytest.raises(qtn.QtnError):
         m64.batch.set_precision(qtn.TN_MFMA_FP64)
+
+
+def test_graph_replay_with_overlapping_executors(monkeypatch):
+    """A batch split over the LDS fused, global-arena and level executors: the
+    global-arena and level work runs on a stream forked after binding and
+    joined before the combine. Eager passes and graph replays (with eager
+    work between them) give identical results, and the eager result matches
+    the state-vector oracle."""
+    qtn, qaoa = _qtn(), _qaoa()
+    n = 24
+    e = workloads.random_regular_graph(3, n, 2)
+    S = 4
+    ang = torch.tensor(workloads.qaoa_angles(7, S, 2), device="cuda", dtype=torch.float64)
+    # executor limits that split this batch three ways
+    for lds, macs in ((40960, 1 << 17), (49152, 1 << 17), (32768, 1 << 18), (49152, 1 << 16)):
+        monkeypatch.setenv("QTN_FUSED_LDS_MAX", str(lds))
+        monkeypatch.setenv("QTN_GMEM_MAX_MACS", str(macs))
+        model = qaoa.MaxCut(n, e, 2, qtn.TN_C64, order="linegraph", max_sets=S, trials=2)
+        info = model.batch.info()
+        _say(f"overlap lds={lds} macs={macs}: fused={info['n_fused']} global={info['n_global']} level={info['n_level']}")
+        if info["n_fused"] > 0 and info["n_global"] > 0 and info["n_level"] > 0:
+            break
+    assert info["n_fused"] > 0 and info["n_global"] > 0 and info["n_level"] > 0
+    # <C> from light-cone state vectors (exact; at most 14 qubits per edge)
+    ref = np.array([sum((1 - statevector.qaoa_zz_edge(n, e, a[:2], a[2:], ed)) / 2 for ed in e)
+                    for a in ang.cpu().numpy()])
+    obj_e, grad_e = model.value_and_grad(ang)
+    torch.cuda.synchronize()
+    obj_e, grad_e = obj_e.cpu().numpy(), grad_e.cpu().numpy()
+    assert np.max(np.abs(obj_e - ref)) <= 1e-5 * max(1, np.abs(ref).max())
+    st = torch.cuda.Stream()
+    obj = torch.empty(S, dtype=torch.float64, device="cuda")
+    grad = torch.empty((S, 4), dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        _say(f"overlap graph replay {rep}")
+        obj.fill_(-1.0)
+        grad.fill_(-1.0)
+        st.wait_stream(torch.cuda.current_stream())
+        model.batch.run_graph(True, ang, obj=obj, grad=grad, stream=st)
+        st.synchronize()
+        assert np.array_equal(obj.cpu().numpy(), obj_e)
+        assert np.array_equal(grad.cpu().numpy(), grad_e)
+        o2, g2 = model.value_and_grad(ang)  # eager pass between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(o2.cpu().numpy(), obj_e) and np.array_equal(g2.cpu().numpy(), grad_e)
