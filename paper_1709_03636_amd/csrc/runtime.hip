@@ -770,11 +770,12 @@ struct tn_batch {
   qtn::GraphCache gc;
   // kernel timing (tn_batch_kernel_timing): event pairs around fused launches
   bool timing = false, capturing = false;
-  // the global-arena and level executors run on `side`, forked from the
-  // caller's stream after binding and joined before the combine, so they
-  // overlap the LDS fused launch (independent networks)
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // with work on two or more executors, the global-arena executor runs on
+  // side[0] and the level executor on side[1], forked from the caller's
+  // stream after binding and joined before the combine, so the executors
+  // (independent networks) overlap
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
 };
 
@@ -803,10 +804,13 @@ static void free_batch_dev(tn_batch *b) {
   b->gc.clear();
   drop_timing_events(b);
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
-  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
-  if (b->side) (void)hipStreamDestroy(b->side);
-  b->ev_fork = b->ev_join = nullptr;
-  b->side = nullptr;
+  b->ev_fork = nullptr;
+  for (int i = 0; i < 2; ++i) {
+    if (b->ev_join[i]) (void)hipEventDestroy(b->ev_join[i]);
+    if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
+    b->ev_join[i] = nullptr;
+    b->side[i] = nullptr;
+  }
   void *ptrs[] = {b->d_nets_fwd, b->d_nets_grad, b->d_ops, b->d_recs, b->d_srecs[0], b->d_srecs[1], b->d_tabs, b->d_task_net, b->d_gtask_net, b->d_garena, b->d_consts, b->d_ptens,
                   b->d_slots, b->d_bound, b->d_dbound, b->d_val, b->d_gnet, b->d_coef, b->d_larena, b->d_lscal,
                   b->d_lpart, b->d_litems[0], b->d_litems[1]};
@@ -1172,10 +1176,12 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   if ((e = dalloc(&b->d_val, (size_t)n_nets * max_sets * 2)) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_gnet, (size_t)n_nets * max_sets * std::max(1, b->n_params))) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_coef, (size_t)n_nets)) != hipSuccess) return fail(e, "hipMalloc");
-  if (!b->task_net.empty() && (!b->gtask_net.empty() || !b->level.empty())) {
-    if ((e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking)) != hipSuccess) return fail(e, "hipStreamCreate");
+  if ((!b->task_net.empty()) + (!b->gtask_net.empty()) + (!b->level.empty()) >= 2) {
     if ((e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming)) != hipSuccess) return fail(e, "hipEventCreate");
-    if ((e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming)) != hipSuccess) return fail(e, "hipEventCreate");
+    for (int i = 0; i < 2; ++i) {
+      if ((e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking)) != hipSuccess) return fail(e, "hipStreamCreate");
+      if ((e = hipEventCreateWithFlags(&b->ev_join[i], hipEventDisableTiming)) != hipSuccess) return fail(e, "hipEventCreate");
+    }
   }
   {
     // bins: level networks that take every parameter vector at once, packed
@@ -1297,17 +1303,19 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     b->poisoned = true;
     return hip_fail(e, "binding launch");
   }
-  // the other executors' stream: forked when the LDS fused launch has work
-  hipStream_t so = st;
-  const bool fork = b->side && !b->task_net.empty();
+  // streams of the global-arena (sg) and level (sl) executors: forked when
+  // two or more executors have work
+  hipStream_t sg = st, sl = st;
+  const bool fork = b->ev_fork != nullptr;
   if (fork) {
     e = hipEventRecord(b->ev_fork, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamWaitEvent(b->side[i], b->ev_fork, 0);
     if (e != hipSuccess) {
       b->poisoned = true;
       return hip_fail(e, "stream fork");
     }
-    so = b->side;
+    sg = b->side[0];
+    sl = b->side[1];
   }
   const int spw = b->spw[v];
   if (spw > 1) {
@@ -1363,7 +1371,7 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     const int cap = std::max(1, std::min(std::min(gl.grid, b->gslots), g.n_tasks));
     const int rounds = (g.n_tasks + cap - 1) / cap;
     g.per_block = rounds;
-    e = launch_fused(b->dtype, 256, grad, false, true, g, (g.n_tasks + rounds - 1) / rounds, gl.lds, so);
+    e = launch_fused(b->dtype, 256, grad, false, true, g, (g.n_tasks + rounds - 1) / rounds, gl.lds, sg);
     if (e != hipSuccess) {
       b->poisoned = true;
       return hip_fail(e, "global-arena executor launch");
@@ -1386,28 +1394,28 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
       const LevelNet &ln = b->level[bn.lv[j]];
       e = level_setup(b->dtype, args(j), (const char *)b->d_consts + (size_t)ln.const_begin * eb, ln.n_const,
                       b->d_ptens + ln.ptens_begin, ln.n_ptens, b->d_bound, b->hp.per_set, 0, (int)ln.gbar_begin,
-                      grad ? (int)ln.ptens_elems : 0, so);
+                      grad ? (int)ln.ptens_elems : 0, sl);
     }
     for (const LevelBin::Step &stp : bn.steps[v]) {
       if (e == hipSuccess)
-        e = level_group(b->dtype, false, b->d_litems[v] + stp.t0, stp.nt, stp.tb, b->d_larena, n_sets, b->d_tabs, so);
+        e = level_group(b->dtype, false, b->d_litems[v] + stp.t0, stp.nt, stp.tb, b->d_larena, n_sets, b->d_tabs, sl);
       if (e == hipSuccess)
-        e = level_group(b->dtype, true, b->d_litems[v] + stp.l0, stp.nl, stp.lb, b->d_larena, n_sets, b->d_tabs, so);
+        e = level_group(b->dtype, true, b->d_litems[v] + stp.l0, stp.nl, stp.lb, b->d_larena, n_sets, b->d_tabs, sl);
       for (int g = stp.g0; g < stp.g0 + stp.ng && e == hipSuccess; ++g) {
         const LevelBin::MGroup &mg = bn.mg[v][g];
-        e = mfma_group(mg.variant, b->d_litems[v] + mg.i0, mg.n, mg.blocks, b->d_larena, n_sets, b->d_tabs, so);
+        e = mfma_group(mg.variant, b->d_litems[v] + mg.i0, mg.n, mg.blocks, b->d_larena, n_sets, b->d_tabs, sl);
       }
       for (int q = stp.o0; q < stp.o0 + stp.no && e == hipSuccess; ++q) {
         const int j = bn.other[v][q];
         const LevelNet &ln = b->level[bn.lv[j]];
         const DOp &op = b->hp.ops[ln.op_begin[v] + (int)(&stp - bn.steps[v].data())];
-        e = level_op(b->dtype, args(j), op, b->d_tabs, 0, so);
+        e = level_op(b->dtype, args(j), op, b->d_tabs, 0, sl);
       }
     }
     for (size_t j = 0; j < bn.lv.size() && e == hipSuccess; ++j) {
       const LevelNet &ln = b->level[bn.lv[j]];
       e = level_finish(b->dtype, args(j), b->d_ptens + ln.ptens_begin, ln.n_ptens, b->d_dbound, b->hp.per_set, 0, ln.net,
-                       n_sets, b->n_params, a.out_val, a.out_grad, grad ? 1 : 0, so);
+                       n_sets, b->n_params, a.out_val, a.out_grad, grad ? 1 : 0, sl);
     }
     if (e != hipSuccess) {
       b->poisoned = true;
@@ -1426,14 +1434,14 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
       la.part = b->d_lpart;
       e = level_setup(b->dtype, la, (const char *)b->d_consts + (size_t)ln.const_begin * eb, ln.n_const,
                       b->d_ptens + ln.ptens_begin, ln.n_ptens, b->d_bound, b->hp.per_set, s0, (int)ln.gbar_begin,
-                      grad ? (int)ln.ptens_elems : 0, so);
+                      grad ? (int)ln.ptens_elems : 0, sl);
       for (int o = 0; o < ln.n_ops[v] && e == hipSuccess; ++o) {
         const DOp &op = b->hp.ops[ln.op_begin[v] + o];
-        e = level_op(b->dtype, la, op, b->d_tabs, level_prec(b, op), so);
+        e = level_op(b->dtype, la, op, b->d_tabs, level_prec(b, op), sl);
       }
       if (e == hipSuccess)
         e = level_finish(b->dtype, la, b->d_ptens + ln.ptens_begin, ln.n_ptens, b->d_dbound, b->hp.per_set, s0, ln.net,
-                         n_sets, b->n_params, a.out_val, a.out_grad, grad ? 1 : 0, so);
+                         n_sets, b->n_params, a.out_val, a.out_grad, grad ? 1 : 0, sl);
       if (e != hipSuccess) {
         b->poisoned = true;
         return hip_fail(e, "level executor launch");
@@ -1441,8 +1449,10 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     }
   }
   if (fork) {
-    e = hipEventRecord(b->ev_join, so);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join, 0);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+      e = hipEventRecord(b->ev_join[i], b->side[i]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join[i], 0);
+    }
     if (e != hipSuccess) {
       b->poisoned = true;
       return hip_fail(e, "stream join");
