@@ -215,6 +215,8 @@ struct LevelNet {
 // launch per kind (thin contractions, leaf adjoints, matrix-core products
 // per kernel variant). Rank-0 and seed steps keep launches of their own.
 struct LevelBin {
+  int lane = 0;                // stream lane (bins of different lanes run concurrently)
+  int64_t part_off = 0;        // offset of its rank-0 partial sums (doubles)
   std::vector<int> lv;         // indices into tn_batch::level
   std::vector<int64_t> abase;  // arena region start (elements)
   std::vector<int64_t> sbase;  // component-scalar region start (doubles)
@@ -770,12 +772,12 @@ struct tn_batch {
   qtn::GraphCache gc;
   // kernel timing (tn_batch_kernel_timing): event pairs around fused launches
   bool timing = false, capturing = false;
-  // with work on two or more executors, the global-arena executor runs on
-  // side[0] and the level executor on side[1], forked from the caller's
-  // stream after binding and joined before the combine, so the executors
-  // (independent networks) overlap
-  hipStream_t side[2] = {nullptr, nullptr};
-  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+  // with work on two or more executors (or two level lanes), the
+  // global-arena executor runs on side[0] and the level lanes on side[1] and
+  // side[2], forked from the caller's stream after binding and joined before
+  // the combine, so the executors (independent networks) overlap
+  hipStream_t side[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
   std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
 };
 
@@ -805,7 +807,7 @@ static void free_batch_dev(tn_batch *b) {
   drop_timing_events(b);
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   b->ev_fork = nullptr;
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < 3; ++i) {
     if (b->ev_join[i]) (void)hipEventDestroy(b->ev_join[i]);
     if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
     b->ev_join[i] = nullptr;
@@ -1176,13 +1178,6 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   if ((e = dalloc(&b->d_val, (size_t)n_nets * max_sets * 2)) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_gnet, (size_t)n_nets * max_sets * std::max(1, b->n_params))) != hipSuccess) return fail(e, "hipMalloc");
   if ((e = dalloc(&b->d_coef, (size_t)n_nets)) != hipSuccess) return fail(e, "hipMalloc");
-  if ((!b->task_net.empty()) + (!b->gtask_net.empty()) + (!b->level.empty()) >= 2) {
-    if ((e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming)) != hipSuccess) return fail(e, "hipEventCreate");
-    for (int i = 0; i < 2; ++i) {
-      if ((e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking)) != hipSuccess) return fail(e, "hipStreamCreate");
-      if ((e = hipEventCreateWithFlags(&b->ev_join[i], hipEventDisableTiming)) != hipSuccess) return fail(e, "hipEventCreate");
-    }
-  }
   {
     // bins: level networks that take every parameter vector at once, packed
     // in order while their regions fit the level budget together
@@ -1211,11 +1206,45 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
       arena = std::max(arena, bin_elems * eb);
       scal = std::max(scal, bin_scal);
     }
+    // one group of several networks: split it into two halves that run
+    // concurrently on two streams (regions stay disjoint: the halves take
+    // consecutive ranges of the same arena), networks dealt alternately
+    if (b->lbins.size() == 1 && b->lbins[0].lv.size() >= 2 && b->lsolo.empty()) {
+      const LevelBin one = b->lbins[0];
+      b->lbins.assign(2, LevelBin{});
+      int64_t off = 0, soff = 0;
+      for (int h = 0; h < 2; ++h) {
+        LevelBin &bn = b->lbins[h];
+        bn.lane = h;
+        bn.part_off = h * part;
+        for (size_t j = h; j < one.lv.size(); j += 2) {
+          const LevelNet &ln = b->level[one.lv[j]];
+          bn.lv.push_back(one.lv[j]);
+          bn.abase.push_back(off);
+          bn.sbase.push_back(soff);
+          off += (ln.stride[ln.grad_ok ? 1 : 0] * max_sets + 63) / 64 * 64;
+          soff += (int64_t)max_sets * std::max(1, ln.n_comp) * 2;
+        }
+      }
+      part *= 2;
+    }
     b->level_bytes = arena;
     if (!b->level.empty()) {
       if ((e = dalloc((char **)&b->d_larena, (size_t)arena)) != hipSuccess) return fail(e, "hipMalloc (level arena)");
       if ((e = dalloc(&b->d_lscal, (size_t)scal)) != hipSuccess) return fail(e, "hipMalloc");
       if ((e = dalloc(&b->d_lpart, (size_t)part)) != hipSuccess) return fail(e, "hipMalloc");
+    }
+  }
+  // side streams only for the executors that have work (streams share the
+  // few hardware queues: an idle stream could take a busy one's queue)
+  const bool two_lanes = b->lbins.size() == 2 && b->lbins[1].lane == 1;
+  if ((!b->task_net.empty()) + (!b->gtask_net.empty()) + (!b->level.empty()) >= 2 || two_lanes) {
+    if ((e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming)) != hipSuccess) return fail(e, "hipEventCreate");
+    const bool need[3] = {!b->gtask_net.empty(), !b->level.empty(), two_lanes};
+    for (int i = 0; i < 3; ++i) {
+      if (!need[i]) continue;
+      if ((e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking)) != hipSuccess) return fail(e, "hipStreamCreate");
+      if ((e = hipEventCreateWithFlags(&b->ev_join[i], hipEventDisableTiming)) != hipSuccess) return fail(e, "hipEventCreate");
     }
   }
   std::vector<float> cf;
@@ -1303,19 +1332,21 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     b->poisoned = true;
     return hip_fail(e, "binding launch");
   }
-  // streams of the global-arena (sg) and level (sl) executors: forked when
-  // two or more executors have work
-  hipStream_t sg = st, sl = st;
+  // streams of the global-arena (sg) and level (sl: lane 0, sl1: lane 1)
+  // executors: forked when two or more of them have work
+  hipStream_t sg = st, sl = st, sl1 = st;
   const bool fork = b->ev_fork != nullptr;
   if (fork) {
     e = hipEventRecord(b->ev_fork, st);
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamWaitEvent(b->side[i], b->ev_fork, 0);
+    for (int i = 0; i < 3 && e == hipSuccess; ++i)
+      if (b->side[i]) e = hipStreamWaitEvent(b->side[i], b->ev_fork, 0);
     if (e != hipSuccess) {
       b->poisoned = true;
       return hip_fail(e, "stream fork");
     }
-    sg = b->side[0];
-    sl = b->side[1];
+    if (b->side[0]) sg = b->side[0];
+    if (b->side[1]) sl = sl1 = b->side[1];
+    if (b->side[2]) sl1 = b->side[2];
   }
   const int spw = b->spw[v];
   if (spw > 1) {
@@ -1379,6 +1410,7 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
   }
   const int eb = b->dtype == TN_C128 ? 16 : 8;
   for (const LevelBin &bn : b->lbins) {
+    hipStream_t bs = bn.lane == 1 ? sl1 : sl;
     auto args = [&](size_t j) {
       const LevelNet &ln = b->level[bn.lv[j]];
       LevelArgs la{};
@@ -1387,35 +1419,35 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
       la.n_sets = n_sets;
       la.scal = b->d_lscal + bn.sbase[j];
       la.n_comp = ln.n_comp;
-      la.part = b->d_lpart;
+      la.part = b->d_lpart + bn.part_off;
       return la;
     };
     for (size_t j = 0; j < bn.lv.size() && e == hipSuccess; ++j) {
       const LevelNet &ln = b->level[bn.lv[j]];
       e = level_setup(b->dtype, args(j), (const char *)b->d_consts + (size_t)ln.const_begin * eb, ln.n_const,
                       b->d_ptens + ln.ptens_begin, ln.n_ptens, b->d_bound, b->hp.per_set, 0, (int)ln.gbar_begin,
-                      grad ? (int)ln.ptens_elems : 0, sl);
+                      grad ? (int)ln.ptens_elems : 0, bs);
     }
     for (const LevelBin::Step &stp : bn.steps[v]) {
       if (e == hipSuccess)
-        e = level_group(b->dtype, false, b->d_litems[v] + stp.t0, stp.nt, stp.tb, b->d_larena, n_sets, b->d_tabs, sl);
+        e = level_group(b->dtype, false, b->d_litems[v] + stp.t0, stp.nt, stp.tb, b->d_larena, n_sets, b->d_tabs, bs);
       if (e == hipSuccess)
-        e = level_group(b->dtype, true, b->d_litems[v] + stp.l0, stp.nl, stp.lb, b->d_larena, n_sets, b->d_tabs, sl);
+        e = level_group(b->dtype, true, b->d_litems[v] + stp.l0, stp.nl, stp.lb, b->d_larena, n_sets, b->d_tabs, bs);
       for (int g = stp.g0; g < stp.g0 + stp.ng && e == hipSuccess; ++g) {
         const LevelBin::MGroup &mg = bn.mg[v][g];
-        e = mfma_group(mg.variant, b->d_litems[v] + mg.i0, mg.n, mg.blocks, b->d_larena, n_sets, b->d_tabs, sl);
+        e = mfma_group(mg.variant, b->d_litems[v] + mg.i0, mg.n, mg.blocks, b->d_larena, n_sets, b->d_tabs, bs);
       }
       for (int q = stp.o0; q < stp.o0 + stp.no && e == hipSuccess; ++q) {
         const int j = bn.other[v][q];
         const LevelNet &ln = b->level[bn.lv[j]];
         const DOp &op = b->hp.ops[ln.op_begin[v] + (int)(&stp - bn.steps[v].data())];
-        e = level_op(b->dtype, args(j), op, b->d_tabs, 0, sl);
+        e = level_op(b->dtype, args(j), op, b->d_tabs, 0, bs);
       }
     }
     for (size_t j = 0; j < bn.lv.size() && e == hipSuccess; ++j) {
       const LevelNet &ln = b->level[bn.lv[j]];
       e = level_finish(b->dtype, args(j), b->d_ptens + ln.ptens_begin, ln.n_ptens, b->d_dbound, b->hp.per_set, 0, ln.net,
-                       n_sets, b->n_params, a.out_val, a.out_grad, grad ? 1 : 0, sl);
+                       n_sets, b->n_params, a.out_val, a.out_grad, grad ? 1 : 0, bs);
     }
     if (e != hipSuccess) {
       b->poisoned = true;
@@ -1449,7 +1481,8 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     }
   }
   if (fork) {
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+      if (!b->side[i]) continue;
       e = hipEventRecord(b->ev_join[i], b->side[i]);
       if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join[i], 0);
     }

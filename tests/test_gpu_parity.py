@@ -275,7 +275,7 @@ def _mixed_level_budget(qtn, qaoa, n, e, S, monkeypatch):
     for k in range(30, 8, -1):
         monkeypatch.setenv("QTN_LEVEL_BUDGET", str(1 << k))
         info = qaoa.MaxCut(n, e, 2, qtn.TN_C128, order="linegraph", max_sets=S).batch.info()
-        if info["n_level_bins"] >= 2 and best is None:
+        if info["n_level_bins"] >= 3 and best is None:  # packed groups (one group is split in two lanes)
             best = 1 << k
         if info["n_level_bins"] >= 2 and info["n_level_chunked"] >= 1:
             return 1 << k
@@ -285,7 +285,8 @@ def _mixed_level_budget(qtn, qaoa, n, e, S, monkeypatch):
 def test_level_executor_matches_fused(monkeypatch):
     """The same batch on the LDS fused executor, on the global-arena fused
     executor and on the level executor: all networks stepped together in one
-    group (one launch per step and kind), in several groups with some
+    group (one launch per step and kind; the group is dealt over two stream
+    lanes that run concurrently), in several groups with some
     networks run alone (arena budget lowered), and every network alone in
     chunks of one parameter vector."""
     qtn, qaoa = _qtn(), _qaoa()
@@ -313,7 +314,7 @@ def test_level_executor_matches_fused(monkeypatch):
         if mode.startswith("level"):
             assert info["n_level"] == len(e) and info["n_fused"] == 0 and info["n_global"] == 0
         if mode == "level":
-            assert info["n_level_bins"] == 1 and info["n_level_chunked"] == 0
+            assert info["n_level_bins"] == 2 and info["n_level_chunked"] == 0  # one group, two stream lanes
         if mode == "level-mixed":
             assert info["n_level_bins"] >= 2
         if mode == "level-chunked":
@@ -503,7 +504,7 @@ def test_level_mfma_tile_shapes(prec, monkeypatch):
     assert shapes == {(64, 64), (16, 64), (64, 16)}
     model.batch.set_precision(qtn.TN_MFMA_FP32 if prec == "fp32" else qtn.TN_MFMA_BF16X3)
     info = model.batch.info()
-    assert info["n_level"] == len(e) and info["n_level_bins"] == 1
+    assert info["n_level"] == len(e) and info["n_level_bins"] == 2
     _say(f"level mfma tiles {prec} launches fwd={info['level_launches_fwd']} grad={info['level_launches_grad']}")
     obj, grad = model.value_and_grad(ang)
     torch.cuda.synchronize()
