@@ -1841,9 +1841,13 @@ void batch_free(tn_batch *b) {
 
 // Single-network plain path: a cached one-network batch; host parameters in,
 // host scalar out; synchronises the stream.
+// Device state of the one-network path: a one-network batch and a pinned,
+// device-mapped host block [params | value (2) | gradient] that the binding
+// kernel reads and the fused kernel writes directly (no copies per call).
 struct NetDev {
   tn_batch *b = nullptr;
-  double *d_params = nullptr, *d_out = nullptr, *d_grad = nullptr;
+  double *h_io = nullptr;                          // host view
+  double *d_params = nullptr, *d_out = nullptr, *d_grad = nullptr;  // device views of h_io
 };
 
 static int net_dev(Net &net, NetDev *&nd) {
@@ -1854,11 +1858,18 @@ static int net_dev(Net &net, NetDev *&nd) {
   int rc = batch_create(&self, 1, nullptr, 0.0, 1, &n->b);
   if (rc != TN_OK) return rc;
   hipError_t e;
-  if ((e = dalloc(&n->d_params, std::max(1, net.n_params))) != hipSuccess ||
-      (e = dalloc(&n->d_out, 2)) != hipSuccess || (e = dalloc(&n->d_grad, std::max(1, net.n_params))) != hipSuccess) {
+  const size_t np = (size_t)std::max(1, net.n_params);
+  double *dv = nullptr;
+  if ((e = hipHostMalloc((void **)&n->h_io, (2 * np + 2) * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent)) !=
+          hipSuccess ||
+      (e = hipHostGetDevicePointer((void **)&dv, n->h_io, 0)) != hipSuccess) {
+    if (n->h_io) (void)hipHostFree(n->h_io);
     batch_free(n->b);
-    return hip_fail(e, "hipMalloc");
+    return hip_fail(e, "hipHostMalloc");
   }
+  n->d_params = dv;
+  n->d_out = dv + np;
+  n->d_grad = dv + np + 2;
   nd = n.release();
   net.dev = nd;
   return TN_OK;
@@ -1868,8 +1879,7 @@ void net_dev_free(Net &net) {
   NetDev *nd = reinterpret_cast<NetDev *>(net.dev);
   if (!nd) return;
   batch_free(nd->b);
-  for (void *p : {(void *)nd->d_params, (void *)nd->d_out, (void *)nd->d_grad})
-    if (p) (void)hipFree(p);
+  if (nd->h_io) (void)hipHostFree(nd->h_io);
   delete nd;
   net.dev = nullptr;
 }
@@ -1896,9 +1906,10 @@ int net_contract(Net &net, const double *params, double *out, double *value, dou
     return hip_fail(e, w);
   };
   hipError_t e;
-  if (net.n_params > 0 &&
-      (e = hipMemcpyAsync(nd->d_params, params, net.n_params * sizeof(double), hipMemcpyHostToDevice, st)) != hipSuccess)
-    return bad(e, "hipMemcpyAsync");
+  // the previous call on this network has finished (it synchronised), so
+  // the mapped block is free to rewrite
+  const size_t np = (size_t)std::max(1, net.n_params);
+  if (net.n_params > 0) std::memcpy(nd->h_io, params, net.n_params * sizeof(double));
   const bool g = grad != nullptr;
   rc = g ? batch_grad(nd->b, nd->d_params, 1, nd->d_out, nullptr, nullptr, nd->d_grad, st)
          : batch_contract(nd->b, nd->d_params, 1, nd->d_out, nullptr, st);
@@ -1906,12 +1917,9 @@ int net_contract(Net &net, const double *params, double *out, double *value, dou
     net.poisoned = rc == TN_EDEVICE;
     return rc;
   }
-  double h[2];
-  if ((e = hipMemcpyAsync(h, nd->d_out, sizeof(h), hipMemcpyDeviceToHost, st)) != hipSuccess) return bad(e, "hipMemcpyAsync");
-  if (g && net.n_params > 0 &&
-      (e = hipMemcpyAsync(grad, nd->d_grad, net.n_params * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
-    return bad(e, "hipMemcpyAsync");
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return bad(e, "hipStreamSynchronize");
+  const double *h = nd->h_io + np;
+  if (g && net.n_params > 0) std::memcpy(grad, h + 2, net.n_params * sizeof(double));
   if (out) {
     out[0] = h[0];
     out[1] = h[1];
