@@ -266,11 +266,7 @@ __device__ __forceinline__ void contract_small_k(V *mem, const DOp &op, const in
     out_addr(op, tbB, (uint32_t)c, fx, fy);
     // operand reads in chunks of up to 8 entries, all issued before the
     // multiply-adds that consume them
-#ifdef QTN_CHUNK
-    constexpr int CH = K < QTN_CHUNK ? K : QTN_CHUNK;
-#else
     constexpr int CH = K < 8 ? K : 8;
-#endif
     V acc = czero<V>();
 #pragma unroll
     for (int k0 = 0; k0 < K; k0 += CH) {
@@ -459,11 +455,7 @@ __device__ __forceinline__ void scalar_rec(const V *mem, double2 *scal, const in
 // steps are still small: no launch per step, the slot stays in L2/MALL);
 // scratch, scalars and gradient sums stay in LDS.
 template <typename T, int BLOCK, bool GRAD, bool RONLY, bool GMEM>
-__global__ __launch_bounds__(BLOCK)
-#ifdef QTN_WAVES
-__attribute__((amdgpu_waves_per_eu(QTN_WAVES, QTN_WAVES)))
-#endif
-void fused_exec_kernel(FusedArgs a) {
+__global__ __launch_bounds__(BLOCK) void fused_exec_kernel(FusedArgs a) {
   using V = typename Cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   V *mem = GMEM ? reinterpret_cast<V *>(a.garena) + (size_t)blockIdx.x * a.garena_stride : reinterpret_cast<V *>(smem);
