@@ -128,8 +128,10 @@ __device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs,
   using R = typename Acc4<V>::R;
   using A4 = typename Acc4<V>::type;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nT = 1 << (op.nFY - T::LN);
-  const int n0 = (tile & (nT - 1)) * BN, m0 = (tile >> (op.nFY - T::LN)) * BM;
+  // a free index narrower than its tile side (2-3 bits) is one padded tile:
+  // rows / columns past it read aliased operand entries and are not written
+  const int sy = op.nFY > T::LN ? op.nFY - T::LN : 0;
+  const int n0 = (tile & ((1 << sy) - 1)) * BN, m0 = (tile >> sy) * BM;
   const V *X = base + op.x;
   const V *Y = base + op.y;
   V *Z = base + op.z;
@@ -181,7 +183,7 @@ __device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs,
     }
   }
   // result layout of the 16x16 tile (mfma4): column lane % 16, row per precision
-  const int N = 1 << op.nFY;
+  const int N = 1 << op.nFY, M = 1 << op.nFX;
 #pragma unroll
   for (int i = 0; i < T::WM; ++i)
 #pragma unroll
@@ -190,7 +192,7 @@ __device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs,
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wr + 16 * i + Acc4<V>::row(lk, r);
         const int col = n0 + wc + 16 * j + lr;
-        Z[(int64_t)row * N + col] = make_c(cre[i][j][r], cim[i][j][r]);
+        if (row < M && col < N) Z[(int64_t)row * N + col] = make_c(cre[i][j][r], cim[i][j][r]);
       }
 }
 
@@ -232,8 +234,10 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
                                             const DOp &op, const int32_t *__restrict__ tab, int tile) {
   using T = TileT<BM, BN>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nT = 1 << (op.nFY - T::LN);
-  const int n0 = (tile & (nT - 1)) * BN, m0 = (tile >> (op.nFY - T::LN)) * BM;
+  // a free index narrower than its tile side (2-3 bits) is one padded tile:
+  // rows / columns past it read aliased operand entries and are not written
+  const int sy = op.nFY > T::LN ? op.nFY - T::LN : 0;
+  const int n0 = (tile & ((1 << sy) - 1)) * BN, m0 = (tile >> sy) * BM;
   const float2 *X = base + op.x;
   const float2 *Y = base + op.y;
   float2 *Z = base + op.z;
@@ -297,7 +301,7 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
       }
     }
   }
-  const int N = 1 << op.nFY;
+  const int N = 1 << op.nFY, M = 1 << op.nFX;
 #pragma unroll
   for (int i = 0; i < T::WM; ++i)
 #pragma unroll
@@ -306,7 +310,7 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wr + 16 * i + 4 * lg + r;
         const int col = n0 + wc + 16 * j + lr;
-        Z[(int64_t)row * N + col] = make_float2(cre[i][j][r], cim[i][j][r]);
+        if (row < M && col < N) Z[(int64_t)row * N + col] = make_float2(cre[i][j][r], cim[i][j][r]);
       }
 }
 
@@ -360,7 +364,7 @@ __global__ __launch_bounds__(256) void mfma_group_kernel(const LItem *__restrict
   int rank, count;
   const LItem &it = items[group_item(items, n, &rank, &count)];
   const DOp op = it.op;
-  const int lt = op.nFX - T::LM + op.nFY - T::LN;  // log2 tiles per parameter vector
+  const int lt = (op.nFX > T::LM ? op.nFX - T::LM : 0) + (op.nFY > T::LN ? op.nFY - T::LN : 0);  // log2 tiles per set
   const int b = xcd_order(rank, count);
   const int set = b >> lt, tile = b & ((1 << lt) - 1);
   if (set >= n_sets) return;
@@ -369,13 +373,13 @@ __global__ __launch_bounds__(256) void mfma_group_kernel(const LItem *__restrict
 }
 
 // True when the MFMA path takes this op: no batch bits, at least 16 summed
-// entries; complex64: both free indices at least 16 wide and one at least 64
-// (tiles 64 x 64, 16 x 64 or 64 x 16 divide the shape); complex128: both at
-// least 64 wide (64 x 64 tiles only).
+// entries; complex64: one free index at least 64 wide, the other at least 4
+// (tiles 64 x 64, 16 x 64 or 64 x 16; a 4- or 8-wide index is one padded
+// 16-wide tile); complex128: both at least 64 wide (64 x 64 tiles only).
 bool mfma_eligible(int dtype, const DOp &op) {
   if (op.type != OP_CONTRACT || op.nB != 0 || op.nS < 4) return false;
   if (dtype == TN_C128) return op.nFX >= 6 && op.nFY >= 6;
-  return dtype == TN_C64 && op.nFX >= 4 && op.nFY >= 4 && (op.nFX >= 6 || op.nFY >= 6);
+  return dtype == TN_C64 && op.nFX >= 2 && op.nFY >= 2 && (op.nFX >= 6 || op.nFY >= 6);
 }
 
 // Tile rows / columns of an eligible op.
@@ -384,7 +388,8 @@ static inline int tile_n(const DOp &op) { return op.nFY >= 6 ? 64 : 16; }
 
 // Workgroups of an eligible op per parameter vector.
 int mfma_tiles(const DOp &op) {
-  return 1 << (op.nFX - (tile_m(op) == 64 ? 6 : 4) + op.nFY - (tile_n(op) == 64 ? 6 : 4));
+  const int lm = tile_m(op) == 64 ? 6 : 4, ln = tile_n(op) == 64 ? 6 : 4;
+  return 1 << ((op.nFX > lm ? op.nFX - lm : 0) + (op.nFY > ln ? op.nFY - ln : 0));
 }
 
 // Kernel variant of an op: bit 0 XK, bit 1 YK, bit 2 BM = 16, bit 3 BN = 16,

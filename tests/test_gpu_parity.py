@@ -481,7 +481,7 @@ def test_dense_split_bf16_precision():
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_level_mfma_tile_shapes(prec, monkeypatch):
     """Matrix-core products of every tile shape (64 x 64, and 16 x 64 / 64 x 16
-    where one free index has 4 or 5 bits), forward and adjoint, launched in
+    where one free index has 2 to 5 bits, padded below 4), forward and adjoint, launched in
     groups across the networks of a batch: 4-regular n=14 p=2 light-cone
     networks on the level executor, complex64, against the state-vector cost
     and the parameter-shift gradient."""
@@ -495,13 +495,14 @@ def test_level_mfma_tile_shapes(prec, monkeypatch):
     ref = np.array([gradients.cost(n, e, list(a)) for a in ang.cpu().numpy()])
     ps = np.array([gradients.parameter_shift(n, e, list(a)) for a in ang.cpu().numpy()])
     model = qaoa.MaxCut(n, e, 2, qtn.TN_C64, order="linegraph", max_sets=S, trials=4)
-    shapes = set()
+    shapes, padded = set(), 0
     for net in model.nets:
         for fx, s, fy in net.plan_steps():
             for a, ss, c in ((fx, s, fy), (fx, fy, s), (s, fx, fy)):  # the step and its two adjoints
-                if ss >= 4 and min(a, c) >= 4 and max(a, c) >= 6:
+                if ss >= 4 and min(a, c) >= 2 and max(a, c) >= 6:
                     shapes.add((64 if a >= 6 else 16, 64 if c >= 6 else 16))
-    assert shapes == {(64, 64), (16, 64), (64, 16)}
+                    padded += min(a, c) < 4  # a 4- or 8-wide index in a padded 16-wide tile
+    assert shapes == {(64, 64), (16, 64), (64, 16)} and padded > 0
     model.batch.set_precision(qtn.TN_MFMA_FP32 if prec == "fp32" else qtn.TN_MFMA_BF16X3)
     info = model.batch.info()
     assert info["n_level"] == len(e) and info["n_level_bins"] == 2
