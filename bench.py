@@ -396,6 +396,79 @@ def differentiation(st, dev):
     return res
 
 
+def crossover(st, dev):
+    """Tensor-network contraction against Hilbert-space simulation, QAOA p=1 on
+    seeded random d-regular graphs with 30 vertices, d = 3..7 (the paper's
+    crossover in degree): time per <C> (all edges) of the full complex64 state
+    vector on this GPU, of the batched light-cone networks (one angle set),
+    and of the whole-circuit folded networks (dense and diagonal gates) where
+    their largest intermediate fits (edge 0 timed, times |E|); n = 40 for the
+    light-cone networks, where the state vector (8 TiB) does not fit."""
+    import torch
+    import workloads
+    from oracle import closed_form
+    from paper_1709_03636_amd import qaoa, qtn
+    g0, b0 = 0.4, 0.3
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ws = None
+    rows = []
+    for n in (30, 40):
+        for d in (3, 4, 5, 6, 7):
+            e = workloads.random_regular_graph(d, n, GRAPH_SEED)
+            ref = closed_form.cost_p1(n, e, g0, b0)
+            row = {"d": d, "n": n, "edges": len(e), "cost_closed_form": ref}
+            if n <= 30:
+                need = qtn.lib().tn_sv_workspace_bytes(n)
+                if ws is None or ws.numel() < need:
+                    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+                v = qtn.sv_maxcut_p1(n, e, g0, b0, workspace=ws, stream=st)
+                t0 = time.perf_counter()
+                for _ in range(3):
+                    v = qtn.sv_maxcut_p1(n, e, g0, b0, workspace=ws, stream=st)
+                row["state_vector"] = {"ms_per_cost": (time.perf_counter() - t0) / 3 * 1e3, "abs_err": abs(v - ref),
+                                       "bytes": 8 * 2 ** n, "hbm_passes": -(-n // 5)}
+            else:
+                row["state_vector"] = {"infeasible": f"2^{n} complex64 amplitudes = {8 * 2 ** n / 2 ** 40:.0f} TiB"}
+            m = qaoa.MaxCut(n, e, 1, qtn.TN_C64, order="linegraph", max_sets=1, trials=4)
+            prm = torch.tensor([[g0, b0]], dtype=torch.float64, device=dev)
+            obj = torch.empty(1, dtype=torch.float64, device=dev)
+            for _ in range(3):
+                m.batch.run_graph(False, prm, obj=obj, stream=st)
+            ev0.record(st)
+            for _ in range(20):
+                m.batch.run_graph(False, prm, obj=obj, stream=st)
+            ev1.record(st)
+            torch.cuda.synchronize()
+            row["tn_lightcone"] = {"ms_per_cost": ev0.elapsed_time(ev1) / 20, "abs_err": abs(obj.item() - ref)}
+            if n <= 30:
+                for mode in ("dense", "diagonal"):
+                    net = qaoa.edge_network(n, e, 1, e[0], dtype=qtn.TN_C64, lightcone=False,
+                                            diagonal=mode == "diagonal")
+                    try:
+                        net.set_order(net.order_linegraph(trials=4, seed=0))
+                    except qtn.QtnError as ex:  # the order's largest intermediate passes the memory limit
+                        row[f"tn_whole_circuit_{mode}"] = {"infeasible": str(ex)}
+                        continue
+                    pi = net.plan_info()
+                    r = {"peak_bits": pi["peak_bits"], "flops_per_edge": pi["flops"]}
+                    if pi["peak_bits"] <= 28 and pi["flops"] <= 2e13:
+                        net.contract([g0, b0], stream=st)
+                        t0 = time.perf_counter()
+                        z = net.contract([g0, b0], stream=st)
+                        r["ms_per_edge"] = (time.perf_counter() - t0) * 1e3
+                        r["ms_per_cost_estimate"] = r["ms_per_edge"] * len(e)
+                        r["abs_err_zz_edge0"] = abs(z.real - closed_form.zz_p1(n, e, g0, b0)[0])
+                    else:
+                        r["infeasible"] = "largest intermediate beyond 2^28 entries or work beyond 2e13 flops"
+                    row[f"tn_whole_circuit_{mode}"] = r
+                    del net
+            rows.append(row)
+            log(f"crossover: {row}")
+    return {"workload": "QAOA p=1 Max-Cut <C>, random d-regular graphs, gamma=0.4, beta=0.3; time per <C> over all "
+                        "edges; state vector: full 2^n complex64 on this GPU",
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -602,6 +675,7 @@ def main():
     nxt = None if args.no_next else next_rows(model, params, edges, st, dev)
     grid = None if args.no_grid else batching_grid(st, dev)
     diff = None if args.no_grid else differentiation(st, dev)
+    cross = None if args.no_grid else crossover(st, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -638,6 +712,7 @@ def main():
         "next_rows": nxt,
         "batching_grid": grid,
         "differentiation_p2_n60": diff,
+        "crossover_in_degree": cross,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -272,6 +272,21 @@ int tn_grad_batch(tn_net *const *nets, int32_t n_nets, const double *params, int
 int tn_bind_params(tn_net *net, const double *params, int32_t n_sets, void *dst, int64_t *per_set,
                    void *stream);
 
+/* State-vector comparator (not the tensor-network path): <C> of the p=1 QAOA
+ * Max-Cut state, |psi> = exp(-i beta sum_q X_q) exp(-i gamma sum_E Z_u Z_v)
+ * H^n |0>, <C> = sum over edges of (1 - <Z_u Z_v>)/2, by a full 2^n complex64
+ * state vector on the GPU (FP32 amplitudes, FP64 accumulation). It is the
+ * Hilbert-space simulation the paper weighs tensor-network contraction
+ * against (Sec. Results, the crossover in graph degree). n_qubits 1..34;
+ * edges: host array of 2 * n_edges qubit indices (at most 256 edges, no
+ * loops); workspace: caller-owned device buffer of at least
+ * tn_sv_workspace_bytes(n_qubits) bytes, overwritten; cost: device pointer to
+ * one double. Asynchronous on stream; TN_EINVAL for bad arguments or a small
+ * workspace. */
+int64_t tn_sv_workspace_bytes(int32_t n_qubits);
+int tn_sv_maxcut_p1(int32_t n_qubits, const int32_t *edges, int32_t n_edges, double gamma, double beta,
+                    void *workspace, int64_t workspace_bytes, double *cost, void *stream);
+
 void tn_free(tn_net *net);
 void tn_batch_free(tn_batch *b);
 const char *tn_last_error(void);

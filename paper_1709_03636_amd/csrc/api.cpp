@@ -334,6 +334,13 @@ int tn_bind_params(tn_net *net, const double *params, int32_t n_sets, void *dst,
   GUARD({ return qtn::net_bind(*net, params, n_sets, dst, per_set, stream); })
 }
 
+int64_t tn_sv_workspace_bytes(int32_t n_qubits) { return qtn::sv_workspace_bytes(n_qubits); }
+
+int tn_sv_maxcut_p1(int32_t n_qubits, const int32_t *edges, int32_t n_edges, double gamma, double beta,
+                    void *workspace, int64_t workspace_bytes, double *cost, void *stream) {
+  GUARD({ return qtn::sv_maxcut_p1(n_qubits, edges, n_edges, gamma, beta, workspace, workspace_bytes, cost, stream); })
+}
+
 void tn_free(tn_net *net) {
   if (!net) return;
   qtn::net_dev_free(*net);

@@ -107,6 +107,11 @@ struct Net {
 // --- shared helpers ---------------------------------------------------------
 void set_error(const std::string &msg);
 
+// State-vector comparator (sv.hip).
+int64_t sv_workspace_bytes(int n);
+int sv_maxcut_p1(int n, const int32_t *edges, int n_edges, double gamma, double beta, void *workspace,
+                 int64_t ws_bytes, double *cost, void *stream);
+
 struct SplitMix64 {
   uint64_t s;
   explicit SplitMix64(uint64_t seed) : s(seed) {}

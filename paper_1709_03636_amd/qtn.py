@@ -87,6 +87,8 @@ _SIGS = {
     "tn_contract_batch": (_I, [ctypes.POINTER(_P), _I, _P, _I, _P, _P]),
     "tn_grad_batch": (_I, [ctypes.POINTER(_P), _I, _P, _I, _P, _P, _P]),
     "tn_bind_params": (_I, [_P, _P, _I, _P, ctypes.POINTER(ctypes.c_int64), _P]),
+    "tn_sv_workspace_bytes": (ctypes.c_int64, [_I]),
+    "tn_sv_maxcut_p1": (_I, [_I, _PI, _I, _D, _D, _P, ctypes.c_int64, _P, _P]),
     "tn_free": (None, [_P]),
     "tn_batch_free": (None, [_P]),
     "tn_last_error": (ctypes.c_char_p, []),
@@ -124,6 +126,27 @@ def _stream(stream):
         import torch
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def sv_maxcut_p1(n, edges, gamma, beta, workspace=None, stream=None):
+    """<C> of the p=1 QAOA Max-Cut state from a full 2^n complex64 state vector
+    on the GPU (tn_sv_maxcut_p1; the Hilbert-space comparator, not the
+    tensor-network path). workspace: optional cuda uint8 tensor of at least
+    tn_sv_workspace_bytes(n) bytes, reused across calls. Returns a float."""
+    import torch
+    need = lib().tn_sv_workspace_bytes(n)
+    if need < 0:
+        raise QtnError(TN_EINVAL, f"no state-vector workspace for {n} qubits")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1))
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    st.wait_stream(torch.cuda.current_stream())  # the buffers exist before the launch stream uses them
+    _check(lib().tn_sv_maxcut_p1(n, e.ctypes.data_as(_PI), len(e) // 2, float(gamma), float(beta),
+                                 _dptr(workspace), workspace.numel(), _dptr(out), _stream(st)))
+    st.synchronize()  # the result is final before `out` can be freed or read
+    return float(out.item())
 
 
 def make_gates(gates):

@@ -28,7 +28,7 @@ def qaoa():
 
 def test_library_exports_every_declared_symbol(qtn):
     hdr = open(os.path.join(ROOT, "include", "qtn.h")).read()
-    names = set(re.findall(r"^\s*(?:int|void|const char \*)\s*(tn_\w+)\s*\(", hdr, re.M))
+    names = set(re.findall(r"^\s*(?:int64_t|int|void|const char \*)\s*(tn_\w+)\s*\(", hdr, re.M))
     assert len(names) >= 20
     L = qtn.lib()
     for n in sorted(names):
@@ -305,3 +305,28 @@ def test_diagonal_mode_hyperedges_and_orders(qtn, qaoa):
     # also belongs to at least two other tensors
     steps = diag.plan_steps()
     assert len(steps) == b["n_steps"]
+
+
+def test_state_vector_comparator_arguments(qtn):
+    """Workspace size and argument checks of the state-vector comparator
+    (all rejected before any device work)."""
+    import ctypes
+    import numpy as np
+    L = qtn.lib()
+    assert L.tn_sv_workspace_bytes(0) == -1 and L.tn_sv_workspace_bytes(35) == -1
+    # 2^30 amplitudes of 8 bytes, then one FP64 partial sum per workgroup of the last pass (+1)
+    assert L.tn_sv_workspace_bytes(30) == 8 * 2 ** 30 + 8 * (2 ** 25 // 256 + 1)
+    assert L.tn_sv_workspace_bytes(3) == 8 * 8 + 8 * 2
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails its checks first
+
+    def call(n, edges, ws_bytes):
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1))
+        return L.tn_sv_maxcut_p1(n, e.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(e) // 2, 0.3, 0.2,
+                                 fake, ws_bytes, fake, None)
+
+    big = 1 << 40
+    assert call(35, [(0, 1)], big) == qtn.TN_EINVAL
+    assert call(8, [(3, 3)], big) == qtn.TN_EINVAL
+    assert call(8, [(0, 8)], big) == qtn.TN_EINVAL
+    assert call(8, [(0, 1)] * 257, big) == qtn.TN_EINVAL
+    assert call(8, [(0, 1)], L.tn_sv_workspace_bytes(8) - 1) == qtn.TN_EINVAL
