@@ -330,3 +330,20 @@ def test_state_vector_comparator_arguments(qtn):
     assert call(8, [(0, 8)], big) == qtn.TN_EINVAL
     assert call(8, [(0, 1)] * 257, big) == qtn.TN_EINVAL
     assert call(8, [(0, 1)], L.tn_sv_workspace_bytes(8) - 1) == qtn.TN_EINVAL
+
+
+def test_binding_constants_match_header(qtn):
+    """Every enumerator of the header has the same value in the binding."""
+    hdr = open(os.path.join(ROOT, "include", "qtn.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    found = 0
+    for body in re.findall(r"enum\s*\{(.*?)\}", hdr, re.S):
+        value = -1
+        for item in filter(None, (x.strip() for x in body.split(","))):
+            name, _, expr = item.partition("=")
+            name = name.strip()
+            value = int(expr.strip(), 0) if expr.strip() else value + 1
+            if hasattr(qtn, name):
+                assert getattr(qtn, name) == value, name
+                found += 1
+    assert found >= 20
