@@ -1,9 +1,11 @@
 // Level executor: runs network programs whose tensors do not fit in one
 // workgroup's LDS. Every buffer of a (network, parameter vector) pair lives
-// in a global-memory arena slice; each op of the program is one launch that
-// covers all parameter vectors of the chunk at once (the batch dimension),
-// with the same addressing as the fused executor (free-index deposit plus
-// a per-op offset table for the summed index, eq. (1)).
+// in a global-memory arena slice, with the same addressing as the fused
+// executor (free-index deposit plus a per-op offset table for the summed
+// index, eq. (1)). Networks stepped together run step k of all of them as
+// one grouped launch per kind (thin contractions, leaf adjoints; matrix-core
+// products in mfma.hip), over all parameter vectors at once; a network run
+// alone takes one launch per op over a chunk of parameter vectors.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
