@@ -71,6 +71,31 @@ __device__ __forceinline__ uint32_t l_deposit(uint32_t v, const int32_t runs[4],
   return r;
 }
 
+// Partial sum of output c of a contraction on one parameter vector's slice:
+// summed entries k = part, part + L, ...; the output index c = (i, b, j)
+// holds the X-only bits, the batch bits (offset table) and the Y-only bits.
+template <typename V>
+__device__ __forceinline__ V thin_output(const V *base, const DOp &op, const DRuns &ru, const int32_t *__restrict__ tab,
+                                         const int32_t *__restrict__ tabB, uint32_t c, int part, int L) {
+  const uint32_t rest = c >> op.nFY;
+  uint32_t bx = 0, by = 0;
+  if (op.nB) {
+    const uint32_t b = rest & ((1u << op.nB) - 1u);
+    bx = tabB[2 * b];
+    by = tabB[2 * b + 1];
+  }
+  const V *X = base + op.x + l_deposit(rest >> op.nB, ru.runsX, op.maskX) + bx;
+  const V *Y = base + op.y + l_deposit(c & ((1u << op.nFY) - 1u), ru.runsY, op.maskY) + by;
+  V acc;
+  acc.x = 0;
+  acc.y = 0;
+  for (int k = part; k < (1 << op.nS); k += L) {
+    const int2 t = l_tab(tab, op.nS, k);
+    acc = l_fma(acc, X[t.x], Y[t.y]);
+  }
+  return acc;
+}
+
 // Z[set][c] = sum_k X[set][fx(c) + tx(k)] * Y[set][fy(c) + ty(k)]; one output per thread.
 template <typename V>
 __global__ __launch_bounds__(256) void level_contract_kernel(LevelArgs a, DOp op, DRuns ru,
@@ -79,31 +104,12 @@ __global__ __launch_bounds__(256) void level_contract_kernel(LevelArgs a, DOp op
   const int lgOut = op.nFX + op.nB + op.nFY;
   const int64_t nOut = (int64_t)1 << lgOut;
   const int64_t total = nOut * a.n_sets;
-  const int K = 1 << op.nS;
-  const uint32_t maskJ = (1u << op.nFY) - 1u;
   V *arena = reinterpret_cast<V *>(a.arena);
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
     const int64_t set = g >> lgOut;
     const uint32_t c = (uint32_t)(g & (nOut - 1));
     V *base = arena + set * a.stride;
-    // output c = (i, b, j): X-only bits, batch bits (table), Y-only bits
-    const uint32_t rest = c >> op.nFY;
-    uint32_t bx = 0, by = 0;
-    if (op.nB) {
-      const uint32_t b = rest & ((1u << op.nB) - 1u);
-      bx = tabB[2 * b];
-      by = tabB[2 * b + 1];
-    }
-    const V *X = base + op.x + l_deposit(rest >> op.nB, ru.runsX, op.maskX) + bx;
-    const V *Y = base + op.y + l_deposit(c & maskJ, ru.runsY, op.maskY) + by;
-    V acc;
-    acc.x = 0;
-    acc.y = 0;
-    for (int k = 0; k < K; ++k) {
-      const int2 o = l_tab(tab, op.nS, k);
-      acc = l_fma(acc, X[o.x], Y[o.y]);
-    }
-    base[op.z + c] = acc;
+    base[op.z + c] = thin_output(base, op, ru, tab, tabB, c, 0, 1);
   }
 }
 
@@ -287,8 +293,6 @@ __global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *
   const int L = 1 << lgl;
   const int64_t nOut = (int64_t)1 << lgOut;
   const int64_t total = (nOut * n_sets) << lgl;
-  const int K = 1 << op.nS;
-  const uint32_t maskJ = (1u << op.nFY) - 1u;
   const int32_t *tab = tabs + op.tab;
   const int32_t *tabB = tabs + op.tabB;
   V *reg = arena + it.base;
@@ -298,22 +302,7 @@ __global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *
     const int64_t set = o >> lgOut;
     const uint32_t c = (uint32_t)(o & (nOut - 1));
     V *base = reg + set * it.stride;
-    const uint32_t rest = c >> op.nFY;
-    uint32_t bx = 0, by = 0;
-    if (op.nB) {
-      const uint32_t bb = rest & ((1u << op.nB) - 1u);
-      bx = tabB[2 * bb];
-      by = tabB[2 * bb + 1];
-    }
-    const V *X = base + op.x + l_deposit(rest >> op.nB, it.ru.runsX, op.maskX) + bx;
-    const V *Y = base + op.y + l_deposit(c & maskJ, it.ru.runsY, op.maskY) + by;
-    V acc;
-    acc.x = 0;
-    acc.y = 0;
-    for (int k = part; k < K; k += L) {
-      const int2 t = l_tab(tab, op.nS, k);
-      acc = l_fma(acc, X[t.x], Y[t.y]);
-    }
+    V acc = thin_output(base, op, it.ru, tab, tabB, c, part, L);
     for (int m = 1; m < L; m <<= 1) {
       acc.x += l_xor(acc.x, m);
       acc.y += l_xor(acc.y, m);

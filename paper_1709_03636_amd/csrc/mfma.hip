@@ -75,6 +75,19 @@ __device__ __forceinline__ uint32_t g_pdep(uint32_t v, uint32_t mask) {
   return r;
 }
 
+// Deposit of v's low bits at the set bits of mask, from the mask's runs of
+// consecutive bits (DRuns encoding; runs[0] < 0: more than four runs, bit loop).
+__device__ __forceinline__ uint32_t g_deposit(uint32_t v, const int32_t runs[4], uint32_t mask) {
+  if (runs[0] < 0) return g_pdep(v, mask);
+  uint32_t r = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t shift = runs[j] & 0xff, len = (runs[j] >> 8) & 0xff, pos = (uint32_t)runs[j] >> 16;
+    r |= __builtin_amdgcn_ubfe(v, shift, len) << pos;
+  }
+  return r;
+}
+
 __device__ __forceinline__ int2 g_tab(const int32_t *__restrict__ tb, int nS, int k) {
   if (nS <= kTabLoBits) return make_int2(tb[2 * k], tb[2 * k + 1]);
   const int lo = k & ((1 << kTabLoBits) - 1), hi = k >> kTabLoBits;
@@ -94,19 +107,19 @@ struct Stager {
   int xr[T::NX], xk[T::NX], yk[T::NY], yn[T::NY];
   uint32_t xrow[T::NX], ycol[T::NY];
   V xv[T::NX], yv[T::NY];
-  __device__ __forceinline__ Stager(const DOp &op, const int32_t *tab, int m0, int n0) {
+  __device__ __forceinline__ Stager(const DOp &op, const DRuns &ru, const int32_t *tab, int m0, int n0) {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < T::NX; ++i) {
       const int e = tid + 256 * i;
       if (XK) { xk[i] = e & (BK - 1); xr[i] = e >> 4; } else { xr[i] = e & (BM - 1); xk[i] = e >> T::LM; }
-      xrow[i] = g_pdep((uint32_t)(m0 + xr[i]), op.maskX) + (uint32_t)g_tab(tab, op.nS, xk[i]).x;
+      xrow[i] = g_deposit((uint32_t)(m0 + xr[i]), ru.runsX, op.maskX) + (uint32_t)g_tab(tab, op.nS, xk[i]).x;
     }
 #pragma unroll
     for (int i = 0; i < T::NY; ++i) {
       const int e = tid + 256 * i;
       if (YK) { yk[i] = e & (BK - 1); yn[i] = e >> 4; } else { yn[i] = e & (BN - 1); yk[i] = e >> T::LN; }
-      ycol[i] = g_pdep((uint32_t)(n0 + yn[i]), op.maskY) + (uint32_t)g_tab(tab, op.nS, yk[i]).y;
+      ycol[i] = g_deposit((uint32_t)(n0 + yn[i]), ru.runsY, op.maskY) + (uint32_t)g_tab(tab, op.nS, yk[i]).y;
     }
   }
   __device__ __forceinline__ void fetch(const V *X, const V *Y, const DOp &op, const int32_t *tab, int k0) {
@@ -122,7 +135,7 @@ struct Stager {
 // Output tile `tile` of the op on one parameter vector's arena slice, 4M
 // products in the precision of V (complex64: FP32, complex128: FP64).
 template <typename V, bool XK, bool YK, int BM, int BN>
-__device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs, V *base, const DOp &op,
+__device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs, V *base, const DOp &op, const DRuns &ru,
                                          const int32_t *__restrict__ tab, int tile) {
   using T = TileT<BM, BN>;
   using R = typename Acc4<V>::R;
@@ -136,7 +149,7 @@ __device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs,
   const V *Y = base + op.y;
   V *Z = base + op.z;
   const int K = 1 << op.nS;
-  Stager<XK, YK, BM, BN, V> sg(op, tab, m0, n0);
+  Stager<XK, YK, BM, BN, V> sg(op, ru, tab, m0, n0);
   A4 cre[T::WM][T::WN], cim[T::WM][T::WN];
 #pragma unroll
   for (int i = 0; i < T::WM; ++i)
@@ -231,7 +244,7 @@ __device__ __forceinline__ u32x4 swap_ri(u32x4 v) { return (v >> 16) | (v << 16)
 template <bool XK, bool YK, int BM, int BN>
 __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t *__restrict__ Al,
                                             uint32_t *__restrict__ Bh, uint32_t *__restrict__ Bl, float2 *base,
-                                            const DOp &op, const int32_t *__restrict__ tab, int tile) {
+                                            const DOp &op, const DRuns &ru, const int32_t *__restrict__ tab, int tile) {
   using T = TileT<BM, BN>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // a free index narrower than its tile side (2-3 bits) is one padded tile:
@@ -242,7 +255,7 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
   const float2 *Y = base + op.y;
   float2 *Z = base + op.z;
   const int K = 1 << op.nS;
-  Stager<XK, YK, BM, BN> sg(op, tab, m0, n0);
+  Stager<XK, YK, BM, BN> sg(op, ru, tab, m0, n0);
   mf4 cre[T::WM][T::WN], cim[T::WM][T::WN];
 #pragma unroll
   for (int i = 0; i < T::WM; ++i)
@@ -317,20 +330,21 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
 // One tile of any precision with its LDS; base: the parameter vector's
 // arena slice (complex128 for TN_MFMA_FP64, else complex64).
 template <int PREC, bool XK, bool YK, int BM, int BN>
-__device__ __forceinline__ void any_tile(void *base, const DOp &op, const int32_t *__restrict__ tab, int tile) {
+__device__ __forceinline__ void any_tile(void *base, const DOp &op, const DRuns &ru, const int32_t *__restrict__ tab,
+                                         int tile) {
   using T = TileT<BM, BN>;
   if constexpr (PREC == TN_MFMA_BF16X3) {
     __shared__ __align__(16) uint32_t Ah[BM * T::PS], Al[BM * T::PS];
     __shared__ __align__(16) uint32_t Bh[BN * T::PS], Bl[BN * T::PS];
-    bf16x3_tile<XK, YK, BM, BN>(Ah, Al, Bh, Bl, (float2 *)base, op, tab, tile);
+    bf16x3_tile<XK, YK, BM, BN>(Ah, Al, Bh, Bl, (float2 *)base, op, ru, tab, tile);
   } else if constexpr (PREC == TN_MFMA_FP64) {
     __shared__ double2 As[BM * T::AS];
     __shared__ double2 Bs[BK * T::BS];
-    c4m_tile<double2, XK, YK, BM, BN>(As, Bs, (double2 *)base, op, tab, tile);
+    c4m_tile<double2, XK, YK, BM, BN>(As, Bs, (double2 *)base, op, ru, tab, tile);
   } else {
     __shared__ float2 As[BM * T::AS];
     __shared__ float2 Bs[BK * T::BS];
-    c4m_tile<float2, XK, YK, BM, BN>(As, Bs, (float2 *)base, op, tab, tile);
+    c4m_tile<float2, XK, YK, BM, BN>(As, Bs, (float2 *)base, op, ru, tab, tile);
   }
 }
 
@@ -348,10 +362,10 @@ __device__ __forceinline__ int xcd_order(int b, int total) {
 
 // One op: grid (tiles, 1, parameter vectors).
 template <int PREC, bool XK, bool YK, int BM, int BN>
-__global__ __launch_bounds__(256) void mfma_cgemm_kernel(LevelArgs a, DOp op, const int32_t *__restrict__ tab) {
+__global__ __launch_bounds__(256) void mfma_cgemm_kernel(LevelArgs a, DOp op, DRuns ru, const int32_t *__restrict__ tab) {
   const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
   char *base = reinterpret_cast<char *>(a.arena) + (int64_t)blockIdx.z * a.stride * elem_bytes(PREC);
-  any_tile<PREC, XK, YK, BM, BN>(base, op, tab, b);
+  any_tile<PREC, XK, YK, BM, BN>(base, op, ru, tab, b);
 }
 
 // One step of several networks: each item is one op in its network's arena
@@ -368,7 +382,7 @@ __global__ __launch_bounds__(256) void mfma_group_kernel(const LItem *__restrict
   const int b = xcd_order(rank, count);
   const int set = b >> lt, tile = b & ((1 << lt) - 1);
   if (set >= n_sets) return;
-  any_tile<PREC, XK, YK, BM, BN>((char *)arena + (it.base + (int64_t)set * it.stride) * elem_bytes(PREC), op,
+  any_tile<PREC, XK, YK, BM, BN>((char *)arena + (it.base + (int64_t)set * it.stride) * elem_bytes(PREC), op, it.ru,
                                  tabs + op.tab, tile);
 }
 
@@ -403,8 +417,11 @@ namespace {
 
 template <int PREC, bool XK, bool YK, int BM, int BN>
 void launch_one(const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream_t st) {
+  DRuns ru;
+  pack_runs(op.maskX, ru.runsX);
+  pack_runs(op.maskY, ru.runsY);
   hipLaunchKernelGGL((mfma_cgemm_kernel<PREC, XK, YK, BM, BN>), dim3(mfma_tiles(op), 1, a.n_sets), dim3(256), 0, st, a,
-                     op, tab);
+                     op, ru, tab);
 }
 
 template <int PREC, bool XK, bool YK, int BM, int BN>

@@ -914,6 +914,8 @@ static int build_level_items(tn_batch *b) {
           const LevelNet &ln = b->level[bn.lv[j]];
           LItem it{};
           it.op = b->hp.ops[ln.op_begin[v] + k];
+          pack_runs(it.op.maskX, it.ru.runsX);
+          pack_runs(it.op.maskY, it.ru.runsY);
           it.base = bn.abase[j];
           it.stride = ln.stride[v];
           it.blk0 = g.blocks;
