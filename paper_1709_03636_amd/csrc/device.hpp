@@ -128,7 +128,8 @@ constexpr int kSetContract = 1, kSetScalar = 2, kSetSeed = 3, kSetLeafGrad = 4;
 // works in its own region of the level arena (`base` elements from its
 // start, `stride` elements per parameter vector).
 // Workgroups [blk0, next item's blk0) of a grouped launch serve the item;
-// a thin contraction sums each output on 2^lgl lanes.
+// a thin contraction sums each output on 2^lgl lanes (lgl < 0: a lane
+// computes four consecutive outputs).
 struct LItem {
   DOp op;
   DRuns ru;

@@ -275,13 +275,49 @@ __global__ __launch_bounds__(256) void level_finish_kernel(LevelArgs a, const DP
 __device__ __forceinline__ float l_xor(float v, int m) { return __shfl_xor(v, m, 64); }
 __device__ __forceinline__ double l_xor(double v, int m) { return __shfl_xor(v, m, 64); }
 
+// Four consecutive outputs c0 .. c0+3 of one parameter vector (c0 a multiple
+// of 4, at least 2 Y-only bits): they share the X row, and their Y columns
+// sit at fixed offsets deposit(r) from the first (disjoint bits add), so one
+// X read serves four products.
+template <typename V>
+__device__ __forceinline__ void thin_output4(V *base, const DOp &op, const DRuns &ru, const int32_t *__restrict__ tab,
+                                            const int32_t *__restrict__ tabB, uint32_t c0) {
+  const uint32_t rest = c0 >> op.nFY;
+  uint32_t bx = 0, by = 0;
+  if (op.nB) {
+    const uint32_t b = rest & ((1u << op.nB) - 1u);
+    bx = tabB[2 * b];
+    by = tabB[2 * b + 1];
+  }
+  const V *X = base + op.x + l_deposit(rest >> op.nB, ru.runsX, op.maskX) + bx;
+  const V *Y = base + op.y + l_deposit(c0 & ((1u << op.nFY) - 1u), ru.runsY, op.maskY) + by;
+  uint32_t dy[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) dy[r] = l_deposit((uint32_t)r, ru.runsY, op.maskY);
+  V acc[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    acc[r].x = 0;
+    acc[r].y = 0;
+  }
+  for (int k = 0; k < (1 << op.nS); ++k) {
+    const int2 t = l_tab(tab, op.nS, k);
+    const V x = X[t.x];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = l_fma(acc[r], x, Y[t.y + dy[r]]);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) base[op.z + c0 + r] = acc[r];
+}
+
 // Thin contractions of several networks at once: each item is one op of one
 // network, with the addressing of level_contract_kernel inside the
 // network's own arena region. An output is summed by L = 2^lgl adjacent
 // lanes (summed entries k = part, part + L, ...; then a butterfly over the
 // L lanes), so that steps with few outputs and long sums still fill the
 // chip. All L lanes of an output are in the same loop iteration: the
-// stride is a multiple of 256 and the total a multiple of L.
+// stride is a multiple of 256 and the total a multiple of L. lgl < 0: a
+// lane computes four consecutive outputs instead (steps with many outputs).
 template <typename V>
 __global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *__restrict__ items, int n, V *arena,
                                                                    int n_sets, const int32_t *__restrict__ tabs) {
@@ -289,13 +325,23 @@ __global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *
   const LItem &it = items[group_item(items, n, &rank, &count)];
   const DOp op = it.op;
   const int lgOut = op.nFX + op.nB + op.nFY;
+  const int32_t *tab = tabs + op.tab;
+  const int32_t *tabB = tabs + op.tabB;
+  V *reg = arena + it.base;
+  if (it.lgl < 0) {  // four outputs per lane (nFY >= 2, so lgOut >= 2)
+    const int64_t nq = (int64_t)1 << (lgOut - 2);
+    const int64_t total4 = nq * n_sets;
+    for (int64_t g = rank * (int64_t)256 + threadIdx.x; g < total4; g += (int64_t)count * 256) {
+      const int64_t set = g >> (lgOut - 2);
+      const uint32_t c0 = (uint32_t)(g & (nq - 1)) << 2;
+      thin_output4(reg + set * it.stride, op, it.ru, tab, tabB, c0);
+    }
+    return;
+  }
   const int lgl = it.lgl;
   const int L = 1 << lgl;
   const int64_t nOut = (int64_t)1 << lgOut;
   const int64_t total = (nOut * n_sets) << lgl;
-  const int32_t *tab = tabs + op.tab;
-  const int32_t *tabB = tabs + op.tabB;
-  V *reg = arena + it.base;
   for (int64_t g = rank * (int64_t)256 + threadIdx.x; g < total; g += (int64_t)count * 256) {
     const int part = (int)(g & (L - 1));
     const int64_t o = g >> lgl;

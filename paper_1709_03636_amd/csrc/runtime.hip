@@ -862,6 +862,11 @@ static int build_level_items(tn_batch *b) {
               while ((int64_t(1) << lgs) < b->max_sets) ++lgs;
               it.lgl = std::max(0, std::min({6, op.nS - 3, 20 - lg - lgs}));
               work <<= it.lgl;
+              // many outputs: four per lane instead (shared X reads)
+              if (it.lgl == 0 && op.nFY >= 2 && lg + lgs >= 16) {
+                it.lgl = -1;
+                work >>= 2;
+              }
             }
             it.op = op;
             pack_runs(op.maskX, it.ru.runsX);
