@@ -635,6 +635,21 @@ def main():
         torch.cuda.synchronize()
         d_ms = ev0.elapsed_time(ev1) / reps
         zz_ref = closed_form.zz_p1(dn, de, angles[0, 0], angles[0, 1])[0]
+        # forward + adjoint gradient of the same network (FP32 products)
+        dgn = torch.empty((1, 1, 2), dtype=torch.float64, device=dev)
+        doutg = torch.empty_like(dout)
+        dbatch.grad(dpar, out=doutg, grad_net=dgn, stream=st)
+        st.synchronize()
+        ev0.record(st)
+        for _ in range(reps):
+            dbatch.grad(dpar, out=doutg, grad_net=dgn, stream=st)
+        ev1.record(st)
+        torch.cuda.synchronize()
+        g_ms = ev0.elapsed_time(ev1) / reps
+        dbi = dbatch.info()
+        g_flops = dbi["flops_fwd"] + dbi["flops_grad"]
+        dg_ref, db_ref = closed_form.zz_p1_grad(dn, de, angles[0, 0], angles[0, 1])
+        g_err = float(np.max(np.abs(dgn[0, 0].cpu().numpy() - np.array([dg_ref[0], db_ref[0]]))))
         # split-BF16 products on the same network
         dbatch.set_precision(qtn.TN_MFMA_BF16X3)
         dbatch.autotune(dpar, reps=2, stream=st)
@@ -665,6 +680,10 @@ def main():
                 "tflops": dinfo["flops"] / (d_ms * 1e-3) / 1e12,
                 "frac_of_fp32_matrix_peak": dinfo["flops"] / (d_ms * 1e-3) / FP32_MFMA_PEAK,
                 "abs_err_zz_vs_closed_form": abs(dout[0, 0, 0].item() - zz_ref),
+                "fwd_grad": {"pass_ms": g_ms, "flops_per_pass": g_flops,
+                             "tflops": g_flops / (g_ms * 1e-3) / 1e12,
+                             "frac_of_fp32_matrix_peak": g_flops / (g_ms * 1e-3) / FP32_MFMA_PEAK,
+                             "abs_err_grad_vs_closed_form": g_err},
                 "split_bf16": {"pass_ms": b_ms, "tflops_fp32_equivalent": dinfo["flops"] / (b_ms * 1e-3) / 1e12,
                                "abs_err_zz_vs_closed_form": abs(dout2[0, 0, 0].item() - zz_ref)},
                 "complex128_fp64": {"pass_ms": f_ms, "tflops": dinfo["flops"] / (f_ms * 1e-3) / 1e12,

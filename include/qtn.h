@@ -225,6 +225,8 @@ typedef struct {
   int32_t n_level_chunked;            /* level networks run alone, in chunks of parameter vectors */
   int32_t level_launches_fwd;         /* kernel launches of the level executor per pass with all */
   int32_t level_launches_grad;        /* parameter vectors: forward / forward+adjoint */
+  int32_t level_split_fwd;            /* matrix-core products of grouped level steps whose summed */
+  int32_t level_split_grad;           /* index is split over workgroups: forward / forward+adjoint */
   double flops_fwd, bytes_fwd;        /* algorithmic, one parameter vector, all networks */
   double flops_grad, bytes_grad;      /* algorithmic, adjoint sweep only */
 } tn_batch_stats;

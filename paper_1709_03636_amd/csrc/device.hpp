@@ -129,11 +129,13 @@ constexpr int kSetContract = 1, kSetScalar = 2, kSetSeed = 3, kSetLeafGrad = 4;
 // start, `stride` elements per parameter vector).
 // Workgroups [blk0, next item's blk0) of a grouped launch serve the item;
 // a thin contraction sums each output on 2^lgl lanes (lgl < 0: a lane
-// computes four consecutive outputs).
+// computes four consecutive outputs); a matrix-core product splits its
+// summed index into 2^lgl ranges, whose partial results go to a scratch
+// buffer from element zs.
 struct LItem {
   DOp op;
   DRuns ru;
-  int64_t base, stride;
+  int64_t base, stride, zs;
   int32_t blk0, lgl;
 };
 

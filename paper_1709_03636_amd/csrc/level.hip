@@ -126,6 +126,7 @@ __global__ __launch_bounds__(256) void level_scalar_part_kernel(LevelArgs a, DOp
   const V *base = reinterpret_cast<const V *>(a.arena) + set * a.stride;
   const int64_t K = (int64_t)1 << op.nS;
   double re = 0.0, im = 0.0;
+#pragma unroll 4
   for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < K; k += (int64_t)G * 256) {
     const int2 o = l_tab(tab, op.nS, (int)k);
     const double2 x = l_d2(base[op.x + o.x]);
@@ -403,9 +404,9 @@ static hipError_t level_op_t(const LevelArgs &a, const DOp &op, const int32_t *t
       break;
     }
     case OP_SCALAR: {
-      // enough workgroups for large sums, at most kScalarParts per set
+      // about four summed entries per thread, at most kScalarParts workgroups per set
       const int64_t K = (int64_t)1 << op.nS;
-      const int G = (int)std::min<int64_t>(kScalarParts, std::max<int64_t>(1, K / 4096));
+      const int G = (int)std::min<int64_t>(kScalarParts, std::max<int64_t>(1, K / 1024));
       hipLaunchKernelGGL(level_scalar_part_kernel<V>, dim3(G, a.n_sets), dim3(256), 0, st, a, op, tab, a.part);
       hipLaunchKernelGGL(level_scalar_final_kernel, dim3((a.n_sets + 63) / 64), dim3(64), 0, st, a, op, a.part, G);
       break;

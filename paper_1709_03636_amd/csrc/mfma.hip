@@ -14,6 +14,14 @@
 // when one free index has only 4 or 5 bits) for four waves; 16 complex
 // summed entries per LDS stage, the next stage prefetched into registers
 // while the matrix cores work on the current one.
+//
+// Split summed index: a product with few output tiles and a long sum (the
+// adjoints of late steps: small result, large summed index) would occupy a
+// handful of workgroups for the whole sum. Such an item of a grouped launch
+// is split into 2^s ranges of the summed index, each tile-range pair on its
+// own workgroup writing a partial tile to a scratch buffer; a second grouped
+// kernel adds the partials of every output in range order (FP64 sums, so the
+// result does not depend on scheduling).
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -134,9 +142,12 @@ struct Stager {
 
 // Output tile `tile` of the op on one parameter vector's arena slice, 4M
 // products in the precision of V (complex64: FP32, complex128: FP64).
+// Summed entries [kb, ke) (multiples of 16); the tile is written to Z
+// (row-major M x N).
 template <typename V, bool XK, bool YK, int BM, int BN>
-__device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs, V *base, const DOp &op, const DRuns &ru,
-                                         const int32_t *__restrict__ tab, int tile) {
+__device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs, const V *base, const DOp &op,
+                                         const DRuns &ru, const int32_t *__restrict__ tab, int tile, int kb, int ke,
+                                         V *__restrict__ Z) {
   using T = TileT<BM, BN>;
   using R = typename Acc4<V>::R;
   using A4 = typename Acc4<V>::type;
@@ -147,8 +158,6 @@ __device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs,
   const int n0 = (tile & ((1 << sy) - 1)) * BN, m0 = (tile >> sy) * BM;
   const V *X = base + op.x;
   const V *Y = base + op.y;
-  V *Z = base + op.z;
-  const int K = 1 << op.nS;
   Stager<XK, YK, BM, BN, V> sg(op, ru, tab, m0, n0);
   A4 cre[T::WM][T::WN], cim[T::WM][T::WN];
 #pragma unroll
@@ -162,15 +171,15 @@ __device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs,
   const int lr = lane & 15, lk = lane >> 4;  // MFMA operand row/col and real-k index
   const int part = lk & 1;
 
-  sg.fetch(X, Y, op, tab, 0);
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  sg.fetch(X, Y, op, tab, kb);
+  for (int k0 = kb; k0 < ke; k0 += BK) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < T::NX; ++i) As[sg.xr[i] * T::AS + sg.xk[i]] = sg.xv[i];
 #pragma unroll
     for (int i = 0; i < T::NY; ++i) Bs[sg.yk[i] * T::BS + sg.yn[i]] = sg.yv[i];
     __syncthreads();
-    if (k0 + BK < K) sg.fetch(X, Y, op, tab, k0 + BK);
+    if (k0 + BK < ke) sg.fetch(X, Y, op, tab, k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 2) {
       const int kc = kk + (lk >> 1);
@@ -243,8 +252,9 @@ __device__ __forceinline__ u32x4 swap_ri(u32x4 v) { return (v >> 16) | (v << 16)
 // packed pairs, hi and lo parts.
 template <bool XK, bool YK, int BM, int BN>
 __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t *__restrict__ Al,
-                                            uint32_t *__restrict__ Bh, uint32_t *__restrict__ Bl, float2 *base,
-                                            const DOp &op, const DRuns &ru, const int32_t *__restrict__ tab, int tile) {
+                                            uint32_t *__restrict__ Bh, uint32_t *__restrict__ Bl, const float2 *base,
+                                            const DOp &op, const DRuns &ru, const int32_t *__restrict__ tab, int tile,
+                                            int kb, int ke, float2 *__restrict__ Z) {
   using T = TileT<BM, BN>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // a free index narrower than its tile side (2-3 bits) is one padded tile:
@@ -253,8 +263,6 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
   const int n0 = (tile & ((1 << sy) - 1)) * BN, m0 = (tile >> sy) * BM;
   const float2 *X = base + op.x;
   const float2 *Y = base + op.y;
-  float2 *Z = base + op.z;
-  const int K = 1 << op.nS;
   Stager<XK, YK, BM, BN> sg(op, ru, tab, m0, n0);
   mf4 cre[T::WM][T::WN], cim[T::WM][T::WN];
 #pragma unroll
@@ -267,8 +275,8 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
   const int wr = (wave / T::GN) * 16 * T::WM, wc = (wave % T::GN) * 16 * T::WN;
   const int lr = lane & 15, lg = lane >> 4;  // operand row/col, group of 4 complex summed entries
 
-  sg.fetch(X, Y, op, tab, 0);
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  sg.fetch(X, Y, op, tab, kb);
+  for (int k0 = kb; k0 < ke; k0 += BK) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < T::NX; ++i) {
@@ -285,7 +293,7 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
       Bl[sg.yn[i] * T::PS + sg.yk[i]] = l;
     }
     __syncthreads();
-    if (k0 + BK < K) sg.fetch(X, Y, op, tab, k0 + BK);
+    if (k0 + BK < ke) sg.fetch(X, Y, op, tab, k0 + BK);
     u32x4 ah[T::WM], al[T::WM], bh[T::WN], bl[T::WN];
 #pragma unroll
     for (int i = 0; i < T::WM; ++i) {
@@ -327,24 +335,25 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
       }
 }
 
-// One tile of any precision with its LDS; base: the parameter vector's
-// arena slice (complex128 for TN_MFMA_FP64, else complex64).
+// One tile of any precision with its LDS over summed entries [kb, ke);
+// base: the parameter vector's arena slice (complex128 for TN_MFMA_FP64,
+// else complex64); z: where the M x N result goes.
 template <int PREC, bool XK, bool YK, int BM, int BN>
-__device__ __forceinline__ void any_tile(void *base, const DOp &op, const DRuns &ru, const int32_t *__restrict__ tab,
-                                         int tile) {
+__device__ __forceinline__ void any_tile(const void *base, const DOp &op, const DRuns &ru,
+                                         const int32_t *__restrict__ tab, int tile, int kb, int ke, void *z) {
   using T = TileT<BM, BN>;
   if constexpr (PREC == TN_MFMA_BF16X3) {
     __shared__ __align__(16) uint32_t Ah[BM * T::PS], Al[BM * T::PS];
     __shared__ __align__(16) uint32_t Bh[BN * T::PS], Bl[BN * T::PS];
-    bf16x3_tile<XK, YK, BM, BN>(Ah, Al, Bh, Bl, (float2 *)base, op, ru, tab, tile);
+    bf16x3_tile<XK, YK, BM, BN>(Ah, Al, Bh, Bl, (const float2 *)base, op, ru, tab, tile, kb, ke, (float2 *)z);
   } else if constexpr (PREC == TN_MFMA_FP64) {
     __shared__ double2 As[BM * T::AS];
     __shared__ double2 Bs[BK * T::BS];
-    c4m_tile<double2, XK, YK, BM, BN>(As, Bs, (double2 *)base, op, ru, tab, tile);
+    c4m_tile<double2, XK, YK, BM, BN>(As, Bs, (const double2 *)base, op, ru, tab, tile, kb, ke, (double2 *)z);
   } else {
     __shared__ float2 As[BM * T::AS];
     __shared__ float2 Bs[BK * T::BS];
-    c4m_tile<float2, XK, YK, BM, BN>(As, Bs, (float2 *)base, op, ru, tab, tile);
+    c4m_tile<float2, XK, YK, BM, BN>(As, Bs, (const float2 *)base, op, ru, tab, tile, kb, ke, (float2 *)z);
   }
 }
 
@@ -365,25 +374,57 @@ template <int PREC, bool XK, bool YK, int BM, int BN>
 __global__ __launch_bounds__(256) void mfma_cgemm_kernel(LevelArgs a, DOp op, DRuns ru, const int32_t *__restrict__ tab) {
   const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
   char *base = reinterpret_cast<char *>(a.arena) + (int64_t)blockIdx.z * a.stride * elem_bytes(PREC);
-  any_tile<PREC, XK, YK, BM, BN>(base, op, ru, tab, b);
+  any_tile<PREC, XK, YK, BM, BN>(base, op, ru, tab, b, 0, 1 << op.nS, base + (int64_t)op.z * elem_bytes(PREC));
 }
 
 // One step of several networks: each item is one op in its network's arena
-// region, on (tiles x parameter vectors) workgroups; the workgroups of
-// parameter vectors past n_sets return at once.
+// region, on (tiles x 2^lgl summed-index ranges x parameter vectors)
+// workgroups; the workgroups of parameter vectors past n_sets return at
+// once. An item with lgl > 0 writes partial tiles to `split` (from element
+// zs: [parameter vector][range][M x N]).
 template <int PREC, bool XK, bool YK, int BM, int BN>
 __global__ __launch_bounds__(256) void mfma_group_kernel(const LItem *__restrict__ items, int n, void *arena,
-                                                         int n_sets, const int32_t *__restrict__ tabs) {
+                                                         void *split, int n_sets, const int32_t *__restrict__ tabs) {
   using T = TileT<BM, BN>;
+  constexpr int eb = elem_bytes(PREC);
   int rank, count;
   const LItem &it = items[group_item(items, n, &rank, &count)];
   const DOp op = it.op;
   const int lt = (op.nFX > T::LM ? op.nFX - T::LM : 0) + (op.nFY > T::LN ? op.nFY - T::LN : 0);  // log2 tiles per set
+  const int ls = it.lgl;  // log2 summed-index ranges
   const int b = xcd_order(rank, count);
-  const int set = b >> lt, tile = b & ((1 << lt) - 1);
+  const int set = b >> (lt + ls), part = (b >> lt) & ((1 << ls) - 1), tile = b & ((1 << lt) - 1);
   if (set >= n_sets) return;
-  any_tile<PREC, XK, YK, BM, BN>((char *)arena + (it.base + (int64_t)set * it.stride) * elem_bytes(PREC), op, it.ru,
-                                 tabs + op.tab, tile);
+  char *base = (char *)arena + (it.base + (int64_t)set * it.stride) * eb;
+  const int kl = op.nS - ls;
+  char *z = ls == 0 ? base + (int64_t)op.z * eb
+                    : (char *)split + (it.zs + ((((int64_t)set << ls) + part) << (op.nFX + op.nFY))) * eb;
+  any_tile<PREC, XK, YK, BM, BN>(base, op, it.ru, tabs + op.tab, tile, part << kl, (part + 1) << kl, z);
+}
+
+// Sum of the partial tiles of split items: Z[i] = sum over ranges r in
+// order of split[zs + ((set 2^lgl + r) M N) + i], in FP64.
+template <typename V>
+__global__ __launch_bounds__(256) void mfma_split_reduce_kernel(const LItem *__restrict__ items, int n, void *arena,
+                                                                const void *split, int n_sets) {
+  int rank, count;
+  const LItem &it = items[group_item(items, n, &rank, &count)];
+  const int ls = it.lgl, lmn = it.op.nFX + it.op.nFY;
+  const int64_t total = (int64_t)n_sets << lmn;
+  const V *sp = reinterpret_cast<const V *>(split) + it.zs;
+  V *ar = reinterpret_cast<V *>(arena);
+  for (int64_t g = (int64_t)rank * 256 + threadIdx.x; g < total; g += (int64_t)count * 256) {
+    const int64_t set = g >> lmn, i = g & ((int64_t(1) << lmn) - 1);
+    const V *src = sp + ((set << ls) << lmn) + i;
+    double re = 0.0, im = 0.0;
+    for (int r = 0; r < (1 << ls); ++r) {
+      const V v = src[(int64_t)r << lmn];
+      re += v.x;
+      im += v.y;
+    }
+    using R = typename Acc4<V>::R;
+    ar[it.base + set * it.stride + it.op.z + i] = make_c((R)re, (R)im);
+  }
 }
 
 // True when the MFMA path takes this op: no batch bits, at least 16 summed
@@ -425,9 +466,10 @@ void launch_one(const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream
 }
 
 template <int PREC, bool XK, bool YK, int BM, int BN>
-void launch_group(const LItem *items, int n, int blocks, void *arena, int n_sets, const int32_t *tabs, hipStream_t st) {
+void launch_group(const LItem *items, int n, int blocks, void *arena, void *split, int n_sets, const int32_t *tabs,
+                  hipStream_t st) {
   hipLaunchKernelGGL((mfma_group_kernel<PREC, XK, YK, BM, BN>), dim3(blocks), dim3(256), 0, st, items, n, arena,
-                     n_sets, tabs);
+                     split, n_sets, tabs);
 }
 
 // Calls F<PREC, XK, YK, BM, BN>::run(args...) for a variant index; false
@@ -465,8 +507,9 @@ struct OneF {
 };
 template <int PREC, bool XK, bool YK, int BM, int BN>
 struct GroupF {
-  static void run(const LItem *items, int n, int blocks, void *arena, int n_sets, const int32_t *tabs, hipStream_t st) {
-    launch_group<PREC, XK, YK, BM, BN>(items, n, blocks, arena, n_sets, tabs, st);
+  static void run(const LItem *items, int n, int blocks, void *arena, void *split, int n_sets, const int32_t *tabs,
+                  hipStream_t st) {
+    launch_group<PREC, XK, YK, BM, BN>(items, n, blocks, arena, split, n_sets, tabs, st);
   }
 };
 
@@ -480,11 +523,26 @@ hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, 
 }
 
 // Grouped launch of n items of one kernel variant (mfma_variant) on
-// `blocks` workgroups (per item: mfma_tiles x the batch's parameter vectors).
-hipError_t mfma_group(int variant, const LItem *items, int n, int blocks, void *arena, int n_sets, const int32_t *tabs,
-                      hipStream_t st) {
+// `blocks` workgroups (per item: mfma_tiles x 2^lgl x the batch's parameter
+// vectors); split: scratch of the items with lgl > 0.
+hipError_t mfma_group(int variant, const LItem *items, int n, int blocks, void *arena, void *split, int n_sets,
+                      const int32_t *tabs, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  if (!dispatch<GroupF>(variant, items, n, blocks, arena, n_sets, tabs, st)) return hipErrorInvalidValue;
+  if (!dispatch<GroupF>(variant, items, n, blocks, arena, split, n_sets, tabs, st)) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// Grouped sum of the partial tiles of split items (one item per split op,
+// at most kGroupItemBlocks workgroups each).
+hipError_t mfma_split_reduce(int dtype, const LItem *items, int n, int blocks, void *arena, const void *split,
+                             int n_sets, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (dtype == TN_C128)
+    hipLaunchKernelGGL(mfma_split_reduce_kernel<double2>, dim3(blocks), dim3(256), 0, st, items, n, arena, split,
+                       n_sets);
+  else
+    hipLaunchKernelGGL(mfma_split_reduce_kernel<float2>, dim3(blocks), dim3(256), 0, st, items, n, arena, split,
+                       n_sets);
   return hipGetLastError();
 }
 

@@ -34,8 +34,10 @@ bool mfma_eligible(int dtype, const DOp &op);
 hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, int prec, hipStream_t st);
 int mfma_tiles(const DOp &op);
 int mfma_variant(const DOp &op, int prec);
-hipError_t mfma_group(int variant, const LItem *items, int n, int blocks, void *arena, int n_sets, const int32_t *tabs,
-                      hipStream_t st);
+hipError_t mfma_group(int variant, const LItem *items, int n, int blocks, void *arena, void *split, int n_sets,
+                      const int32_t *tabs, hipStream_t st);
+hipError_t mfma_split_reduce(int dtype, const LItem *items, int n, int blocks, void *arena, const void *split,
+                             int n_sets, hipStream_t st);
 hipError_t level_setup(int dtype, const LevelArgs &a, const void *consts, int n_const, const DParam *pt, int n_pt,
                        const void *bound, int per_set, int set0, int zero_begin, int zero_n, hipStream_t st);
 hipError_t level_finish(int dtype, const LevelArgs &a, const DParam *pt, int n_pt, const void *dbound, int per_set,
@@ -226,10 +228,11 @@ struct LevelBin {
   };
   // per step: thin items [t0, t0+nt) on tb workgroups, leaf items [l0,
   // l0+nl) on lb workgroups (into the variant's item array), matrix-core
-  // groups [g0, g0+ng) of `mg`, separately launched ops [o0, o0+no) of
-  // `other`
+  // groups [g0, g0+ng) of `mg`, the partial-tile sums of its split
+  // matrix-core items [r0, r0+nr) on rb workgroups, separately launched ops
+  // [o0, o0+no) of `other`
   struct Step {
-    int t0 = 0, nt = 0, tb = 0, l0 = 0, nl = 0, lb = 0, g0 = 0, ng = 0, o0 = 0, no = 0;
+    int t0 = 0, nt = 0, tb = 0, l0 = 0, nl = 0, lb = 0, g0 = 0, ng = 0, r0 = 0, nr = 0, rb = 0, o0 = 0, no = 0;
   };
   std::vector<Step> steps[2];
   std::vector<MGroup> mg[2];
@@ -238,6 +241,15 @@ struct LevelBin {
 
 // Most workgroups one item of a grouped launch takes.
 static constexpr int64_t kGroupItemBlocks = 65536;
+
+// Split summed index of matrix-core items: an item whose tiles over all
+// parameter vectors number fewer than kSplitTarget workgroups (default;
+// QTN_SPLIT_TARGET) is split into
+// up to 64 ranges (at least 512 summed entries each) until it has about
+// kSplitTarget; the partial tiles of one step and stream lane take at most
+// kSplitStepBytes of scratch.
+static constexpr int64_t kSplitTarget = 1024;
+static constexpr int64_t kSplitStepBytes = int64_t(512) << 20;
 
 static int slot_for(HostProgram &hp, const ParamTensor &pt) {
   auto key = std::make_tuple(pt.kind, pt.param, pt.coeff, pt.folded + 2 * pt.diag);
@@ -749,6 +761,10 @@ struct tn_batch {
   std::vector<int> lsolo;              // level networks run one by one, in chunks of parameter vectors
   qtn::LItem *d_litems[2] = {nullptr, nullptr};
   size_t litem_cap[2] = {0, 0};
+  void *d_lsplit = nullptr;                       // partial tiles of split matrix-core items
+  size_t lsplit_cap = 0;                          // its bytes
+  int64_t lsplit_off[2][2] = {{0, 0}, {0, 0}};    // [program variant][lane]: region start (elements)
+  int64_t split_target = 0;                       // workgroups a split item aims at (0: no splits)
   // device
   qtn::DNet *d_nets_fwd = nullptr, *d_nets_grad = nullptr;
   qtn::DOp *d_ops = nullptr;
@@ -815,7 +831,7 @@ static void free_batch_dev(tn_batch *b) {
   }
   void *ptrs[] = {b->d_nets_fwd, b->d_nets_grad, b->d_ops, b->d_recs, b->d_srecs[0], b->d_srecs[1], b->d_tabs, b->d_task_net, b->d_gtask_net, b->d_garena, b->d_consts, b->d_ptens,
                   b->d_slots, b->d_bound, b->d_dbound, b->d_val, b->d_gnet, b->d_coef, b->d_larena, b->d_lscal,
-                  b->d_lpart, b->d_litems[0], b->d_litems[1]};
+                  b->d_lpart, b->d_litems[0], b->d_litems[1], b->d_lsplit};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -833,6 +849,8 @@ static int level_prec(const tn_batch *b, const DOp &op) {
 // uploaded to the device. Runs after every change of those choices, never
 // under capture.
 static int build_level_items(tn_batch *b) {
+  const int eb = b->dtype == TN_C128 ? 16 : 8;
+  int64_t split_need[2][2] = {{0, 0}, {0, 0}};  // [variant][lane]: scratch elements
   for (int v = 0; v < 2; ++v) {
     std::vector<LItem> items;
     for (LevelBin &bn : b->lbins) {
@@ -907,6 +925,8 @@ static int build_level_items(tn_batch *b) {
           return x.first < y.first;
         });
         stp.g0 = (int)bn.mg[v].size();
+        std::vector<LItem> splits;
+        int64_t zoff = 0;  // scratch elements of this step's split items
         for (size_t q = 0; q < mf.size(); ++q) {
           if (q == 0 || mf[q].first != mf[q - 1].first) {
             LevelBin::MGroup g;
@@ -924,11 +944,33 @@ static int build_level_items(tn_batch *b) {
           it.base = bn.abase[j];
           it.stride = ln.stride[v];
           it.blk0 = g.blocks;
-          g.blocks += mfma_tiles(it.op) * b->max_sets;
+          const int64_t wg = (int64_t)mfma_tiles(it.op) * b->max_sets;
+          const int64_t part = ((int64_t)b->max_sets << (it.op.nFX + it.op.nFY));  // elements per range
+          int ls = 0;
+          while (ls < 6 && it.op.nS - ls > 9 && (wg << ls) < b->split_target &&
+                 (zoff + (part << (ls + 1))) * eb <= kSplitStepBytes)
+            ++ls;
+          if (ls > 0) {
+            it.lgl = ls;
+            it.zs = zoff;
+            zoff += part << ls;
+            splits.push_back(it);
+          }
+          g.blocks += (int)(wg << ls);
           ++g.n;
           items.push_back(it);
         }
         stp.ng = (int)bn.mg[v].size() - stp.g0;
+        // sums of the split items' partial tiles
+        stp.r0 = (int)items.size();
+        stp.nr = (int)splits.size();
+        for (LItem &it : splits) {
+          it.blk0 = stp.rb;
+          const int64_t outs = (int64_t)b->max_sets << (it.op.nFX + it.op.nFY);
+          stp.rb += (int)std::max<int64_t>(1, std::min<int64_t>(kGroupItemBlocks, (outs + 255) / 256));
+          items.push_back(it);
+        }
+        split_need[v][bn.lane] = std::max(split_need[v][bn.lane], zoff);
         bn.steps[v].push_back(stp);
       }
     }
@@ -942,6 +984,21 @@ static int build_level_items(tn_batch *b) {
     // earlier launches may still read the old lists
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipMemcpy(b->d_litems[v], items.data(), items.size() * sizeof(LItem), hipMemcpyHostToDevice));
+  }
+  // split scratch: lane 0's region, then lane 1's (the lanes run concurrently)
+  size_t need = 0;
+  for (int v = 0; v < 2; ++v) {
+    b->lsplit_off[v][0] = 0;
+    b->lsplit_off[v][1] = split_need[v][0];
+    need = std::max(need, (size_t)(split_need[v][0] + split_need[v][1]) * eb);
+  }
+  if (need > b->lsplit_cap) {
+    HIPCHK(hipDeviceSynchronize());
+    if (b->d_lsplit) HIPCHK(hipFree(b->d_lsplit));
+    b->d_lsplit = nullptr;
+    b->lsplit_cap = 0;
+    HIPCHK(hipMalloc(&b->d_lsplit, need));
+    b->lsplit_cap = need;
   }
   b->gc.clear();
   return TN_OK;
@@ -1089,6 +1146,8 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
   if (const char *env = std::getenv("QTN_GMEM_MAX_MACS")) gmem_max = std::atoll(env);
   int64_t level_budget = kLevelBudget;  // QTN_LEVEL_BUDGET (bytes): level arena limit
   if (const char *env = std::getenv("QTN_LEVEL_BUDGET")) level_budget = std::max<int64_t>(1, std::atoll(env));
+  b->split_target = kSplitTarget;  // QTN_SPLIT_TARGET=0 keeps every matrix-core sum on one workgroup
+  if (const char *env = std::getenv("QTN_SPLIT_TARGET")) b->split_target = std::max<int64_t>(0, std::atoll(env));
   std::vector<double> cost(n_nets);
   std::vector<int> fused_ids, gmem_ids;
   int maxbits = 0;
@@ -1440,10 +1499,14 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
         e = level_group(b->dtype, false, b->d_litems[v] + stp.t0, stp.nt, stp.tb, b->d_larena, n_sets, b->d_tabs, bs);
       if (e == hipSuccess)
         e = level_group(b->dtype, true, b->d_litems[v] + stp.l0, stp.nl, stp.lb, b->d_larena, n_sets, b->d_tabs, bs);
+      void *split = b->d_lsplit ? (char *)b->d_lsplit + b->lsplit_off[v][bn.lane] * eb : nullptr;
       for (int g = stp.g0; g < stp.g0 + stp.ng && e == hipSuccess; ++g) {
         const LevelBin::MGroup &mg = bn.mg[v][g];
-        e = mfma_group(mg.variant, b->d_litems[v] + mg.i0, mg.n, mg.blocks, b->d_larena, n_sets, b->d_tabs, bs);
+        e = mfma_group(mg.variant, b->d_litems[v] + mg.i0, mg.n, mg.blocks, b->d_larena, split, n_sets, b->d_tabs,
+                       bs);
       }
+      if (e == hipSuccess && stp.nr > 0)
+        e = mfma_split_reduce(b->dtype, b->d_litems[v] + stp.r0, stp.nr, stp.rb, b->d_larena, split, n_sets, bs);
       for (int q = stp.o0; q < stp.o0 + stp.no && e == hipSuccess; ++q) {
         const int j = bn.other[v][q];
         const LevelNet &ln = b->level[bn.lv[j]];
@@ -1806,7 +1869,7 @@ int batch_info(const tn_batch *b, tn_batch_stats *s) {
     for (const LevelBin &bn : b->lbins) {
       n += 2 * (int64_t)bn.lv.size();  // set-up and outputs
       for (const LevelBin::Step &stp : bn.steps[v]) {
-        n += (stp.nt > 0) + (stp.nl > 0) + stp.ng;
+        n += (stp.nt > 0) + (stp.nl > 0) + stp.ng + (stp.nr > 0);
         for (int q = stp.o0; q < stp.o0 + stp.no; ++q) {
           const LevelNet &ln = b->level[bn.lv[bn.other[v][q]]];
           n += b->hp.ops[ln.op_begin[v] + (int)(&stp - bn.steps[v].data())].type == OP_SCALAR ? 2 : 1;
@@ -1820,6 +1883,10 @@ int batch_info(const tn_batch *b, tn_batch_stats *s) {
       n += per * ((b->max_sets + ln.chunk - 1) / ln.chunk);
     }
     (v == 0 ? s->level_launches_fwd : s->level_launches_grad) = (int32_t)std::min<int64_t>(n, INT32_MAX);
+    int32_t ns = 0;
+    for (const LevelBin &bn : b->lbins)
+      for (const LevelBin::Step &stp : bn.steps[v]) ns += stp.nr;
+    (v == 0 ? s->level_split_fwd : s->level_split_grad) = ns;
   }
   s->n_programs = b->hp.n_programs;
   s->fused_block = b->block;

@@ -52,7 +52,7 @@ class tn_batch_stats(ctypes.Structure):
                                                "lds_bytes_grad", "n_programs", "fused_block", "rec_only",
                                                "sets_per_wave_fwd", "sets_per_wave_grad", "n_global",
                                                "n_level_bins", "n_level_chunked", "level_launches_fwd",
-                                               "level_launches_grad")] + \
+                                               "level_launches_grad", "level_split_fwd", "level_split_grad")] + \
                [(n, ctypes.c_double) for n in ("flops_fwd", "bytes_fwd", "flops_grad", "bytes_grad")]
 
 

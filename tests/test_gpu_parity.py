@@ -478,6 +478,72 @@ def test_dense_split_bf16_precision():
     assert errs[qtn.TN_MFMA_BF16X3] < 2e-4
 
 
+def test_dense_whole_circuit_gradient():
+    """Adjoint contraction of whole-circuit (no light cone) networks, whose
+    large steps and their adjoints are matrix-core products: d<ZZ>/d(gamma, beta)
+    of three edges of a 6-regular n=12 graph against the differentiated p=1
+    closed form, complex64 (FP32 products) and complex128 (FP64 products)."""
+    qtn, qaoa = _qtn(), _qaoa()
+    d, n = 6, 12
+    e = workloads.random_regular_graph(d, n, 0)
+    ang = np.array(workloads.qaoa_angles(6, 2, 1))
+    for dt, tol_v, tol_g in ((qtn.TN_C64, 2e-5, 1e-4), (qtn.TN_C128, 1e-12, 1e-11)):
+        nets = []
+        for ed in e[:3]:
+            net = qaoa.edge_network(n, e, 1, ed, dtype=dt, lightcone=False)
+            net.set_order(net.order_linegraph(trials=4, seed=0))
+            nets.append(net)
+        batch = qtn.Batch(nets, max_sets=2)
+        assert batch.info()["n_level"] == 3
+        out = torch.empty((3, 2, 2), dtype=torch.float64, device="cuda")
+        gn = torch.empty((3, 2, 2), dtype=torch.float64, device="cuda")
+        _say(f"dense whole-circuit gradient dtype {dt}")
+        batch.grad(torch.tensor(ang, device="cuda"), out=out, grad_net=gn)
+        torch.cuda.synchronize()
+        got_v, got_g = out.cpu().numpy(), gn.cpu().numpy()
+        for s in range(2):
+            zz = closed_form.zz_p1(n, e, ang[s, 0], ang[s, 1])[:3]
+            dg, db = closed_form.zz_p1_grad(n, e, ang[s, 0], ang[s, 1])
+            assert np.max(np.abs(got_v[:, s, 0] - zz)) < tol_v
+            assert np.max(np.abs(got_g[:, s, 0] - dg[:3])) < tol_g, (dt, s, got_g[:, s], dg[:3], db[:3])
+            assert np.max(np.abs(got_g[:, s, 1] - db[:3])) < tol_g, (dt, s, got_g[:, s], dg[:3], db[:3])
+
+
+def test_split_summed_index(monkeypatch):
+    """Matrix-core products with few output tiles and a long sum split their
+    summed index over workgroups (partial tiles summed in range order): a
+    whole-circuit 6-regular n=16 network, one parameter vector, forward and
+    adjoint with splits (up to 32 ranges) and without, against the p=1 closed
+    form and its derivative."""
+    qtn, qaoa = _qtn(), _qaoa()
+    d, n = 6, 16
+    e = workloads.random_regular_graph(d, n, 0)
+    ang = np.array(workloads.qaoa_angles(7, 1, 1))
+    zz = closed_form.zz_p1(n, e, ang[0, 0], ang[0, 1])[0]
+    dg, db = closed_form.zz_p1_grad(n, e, ang[0, 0], ang[0, 1])
+    res = {}
+    for target in ("0", "1024"):
+        monkeypatch.setenv("QTN_SPLIT_TARGET", target)
+        for dt in (qtn.TN_C64, qtn.TN_C128):
+            net = qaoa.edge_network(n, e, 1, e[0], dtype=dt, lightcone=False)
+            net.set_order(net.order_linegraph(trials=4, seed=0))
+            batch = qtn.Batch([net], max_sets=1)
+            info = batch.info()
+            assert (info["level_split_grad"] > 0) == (target != "0") and info["n_level"] == 1
+            out = torch.empty((1, 1, 2), dtype=torch.float64, device="cuda")
+            gn = torch.empty((1, 1, 2), dtype=torch.float64, device="cuda")
+            _say(f"split target {target} dtype {dt}: splits fwd {info['level_split_fwd']} grad {info['level_split_grad']}")
+            batch.grad(torch.tensor(ang, device="cuda"), out=out, grad_net=gn)
+            torch.cuda.synchronize()
+            res[(target, dt)] = (out[0, 0, 0].item(), gn[0, 0].cpu().numpy())
+    for (target, dt), (v, g) in res.items():
+        tol_v, tol_g = (2e-5, 1e-4) if dt == qtn.TN_C64 else (1e-12, 1e-11)
+        assert abs(v - zz) < tol_v, (target, dt, v, zz)
+        assert np.max(np.abs(g - np.array([dg[0], db[0]]))) < tol_g, (target, dt, g, dg[0], db[0])
+    # complex128: the split changes only the order of FP64 sums
+    assert abs(res[("0", qtn.TN_C128)][0] - res[("1024", qtn.TN_C128)][0]) < 1e-13
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_level_mfma_tile_shapes(prec, monkeypatch):
     """Matrix-core products of every tile shape (64 x 64, and 16 x 64 / 64 x 16
