@@ -479,8 +479,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-next", action="store_true", help="skip the optimisation / answer-string / noise lines")
     ap.add_argument("--no-grid", action="store_true", help="skip the 4-/5-regular batching grid")
-    ap.add_argument("--grid-case", default=None,
-                    help="only the batching-grid rows d,n,p (e.g. 5,50,2); prints them as one JSON line")
+    ap.add_argument("--grid-case", action="append", default=None,
+                    help="only this batching-grid row d,n,p (e.g. 5,50,2; repeatable); prints the rows as one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note "
@@ -496,8 +496,8 @@ def main():
 
     dev = torch.device("cuda:0")
     if args.grid_case:
-        case = tuple(int(x) for x in args.grid_case.split(","))
-        print(json.dumps(batching_grid(torch.cuda.Stream(), dev, cases={case})), flush=True)
+        cases = {tuple(int(x) for x in c.split(",")) for c in args.grid_case}
+        print(json.dumps(batching_grid(torch.cuda.Stream(), dev, cases=cases)), flush=True)
         return
     edges = workloads.random_regular_graph(D, N_VERT, GRAPH_SEED)
     angles = np.array(workloads.qaoa_angles(ANGLE_SEED, N_SETS, P_LAYERS))

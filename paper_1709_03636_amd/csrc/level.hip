@@ -89,7 +89,26 @@ __device__ __forceinline__ V thin_output(const V *base, const DOp &op, const DRu
   V acc;
   acc.x = 0;
   acc.y = 0;
-  for (int k = part; k < (1 << op.nS); k += L) {
+  const int K = 1 << op.nS;
+  if (K >= 4 * L) {
+    // four summed entries per iteration: their table and operand loads are
+    // issued together (a lane's entries number a multiple of four)
+    for (int k = part; k < K; k += 4 * L) {
+      int2 t[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) t[u] = l_tab(tab, op.nS, k + u * L);
+      V x[4], y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        x[u] = X[t[u].x];
+        y[u] = Y[t[u].y];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = l_fma(acc, x[u], y[u]);
+    }
+    return acc;
+  }
+  for (int k = part; k < K; k += L) {
     const int2 t = l_tab(tab, op.nS, k);
     acc = l_fma(acc, X[t.x], Y[t.y]);
   }
@@ -301,7 +320,22 @@ __device__ __forceinline__ void thin_output4(V *base, const DOp &op, const DRuns
     acc[r].x = 0;
     acc[r].y = 0;
   }
-  for (int k = 0; k < (1 << op.nS); ++k) {
+  const int K = 1 << op.nS;
+  int k = 0;
+  // two summed entries per iteration: ten operand loads in flight
+  for (; k + 2 <= K; k += 2) {
+    const int2 t0 = l_tab(tab, op.nS, k), t1 = l_tab(tab, op.nS, k + 1);
+    const V x0 = X[t0.x], x1 = X[t1.x];
+    V y0[4], y1[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      y0[r] = Y[t0.y + dy[r]];
+      y1[r] = Y[t1.y + dy[r]];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = l_fma(l_fma(acc[r], x0, y0[r]), x1, y1[r]);
+  }
+  if (k < K) {
     const int2 t = l_tab(tab, op.nS, k);
     const V x = X[t.x];
 #pragma unroll
