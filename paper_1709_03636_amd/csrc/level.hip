@@ -354,10 +354,11 @@ __device__ __forceinline__ void thin_output4(V *base, const DOp &op, const DRuns
 // stride is a multiple of 256 and the total a multiple of L. lgl < 0: a
 // lane computes four consecutive outputs instead (steps with many outputs).
 template <typename V>
-__global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *__restrict__ items, int n, V *arena,
+__global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *__restrict__ items,
+                                                                   const int32_t *__restrict__ blk, int n, V *arena,
                                                                    int n_sets, const int32_t *__restrict__ tabs) {
   int rank, count;
-  const LItem &it = items[group_item(items, n, &rank, &count)];
+  const LItem &it = items[group_item(blk, n, &rank, &count)];
   const DOp op = it.op;
   const int lgOut = op.nFX + op.nB + op.nFY;
   const int32_t *tab = tabs + op.tab;
@@ -394,10 +395,11 @@ __global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *
 
 // Leaf adjoints of several networks at once (level_leafgrad_kernel per item).
 template <typename V>
-__global__ __launch_bounds__(256) void level_group_leafgrad_kernel(const LItem *__restrict__ items, int n, V *arena,
+__global__ __launch_bounds__(256) void level_group_leafgrad_kernel(const LItem *__restrict__ items,
+                                                                   const int32_t *__restrict__ blk, int n, V *arena,
                                                                    int n_sets, const int32_t *__restrict__ tabs) {
   int rank, count;
-  const LItem &it = items[group_item(items, n, &rank, &count)];
+  const LItem &it = items[group_item(blk, n, &rank, &count)];
   const DOp op = it.op;
   const int m = 1 << op.nFX;
   const int64_t total = (int64_t)m * n_sets;
@@ -465,25 +467,26 @@ hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t 
   return dtype == TN_C128 ? level_op_t<double2>(a, op, tabs, st) : level_op_t<float2>(a, op, tabs, st);
 }
 
-// One grouped launch: n items (device array, blk0 ascending from 0) on
-// `blocks` workgroups; leafgrad selects the kind of every item.
-hipError_t level_group(int dtype, bool leafgrad, const LItem *items, int n, int blocks, void *arena, int n_sets,
-                       const int32_t *tabs, hipStream_t st) {
+// One grouped launch: n items (device array; blk: their first-workgroup
+// indices, ascending from 0) on `blocks` workgroups; leafgrad selects the
+// kind of every item.
+hipError_t level_group(int dtype, bool leafgrad, const LItem *items, const int32_t *blk, int n, int blocks,
+                       void *arena, int n_sets, const int32_t *tabs, hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (dtype == TN_C128) {
     if (leafgrad)
-      hipLaunchKernelGGL(level_group_leafgrad_kernel<double2>, dim3(blocks), dim3(256), 0, st, items, n, (double2 *)arena,
-                         n_sets, tabs);
+      hipLaunchKernelGGL(level_group_leafgrad_kernel<double2>, dim3(blocks), dim3(256), 0, st, items, blk, n,
+                         (double2 *)arena, n_sets, tabs);
     else
-      hipLaunchKernelGGL(level_group_contract_kernel<double2>, dim3(blocks), dim3(256), 0, st, items, n, (double2 *)arena,
-                         n_sets, tabs);
+      hipLaunchKernelGGL(level_group_contract_kernel<double2>, dim3(blocks), dim3(256), 0, st, items, blk, n,
+                         (double2 *)arena, n_sets, tabs);
   } else {
     if (leafgrad)
-      hipLaunchKernelGGL(level_group_leafgrad_kernel<float2>, dim3(blocks), dim3(256), 0, st, items, n, (float2 *)arena,
-                         n_sets, tabs);
+      hipLaunchKernelGGL(level_group_leafgrad_kernel<float2>, dim3(blocks), dim3(256), 0, st, items, blk, n,
+                         (float2 *)arena, n_sets, tabs);
     else
-      hipLaunchKernelGGL(level_group_contract_kernel<float2>, dim3(blocks), dim3(256), 0, st, items, n, (float2 *)arena,
-                         n_sets, tabs);
+      hipLaunchKernelGGL(level_group_contract_kernel<float2>, dim3(blocks), dim3(256), 0, st, items, blk, n,
+                         (float2 *)arena, n_sets, tabs);
   }
   return hipGetLastError();
 }

@@ -108,8 +108,12 @@ __device__ __forceinline__ int2 g_tab(const int32_t *__restrict__ tb, int nS, in
 // a multiple of BK, k < BK) is t(k0) + t(k): the per-thread parts t(k) are
 // fixed, and t(k0) is one workgroup-uniform lookup per stage.
 // XK: X's lowest address bit is summed (stage X with k fastest), else m
-// fastest; YK likewise for Y.
-template <bool XK, bool YK, int BM, int BN, typename V = float2>
+// fastest; YK likewise for Y. BLK (split-BF16 tiles, whose LDS rows are
+// [row][k] with a 20-dword stride): with m (n) fastest, a wave stages a
+// 16 x 4 block (16 consecutive rows, 128 contiguous bytes each, at 4 summed
+// entries) instead of 64 rows at one summed entry, so its LDS writes fall
+// on 64 different banks instead of 16.
+template <bool XK, bool YK, int BM, int BN, typename V = float2, bool BLK = false>
 struct Stager {
   using T = TileT<BM, BN>;
   int xr[T::NX], xk[T::NX], yk[T::NY], yn[T::NY];
@@ -120,13 +124,31 @@ struct Stager {
 #pragma unroll
     for (int i = 0; i < T::NX; ++i) {
       const int e = tid + 256 * i;
-      if (XK) { xk[i] = e & (BK - 1); xr[i] = e >> 4; } else { xr[i] = e & (BM - 1); xk[i] = e >> T::LM; }
+      if (XK) {
+        xk[i] = e & (BK - 1);
+        xr[i] = e >> 4;
+      } else if (BLK) {
+        xr[i] = (e & 15) + 16 * ((e >> 6) & (BM / 16 - 1));
+        xk[i] = ((e >> 4) & 3) + 4 * (e >> (T::LM + 2));
+      } else {
+        xr[i] = e & (BM - 1);
+        xk[i] = e >> T::LM;
+      }
       xrow[i] = g_deposit((uint32_t)(m0 + xr[i]), ru.runsX, op.maskX) + (uint32_t)g_tab(tab, op.nS, xk[i]).x;
     }
 #pragma unroll
     for (int i = 0; i < T::NY; ++i) {
       const int e = tid + 256 * i;
-      if (YK) { yk[i] = e & (BK - 1); yn[i] = e >> 4; } else { yn[i] = e & (BN - 1); yk[i] = e >> T::LN; }
+      if (YK) {
+        yk[i] = e & (BK - 1);
+        yn[i] = e >> 4;
+      } else if (BLK) {
+        yn[i] = (e & 15) + 16 * ((e >> 6) & (BN / 16 - 1));
+        yk[i] = ((e >> 4) & 3) + 4 * (e >> (T::LN + 2));
+      } else {
+        yn[i] = e & (BN - 1);
+        yk[i] = e >> T::LN;
+      }
       ycol[i] = g_deposit((uint32_t)(n0 + yn[i]), ru.runsY, op.maskY) + (uint32_t)g_tab(tab, op.nS, yk[i]).y;
     }
   }
@@ -263,7 +285,7 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
   const int n0 = (tile & ((1 << sy) - 1)) * BN, m0 = (tile >> sy) * BM;
   const float2 *X = base + op.x;
   const float2 *Y = base + op.y;
-  Stager<XK, YK, BM, BN> sg(op, ru, tab, m0, n0);
+  Stager<XK, YK, BM, BN, float2, true> sg(op, ru, tab, m0, n0);
   mf4 cre[T::WM][T::WN], cim[T::WM][T::WN];
 #pragma unroll
   for (int i = 0; i < T::WM; ++i)
@@ -369,9 +391,16 @@ __device__ __forceinline__ int xcd_order(int b, int total) {
 
 }  // namespace
 
+// Waves per SIMD the tile kernels are compiled for: the split-BF16 64 x 64
+// tile holds 132 registers unconstrained (3 waves per SIMD); capped at 128 it
+// runs 4 without spills. The others keep the compiler's choice (FP64 would
+// spill).
+template <int PREC>
+constexpr int kMinWaves = PREC == TN_MFMA_BF16X3 ? 4 : 1;
+
 // One op: grid (tiles, 1, parameter vectors).
 template <int PREC, bool XK, bool YK, int BM, int BN>
-__global__ __launch_bounds__(256) void mfma_cgemm_kernel(LevelArgs a, DOp op, DRuns ru, const int32_t *__restrict__ tab) {
+__global__ __launch_bounds__(256, kMinWaves<PREC>) void mfma_cgemm_kernel(LevelArgs a, DOp op, DRuns ru, const int32_t *__restrict__ tab) {
   const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
   char *base = reinterpret_cast<char *>(a.arena) + (int64_t)blockIdx.z * a.stride * elem_bytes(PREC);
   any_tile<PREC, XK, YK, BM, BN>(base, op, ru, tab, b, 0, 1 << op.nS, base + (int64_t)op.z * elem_bytes(PREC));
@@ -383,12 +412,13 @@ __global__ __launch_bounds__(256) void mfma_cgemm_kernel(LevelArgs a, DOp op, DR
 // once. An item with lgl > 0 writes partial tiles to `split` (from element
 // zs: [parameter vector][range][M x N]).
 template <int PREC, bool XK, bool YK, int BM, int BN>
-__global__ __launch_bounds__(256) void mfma_group_kernel(const LItem *__restrict__ items, int n, void *arena,
+__global__ __launch_bounds__(256, kMinWaves<PREC>) void mfma_group_kernel(const LItem *__restrict__ items,
+                                                         const int32_t *__restrict__ blk, int n, void *arena,
                                                          void *split, int n_sets, const int32_t *__restrict__ tabs) {
   using T = TileT<BM, BN>;
   constexpr int eb = elem_bytes(PREC);
   int rank, count;
-  const LItem &it = items[group_item(items, n, &rank, &count)];
+  const LItem &it = items[group_item(blk, n, &rank, &count)];
   const DOp op = it.op;
   const int lt = (op.nFX > T::LM ? op.nFX - T::LM : 0) + (op.nFY > T::LN ? op.nFY - T::LN : 0);  // log2 tiles per set
   const int ls = it.lgl;  // log2 summed-index ranges
@@ -405,10 +435,11 @@ __global__ __launch_bounds__(256) void mfma_group_kernel(const LItem *__restrict
 // Sum of the partial tiles of split items: Z[i] = sum over ranges r in
 // order of split[zs + ((set 2^lgl + r) M N) + i], in FP64.
 template <typename V>
-__global__ __launch_bounds__(256) void mfma_split_reduce_kernel(const LItem *__restrict__ items, int n, void *arena,
+__global__ __launch_bounds__(256) void mfma_split_reduce_kernel(const LItem *__restrict__ items,
+                                                                const int32_t *__restrict__ blk, int n, void *arena,
                                                                 const void *split, int n_sets) {
   int rank, count;
-  const LItem &it = items[group_item(items, n, &rank, &count)];
+  const LItem &it = items[group_item(blk, n, &rank, &count)];
   const int ls = it.lgl, lmn = it.op.nFX + it.op.nFY;
   const int64_t total = (int64_t)n_sets << lmn;
   const V *sp = reinterpret_cast<const V *>(split) + it.zs;
@@ -466,9 +497,9 @@ void launch_one(const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream
 }
 
 template <int PREC, bool XK, bool YK, int BM, int BN>
-void launch_group(const LItem *items, int n, int blocks, void *arena, void *split, int n_sets, const int32_t *tabs,
-                  hipStream_t st) {
-  hipLaunchKernelGGL((mfma_group_kernel<PREC, XK, YK, BM, BN>), dim3(blocks), dim3(256), 0, st, items, n, arena,
+void launch_group(const LItem *items, const int32_t *blk, int n, int blocks, void *arena, void *split, int n_sets,
+                  const int32_t *tabs, hipStream_t st) {
+  hipLaunchKernelGGL((mfma_group_kernel<PREC, XK, YK, BM, BN>), dim3(blocks), dim3(256), 0, st, items, blk, n, arena,
                      split, n_sets, tabs);
 }
 
@@ -507,9 +538,9 @@ struct OneF {
 };
 template <int PREC, bool XK, bool YK, int BM, int BN>
 struct GroupF {
-  static void run(const LItem *items, int n, int blocks, void *arena, void *split, int n_sets, const int32_t *tabs,
-                  hipStream_t st) {
-    launch_group<PREC, XK, YK, BM, BN>(items, n, blocks, arena, split, n_sets, tabs, st);
+  static void run(const LItem *items, const int32_t *blk, int n, int blocks, void *arena, void *split, int n_sets,
+                  const int32_t *tabs, hipStream_t st) {
+    launch_group<PREC, XK, YK, BM, BN>(items, blk, n, blocks, arena, split, n_sets, tabs, st);
   }
 };
 
@@ -525,23 +556,23 @@ hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, 
 // Grouped launch of n items of one kernel variant (mfma_variant) on
 // `blocks` workgroups (per item: mfma_tiles x 2^lgl x the batch's parameter
 // vectors); split: scratch of the items with lgl > 0.
-hipError_t mfma_group(int variant, const LItem *items, int n, int blocks, void *arena, void *split, int n_sets,
-                      const int32_t *tabs, hipStream_t st) {
+hipError_t mfma_group(int variant, const LItem *items, const int32_t *blk, int n, int blocks, void *arena,
+                      void *split, int n_sets, const int32_t *tabs, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  if (!dispatch<GroupF>(variant, items, n, blocks, arena, split, n_sets, tabs, st)) return hipErrorInvalidValue;
+  if (!dispatch<GroupF>(variant, items, blk, n, blocks, arena, split, n_sets, tabs, st)) return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 // Grouped sum of the partial tiles of split items (one item per split op,
 // at most kGroupItemBlocks workgroups each).
-hipError_t mfma_split_reduce(int dtype, const LItem *items, int n, int blocks, void *arena, const void *split,
-                             int n_sets, hipStream_t st) {
+hipError_t mfma_split_reduce(int dtype, const LItem *items, const int32_t *blk, int n, int blocks, void *arena,
+                             const void *split, int n_sets, hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (dtype == TN_C128)
-    hipLaunchKernelGGL(mfma_split_reduce_kernel<double2>, dim3(blocks), dim3(256), 0, st, items, n, arena, split,
+    hipLaunchKernelGGL(mfma_split_reduce_kernel<double2>, dim3(blocks), dim3(256), 0, st, items, blk, n, arena, split,
                        n_sets);
   else
-    hipLaunchKernelGGL(mfma_split_reduce_kernel<float2>, dim3(blocks), dim3(256), 0, st, items, n, arena, split,
+    hipLaunchKernelGGL(mfma_split_reduce_kernel<float2>, dim3(blocks), dim3(256), 0, st, items, blk, n, arena, split,
                        n_sets);
   return hipGetLastError();
 }

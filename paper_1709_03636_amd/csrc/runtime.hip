@@ -28,16 +28,16 @@ hipError_t launch_combine(const double *val, const double *gnet, const double *c
 hipError_t launch_bind(int dtype, const DParam *slots, int n_slots, const double *params, int n_params, int n_sets,
                        int per_set, void *G, void *dG, hipStream_t st);
 hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tabs, int mfma, hipStream_t st);
-hipError_t level_group(int dtype, bool leafgrad, const LItem *items, int n, int blocks, void *arena, int n_sets,
-                       const int32_t *tabs, hipStream_t st);
+hipError_t level_group(int dtype, bool leafgrad, const LItem *items, const int32_t *blk, int n, int blocks,
+                       void *arena, int n_sets, const int32_t *tabs, hipStream_t st);
 bool mfma_eligible(int dtype, const DOp &op);
 hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, int prec, hipStream_t st);
 int mfma_tiles(const DOp &op);
 int mfma_variant(const DOp &op, int prec);
-hipError_t mfma_group(int variant, const LItem *items, int n, int blocks, void *arena, void *split, int n_sets,
-                      const int32_t *tabs, hipStream_t st);
-hipError_t mfma_split_reduce(int dtype, const LItem *items, int n, int blocks, void *arena, const void *split,
-                             int n_sets, hipStream_t st);
+hipError_t mfma_group(int variant, const LItem *items, const int32_t *blk, int n, int blocks, void *arena,
+                      void *split, int n_sets, const int32_t *tabs, hipStream_t st);
+hipError_t mfma_split_reduce(int dtype, const LItem *items, const int32_t *blk, int n, int blocks, void *arena,
+                             const void *split, int n_sets, hipStream_t st);
 hipError_t level_setup(int dtype, const LevelArgs &a, const void *consts, int n_const, const DParam *pt, int n_pt,
                        const void *bound, int per_set, int set0, int zero_begin, int zero_n, hipStream_t st);
 hipError_t level_finish(int dtype, const LevelArgs &a, const DParam *pt, int n_pt, const void *dbound, int per_set,
@@ -760,6 +760,7 @@ struct tn_batch {
   std::vector<qtn::LevelBin> lbins;    // level networks run with grouped launches
   std::vector<int> lsolo;              // level networks run one by one, in chunks of parameter vectors
   qtn::LItem *d_litems[2] = {nullptr, nullptr};
+  int32_t *d_lblk[2] = {nullptr, nullptr};  // the items' first-workgroup indices (compact copy)
   size_t litem_cap[2] = {0, 0};
   void *d_lsplit = nullptr;                       // partial tiles of split matrix-core items
   size_t lsplit_cap = 0;                          // its bytes
@@ -831,7 +832,7 @@ static void free_batch_dev(tn_batch *b) {
   }
   void *ptrs[] = {b->d_nets_fwd, b->d_nets_grad, b->d_ops, b->d_recs, b->d_srecs[0], b->d_srecs[1], b->d_tabs, b->d_task_net, b->d_gtask_net, b->d_garena, b->d_consts, b->d_ptens,
                   b->d_slots, b->d_bound, b->d_dbound, b->d_val, b->d_gnet, b->d_coef, b->d_larena, b->d_lscal,
-                  b->d_lpart, b->d_litems[0], b->d_litems[1], b->d_lsplit};
+                  b->d_lpart, b->d_litems[0], b->d_litems[1], b->d_lblk[0], b->d_lblk[1], b->d_lsplit};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -976,14 +977,23 @@ static int build_level_items(tn_batch *b) {
     }
     if (items.empty()) continue;
     if (items.size() > b->litem_cap[v]) {
+      // earlier launches may still read the old lists
+      HIPCHK(hipDeviceSynchronize());
       if (b->d_litems[v]) HIPCHK(hipFree(b->d_litems[v]));
+      if (b->d_lblk[v]) HIPCHK(hipFree(b->d_lblk[v]));
       b->d_litems[v] = nullptr;
+      b->d_lblk[v] = nullptr;
+      b->litem_cap[v] = 0;
       HIPCHK(hipMalloc((void **)&b->d_litems[v], items.size() * sizeof(LItem)));
+      HIPCHK(hipMalloc((void **)&b->d_lblk[v], items.size() * sizeof(int32_t)));
       b->litem_cap[v] = items.size();
     }
+    std::vector<int32_t> blk(items.size());
+    for (size_t i = 0; i < items.size(); ++i) blk[i] = items[i].blk0;
     // earlier launches may still read the old lists
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipMemcpy(b->d_litems[v], items.data(), items.size() * sizeof(LItem), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->d_lblk[v], blk.data(), blk.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   }
   // split scratch: lane 0's region, then lane 1's (the lanes run concurrently)
   size_t need = 0;
@@ -1496,17 +1506,20 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     }
     for (const LevelBin::Step &stp : bn.steps[v]) {
       if (e == hipSuccess)
-        e = level_group(b->dtype, false, b->d_litems[v] + stp.t0, stp.nt, stp.tb, b->d_larena, n_sets, b->d_tabs, bs);
+        e = level_group(b->dtype, false, b->d_litems[v] + stp.t0, b->d_lblk[v] + stp.t0, stp.nt, stp.tb, b->d_larena,
+                        n_sets, b->d_tabs, bs);
       if (e == hipSuccess)
-        e = level_group(b->dtype, true, b->d_litems[v] + stp.l0, stp.nl, stp.lb, b->d_larena, n_sets, b->d_tabs, bs);
+        e = level_group(b->dtype, true, b->d_litems[v] + stp.l0, b->d_lblk[v] + stp.l0, stp.nl, stp.lb, b->d_larena,
+                        n_sets, b->d_tabs, bs);
       void *split = b->d_lsplit ? (char *)b->d_lsplit + b->lsplit_off[v][bn.lane] * eb : nullptr;
       for (int g = stp.g0; g < stp.g0 + stp.ng && e == hipSuccess; ++g) {
         const LevelBin::MGroup &mg = bn.mg[v][g];
-        e = mfma_group(mg.variant, b->d_litems[v] + mg.i0, mg.n, mg.blocks, b->d_larena, split, n_sets, b->d_tabs,
-                       bs);
+        e = mfma_group(mg.variant, b->d_litems[v] + mg.i0, b->d_lblk[v] + mg.i0, mg.n, mg.blocks, b->d_larena, split,
+                       n_sets, b->d_tabs, bs);
       }
       if (e == hipSuccess && stp.nr > 0)
-        e = mfma_split_reduce(b->dtype, b->d_litems[v] + stp.r0, stp.nr, stp.rb, b->d_larena, split, n_sets, bs);
+        e = mfma_split_reduce(b->dtype, b->d_litems[v] + stp.r0, b->d_lblk[v] + stp.r0, stp.nr, stp.rb, b->d_larena,
+                              split, n_sets, bs);
       for (int q = stp.o0; q < stp.o0 + stp.no && e == hipSuccess; ++q) {
         const int j = bn.other[v][q];
         const LevelNet &ln = b->level[bn.lv[j]];

@@ -282,6 +282,35 @@ def _mixed_level_budget(qtn, qaoa, n, e, S, monkeypatch):
     return best
 
 
+def test_level_group_many_items(monkeypatch):
+    """Grouped level launches of more than 64 items (the workgroup-to-item
+    lookup scans 64 first-workgroup indices at a time): 150 light-cone
+    networks of a 3-regular n=100 graph, p=1, all on the level executor in
+    one group over two stream lanes (75 items per launch), against the p=1
+    closed form and its derivative on every edge and parameter vector."""
+    qtn, qaoa = _qtn(), _qaoa()
+    monkeypatch.setenv("QTN_FUSED_LDS_MAX", "0")
+    monkeypatch.setenv("QTN_GMEM_MAX_MACS", "0")
+    n, S = 100, 3
+    e = workloads.random_regular_graph(3, n, 0)
+    ang = np.array(workloads.qaoa_angles(9, S, 1))
+    nets = qaoa.edge_networks(n, e, 1, qtn.TN_C64, order="linegraph", trials=2)
+    batch = qtn.Batch(nets, max_sets=S)
+    info = batch.info()
+    assert info["n_level"] == len(e) and info["n_level_bins"] == 2 and info["n_level_chunked"] == 0
+    out = torch.empty((len(e), S, 2), dtype=torch.float64, device="cuda")
+    gn = torch.empty((len(e), S, 2), dtype=torch.float64, device="cuda")
+    _say(f"level group of {len(e)} networks, launches {info['level_launches_grad']}")
+    batch.grad(torch.tensor(ang, device="cuda"), out=out, grad_net=gn)
+    torch.cuda.synchronize()
+    got, g = out.cpu().numpy(), gn.cpu().numpy()
+    for s in range(S):
+        zz = closed_form.zz_p1(n, e, ang[s, 0], ang[s, 1])
+        dg, db = closed_form.zz_p1_grad(n, e, ang[s, 0], ang[s, 1])
+        assert np.max(np.abs(got[:, s, 0] - zz)) < 1e-5
+        assert np.max(np.abs(g[:, s, 0] - dg)) < 1e-4 and np.max(np.abs(g[:, s, 1] - db)) < 1e-4
+
+
 def test_level_executor_matches_fused(monkeypatch):
     """The same batch on the LDS fused executor, on the global-arena fused
     executor and on the level executor: all networks stepped together in one
