@@ -9,6 +9,7 @@ evaluated with one folded light-cone network per edge (measurement Z on u and
 v, trace elsewhere), combined on the GPU in FP64.
 """
 import math
+import os
 
 import numpy as np
 
@@ -144,20 +145,27 @@ def edge_network(n, edges, p, edge, dtype=qtn.TN_C64, lightcone=True, noise=None
 
 
 def edge_networks(n, edges, p, dtype=qtn.TN_C64, order="stochastic", seed=0, trials=8, lightcone=True, noise=None,
-                  diagonal=False):
-    """One network per edge with its contraction order set."""
-    nets = []
-    for e in edges:
+                  diagonal=False, workers=None):
+    """One network per edge with its contraction order set. The networks are
+    built and ordered on `workers` host threads (default: up to 16; the
+    library's host calls release the interpreter lock and share no state);
+    each order depends only on its network and seed."""
+    if order not in ("stochastic", "linegraph"):
+        raise ValueError(order)
+
+    def one(e):
         net = edge_network(n, edges, p, e, dtype, lightcone, noise, diagonal)
-        if order == "stochastic":
-            pi = net.order_stochastic(seed)
-        elif order == "linegraph":
-            pi = net.order_linegraph(trials=trials, seed=seed)
-        else:
-            raise ValueError(order)
+        pi = net.order_stochastic(seed) if order == "stochastic" else net.order_linegraph(trials=trials, seed=seed)
         net.set_order(pi)
-        nets.append(net)
-    return nets
+        return net
+
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    if workers <= 1 or len(edges) < 8:
+        return [one(e) for e in edges]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(one, edges))
 
 
 class MaxCut:

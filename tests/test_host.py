@@ -137,6 +137,24 @@ def test_linegraph_order_quality(qtn, qaoa):
     assert lg["n_steps"] == lg["n_tensors"] - lg["n_components"]
 
 
+def test_linegraph_restarts_and_threads(qtn, qaoa):
+    """More restarts of the line-graph search never give a worse order by its
+    (peak, flops) key, and networks ordered on host threads get the same
+    orders as built one after another."""
+    e = workloads.random_regular_graph(5, 30, 0)
+    key = {}
+    for trials in (4, 32):
+        net = qaoa.edge_network(30, e, 2, e[3])
+        net.set_order(net.order_linegraph(trials=trials, seed=0))
+        pi = net.plan_info()
+        key[trials] = (pi["peak_bits"], pi["flops"])
+    assert key[32] <= key[4]
+    seq = qaoa.edge_networks(30, e[:10], 2, order="linegraph", trials=8, workers=1)
+    par = qaoa.edge_networks(30, e[:10], 2, order="linegraph", trials=8, workers=4)
+    for a, b in zip(seq, par):
+        assert np.array_equal(a.plan_steps(), b.plan_steps())
+
+
 def test_plan_shapes_and_flops(qtn, qaoa):
     """Eq. (1): C has rank x+z and costs m^(x+y+z) multiply-adds (m = 4 per wire = 2 bits)."""
     e = workloads.random_regular_graph(3, 12, 0)
