@@ -345,14 +345,72 @@ __device__ __forceinline__ void thin_output4(V *base, const DOp &op, const DRuns
   for (int r = 0; r < 4; ++r) base[op.z + c0 + r] = acc[r];
 }
 
-// Thin contractions of several networks at once: each item is one op of one
-// network, with the addressing of level_contract_kernel inside the
-// network's own arena region. An output is summed by L = 2^lgl adjacent
-// lanes (summed entries k = part, part + L, ...; then a butterfly over the
+// Four outputs c0 + 64 r (r < 4) of one parameter vector, c0 mod 256 < 64:
+// bits 6-7 of the output index pick the four, and they are Y-only bits
+// (ALONG_X false: at least 8 Y-only bits) or X-only bits (ALONG_X true: no
+// Y-only or batch bits), so the four share the other operand's entry and
+// their own entries sit at fixed offsets deposit(64 r). Consecutive lanes
+// take consecutive c0: every load and store instruction is coalesced.
+template <typename V, bool ALONG_X>
+__device__ __forceinline__ void thin_output4s(V *base, const DOp &op, const DRuns &ru, const int32_t *__restrict__ tab,
+                                             const int32_t *__restrict__ tabB, uint32_t c0) {
+  uint32_t bx = 0, by = 0, fx, fy;
+  if (ALONG_X) {
+    fx = c0;
+    fy = 0;
+  } else {
+    const uint32_t rest = c0 >> op.nFY;
+    if (op.nB) {
+      const uint32_t b = rest & ((1u << op.nB) - 1u);
+      bx = tabB[2 * b];
+      by = tabB[2 * b + 1];
+    }
+    fx = rest >> op.nB;
+    fy = c0 & ((1u << op.nFY) - 1u);
+  }
+  const V *X = base + op.x + l_deposit(fx, ru.runsX, op.maskX) + bx;
+  const V *Y = base + op.y + l_deposit(fy, ru.runsY, op.maskY) + by;
+  uint32_t d[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    d[r] = ALONG_X ? l_deposit(64u * r, ru.runsX, op.maskX) : l_deposit(64u * r, ru.runsY, op.maskY);
+  V acc[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    acc[r].x = 0;
+    acc[r].y = 0;
+  }
+  for (int k = 0; k < (1 << op.nS); ++k) {
+    const int2 t = l_tab(tab, op.nS, k);
+    V v[4];
+    if (ALONG_X) {
+      const V y = Y[t.y];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = X[t.x + d[r]];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = l_fma(acc[r], v[r], y);
+    } else {
+      const V x = X[t.x];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = Y[t.y + d[r]];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = l_fma(acc[r], x, v[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) base[op.z + c0 + 64u * r] = acc[r];
+}
+
+// Thin contractions and leaf adjoints of several networks at once: each item
+// is one op of one network, with the addressing of level_contract_kernel
+// (level_leafgrad_kernel) inside the network's own arena region. A thin
+// contraction's output is summed by L = 2^lgl adjacent lanes (summed entries k = part, part + L, ...; then a butterfly over the
 // L lanes), so that steps with few outputs and long sums still fill the
 // chip. All L lanes of an output are in the same loop iteration: the
-// stride is a multiple of 256 and the total a multiple of L. lgl < 0: a
-// lane computes four consecutive outputs instead (steps with many outputs).
+// stride is a multiple of 256 and the total a multiple of L. Steps with many
+// outputs give a lane four of them instead: lgl = -1 four consecutive ones
+// (at least 2 Y-only bits), -2 / -3 four 64 apart along Y / X
+// (thin_output4s).
 template <typename V>
 __global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *__restrict__ items,
                                                                    const int32_t *__restrict__ blk, int n, V *arena,
@@ -364,6 +422,35 @@ __global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *
   const int32_t *tab = tabs + op.tab;
   const int32_t *tabB = tabs + op.tabB;
   V *reg = arena + it.base;
+  if (op.type == OP_LEAFGRAD) {  // leaf adjoint (level_leafgrad_kernel per item)
+    const int m = 1 << op.nFX;
+    const int64_t tot = (int64_t)m * n_sets;
+    for (int64_t g = rank * (int64_t)256 + threadIdx.x; g < tot; g += (int64_t)count * 256) {
+      const int64_t set = g >> op.nFX;
+      const int i = (int)(g & (m - 1));
+      V *base = reg + set * it.stride;
+      V v = base[op.y + tab[i]];
+      const V x = base[op.x + i];
+      v.x += x.x;
+      v.y += x.y;
+      base[op.y + tab[i]] = v;
+    }
+    return;
+  }
+  if (it.lgl <= -2) {  // four outputs 64 apart per lane (lgOut >= 8)
+    const int64_t nq = (int64_t)1 << (lgOut - 2);
+    const int64_t total4 = nq * n_sets;
+    for (int64_t g = rank * (int64_t)256 + threadIdx.x; g < total4; g += (int64_t)count * 256) {
+      const int64_t set = g >> (lgOut - 2);
+      const uint32_t q = (uint32_t)(g & (nq - 1));
+      const uint32_t c0 = ((q >> 6) << 8) | (q & 63u);
+      if (it.lgl == -3)
+        thin_output4s<V, true>(reg + set * it.stride, op, it.ru, tab, tabB, c0);
+      else
+        thin_output4s<V, false>(reg + set * it.stride, op, it.ru, tab, tabB, c0);
+    }
+    return;
+  }
   if (it.lgl < 0) {  // four outputs per lane (nFY >= 2, so lgOut >= 2)
     const int64_t nq = (int64_t)1 << (lgOut - 2);
     const int64_t total4 = nq * n_sets;
@@ -390,30 +477,6 @@ __global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *
       acc.y += l_xor(acc.y, m);
     }
     if (part == 0) base[op.z + c] = acc;
-  }
-}
-
-// Leaf adjoints of several networks at once (level_leafgrad_kernel per item).
-template <typename V>
-__global__ __launch_bounds__(256) void level_group_leafgrad_kernel(const LItem *__restrict__ items,
-                                                                   const int32_t *__restrict__ blk, int n, V *arena,
-                                                                   int n_sets, const int32_t *__restrict__ tabs) {
-  int rank, count;
-  const LItem &it = items[group_item(blk, n, &rank, &count)];
-  const DOp op = it.op;
-  const int m = 1 << op.nFX;
-  const int64_t total = (int64_t)m * n_sets;
-  const int32_t *tab = tabs + op.tab;
-  V *reg = arena + it.base;
-  for (int64_t g = rank * (int64_t)256 + threadIdx.x; g < total; g += (int64_t)count * 256) {
-    const int64_t set = g / m;
-    const int i = (int)(g - set * m);
-    V *base = reg + set * it.stride;
-    V v = base[op.y + tab[i]];
-    const V x = base[op.x + i];
-    v.x += x.x;
-    v.y += x.y;
-    base[op.y + tab[i]] = v;
   }
 }
 
@@ -467,27 +530,18 @@ hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t 
   return dtype == TN_C128 ? level_op_t<double2>(a, op, tabs, st) : level_op_t<float2>(a, op, tabs, st);
 }
 
-// One grouped launch: n items (device array; blk: their first-workgroup
-// indices, ascending from 0) on `blocks` workgroups; leafgrad selects the
-// kind of every item.
-hipError_t level_group(int dtype, bool leafgrad, const LItem *items, const int32_t *blk, int n, int blocks,
-                       void *arena, int n_sets, const int32_t *tabs, hipStream_t st) {
+// One grouped launch of thin contractions and leaf adjoints: n items
+// (device array; blk: their first-workgroup indices, ascending from 0) on
+// `blocks` workgroups.
+hipError_t level_group(int dtype, const LItem *items, const int32_t *blk, int n, int blocks, void *arena, int n_sets,
+                       const int32_t *tabs, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  if (dtype == TN_C128) {
-    if (leafgrad)
-      hipLaunchKernelGGL(level_group_leafgrad_kernel<double2>, dim3(blocks), dim3(256), 0, st, items, blk, n,
-                         (double2 *)arena, n_sets, tabs);
-    else
-      hipLaunchKernelGGL(level_group_contract_kernel<double2>, dim3(blocks), dim3(256), 0, st, items, blk, n,
-                         (double2 *)arena, n_sets, tabs);
-  } else {
-    if (leafgrad)
-      hipLaunchKernelGGL(level_group_leafgrad_kernel<float2>, dim3(blocks), dim3(256), 0, st, items, blk, n,
-                         (float2 *)arena, n_sets, tabs);
-    else
-      hipLaunchKernelGGL(level_group_contract_kernel<float2>, dim3(blocks), dim3(256), 0, st, items, blk, n,
-                         (float2 *)arena, n_sets, tabs);
-  }
+  if (dtype == TN_C128)
+    hipLaunchKernelGGL(level_group_contract_kernel<double2>, dim3(blocks), dim3(256), 0, st, items, blk, n,
+                       (double2 *)arena, n_sets, tabs);
+  else
+    hipLaunchKernelGGL(level_group_contract_kernel<float2>, dim3(blocks), dim3(256), 0, st, items, blk, n,
+                       (float2 *)arena, n_sets, tabs);
   return hipGetLastError();
 }
 

@@ -28,8 +28,8 @@ hipError_t launch_combine(const double *val, const double *gnet, const double *c
 hipError_t launch_bind(int dtype, const DParam *slots, int n_slots, const double *params, int n_params, int n_sets,
                        int per_set, void *G, void *dG, hipStream_t st);
 hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tabs, int mfma, hipStream_t st);
-hipError_t level_group(int dtype, bool leafgrad, const LItem *items, const int32_t *blk, int n, int blocks,
-                       void *arena, int n_sets, const int32_t *tabs, hipStream_t st);
+hipError_t level_group(int dtype, const LItem *items, const int32_t *blk, int n, int blocks, void *arena, int n_sets,
+                       const int32_t *tabs, hipStream_t st);
 bool mfma_eligible(int dtype, const DOp &op);
 hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, int prec, hipStream_t st);
 int mfma_tiles(const DOp &op);
@@ -226,13 +226,13 @@ struct LevelBin {
   struct MGroup {
     int variant = 0, i0 = 0, n = 0, blocks = 0;
   };
-  // per step: thin items [t0, t0+nt) on tb workgroups, leaf items [l0,
-  // l0+nl) on lb workgroups (into the variant's item array), matrix-core
-  // groups [g0, g0+ng) of `mg`, the partial-tile sums of its split
-  // matrix-core items [r0, r0+nr) on rb workgroups, separately launched ops
-  // [o0, o0+no) of `other`
+  // per step: thin-contraction and leaf-adjoint items [t0, t0+nt) on tb
+  // workgroups (into the variant's item array), matrix-core groups [g0,
+  // g0+ng) of `mg`, the partial-tile sums of its split matrix-core items
+  // [r0, r0+nr) on rb workgroups, separately launched ops [o0, o0+no) of
+  // `other`
   struct Step {
-    int t0 = 0, nt = 0, tb = 0, l0 = 0, nl = 0, lb = 0, g0 = 0, ng = 0, r0 = 0, nr = 0, rb = 0, o0 = 0, no = 0;
+    int t0 = 0, nt = 0, tb = 0, g0 = 0, ng = 0, r0 = 0, nr = 0, rb = 0, o0 = 0, no = 0;
   };
   std::vector<Step> steps[2];
   std::vector<MGroup> mg[2];
@@ -862,7 +862,8 @@ static int build_level_items(tn_batch *b) {
       for (int l : bn.lv) n_steps = std::max(n_steps, b->level[l].n_ops[v]);
       for (int k = 0; k < n_steps; ++k) {
         LevelBin::Step stp;
-        for (int kind = 0; kind < 2; ++kind) {
+        {
+          // thin contractions and leaf adjoints: one launch
           const int first = (int)items.size();
           int blocks = 0;
           for (size_t j = 0; j < bn.lv.size(); ++j) {
@@ -870,11 +871,12 @@ static int build_level_items(tn_batch *b) {
             if (k >= ln.n_ops[v]) continue;
             const DOp &op = b->hp.ops[ln.op_begin[v] + k];
             const bool thin = op.type == OP_CONTRACT && level_prec(b, op) == 0;
-            if (kind == 0 ? !thin : op.type != OP_LEAFGRAD) continue;
-            const int lg = kind == 0 ? op.nFX + op.nB + op.nFY : op.nFX;
+            const bool leaf = op.type == OP_LEAFGRAD;
+            if (!(thin || leaf)) continue;
+            const int lg = thin ? op.nFX + op.nB + op.nFY : op.nFX;
             int64_t work = ((int64_t)1 << lg) * b->max_sets;
             LItem it{};
-            if (kind == 0) {
+            if (thin) {
               // lanes per output: at least 8 summed entries each, up to 64,
               // while the step has fewer than 2^20 (output, lane) pairs
               int lgs = 0;
@@ -882,8 +884,9 @@ static int build_level_items(tn_batch *b) {
               it.lgl = std::max(0, std::min({6, op.nS - 3, 20 - lg - lgs}));
               work <<= it.lgl;
               // many outputs: four per lane instead (shared X reads)
-              if (it.lgl == 0 && op.nFY >= 2 && lg + lgs >= 16) {
-                it.lgl = -1;
+              if (it.lgl == 0 && lg + lgs >= 16 && (op.nFY >= 2 || (op.nFY == 0 && op.nB == 0 && op.nFX >= 8))) {
+                // 64 apart along Y (>= 8 Y-only bits) or X (X-only output bits), else consecutive
+                it.lgl = op.nFY >= 8 ? -2 : op.nFY == 0 ? -3 : -1;
                 work >>= 2;
               }
             }
@@ -896,15 +899,9 @@ static int build_level_items(tn_batch *b) {
             blocks += (int)std::max<int64_t>(1, std::min<int64_t>(kGroupItemBlocks, (work + 255) / 256));
             items.push_back(it);
           }
-          if (kind == 0) {
-            stp.t0 = first;
-            stp.nt = (int)items.size() - first;
-            stp.tb = blocks;
-          } else {
-            stp.l0 = first;
-            stp.nl = (int)items.size() - first;
-            stp.lb = blocks;
-          }
+          stp.t0 = first;
+          stp.nt = (int)items.size() - first;
+          stp.tb = blocks;
         }
         // matrix-core products, grouped by kernel variant
         std::vector<std::pair<int, int>> mf;  // (variant, member)
@@ -1506,11 +1503,8 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     }
     for (const LevelBin::Step &stp : bn.steps[v]) {
       if (e == hipSuccess)
-        e = level_group(b->dtype, false, b->d_litems[v] + stp.t0, b->d_lblk[v] + stp.t0, stp.nt, stp.tb, b->d_larena,
-                        n_sets, b->d_tabs, bs);
-      if (e == hipSuccess)
-        e = level_group(b->dtype, true, b->d_litems[v] + stp.l0, b->d_lblk[v] + stp.l0, stp.nl, stp.lb, b->d_larena,
-                        n_sets, b->d_tabs, bs);
+        e = level_group(b->dtype, b->d_litems[v] + stp.t0, b->d_lblk[v] + stp.t0, stp.nt, stp.tb, b->d_larena, n_sets,
+                        b->d_tabs, bs);
       void *split = b->d_lsplit ? (char *)b->d_lsplit + b->lsplit_off[v][bn.lane] * eb : nullptr;
       for (int g = stp.g0; g < stp.g0 + stp.ng && e == hipSuccess; ++g) {
         const LevelBin::MGroup &mg = bn.mg[v][g];
@@ -1882,7 +1876,7 @@ int batch_info(const tn_batch *b, tn_batch_stats *s) {
     for (const LevelBin &bn : b->lbins) {
       n += 2 * (int64_t)bn.lv.size();  // set-up and outputs
       for (const LevelBin::Step &stp : bn.steps[v]) {
-        n += (stp.nt > 0) + (stp.nl > 0) + stp.ng + (stp.nr > 0);
+        n += (stp.nt > 0) + stp.ng + (stp.nr > 0);
         for (int q = stp.o0; q < stp.o0 + stp.no; ++q) {
           const LevelNet &ln = b->level[bn.lv[bn.other[v][q]]];
           n += b->hp.ops[ln.op_begin[v] + (int)(&stp - bn.steps[v].data())].type == OP_SCALAR ? 2 : 1;
