@@ -129,18 +129,15 @@ constexpr int kSetContract = 1, kSetScalar = 2, kSetSeed = 3, kSetLeafGrad = 4;
 // start, `stride` elements per parameter vector).
 // Workgroups [blk0, next item's blk0) of a grouped launch serve the item;
 // mv: the matrix-core kernel variant of a product on the matrix cores, -1
-// for the other ops (thin contraction, leaf adjoint, rank-0 step, seed). A
-// thin contraction sums each output on 2^lgl lanes (lgl < 0: a lane
-// computes four outputs); a matrix-core product splits its summed index
-// into 2^lgl ranges, whose partial results go to a scratch buffer from
-// element zs; a rank-0 step writes G partial sums per parameter vector
-// there. sc / ncomp: the network's component-scalar region (doubles) and
-// its number of components (rank-0 steps and seeds).
+// for a thin contraction or a leaf adjoint. A thin contraction sums each
+// output on 2^lgl lanes (lgl < 0: a lane computes four outputs); a
+// matrix-core product splits its summed index into 2^lgl ranges, whose
+// partial results go to a scratch buffer from element zs.
 struct LItem {
   DOp op;
   DRuns ru;
-  int64_t base, stride, zs, sc;
-  int32_t blk0, lgl, mv, ncomp, G, pad;
+  int64_t base, stride, zs;
+  int32_t blk0, lgl, mv, pad;
 };
 
 // Arguments of the fused executor kernel.

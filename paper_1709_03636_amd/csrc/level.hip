@@ -199,11 +199,10 @@ __global__ __launch_bounds__(256) void level_finish_kernel(LevelArgs a, const DP
 template <typename V>
 __global__ __launch_bounds__(256) void level_group_contract_kernel(const LItem *__restrict__ items,
                                                                    const int32_t *__restrict__ blk, int n, V *arena,
-                                                                   int n_sets, const int32_t *__restrict__ tabs,
-                                                                   double *scal, void *split) {
+                                                                   int n_sets, const int32_t *__restrict__ tabs) {
   int rank, count;
   const LItem &it = items[group_item(blk, n, &rank, &count)];
-  thin_item<V>(it, rank, count, arena, n_sets, tabs, scal, split);
+  thin_item<V>(it, rank, count, arena, n_sets, tabs);
 }
 
 // --- host launchers ------------------------------------------------------------------------
@@ -260,14 +259,14 @@ hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t 
 // (device array; blk: their first-workgroup indices, ascending from 0) on
 // `blocks` workgroups.
 hipError_t level_group(int dtype, const LItem *items, const int32_t *blk, int n, int blocks, void *arena, int n_sets,
-                       const int32_t *tabs, double *scal, void *split, hipStream_t st) {
+                       const int32_t *tabs, hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (dtype == TN_C128)
     hipLaunchKernelGGL(level_group_contract_kernel<double2>, dim3(blocks), dim3(256), 0, st, items, blk, n,
-                       (double2 *)arena, n_sets, tabs, scal, split);
+                       (double2 *)arena, n_sets, tabs);
   else
     hipLaunchKernelGGL(level_group_contract_kernel<float2>, dim3(blocks), dim3(256), 0, st, items, blk, n,
-                       (float2 *)arena, n_sets, tabs, scal, split);
+                       (float2 *)arena, n_sets, tabs);
   return hipGetLastError();
 }
 

@@ -483,14 +483,13 @@ template <int PREC>
 __global__ __launch_bounds__(256, kMinWaves<PREC>) void step_group_kernel(const LItem *__restrict__ items,
                                                                          const int32_t *__restrict__ blk, int n,
                                                                          void *arena, void *split, int n_sets,
-                                                                         const int32_t *__restrict__ tabs,
-                                                                         double *scal) {
+                                                                         const int32_t *__restrict__ tabs) {
   __shared__ __align__(16) char lds[step_lds<PREC>()];
   int rank, count;
   const LItem &it = items[group_item(blk, n, &rank, &count)];
   using V = typename std::conditional<PREC == TN_MFMA_FP64, double2, float2>::type;
   if (it.mv < 0) {
-    thin_item<V>(it, rank, count, (V *)arena, n_sets, tabs, scal, split);
+    thin_item<V>(it, rank, count, (V *)arena, n_sets, tabs);
     return;
   }
 #define QTN_ITEM(XK, YK, BM, BN)                                                                   \
@@ -515,27 +514,13 @@ __global__ __launch_bounds__(256, kMinWaves<PREC>) void step_group_kernel(const 
 }
 
 // Sum of the partial tiles of split items: Z[i] = sum over ranges r in
-// order of split[zs + ((set 2^lgl + r) M N) + i], in FP64; for a rank-0
-// step, its scalar = the sum of its G partial sums in index order.
+// order of split[zs + ((set 2^lgl + r) M N) + i], in FP64.
 template <typename V>
 __global__ __launch_bounds__(256) void mfma_split_reduce_kernel(const LItem *__restrict__ items,
                                                                 const int32_t *__restrict__ blk, int n, void *arena,
-                                                                const void *split, int n_sets, double *scal) {
+                                                                const void *split, int n_sets) {
   int rank, count;
   const LItem &it = items[group_item(blk, n, &rank, &count)];
-  if (it.op.type == OP_SCALAR) {
-    const double *part = reinterpret_cast<const double *>(reinterpret_cast<const V *>(split) + it.zs);
-    for (int set = rank * 256 + threadIdx.x; set < n_sets; set += count * 256) {
-      double re = 0.0, im = 0.0;
-      for (int g = 0; g < it.G; ++g) {
-        re += part[((size_t)set * it.G + g) * 2];
-        im += part[((size_t)set * it.G + g) * 2 + 1];
-      }
-      scal[it.sc + ((size_t)set * it.ncomp + it.op.z) * 2] = re;
-      scal[it.sc + ((size_t)set * it.ncomp + it.op.z) * 2 + 1] = im;
-    }
-    return;
-  }
   const int ls = it.lgl, lmn = it.op.nFX + it.op.nFY;
   const int64_t total = (int64_t)n_sets << lmn;
   const V *sp = reinterpret_cast<const V *>(split) + it.zs;
@@ -638,20 +623,20 @@ hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, 
 // batch's matrix-core precision) on `blocks` workgroups; split: scratch of
 // the matrix-core items with lgl > 0.
 hipError_t step_group(int prec, const LItem *items, const int32_t *blk, int n, int blocks, void *arena, void *split,
-                      int n_sets, const int32_t *tabs, double *scal, hipStream_t st) {
+                      int n_sets, const int32_t *tabs, hipStream_t st) {
   if (n == 0) return hipSuccess;
   switch (prec) {
     case TN_MFMA_FP32:
       hipLaunchKernelGGL(step_group_kernel<TN_MFMA_FP32>, dim3(blocks), dim3(256), 0, st, items, blk, n, arena, split,
-                         n_sets, tabs, scal);
+                         n_sets, tabs);
       break;
     case TN_MFMA_BF16X3:
       hipLaunchKernelGGL(step_group_kernel<TN_MFMA_BF16X3>, dim3(blocks), dim3(256), 0, st, items, blk, n, arena,
-                         split, n_sets, tabs, scal);
+                         split, n_sets, tabs);
       break;
     case TN_MFMA_FP64:
       hipLaunchKernelGGL(step_group_kernel<TN_MFMA_FP64>, dim3(blocks), dim3(256), 0, st, items, blk, n, arena, split,
-                         n_sets, tabs, scal);
+                         n_sets, tabs);
       break;
     default:
       return hipErrorInvalidValue;
@@ -659,18 +644,17 @@ hipError_t step_group(int prec, const LItem *items, const int32_t *blk, int n, i
   return hipGetLastError();
 }
 
-// Grouped sums after a step: partial tiles of split items and partial sums
-// of rank-0 steps (one item per op, at most kGroupItemBlocks workgroups
-// each).
+// Grouped sum of the partial tiles of split items (one item per split op,
+// at most kGroupItemBlocks workgroups each).
 hipError_t mfma_split_reduce(int dtype, const LItem *items, const int32_t *blk, int n, int blocks, void *arena,
-                             const void *split, int n_sets, double *scal, hipStream_t st) {
+                             const void *split, int n_sets, hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (dtype == TN_C128)
     hipLaunchKernelGGL(mfma_split_reduce_kernel<double2>, dim3(blocks), dim3(256), 0, st, items, blk, n, arena, split,
-                       n_sets, scal);
+                       n_sets);
   else
     hipLaunchKernelGGL(mfma_split_reduce_kernel<float2>, dim3(blocks), dim3(256), 0, st, items, blk, n, arena, split,
-                       n_sets, scal);
+                       n_sets);
   return hipGetLastError();
 }
 

@@ -29,15 +29,15 @@ hipError_t launch_bind(int dtype, const DParam *slots, int n_slots, const double
                        int per_set, void *G, void *dG, hipStream_t st);
 hipError_t level_op(int dtype, const LevelArgs &a, const DOp &op, const int32_t *tabs, int mfma, hipStream_t st);
 hipError_t level_group(int dtype, const LItem *items, const int32_t *blk, int n, int blocks, void *arena, int n_sets,
-                       const int32_t *tabs, double *scal, void *split, hipStream_t st);
+                       const int32_t *tabs, hipStream_t st);
 bool mfma_eligible(int dtype, const DOp &op);
 hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, int prec, hipStream_t st);
 int mfma_tiles(const DOp &op);
 int mfma_variant(const DOp &op, int prec);
 hipError_t step_group(int prec, const LItem *items, const int32_t *blk, int n, int blocks, void *arena, void *split,
-                      int n_sets, const int32_t *tabs, double *scal, hipStream_t st);
+                      int n_sets, const int32_t *tabs, hipStream_t st);
 hipError_t mfma_split_reduce(int dtype, const LItem *items, const int32_t *blk, int n, int blocks, void *arena,
-                             const void *split, int n_sets, double *scal, hipStream_t st);
+                             const void *split, int n_sets, hipStream_t st);
 hipError_t level_setup(int dtype, const LevelArgs &a, const void *consts, int n_const, const DParam *pt, int n_pt,
                        const void *bound, int per_set, int set0, int zero_begin, int zero_n, hipStream_t st);
 hipError_t level_finish(int dtype, const LevelArgs &a, const DParam *pt, int n_pt, const void *dbound, int per_set,
@@ -222,16 +222,17 @@ struct LevelBin {
   std::vector<int> lv;         // indices into tn_batch::level
   std::vector<int64_t> abase;  // arena region start (elements)
   std::vector<int64_t> sbase;  // component-scalar region start (doubles)
-  // per step: the items of every op of the step [t0, t0+nt) on tb
-  // workgroups (into the variant's item array; mfma: some are matrix-core
-  // products, so the launch takes the per-step kernel), then the sums of
-  // partial results [r0, r0+nr) on rb workgroups: the first nsplit of split
-  // matrix-core products, the others of rank-0 steps
+  // per step: thin-contraction, leaf-adjoint and matrix-core items [t0,
+  // t0+nt) on tb workgroups (into the variant's item array; mfma: some are
+  // matrix-core products, so the launch takes the per-step kernel), the
+  // partial-tile sums of its split matrix-core items [r0, r0+nr) on rb
+  // workgroups, separately launched ops [o0, o0+no) of `other`
   struct Step {
-    int t0 = 0, nt = 0, tb = 0, r0 = 0, nr = 0, rb = 0, nsplit = 0;
+    int t0 = 0, nt = 0, tb = 0, r0 = 0, nr = 0, rb = 0, o0 = 0, no = 0;
     bool mfma = false;
   };
   std::vector<Step> steps[2];
+  std::vector<int> other[2];  // members whose op of the step runs on its own
 };
 
 // Most workgroups one item of a grouped launch takes.
@@ -851,6 +852,7 @@ static int build_level_items(tn_batch *b) {
     std::vector<LItem> items;
     for (LevelBin &bn : b->lbins) {
       bn.steps[v].clear();
+      bn.other[v].clear();
       int n_steps = 0;
       for (int l : bn.lv) n_steps = std::max(n_steps, b->level[l].n_ops[v]);
       for (int k = 0; k < n_steps; ++k) {
@@ -859,41 +861,17 @@ static int build_level_items(tn_batch *b) {
         // step: one launch (thin items first, then products by kernel variant)
         const int first = (int)items.size();
         int blocks = 0;
-        int64_t zoff = 0;            // scratch elements of this step (split products, rank-0 partial sums)
-        std::vector<LItem> finals;   // rank-0 steps: partial sums added by the launch after the step
         {
           for (size_t j = 0; j < bn.lv.size(); ++j) {
             const LevelNet &ln = b->level[bn.lv[j]];
             if (k >= ln.n_ops[v]) continue;
             const DOp &op = b->hp.ops[ln.op_begin[v] + k];
             const bool thin = op.type == OP_CONTRACT && level_prec(b, op) == 0;
-            if (op.type == OP_CONTRACT && !thin) continue;  // matrix-core product, below
-            LItem it{};
-            it.mv = -1;
-            it.op = op;
-            it.base = bn.abase[j];
-            it.stride = ln.stride[v];
-            it.sc = bn.sbase[j];
-            it.ncomp = ln.n_comp;
-            it.blk0 = blocks;
-            if (op.type == OP_SCALAR || op.type == OP_SEED) {
-              int64_t wg = (b->max_sets + 255) / 256;
-              if (op.type == OP_SCALAR) {
-                // about four summed entries per thread, at most kScalarParts
-                // workgroups per parameter vector; 16-byte partial sums
-                const int64_t K = (int64_t)1 << op.nS;
-                it.G = (int)std::min<int64_t>(kScalarParts, std::max<int64_t>(1, K / 1024));
-                wg = (int64_t)it.G * b->max_sets;
-                it.zs = zoff;
-                zoff += ((int64_t)it.G * b->max_sets * 16 + eb - 1) / eb;
-                finals.push_back(it);
-              }
-              blocks += (int)wg;
-              items.push_back(it);
-              continue;
-            }
+            const bool leaf = op.type == OP_LEAFGRAD;
+            if (!(thin || leaf)) continue;
             const int lg = thin ? op.nFX + op.nB + op.nFY : op.nFX;
             int64_t work = ((int64_t)1 << lg) * b->max_sets;
+            LItem it{};
             if (thin) {
               // lanes per output: at least 8 summed entries each, up to 64,
               // while the step has fewer than 2^20 (output, lane) pairs
@@ -908,25 +886,37 @@ static int build_level_items(tn_batch *b) {
                 work >>= 2;
               }
             }
+            it.mv = -1;
+            it.op = op;
             pack_runs(op.maskX, it.ru.runsX);
             pack_runs(op.maskY, it.ru.runsY);
+            it.base = bn.abase[j];
+            it.stride = ln.stride[v];
+            it.blk0 = blocks;
             blocks += (int)std::max<int64_t>(1, std::min<int64_t>(kGroupItemBlocks, (work + 255) / 256));
             items.push_back(it);
           }
         }
         std::vector<std::pair<int, int>> mf;  // (variant, member)
+        stp.o0 = (int)bn.other[v].size();
         for (size_t j = 0; j < bn.lv.size(); ++j) {
           const LevelNet &ln = b->level[bn.lv[j]];
           if (k >= ln.n_ops[v]) continue;
           const DOp &op = b->hp.ops[ln.op_begin[v] + k];
-          if (op.type != OP_CONTRACT) continue;
-          const int prec = level_prec(b, op);
-          if (prec) mf.emplace_back(mfma_variant(op, prec), (int)j);
+          if (op.type == OP_LEAFGRAD) continue;
+          if (op.type == OP_CONTRACT) {
+            const int prec = level_prec(b, op);
+            if (prec) mf.emplace_back(mfma_variant(op, prec), (int)j);
+            continue;
+          }
+          bn.other[v].push_back((int)j);
         }
+        stp.no = (int)bn.other[v].size() - stp.o0;
         std::stable_sort(mf.begin(), mf.end(), [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
           return x.first < y.first;
         });
         std::vector<LItem> splits;
+        int64_t zoff = 0;  // scratch elements of this step's split items
         for (size_t q = 0; q < mf.size(); ++q) {
           const int j = mf[q].second;
           const LevelNet &ln = b->level[bn.lv[j]];
@@ -957,20 +947,13 @@ static int build_level_items(tn_batch *b) {
         stp.nt = (int)items.size() - first;
         stp.tb = blocks;
         stp.mfma = !mf.empty();
-        // sums of the split items' partial tiles and of the rank-0 steps'
-        // partial sums
+        // sums of the split items' partial tiles
         stp.r0 = (int)items.size();
-        stp.nsplit = (int)splits.size();
-        stp.nr = (int)(splits.size() + finals.size());
+        stp.nr = (int)splits.size();
         for (LItem &it : splits) {
           it.blk0 = stp.rb;
           const int64_t outs = (int64_t)b->max_sets << (it.op.nFX + it.op.nFY);
           stp.rb += (int)std::max<int64_t>(1, std::min<int64_t>(kGroupItemBlocks, (outs + 255) / 256));
-          items.push_back(it);
-        }
-        for (LItem &it : finals) {
-          it.blk0 = stp.rb;
-          stp.rb += (b->max_sets + 255) / 256;
           items.push_back(it);
         }
         split_need[v][bn.lane] = std::max(split_need[v][bn.lane], zoff);
@@ -1510,13 +1493,19 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
       void *split = b->d_lsplit ? (char *)b->d_lsplit + b->lsplit_off[v][bn.lane] * eb : nullptr;
       if (e == hipSuccess && stp.mfma)
         e = step_group(b->mfma_prec, b->d_litems[v] + stp.t0, b->d_lblk[v] + stp.t0, stp.nt, stp.tb, b->d_larena,
-                       split, n_sets, b->d_tabs, b->d_lscal, bs);
+                       split, n_sets, b->d_tabs, bs);
       else if (e == hipSuccess)
         e = level_group(b->dtype, b->d_litems[v] + stp.t0, b->d_lblk[v] + stp.t0, stp.nt, stp.tb, b->d_larena, n_sets,
-                        b->d_tabs, b->d_lscal, split, bs);
+                        b->d_tabs, bs);
       if (e == hipSuccess && stp.nr > 0)
         e = mfma_split_reduce(b->dtype, b->d_litems[v] + stp.r0, b->d_lblk[v] + stp.r0, stp.nr, stp.rb, b->d_larena,
-                              split, n_sets, b->d_lscal, bs);
+                              split, n_sets, bs);
+      for (int q = stp.o0; q < stp.o0 + stp.no && e == hipSuccess; ++q) {
+        const int j = bn.other[v][q];
+        const LevelNet &ln = b->level[bn.lv[j]];
+        const DOp &op = b->hp.ops[ln.op_begin[v] + (int)(&stp - bn.steps[v].data())];
+        e = level_op(b->dtype, args(j), op, b->d_tabs, 0, bs);
+      }
     }
     for (size_t j = 0; j < bn.lv.size() && e == hipSuccess; ++j) {
       const LevelNet &ln = b->level[bn.lv[j]];
@@ -1874,6 +1863,10 @@ int batch_info(const tn_batch *b, tn_batch_stats *s) {
       n += 2 * (int64_t)bn.lv.size();  // set-up and outputs
       for (const LevelBin::Step &stp : bn.steps[v]) {
         n += (stp.nt > 0) + (stp.nr > 0);
+        for (int q = stp.o0; q < stp.o0 + stp.no; ++q) {
+          const LevelNet &ln = b->level[bn.lv[bn.other[v][q]]];
+          n += b->hp.ops[ln.op_begin[v] + (int)(&stp - bn.steps[v].data())].type == OP_SCALAR ? 2 : 1;
+        }
       }
     }
     for (int l : b->lsolo) {
@@ -1885,7 +1878,7 @@ int batch_info(const tn_batch *b, tn_batch_stats *s) {
     (v == 0 ? s->level_launches_fwd : s->level_launches_grad) = (int32_t)std::min<int64_t>(n, INT32_MAX);
     int32_t ns = 0;
     for (const LevelBin &bn : b->lbins)
-      for (const LevelBin::Step &stp : bn.steps[v]) ns += stp.nsplit;
+      for (const LevelBin::Step &stp : bn.steps[v]) ns += stp.nr;
     (v == 0 ? s->level_split_fwd : s->level_split_grad) = ns;
   }
   s->n_programs = b->hp.n_programs;

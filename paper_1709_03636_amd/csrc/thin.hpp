@@ -230,67 +230,14 @@ __device__ __forceinline__ void thin_output4s(V *base, const DOp &op, const DRun
 // the total a multiple of L. Steps with many outputs give a lane four of
 // them instead: lgl = -1 four consecutive ones (at least 2 Y-only bits),
 // -2 / -3 four 64 apart along Y / X (thin_output4s).
-//
-// Rank-0 steps and adjoint seeds are items too (scal: the component
-// scalars, FP64; split: the scratch buffer of the launch). A rank-0 step
-// runs on G x parameter-vector workgroups: workgroup g of vector s sums the
-// summed entries g*256 + t, (g + G)*256 + t, ... into partial sum g, a fixed
-// tree; the partials are added in index order by the launch that follows
-// (split_reduce). A seed writes, per vector, the product of the network's
-// other component scalars.
 template <typename V>
 __device__ __forceinline__ void thin_item(const LItem &it, int rank, int count, V *arena, int n_sets,
-                                          const int32_t *__restrict__ tabs, double *scal, void *split) {
+                                          const int32_t *__restrict__ tabs) {
   const DOp op = it.op;
   const int lgOut = op.nFX + op.nB + op.nFY;
   const int32_t *tab = tabs + op.tab;
   const int32_t *tabB = tabs + op.tabB;
   V *reg = arena + it.base;
-  if (op.type == OP_SCALAR) {
-    __shared__ double red[2][4];
-    const int set = rank / it.G, g = rank - set * it.G;
-    if (set >= n_sets) return;  // uniform per workgroup
-    const V *base = reg + set * it.stride;
-    const int64_t K = (int64_t)1 << op.nS;
-    double re = 0.0, im = 0.0;
-#pragma unroll 4
-    for (int64_t k = g * 256 + threadIdx.x; k < K; k += (int64_t)it.G * 256) {
-      const int2 o = l_tab(tab, op.nS, (int)k);
-      const double2 x = l_d2(base[op.x + o.x]);
-      const double2 y = l_d2(base[op.y + o.y]);
-      re += x.x * y.x - x.y * y.y;
-      im += x.x * y.y + x.y * y.x;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      re += __shfl_xor(re, o, 64);
-      im += __shfl_xor(im, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-      red[0][threadIdx.x >> 6] = re;
-      red[1][threadIdx.x >> 6] = im;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double *part = reinterpret_cast<double *>(reinterpret_cast<V *>(split) + it.zs);
-      part[((size_t)set * it.G + g) * 2] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-      part[((size_t)set * it.G + g) * 2 + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
-    }
-    return;
-  }
-  if (op.type == OP_SEED) {
-    for (int set = rank * 256 + threadIdx.x; set < n_sets; set += count * 256) {
-      const double *sv = scal + it.sc + (size_t)set * it.ncomp * 2;
-      double pr = 1.0, pi = 0.0;
-      for (int j = 0; j < it.ncomp; ++j) {
-        if (j == op.aux0) continue;
-        const double nr = pr * sv[2 * j] - pi * sv[2 * j + 1], ni = pr * sv[2 * j + 1] + pi * sv[2 * j];
-        pr = nr;
-        pi = ni;
-      }
-      reg[set * it.stride + op.z] = l_from<V>(make_double2(pr, pi));
-    }
-    return;
-  }
   if (op.type == OP_LEAFGRAD) {  // leaf adjoint (level_leafgrad_kernel per item)
     const int m = 1 << op.nFX;
     const int64_t tot = (int64_t)m * n_sets;
