@@ -128,16 +128,15 @@ constexpr int kSetContract = 1, kSetScalar = 2, kSetSeed = 3, kSetLeafGrad = 4;
 // works in its own region of the level arena (`base` elements from its
 // start, `stride` elements per parameter vector).
 // Workgroups [blk0, next item's blk0) of a grouped launch serve the item;
-// mv: the matrix-core kernel variant of a product on the matrix cores, -1
-// for a thin contraction or a leaf adjoint. A thin contraction sums each
-// output on 2^lgl lanes (lgl < 0: a lane computes four outputs); a
-// matrix-core product splits its summed index into 2^lgl ranges, whose
-// partial results go to a scratch buffer from element zs.
+// a thin contraction sums each output on 2^lgl lanes (lgl < 0: a lane
+// computes four consecutive outputs); a matrix-core product splits its
+// summed index into 2^lgl ranges, whose partial results go to a scratch
+// buffer from element zs.
 struct LItem {
   DOp op;
   DRuns ru;
   int64_t base, stride, zs;
-  int32_t blk0, lgl, mv, pad;
+  int32_t blk0, lgl;
 };
 
 // Arguments of the fused executor kernel.

@@ -19,20 +19,18 @@ namespace qtn {
 __device__ __forceinline__ int group_item(const int32_t *__restrict__ blk, int n, int *rank, int *count) {
   const int b = (int)blockIdx.x;
   const int lane = (int)(threadIdx.x & 63);
-  int idx = 0, first = 0, end = (int)gridDim.x;
+  int idx = 0, end = (int)gridDim.x;
   for (int c0 = 0; c0 < n; c0 += 64) {
     const int i = c0 + lane;
     const int v = i < n ? blk[i] : INT_MAX;
     const int cnt = __popcll(__ballot(v <= b));  // ascending: the items at or before b form a prefix
-    if (cnt > 0) {
-      idx = c0 + cnt - 1;
-      first = __builtin_amdgcn_readlane(v, cnt - 1);
-    }
+    if (cnt > 0) idx = c0 + cnt - 1;
     if (cnt < 64) {  // this chunk holds the first item past b, or the list ends in it
       if (c0 + cnt < n) end = __builtin_amdgcn_readlane(v, cnt);
       break;
     }
   }
+  const int first = blk[idx];
   *rank = b - first;
   *count = end - first;
   return idx;

@@ -24,13 +24,9 @@
 // result does not depend on scheduling).
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
-#include <type_traits>
-
 #include "device.hpp"
 #include "group.hpp"
 #include "internal.hpp"
-#include "thin.hpp"
 
 namespace qtn {
 
@@ -383,42 +379,6 @@ __device__ __forceinline__ void any_tile(const void *base, const DOp &op, const 
   }
 }
 
-// The same with its LDS carved from `lds` (a buffer of at least
-// step_lds(PREC) bytes, 16-byte aligned), for kernels that hold several
-// tile shapes.
-template <int PREC, bool XK, bool YK, int BM, int BN>
-__device__ __forceinline__ void any_tile_at(char *lds, const void *base, const DOp &op, const DRuns &ru,
-                                            const int32_t *__restrict__ tab, int tile, int kb, int ke, void *z) {
-  using T = TileT<BM, BN>;
-  if constexpr (PREC == TN_MFMA_BF16X3) {
-    uint32_t *Ah = reinterpret_cast<uint32_t *>(lds), *Al = Ah + BM * T::PS;
-    uint32_t *Bh = Al + BM * T::PS, *Bl = Bh + BN * T::PS;
-    bf16x3_tile<XK, YK, BM, BN>(Ah, Al, Bh, Bl, (const float2 *)base, op, ru, tab, tile, kb, ke, (float2 *)z);
-  } else if constexpr (PREC == TN_MFMA_FP64) {
-    double2 *As = reinterpret_cast<double2 *>(lds), *Bs = As + BM * T::AS;
-    c4m_tile<double2, XK, YK, BM, BN>(As, Bs, (const double2 *)base, op, ru, tab, tile, kb, ke, (double2 *)z);
-  } else {
-    float2 *As = reinterpret_cast<float2 *>(lds), *Bs = As + BM * T::AS;
-    c4m_tile<float2, XK, YK, BM, BN>(As, Bs, (const float2 *)base, op, ru, tab, tile, kb, ke, (float2 *)z);
-  }
-}
-
-// LDS bytes of one tile of a precision and shape (any_tile_at's layout).
-template <int PREC, int BM, int BN>
-constexpr int tile_lds() {
-  using T = TileT<BM, BN>;
-  return PREC == TN_MFMA_BF16X3 ? 4 * 2 * (BM + BN) * T::PS
-                                : (PREC == TN_MFMA_FP64 ? 16 : 8) * (BM * T::AS + BK * T::BS);
-}
-
-// LDS of the per-step kernel: the largest tile shape of the precision
-// (complex128 runs 64 x 64 tiles only).
-template <int PREC>
-constexpr int step_lds() {
-  return PREC == TN_MFMA_FP64 ? tile_lds<PREC, 64, 64>()
-                              : std::max({tile_lds<PREC, 64, 64>(), tile_lds<PREC, 16, 64>(), tile_lds<PREC, 64, 16>()});
-}
-
 // Bytes of one complex element of a precision's operands.
 constexpr int elem_bytes(int prec) { return prec == TN_MFMA_FP64 ? 16 : 8; }
 
@@ -446,19 +406,19 @@ __global__ __launch_bounds__(256, kMinWaves<PREC>) void mfma_cgemm_kernel(LevelA
   any_tile<PREC, XK, YK, BM, BN>(base, op, ru, tab, b, 0, 1 << op.nS, base + (int64_t)op.z * elem_bytes(PREC));
 }
 
-namespace {
-
-// One matrix-core item of a grouped launch (rank / count: this workgroup's
-// place among the item's workgroups): one op in its network's arena region,
-// on (tiles x 2^lgl summed-index ranges x parameter vectors) workgroups;
-// the workgroups of parameter vectors past n_sets return at once. An item
-// with lgl > 0 writes partial tiles to `split` (from element zs: [parameter
-// vector][range][M x N]).
+// One step of several networks: each item is one op in its network's arena
+// region, on (tiles x 2^lgl summed-index ranges x parameter vectors)
+// workgroups; the workgroups of parameter vectors past n_sets return at
+// once. An item with lgl > 0 writes partial tiles to `split` (from element
+// zs: [parameter vector][range][M x N]).
 template <int PREC, bool XK, bool YK, int BM, int BN>
-__device__ __forceinline__ void mfma_item(char *lds, const LItem &it, int rank, int count, void *arena, void *split,
-                                          int n_sets, const int32_t *__restrict__ tabs) {
+__global__ __launch_bounds__(256, kMinWaves<PREC>) void mfma_group_kernel(const LItem *__restrict__ items,
+                                                         const int32_t *__restrict__ blk, int n, void *arena,
+                                                         void *split, int n_sets, const int32_t *__restrict__ tabs) {
   using T = TileT<BM, BN>;
   constexpr int eb = elem_bytes(PREC);
+  int rank, count;
+  const LItem &it = items[group_item(blk, n, &rank, &count)];
   const DOp op = it.op;
   const int lt = (op.nFX > T::LM ? op.nFX - T::LM : 0) + (op.nFY > T::LN ? op.nFY - T::LN : 0);  // log2 tiles per set
   const int ls = it.lgl;  // log2 summed-index ranges
@@ -469,48 +429,7 @@ __device__ __forceinline__ void mfma_item(char *lds, const LItem &it, int rank, 
   const int kl = op.nS - ls;
   char *z = ls == 0 ? base + (int64_t)op.z * eb
                     : (char *)split + (it.zs + ((((int64_t)set << ls) + part) << (op.nFX + op.nFY))) * eb;
-  any_tile_at<PREC, XK, YK, BM, BN>(lds, base, op, it.ru, tabs + op.tab, tile, part << kl, (part + 1) << kl, z);
-}
-
-}  // namespace
-
-// One step of several networks in one launch: thin contractions and leaf
-// adjoints (items with mv < 0, thin_item) and matrix-core products of every
-// kernel variant of the batch's precision (mv: bit 0 XK, bit 1 YK, bit 2
-// BM = 16, bit 3 BN = 16). Every workgroup branches once on its item; all
-// tile shapes share one LDS buffer.
-template <int PREC>
-__global__ __launch_bounds__(256, kMinWaves<PREC>) void step_group_kernel(const LItem *__restrict__ items,
-                                                                         const int32_t *__restrict__ blk, int n,
-                                                                         void *arena, void *split, int n_sets,
-                                                                         const int32_t *__restrict__ tabs) {
-  __shared__ __align__(16) char lds[step_lds<PREC>()];
-  int rank, count;
-  const LItem &it = items[group_item(blk, n, &rank, &count)];
-  using V = typename std::conditional<PREC == TN_MFMA_FP64, double2, float2>::type;
-  if (it.mv < 0) {
-    thin_item<V>(it, rank, count, (V *)arena, n_sets, tabs);
-    return;
-  }
-#define QTN_ITEM(XK, YK, BM, BN)                                                                   \
-  case (XK ? 1 : 0) | (YK ? 2 : 0) | (BM == 16 ? 4 : 0) | (BN == 16 ? 8 : 0):                      \
-    mfma_item<PREC, XK, YK, BM, BN>(lds, it, rank, count, arena, split, n_sets, tabs);               \
-    break;
-#define QTN_ITEMS(BM, BN) QTN_ITEM(false, false, BM, BN) QTN_ITEM(true, false, BM, BN) \
-  QTN_ITEM(false, true, BM, BN) QTN_ITEM(true, true, BM, BN)
-  if constexpr (PREC == TN_MFMA_FP64) {
-    switch (it.mv & 15) { QTN_ITEMS(64, 64) default: break; }
-  } else {
-    switch (it.mv & 15) {
-      QTN_ITEMS(64, 64)
-      QTN_ITEMS(16, 64)
-      QTN_ITEMS(64, 16)
-      default:
-        break;
-    }
-  }
-#undef QTN_ITEMS
-#undef QTN_ITEM
+  any_tile<PREC, XK, YK, BM, BN>(base, op, it.ru, tabs + op.tab, tile, part << kl, (part + 1) << kl, z);
 }
 
 // Sum of the partial tiles of split items: Z[i] = sum over ranges r in
@@ -577,6 +496,13 @@ void launch_one(const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream
                      op, ru, tab);
 }
 
+template <int PREC, bool XK, bool YK, int BM, int BN>
+void launch_group(const LItem *items, const int32_t *blk, int n, int blocks, void *arena, void *split, int n_sets,
+                  const int32_t *tabs, hipStream_t st) {
+  hipLaunchKernelGGL((mfma_group_kernel<PREC, XK, YK, BM, BN>), dim3(blocks), dim3(256), 0, st, items, blk, n, arena,
+                     split, n_sets, tabs);
+}
+
 // Calls F<PREC, XK, YK, BM, BN>::run(args...) for a variant index; false
 // for an index without a kernel.
 template <template <int, bool, bool, int, int> class F, typename... A>
@@ -610,6 +536,14 @@ struct OneF {
     launch_one<PREC, XK, YK, BM, BN>(*a, *op, tab, st);
   }
 };
+template <int PREC, bool XK, bool YK, int BM, int BN>
+struct GroupF {
+  static void run(const LItem *items, const int32_t *blk, int n, int blocks, void *arena, void *split, int n_sets,
+                  const int32_t *tabs, hipStream_t st) {
+    launch_group<PREC, XK, YK, BM, BN>(items, blk, n, blocks, arena, split, n_sets, tabs, st);
+  }
+};
+
 }  // namespace
 
 // prec: TN_MFMA_FP32 (4M FP32 products) or TN_MFMA_BF16X3 (split-BF16 products).
@@ -619,28 +553,13 @@ hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, 
   return hipGetLastError();
 }
 
-// One step's grouped launch of thin, leaf and matrix-core items (prec: the
-// batch's matrix-core precision) on `blocks` workgroups; split: scratch of
-// the matrix-core items with lgl > 0.
-hipError_t step_group(int prec, const LItem *items, const int32_t *blk, int n, int blocks, void *arena, void *split,
-                      int n_sets, const int32_t *tabs, hipStream_t st) {
+// Grouped launch of n items of one kernel variant (mfma_variant) on
+// `blocks` workgroups (per item: mfma_tiles x 2^lgl x the batch's parameter
+// vectors); split: scratch of the items with lgl > 0.
+hipError_t mfma_group(int variant, const LItem *items, const int32_t *blk, int n, int blocks, void *arena,
+                      void *split, int n_sets, const int32_t *tabs, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  switch (prec) {
-    case TN_MFMA_FP32:
-      hipLaunchKernelGGL(step_group_kernel<TN_MFMA_FP32>, dim3(blocks), dim3(256), 0, st, items, blk, n, arena, split,
-                         n_sets, tabs);
-      break;
-    case TN_MFMA_BF16X3:
-      hipLaunchKernelGGL(step_group_kernel<TN_MFMA_BF16X3>, dim3(blocks), dim3(256), 0, st, items, blk, n, arena,
-                         split, n_sets, tabs);
-      break;
-    case TN_MFMA_FP64:
-      hipLaunchKernelGGL(step_group_kernel<TN_MFMA_FP64>, dim3(blocks), dim3(256), 0, st, items, blk, n, arena, split,
-                         n_sets, tabs);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
+  if (!dispatch<GroupF>(variant, items, blk, n, blocks, arena, split, n_sets, tabs, st)) return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -34,8 +34,8 @@ bool mfma_eligible(int dtype, const DOp &op);
 hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, int prec, hipStream_t st);
 int mfma_tiles(const DOp &op);
 int mfma_variant(const DOp &op, int prec);
-hipError_t step_group(int prec, const LItem *items, const int32_t *blk, int n, int blocks, void *arena, void *split,
-                      int n_sets, const int32_t *tabs, hipStream_t st);
+hipError_t mfma_group(int variant, const LItem *items, const int32_t *blk, int n, int blocks, void *arena,
+                      void *split, int n_sets, const int32_t *tabs, hipStream_t st);
 hipError_t mfma_split_reduce(int dtype, const LItem *items, const int32_t *blk, int n, int blocks, void *arena,
                              const void *split, int n_sets, hipStream_t st);
 hipError_t level_setup(int dtype, const LevelArgs &a, const void *consts, int n_const, const DParam *pt, int n_pt,
@@ -222,16 +222,20 @@ struct LevelBin {
   std::vector<int> lv;         // indices into tn_batch::level
   std::vector<int64_t> abase;  // arena region start (elements)
   std::vector<int64_t> sbase;  // component-scalar region start (doubles)
-  // per step: thin-contraction, leaf-adjoint and matrix-core items [t0,
-  // t0+nt) on tb workgroups (into the variant's item array; mfma: some are
-  // matrix-core products, so the launch takes the per-step kernel), the
-  // partial-tile sums of its split matrix-core items [r0, r0+nr) on rb
-  // workgroups, separately launched ops [o0, o0+no) of `other`
+  // Matrix-core items of one kernel variant in a step.
+  struct MGroup {
+    int variant = 0, i0 = 0, n = 0, blocks = 0;
+  };
+  // per step: thin-contraction and leaf-adjoint items [t0, t0+nt) on tb
+  // workgroups (into the variant's item array), matrix-core groups [g0,
+  // g0+ng) of `mg`, the partial-tile sums of its split matrix-core items
+  // [r0, r0+nr) on rb workgroups, separately launched ops [o0, o0+no) of
+  // `other`
   struct Step {
-    int t0 = 0, nt = 0, tb = 0, r0 = 0, nr = 0, rb = 0, o0 = 0, no = 0;
-    bool mfma = false;
+    int t0 = 0, nt = 0, tb = 0, g0 = 0, ng = 0, r0 = 0, nr = 0, rb = 0, o0 = 0, no = 0;
   };
   std::vector<Step> steps[2];
+  std::vector<MGroup> mg[2];
   std::vector<int> other[2];  // members whose op of the step runs on its own
 };
 
@@ -853,15 +857,15 @@ static int build_level_items(tn_batch *b) {
     for (LevelBin &bn : b->lbins) {
       bn.steps[v].clear();
       bn.other[v].clear();
+      bn.mg[v].clear();
       int n_steps = 0;
       for (int l : bn.lv) n_steps = std::max(n_steps, b->level[l].n_ops[v]);
       for (int k = 0; k < n_steps; ++k) {
         LevelBin::Step stp;
-        // thin contractions, leaf adjoints and matrix-core products of the
-        // step: one launch (thin items first, then products by kernel variant)
-        const int first = (int)items.size();
-        int blocks = 0;
         {
+          // thin contractions and leaf adjoints: one launch
+          const int first = (int)items.size();
+          int blocks = 0;
           for (size_t j = 0; j < bn.lv.size(); ++j) {
             const LevelNet &ln = b->level[bn.lv[j]];
             if (k >= ln.n_ops[v]) continue;
@@ -886,7 +890,6 @@ static int build_level_items(tn_batch *b) {
                 work >>= 2;
               }
             }
-            it.mv = -1;
             it.op = op;
             pack_runs(op.maskX, it.ru.runsX);
             pack_runs(op.maskY, it.ru.runsY);
@@ -896,7 +899,11 @@ static int build_level_items(tn_batch *b) {
             blocks += (int)std::max<int64_t>(1, std::min<int64_t>(kGroupItemBlocks, (work + 255) / 256));
             items.push_back(it);
           }
+          stp.t0 = first;
+          stp.nt = (int)items.size() - first;
+          stp.tb = blocks;
         }
+        // matrix-core products, grouped by kernel variant
         std::vector<std::pair<int, int>> mf;  // (variant, member)
         stp.o0 = (int)bn.other[v].size();
         for (size_t j = 0; j < bn.lv.size(); ++j) {
@@ -915,19 +922,26 @@ static int build_level_items(tn_batch *b) {
         std::stable_sort(mf.begin(), mf.end(), [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
           return x.first < y.first;
         });
+        stp.g0 = (int)bn.mg[v].size();
         std::vector<LItem> splits;
         int64_t zoff = 0;  // scratch elements of this step's split items
         for (size_t q = 0; q < mf.size(); ++q) {
+          if (q == 0 || mf[q].first != mf[q - 1].first) {
+            LevelBin::MGroup g;
+            g.variant = mf[q].first;
+            g.i0 = (int)items.size();
+            bn.mg[v].push_back(g);
+          }
+          LevelBin::MGroup &g = bn.mg[v].back();
           const int j = mf[q].second;
           const LevelNet &ln = b->level[bn.lv[j]];
           LItem it{};
-          it.mv = mf[q].first;
           it.op = b->hp.ops[ln.op_begin[v] + k];
           pack_runs(it.op.maskX, it.ru.runsX);
           pack_runs(it.op.maskY, it.ru.runsY);
           it.base = bn.abase[j];
           it.stride = ln.stride[v];
-          it.blk0 = blocks;
+          it.blk0 = g.blocks;
           const int64_t wg = (int64_t)mfma_tiles(it.op) * b->max_sets;
           const int64_t part = ((int64_t)b->max_sets << (it.op.nFX + it.op.nFY));  // elements per range
           int ls = 0;
@@ -940,13 +954,11 @@ static int build_level_items(tn_batch *b) {
             zoff += part << ls;
             splits.push_back(it);
           }
-          blocks += (int)(wg << ls);
+          g.blocks += (int)(wg << ls);
+          ++g.n;
           items.push_back(it);
         }
-        stp.t0 = first;
-        stp.nt = (int)items.size() - first;
-        stp.tb = blocks;
-        stp.mfma = !mf.empty();
+        stp.ng = (int)bn.mg[v].size() - stp.g0;
         // sums of the split items' partial tiles
         stp.r0 = (int)items.size();
         stp.nr = (int)splits.size();
@@ -1490,13 +1502,15 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
                       grad ? (int)ln.ptens_elems : 0, bs);
     }
     for (const LevelBin::Step &stp : bn.steps[v]) {
-      void *split = b->d_lsplit ? (char *)b->d_lsplit + b->lsplit_off[v][bn.lane] * eb : nullptr;
-      if (e == hipSuccess && stp.mfma)
-        e = step_group(b->mfma_prec, b->d_litems[v] + stp.t0, b->d_lblk[v] + stp.t0, stp.nt, stp.tb, b->d_larena,
-                       split, n_sets, b->d_tabs, bs);
-      else if (e == hipSuccess)
+      if (e == hipSuccess)
         e = level_group(b->dtype, b->d_litems[v] + stp.t0, b->d_lblk[v] + stp.t0, stp.nt, stp.tb, b->d_larena, n_sets,
                         b->d_tabs, bs);
+      void *split = b->d_lsplit ? (char *)b->d_lsplit + b->lsplit_off[v][bn.lane] * eb : nullptr;
+      for (int g = stp.g0; g < stp.g0 + stp.ng && e == hipSuccess; ++g) {
+        const LevelBin::MGroup &mg = bn.mg[v][g];
+        e = mfma_group(mg.variant, b->d_litems[v] + mg.i0, b->d_lblk[v] + mg.i0, mg.n, mg.blocks, b->d_larena, split,
+                       n_sets, b->d_tabs, bs);
+      }
       if (e == hipSuccess && stp.nr > 0)
         e = mfma_split_reduce(b->dtype, b->d_litems[v] + stp.r0, b->d_lblk[v] + stp.r0, stp.nr, stp.rb, b->d_larena,
                               split, n_sets, bs);
@@ -1862,7 +1876,7 @@ int batch_info(const tn_batch *b, tn_batch_stats *s) {
     for (const LevelBin &bn : b->lbins) {
       n += 2 * (int64_t)bn.lv.size();  // set-up and outputs
       for (const LevelBin::Step &stp : bn.steps[v]) {
-        n += (stp.nt > 0) + (stp.nr > 0);
+        n += (stp.nt > 0) + stp.ng + (stp.nr > 0);
         for (int q = stp.o0; q < stp.o0 + stp.no; ++q) {
           const LevelNet &ln = b->level[bn.lv[bn.other[v][q]]];
           n += b->hp.ops[ln.op_begin[v] + (int)(&stp - bn.steps[v].data())].type == OP_SCALAR ? 2 : 1;
