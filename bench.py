@@ -482,6 +482,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-next", action="store_true", help="skip the optimisation / answer-string / noise lines")
     ap.add_argument("--no-grid", action="store_true", help="skip the 4-/5-regular batching grid")
+    ap.add_argument("--extras", action="store_true",
+                    help="only the batching grid, differentiation and crossover rows, as one JSON line")
     ap.add_argument("--grid-case", action="append", default=None,
                     help="only this batching-grid row d,n,p (e.g. 5,50,2; repeatable); prints the rows as one JSON line")
     args = ap.parse_args()
@@ -501,6 +503,11 @@ def main():
     if args.grid_case:
         cases = {tuple(int(x) for x in c.split(",")) for c in args.grid_case}
         print(json.dumps(batching_grid(torch.cuda.Stream(), dev, cases=cases)), flush=True)
+        return
+    if args.extras:
+        st = torch.cuda.Stream()
+        print(json.dumps({"batching_grid": batching_grid(st, dev), "differentiation_p2_n60": differentiation(st, dev),
+                          "crossover_in_degree": crossover(st, dev)}), flush=True)
         return
     edges = workloads.random_regular_graph(D, N_VERT, GRAPH_SEED)
     angles = np.array(workloads.qaoa_angles(ANGLE_SEED, N_SETS, P_LAYERS))
@@ -695,9 +702,23 @@ def main():
         log(f"dense/MFMA: {mfma}")
 
     nxt = None if args.no_next else next_rows(model, params, edges, st, dev)
-    grid = None if args.no_grid else batching_grid(st, dev)
-    diff = None if args.no_grid else differentiation(st, dev)
-    cross = None if args.no_grid else crossover(st, dev)
+    grid = diff = cross = None
+    if not args.no_grid:
+        # the other configurations run in a child process (its own GPU context): a failure there is
+        # recorded in their entries and does not take the headline measurement with it
+        import subprocess
+        try:
+            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--extras"], stdout=subprocess.PIPE,
+                               text=True, timeout=1200)
+            status = r.returncode
+            ex = json.loads(r.stdout.strip().splitlines()[-1])
+            grid, diff, cross = ex["batching_grid"], ex["differentiation_p2_n60"], ex["crossover_in_degree"]
+        except subprocess.TimeoutExpired:
+            grid = diff = cross = {"error": "child process killed after 1200 s"}
+            log("extras failed: time limit")
+        except (ValueError, IndexError, KeyError):
+            grid = diff = cross = {"error": f"child process exited with status {status}"}
+            log(f"extras failed: exit status {status}")
 
     cpu = None
     if not args.no_cpu_baseline:
