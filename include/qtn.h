@@ -204,9 +204,11 @@ int tn_batch_grad(tn_batch *b, const double *params, int32_t n_sets, double *out
                   double *grad, double *grad_net, void *stream);
 
 /* Replay the forward (with_grad = 0) or forward+gradient (1) pass through a
- * HIP graph captured on first use for these exact pointers and n_sets. */
+ * HIP graph captured on first use for these exact pointers and n_sets;
+ * arguments as in tn_batch_grad (grad and grad_net are ignored when
+ * with_grad = 0). */
 int tn_batch_run_graph(tn_batch *b, int32_t with_grad, const double *params, int32_t n_sets,
-                       double *out, double *obj, double *grad, void *stream);
+                       double *out, double *obj, double *grad, double *grad_net, void *stream);
 
 typedef struct {
   int32_t n_nets, n_fused, n_level;   /* networks on the LDS fused and the level-synchronous path */

@@ -83,3 +83,37 @@ def parameter_shift_edge(n, edges, params, edge):
         minus[idx] = (kd, q0, q1, th - np.pi / 2)
         g[slot] += statevector.zz_of(m, plus, uv) - statevector.zz_of(m, minus, uv)
     return g
+
+
+def parameter_shift_edge_tn(n, edges, params, edge):
+    """d<Z_u Z_v>/d(gamma_k, beta_k) for one edge by the shift rule, each
+    shifted circuit evaluated by the plain tensor-network contraction of its
+    light cone (for light cones too wide for a state vector).
+
+    The kept gates are found once on the tagged gate list (the light cone does
+    not depend on the angles); every occurrence of an angle is shifted by
+    +-pi/4 in turn (+-pi/2 in the listed ZZ(2a) or R_X(2a) angle) and the two
+    folded networks are contracted.
+    """
+    from . import tensornet
+    p = len(params) // 2
+    gl = gates.qaoa_gate_list(n, edges, params[:p], params[p:])
+    tagged = [g + (i,) for i, g in enumerate(gl)][n:]  # the H layer is the |+> boundary
+    kept, sup = tensornet.light_cone(n, tagged, {edge[0], edge[1]})
+    ops = [gates.PAULI[3] if q in edge else gates.PAULI[0] for q in range(n)]
+    plus = [np.array([1.0, 1.0]) / np.sqrt(2.0)] * n
+    per_layer = len(edges) + n
+
+    def zz(gate_list):
+        net = tensornet.folded_network(n, [g[:4] for g in gate_list], ops, init=plus, qubits=sup)
+        return tensornet.contract(net).real
+
+    g = np.zeros(2 * p)
+    for idx, (kd, q0, q1, th, full) in enumerate(kept):
+        k = (full - n) // per_layer
+        slot = k if kd == "ZZ" else p + k
+        plus_l, minus_l = list(kept), list(kept)
+        plus_l[idx] = (kd, q0, q1, th + np.pi / 2, full)
+        minus_l[idx] = (kd, q0, q1, th - np.pi / 2, full)
+        g[slot] += zz(plus_l) - zz(minus_l)
+    return g

@@ -19,7 +19,7 @@ int batch_contract(tn_batch *b, const double *params, int n_sets, double *out, d
 int batch_grad(tn_batch *b, const double *params, int n_sets, double *out, double *obj, double *grad, double *gnet,
                void *stream);
 int batch_run_graph(tn_batch *b, int with_grad, const double *params, int n_sets, double *out, double *obj,
-                    double *grad, void *stream);
+                    double *grad, double *grad_net, void *stream);
 int batch_info(const tn_batch *b, tn_batch_stats *s);
 int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, const char *cache_path, void *stream);
 int batch_apply_cache(tn_batch *b, const char *cache_path);
@@ -235,12 +235,12 @@ int tn_batch_grad(tn_batch *b, const double *params, int32_t n_sets, double *out
 }
 
 int tn_batch_run_graph(tn_batch *b, int32_t with_grad, const double *params, int32_t n_sets, double *out, double *obj,
-                       double *grad, void *stream) {
+                       double *grad, double *grad_net, void *stream) {
   if (!b) {
     qtn::set_error("tn_batch_run_graph: NULL batch");
     return TN_EINVAL;
   }
-  GUARD({ return qtn::batch_run_graph(b, with_grad, params, n_sets, out, obj, grad, stream); })
+  GUARD({ return qtn::batch_run_graph(b, with_grad, params, n_sets, out, obj, grad, grad_net, stream); })
 }
 
 int tn_batch_autotune(tn_batch *b, const double *params, int32_t n_sets, int32_t reps, const char *cache_path,

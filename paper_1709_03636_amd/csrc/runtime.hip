@@ -732,7 +732,7 @@ struct GraphCache {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   int with_grad = -1, n_sets = -1;
-  const void *params = nullptr, *out = nullptr, *obj = nullptr, *grad = nullptr;
+  const void *params = nullptr, *out = nullptr, *obj = nullptr, *grad = nullptr, *grad_net = nullptr;
   hipStream_t stream = nullptr;
   void clear() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -1589,7 +1589,7 @@ int batch_grad(tn_batch *b, const double *params, int n_sets, double *out, doubl
 }
 
 int batch_run_graph(tn_batch *b, int with_grad, const double *params, int n_sets, double *out, double *obj,
-                    double *grad, void *stream) {
+                    double *grad, double *grad_net, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   if (!st) {
     set_error("tn_batch_run_graph: needs a non-default stream (graph capture)");
@@ -1597,12 +1597,12 @@ int batch_run_graph(tn_batch *b, int with_grad, const double *params, int n_sets
   }
   GraphCache &g = b->gc;
   bool hit = g.exec && g.with_grad == with_grad && g.n_sets == n_sets && g.params == params && g.out == out &&
-             g.obj == obj && g.grad == grad && g.stream == st;
+             g.obj == obj && g.grad == grad && g.grad_net == grad_net && g.stream == st;
   if (!hit) {
     g.clear();
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     b->capturing = true;
-    int rc = run_batch(b, with_grad != 0, params, n_sets, out, obj, grad, nullptr, st);
+    int rc = run_batch(b, with_grad != 0, params, n_sets, out, obj, grad, with_grad ? grad_net : nullptr, st);
     b->capturing = false;
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(st, &graph);
@@ -1619,6 +1619,7 @@ int batch_run_graph(tn_batch *b, int with_grad, const double *params, int n_sets
     g.out = out;
     g.obj = obj;
     g.grad = grad;
+    g.grad_net = grad_net;
     g.stream = st;
   }
   hipError_t e = hipGraphLaunch(g.exec, st);

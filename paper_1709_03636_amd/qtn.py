@@ -77,7 +77,7 @@ _SIGS = {
     "tn_batch_create": (_I, [ctypes.POINTER(_P), _I, _PD, _D, _I, ctypes.POINTER(_P)]),
     "tn_batch_contract": (_I, [_P, _P, _I, _P, _P, _P]),
     "tn_batch_grad": (_I, [_P, _P, _I, _P, _P, _P, _P, _P]),
-    "tn_batch_run_graph": (_I, [_P, _I, _P, _I, _P, _P, _P, _P]),
+    "tn_batch_run_graph": (_I, [_P, _I, _P, _I, _P, _P, _P, _P, _P]),
     "tn_batch_info": (_I, [_P, ctypes.POINTER(tn_batch_stats)]),
     "tn_batch_autotune": (_I, [_P, _P, _I, _I, ctypes.c_char_p, _P]),
     "tn_batch_apply_tuning": (_I, [_P, ctypes.c_char_p]),
@@ -315,6 +315,6 @@ class Batch:
         _check(lib().tn_batch_grad(self.h, _dptr(params), params.shape[0], _dptr(out), _dptr(obj), _dptr(grad),
                                    _dptr(grad_net), _stream(stream)))
 
-    def run_graph(self, with_grad, params, out=None, obj=None, grad=None, stream=None):
+    def run_graph(self, with_grad, params, out=None, obj=None, grad=None, grad_net=None, stream=None):
         _check(lib().tn_batch_run_graph(self.h, 1 if with_grad else 0, _dptr(params), params.shape[0], _dptr(out),
-                                        _dptr(obj), _dptr(grad), _stream(stream)))
+                                        _dptr(obj), _dptr(grad), _dptr(grad_net), _stream(stream)))

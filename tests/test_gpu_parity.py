@@ -69,7 +69,7 @@ def test_config1_per_edge(dtype, tol):
 
 # --- random circuits in all three modes ---------------------------------------------------
 
-@pytest.mark.parametrize("dtype,tol", [("c128", 1e-12), ("c64", 2e-5)])
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-12), ("c64", 1e-5)])
 @pytest.mark.parametrize("seed", range(4))
 def test_random_circuit_expectation(dtype, tol, seed):
     qtn = _qtn()
@@ -91,7 +91,7 @@ def test_random_circuit_expectation(dtype, tol, seed):
             assert abs(got - ref) < tol, (got, ref)
 
 
-@pytest.mark.parametrize("dtype,tol", [("c128", 1e-12), ("c64", 2e-5)])
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-12), ("c64", 1e-5)])
 @pytest.mark.parametrize("seed", range(3))
 def test_random_circuit_amplitude_probability(dtype, tol, seed):
     qtn = _qtn()
@@ -419,7 +419,7 @@ def test_dense_whole_circuit_mfma(d, n, monkeypatch):
     S = len(ang)
     edges = e[:3]
     ref = np.array([statevector.qaoa_zz(n, e, [a[0]], [a[1]]) for a in ang])  # [set][edge]
-    for dtype, tol in (("c64", 2e-5), ("c128", 1e-12)):
+    for dtype, tol in (("c64", 1e-5), ("c128", 1e-12)):
         dt = qtn.TN_C64 if dtype == "c64" else qtn.TN_C128
         nets = []
         for ed in edges:
@@ -468,21 +468,31 @@ def test_autotune_keeps_results(tmp_path):
     batch.autotune(ang, reps=2, cache_path=cache)
     batch.grad(ang, out=out1, grad_net=g1)
     torch.cuda.synchronize()
-    assert np.max(np.abs(out0.cpu().numpy() - out1.cpu().numpy())) < 2e-5
-    assert np.max(np.abs(g0.cpu().numpy() - g1.cpu().numpy())) < 2e-4
+    # against the oracle: the p=1 closed form and its derivative on every network, before and after tuning
+    a = ang.cpu().numpy()
+    for s in range(2):
+        zz = closed_form.zz_p1(12, e, a[s, 0], a[s, 1])[:4]
+        dg, db = closed_form.zz_p1_grad(12, e, a[s, 0], a[s, 1])
+        g_ref = np.stack([dg[:4], db[:4]], axis=1)
+        for o, g in ((out0, g0), (out1, g1)):
+            assert np.max(np.abs(o.cpu().numpy()[:, s, 0] - zz)) < 1e-5
+            assert np.max(np.abs(g.cpu().numpy()[:, s] - g_ref)) <= 1e-4 * max(1.0, np.abs(g_ref).max())
     text = open(cache).read()
     assert "fused_block:" in text and "mfma:" in text
     batch2 = qtn.Batch(nets, max_sets=2)
     batch2.apply_tuning(cache)
     batch2.contract(ang, out=out1)
     torch.cuda.synchronize()
-    assert np.max(np.abs(out0.cpu().numpy() - out1.cpu().numpy())) < 2e-5
+    for s in range(2):
+        zz = closed_form.zz_p1(12, e, a[s, 0], a[s, 1])[:4]
+        assert np.max(np.abs(out1.cpu().numpy()[:, s, 0] - zz)) < 1e-5
 
 
 def test_dense_split_bf16_precision():
     """Split-BF16 MFMA products on the dense whole-circuit networks: error
-    against the state vector within the split's bound (relative 2^-16 per
-    product, summed over the contraction: 2e-4 absolute on <ZZ>)."""
+    against the state vector within the split's bound (at most 3 * 2^-18
+    relative per product, errors of the matrix-core steps adding in
+    quadrature: 5e-5 absolute on <ZZ>); FP32 products within 1e-5."""
     qtn, qaoa = _qtn(), _qaoa()
     d, n = 6, 12
     e = workloads.random_regular_graph(d, n, 0)
@@ -503,8 +513,8 @@ def test_dense_split_bf16_precision():
         torch.cuda.synchronize()
         errs[prec] = float(np.max(np.abs(out.cpu().numpy()[:, :, 0] - ref[:, :3].T)))
     _say(f"errors {errs}")
-    assert errs[qtn.TN_MFMA_FP32] < 2e-5
-    assert errs[qtn.TN_MFMA_BF16X3] < 2e-4
+    assert errs[qtn.TN_MFMA_FP32] < 1e-5
+    assert errs[qtn.TN_MFMA_BF16X3] < 5e-5
 
 
 def test_dense_whole_circuit_gradient():
@@ -516,7 +526,7 @@ def test_dense_whole_circuit_gradient():
     d, n = 6, 12
     e = workloads.random_regular_graph(d, n, 0)
     ang = np.array(workloads.qaoa_angles(6, 2, 1))
-    for dt, tol_v, tol_g in ((qtn.TN_C64, 2e-5, 1e-4), (qtn.TN_C128, 1e-12, 1e-11)):
+    for dt, tol_v, tol_g in ((qtn.TN_C64, 1e-5, 1e-4), (qtn.TN_C128, 1e-12, 1e-11)):
         nets = []
         for ed in e[:3]:
             net = qaoa.edge_network(n, e, 1, ed, dtype=dt, lightcone=False)
@@ -566,7 +576,7 @@ def test_split_summed_index(monkeypatch):
             torch.cuda.synchronize()
             res[(target, dt)] = (out[0, 0, 0].item(), gn[0, 0].cpu().numpy())
     for (target, dt), (v, g) in res.items():
-        tol_v, tol_g = (2e-5, 1e-4) if dt == qtn.TN_C64 else (1e-12, 1e-11)
+        tol_v, tol_g = (1e-5, 1e-4) if dt == qtn.TN_C64 else (1e-12, 1e-11)
         assert abs(v - zz) < tol_v, (target, dt, v, zz)
         assert np.max(np.abs(g - np.array([dg[0], db[0]]))) < tol_g, (target, dt, g, dg[0], db[0])
     # complex128: the split changes only the order of FP64 sums

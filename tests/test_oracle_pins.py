@@ -295,3 +295,51 @@ def test_edge_parameter_shift_sums_to_full_gradient():
     full = gradients.parameter_shift(8, e, params)
     per_edge = sum(-0.5 * gradients.parameter_shift_edge(8, e, params, ed) for ed in e)
     np.testing.assert_allclose(per_edge, full, atol=1e-12)
+
+
+def test_tn_parameter_shift_sums_to_full_gradient():
+    """The light-cone tensor-network shift rule (used for the wide p=2 cones of
+    the batching configuration) summed over all edges equals the full-state
+    parameter shift, and each edge's entries equal the light-cone state-vector
+    shift rule."""
+    e = workloads.random_regular_graph(4, 8, 2)
+    params = workloads.qaoa_angles(8, 1, 2)[0]
+    full = gradients.parameter_shift(8, e, params)
+    per = [gradients.parameter_shift_edge_tn(8, e, np.array(params), ed) for ed in e]
+    np.testing.assert_allclose(sum(-0.5 * g for g in per), full, atol=1e-12)
+    for ed, g in zip(e[:3], per):
+        np.testing.assert_allclose(g, gradients.parameter_shift_edge(8, e, params, ed), atol=1e-12)
+
+
+def test_config3_golden_values_are_consistent():
+    """tests/golden/config3_p2.json (written by make_config3_p2.py from the
+    oracle): one stored value recomputed, every <Z_u Z_v> in [-1, 1], and the
+    stored gradient of one pair against central differences of the oracle's
+    light-cone contraction (h = 1e-4; O(h^2) truncation)."""
+    import json
+    import os
+    from oracle import gates as og
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "config3_p2.json")))
+    g = next(x for x in gold["graphs"] if (x["d"], x["n"]) == (4, 50))
+    e = workloads.random_regular_graph(4, 50, 0)
+    ang = np.array(workloads.qaoa_angles(0, 64, 2))
+    for gg in gold["graphs"]:
+        assert all(-1.0 <= v <= 1.0 for _, _, v in gg["values"])
+
+    def zz(prm, edge):
+        gl = og.qaoa_gate_list(50, e, prm[:2], prm[2:])[50:]
+        pauli = [0] * 50
+        pauli[edge[0]] = pauli[edge[1]] = 3
+        return tensornet.expectation(50, gl, pauli, init=[np.array([1.0, 1.0]) / np.sqrt(2.0)] * 50,
+                                     lightcone=True).real
+
+    i, s, v = g["values"][0]
+    assert abs(zz(ang[s], e[i]) - v) < 1e-13
+    i, s, gv = g["grads"][0]
+    h = 1e-4
+    fd = []
+    for k in range(4):
+        d = np.zeros(4)
+        d[k] = h
+        fd.append((zz(ang[s] + d, e[i]) - zz(ang[s] - d, e[i])) / (2 * h))
+    np.testing.assert_allclose(gv, fd, atol=1e-6)
