@@ -187,6 +187,29 @@ int tn_grad(tn_net *net, const double *params, double *value, double *grad, void
 int tn_batch_create(tn_net *const *nets, int32_t n_nets, const double *coef, double offset,
                     int32_t max_sets, tn_batch **out);
 
+/* Device workspace of a batch: every device array it uses (program
+ * descriptors and tables, bound tensors, executor arenas, level items and
+ * task queue, outputs of its own). *bytes receives the size the batch needs.
+ * Host only. */
+int tn_batch_workspace_bytes(const tn_batch *b, int64_t *bytes);
+
+/* Bind a caller-owned device buffer of at least tn_batch_workspace_bytes
+ * bytes as the batch's workspace (e.g. a torch.empty(bytes, uint8) tensor);
+ * the program arrays are uploaded (synchronous). The buffer must outlive the
+ * batch or the next call of this function, and no other work may write it.
+ * A batch run without a bound workspace gets one from the allocator
+ * (tn_set_allocator), owned and freed by the batch. TN_EINVAL when the
+ * buffer is NULL or too small. */
+int tn_batch_set_workspace(tn_batch *b, void *workspace, int64_t bytes);
+
+/* Device allocator for the library's own device memory (workspaces of
+ * batches without a bound one, the one-network path, autotuner scratch):
+ * alloc(bytes, ctx) returns device memory or NULL, release(ptr, ctx) frees
+ * it. Both NULL restores hipMalloc / hipFree. Process-wide. */
+typedef void *(*tn_alloc_fn)(uint64_t bytes, void *ctx);
+typedef void (*tn_free_fn)(void *ptr, void *ctx);
+int tn_set_allocator(tn_alloc_fn alloc, tn_free_fn release, void *ctx);
+
 /* Forward pass over n_sets parameter vectors. Device pointers:
  *   params: n_sets x n_params doubles (may be NULL when n_params = 0);
  *   out:    n_nets x n_sets complex scalars (2 doubles each, network-major), may be NULL;
@@ -222,8 +245,11 @@ typedef struct {
   int32_t sets_per_wave_grad;         /* forward / adjoint programs (1, 2 or 4) */
   int32_t n_global;                   /* networks on the global-arena fused executor (too large for
                                          LDS, steps small enough for one workgroup) */
-  int32_t n_level_bins;               /* groups of level networks stepped together (one launch per
-                                         step and kind for the whole group) */
+  int32_t n_level_groups;             /* groups of level networks that share one arena region, run
+                                         one after another */
+  int32_t n_level_tasked;             /* of those, groups run by the task executor (one launch; a
+                                         workgroup runs a whole program for one parameter vector);
+                                         the others run one launch per step, spread over the chip */
   int32_t n_level_chunked;            /* level networks run alone, in chunks of parameter vectors */
   int32_t level_launches_fwd;         /* kernel launches of the level executor per pass with all */
   int32_t level_launches_grad;        /* parameter vectors: forward / forward+adjoint */

@@ -21,6 +21,9 @@ int batch_grad(tn_batch *b, const double *params, int n_sets, double *out, doubl
 int batch_run_graph(tn_batch *b, int with_grad, const double *params, int n_sets, double *out, double *obj,
                     double *grad, double *grad_net, void *stream);
 int batch_info(const tn_batch *b, tn_batch_stats *s);
+int64_t batch_workspace_bytes(const tn_batch *b);
+int batch_bind(tn_batch *b, void *ptr, int64_t bytes);
+int set_allocator(tn_alloc_fn alloc, tn_free_fn release, void *ctx);
 int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, const char *cache_path, void *stream);
 int batch_apply_cache(tn_batch *b, const char *cache_path);
 int batch_set_precision(tn_batch *b, int prec);
@@ -216,6 +219,25 @@ int tn_batch_create(tn_net *const *nets, int32_t n_nets, const double *coef, dou
                     tn_batch **out) {
   GUARD({ return qtn::batch_create(nets, n_nets, coef, offset, max_sets, out); })
 }
+
+int tn_batch_workspace_bytes(const tn_batch *b, int64_t *bytes) {
+  if (!b || !bytes) {
+    qtn::set_error("tn_batch_workspace_bytes: NULL argument");
+    return TN_EINVAL;
+  }
+  *bytes = qtn::batch_workspace_bytes(b);
+  return TN_OK;
+}
+
+int tn_batch_set_workspace(tn_batch *b, void *workspace, int64_t bytes) {
+  if (!b) {
+    qtn::set_error("tn_batch_set_workspace: NULL batch");
+    return TN_EINVAL;
+  }
+  GUARD({ return qtn::batch_bind(b, workspace, bytes); })
+}
+
+int tn_set_allocator(tn_alloc_fn alloc, tn_free_fn release, void *ctx) { return qtn::set_allocator(alloc, release, ctx); }
 
 int tn_batch_contract(tn_batch *b, const double *params, int32_t n_sets, double *out, double *obj, void *stream) {
   if (!b) {

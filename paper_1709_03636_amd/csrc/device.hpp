@@ -124,53 +124,53 @@ constexpr int kRecLanes = 64;
 constexpr int kMaxGroupLanes = 16, kLgMaxGroupLanes = 4;
 constexpr int kSetContract = 1, kSetScalar = 2, kSetSeed = 3, kSetLeafGrad = 4;
 
-// One step of one network for the grouped level launches: every network
-// works in its own region of the level arena (`base` elements from its
-// start, `stride` elements per parameter vector).
-// Workgroups [blk0, next item's blk0) of a grouped launch serve the item;
-// a thin contraction sums each output on 2^lgl lanes (lgl < 0: a lane
-// computes four consecutive outputs); a matrix-core product splits its
-// summed index into 2^lgl ranges, whose partial results go to a scratch
-// buffer from element zs.
-struct LItem {
+// Level executor: every op of a network program too large for LDS is an
+// item of workgroup-sized tasks (rank 0..count-1) working in the network's
+// region of the level arena (`base` elements from its start, `stride`
+// elements per parameter vector). Item mode launches the items of a network
+// one by one, each over all parameter vectors on the whole chip; the task
+// executor runs whole (network, parameter vector) programs, one per
+// workgroup, with items built for one vector (TNet).
+enum PKind : int32_t {
+  PK_SETUP = 0,       // constants and bound parametric tensors into the region, adjoint accumulators cleared
+  PK_THIN = 1,        // thin contraction (eq. (1)) or leaf adjoint on the vector units
+  PK_MFMA = 2,        // contraction as a complex GEMM on the matrix cores
+  PK_SPLITSUM = 3,    // sum of the partial tiles of a split matrix-core product, in range order (FP64)
+  PK_SCALAR = 4,      // rank-0 result: partial sums of the summed index (FP64)
+  PK_SCALAR_SUM = 5,  // rank-0 result: sum of the partial sums in index order (FP64)
+  PK_SEED = 6,        // adjoint seed: product of the other component scalars
+  PK_FINISH = 7       // value and gradient of the network into the outputs
+};
+
+struct PItem {
   DOp op;
   DRuns ru;
-  int64_t base, stride, zs;
-  int32_t blk0, lgl;
-};
-
-// Arguments of the fused executor kernel.
-struct FusedArgs {
-  const DNet *nets;
-  const DOp *ops;
-  const int4 *recs;
-  const int32_t *tabs;
-  const void *consts;
-  const DParam *ptens;
-  const void *bound;        // [set][per_set] parametric tensors (binding kernel output)
-  const void *dbound;       // [set][per_set] their angle derivatives (adjoint programs)
-  const int32_t *task_net;  // queue position -> network index (cost order)
-  double *out_val;          // [net][set][2]
-  double *out_grad;         // [net][set][n_params] (adjoint programs)
-  int n_params, n_sets, n_tasks, per_set;
-  int set_stride, n_groups, max_comp;  // set-packed executor: LDS elements per set, set groups, scalars per set
-  int per_block;            // workgroup b runs tasks [b*per_block, (b+1)*per_block)
-  void *garena;             // global-arena executor: workgroup b works in garena + b * garena_stride
-  int64_t garena_stride;    // (elements)
-  int scratch_off, scal_off, gacc_off, red_off, gbar_off;  // LDS byte offsets
-};
-
-// Arguments of the level executor kernels (one chunk of parameter vectors).
-struct LevelArgs {
-  void *arena;     // [set][stride] elements
+  int64_t base;    // the network's arena region (elements)
   int64_t stride;  // elements per parameter vector
-  int n_sets;      // parameter vectors in this chunk
-  double *scal;    // [set][n_comp] component scalars (complex, FP64)
-  int n_comp;
-  double *part;    // [set][kScalarParts] partial sums of a large rank-0 contraction
+  int64_t zs;      // MFMA (split) and SPLITSUM: partial tiles from this element of the split scratch;
+                   // SCALAR / SCALAR_SUM: partial sums from this double of the partial-sum buffer
+  int64_t sbase;   // the network's component scalars (doubles; [set][n_comp] complex)
+  int32_t kind;    // PKind
+  int32_t count;   // tasks of the item (workgroups of a one-item launch)
+  int32_t lgl;     // THIN: 2^lgl lanes per output (< 0: four outputs per lane); MFMA / SPLITSUM: log2 of the
+                   // summed-index ranges; SCALAR: workgroups per parameter vector (1: writes the scalar)
+  int32_t mv;      // MFMA: kernel variant (tile shape, operand layouts)
+  int32_t n_comp;  // component scalars of the network
+  int32_t a0, a1, a2, a3, a4, a5;  // SETUP: const_begin, n_const, ptens_begin, n_pt, zero_begin, zero_n;
+                                   // FINISH: network index, ptens_begin, n_pt
 };
 
-// Workgroups per parameter vector for a large rank-0 contraction.
+// One network of a task-executor launch: task (network j, vector s) runs
+// items [item0, item0 + n_items) (built for one vector) on the vector's
+// slice of the network's region.
+struct TNet {
+  int64_t abase;   // arena region (elements): vector s at abase + s * stride
+  int64_t stride;  // elements per parameter vector
+  int64_t sbase;   // component scalars (doubles): vector s at sbase + s * n_comp * 2
+  int32_t item0, n_items, n_comp, pad;
+};
+
+// Workgroups per parameter vector of a large rank-0 contraction.
 constexpr int kScalarParts = 256;
 
 }  // namespace qtn

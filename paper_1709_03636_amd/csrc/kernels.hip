@@ -14,6 +14,7 @@
 
 #include "device.hpp"
 #include "internal.hpp"
+#include "kargs.hpp"
 
 namespace qtn {
 

@@ -1,5 +1,5 @@
-// Pairwise contraction on the matrix cores (large steps of the level
-// executor): eq. (1) as a complex GEMM
+// Complex GEMM tiles on the matrix cores (device code of the level
+// executor's matrix-core items): eq. (1) as
 //   Z[m*N + n] = sum_k X[rX(m) + tX(k)] * Y[tY(k) + cY(n)],
 // with rX / cY the deposit of the free-index bits into X / Y and (tX, tY)
 // the op's summed-index offsets. The bit permutation is applied while the
@@ -7,25 +7,16 @@
 //
 // Complex products use four real products (4M) on v_mfma_f32_16x16x4_f32
 // with FP32 accumulation for complex64 (or split-BF16 products, below), on
-// v_mfma_f64_16x16x4_f64 with FP64 accumulation for complex128: with the summed
-// index interleaved as (re, im) pairs, Re Z = [Xr, -Xi] . [Yr; Yi] and
-// Im Z = [Xi, Xr] . [Yr; Yi].
-// Workgroup tile: BM x BN complex outputs (64 x 64, or 16 x 64 / 64 x 16
-// when one free index has only 4 or 5 bits) for four waves; 16 complex
-// summed entries per LDS stage, the next stage prefetched into registers
-// while the matrix cores work on the current one.
-//
-// Split summed index: a product with few output tiles and a long sum (the
-// adjoints of late steps: small result, large summed index) would occupy a
-// handful of workgroups for the whole sum. Such an item of a grouped launch
-// is split into 2^s ranges of the summed index, each tile-range pair on its
-// own workgroup writing a partial tile to a scratch buffer; a second grouped
-// kernel adds the partials of every output in range order (FP64 sums, so the
-// result does not depend on scheduling).
+// v_mfma_f64_16x16x4_f64 with FP64 accumulation for complex128: with the
+// summed index interleaved as (re, im) pairs, Re Z = [Xr, -Xi] . [Yr; Yi] and
+// Im Z = [Xi, Xr] . [Yr; Yi]. Workgroup tile: BM x BN complex outputs
+// (64 x 64, or 16 x 64 / 64 x 16 when one free index has only 2-5 bits) for
+// four waves; 16 complex summed entries per LDS stage, the next stage
+// prefetched into registers while the matrix cores work on the current one.
+#pragma once
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
-#include "group.hpp"
 #include "internal.hpp"
 
 namespace qtn {
@@ -357,224 +348,36 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
       }
 }
 
-// One tile of any precision with its LDS over summed entries [kb, ke);
-// base: the parameter vector's arena slice (complex128 for TN_MFMA_FP64,
-// else complex64); z: where the M x N result goes.
+// One tile of any precision over summed entries [kb, ke), staged through
+// the LDS at `lds` (kTileLds bytes, 16-byte aligned); base: the parameter
+// vector's arena slice (complex128 for TN_MFMA_FP64, else complex64); z:
+// where the M x N result goes.
 template <int PREC, bool XK, bool YK, int BM, int BN>
-__device__ __forceinline__ void any_tile(const void *base, const DOp &op, const DRuns &ru,
+__device__ __forceinline__ void any_tile(char *lds, const void *base, const DOp &op, const DRuns &ru,
                                          const int32_t *__restrict__ tab, int tile, int kb, int ke, void *z) {
   using T = TileT<BM, BN>;
   if constexpr (PREC == TN_MFMA_BF16X3) {
-    __shared__ __align__(16) uint32_t Ah[BM * T::PS], Al[BM * T::PS];
-    __shared__ __align__(16) uint32_t Bh[BN * T::PS], Bl[BN * T::PS];
+    uint32_t *Ah = reinterpret_cast<uint32_t *>(lds), *Al = Ah + BM * T::PS;
+    uint32_t *Bh = Al + BM * T::PS, *Bl = Bh + BN * T::PS;
     bf16x3_tile<XK, YK, BM, BN>(Ah, Al, Bh, Bl, (const float2 *)base, op, ru, tab, tile, kb, ke, (float2 *)z);
   } else if constexpr (PREC == TN_MFMA_FP64) {
-    __shared__ double2 As[BM * T::AS];
-    __shared__ double2 Bs[BK * T::BS];
+    double2 *As = reinterpret_cast<double2 *>(lds), *Bs = As + BM * T::AS;
     c4m_tile<double2, XK, YK, BM, BN>(As, Bs, (const double2 *)base, op, ru, tab, tile, kb, ke, (double2 *)z);
   } else {
-    __shared__ float2 As[BM * T::AS];
-    __shared__ float2 Bs[BK * T::BS];
+    float2 *As = reinterpret_cast<float2 *>(lds), *Bs = As + BM * T::AS;
     c4m_tile<float2, XK, YK, BM, BN>(As, Bs, (const float2 *)base, op, ru, tab, tile, kb, ke, (float2 *)z);
   }
 }
 
+// LDS bytes of the largest tile of a precision (64 x 64).
+template <int PREC>
+constexpr int kTileLds = PREC == TN_MFMA_BF16X3 ? 4 * 64 * TileT<64, 64>::PS * 4
+                         : PREC == TN_MFMA_FP64 ? (64 * TileT<64, 64>::AS + BK * TileT<64, 64>::BS) * 16
+                                                : (64 * TileT<64, 64>::AS + BK * TileT<64, 64>::BS) * 8;
+
 // Bytes of one complex element of a precision's operands.
 constexpr int elem_bytes(int prec) { return prec == TN_MFMA_FP64 ? 16 : 8; }
 
-// XCD-aware order of a run of `total` workgroups: consecutive workgroups
-// land on different XCDs, so each XCD is given a contiguous run of tiles
-// (shared operand rows stay in its L2).
-__device__ __forceinline__ int xcd_order(int b, int total) {
-  return total % 8 == 0 ? (b & 7) * (total >> 3) + (b >> 3) : b;
-}
-
 }  // namespace
-
-// Waves per SIMD the tile kernels are compiled for: the split-BF16 64 x 64
-// tile holds 132 registers unconstrained (3 waves per SIMD); capped at 128 it
-// runs 4 without spills. The others keep the compiler's choice (FP64 would
-// spill).
-template <int PREC>
-constexpr int kMinWaves = PREC == TN_MFMA_BF16X3 ? 4 : 1;
-
-// One op: grid (tiles, 1, parameter vectors).
-template <int PREC, bool XK, bool YK, int BM, int BN>
-__global__ __launch_bounds__(256, kMinWaves<PREC>) void mfma_cgemm_kernel(LevelArgs a, DOp op, DRuns ru, const int32_t *__restrict__ tab) {
-  const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
-  char *base = reinterpret_cast<char *>(a.arena) + (int64_t)blockIdx.z * a.stride * elem_bytes(PREC);
-  any_tile<PREC, XK, YK, BM, BN>(base, op, ru, tab, b, 0, 1 << op.nS, base + (int64_t)op.z * elem_bytes(PREC));
-}
-
-// One step of several networks: each item is one op in its network's arena
-// region, on (tiles x 2^lgl summed-index ranges x parameter vectors)
-// workgroups; the workgroups of parameter vectors past n_sets return at
-// once. An item with lgl > 0 writes partial tiles to `split` (from element
-// zs: [parameter vector][range][M x N]).
-template <int PREC, bool XK, bool YK, int BM, int BN>
-__global__ __launch_bounds__(256, kMinWaves<PREC>) void mfma_group_kernel(const LItem *__restrict__ items,
-                                                         const int32_t *__restrict__ blk, int n, void *arena,
-                                                         void *split, int n_sets, const int32_t *__restrict__ tabs) {
-  using T = TileT<BM, BN>;
-  constexpr int eb = elem_bytes(PREC);
-  int rank, count;
-  const LItem &it = items[group_item(blk, n, &rank, &count)];
-  const DOp op = it.op;
-  const int lt = (op.nFX > T::LM ? op.nFX - T::LM : 0) + (op.nFY > T::LN ? op.nFY - T::LN : 0);  // log2 tiles per set
-  const int ls = it.lgl;  // log2 summed-index ranges
-  const int b = xcd_order(rank, count);
-  const int set = b >> (lt + ls), part = (b >> lt) & ((1 << ls) - 1), tile = b & ((1 << lt) - 1);
-  if (set >= n_sets) return;
-  char *base = (char *)arena + (it.base + (int64_t)set * it.stride) * eb;
-  const int kl = op.nS - ls;
-  char *z = ls == 0 ? base + (int64_t)op.z * eb
-                    : (char *)split + (it.zs + ((((int64_t)set << ls) + part) << (op.nFX + op.nFY))) * eb;
-  any_tile<PREC, XK, YK, BM, BN>(base, op, it.ru, tabs + op.tab, tile, part << kl, (part + 1) << kl, z);
-}
-
-// Sum of the partial tiles of split items: Z[i] = sum over ranges r in
-// order of split[zs + ((set 2^lgl + r) M N) + i], in FP64.
-template <typename V>
-__global__ __launch_bounds__(256) void mfma_split_reduce_kernel(const LItem *__restrict__ items,
-                                                                const int32_t *__restrict__ blk, int n, void *arena,
-                                                                const void *split, int n_sets) {
-  int rank, count;
-  const LItem &it = items[group_item(blk, n, &rank, &count)];
-  const int ls = it.lgl, lmn = it.op.nFX + it.op.nFY;
-  const int64_t total = (int64_t)n_sets << lmn;
-  const V *sp = reinterpret_cast<const V *>(split) + it.zs;
-  V *ar = reinterpret_cast<V *>(arena);
-  for (int64_t g = (int64_t)rank * 256 + threadIdx.x; g < total; g += (int64_t)count * 256) {
-    const int64_t set = g >> lmn, i = g & ((int64_t(1) << lmn) - 1);
-    const V *src = sp + ((set << ls) << lmn) + i;
-    double re = 0.0, im = 0.0;
-    for (int r = 0; r < (1 << ls); ++r) {
-      const V v = src[(int64_t)r << lmn];
-      re += v.x;
-      im += v.y;
-    }
-    using R = typename Acc4<V>::R;
-    ar[it.base + set * it.stride + it.op.z + i] = make_c((R)re, (R)im);
-  }
-}
-
-// True when the MFMA path takes this op: no batch bits, at least 16 summed
-// entries; complex64: one free index at least 64 wide, the other at least 4
-// (tiles 64 x 64, 16 x 64 or 64 x 16; a 4- or 8-wide index is one padded
-// 16-wide tile); complex128: both at least 64 wide (64 x 64 tiles only).
-bool mfma_eligible(int dtype, const DOp &op) {
-  if (op.type != OP_CONTRACT || op.nB != 0 || op.nS < 4) return false;
-  if (dtype == TN_C128) return op.nFX >= 6 && op.nFY >= 6;
-  return dtype == TN_C64 && op.nFX >= 2 && op.nFY >= 2 && (op.nFX >= 6 || op.nFY >= 6);
-}
-
-// Tile rows / columns of an eligible op.
-static inline int tile_m(const DOp &op) { return op.nFX >= 6 ? 64 : 16; }
-static inline int tile_n(const DOp &op) { return op.nFY >= 6 ? 64 : 16; }
-
-// Workgroups of an eligible op per parameter vector.
-int mfma_tiles(const DOp &op) {
-  const int lm = tile_m(op) == 64 ? 6 : 4, ln = tile_n(op) == 64 ? 6 : 4;
-  return 1 << ((op.nFX > lm ? op.nFX - lm : 0) + (op.nFY > ln ? op.nFY - ln : 0));
-}
-
-// Kernel variant of an op: bit 0 XK, bit 1 YK, bit 2 BM = 16, bit 3 BN = 16,
-// bit 4 split-BF16, bit 5 FP64.
-int mfma_variant(const DOp &op, int prec) {
-  return (!(op.maskX & 1u) ? 1 : 0) | (!(op.maskY & 1u) ? 2 : 0) | (tile_m(op) == 16 ? 4 : 0) |
-         (tile_n(op) == 16 ? 8 : 0) | (prec == TN_MFMA_BF16X3 ? 16 : 0) | (prec == TN_MFMA_FP64 ? 32 : 0);
-}
-
-namespace {
-
-template <int PREC, bool XK, bool YK, int BM, int BN>
-void launch_one(const LevelArgs &a, const DOp &op, const int32_t *tab, hipStream_t st) {
-  DRuns ru;
-  pack_runs(op.maskX, ru.runsX);
-  pack_runs(op.maskY, ru.runsY);
-  hipLaunchKernelGGL((mfma_cgemm_kernel<PREC, XK, YK, BM, BN>), dim3(mfma_tiles(op), 1, a.n_sets), dim3(256), 0, st, a,
-                     op, ru, tab);
-}
-
-template <int PREC, bool XK, bool YK, int BM, int BN>
-void launch_group(const LItem *items, const int32_t *blk, int n, int blocks, void *arena, void *split, int n_sets,
-                  const int32_t *tabs, hipStream_t st) {
-  hipLaunchKernelGGL((mfma_group_kernel<PREC, XK, YK, BM, BN>), dim3(blocks), dim3(256), 0, st, items, blk, n, arena,
-                     split, n_sets, tabs);
-}
-
-// Calls F<PREC, XK, YK, BM, BN>::run(args...) for a variant index; false
-// for an index without a kernel.
-template <template <int, bool, bool, int, int> class F, typename... A>
-bool dispatch(int v, A... args) {
-#define QTN_TILE(PREC, XK, YK, BM, BN)              \
-  case (XK ? 1 : 0) | (YK ? 2 : 0) | (BM == 16 ? 4 : 0) | (BN == 16 ? 8 : 0) | (PREC == TN_MFMA_BF16X3 ? 16 : 0) | \
-      (PREC == TN_MFMA_FP64 ? 32 : 0):              \
-    F<PREC, XK, YK, BM, BN>::run(args...);          \
-    return true;
-#define QTN_TILES(PREC, BM, BN) \
-  QTN_TILE(PREC, false, false, BM, BN) QTN_TILE(PREC, true, false, BM, BN) QTN_TILE(PREC, false, true, BM, BN) \
-  QTN_TILE(PREC, true, true, BM, BN)
-  switch (v) {
-    QTN_TILES(TN_MFMA_FP32, 64, 64)
-    QTN_TILES(TN_MFMA_FP32, 16, 64)
-    QTN_TILES(TN_MFMA_FP32, 64, 16)
-    QTN_TILES(TN_MFMA_BF16X3, 64, 64)
-    QTN_TILES(TN_MFMA_BF16X3, 16, 64)
-    QTN_TILES(TN_MFMA_BF16X3, 64, 16)
-    QTN_TILES(TN_MFMA_FP64, 64, 64)
-    default:
-      return false;
-  }
-#undef QTN_TILES
-#undef QTN_TILE
-}
-
-template <int PREC, bool XK, bool YK, int BM, int BN>
-struct OneF {
-  static void run(const LevelArgs *a, const DOp *op, const int32_t *tab, hipStream_t st) {
-    launch_one<PREC, XK, YK, BM, BN>(*a, *op, tab, st);
-  }
-};
-template <int PREC, bool XK, bool YK, int BM, int BN>
-struct GroupF {
-  static void run(const LItem *items, const int32_t *blk, int n, int blocks, void *arena, void *split, int n_sets,
-                  const int32_t *tabs, hipStream_t st) {
-    launch_group<PREC, XK, YK, BM, BN>(items, blk, n, blocks, arena, split, n_sets, tabs, st);
-  }
-};
-
-}  // namespace
-
-// prec: TN_MFMA_FP32 (4M FP32 products) or TN_MFMA_BF16X3 (split-BF16 products).
-hipError_t mfma_contract(const LevelArgs &a, const DOp &op, const int32_t *tab, int prec, hipStream_t st) {
-  if (!mfma_eligible(prec == TN_MFMA_FP64 ? TN_C128 : TN_C64, op) || !dispatch<OneF>(mfma_variant(op, prec), &a, &op, tab, st))
-    return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-
-// Grouped launch of n items of one kernel variant (mfma_variant) on
-// `blocks` workgroups (per item: mfma_tiles x 2^lgl x the batch's parameter
-// vectors); split: scratch of the items with lgl > 0.
-hipError_t mfma_group(int variant, const LItem *items, const int32_t *blk, int n, int blocks, void *arena,
-                      void *split, int n_sets, const int32_t *tabs, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  if (!dispatch<GroupF>(variant, items, blk, n, blocks, arena, split, n_sets, tabs, st)) return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-
-// Grouped sum of the partial tiles of split items (one item per split op,
-// at most kGroupItemBlocks workgroups each).
-hipError_t mfma_split_reduce(int dtype, const LItem *items, const int32_t *blk, int n, int blocks, void *arena,
-                             const void *split, int n_sets, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  if (dtype == TN_C128)
-    hipLaunchKernelGGL(mfma_split_reduce_kernel<double2>, dim3(blocks), dim3(256), 0, st, items, blk, n, arena, split,
-                       n_sets);
-  else
-    hipLaunchKernelGGL(mfma_split_reduce_kernel<float2>, dim3(blocks), dim3(256), 0, st, items, blk, n, arena, split,
-                       n_sets);
-  return hipGetLastError();
-}
 
 }  // namespace qtn

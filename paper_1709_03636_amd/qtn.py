@@ -51,7 +51,7 @@ class tn_batch_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("n_nets", "n_fused", "n_level", "n_levels", "lds_bytes_fwd",
                                                "lds_bytes_grad", "n_programs", "fused_block", "rec_only",
                                                "sets_per_wave_fwd", "sets_per_wave_grad", "n_global",
-                                               "n_level_bins", "n_level_chunked", "level_launches_fwd",
+                                               "n_level_groups", "n_level_tasked", "n_level_chunked", "level_launches_fwd",
                                                "level_launches_grad", "level_split_fwd", "level_split_grad")] + \
                [(n, ctypes.c_double) for n in ("flops_fwd", "bytes_fwd", "flops_grad", "bytes_grad")]
 
@@ -75,6 +75,9 @@ _SIGS = {
     "tn_contract": (_I, [_P, _PD, _PD, _P]),
     "tn_grad": (_I, [_P, _PD, _PD, _PD, _P]),
     "tn_batch_create": (_I, [ctypes.POINTER(_P), _I, _PD, _D, _I, ctypes.POINTER(_P)]),
+    "tn_batch_workspace_bytes": (_I, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "tn_batch_set_workspace": (_I, [_P, _P, ctypes.c_int64]),
+    "tn_set_allocator": (_I, [_P, _P, _P]),
     "tn_batch_contract": (_I, [_P, _P, _I, _P, _P, _P]),
     "tn_batch_grad": (_I, [_P, _P, _I, _P, _P, _P, _P, _P]),
     "tn_batch_run_graph": (_I, [_P, _I, _P, _I, _P, _P, _P, _P, _P]),
@@ -121,7 +124,40 @@ def _dptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+# Device memory the library needs beyond a batch's bound workspace (the
+# one-network path, batches run without a workspace, autotuner scratch) comes
+# from PyTorch's allocator through tn_set_allocator.
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_torch_blocks = {}
+
+
+def _torch_alloc(nbytes, ctx):
+    import torch
+    t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+    _torch_blocks[t.data_ptr()] = t
+    return t.data_ptr()
+
+
+def _torch_free(ptr, ctx):
+    _torch_blocks.pop(ptr, None)
+
+
+_alloc_cb = _ALLOC_FN(_torch_alloc)
+_free_cb = _FREE_FN(_torch_free)
+_allocator_set = False
+
+
+def _device_setup():
+    """Route the library's device allocations through PyTorch (once)."""
+    global _allocator_set
+    if not _allocator_set:
+        _check(lib().tn_set_allocator(ctypes.cast(_alloc_cb, _P), ctypes.cast(_free_cb, _P), None))
+        _allocator_set = True
+
+
 def _stream(stream):
+    _device_setup()
     if stream is None:
         import torch
         stream = torch.cuda.current_stream()
@@ -259,7 +295,10 @@ class Network:
 
 
 class Batch:
-    """Many networks x many parameter vectors in one fused launch (tn_batch_*)."""
+    """Many networks x many parameter vectors (tn_batch_*). The device
+    workspace is a torch uint8 tensor bound on first use (or explicitly by
+    bind_workspace); device tensors passed to the calls are checked for dtype,
+    device, layout and size before anything is launched."""
 
     def __init__(self, nets, coef=None, offset=0.0, max_sets=1):
         self.nets = list(nets)
@@ -273,11 +312,52 @@ class Batch:
         self.h = h
         self.max_sets = max_sets
         self.n_params = self.nets[0].n_params
+        self.n_nets = len(self.nets)
+        self.workspace = None
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.tn_batch_free(self.h)
             self.h = None
+
+    def workspace_bytes(self):
+        n = ctypes.c_int64()
+        _check(lib().tn_batch_workspace_bytes(self.h, ctypes.byref(n)))
+        return n.value
+
+    def bind_workspace(self, workspace=None):
+        """Bind a cuda uint8 tensor (allocated here when None) as the batch's
+        device workspace (tn_batch_set_workspace)."""
+        import torch
+        need = self.workspace_bytes()
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+        if workspace.dtype != torch.uint8 or not workspace.is_cuda or not workspace.is_contiguous() \
+                or workspace.numel() < need:
+            raise QtnError(TN_EINVAL, f"workspace must be a contiguous cuda uint8 tensor of at least {need} bytes")
+        _device_setup()
+        _check(lib().tn_batch_set_workspace(self.h, _dptr(workspace), workspace.numel()))
+        self.workspace = workspace
+
+    def _ready(self):
+        if self.workspace is None:
+            self.bind_workspace()
+
+    def _n_sets(self, params):
+        """Check params (cuda float64 [n_sets, n_params], contiguous) and return n_sets."""
+        if params.dim() != 2 or params.shape[1] != self.n_params:
+            raise QtnError(TN_EINVAL, f"params must be [n_sets, {self.n_params}], got {tuple(params.shape)}")
+        _need_f64(params, "params", params.numel())
+        n = params.shape[0]
+        if not 1 <= n <= self.max_sets:
+            raise QtnError(TN_EINVAL, f"n_sets {n} outside 1..{self.max_sets}")
+        return n
+
+    def _outs(self, n, out=None, obj=None, grad=None, grad_net=None):
+        _need_f64(out, "out", self.n_nets * n * 2)
+        _need_f64(obj, "obj", n)
+        _need_f64(grad, "grad", n * self.n_params)
+        _need_f64(grad_net, "grad_net", self.n_nets * n * self.n_params)
 
     def info(self):
         s = tn_batch_stats()
@@ -286,8 +366,10 @@ class Batch:
 
     def autotune(self, params, reps=3, cache_path=None, stream=None):
         """Pick fused workgroup size and MFMA/thin per large-op shape (tn_batch_autotune)."""
+        n = self._n_sets(params)
+        self._ready()
         cp = cache_path.encode() if cache_path else None
-        _check(lib().tn_batch_autotune(self.h, _dptr(params), params.shape[0], reps, cp, _stream(stream)))
+        _check(lib().tn_batch_autotune(self.h, _dptr(params), n, reps, cp, _stream(stream)))
 
     def set_precision(self, mfma_precision):
         """TN_MFMA_FP32 or TN_MFMA_BF16X3 (complex64 batch), TN_MFMA_FP64 (complex128 batch)."""
@@ -308,13 +390,34 @@ class Batch:
 
     def contract(self, params, out=None, obj=None, stream=None):
         """params: cuda float64 [n_sets, n_params]; out: [n_nets, n_sets, 2]; obj: [n_sets]."""
-        _check(lib().tn_batch_contract(self.h, _dptr(params), params.shape[0], _dptr(out), _dptr(obj),
-                                       _stream(stream)))
+        n = self._n_sets(params)
+        self._outs(n, out, obj)
+        self._ready()
+        _check(lib().tn_batch_contract(self.h, _dptr(params), n, _dptr(out), _dptr(obj), _stream(stream)))
 
     def grad(self, params, out=None, obj=None, grad=None, grad_net=None, stream=None):
-        _check(lib().tn_batch_grad(self.h, _dptr(params), params.shape[0], _dptr(out), _dptr(obj), _dptr(grad),
+        """As contract, plus grad: [n_sets, n_params], grad_net: [n_nets, n_sets, n_params]."""
+        n = self._n_sets(params)
+        self._outs(n, out, obj, grad, grad_net)
+        self._ready()
+        _check(lib().tn_batch_grad(self.h, _dptr(params), n, _dptr(out), _dptr(obj), _dptr(grad),
                                    _dptr(grad_net), _stream(stream)))
 
     def run_graph(self, with_grad, params, out=None, obj=None, grad=None, grad_net=None, stream=None):
-        _check(lib().tn_batch_run_graph(self.h, 1 if with_grad else 0, _dptr(params), params.shape[0], _dptr(out),
+        n = self._n_sets(params)
+        self._outs(n, out, obj, grad if with_grad else None, grad_net if with_grad else None)
+        self._ready()
+        _check(lib().tn_batch_run_graph(self.h, 1 if with_grad else 0, _dptr(params), n, _dptr(out),
                                         _dptr(obj), _dptr(grad), _dptr(grad_net), _stream(stream)))
+
+
+def _need_f64(t, name, numel):
+    """A device output or input: None, or a contiguous cuda float64 tensor of
+    at least `numel` entries."""
+    if t is None:
+        return
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() < numel:
+        raise QtnError(TN_EINVAL, f"{name} must be a contiguous cuda float64 tensor of at least {numel} entries "
+                                  f"(got {t.dtype}, {'cuda' if t.is_cuda else 'cpu'}, "
+                                  f"{'contiguous' if t.is_contiguous() else 'strided'}, {t.numel()})")

@@ -275,29 +275,31 @@ def _mixed_level_budget(qtn, qaoa, n, e, S, monkeypatch):
     for k in range(30, 8, -1):
         monkeypatch.setenv("QTN_LEVEL_BUDGET", str(1 << k))
         info = qaoa.MaxCut(n, e, 2, qtn.TN_C128, order="linegraph", max_sets=S).batch.info()
-        if info["n_level_bins"] >= 3 and best is None:  # packed groups (one group is split in two lanes)
+        if info["n_level_groups"] >= 2 and best is None:  # packed groups
             best = 1 << k
-        if info["n_level_bins"] >= 2 and info["n_level_chunked"] >= 1:
+        if info["n_level_groups"] >= 2 and info["n_level_chunked"] >= 1:
             return 1 << k
     return best
 
 
-def test_level_group_many_items(monkeypatch):
-    """Grouped level launches of more than 64 items (the workgroup-to-item
-    lookup scans 64 first-workgroup indices at a time): 150 light-cone
-    networks of a 3-regular n=100 graph, p=1, all on the level executor in
-    one group over two stream lanes (75 items per launch), against the p=1
+@pytest.mark.parametrize("mode", ["item", "task"])
+def test_level_group_many_items(mode, monkeypatch):
+    """A large level group: 150 light-cone networks of a 3-regular n=100
+    graph, p=1, all on the level executor in one group, run one launch per
+    item (item mode) or by the task executor (450 tasks), against the p=1
     closed form and its derivative on every edge and parameter vector."""
     qtn, qaoa = _qtn(), _qaoa()
     monkeypatch.setenv("QTN_FUSED_LDS_MAX", "0")
     monkeypatch.setenv("QTN_GMEM_MAX_MACS", "0")
+    monkeypatch.setenv("QTN_TASK_MIN", "1" if mode == "task" else "1000000000")
     n, S = 100, 3
     e = workloads.random_regular_graph(3, n, 0)
     ang = np.array(workloads.qaoa_angles(9, S, 1))
     nets = qaoa.edge_networks(n, e, 1, qtn.TN_C64, order="linegraph", trials=2)
     batch = qtn.Batch(nets, max_sets=S)
     info = batch.info()
-    assert info["n_level"] == len(e) and info["n_level_bins"] == 2 and info["n_level_chunked"] == 0
+    assert info["n_level"] == len(e) and info["n_level_groups"] == 1 and info["n_level_chunked"] == 0
+    assert info["n_level_tasked"] == (mode == "task")
     out = torch.empty((len(e), S, 2), dtype=torch.float64, device="cuda")
     gn = torch.empty((len(e), S, 2), dtype=torch.float64, device="cuda")
     _say(f"level group of {len(e)} networks, launches {info['level_launches_grad']}")
@@ -313,11 +315,10 @@ def test_level_group_many_items(monkeypatch):
 
 def test_level_executor_matches_fused(monkeypatch):
     """The same batch on the LDS fused executor, on the global-arena fused
-    executor and on the level executor: all networks stepped together in one
-    group (one launch per step and kind; the group is dealt over two stream
-    lanes that run concurrently), in several groups with some
-    networks run alone (arena budget lowered), and every network alone in
-    chunks of one parameter vector."""
+    executor and on the level executor: all networks in one group, stepped
+    together one launch per step (item mode) or run by the task executor, in
+    several groups with some networks run alone (arena budget lowered), and
+    every network alone in chunks of one parameter vector."""
     qtn, qaoa = _qtn(), _qaoa()
     n = 14
     e = workloads.random_regular_graph(3, n, 8)
@@ -330,10 +331,14 @@ def test_level_executor_matches_fused(monkeypatch):
     monkeypatch.setenv("QTN_GMEM_MAX_MACS", "0")
     mixed = _mixed_level_budget(qtn, qaoa, n, e, S, monkeypatch)
     assert mixed is not None
-    for mode, lim, gmem, budget in (("fused", str(160 * 1024), None, None), ("global", "0", None, None),
-                                    ("level", "0", "0", None), ("level-mixed", "0", "0", str(mixed)),
-                                    ("level-chunked", "0", "0", "1")):
-        for var, val in (("QTN_FUSED_LDS_MAX", lim), ("QTN_GMEM_MAX_MACS", gmem), ("QTN_LEVEL_BUDGET", budget)):
+    for mode, lim, gmem, budget, tmin in (("fused", str(160 * 1024), None, None, None),
+                                          ("global", "0", None, None, None), ("level", "0", "0", None, None),
+                                          ("level-task", "0", "0", None, "1"),
+                                          ("level-mixed", "0", "0", str(mixed), None),
+                                          ("level-mixed-task", "0", "0", str(mixed), "1"),
+                                          ("level-chunked", "0", "0", "1", None)):
+        for var, val in (("QTN_FUSED_LDS_MAX", lim), ("QTN_GMEM_MAX_MACS", gmem), ("QTN_LEVEL_BUDGET", budget),
+                         ("QTN_TASK_MIN", tmin)):
             if val is None:
                 monkeypatch.delenv(var, raising=False)
             else:
@@ -342,18 +347,20 @@ def test_level_executor_matches_fused(monkeypatch):
         info = model.batch.info()
         if mode.startswith("level"):
             assert info["n_level"] == len(e) and info["n_fused"] == 0 and info["n_global"] == 0
-        if mode == "level":
-            assert info["n_level_bins"] == 2 and info["n_level_chunked"] == 0  # one group, two stream lanes
-        if mode == "level-mixed":
-            assert info["n_level_bins"] >= 2
+        if mode in ("level", "level-task"):
+            assert info["n_level_groups"] == 1 and info["n_level_chunked"] == 0
+            assert info["n_level_tasked"] == (mode == "level-task")
+        if mode.startswith("level-mixed"):
+            assert info["n_level_groups"] >= 2
+            assert info["n_level_tasked"] == (info["n_level_groups"] if mode == "level-mixed-task" else 0)
         if mode == "level-chunked":
-            assert info["n_level_bins"] == 0 and info["n_level_chunked"] == len(e)
+            assert info["n_level_groups"] == 0 and info["n_level_chunked"] == len(e)
         if mode == "global":
             assert info["n_global"] == len(e) and info["n_fused"] == 0 and info["n_level"] == 0
         if mode == "fused":
             assert info["n_fused"] > 0
         _say(f"executor {mode} n_fused={info['n_fused']} n_global={info['n_global']} n_level={info['n_level']} "
-             f"bins={info['n_level_bins']} chunked={info['n_level_chunked']} launches={info['level_launches_grad']}")
+             f"groups={info['n_level_groups']} tasked={info['n_level_tasked']} chunked={info['n_level_chunked']} launches={info['level_launches_grad']}")
         obj, grad = model.value_and_grad(ang)
         torch.cuda.synchronize()
         res[mode] = (obj.cpu().numpy(), grad.cpu().numpy())
@@ -583,16 +590,20 @@ def test_split_summed_index(monkeypatch):
     assert abs(res[("0", qtn.TN_C128)][0] - res[("1024", qtn.TN_C128)][0]) < 1e-13
 
 
+@pytest.mark.parametrize("mode", ["item", "task"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_level_mfma_tile_shapes(prec, monkeypatch):
+def test_level_mfma_tile_shapes(prec, mode, monkeypatch):
     """Matrix-core products of every tile shape (64 x 64, and 16 x 64 / 64 x 16
-    where one free index has 2 to 5 bits, padded below 4), forward and adjoint, launched in
-    groups across the networks of a batch: 4-regular n=14 p=2 light-cone
-    networks on the level executor, complex64, against the state-vector cost
-    and the parameter-shift gradient."""
+    where one free index has 2 to 5 bits, padded below 4), forward and adjoint,
+    one launch per item over the networks of a group (item mode: products
+    spread over many workgroups) or within one workgroup's whole program (task
+    executor): 4-regular n=14 p=2 light-cone networks on the level executor,
+    complex64, against the state-vector cost and the parameter-shift
+    gradient."""
     qtn, qaoa = _qtn(), _qaoa()
     monkeypatch.setenv("QTN_FUSED_LDS_MAX", "0")
     monkeypatch.setenv("QTN_GMEM_MAX_MACS", "0")
+    monkeypatch.setenv("QTN_TASK_MIN", "1" if mode == "task" else "1000000000")
     n = 14
     e = workloads.random_regular_graph(4, n, 0)
     S = 3
@@ -610,8 +621,8 @@ def test_level_mfma_tile_shapes(prec, monkeypatch):
     assert shapes == {(64, 64), (16, 64), (64, 16)} and padded > 0
     model.batch.set_precision(qtn.TN_MFMA_FP32 if prec == "fp32" else qtn.TN_MFMA_BF16X3)
     info = model.batch.info()
-    assert info["n_level"] == len(e) and info["n_level_bins"] == 2
-    _say(f"level mfma tiles {prec} launches fwd={info['level_launches_fwd']} grad={info['level_launches_grad']}")
+    assert info["n_level"] == len(e) and info["n_level_groups"] == 1 and info["n_level_tasked"] == (mode == "task")
+    _say(f"level mfma tiles {prec} {mode} launches fwd={info['level_launches_fwd']} grad={info['level_launches_grad']}")
     obj, grad = model.value_and_grad(ang)
     torch.cuda.synchronize()
     obj, grad = obj.cpu().numpy(), grad.cpu().numpy()
@@ -622,16 +633,18 @@ def test_level_mfma_tile_shapes(prec, monkeypatch):
     assert err_c <= tol_c and err_g <= tol_g
 
 
-def test_level_mfma_fp64(monkeypatch):
+@pytest.mark.parametrize("mode", ["item", "task"])
+def test_level_mfma_fp64(mode, monkeypatch):
     """complex128 batches take their large steps on FP64 matrix-core products
     (64 x 64 tiles, FP64 accumulation): 4-regular n=14 p=2 light-cone networks
-    on the level executor, forward and adjoint, against the state-vector cost
-    (1e-12) and the parameter-shift gradient (1e-10). The precision is fixed
-    by the dtype: FP32 / split-BF16 are refused for complex128 and FP64 for
-    complex64."""
+    on the level executor (item mode and task executor), forward and adjoint,
+    against the state-vector cost (1e-12) and the parameter-shift gradient
+    (1e-10). The precision is fixed by the dtype: FP32 / split-BF16 are
+    refused for complex128 and FP64 for complex64."""
     qtn, qaoa = _qtn(), _qaoa()
     monkeypatch.setenv("QTN_FUSED_LDS_MAX", "0")
     monkeypatch.setenv("QTN_GMEM_MAX_MACS", "0")
+    monkeypatch.setenv("QTN_TASK_MIN", "1" if mode == "task" else "1000000000")
     n = 14
     e = workloads.random_regular_graph(4, n, 0)
     S = 3
@@ -702,3 +715,42 @@ def test_graph_replay_with_overlapping_executors(monkeypatch):
         o2, g2 = model.value_and_grad(ang)  # eager pass between replays
         torch.cuda.synchronize()
         assert np.array_equal(o2.cpu().numpy(), obj_e) and np.array_equal(g2.cpu().numpy(), grad_e)
+
+
+def test_task_executor_matches_item_mode(monkeypatch):
+    """The level executor's two launch modes on the same whole-circuit
+    networks: the task executor (one launch; a workgroup runs a whole
+    network program for one parameter vector) and item mode (one launch per
+    op, the op spread over the chip). Both match the p=1 closed form, forward
+    and gradient, for every parameter vector; more vectors than networks so
+    that tasks of one network run on several workgroups at once."""
+    qtn, qaoa = _qtn(), _qaoa()
+    monkeypatch.setenv("QTN_GMEM_MAX_MACS", "0")  # whole-circuit networks on the level executor
+    d, n, ns = 6, 12, 5
+    e = workloads.random_regular_graph(d, n, 0)
+    ang = np.array(workloads.qaoa_angles(3, ns, 1))
+    nets = []
+    for ed in e[:3]:
+        net = qaoa.edge_network(n, e, 1, ed, dtype=qtn.TN_C64, lightcone=False)
+        net.set_order(net.order_linegraph(trials=4, seed=0))
+        nets.append(net)
+    prm = torch.tensor(ang, device="cuda")
+    res = {}
+    for mode, task_min in (("task", "1"), ("item", "1000000000")):
+        monkeypatch.setenv("QTN_TASK_MIN", task_min)
+        batch = qtn.Batch(nets, max_sets=ns)
+        assert batch.info()["n_level"] == 3
+        out = torch.zeros((3, ns, 2), dtype=torch.float64, device="cuda")
+        gn = torch.zeros((3, ns, 2), dtype=torch.float64, device="cuda")
+        _say(f"level executor {mode} mode, 3 nets, {ns} sets")
+        batch.grad(prm, out=out, grad_net=gn)
+        torch.cuda.synchronize()
+        o, g = out.cpu().numpy(), gn.cpu().numpy()
+        for s in range(ns):
+            zz = closed_form.zz_p1(n, e, ang[s, 0], ang[s, 1])[:3]
+            dg, db = closed_form.zz_p1_grad(n, e, ang[s, 0], ang[s, 1])
+            assert np.max(np.abs(o[:, s, 0] - zz)) < 1e-5
+            assert np.max(np.abs(g[:, s, 0] - dg[:3])) <= 1e-4 * max(1.0, np.abs(dg[:3]).max())
+            assert np.max(np.abs(g[:, s, 1] - db[:3])) <= 1e-4 * max(1.0, np.abs(db[:3]).max())
+        res[mode] = (o, g)
+    assert np.max(np.abs(res["task"][0] - res["item"][0])) < 1e-5
