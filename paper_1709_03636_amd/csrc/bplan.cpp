@@ -963,7 +963,9 @@ int plan_batch(tn_net *const *nets, int n_nets, const double *coef, double offse
   // global-arena slots: one per resident workgroup, within the budget
   if (!b->gtask_net.empty()) {
     b->gstride = (std::max(b->hp.max_mem_g[0], b->hp.max_mem_g[1]) + 63) & ~int64_t(63);
-    b->gslots = (int)std::max<int64_t>(1, std::min<int64_t>(2048, kGmemBudget / (b->gstride * eb)));
+    // no more slots than tasks: a launch never runs more workgroups
+    const int64_t tasks = (int64_t)b->gtask_net.size() * max_sets;
+    b->gslots = (int)std::max<int64_t>(1, std::min<int64_t>({2048, kGmemBudget / (b->gstride * eb), tasks}));
   }
   // groups: level networks that take every parameter vector at once, packed
   // in order while their regions fit the level budget together
