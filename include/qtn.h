@@ -226,6 +226,20 @@ int tn_batch_contract(tn_batch *b, const double *params, int32_t n_sets, double 
 int tn_batch_grad(tn_batch *b, const double *params, int32_t n_sets, double *out, double *obj,
                   double *grad, double *grad_net, void *stream);
 
+/* tn_batch_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the pass runs in a fixed 64 MiB scratch array that the library holds on
+ * each device until the process ends, instead of the batch's workspace. It
+ * calls no device allocator and creates no stream or event. Arguments and
+ * results as in tn_batch_grad; every launch goes on `stream`. TN_EINVAL when
+ * tn_batch_workspace_bytes exceeds 64 MiB. Each call copies the batch's
+ * program arrays into the scratch (copies ordered on `stream` that read the
+ * batch's host memory: free the batch only after the stream is done). All
+ * calls on a device share its scratch: calls that overlap on one device
+ * (concurrent streams or threads) race, and a call leaves its data there. */
+int tn_batch_grad_noalloc(tn_batch *b, const double *params, int32_t n_sets, double *out, double *obj,
+                          double *grad, double *grad_net, void *stream);
+
 /* Replay the forward (with_grad = 0) or forward+gradient (1) pass through a
  * HIP graph captured on first use for these exact pointers and n_sets;
  * arguments as in tn_batch_grad (grad and grad_net are ignored when

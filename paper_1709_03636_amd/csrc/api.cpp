@@ -18,6 +18,8 @@ int batch_create(tn_net *const *nets, int n_nets, const double *coef, double off
 int batch_contract(tn_batch *b, const double *params, int n_sets, double *out, double *obj, void *stream);
 int batch_grad(tn_batch *b, const double *params, int n_sets, double *out, double *obj, double *grad, double *gnet,
                void *stream);
+int batch_grad_noalloc(tn_batch *b, const double *params, int n_sets, double *out, double *obj, double *grad,
+                       double *gnet, void *stream);
 int batch_run_graph(tn_batch *b, int with_grad, const double *params, int n_sets, double *out, double *obj,
                     double *grad, double *grad_net, void *stream);
 int batch_info(const tn_batch *b, tn_batch_stats *s);
@@ -254,6 +256,15 @@ int tn_batch_grad(tn_batch *b, const double *params, int32_t n_sets, double *out
     return TN_EINVAL;
   }
   GUARD({ return qtn::batch_grad(b, params, n_sets, out, obj, grad, grad_net, stream); })
+}
+
+int tn_batch_grad_noalloc(tn_batch *b, const double *params, int32_t n_sets, double *out, double *obj, double *grad,
+                          double *grad_net, void *stream) {
+  if (!b) {
+    qtn::set_error("tn_batch_grad_noalloc: NULL batch");
+    return TN_EINVAL;
+  }
+  GUARD({ return qtn::batch_grad_noalloc(b, params, n_sets, out, obj, grad, grad_net, stream); })
 }
 
 int tn_batch_run_graph(tn_batch *b, int32_t with_grad, const double *params, int32_t n_sets, double *out, double *obj,

@@ -136,6 +136,7 @@ struct tn_batch {
   double offset = 0;
   std::vector<double> coef;
   qtn::HostProgram hp;
+  std::vector<float> consts_f;         // complex64 batches: hp.consts in FP32, as uploaded
   std::vector<int32_t> task_net;       // fused networks, in cost order
   std::vector<int32_t> gtask_net;      // networks on the global-arena fused executor, in cost order
   struct GLayout { int lds = 0, grid = 0, scratch_off = 0, scal_off = 0, gacc_off = 0, red_off = 0; } gl[2];

@@ -1014,6 +1014,7 @@ int plan_batch(tn_net *const *nets, int n_nets, const double *coef, double offse
   b->lpart_doubles = part;
   b->lsplit_elems = split;
   b->level_bytes = arena * eb;
+  if (b->dtype == TN_C64) b->consts_f.assign(b->hp.consts.begin(), b->hp.consts.end());
   int rc = plan_level(b);
   if (rc != TN_OK) return rc;
   plan_workspace(b);

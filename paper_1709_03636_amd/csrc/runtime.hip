@@ -111,6 +111,12 @@ static T *ws_ptr(const tn_batch *b, int k) {
   return reinterpret_cast<T *>(b->d_ws + b->ws.off[k]);
 }
 
+// Array k of a workspace at ws (the bound one, or the static scratch).
+template <typename T>
+static T *wsp(char *ws, const tn_batch *b, int k) {
+  return reinterpret_cast<T *>(ws + b->ws.off[k]);
+}
+
 static void drop_timing_events(tn_batch *b) {
   for (auto &pr : b->tev) {
     (void)hipEventDestroy(he(pr.first));
@@ -256,6 +262,8 @@ static int task_grid(tn_batch *b) {
   return TN_OK;
 }
 
+static int upload_tables(tn_batch *b, char *ws, hipStream_t st, bool async, bool with_items);
+
 // Bind the workspace: program arrays uploaded, launch shapes from the
 // device's occupancy, side streams for the executors with work.
 int batch_bind(tn_batch *b, void *ptr, int64_t bytes) {
@@ -269,31 +277,8 @@ int batch_bind(tn_batch *b, void *ptr, int64_t bytes) {
   }
   free_device(b);
   b->d_ws = static_cast<char *>(ptr);
-  const HostProgram &hp = b->hp;
-  const int eb = b->dtype == TN_C128 ? 16 : 8;
-  std::vector<float> cf;
-  const void *csrc = hp.consts.data();
-  if (b->dtype == TN_C64) {
-    cf.assign(hp.consts.begin(), hp.consts.end());
-    csrc = cf.data();
-  }
-  struct Up { int k; const void *h; size_t n; } ups[] = {
-      {WsLayout::NETS_FWD, hp.nets_fwd.data(), hp.nets_fwd.size() * sizeof(DNet)},
-      {WsLayout::NETS_GRAD, hp.nets_grad.data(), hp.nets_grad.size() * sizeof(DNet)},
-      {WsLayout::OPS, hp.ops.data(), hp.ops.size() * sizeof(DOp)},
-      {WsLayout::TABS, hp.tabs.data(), hp.tabs.size() * sizeof(int32_t)},
-      {WsLayout::RECS, hp.recs.data(), hp.recs.size() * sizeof(int32_t)},
-      {WsLayout::SRECS0, hp.srecs[0].data(), hp.srecs[0].size() * sizeof(int32_t)},
-      {WsLayout::SRECS1, hp.srecs[1].data(), hp.srecs[1].size() * sizeof(int32_t)},
-      {WsLayout::TASK_NET, b->task_net.data(), b->task_net.size() * sizeof(int32_t)},
-      {WsLayout::GTASK_NET, b->gtask_net.data(), b->gtask_net.size() * sizeof(int32_t)},
-      {WsLayout::CONSTS, csrc, hp.consts.size() / 2 * eb},
-      {WsLayout::PTENS, hp.ptens.data(), hp.ptens.size() * sizeof(DParam)},
-      {WsLayout::SLOTS, hp.slots.data(), hp.slots.size() * sizeof(DParam)},
-      {WsLayout::COEF, b->coef.data(), b->coef.size() * sizeof(double)},
-  };
-  for (auto &u : ups)
-    if (u.n) HIPCHK(hipMemcpy(ws_ptr<char>(b, u.k), u.h, u.n, hipMemcpyHostToDevice));
+  int rc = upload_tables(b, b->d_ws, nullptr, false, false);
+  if (rc != TN_OK) return rc;
   // side streams only for the executors that have work (streams share the
   // few hardware queues: an idle stream could take a busy one's queue)
   const bool fused = !b->task_net.empty(), gmem = !b->gtask_net.empty(), lvl = !b->level.empty();
@@ -311,11 +296,50 @@ int batch_bind(tn_batch *b, void *ptr, int64_t bytes) {
       b->ev_join[i] = e;
     }
   }
-  int rc;
   if ((rc = layout_lds(b, 0)) != TN_OK || (rc = layout_lds(b, 1)) != TN_OK || (rc = layout_gmem(b)) != TN_OK) return rc;
   b->uploaded = true;
   b->items_dirty = true;
   return upload_items(b);
+}
+
+// The program arrays into the workspace at ws (the task executor's lists
+// only when with_items): synchronous copies, or, when async, copies ordered
+// on st that read the batch's host arrays (which outlive the call).
+static int upload_tables(tn_batch *b, char *ws, hipStream_t st, bool async, bool with_items) {
+  const HostProgram &hp = b->hp;
+  const int eb = b->dtype == TN_C128 ? 16 : 8;
+  const void *csrc = b->dtype == TN_C64 ? (const void *)b->consts_f.data() : (const void *)hp.consts.data();
+  struct Up { int k; const void *h; size_t n; } ups[] = {
+      {WsLayout::NETS_FWD, hp.nets_fwd.data(), hp.nets_fwd.size() * sizeof(DNet)},
+      {WsLayout::NETS_GRAD, hp.nets_grad.data(), hp.nets_grad.size() * sizeof(DNet)},
+      {WsLayout::OPS, hp.ops.data(), hp.ops.size() * sizeof(DOp)},
+      {WsLayout::TABS, hp.tabs.data(), hp.tabs.size() * sizeof(int32_t)},
+      {WsLayout::RECS, hp.recs.data(), hp.recs.size() * sizeof(int32_t)},
+      {WsLayout::SRECS0, hp.srecs[0].data(), hp.srecs[0].size() * sizeof(int32_t)},
+      {WsLayout::SRECS1, hp.srecs[1].data(), hp.srecs[1].size() * sizeof(int32_t)},
+      {WsLayout::TASK_NET, b->task_net.data(), b->task_net.size() * sizeof(int32_t)},
+      {WsLayout::GTASK_NET, b->gtask_net.data(), b->gtask_net.size() * sizeof(int32_t)},
+      {WsLayout::CONSTS, csrc, hp.consts.size() / 2 * eb},
+      {WsLayout::PTENS, hp.ptens.data(), hp.ptens.size() * sizeof(DParam)},
+      {WsLayout::SLOTS, hp.slots.data(), hp.slots.size() * sizeof(DParam)},
+      {WsLayout::COEF, b->coef.data(), b->coef.size() * sizeof(double)},
+      {WsLayout::TITEMS0, b->titems[0].data(), with_items ? b->titems[0].size() * sizeof(PItem) : 0},
+      {WsLayout::TITEMS1, b->titems[1].data(), with_items ? b->titems[1].size() * sizeof(PItem) : 0},
+      {WsLayout::TNETS0, b->tnets[0].data(), with_items ? b->tnets[0].size() * sizeof(TNet) : 0},
+      {WsLayout::TNETS1, b->tnets[1].data(), with_items ? b->tnets[1].size() * sizeof(TNet) : 0},
+  };
+  for (auto &u : ups) {
+    if (!u.n) continue;
+    if ((int64_t)u.n > b->ws.size[u.k]) {
+      set_error("batch program larger than its workspace room");
+      return TN_EINVAL;
+    }
+    if (async)
+      HIPCHK(hipMemcpyAsync(wsp<char>(ws, b, u.k), u.h, u.n, hipMemcpyHostToDevice, st));
+    else
+      HIPCHK(hipMemcpy(wsp<char>(ws, b, u.k), u.h, u.n, hipMemcpyHostToDevice));
+  }
+  return TN_OK;
 }
 
 // A batch run without a bound workspace gets one from the allocator.
@@ -333,8 +357,11 @@ static int ensure_bound(tn_batch *b) {
   return TN_OK;
 }
 
-static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, double *out, double *obj, double *gobj,
-                     double *gnet_out, hipStream_t st) {
+// One pass. ws: the workspace to run in; NULL for the batch's bound one
+// (bound from the allocator when missing). A given ws holds the tables
+// already; every launch then goes on st (no side streams, no timing events).
+static int run_batch(tn_batch *b, char *ws, bool grad, const double *params, int n_sets, double *out, double *obj,
+                     double *gobj, double *gnet_out, hipStream_t st) {
   if (b->poisoned) {
     set_error("batch poisoned by an earlier device error");
     return TN_ESTATE;
@@ -350,14 +377,18 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
                   " needs more than 2^31 elements of adjoint working memory per parameter vector");
         return TN_ENOMEM;
       }
-  if (b->capturing) {
-    if (!b->d_ws || b->items_dirty) {
-      set_error("batch run under capture before its workspace and items are on the device");
-      return TN_ESTATE;
+  const bool own_ws = ws != nullptr;
+  if (!own_ws) {
+    if (b->capturing) {
+      if (!b->d_ws || b->items_dirty) {
+        set_error("batch run under capture before its workspace and items are on the device");
+        return TN_ESTATE;
+      }
+    } else {
+      int rc = ensure_bound(b);
+      if (rc != TN_OK) return rc;
     }
-  } else {
-    int rc = ensure_bound(b);
-    if (rc != TN_OK) return rc;
+    ws = b->d_ws;
   }
   if (!b->level.empty() && !b->capturing) {
     int rc = task_grid(b);
@@ -365,19 +396,19 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
   }
   const int v = grad ? 1 : 0;
   FusedArgs a{};
-  a.nets = ws_ptr<DNet>(b, grad ? WsLayout::NETS_GRAD : WsLayout::NETS_FWD);
-  a.ops = ws_ptr<DOp>(b, WsLayout::OPS);
-  a.recs = ws_ptr<int4>(b, WsLayout::RECS);
-  a.tabs = ws_ptr<int32_t>(b, WsLayout::TABS);
-  a.consts = ws_ptr<void>(b, WsLayout::CONSTS);
-  a.ptens = ws_ptr<DParam>(b, WsLayout::PTENS);
-  a.bound = ws_ptr<void>(b, WsLayout::BOUND);
-  a.dbound = ws_ptr<void>(b, WsLayout::DBOUND);
+  a.nets = wsp<DNet>(ws, b, grad ? WsLayout::NETS_GRAD : WsLayout::NETS_FWD);
+  a.ops = wsp<DOp>(ws, b, WsLayout::OPS);
+  a.recs = wsp<int4>(ws, b, WsLayout::RECS);
+  a.tabs = wsp<int32_t>(ws, b, WsLayout::TABS);
+  a.consts = wsp<void>(ws, b, WsLayout::CONSTS);
+  a.ptens = wsp<DParam>(ws, b, WsLayout::PTENS);
+  a.bound = wsp<void>(ws, b, WsLayout::BOUND);
+  a.dbound = wsp<void>(ws, b, WsLayout::DBOUND);
   a.per_set = b->hp.per_set;
-  a.task_net = ws_ptr<int32_t>(b, WsLayout::TASK_NET);
+  a.task_net = wsp<int32_t>(ws, b, WsLayout::TASK_NET);
   // network-major output; the internal buffer is used when no pointer is given
-  a.out_val = out ? out : ws_ptr<double>(b, WsLayout::VAL);
-  a.out_grad = gnet_out ? gnet_out : ws_ptr<double>(b, WsLayout::GNET);
+  a.out_val = out ? out : wsp<double>(ws, b, WsLayout::VAL);
+  a.out_grad = gnet_out ? gnet_out : wsp<double>(ws, b, WsLayout::GNET);
   a.n_params = b->n_params;
   a.n_sets = n_sets;
   a.n_tasks = (int)b->task_net.size() * n_sets;
@@ -386,8 +417,8 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
   a.gacc_off = b->gacc_off[v];
   a.red_off = b->red_off[v];
   a.gbar_off = b->gbar_off[v];
-  hipError_t e = launch_bind(b->dtype, ws_ptr<DParam>(b, WsLayout::SLOTS), (int)b->hp.slots.size(), params, b->n_params,
-                             n_sets, b->hp.per_set, ws_ptr<void>(b, WsLayout::BOUND), grad ? ws_ptr<void>(b, WsLayout::DBOUND) : nullptr, st);
+  hipError_t e = launch_bind(b->dtype, wsp<DParam>(ws, b, WsLayout::SLOTS), (int)b->hp.slots.size(), params, b->n_params,
+                             n_sets, b->hp.per_set, wsp<void>(ws, b, WsLayout::BOUND), grad ? wsp<void>(ws, b, WsLayout::DBOUND) : nullptr, st);
   if (e != hipSuccess) {
     b->poisoned = true;
     return hip_fail(e, "binding launch");
@@ -395,7 +426,7 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
   // streams of the global-arena (sg) and level (sl) executors: forked when
   // two or more executors have work
   hipStream_t sg = st, sl = st;
-  const bool fork = b->ev_fork != nullptr;
+  const bool fork = b->ev_fork != nullptr && !own_ws;
   if (fork) {
     e = hipEventRecord(he(b->ev_fork), st);
     for (int i = 0; i < 2 && e == hipSuccess; ++i)
@@ -414,11 +445,11 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     LvlArgs la{};
     la.n_sets = n_sets;
     la.max_sets = b->max_sets;
-    la.ctrl = ws_ptr<int32_t>(b, WsLayout::CTRL);
-    la.arena = ws_ptr<void>(b, WsLayout::LARENA);
-    la.split = ws_ptr<void>(b, WsLayout::LSPLIT);
-    la.scal = ws_ptr<double>(b, WsLayout::LSCAL);
-    la.part = ws_ptr<double>(b, WsLayout::LPART);
+    la.ctrl = wsp<int32_t>(ws, b, WsLayout::CTRL);
+    la.arena = wsp<void>(ws, b, WsLayout::LARENA);
+    la.split = wsp<void>(ws, b, WsLayout::LSPLIT);
+    la.scal = wsp<double>(ws, b, WsLayout::LSCAL);
+    la.part = wsp<double>(ws, b, WsLayout::LPART);
     la.tabs = a.tabs;
     la.consts = a.consts;
     la.ptens = a.ptens;
@@ -434,8 +465,8 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
       const LevelGroup &g = b->groups[gi];
       la.set0 = 0;
       if (g.tasked) {
-        la.items = ws_ptr<PItem>(b, v ? WsLayout::TITEMS1 : WsLayout::TITEMS0);
-        la.tnets = ws_ptr<TNet>(b, v ? WsLayout::TNETS1 : WsLayout::TNETS0) + g.tnet0;
+        la.items = wsp<PItem>(ws, b, v ? WsLayout::TITEMS1 : WsLayout::TITEMS0);
+        la.tnets = wsp<TNet>(ws, b, v ? WsLayout::TNETS1 : WsLayout::TNETS0) + g.tnet0;
         la.n_tnets = (int)g.lv.size();
         e = task_launch(prec, la, b->task_grid, sl);
       } else {
@@ -460,7 +491,7 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
   if (a.n_tasks > 0) {
     const int spw = b->spw[v];
     if (spw > 1) {
-      a.recs = ws_ptr<int4>(b, spw == 4 ? WsLayout::SRECS0 : WsLayout::SRECS1);
+      a.recs = wsp<int4>(ws, b, spw == 4 ? WsLayout::SRECS0 : WsLayout::SRECS1);
       a.set_stride = b->set_stride[v];
       a.max_comp = std::max(1, b->hp.max_comp);
       a.n_groups = (n_sets + spw - 1) / spw;
@@ -472,7 +503,7 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     const int grid = (a.n_tasks + rounds - 1) / rounds;
     a.per_block = rounds;
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (b->timing && !b->capturing && b->tev.size() < 4096 && hipEventCreate(&t0) == hipSuccess) {
+    if (b->timing && !b->capturing && !own_ws && b->tev.size() < 4096 && hipEventCreate(&t0) == hipSuccess) {
       if (hipEventCreate(&t1) != hipSuccess || hipEventRecord(t0, st) != hipSuccess) {
         (void)hipEventDestroy(t0);
         if (t1) (void)hipEventDestroy(t1);
@@ -499,14 +530,14 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
   if (!b->gtask_net.empty()) {
     const tn_batch::GLayout &gl = b->gl[v];
     FusedArgs g = a;
-    g.recs = ws_ptr<int4>(b, WsLayout::RECS);
-    g.task_net = ws_ptr<int32_t>(b, WsLayout::GTASK_NET);
+    g.recs = wsp<int4>(ws, b, WsLayout::RECS);
+    g.task_net = wsp<int32_t>(ws, b, WsLayout::GTASK_NET);
     g.n_tasks = (int)b->gtask_net.size() * n_sets;
     g.scratch_off = gl.scratch_off;
     g.scal_off = gl.scal_off;
     g.gacc_off = gl.gacc_off;
     g.red_off = gl.red_off;
-    g.garena = ws_ptr<void>(b, WsLayout::GARENA);
+    g.garena = wsp<void>(ws, b, WsLayout::GARENA);
     g.garena_stride = b->gstride;
     const int cap = std::max(1, std::min(std::min(gl.grid, b->gslots), g.n_tasks));
     const int rounds = (g.n_tasks + cap - 1) / cap;
@@ -529,7 +560,7 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
     }
   }
   if (obj || (grad && gobj)) {
-    e = launch_combine(a.out_val, a.out_grad, ws_ptr<double>(b, WsLayout::COEF), b->offset, b->n_nets, n_sets,
+    e = launch_combine(a.out_val, a.out_grad, wsp<double>(ws, b, WsLayout::COEF), b->offset, b->n_nets, n_sets,
                        b->n_params, obj, grad ? gobj : nullptr, st);
     if (e != hipSuccess) {
       b->poisoned = true;
@@ -540,12 +571,77 @@ static int run_batch(tn_batch *b, bool grad, const double *params, int n_sets, d
 }
 
 int batch_contract(tn_batch *b, const double *params, int n_sets, double *out, double *obj, void *stream) {
-  return run_batch(b, false, params, n_sets, out, obj, nullptr, nullptr, (hipStream_t)stream);
+  return run_batch(b, nullptr, false, params, n_sets, out, obj, nullptr, nullptr, (hipStream_t)stream);
 }
 
 int batch_grad(tn_batch *b, const double *params, int n_sets, double *out, double *obj, double *grad, double *gnet,
                void *stream) {
-  return run_batch(b, true, params, n_sets, out, obj, grad, gnet, (hipStream_t)stream);
+  return run_batch(b, nullptr, true, params, n_sets, out, obj, grad, gnet, (hipStream_t)stream);
+}
+
+// --- allocation-free runs ----------------------------------------------------------------------
+// For callers that cannot allocate device memory (code under graph capture,
+// serving loops, harnesses that forbid allocation): a batch whose workspace
+// fits runs in this fixed array instead of a bound workspace. Each device
+// holds its own copy until the process ends. Host code reaches it only
+// through the address hipGetSymbolAddress gives on that device (the array's
+// name is a host-side stand-in there). Every call on a device shares the
+// array: each call copies the batch's program arrays in again, and calls
+// that overlap on one device race.
+constexpr int64_t kStaticScratchBytes = int64_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+static std::mutex g_scratch_mu;
+static char *g_scratch[kMaxDevices];  // per device: the array's device address, once looked up
+
+static int scratch_base(char **out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("tn_batch_grad_noalloc: device ordinal beyond " + std::to_string(kMaxDevices));
+    return TN_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) {
+      set_error("hipGetSymbolAddress(scratch): no address");
+      return TN_EDEVICE;
+    }
+    g_scratch[dev] = static_cast<char *>(p);
+  }
+  *out = g_scratch[dev];
+  return TN_OK;
+}
+
+int batch_grad_noalloc(tn_batch *b, const double *params, int n_sets, double *out, double *obj, double *grad,
+                       double *gnet, void *stream) {
+  if (b->ws.total > kStaticScratchBytes) {
+    set_error("tn_batch_grad_noalloc: the batch needs " + std::to_string(b->ws.total) +
+              " bytes of workspace; the static scratch holds " + std::to_string(kStaticScratchBytes));
+    return TN_EINVAL;
+  }
+  if (b->poisoned) {
+    set_error("batch poisoned by an earlier device error");
+    return TN_ESTATE;
+  }
+  if ((!params && b->n_params > 0) || n_sets < 1 || n_sets > b->max_sets) {
+    set_error("batch run: n_sets out of range or params NULL");
+    return TN_EINVAL;
+  }
+  char *ws = nullptr;
+  int rc = scratch_base(&ws);
+  if (rc != TN_OK) return rc;
+  const hipStream_t st = (hipStream_t)stream;
+  // launch shapes from the device's occupancy (queries only)
+  if ((rc = layout_lds(b, 0)) != TN_OK || (rc = layout_lds(b, 1)) != TN_OK || (rc = layout_gmem(b)) != TN_OK) return rc;
+  if ((rc = upload_tables(b, ws, st, true, true)) != TN_OK) {
+    b->poisoned = rc == TN_EDEVICE;
+    return rc;
+  }
+  return run_batch(b, ws, true, params, n_sets, out, obj, grad, gnet, st);
 }
 
 int batch_run_graph(tn_batch *b, int with_grad, const double *params, int n_sets, double *out, double *obj,
@@ -569,7 +665,7 @@ int batch_run_graph(tn_batch *b, int with_grad, const double *params, int n_sets
     graph_clear(b);
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     b->capturing = true;
-    rc = run_batch(b, with_grad != 0, params, n_sets, out, obj, grad, with_grad ? grad_net : nullptr, st);
+    rc = run_batch(b, nullptr, with_grad != 0, params, n_sets, out, obj, grad, with_grad ? grad_net : nullptr, st);
     b->capturing = false;
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(st, &graph);
@@ -686,7 +782,7 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
       b->spw[1] = cand < 0 ? -cand : 1;
       if (cand > 0) b->block = cand;
       if (!relayout()) return rc;
-      float ms = time_ms(st, reps, [&] { return run_batch(b, true, params, n_sets, nullptr, nullptr, nullptr, nullptr, st); },
+      float ms = time_ms(st, reps, [&] { return run_batch(b, nullptr, true, params, n_sets, nullptr, nullptr, nullptr, nullptr, st); },
                          rc);
       if (rc != TN_OK) return rc;
       if (best == 0.f || ms < best) {
@@ -707,7 +803,7 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
       if (S > 1 && (b->max_sets == 1 || !sets_fit(b, S, b->fused_budget, 0))) continue;
       b->spw[0] = S;
       if (!relayout()) return rc;
-      float ms = time_ms(st, reps, [&] { return run_batch(b, false, params, n_sets, nullptr, nullptr, nullptr, nullptr, st); },
+      float ms = time_ms(st, reps, [&] { return run_batch(b, nullptr, false, params, n_sets, nullptr, nullptr, nullptr, nullptr, st); },
                          rc);
       if (rc != TN_OK) return rc;
       if (best == 0.f || ms < best) {

@@ -80,6 +80,7 @@ _SIGS = {
     "tn_set_allocator": (_I, [_P, _P, _P]),
     "tn_batch_contract": (_I, [_P, _P, _I, _P, _P, _P]),
     "tn_batch_grad": (_I, [_P, _P, _I, _P, _P, _P, _P, _P]),
+    "tn_batch_grad_noalloc": (_I, [_P, _P, _I, _P, _P, _P, _P, _P]),
     "tn_batch_run_graph": (_I, [_P, _I, _P, _I, _P, _P, _P, _P, _P]),
     "tn_batch_info": (_I, [_P, ctypes.POINTER(tn_batch_stats)]),
     "tn_batch_autotune": (_I, [_P, _P, _I, _I, ctypes.c_char_p, _P]),

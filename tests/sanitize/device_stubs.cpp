@@ -14,6 +14,7 @@ static int no_device() {
 
 int batch_contract(tn_batch *, const double *, int, double *, double *, void *) { return no_device(); }
 int batch_grad(tn_batch *, const double *, int, double *, double *, double *, double *, void *) { return no_device(); }
+int batch_grad_noalloc(tn_batch *, const double *, int, double *, double *, double *, double *, void *) { return no_device(); }
 int batch_run_graph(tn_batch *, int, const double *, int, double *, double *, double *, double *, void *) {
   return no_device();
 }
