@@ -292,15 +292,23 @@ int tn_batch_set_precision(tn_batch *b, int32_t mfma_precision);
 /* Apply decisions from an autotuner cache file without timing. */
 int tn_batch_apply_tuning(tn_batch *b, const char *cache_path);
 
+/* Executors of a batch, for kernel timing. */
+enum {
+  TN_EXEC_FUSED = 0,  /* the LDS fused executor's launch */
+  TN_EXEC_LEVEL = 1,  /* per level group: the task executor's launch, or the group's item launches */
+  TN_EXEC_GLOBAL = 2  /* the global-arena fused executor's launch */
+};
+
 /* Kernel timing (profiling aid, not in the paper). With enable = 1, every
  * later eager tn_batch_contract / tn_batch_grad records a pair of HIP events
- * on its stream around the fused-executor launch (at most 4096 pending
- * pairs; graph captures record none). tn_batch_kernel_time waits for those
- * events, returns how many launches were timed and their summed duration in
- * milliseconds, and forgets them. enable = 0 stops recording and drops
- * pending pairs. */
+ * around each executor launch, on the stream that launch goes on (at most
+ * 4096 pending pairs per executor; graph captures and
+ * tn_batch_grad_noalloc record none). tn_batch_kernel_time waits for one
+ * executor's events, returns how many launches were timed and their summed
+ * duration in milliseconds, and forgets them. enable = 0 stops recording and
+ * drops pending pairs. */
 int tn_batch_kernel_timing(tn_batch *b, int32_t enable);
-int tn_batch_kernel_time(tn_batch *b, int32_t *n_launches, double *total_ms);
+int tn_batch_kernel_time(tn_batch *b, int32_t executor, int32_t *n_launches, double *total_ms);
 
 /* One-shot conveniences: create a transient batch, run, free. Device pointers. */
 int tn_contract_batch(tn_net *const *nets, int32_t n_nets, const double *params, int32_t n_sets,

@@ -30,7 +30,7 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
 int batch_apply_cache(tn_batch *b, const char *cache_path);
 int batch_set_precision(tn_batch *b, int prec);
 int batch_kernel_timing(tn_batch *b, int enable);
-int batch_kernel_time(tn_batch *b, int *n, double *total_ms);
+int batch_kernel_time(tn_batch *b, int kind, int *n, double *total_ms);
 void batch_free(tn_batch *b);
 int net_contract(Net &net, const double *params, double *out, double *value, double *grad, void *stream);
 int net_bind(Net &net, const double *params, int n_sets, void *dst, int64_t *per_set, void *stream);
@@ -301,13 +301,13 @@ int tn_batch_kernel_timing(tn_batch *b, int32_t enable) {
   return qtn::batch_kernel_timing(b, enable);
 }
 
-int tn_batch_kernel_time(tn_batch *b, int32_t *n_launches, double *total_ms) {
+int tn_batch_kernel_time(tn_batch *b, int32_t executor, int32_t *n_launches, double *total_ms) {
   if (!b || !n_launches || !total_ms) {
     qtn::set_error("tn_batch_kernel_time: NULL argument");
     return TN_EINVAL;
   }
   int n = 0;
-  const int rc = qtn::batch_kernel_time(b, &n, total_ms);
+  const int rc = qtn::batch_kernel_time(b, executor, &n, total_ms);
   *n_launches = n;
   return rc;
 }

@@ -95,6 +95,7 @@ struct LevelNet {
   int const_begin = 0, n_const = 0;             // into HostProgram::consts (elements)
   int ptens_begin = 0, n_ptens = 0;             // into HostProgram::ptens (absolute offsets)
   int64_t gbar_begin = 0, ptens_elems = 0;      // adjoint accumulators (variant 1)
+  int64_t leaf_region = 0;                      // constants and parametric tensors: region [0, leaf_region)
   int chunk = 1;                                // parameter vectors per pass
   bool grad_ok = true;                          // the adjoint arena is addressable (< 2^31 elements)
   double cost = 0;                              // flops of forward + adjoint, one parameter vector
@@ -175,7 +176,7 @@ struct tn_batch {
   // stream after binding and joined before the combine
   void *side[2] = {nullptr, nullptr};
   void *ev_fork = nullptr, *ev_join[2] = {nullptr, nullptr};
-  std::vector<std::pair<void *, void *>> tev;  // timing event pairs
+  std::vector<std::pair<void *, void *>> tev[3];  // timing event pairs per executor (fused, level, global)
   struct GraphCache {
     void *exec = nullptr, *graph = nullptr;
     int with_grad = -1, n_sets = -1;
@@ -196,7 +197,9 @@ struct ItemCtx {
   bool all_thin = false;
   bool one_wg = false;  // items for one workgroup and one vector (task executor): no split sums, one
                         // workgroup per rank-0 sum and set-up
+  int lds_elems = 0;    // one_wg: elements of the workgroup's LDS arena for small tensors (0: none)
   const std::vector<DOp> *ops = nullptr;
+  const std::vector<int32_t> *tabs = nullptr;
 };
 
 // bplan.cpp

@@ -4,7 +4,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <array>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <numeric>
 
@@ -540,6 +542,7 @@ static LevelNet append_level(const Net &net, const NetLayout &lay, HostProgram &
   ln.stride[0] = lay.leaf_region + lay.arena[0];
   ln.gbar_begin = lay.leaf_region + lay.arena[1];
   ln.ptens_elems = lay.ptens_elems;
+  ln.leaf_region = lay.leaf_region;
   ln.stride[1] = ln.gbar_begin + lay.ptens_elems;
   for (int v = 0; v < 2; ++v) ln.stride[v] = (ln.stride[v] + 63) & ~int64_t(63);
   ln.ptens_begin = (int)hp.ptens.size();
@@ -631,7 +634,135 @@ ItemCtx item_ctx(const tn_batch *b) {
   c.split_target = b->split_target;
   c.use_mfma = &b->use_mfma;
   c.ops = &b->hp.ops;
+  c.tabs = &b->hp.tabs;
   return c;
+}
+
+// --- LDS residency of the task executor -------------------------------------------------------
+
+// Which tensors of one network program (variant v) a task-executor
+// workgroup keeps in its LDS arena of c.lds_elems elements, per op: a0 flags
+// (kLdsX / kLdsY / kLdsZ) and the LDS element offsets of those operands.
+// The leaf region is mirrored to LDS [0, leaf region) when it takes at most
+// half the arena. An intermediate is a candidate when every op that writes
+// or reads it runs on the vector units (a thin contraction, or a leaf
+// adjoint reading it); the matrix-core tiles, rank-0 sums and seeds read and
+// write global memory. Candidates take arena space first-fit when written
+// and give it back after their last read; one that does not fit stays in
+// the region. Tensors are told apart by their region offset (a write at an
+// offset starts a new tensor there).
+struct LdsOp {
+  int32_t flags = 0, x = 0, y = 0, z = 0;
+};
+
+static bool lds_mirror(const ItemCtx &c, const LevelNet &ln) {
+  return c.one_wg && c.lds_elems > 0 && ln.leaf_region > 0 && 2 * ln.leaf_region <= c.lds_elems;
+}
+
+static std::vector<LdsOp> lds_assign(const ItemCtx &c, const LevelNet &ln, int v) {
+  const int n = ln.n_ops[v];
+  std::vector<LdsOp> res(n);
+  if (!c.one_wg || c.lds_elems <= 0) return res;
+  const bool mirror = lds_mirror(c, ln);
+  const int64_t leaf = ln.leaf_region;
+  struct Inst {
+    int64_t off, size;
+    int last = -1;
+    bool banned = false;
+    int64_t lds = -1;
+  };
+  std::vector<Inst> inst;
+  std::map<int64_t, int> cur;  // region offset -> current tensor there
+  std::vector<std::array<int, 3>> uses(n, {-1, -1, -1});  // tensors read as X, Y and written as Z
+  auto bits = [](int b) { return (int64_t)1 << b; };
+  for (int k = 0; k < n; ++k) {
+    const DOp &op = (*c.ops)[ln.op_begin[v] + k];
+    const bool thin = op.type == OP_CONTRACT && level_prec(c, op) == 0;
+    const bool vector_read = thin || op.type == OP_LEAFGRAD;
+    auto read = [&](int32_t off, int slot) {
+      if (off < leaf) return;
+      auto it = cur.find(off);
+      if (it == cur.end()) return;
+      Inst &t = inst[it->second];
+      t.last = k;
+      if (!vector_read) t.banned = true;
+      uses[k][slot] = it->second;
+    };
+    if (op.type == OP_CONTRACT || op.type == OP_SCALAR) {
+      read(op.x, 0);
+      read(op.y, 1);
+    } else if (op.type == OP_LEAFGRAD) {
+      read(op.x, 0);
+    }
+    if (op.type == OP_CONTRACT || op.type == OP_SEED) {
+      Inst t;
+      t.off = op.z;
+      t.size = op.type == OP_SEED ? 1 : bits(op.nFX + op.nB + op.nFY);
+      t.banned = !thin;
+      cur[op.z] = (int)inst.size();
+      uses[k][2] = (int)inst.size();
+      inst.push_back(t);
+    }
+  }
+  const int64_t base = mirror ? ((leaf + 31) & ~int64_t(31)) : 0;
+  const int64_t cap = c.lds_elems - base;
+  Arena ar;
+  for (int k = 0; k < n; ++k) {
+    const int w = uses[k][2];
+    if (w >= 0 && !inst[w].banned && inst[w].size <= cap) {
+      const int64_t off = ar.alloc(inst[w].size);
+      if (off + inst[w].size <= cap)
+        inst[w].lds = base + off;
+      else
+        ar.release(off, inst[w].size);
+    }
+    const DOp &op = (*c.ops)[ln.op_begin[v] + k];
+    LdsOp &r = res[k];
+    const bool thin = op.type == OP_CONTRACT && level_prec(c, op) == 0;
+    if (thin || op.type == OP_LEAFGRAD) {
+      const int32_t offs[2] = {op.x, op.y};
+      for (int s = 0; s < (thin ? 2 : 1); ++s) {
+        const int t = uses[k][s];
+        const int32_t flag = s == 0 ? kLdsX : kLdsY;
+        int64_t at = -1;
+        if (offs[s] < leaf) at = mirror ? offs[s] : -1;
+        else if (t >= 0) at = inst[t].lds;
+        if (at >= 0) {
+          r.flags |= flag;
+          (s == 0 ? r.x : r.y) = (int32_t)at;
+        }
+      }
+      if (thin && w >= 0 && inst[w].lds >= 0) {
+        r.flags |= kLdsZ;
+        r.z = (int32_t)inst[w].lds;
+      }
+    }
+    // give back what this op read for the last time, and a result nobody reads
+    for (int s = 0; s < 3; ++s) {
+      const int t = uses[k][s];
+      if (t < 0 || inst[t].lds < 0) continue;
+      if ((s < 2 && inst[t].last == k) || (s == 2 && inst[t].last < 0)) {
+        ar.release(inst[t].lds - base, inst[t].size);
+        inst[t].lds = -2;  // released
+      }
+    }
+  }
+  return res;
+}
+
+// Summed-index bit positions of a thin op with nS <= kPackedTabBits, from
+// its table (entry 2^t holds the offsets of summed bit t alone): 5 bits per
+// position, lowest summed bit first.
+static bool packed_tab(const ItemCtx &c, const DOp &op, int32_t &px, int32_t &py) {
+  if (op.type != OP_CONTRACT || op.nS > kPackedTabBits || op.nS > kTabLoBits || !c.tabs) return false;
+  px = py = 0;
+  for (int t = 0; t < op.nS; ++t) {
+    const int32_t ox = (*c.tabs)[op.tab + 2 * (1 << t)], oy = (*c.tabs)[op.tab + 2 * (1 << t) + 1];
+    if (ox <= 0 || oy <= 0 || (ox & (ox - 1)) || (oy & (oy - 1))) return false;
+    px |= (__builtin_ctz((uint32_t)ox) & 31) << (5 * t);
+    py |= (__builtin_ctz((uint32_t)oy) & 31) << (5 * t);
+  }
+  return true;
 }
 
 // --- level items ------------------------------------------------------------------------------
@@ -657,8 +788,10 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
     return it;
   };
   auto push = [&](const PItem &it) { out.push_back(it); };
+  const std::vector<LdsOp> lds = lds_assign(c, ln, v);
   {
     PItem it = base_item(PK_SETUP);
+    it.mv = lds_mirror(c, ln) ? 1 : 0;
     const int64_t zero_n = v == 1 ? ln.ptens_elems : 0;
     const int64_t per = ln.n_const + ln.ptens_elems + zero_n;
     it.lgl = c.one_wg ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>(64, ceil_div(per, 1024)));
@@ -702,6 +835,14 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
       }
     } else if (op.type == OP_CONTRACT || op.type == OP_LEAFGRAD) {
       const bool thin = op.type == OP_CONTRACT;
+      if (c.one_wg) {
+        const LdsOp &r = lds[k];
+        it.a0 = r.flags;
+        if (r.flags & kLdsX) it.op.x = r.x;
+        if (r.flags & kLdsY) it.op.y = r.y;
+        if (r.flags & kLdsZ) it.op.z = r.z;
+        if (thin && packed_tab(c, op, it.a1, it.a2)) it.a0 |= kPackedTab;
+      }
       const int lg = thin ? op.nFX + op.nB + op.nFY : op.nFX;
       int64_t work = ((int64_t)1 << lg) * n_sets;
       it.lgl = 0;
@@ -781,6 +922,8 @@ int plan_level(tn_batch *b) {
                        [&](int x, int y) { return b->level[g.lv[x]].cost > b->level[g.lv[y]].cost; });
       ItemCtx c = item_ctx(b);
       c.one_wg = true;
+      c.lds_elems = b->dtype == TN_C128 ? kLdsArenaBytes<TN_MFMA_FP64> / 16 : kLdsArenaBytes<TN_MFMA_FP32> / 8;
+      if (const char *env = std::getenv("QTN_TASK_LDS")) c.lds_elems = std::min(c.lds_elems, std::max(0, std::atoi(env)));
       for (int j : order) {
         const LevelNet &ln = b->level[g.lv[j]];
         TNet tn{};

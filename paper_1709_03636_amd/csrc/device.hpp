@@ -2,6 +2,8 @@
 #pragma once
 #include <cstdint>
 
+#include "../../include/qtn.h"
+
 namespace qtn {
 
 // One op of a compiled network program, as the kernels read it (56 bytes).
@@ -157,8 +159,20 @@ struct PItem {
   int32_t mv;      // MFMA: kernel variant (tile shape, operand layouts)
   int32_t n_comp;  // component scalars of the network
   int32_t a0, a1, a2, a3, a4, a5;  // SETUP: const_begin, n_const, ptens_begin, n_pt, zero_begin, zero_n;
-                                   // FINISH: network index, ptens_begin, n_pt
+                                   // FINISH: network index, ptens_begin, n_pt; THIN: see kLdsX
 };
+
+// Task executor: a workgroup keeps the small tensors of its program in an
+// LDS arena of kLdsArenaBytes. SETUP with mv = 1 also copies the leaf
+// region (constants and bound parametric tensors) to LDS [0, leaf region).
+// A THIN item's a0 says which operands live there: kLdsX / kLdsY / kLdsZ
+// (op.x / op.y / op.z are then LDS element offsets); kPackedTab: the
+// summed-index offsets come from the bit positions in a1 (X) and a2 (Y), 5
+// bits per summed bit, lowest first, instead of the table (nS <= 6).
+constexpr int kLdsX = 1, kLdsY = 2, kLdsZ = 4, kPackedTab = 8;
+constexpr int kPackedTabBits = 6;
+template <int PREC>
+constexpr int kLdsArenaBytes = PREC == TN_MFMA_FP64 ? 24576 : 32768;  // complex128: its tiles take more LDS
 
 // One network of a task-executor launch: task (network j, vector s) runs
 // items [item0, item0 + n_items) (built for one vector) on the vector's

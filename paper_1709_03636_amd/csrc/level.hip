@@ -19,11 +19,16 @@
 
 namespace qtn {
 
-// Waves per SIMD the kernels are compiled for: the split-BF16 64 x 64 tile
-// holds 132 registers unconstrained (3 waves per SIMD); capped at 128 it runs
-// 4 without spills. The others keep the compiler's choice (FP64 would spill).
+// Waves per SIMD the kernels are compiled for. Item kernels: the split-BF16
+// 64 x 64 tile holds 132 registers unconstrained (3 waves per SIMD); capped
+// at 128 it runs 4 without spills; the others keep the compiler's choice
+// (FP64 would spill). Task executor: three workgroups per CU share its LDS
+// (tile staging plus the small-tensor arena), so complex64 programs are
+// built for 3 waves per SIMD (at most 168 registers).
 template <int PREC>
 constexpr int kMinWaves = PREC == TN_MFMA_BF16X3 ? 4 : 1;
+template <int PREC>
+constexpr int kTaskWaves = PREC == TN_MFMA_FP64 ? 1 : 3;
 // LDS of a workgroup: the largest tile, and at least the 72 doubles of the
 // FP64 sums.
 template <int PREC>
@@ -32,7 +37,7 @@ constexpr int kItemLds = kTileLds<PREC> > 576 ? kTileLds<PREC> : 576;
 template <int PREC>
 __global__ __launch_bounds__(256, kMinWaves<PREC>) void item_kernel(PItem it, LvlArgs a) {
   __shared__ __align__(16) char lds[kItemLds<PREC>];
-  run_item<PREC>(lds, it, (int)blockIdx.x, (int)gridDim.x, a);
+  run_item<PREC, false>(lds, nullptr, it, (int)blockIdx.x, (int)gridDim.x, a);
 }
 
 // The loop's only per-thread branch (thread 0 takes the next task) sits at
@@ -40,12 +45,26 @@ __global__ __launch_bounds__(256, kMinWaves<PREC>) void item_kernel(PItem it, Lv
 // loop branches on is read into scalar registers: a thread-0 branch next to
 // the back edge can be compiled into an inner loop that the other threads
 // re-enter without thread 0.
+//
+// Item descriptors are staged through LDS: the next item's words are
+// loaded (one word per thread, all at once) while the current item runs and
+// stored before the barrier that ends it, so an item starts without a
+// memory round trip per descriptor field. Every thread takes part (indices
+// clamped; threads past the descriptor rewrite its padding word), keeping
+// the loop free of per-thread branches.
+constexpr int kItemWords = (int)(sizeof(PItem) / 4);
+constexpr int kItemRow = (kItemWords + 4 + 3) & ~3;  // 16-byte rows with padding
+static_assert(sizeof(PItem) % 4 == 0, "item descriptors are copied in whole words");
+
 template <int PREC>
-__global__ __launch_bounds__(256, kMinWaves<PREC>) void task_kernel(LvlArgs a) {
+__global__ __launch_bounds__(256, kTaskWaves<PREC>) void task_kernel(LvlArgs a) {
   __shared__ __align__(16) char lds[kItemLds<PREC>];
+  __shared__ __align__(16) char lar[kLdsArenaBytes<PREC>];  // the program's small tensors
+  __shared__ __align__(16) int32_t s_item[2][kItemRow];     // current and next item descriptor
   __shared__ int s_task;
   constexpr int eb = PREC == TN_MFMA_FP64 ? 16 : 8;
   const int total = a.n_tnets * a.max_sets;
+  const int word = min((int)threadIdx.x, kItemWords - 1), slot = min((int)threadIdx.x, kItemRow - 1);
   for (;;) {
     if (threadIdx.x == 0) s_task = __hip_atomic_fetch_add(a.ctrl, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
@@ -61,11 +80,18 @@ __global__ __launch_bounds__(256, kMinWaves<PREC>) void task_kernel(LvlArgs a) {
       v.n_sets = 1;
       v.n_sets_total = a.n_sets;
       const int i0 = __builtin_amdgcn_readfirstlane(tn.item0), n = __builtin_amdgcn_readfirstlane(tn.n_items);
-      for (int i = i0; i < i0 + n; ++i) {
-        const PItem &it = a.items[i];
+      const int32_t *src = reinterpret_cast<const int32_t *>(a.items + i0);
+      if (n > 0) s_item[0][slot] = src[word];
+      __syncthreads();
+      for (int i = 0; i < n; ++i) {
+        const bool more = i + 1 < n;  // uniform
+        int32_t next = 0;
+        if (more) next = src[(int64_t)(i + 1) * kItemWords + word];
+        const PItem &it = *reinterpret_cast<const PItem *>(s_item[i & 1]);
         const int cnt = __builtin_amdgcn_readfirstlane(it.kind == PK_MFMA ? it.count : 1);
-        for (int r = 0; r < cnt; ++r) run_item<PREC>(lds, it, r, cnt, v);
-        __syncthreads();  // the next item reads what this one wrote (same workgroup)
+        for (int r = 0; r < cnt; ++r) run_item<PREC, true>(lds, lar, it, r, cnt, v);
+        if (more) s_item[(i + 1) & 1][slot] = next;
+        __syncthreads();  // the next item reads what this one wrote (same workgroup) and its descriptor
       }
     }
     __syncthreads();  // every thread has read s_task before it is rewritten
@@ -102,11 +128,15 @@ hipError_t item_launch(int prec, const PItem &it, const LvlArgs &a, hipStream_t 
   return hipLaunchKernel(item_kernel_ptr(prec), dim3(it.count), dim3(256), args, 0, st);
 }
 
-// Task counter cleared, then the task executor on `grid` workgroups.
-hipError_t task_launch(int prec, const LvlArgs &a, int grid, hipStream_t st) {
+// The task counter cleared (a kernel, so that captured graphs hold no
+// memset node).
+hipError_t task_reset(const LvlArgs &a, hipStream_t st) {
   hipLaunchKernelGGL(task_reset_kernel, dim3(1), dim3(64), 0, st, a.ctrl);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+// The task executor on `grid` workgroups (after task_reset on the same stream).
+hipError_t task_run(int prec, const LvlArgs &a, int grid, hipStream_t st) {
   void *args[] = {(void *)&a};
   return hipLaunchKernel(task_kernel_ptr(prec), dim3(grid), dim3(256), args, 0, st);
 }

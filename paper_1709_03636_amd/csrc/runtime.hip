@@ -32,7 +32,8 @@ hipError_t launch_combine(const double *val, const double *gnet, const double *c
 hipError_t launch_bind(int dtype, const DParam *slots, int n_slots, const double *params, int n_params, int n_sets,
                        int per_set, void *G, void *dG, hipStream_t st);
 hipError_t item_launch(int prec, const PItem &it, const LvlArgs &a, hipStream_t st);
-hipError_t task_launch(int prec, const LvlArgs &a, int grid, hipStream_t st);
+hipError_t task_reset(const LvlArgs &a, hipStream_t st);
+hipError_t task_run(int prec, const LvlArgs &a, int grid, hipStream_t st);
 const void *task_kernel_ptr(int prec);
 
 // --- device memory: the caller's allocator, or hipMalloc ----------------------------------------
@@ -118,11 +119,42 @@ static T *wsp(char *ws, const tn_batch *b, int k) {
 }
 
 static void drop_timing_events(tn_batch *b) {
-  for (auto &pr : b->tev) {
-    (void)hipEventDestroy(he(pr.first));
-    (void)hipEventDestroy(he(pr.second));
+  for (auto &v : b->tev) {
+    for (auto &pr : v) {
+      (void)hipEventDestroy(he(pr.first));
+      (void)hipEventDestroy(he(pr.second));
+    }
+    v.clear();
   }
-  b->tev.clear();
+}
+
+// Kernel timing: an event pair around one executor's launch on its stream
+// (eager runs in the bound workspace only; at most 4096 pending pairs each).
+struct TimedLaunch {
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+};
+
+static TimedLaunch timing_begin(tn_batch *b, int kind, bool own_ws, hipStream_t s) {
+  TimedLaunch t;
+  if (!b->timing || b->capturing || own_ws || b->tev[kind].size() >= 4096) return t;
+  if (hipEventCreate(&t.t0) != hipSuccess) return TimedLaunch{};
+  if (hipEventCreate(&t.t1) != hipSuccess || hipEventRecord(t.t0, s) != hipSuccess) {
+    (void)hipEventDestroy(t.t0);
+    if (t.t1) (void)hipEventDestroy(t.t1);
+    return TimedLaunch{};
+  }
+  return t;
+}
+
+static void timing_end(tn_batch *b, int kind, hipStream_t s, hipError_t launched, TimedLaunch &t) {
+  if (!t.t0) return;
+  if (launched == hipSuccess && hipEventRecord(t.t1, s) == hipSuccess) {
+    b->tev[kind].emplace_back(t.t0, t.t1);
+  } else {
+    (void)hipEventDestroy(t.t0);
+    (void)hipEventDestroy(t.t1);
+  }
+  t = TimedLaunch{};
 }
 
 static void graph_clear(tn_batch *b) {
@@ -468,10 +500,16 @@ static int run_batch(tn_batch *b, char *ws, bool grad, const double *params, int
         la.items = wsp<PItem>(ws, b, v ? WsLayout::TITEMS1 : WsLayout::TITEMS0);
         la.tnets = wsp<TNet>(ws, b, v ? WsLayout::TNETS1 : WsLayout::TNETS0) + g.tnet0;
         la.n_tnets = (int)g.lv.size();
-        e = task_launch(prec, la, b->task_grid, sl);
+        e = task_reset(la, sl);
+        if (e != hipSuccess) break;
+        TimedLaunch tl = timing_begin(b, 1, own_ws, sl);
+        e = task_run(prec, la, b->task_grid, sl);
+        timing_end(b, 1, sl, e, tl);
       } else {
+        TimedLaunch tl = timing_begin(b, 1, own_ws, sl);
         for (int i = g.item0[v]; i < g.item0[v] + g.n_items[v] && e == hipSuccess; ++i)
           e = item_launch(prec, b->items[v][i], la, sl);
+        timing_end(b, 1, sl, e, tl);
       }
     }
     for (size_t q = 0; q < b->lsolo.size() && e == hipSuccess; ++q) {
@@ -502,26 +540,12 @@ static int run_batch(tn_batch *b, char *ws, bool grad, const double *params, int
     const int rounds = (a.n_tasks + cap - 1) / cap;
     const int grid = (a.n_tasks + rounds - 1) / rounds;
     a.per_block = rounds;
-    hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (b->timing && !b->capturing && !own_ws && b->tev.size() < 4096 && hipEventCreate(&t0) == hipSuccess) {
-      if (hipEventCreate(&t1) != hipSuccess || hipEventRecord(t0, st) != hipSuccess) {
-        (void)hipEventDestroy(t0);
-        if (t1) (void)hipEventDestroy(t1);
-        t0 = t1 = nullptr;
-      }
-    }
+    TimedLaunch tl = timing_begin(b, 0, own_ws, st);
     if (spw > 1)
       e = launch_fused_sets(b->dtype, grad, spw, a, grid, grad ? b->lds_grad : b->lds_fwd, st);
     else
       e = launch_fused(b->dtype, b->block, grad, rec_only(b, v), false, a, grid, grad ? b->lds_grad : b->lds_fwd, st);
-    if (t0) {
-      if (e == hipSuccess && hipEventRecord(t1, st) == hipSuccess) {
-        b->tev.emplace_back(t0, t1);
-      } else {
-        (void)hipEventDestroy(t0);
-        (void)hipEventDestroy(t1);
-      }
-    }
+    timing_end(b, 0, st, e, tl);
     if (e != hipSuccess) {
       b->poisoned = true;
       return hip_fail(e, "fused executor launch");
@@ -542,7 +566,9 @@ static int run_batch(tn_batch *b, char *ws, bool grad, const double *params, int
     const int cap = std::max(1, std::min(std::min(gl.grid, b->gslots), g.n_tasks));
     const int rounds = (g.n_tasks + cap - 1) / cap;
     g.per_block = rounds;
+    TimedLaunch tl = timing_begin(b, 2, own_ws, sg);
     e = launch_fused(b->dtype, 256, grad, false, true, g, (g.n_tasks + rounds - 1) / rounds, gl.lds, sg);
+    timing_end(b, 2, sg, e, tl);
     if (e != hipSuccess) {
       b->poisoned = true;
       return hip_fail(e, "global-arena executor launch");
@@ -890,11 +916,15 @@ int batch_kernel_timing(tn_batch *b, int enable) {
   return TN_OK;
 }
 
-int batch_kernel_time(tn_batch *b, int *n, double *total_ms) {
+int batch_kernel_time(tn_batch *b, int kind, int *n, double *total_ms) {
+  if (kind < 0 || kind > 2) {
+    set_error("tn_batch_kernel_time: executor must be TN_EXEC_FUSED, TN_EXEC_LEVEL or TN_EXEC_GLOBAL");
+    return TN_EINVAL;
+  }
   double sum = 0.0;
   int cnt = 0;
   hipError_t e = hipSuccess;
-  for (auto &pr : b->tev) {
+  for (auto &pr : b->tev[kind]) {
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventSynchronize(he(pr.second));
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, he(pr.first), he(pr.second));
@@ -903,7 +933,11 @@ int batch_kernel_time(tn_batch *b, int *n, double *total_ms) {
       ++cnt;
     }
   }
-  drop_timing_events(b);
+  for (auto &pr : b->tev[kind]) {
+    (void)hipEventDestroy(he(pr.first));
+    (void)hipEventDestroy(he(pr.second));
+  }
+  b->tev[kind].clear();
   if (e != hipSuccess) return hip_fail(e, "tn_batch_kernel_time");
   *n = cnt;
   *total_ms = sum;

@@ -46,6 +46,26 @@ __device__ __forceinline__ int2 l_tab(const int32_t *__restrict__ tb, int nS, in
   return make_int2(tb[2 * lo] + h[2 * hi], tb[2 * lo + 1] + h[2 * hi + 1]);
 }
 
+// Offsets of summed entry k from packed bit positions (5 bits each, lowest
+// summed bit first; at most kPackedTabBits bits).
+__device__ __forceinline__ int2 l_ptab(uint32_t px, uint32_t py, int nS, int k) {
+  int ox = 0, oy = 0;
+#pragma unroll
+  for (int t = 0; t < kPackedTabBits; ++t)
+    if (t < nS) {
+      const int b = (k >> t) & 1;
+      ox |= b << ((px >> (5 * t)) & 31);
+      oy |= b << ((py >> (5 * t)) & 31);
+    }
+  return make_int2(ox, oy);
+}
+
+// Summed-index offsets of an op: packed positions (pk.x, pk.y) when pk.z,
+// else its table.
+__device__ __forceinline__ int2 l_koff(const int32_t *__restrict__ tb, const int3 &pk, int nS, int k) {
+  return pk.z ? l_ptab((uint32_t)pk.x, (uint32_t)pk.y, nS, k) : l_tab(tb, nS, k);
+}
+
 __device__ __forceinline__ uint32_t l_pdep(uint32_t v, uint32_t mask) {
   uint32_t r = 0;
   while (mask) {
@@ -75,7 +95,8 @@ __device__ __forceinline__ double l_xor(double v, int m) { return __shfl_xor(v, 
 // summed entries k = part, part + L, ...; the output index c = (i, b, j)
 // holds the X-only bits, the batch bits (offset table) and the Y-only bits.
 template <typename V>
-__device__ __forceinline__ V thin_output(const V *base, const DOp &op, const DRuns &ru, const int32_t *__restrict__ tab,
+__device__ __forceinline__ V thin_output(const V *xb, const V *yb, const DOp &op, const DRuns &ru,
+                                         const int32_t *__restrict__ tab, const int3 &pk,
                                          const int32_t *__restrict__ tabB, uint32_t c, int part, int L) {
   const uint32_t rest = c >> op.nFY;
   uint32_t bx = 0, by = 0;
@@ -84,8 +105,8 @@ __device__ __forceinline__ V thin_output(const V *base, const DOp &op, const DRu
     bx = tabB[2 * b];
     by = tabB[2 * b + 1];
   }
-  const V *X = base + op.x + l_deposit(rest >> op.nB, ru.runsX, op.maskX) + bx;
-  const V *Y = base + op.y + l_deposit(c & ((1u << op.nFY) - 1u), ru.runsY, op.maskY) + by;
+  const V *X = xb + op.x + l_deposit(rest >> op.nB, ru.runsX, op.maskX) + bx;
+  const V *Y = yb + op.y + l_deposit(c & ((1u << op.nFY) - 1u), ru.runsY, op.maskY) + by;
   V acc;
   acc.x = 0;
   acc.y = 0;
@@ -96,7 +117,7 @@ __device__ __forceinline__ V thin_output(const V *base, const DOp &op, const DRu
     for (int k = part; k < K; k += 4 * L) {
       int2 t[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) t[u] = l_tab(tab, op.nS, k + u * L);
+      for (int u = 0; u < 4; ++u) t[u] = l_koff(tab, pk, op.nS, k + u * L);
       V x[4], y[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -109,7 +130,7 @@ __device__ __forceinline__ V thin_output(const V *base, const DOp &op, const DRu
     return acc;
   }
   for (int k = part; k < K; k += L) {
-    const int2 t = l_tab(tab, op.nS, k);
+    const int2 t = l_koff(tab, pk, op.nS, k);
     acc = l_fma(acc, X[t.x], Y[t.y]);
   }
   return acc;
@@ -120,7 +141,8 @@ __device__ __forceinline__ V thin_output(const V *base, const DOp &op, const DRu
 // sit at fixed offsets deposit(r) from the first (disjoint bits add), so one
 // X read serves four products.
 template <typename V>
-__device__ __forceinline__ void thin_output4(V *base, const DOp &op, const DRuns &ru, const int32_t *__restrict__ tab,
+__device__ __forceinline__ void thin_output4(const V *xb, const V *yb, V *zb, const DOp &op, const DRuns &ru,
+                                            const int32_t *__restrict__ tab, const int3 &pk,
                                             const int32_t *__restrict__ tabB, uint32_t c0) {
   const uint32_t rest = c0 >> op.nFY;
   uint32_t bx = 0, by = 0;
@@ -129,8 +151,8 @@ __device__ __forceinline__ void thin_output4(V *base, const DOp &op, const DRuns
     bx = tabB[2 * b];
     by = tabB[2 * b + 1];
   }
-  const V *X = base + op.x + l_deposit(rest >> op.nB, ru.runsX, op.maskX) + bx;
-  const V *Y = base + op.y + l_deposit(c0 & ((1u << op.nFY) - 1u), ru.runsY, op.maskY) + by;
+  const V *X = xb + op.x + l_deposit(rest >> op.nB, ru.runsX, op.maskX) + bx;
+  const V *Y = yb + op.y + l_deposit(c0 & ((1u << op.nFY) - 1u), ru.runsY, op.maskY) + by;
   uint32_t dy[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) dy[r] = l_deposit((uint32_t)r, ru.runsY, op.maskY);
@@ -144,7 +166,7 @@ __device__ __forceinline__ void thin_output4(V *base, const DOp &op, const DRuns
   int k = 0;
   // two summed entries per iteration: ten operand loads in flight
   for (; k + 2 <= K; k += 2) {
-    const int2 t0 = l_tab(tab, op.nS, k), t1 = l_tab(tab, op.nS, k + 1);
+    const int2 t0 = l_koff(tab, pk, op.nS, k), t1 = l_koff(tab, pk, op.nS, k + 1);
     const V x0 = X[t0.x], x1 = X[t1.x];
     V y0[4], y1[4];
 #pragma unroll
@@ -156,13 +178,13 @@ __device__ __forceinline__ void thin_output4(V *base, const DOp &op, const DRuns
     for (int r = 0; r < 4; ++r) acc[r] = l_fma(l_fma(acc[r], x0, y0[r]), x1, y1[r]);
   }
   if (k < K) {
-    const int2 t = l_tab(tab, op.nS, k);
+    const int2 t = l_koff(tab, pk, op.nS, k);
     const V x = X[t.x];
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = l_fma(acc[r], x, Y[t.y + dy[r]]);
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) base[op.z + c0 + r] = acc[r];
+  for (int r = 0; r < 4; ++r) zb[op.z + c0 + r] = acc[r];
 }
 
 // Four outputs c0 + 64 r (r < 4) of one parameter vector, c0 mod 256 < 64:
@@ -172,7 +194,8 @@ __device__ __forceinline__ void thin_output4(V *base, const DOp &op, const DRuns
 // their own entries sit at fixed offsets deposit(64 r). Consecutive lanes
 // take consecutive c0: every load and store instruction is coalesced.
 template <typename V, bool ALONG_X>
-__device__ __forceinline__ void thin_output4s(V *base, const DOp &op, const DRuns &ru, const int32_t *__restrict__ tab,
+__device__ __forceinline__ void thin_output4s(const V *xb, const V *yb, V *zb, const DOp &op, const DRuns &ru,
+                                             const int32_t *__restrict__ tab, const int3 &pk,
                                              const int32_t *__restrict__ tabB, uint32_t c0) {
   uint32_t bx = 0, by = 0, fx, fy;
   if (ALONG_X) {
@@ -188,8 +211,8 @@ __device__ __forceinline__ void thin_output4s(V *base, const DOp &op, const DRun
     fx = rest >> op.nB;
     fy = c0 & ((1u << op.nFY) - 1u);
   }
-  const V *X = base + op.x + l_deposit(fx, ru.runsX, op.maskX) + bx;
-  const V *Y = base + op.y + l_deposit(fy, ru.runsY, op.maskY) + by;
+  const V *X = xb + op.x + l_deposit(fx, ru.runsX, op.maskX) + bx;
+  const V *Y = yb + op.y + l_deposit(fy, ru.runsY, op.maskY) + by;
   uint32_t d[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
@@ -201,7 +224,7 @@ __device__ __forceinline__ void thin_output4s(V *base, const DOp &op, const DRun
     acc[r].y = 0;
   }
   for (int k = 0; k < (1 << op.nS); ++k) {
-    const int2 t = l_tab(tab, op.nS, k);
+    const int2 t = l_koff(tab, pk, op.nS, k);
     V v[4];
     if (ALONG_X) {
       const V y = Y[t.y];
@@ -218,7 +241,7 @@ __device__ __forceinline__ void thin_output4s(V *base, const DOp &op, const DRun
     }
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) base[op.z + c0 + 64u * r] = acc[r];
+  for (int r = 0; r < 4; ++r) zb[op.z + c0 + 64u * r] = acc[r];
 }
 
 // PK_THIN: a thin contraction or a leaf adjoint over the pass's parameter
@@ -231,14 +254,21 @@ __device__ __forceinline__ void thin_output4s(V *base, const DOp &op, const DRun
 // Y-only bits), -2 / -3 four 64 apart along Y / X (thin_output4s). A leaf
 // adjoint adds the adjoint of a parametric leaf into the tensor's
 // canonical-layout accumulator at y (the table maps buffer to canonical index).
-template <typename V>
-__device__ __forceinline__ void task_thin(const PItem &it, int rank, int count, V *arena, int n_sets,
+// LDSOK (task executor): operands flagged in it.a0 (kLdsX / kLdsY / kLdsZ)
+// are read from / written to the workgroup's LDS arena `lar` instead of the
+// region, and kPackedTab items take their summed-index offsets from packed
+// bit positions instead of the table.
+template <typename V, bool LDSOK>
+__device__ __forceinline__ void task_thin(const PItem &it, int rank, int count, V *arena, V *lar, int n_sets,
                                           const int32_t *__restrict__ tabs) {
   const DOp &op = it.op;
   const int lgOut = op.nFX + op.nB + op.nFY;
   const int32_t *tab = tabs + op.tab;
   const int32_t *tabB = tabs + op.tabB;
+  const int fl = LDSOK ? it.a0 : 0;
+  const int3 pk = make_int3(it.a1, it.a2, fl & kPackedTab);
   V *reg = arena + it.base;
+  auto pick = [&](V *base, int bit) { return LDSOK && (fl & bit) ? lar : base; };
   if (op.type == OP_LEAFGRAD) {
     const int m = 1 << op.nFX;
     const int64_t tot = (int64_t)m * n_sets;
@@ -247,7 +277,7 @@ __device__ __forceinline__ void task_thin(const PItem &it, int rank, int count, 
       const int i = (int)(g & (m - 1));
       V *base = reg + set * it.stride;
       V v = base[op.y + tab[i]];
-      const V x = base[op.x + i];
+      const V x = pick(base, kLdsX)[op.x + i];
       v.x += x.x;
       v.y += x.y;
       base[op.y + tab[i]] = v;
@@ -261,10 +291,11 @@ __device__ __forceinline__ void task_thin(const PItem &it, int rank, int count, 
       const int64_t set = g >> (lgOut - 2);
       const uint32_t q = (uint32_t)(g & (nq - 1));
       const uint32_t c0 = ((q >> 6) << 8) | (q & 63u);
+      V *base = reg + set * it.stride;
       if (it.lgl == -3)
-        thin_output4s<V, true>(reg + set * it.stride, op, it.ru, tab, tabB, c0);
+        thin_output4s<V, true>(pick(base, kLdsX), pick(base, kLdsY), pick(base, kLdsZ), op, it.ru, tab, pk, tabB, c0);
       else
-        thin_output4s<V, false>(reg + set * it.stride, op, it.ru, tab, tabB, c0);
+        thin_output4s<V, false>(pick(base, kLdsX), pick(base, kLdsY), pick(base, kLdsZ), op, it.ru, tab, pk, tabB, c0);
     }
     return;
   }
@@ -274,7 +305,8 @@ __device__ __forceinline__ void task_thin(const PItem &it, int rank, int count, 
     for (int64_t g = rank * (int64_t)256 + threadIdx.x; g < total4; g += (int64_t)count * 256) {
       const int64_t set = g >> (lgOut - 2);
       const uint32_t c0 = (uint32_t)(g & (nq - 1)) << 2;
-      thin_output4(reg + set * it.stride, op, it.ru, tab, tabB, c0);
+      V *base = reg + set * it.stride;
+      thin_output4(pick(base, kLdsX), pick(base, kLdsY), pick(base, kLdsZ), op, it.ru, tab, pk, tabB, c0);
     }
     return;
   }
@@ -288,12 +320,12 @@ __device__ __forceinline__ void task_thin(const PItem &it, int rank, int count, 
     const int64_t set = o >> lgOut;
     const uint32_t c = (uint32_t)(o & (nOut - 1));
     V *base = reg + set * it.stride;
-    V acc = thin_output(base, op, it.ru, tab, tabB, c, part, L);
+    V acc = thin_output(pick(base, kLdsX), pick(base, kLdsY), op, it.ru, tab, pk, tabB, c, part, L);
     for (int m = 1; m < L; m <<= 1) {
       acc.x += l_xor(acc.x, m);
       acc.y += l_xor(acc.y, m);
     }
-    if (part == 0) base[op.z + c] = acc;
+    if (part == 0) pick(base, kLdsZ)[op.z + c] = acc;
   }
 }
 
@@ -448,18 +480,27 @@ __device__ __forceinline__ void task_seed(const PItem &it, int rank, const LvlAr
 // (DParams a2 .. a2 + a3) into the vector's slice and clears the a5 adjoint
 // accumulator entries from a4.
 template <typename V>
-__device__ __forceinline__ void task_setup(const PItem &it, int rank, const LvlArgs &a) {
+__device__ __forceinline__ void task_setup(const PItem &it, int rank, const LvlArgs &a, V *lar) {
   const int G = it.lgl;
   const int set = rank / G, chunk = rank - set * G;
   if (set >= a.n_sets) return;
   V *base = reinterpret_cast<V *>(a.arena) + it.base + set * it.stride;
   const V *consts = reinterpret_cast<const V *>(a.consts) + it.a0;
   const int step = G * 256, first = chunk * 256 + (int)threadIdx.x;
-  for (int e = first; e < it.a1; e += step) base[e] = consts[e];
+  const bool mirror = lar && (it.mv & 1);  // task executor: the leaf region also into LDS
+  for (int e = first; e < it.a1; e += step) {
+    const V v = consts[e];
+    base[e] = v;
+    if (mirror) lar[e] = v;
+  }
   const V *bs = reinterpret_cast<const V *>(a.bound) + (size_t)(a.set0 + set) * a.per_set;
   for (int t = 0; t < it.a3; ++t) {
     const DParam d = a.ptens[it.a2 + t];
-    for (int e = first; e < (1 << d.bits); e += step) base[d.off + e] = bs[d.slot + e];
+    for (int e = first; e < (1 << d.bits); e += step) {
+      const V v = bs[d.slot + e];
+      base[d.off + e] = v;
+      if (mirror) lar[d.off + e] = v;
+    }
   }
   for (int e = first; e < it.a5; e += step) {
     V z;
@@ -517,12 +558,14 @@ __device__ __forceinline__ void task_finish(char *lds, const PItem &it, int rank
 // Task `rank` of `count` of an item; PREC: the matrix-core precision
 // (TN_MFMA_FP32 or TN_MFMA_BF16X3 for complex64, TN_MFMA_FP64 for
 // complex128). lds: at least max(kTileLds<PREC>, 72 doubles), 16-byte aligned.
-template <int PREC>
-__device__ __forceinline__ void run_item(char *lds, const PItem &it, int rank, int count, const LvlArgs &a) {
+// lar: the task executor's LDS arena for small tensors (LDSOK), else unused.
+template <int PREC, bool LDSOK>
+__device__ __forceinline__ void run_item(char *lds, char *lar, const PItem &it, int rank, int count, const LvlArgs &a) {
   using V = typename std::conditional<PREC == TN_MFMA_FP64, double2, float2>::type;
+  V *larv = LDSOK ? reinterpret_cast<V *>(lar) : nullptr;
   switch (it.kind) {
-    case PK_SETUP: task_setup<V>(it, rank, a); break;
-    case PK_THIN: task_thin<V>(it, rank, count, reinterpret_cast<V *>(a.arena), a.n_sets, a.tabs); break;
+    case PK_SETUP: task_setup<V>(it, rank, a, larv); break;
+    case PK_THIN: task_thin<V, LDSOK>(it, rank, count, reinterpret_cast<V *>(a.arena), larv, a.n_sets, a.tabs); break;
     case PK_MFMA: task_mfma<PREC>(lds, it, rank, a); break;
     case PK_SPLITSUM: task_splitsum<V>(it, rank, count, a); break;
     case PK_SCALAR: task_scalar<V>(lds, it, rank, a); break;

@@ -16,6 +16,7 @@ LIB_PATH = os.environ.get("QTN_LIB", os.path.join(HERE, "libqtn.so"))
 TN_OK, TN_EINVAL, TN_ENOMEM, TN_EORDER, TN_EDEVICE, TN_ESTATE = 0, -1, -2, -3, -4, -5
 TN_H, TN_X, TN_Y, TN_Z, TN_RX, TN_RY, TN_RZ, TN_ZZ, TN_CNOT, TN_CZ, TN_U1, TN_U2, TN_SUPER1, TN_SUPER2 = range(14)
 TN_AMPLITUDE, TN_PROBABILITY, TN_EXPECTATION = 0, 1, 2
+TN_EXEC_FUSED, TN_EXEC_LEVEL, TN_EXEC_GLOBAL = 0, 1, 2
 TN_C64, TN_C128 = 0, 1
 TN_MFMA_FP32, TN_MFMA_BF16X3, TN_MFMA_FP64 = 1, 2, 3
 GATE_KINDS = {"H": TN_H, "X": TN_X, "Y": TN_Y, "Z": TN_Z, "RX": TN_RX, "RY": TN_RY, "RZ": TN_RZ, "ZZ": TN_ZZ,
@@ -87,7 +88,7 @@ _SIGS = {
     "tn_batch_apply_tuning": (_I, [_P, ctypes.c_char_p]),
     "tn_batch_set_precision": (_I, [_P, _I]),
     "tn_batch_kernel_timing": (_I, [_P, _I]),
-    "tn_batch_kernel_time": (_I, [_P, _PI, _PD]),
+    "tn_batch_kernel_time": (_I, [_P, _I, _PI, _PD]),
     "tn_contract_batch": (_I, [ctypes.POINTER(_P), _I, _P, _I, _P, _P]),
     "tn_grad_batch": (_I, [ctypes.POINTER(_P), _I, _P, _I, _P, _P, _P]),
     "tn_bind_params": (_I, [_P, _P, _I, _P, ctypes.POINTER(ctypes.c_int64), _P]),
@@ -377,13 +378,14 @@ class Batch:
         _check(lib().tn_batch_set_precision(self.h, mfma_precision))
 
     def kernel_timing(self, enable=True):
-        """Record HIP events around later eager fused launches (tn_batch_kernel_timing)."""
+        """Record HIP events around later eager executor launches (tn_batch_kernel_timing)."""
         _check(lib().tn_batch_kernel_timing(self.h, 1 if enable else 0))
 
-    def kernel_time(self):
-        """(launches timed, summed milliseconds) since the last call (tn_batch_kernel_time)."""
+    def kernel_time(self, executor=0):
+        """(launches timed, summed milliseconds) of one executor (TN_EXEC_FUSED, TN_EXEC_LEVEL,
+        TN_EXEC_GLOBAL) since the last call for it (tn_batch_kernel_time)."""
         n, ms = ctypes.c_int32(), ctypes.c_double()
-        _check(lib().tn_batch_kernel_time(self.h, ctypes.byref(n), ctypes.byref(ms)))
+        _check(lib().tn_batch_kernel_time(self.h, executor, ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
 
     def apply_tuning(self, cache_path):

@@ -22,7 +22,7 @@ int batch_autotune(tn_batch *, const double *, int, int, const char *, void *) {
 int batch_apply_cache(tn_batch *, const char *) { return no_device(); }
 int batch_set_precision(tn_batch *b, int prec) { return plan_set_precision(b, prec); }
 int batch_kernel_timing(tn_batch *, int) { return no_device(); }
-int batch_kernel_time(tn_batch *, int *, double *) { return no_device(); }
+int batch_kernel_time(tn_batch *, int, int *, double *) { return no_device(); }
 int batch_bind(tn_batch *, void *, int64_t) { return no_device(); }
 void batch_free(tn_batch *b) { delete b; }
 int set_allocator(tn_alloc_fn, tn_free_fn, void *) { return no_device(); }

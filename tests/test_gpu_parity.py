@@ -214,9 +214,11 @@ def test_batch_forward_matches_grad_pass_and_graph_replay():
         _ = (ang * 2).sum().item()  # eager work between replays
 
 
-def test_kernel_timing_hook():
-    """tn_batch_kernel_timing records one event pair per eager fused launch
-    and none inside graph captures; the results are unchanged."""
+def test_kernel_timing_hook(monkeypatch):
+    """tn_batch_kernel_timing records one event pair per eager executor
+    launch and none inside graph captures; the results are unchanged. A batch
+    split over the three executors (level networks on the task executor)
+    times each executor on its own stream."""
     qtn, qaoa = _qtn(), _qaoa()
     n = 12
     e = workloads.random_regular_graph(3, n, 3)
@@ -243,6 +245,32 @@ def test_kernel_timing_hook():
     assert np.array_equal(grad0.cpu().numpy(), grad1.cpu().numpy())
     # forward-only graph vs the adjoint pass's value: different kernels, c64 tolerance
     assert np.max(np.abs(obj.cpu().numpy() - obj0.cpu().numpy())) <= 1e-5 * max(1.0, float(obj0.abs().max()))
+    # three executors
+    n = 24
+    e = workloads.random_regular_graph(3, n, 2)
+    monkeypatch.setenv("QTN_FUSED_LDS_MAX", "32768")
+    monkeypatch.setenv("QTN_GMEM_MAX_MACS", str(1 << 18))
+    monkeypatch.setenv("QTN_TASK_MIN", "1")
+    model = qaoa.MaxCut(n, e, 2, qtn.TN_C64, order="linegraph", max_sets=S, trials=2)
+    info = model.batch.info()
+    assert info["n_fused"] > 0 and info["n_global"] > 0 and info["n_level_tasked"] == info["n_level_groups"] == 1
+    ang = torch.tensor(workloads.qaoa_angles(4, S, 2), device="cuda", dtype=torch.float64)
+    obj0, grad0 = model.value_and_grad(ang)
+    model.batch.kernel_timing(True)
+    for _ in range(3):
+        model.batch.grad(ang, stream=st)
+    model.batch.contract(ang, stream=st)
+    st.synchronize()
+    _say("kernel timing, three executors")
+    for ex in (qtn.TN_EXEC_FUSED, qtn.TN_EXEC_LEVEL, qtn.TN_EXEC_GLOBAL):
+        n_timed, ms = model.batch.kernel_time(ex)
+        assert n_timed == 4 and 0.0 < ms < 1e3, (ex, n_timed, ms)
+        assert model.batch.kernel_time(ex) == (0, 0.0)
+    model.batch.kernel_timing(False)
+    obj1, grad1 = model.value_and_grad(ang)
+    torch.cuda.synchronize()
+    assert np.array_equal(obj0.cpu().numpy(), obj1.cpu().numpy())
+    assert np.array_equal(grad0.cpu().numpy(), grad1.cpu().numpy())
 
 
 def test_bind_params_kernel():
@@ -754,3 +782,36 @@ def test_task_executor_matches_item_mode(monkeypatch):
             assert np.max(np.abs(g[:, s, 1] - db[:3])) <= 1e-4 * max(1.0, np.abs(db[:3]).max())
         res[mode] = (o, g)
     assert np.max(np.abs(res["task"][0] - res["item"][0])) < 1e-5
+
+
+def test_task_executor_lds_residency_is_exact(monkeypatch):
+    """The task executor keeps a program's small tensors (and a mirror of its
+    leaves) in LDS and takes small summed-index offsets from packed bit
+    positions: 4-regular n=14 p=2 light-cone networks, forward + adjoint,
+    give bit-identical values and gradients with that arena switched off
+    (every tensor in the region, every offset from its table), and match the
+    state-vector cost and parameter-shift gradient."""
+    qtn, qaoa = _qtn(), _qaoa()
+    monkeypatch.setenv("QTN_FUSED_LDS_MAX", "0")
+    monkeypatch.setenv("QTN_GMEM_MAX_MACS", "0")
+    monkeypatch.setenv("QTN_TASK_MIN", "1")
+    n = 14
+    e = workloads.random_regular_graph(4, n, 0)
+    S = 3
+    ang = torch.tensor(workloads.qaoa_angles(12, S, 2), device="cuda", dtype=torch.float64)
+    ref = np.array([gradients.cost(n, e, list(a)) for a in ang.cpu().numpy()])
+    ps = np.array([gradients.parameter_shift(n, e, list(a)) for a in ang.cpu().numpy()])
+    res = {}
+    for lds in ("default", "0"):
+        if lds == "0":
+            monkeypatch.setenv("QTN_TASK_LDS", "0")
+        model = qaoa.MaxCut(n, e, 2, qtn.TN_C64, order="linegraph", max_sets=S, trials=4)
+        assert model.batch.info()["n_level_tasked"] == 1
+        _say(f"task executor LDS arena {lds}")
+        obj, grad = model.value_and_grad(ang)
+        torch.cuda.synchronize()
+        res[lds] = (obj.cpu().numpy(), grad.cpu().numpy())
+    assert np.array_equal(res["default"][0], res["0"][0]) and np.array_equal(res["default"][1], res["0"][1])
+    obj, grad = res["default"]
+    assert np.max(np.abs(obj - ref)) <= 1e-5 * np.abs(ref).max()
+    assert np.max(np.abs(grad - ps)) <= 1e-4 * np.abs(ps).max()
