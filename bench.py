@@ -1,17 +1,26 @@
 """Benchmark: batched QAOA <Z_u Z_v> network contraction, forward + adjoint gradient.
 
-Workload: QAOA p=1 Max-Cut on a seeded random 3-regular graph with 100
-vertices (150 edges), one folded light-cone network per edge, line-graph
-(min-fill) contraction order, complex64 contraction with FP64 final scalars
-and gradient sums, 64 angle sets (gamma, beta) uniform in [0, pi) from seed 0.
-One step = one pass of the whole path over the batch: angle binding, every
-pairwise contraction, the final FP64 scalars, the adjoint sweep and the FP64
-objective/gradient combine, replayed from a captured HIP graph.
+Headline workload (the largest batching configuration): QAOA p=2 Max-Cut on
+a seeded random 5-regular graph with 100 vertices (250 edges), one folded
+light-cone network per edge, line-graph (min-fill) contraction order (best
+of 128 restarts), 64 angle sets (gamma_1, gamma_2, beta_1, beta_2) uniform
+in [0, pi) from seed 0; complex64 contraction with split-BF16 matrix-core
+products (FP32 accumulation), FP64 final scalars and gradient sums. One step
+= one pass of the whole path over the batch: angle binding, every pairwise
+contraction, the final scalars, the adjoint sweep and the objective and
+gradient combine, replayed from a captured HIP graph.
 
-Prints one JSON line (rank 0). Also measured: forward-only throughput, the
-plain one-network-per-launch path in complex64 and complex128, the error
-against the closed-form p=1 oracle, the dominant kernel's roofline figures
-and the FP64 CPU oracle timed on a bounded sample.
+After the timed steps, the last replay's per-network values and gradients
+are checked against FP64 oracle values stored in tests/golden (written by
+committed scripts that call only the oracle); a miss fails the run. Also
+measured: forward-only throughput, each executor's kernel time and roofline
+figures, the 3-regular n=100 p=1 batch (plain one-network-per-launch path in
+complex64 and complex128, and batched), the dense regime on the matrix
+cores, the rows past the hot path, the other batching configurations, the
+differentiation and crossover rows, and the FP64 CPU oracle timed on a
+bounded sample of the headline workload and of the p=1 batch.
+
+Prints one JSON line (rank 0).
 """
 import argparse
 import json
@@ -25,49 +34,80 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-D, N_VERT, P_LAYERS, N_SETS, GRAPH_SEED, ANGLE_SEED = 3, 100, 1, 64, 0, 0
-# restarts of the line-graph order search per network in the batching grid: at p = 2 on 5-regular
-# graphs the best of 128 has 2-4x fewer flops than the best of 4 (plan time, on host threads)
+HEAD_D, HEAD_N, HEAD_P = 5, 100, 2
+N_SETS, GRAPH_SEED, ANGLE_SEED = 64, 0, 0
+# restarts of the line-graph order search per network: at p = 2 on 5-regular graphs the best of 128 has
+# 2-4x fewer flops than the best of 4 (plan time, on host threads)
 GRID_TRIALS = {1: 4, 2: 128}
 HBM_PEAK = 8.0e12
 FP32_MFMA_PEAK = 157.3e12
 FP64_MFMA_PEAK = 78.6e12
+BF16_MFMA_PEAK = 2.5e15
+FP32_VALU_PEAK = 157.3e12  # published FP32 vector peak (packed FP32); 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# x 2.4 GHz = 78.6e12 without packed instructions, which this build does not emit
+# split-BF16 tolerances (complex64 with three bf16 products per real product, FP32 accumulation):
+# <Z_u Z_v> values and per-network gradients, absolute (derivation in the GPU configuration tests)
+TOL_ZZ_BF16, TOL_G_BF16 = 5e-5, 5e-4
+BOX_CORES = 16  # host cores the GPU machine allots to one GPU (worker pools stay within it)
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def load_refs():
+    """Oracle values for the checks (tests/golden, written by scripts that call only oracle/)."""
+    g = os.path.join(ROOT, "tests", "golden")
+    refs = json.load(open(os.path.join(g, "bench_refs.json")))
+    refs["config3_p2"] = {(x["d"], x["n"]): x for x in json.load(open(os.path.join(g, "config3_p2.json")))["graphs"]}
+    return refs
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def _oracle_worker(args):
+    """One (edge, angle set) network by the FP64 oracle: the value and the
+    central finite-difference gradient in every parameter (1 + 4p plain
+    tensordot contractions of the edge's light cone)."""
     n, edges, p, edge, params = args
+    from threadpoolctl import threadpool_limits
     from oracle import tensornet, gates
-    import numpy as np
-    # forward plus central finite differences in every parameter (2p)
-    def zz(prm):
-        gl = gates.qaoa_gate_list(n, edges, prm[:p], prm[p:])[n:]
-        plus = [np.array([1.0, 1.0]) / np.sqrt(2.0)] * n
-        pauli = [0] * n
-        pauli[edge[0]] = pauli[edge[1]] = 3
-        return tensornet.expectation(n, gl, pauli, init=plus, lightcone=True).real
-    v = zz(params)
-    h = 1e-4
-    g = []
-    for i in range(2 * p):
-        e = np.zeros(2 * p)
-        e[i] = h
-        g.append((zz(params + e) - zz(params - e)) / (2 * h))
+    with threadpool_limits(1):
+        def zz(prm):
+            gl = gates.qaoa_gate_list(n, edges, prm[:p], prm[p:])[n:]
+            plus = [np.array([1.0, 1.0]) / np.sqrt(2.0)] * n
+            pauli = [0] * n
+            pauli[edge[0]] = pauli[edge[1]] = 3
+            return tensornet.expectation(n, gl, pauli, init=plus, lightcone=True).real
+        v = zz(params)
+        h = 1e-4
+        g = []
+        for i in range(2 * p):
+            e = np.zeros(2 * p)
+            e[i] = h
+            g.append((zz(params + e) - zz(params - e)) / (2 * h))
     return v, g
 
 
-def cpu_baseline(edges, angles, budget_s=12.0):
-    """The FP64 oracle (plain tensordot contraction) on a bounded sample."""
+def cpu_baseline(n, edges, p, angles, budget_s, label):
+    """The FP64 oracle (plain tensordot contraction, forward plus
+    finite-difference gradient per network) on a bounded sample of a batch's
+    (edge, angle set) networks, in worker processes on the machine's cores."""
     import multiprocessing as mp
-    workers = max(1, min(16, os.cpu_count() or 1))
-    tasks = []
-    for s in range(angles.shape[0]):
-        for e in edges:
-            tasks.append((N_VERT, edges, P_LAYERS, e, np.array(angles[s])))
-    # size the sample from a single-network probe
+    workers = max(1, min(BOX_CORES, os.cpu_count() or 1))
+    # sample: edges in a seeded order, angle sets round robin
+    rng = np.random.default_rng(1234)
+    order = rng.permutation(len(edges))
+    tasks = [(n, edges, p, edges[int(order[k % len(edges)])], np.array(angles[k % angles.shape[0]]))
+             for k in range(len(edges) * angles.shape[0])]
     t0 = time.perf_counter()
     _oracle_worker(tasks[0])
     one = time.perf_counter() - t0
@@ -76,35 +116,35 @@ def cpu_baseline(edges, angles, budget_s=12.0):
     ctx = mp.get_context("fork")
     with ctx.Pool(workers) as pool:
         t0 = time.perf_counter()
-        pool.map(_oracle_worker, sample, chunksize=max(1, n_sample // (4 * workers)))
+        pool.map(_oracle_worker, sample, chunksize=1)
         dt = time.perf_counter() - t0
-    # one core: a short sample in this process
-    n1 = int(max(4, min(len(tasks), 2.0 / max(one, 1e-4))))
-    t0 = time.perf_counter()
-    for t in tasks[:n1]:
-        _oracle_worker(t)
-    dt1 = time.perf_counter() - t0
     return {"value": n_sample / dt, "unit": "networks/s (fwd+grad)", "cores": workers, "kind": "oracle",
-            "value_1core": n1 / dt1,
-            "sample": f"{n_sample} (edge, angle-set) networks of the same workload, forward plus central "
-                      f"finite-difference gradient (5 FP64 contractions each), {workers} processes; "
-                      f"1-core figure from {n1} networks in one process"}
+            "sample": f"{n_sample} of the {len(tasks)} (edge, angle set) networks of {label}, each forward plus "
+                      f"central finite-difference gradient ({1 + 4 * p} FP64 light-cone contractions), "
+                      f"{workers} worker processes with one BLAS thread each",
+            "seconds": dt, "host_cpu": cpu_model(), "host_cpu_count": os.cpu_count(),
+            "cores_note": f"the GPU box allots {BOX_CORES} host cores to one GPU; pools stay within them"}
 
 
-def traffic_from_profile(kernel):
-    """HBM bytes per launch of the fused adjoint kernel from the committed
-    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the summary covers
-    another kernel instance or the kernel source changed since the counters
-    were taken."""
+def kernel_src_sha():
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic.fused_exec_grad.json")
-    src = os.path.join(ROOT, "paper_1709_03636_amd", "csrc", "kernels.hip")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1709_03636_amd", "csrc"))):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(ROOT, "paper_1709_03636_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(tag, kernel):
+    """HBM bytes per launch of a kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary (profiles/traffic.<tag>.json), or None
+    when the summary covers another kernel or the device sources changed
+    since the counters were taken."""
     try:
-        rec = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        rec = json.load(open(os.path.join(ROOT, "profiles", f"traffic.{tag}.json")))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_src_sha256_prefix") != sha or rec.get("kernel") != kernel:
+    if rec.get("device_src_sha256_prefix") != kernel_src_sha() or rec.get("kernel") != kernel:
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -132,9 +172,51 @@ def max_cut_brute_force(n, edges):
     return int(cut.max())
 
 
-def next_rows(model, params, edges, st, dev):
-    """Rows past the hot path: angle optimisation on the adjoint gradient,
-    answer-string estimation, and the batched pass with noise channels."""
+def p1_errors(block, out, gnet=None, obj=None, grad=None):
+    """Largest deviations of a p=1 batch's results from the stored closed-form
+    values: per-edge <Z_u Z_v> (and gradients) on the sampled sets, the
+    objective and its gradient on every set (when stored)."""
+    o = out.cpu().numpy()
+    r = {"max_abs_zz": max(float(np.max(np.abs(o[:, s, 0] - np.array(block["zz"][j]))))
+                           for j, s in enumerate(block["sets"]))}
+    if gnet is not None:
+        g = gnet.cpu().numpy()
+        r["max_abs_grad_net"] = max(float(np.max(np.abs(g[:, s, :] - np.array(block["dzz"][j]))))
+                                    for j, s in enumerate(block["sets"]))
+    if obj is not None and "cost" in block:
+        c = np.array(block["cost"][:obj.shape[0]])
+        r["max_rel_cost"] = float(np.max(np.abs(obj.cpu().numpy() - c) / np.maximum(1.0, np.abs(c))))
+    if grad is not None and "grad" in block:
+        gr = np.array(block["grad"][:grad.shape[0]])
+        r["max_rel_grad"] = float(np.max(np.abs(grad.cpu().numpy() - gr)) / max(1.0, np.abs(gr).max()))
+    return r
+
+
+def config3_check(gold, n_edges, out, gnet, obj, grad):
+    """A p=2 batch's results against the stored oracle values: <Z_u Z_v> on 32
+    sampled (edge, set) pairs and d<Z_u Z_v>/d(params) on 2 of them; and the
+    objective and its gradient against the per-network results they combine
+    (obj = |E|/2 - sum Re / 2, grad = -sum grad_net / 2)."""
+    o, gn, ob, gr = out.cpu().numpy(), gnet.cpu().numpy(), obj.cpu().numpy(), grad.cpu().numpy()
+    err_zz = max(abs(o[i, s, 0] - v) for i, s, v in gold["values"])
+    err_g = max(float(np.max(np.abs(gn[i, s] - np.array(g)))) for i, s, g in gold["grads"])
+    err_obj = float(np.max(np.abs(ob - (n_edges / 2 - 0.5 * o[:, :, 0].sum(axis=0)))))
+    err_gsum = float(np.max(np.abs(gr + 0.5 * gn.sum(axis=0))))
+    ok = err_zz <= TOL_ZZ_BF16 and err_g <= TOL_G_BF16 and err_obj <= 1e-9 * n_edges and err_gsum <= 1e-9 * n_edges
+    return {"max_abs_zz_vs_oracle": float(err_zz), "max_abs_grad_vs_parameter_shift": err_g,
+            "obj_vs_values": err_obj, "grad_vs_grad_net": err_gsum,
+            "pairs_checked": len(gold["values"]), "grads_checked": len(gold["grads"]),
+            "tolerance": {"zz": TOL_ZZ_BF16, "grad": TOL_G_BF16}, "ok": bool(ok)}
+
+
+P1_N, P1_D = 100, 3  # the 3-regular n=100 p=1 batch (plain path, batched p=1 row, rows past the hot path)
+
+
+def next_rows(model, params, edges, st, dev, refs):
+    """Rows past the hot path, on the 3-regular n=100 p=1 batch: angle
+    optimisation on the adjoint gradient, answer-string estimation, the
+    batched pass with noise channels and with diagonal gates."""
+    N_VERT, P_LAYERS = P1_N, 1
     import torch
     import workloads
     from paper_1709_03636_amd import answer, noise, optimize, qaoa, qtn
@@ -149,7 +231,7 @@ def next_rows(model, params, edges, st, dev):
     k = int(fb.argmax())
     best = xb[k].cpu().numpy()
     res["angle_optimisation"] = {
-        "workload": f"Adam ascent of <C>, QAOA p={P_LAYERS} on the headline graph, {params.shape[0]} starts at once",
+        "workload": f"Adam ascent of <C>, QAOA p=1 on the 3-regular n=100 graph, {params.shape[0]} starts at once",
         "steps": steps, "ms_per_iteration": dt / (steps + 1) * 1e3, "start_best_cost": float(trace[0]),
         "final_best_cost": float(fb[k]), "edges": len(edges), "best_angles": best.tolist()}
     log(f"optimisation: {res['angle_optimisation']}")
@@ -201,19 +283,18 @@ def next_rows(model, params, edges, st, dev):
         nm.batch.grad(params, stream=st)
     ev1.record(st)
     torch.cuda.synchronize()
-    n_t, k_ms = nm.batch.kernel_time()
+    n_t, k_ms = nm.batch.kernel_time(0)
     nm.batch.kernel_timing(False)
     ms = ev0.elapsed_time(ev1) / reps
     ninfo = nm.batch.info()
     res["noise"] = {
-        "workload": "headline batch with a depolarizing channel (p = 0.01) after every gate on each of its qubits "
+        "workload": "the p=1 batch with a depolarizing channel (p = 0.01) after every gate on each of its qubits "
                     "(folded superoperator tensors, light cone kept: trace preserving)",
         "fwd_grad_networks_per_s": len(edges) * N_SETS / (ms * 1e-3), "ms_per_pass": ms,
         "fused_kernel_us": k_ms / max(1, n_t) * 1e3, "n_programs": ninfo["n_programs"]}
     log(f"noise: {res['noise']}")
 
-    # diagonal gates as hyperedge tensors: the headline batch, and whole-circuit networks
-    from oracle import closed_form
+    # diagonal gates as hyperedge tensors: the p=1 batch, and whole-circuit networks
     dm = qaoa.MaxCut(N_VERT, edges, P_LAYERS, qtn.TN_C64, order="linegraph", max_sets=N_SETS, trials=4,
                      diagonal=True)
     dm.batch.autotune(params, reps=10, stream=st)
@@ -223,8 +304,7 @@ def next_rows(model, params, edges, st, dev):
     dm.batch.grad(params, out=out, obj=obj, grad=grad, stream=st)
     st.synchronize()
     ang = params.cpu().numpy()
-    err = max(float(np.max(np.abs(out[:, s, 0].cpu().numpy() - closed_form.zz_p1(N_VERT, edges, *ang[s]))))
-              for s in range(N_SETS))
+    err = p1_errors(refs["d3_n100_p1"], out)["max_abs_zz"]
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     timed = {}
     for wg in (True, False):
@@ -239,7 +319,7 @@ def next_rows(model, params, edges, st, dev):
     dm.batch.kernel_timing(True)
     for _ in range(20):
         dm.batch.grad(params, stream=st)
-    n_t, k_ms = dm.batch.kernel_time()
+    n_t, k_ms = dm.batch.kernel_time(0)
     dm.batch.kernel_timing(False)
     dinfo = dm.batch.info()
     whole = {}
@@ -255,11 +335,11 @@ def next_rows(model, params, edges, st, dev):
         for _ in range(3):
             v = net.contract(a0, stream=st)
         ms = (time.perf_counter() - t0) / 3 * 1e3
+        zz_ref = refs["whole_circuit_edge0_set0"][f"d{dd}_n{dn}"]["zz_edge0"]
         whole[f"d{dd}_n{dn}"] = {"peak_bits": pinfo["peak_bits"], "flops": pinfo["flops"], "bytes": pinfo["bytes"],
-                                 "ms_per_contraction": ms,
-                                 "abs_err_zz_vs_closed_form": abs(v.real - closed_form.zz_p1(dn, de, *a0)[0])}
+                                 "ms_per_contraction": ms, "abs_err_zz_vs_closed_form": abs(v.real - zz_ref)}
     res["diagonal"] = {
-        "workload": "the headline batch with ZZ gates as 16-entry diagonal tensors on hyperedge wires "
+        "workload": "the p=1 batch with ZZ gates as 16-entry diagonal tensors on hyperedge wires "
                     "(exact; the paper keeps gates dense), complex64",
         "fwd_grad_networks_per_s": len(edges) * N_SETS / (timed[True] * 1e-3), "ms_per_step": timed[True],
         "fwd_networks_per_s": len(edges) * N_SETS / (timed[False] * 1e-3), "ms_per_step_fwd": timed[False],
@@ -270,20 +350,22 @@ def next_rows(model, params, edges, st, dev):
     return res
 
 
-def batching_grid(st, dev, cases=None):
+def batching_grid(st, dev, refs, cases=None):
     """The batching configurations: seeded random 4- and 5-regular graphs with
     n in {50, 70, 100}, p in {1, 2}; all edge light-cone networks x 64 angle
     sets per batch, forward + adjoint gradient from a captured graph, complex64
     with split-BF16 matrix-core products (FP32 accumulation). Also the same
     batches with the diagonal gates on hyperedge wires. Error against the FP64
-    oracle: closed form for every edge and set at p = 1, the oracle's
-    light-cone contraction on 4 sampled (edge, set) pairs at p = 2."""
+    oracle (stored values): closed form on every edge of 4 angle sets at p = 1,
+    the oracle's light-cone contraction on 32 sampled (edge, set) pairs and the
+    parameter-shift gradient on 2 of them at p = 2, checked on the last
+    replay."""
     import torch
     import workloads
-    from oracle import closed_form, gates, tensornet
     from paper_1709_03636_amd import qaoa, qtn
     rows = []
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    p1 = {(b["d"], b["n"]): b for b in refs["grid_p1"]}
     for d in (4, 5):
         for n in (50, 70, 100):
             for p in (1, 2):
@@ -292,19 +374,6 @@ def batching_grid(st, dev, cases=None):
                 e = workloads.random_regular_graph(d, n, GRAPH_SEED)
                 ang = np.array(workloads.qaoa_angles(ANGLE_SEED, N_SETS, p))
                 prm = torch.tensor(ang, dtype=torch.float64, device=dev)
-                if p == 1:
-                    ref = {(i, s): v for s in range(N_SETS)
-                           for i, v in enumerate(closed_form.zz_p1(n, e, ang[s, 0], ang[s, 1]))}
-                else:
-                    rng = workloads.SplitMix64(d * 1000 + n)
-                    ref = {}
-                    for _ in range(4):
-                        i, s = rng.below(len(e)), rng.below(N_SETS)
-                        gl = gates.qaoa_gate_list(n, e, ang[s, :p], ang[s, p:])[n:]
-                        pauli = [0] * n
-                        pauli[e[i][0]] = pauli[e[i][1]] = 3
-                        ref[(i, s)] = tensornet.expectation(n, gl, pauli, init=[np.array([1.0, 1.0]) / math.sqrt(2)] * n,
-                                                            lightcone=True).real
                 row = {"d": d, "n": n, "p": p, "edges": len(e)}
                 for mode in ("dense", "diagonal"):
                     m = qaoa.MaxCut(n, e, p, qtn.TN_C64, order="linegraph", max_sets=N_SETS, trials=GRID_TRIALS[p],
@@ -312,50 +381,54 @@ def batching_grid(st, dev, cases=None):
                     m.batch.set_precision(qtn.TN_MFMA_BF16X3)
                     m.batch.autotune(prm, reps=2, stream=st)
                     out = torch.empty((len(e), N_SETS, 2), dtype=torch.float64, device=dev)
+                    gnet = torch.empty((len(e), N_SETS, 2 * p), dtype=torch.float64, device=dev)
                     obj = torch.empty(N_SETS, dtype=torch.float64, device=dev)
                     grad = torch.empty((N_SETS, 2 * p), dtype=torch.float64, device=dev)
-                    m.batch.grad(prm, out=out, obj=obj, grad=grad, stream=st)
-                    st.synchronize()
-                    o = out.cpu().numpy()
-                    err = max(abs(o[i, s, 0] - v) for (i, s), v in ref.items())
                     t = {}
-                    for wg in (True, False):
+                    for wg in (False, True):
+                        def rep():
+                            m.batch.run_graph(wg, prm, out=out, obj=obj, grad=grad if wg else None,
+                                              grad_net=gnet if wg else None, stream=st)
                         for _ in range(2):
-                            m.batch.run_graph(wg, prm, obj=obj, grad=grad if wg else None, stream=st)
+                            rep()
                         reps = 3
                         ev0.record(st)
                         for _ in range(reps):
-                            m.batch.run_graph(wg, prm, obj=obj, grad=grad if wg else None, stream=st)
+                            rep()
                         ev1.record(st)
                         torch.cuda.synchronize()
                         t[wg] = ev0.elapsed_time(ev1) / reps
+                    if p == 1:
+                        chk = p1_errors(p1[(d, n)], out, gnet)
+                    else:
+                        chk = config3_check(refs["config3_p2"][(d, n)], len(e), out, gnet, obj, grad)
                     ms = t[True]
                     inf = m.batch.info()
                     row[mode] = {"ms_per_step": ms, "fwd_grad_networks_per_s": len(e) * N_SETS / (ms * 1e-3),
                                  "ms_per_step_fwd": t[False],
                                  "fwd_networks_per_s": len(e) * N_SETS / (t[False] * 1e-3),
-                                 "max_abs_err_zz": float(err),
+                                 "check_vs_oracle": chk,
                                  "executors": {"lds_fused": inf["n_fused"], "global_arena": inf["n_global"],
-                                               "level": inf["n_level"]},
+                                               "level": inf["n_level"], "level_task_groups": inf["n_level_tasked"]},
                                  "flops_per_set": inf["flops_fwd"] + inf["flops_grad"]}
                     del m
                 rows.append(row)
                 log(f"batching grid: {row}")
     return {"workload": "all edge light-cone networks x 64 angle sets, fwd + adjoint grad, graph replay, complex64 "
                         "with split-BF16 matrix-core products; diagonal: ZZ gates on hyperedge wires",
-            "oracle_check": "closed form, all edges and sets (p=1); FP64 light-cone contraction, 4 sampled (edge, "
-                            "set) pairs (p=2)",
+            "oracle_check": "stored FP64 oracle values: closed form on every edge of 4 angle sets (p=1); light-cone "
+                            "contraction on 32 sampled (edge, set) pairs and parameter shift on 2 (p=2); last replay",
             "rows": rows}
 
 
-def differentiation(st, dev):
+def differentiation(st, dev, refs):
     """QAOA p=2 on the seeded 3-regular graph with 60 vertices (90 edge
     networks) x 64 angle sets: forward + adjoint gradient from a captured
-    graph, complex64; error of <C> on every set against light-cone state
-    vectors, of the gradient on one set against the parameter-shift rule."""
+    graph, complex64; error of <C> on 4 sets against light-cone state vectors
+    and of the gradient on one set against the parameter-shift rule (stored
+    oracle values)."""
     import torch
     import workloads
-    from oracle import gradients, statevector
     from paper_1709_03636_amd import qaoa, qtn
     n, p = 60, 2
     e = workloads.random_regular_graph(3, n, GRAPH_SEED)
@@ -379,14 +452,10 @@ def differentiation(st, dev):
     m.batch.run_graph(True, prm, obj=obj, grad=grad, stream=st)
     torch.cuda.synchronize()
     ob, gr = obj.cpu().numpy(), grad.cpu().numpy()
-    err_c = 0.0
-    for s in range(0, N_SETS, 16):
-        zz = np.array([statevector.qaoa_zz_edge(n, e, ang[s, :p], ang[s, p:], ed) for ed in e])
-        c_ref = float(np.sum((1 - zz) / 2))
-        err_c = max(err_c, abs(ob[s] - c_ref) / c_ref)
-    s = 1
-    ps = sum(-0.5 * gradients.parameter_shift_edge(n, e, ang[s], ed) for ed in e)
-    err_g = float(np.max(np.abs(gr[s] - ps)) / max(1.0, np.abs(ps).max()))
+    r = refs["d3_n60_p2"]
+    err_c = max(abs(ob[s] - c) / c for s, c in zip(r["cost_sets"], r["cost"]))
+    ps = np.array(r["grad"])
+    err_g = float(np.max(np.abs(gr[r["grad_set"]] - ps)) / max(1.0, np.abs(ps).max()))
     info = m.batch.info()
     res = {"workload": "QAOA p=2 Max-Cut, random 3-regular n=60 (90 edge light-cone networks) x 64 angle sets, "
                        "fwd + adjoint gradient (4 entries), complex64, graph replay",
@@ -399,17 +468,17 @@ def differentiation(st, dev):
     return res
 
 
-def crossover(st, dev):
+def crossover(st, dev, refs):
     """Tensor-network contraction against Hilbert-space simulation, QAOA p=1 on
     seeded random d-regular graphs with 30 vertices, d = 3..7 (the paper's
     crossover in degree): time per <C> (all edges) of the full complex64 state
     vector on this GPU, of the batched light-cone networks (one angle set),
     and of the whole-circuit folded networks (dense and diagonal gates) where
     their largest intermediate fits (edge 0 timed, times |E|); n = 40 for the
-    light-cone networks, where the state vector (8 TiB) does not fit."""
+    light-cone networks, where the state vector (8 TiB) does not fit.
+    Errors against the stored closed-form values."""
     import torch
     import workloads
-    from oracle import closed_form
     from paper_1709_03636_amd import qaoa, qtn
     g0, b0 = 0.4, 0.3
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -418,7 +487,8 @@ def crossover(st, dev):
     for n in (30, 40):
         for d in (3, 4, 5, 6, 7):
             e = workloads.random_regular_graph(d, n, GRAPH_SEED)
-            ref = closed_form.cost_p1(n, e, g0, b0)
+            cr = next(r for r in refs["crossover_g0.4_b0.3"] if r["d"] == d and r["n"] == n)
+            ref = cr["cost"]
             row = {"d": d, "n": n, "edges": len(e), "cost_closed_form": ref}
             if n <= 30:
                 need = qtn.lib().tn_sv_workspace_bytes(n)
@@ -460,7 +530,7 @@ def crossover(st, dev):
                         z = net.contract([g0, b0], stream=st)
                         r["ms_per_edge"] = (time.perf_counter() - t0) * 1e3
                         r["ms_per_cost_estimate"] = r["ms_per_edge"] * len(e)
-                        r["abs_err_zz_edge0"] = abs(z.real - closed_form.zz_p1(n, e, g0, b0)[0])
+                        r["abs_err_zz_edge0"] = abs(z.real - cr["zz_edge0"])
                     else:
                         r["infeasible"] = "largest intermediate beyond 2^28 entries or work beyond 2e13 flops"
                     row[f"tn_whole_circuit_{mode}"] = r
@@ -472,16 +542,278 @@ def crossover(st, dev):
             "rows": rows}
 
 
+def executor_rooflines(model, params, st, steps, n_sets, prec_name):
+    """Each executor's kernel on eager passes (HIP events around each launch,
+    on its stream): average duration, algorithmic rates and roofline figures.
+    Level (task executor): bound by the matrix cores, priced at the executed
+    precision (split-BF16: three bf16 products per real product), with the
+    FP32-equivalent rate beside it. Fused executors (thin contractions on the
+    vector units, operands in LDS or L2): bound by vector instruction issue,
+    priced against the FP32 vector peak."""
+    import torch
+    from paper_1709_03636_amd import qtn
+    info = model.batch.info()
+    for _ in range(2):
+        model.batch.grad(params, stream=st)
+    torch.cuda.synchronize()
+    model.batch.kernel_timing(True)
+    for _ in range(steps):
+        model.batch.grad(params, stream=st)
+    torch.cuda.synchronize()
+    res = {}
+    names = {qtn.TN_EXEC_FUSED: "lds_fused", qtn.TN_EXEC_LEVEL: "level", qtn.TN_EXEC_GLOBAL: "global_arena"}
+    for ex, name in names.items():
+        n_t, total = model.batch.kernel_time(ex)
+        if n_t == 0:
+            continue
+        ms = total / n_t
+        flops = info["exec_flops"][ex] * n_sets
+        byts = info["exec_bytes"][ex] * n_sets
+        r = {"launches_timed": n_t, "kernel_ms": ms, "algorithmic_flops_per_launch": flops,
+             "algorithmic_bytes_per_launch": byts, "fp32_equiv_tflops": flops / (ms * 1e-3) / 1e12}
+        if ex == qtn.TN_EXEC_LEVEL:
+            mf = info["level_mfma_flops"] * n_sets
+            mult, peak = (3.0, BF16_MFMA_PEAK) if prec_name == "bf16x3" else (1.0, FP32_MFMA_PEAK)
+            if prec_name == "fp64":
+                peak = FP64_MFMA_PEAK
+            ach = mult * mf / (ms * 1e-3)
+            r.update({"bound": "mfma", "matrix_core_share_of_flops": mf / max(flops, 1.0),
+                      "executed_precision": prec_name, "achieved": ach / 1e12, "peak": peak / 1e12,
+                      "unit": "TFLOP/s", "frac": ach / peak,
+                      "fp32_equiv_frac_of_fp32_matrix_peak": flops / (ms * 1e-3) / FP32_MFMA_PEAK})
+        else:
+            ach = flops / (ms * 1e-3)
+            r.update({"bound": "alu", "achieved": ach / 1e12, "peak": FP32_VALU_PEAK / 1e12, "unit": "TFLOP/s",
+                      "frac": ach / FP32_VALU_PEAK, "algorithmic_gbps": byts / (ms * 1e-3) / 1e9})
+        res[name] = r
+    model.batch.kernel_timing(False)
+    return res
+
+
+def headline(args, st, dev, refs):
+    """The timed step on the headline workload, its post-timing oracle check,
+    and the executors' kernel figures."""
+    import torch
+    import workloads
+    from paper_1709_03636_amd import qtn, qaoa
+    d, n, p = HEAD_D, HEAD_N, HEAD_P
+    edges = workloads.random_regular_graph(d, n, GRAPH_SEED)
+    angles = np.array(workloads.qaoa_angles(ANGLE_SEED, N_SETS, p))
+    n_nets = len(edges)
+    log(f"headline: d={d} n={n} p={p} edges={n_nets} sets={N_SETS}")
+    t0 = time.perf_counter()
+    model = qaoa.MaxCut(n, edges, p, qtn.TN_C64, order="linegraph", max_sets=N_SETS, trials=GRID_TRIALS[p])
+    plan_s = time.perf_counter() - t0
+    model.batch.set_precision(qtn.TN_MFMA_BF16X3)
+    params = torch.tensor(angles, dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    model.batch.autotune(params, reps=2, stream=st)
+    st.synchronize()
+    tune_s = time.perf_counter() - t0
+    info = model.batch.info()
+    log(f"planned in {plan_s:.1f}s, autotuned in {tune_s:.1f}s: {info}")
+    out = torch.empty((n_nets, N_SETS, 2), dtype=torch.float64, device=dev)
+    gnet = torch.empty((n_nets, N_SETS, 2 * p), dtype=torch.float64, device=dev)
+    obj = torch.empty(N_SETS, dtype=torch.float64, device=dev)
+    grad = torch.empty((N_SETS, 2 * p), dtype=torch.float64, device=dev)
+
+    def replay(with_grad):
+        model.batch.run_graph(with_grad, params, out=out, obj=obj, grad=grad if with_grad else None,
+                              grad_net=gnet if with_grad else None, stream=st)
+
+    for _ in range(args.warmup):
+        replay(True)
+    torch.cuda.synchronize()
+    out.fill_(float("nan"))
+    gnet.fill_(float("nan"))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    ev0.record(st)
+    for _ in range(args.steps):
+        replay(True)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    value = n_nets * N_SETS / (ms_step * 1e-3)
+    log(f"fwd+grad: {ms_step:.3f} ms/step, {value:.4e} networks/s (wall {wall:.3f}s for {args.steps} steps)")
+    # the last timed replay's results against the oracle
+    check = config3_check(refs["config3_p2"][(d, n)], n_nets, out, gnet, obj, grad)
+    log(f"post-timing check: {check}")
+    # forward only
+    for _ in range(args.warmup):
+        replay(False)
+    ev0.record(st)
+    for _ in range(args.steps):
+        replay(False)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    ms_fwd = ev0.elapsed_time(ev1) / args.steps
+    log(f"fwd: {ms_fwd:.3f} ms/step")
+    kern = executor_rooflines(model, params, st, max(3, min(args.steps, 10)), N_SETS, "bf16x3")
+    log(f"executor kernels: {kern}")
+    return {"value": value, "ms_per_step": ms_step, "wall_s": wall, "ms_per_step_fwd": ms_fwd,
+            "fwd_networks_per_s": n_nets * N_SETS / (ms_fwd * 1e-3), "n_nets": n_nets, "check": check,
+            "kernels": kern, "info": info, "plan_s": plan_s, "autotune_s": tune_s, "edges": edges,
+            "angles": angles}
+
+
+def p1_rows(args, st, dev, refs):
+    """The 3-regular n=100 p=1 batch x 64 angle sets: batched fwd+grad (graph
+    replay, FP32 products), its fused kernel's figures, and the plain path
+    (one network per launch) in complex64 and complex128."""
+    import torch
+    import workloads
+    from paper_1709_03636_amd import qtn, qaoa
+    n, p = P1_N, 1
+    edges = workloads.random_regular_graph(P1_D, n, GRAPH_SEED)
+    angles = np.array(workloads.qaoa_angles(ANGLE_SEED, N_SETS, p))
+    model = qaoa.MaxCut(n, edges, p, qtn.TN_C64, order="linegraph", max_sets=N_SETS, trials=GRID_TRIALS[p])
+    params = torch.tensor(angles, dtype=torch.float64, device=dev)
+    model.batch.autotune(params, reps=10, stream=st)
+    info = model.batch.info()
+    out = torch.empty((len(edges), N_SETS, 2), dtype=torch.float64, device=dev)
+    gnet = torch.empty((len(edges), N_SETS, 2), dtype=torch.float64, device=dev)
+    obj = torch.empty(N_SETS, dtype=torch.float64, device=dev)
+    grad = torch.empty((N_SETS, 2), dtype=torch.float64, device=dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    timed = {}
+    for wg in (True, False):
+        def rep():
+            model.batch.run_graph(wg, params, out=out, obj=obj, grad=grad if wg else None,
+                                  grad_net=gnet if wg else None, stream=st)
+        for _ in range(5):
+            rep()
+        ev0.record(st)
+        for _ in range(args.steps):
+            rep()
+        ev1.record(st)
+        torch.cuda.synchronize()
+        timed[wg] = ev0.elapsed_time(ev1) / args.steps
+        if wg:
+            chk = p1_errors(refs["d3_n100_p1"], out, gnet, obj, grad)
+    kern = executor_rooflines(model, params, st, args.steps, N_SETS, "fp32")
+    if info["sets_per_wave_grad"] > 1:
+        kname = f"fused_sets_kernel<float, true, {6 - info['sets_per_wave_grad'] // 2}>"
+    else:
+        kname = (f"fused_exec_kernel<float, {info['fused_block']}, true, "
+                 f"{'true' if info['rec_only'] & 2 else 'false'}, false>")
+    if "lds_fused" in kern:
+        kern["lds_fused"]["kernel"] = kname
+        kern["lds_fused"]["bound_note"] = ("operands stay in LDS (HBM traffic is a small fraction of the "
+                                           "algorithmic bytes); the limiter is vector instruction issue")
+        kern["lds_fused"]["traffic"] = traffic_from_profile("fused_exec_grad.qaoa_d3_n100_p1_s64", kname)
+    batched = {"workload": f"QAOA p=1 Max-Cut, random 3-regular graph n={n} ({len(edges)} edge light-cone networks) "
+                           f"x {N_SETS} angle sets, fwd + adjoint grad, complex64 (FP32), graph replay",
+               "ms_per_step": timed[True], "fwd_grad_networks_per_s": len(edges) * N_SETS / (timed[True] * 1e-3),
+               "ms_per_step_fwd": timed[False], "fwd_networks_per_s": len(edges) * N_SETS / (timed[False] * 1e-3),
+               "check_vs_closed_form": chk, "kernels": kern}
+    log(f"p=1 batch: {batched}")
+    # plain path: one network per launch, complex64 and complex128 (host sync per network)
+    plain = {}
+    blk = refs["d3_n100_p1"]
+    for name, dt in (("c64", qtn.TN_C64), ("c128", qtn.TN_C128)):
+        nets = qaoa.edge_networks(n, edges, p, dt, order="linegraph", trials=4)
+        a0 = angles[0]
+        for net in nets:  # plan-time device set-up of every network, outside the timed loops
+            net.contract(a0, stream=st)
+            net.grad(a0, stream=st)
+        t0 = time.perf_counter()
+        vals = [net.contract(a0, stream=st) for net in nets]
+        dtp = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        grads = [net.grad(a0, stream=st) for net in nets]
+        dtg = time.perf_counter() - t0
+        zz = np.array(blk["zz"][blk["sets"].index(0)])
+        dzz = np.array(blk["dzz"][blk["sets"].index(0)])
+        gerr = max(float(np.max(np.abs(g - dzz[i]))) for i, (_, g) in enumerate(grads))
+        plain[name] = {"networks_per_s": len(nets) / dtp,
+                       "max_abs_err_zz": float(np.max(np.abs(np.array(vals).real - zz))),
+                       "fwd_grad_networks_per_s": len(nets) / dtg, "max_abs_err_grad": gerr}
+        log(f"plain {name}: {plain[name]}")
+    return model, params, edges, angles, batched, plain
+
+
+def dense_row(st, dev, refs, angles):
+    """The dense regime on the matrix cores: the whole-circuit network of one
+    edge, 6-regular n=20, p=1 (no light cone), FP32 4M, split-BF16 and FP64
+    products."""
+    import torch
+    import workloads
+    from paper_1709_03636_amd import qtn, qaoa
+    dd, dn = 6, 20
+    ref = refs["whole_circuit_edge0_set0"][f"d{dd}_n{dn}"]
+    de = workloads.random_regular_graph(dd, dn, GRAPH_SEED)
+    a0 = np.array(workloads.qaoa_angles(ANGLE_SEED, N_SETS, 1))[0]
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ev0.record(st)
+        for _ in range(reps):
+            fn()
+        ev1.record(st)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    dnet = qaoa.edge_network(dn, de, 1, de[0], dtype=qtn.TN_C64, lightcone=False)
+    dnet.set_order(dnet.order_linegraph(trials=8, seed=0))
+    dinfo = dnet.plan_info()
+    dbatch = qtn.Batch([dnet], max_sets=1)
+    dpar = torch.tensor([a0], dtype=torch.float64, device=dev)
+    dbatch.autotune(dpar, reps=2, stream=st)
+    dout = torch.empty((1, 1, 2), dtype=torch.float64, device=dev)
+    d_ms = timed(lambda: dbatch.contract(dpar, out=dout, stream=st))
+    v32 = dout[0, 0, 0].item()
+    dgn = torch.empty((1, 1, 2), dtype=torch.float64, device=dev)
+    doutg = torch.empty_like(dout)
+    g_ms = timed(lambda: dbatch.grad(dpar, out=doutg, grad_net=dgn, stream=st))
+    dbi = dbatch.info()
+    g_flops = dbi["flops_fwd"] + dbi["flops_grad"]
+    g_err = float(np.max(np.abs(dgn[0, 0].cpu().numpy() - np.array(ref["dzz_edge0"]))))
+    dbatch.set_precision(qtn.TN_MFMA_BF16X3)
+    dbatch.autotune(dpar, reps=2, stream=st)
+    dout2 = torch.empty_like(dout)
+    b_ms = timed(lambda: dbatch.contract(dpar, out=dout2, stream=st))
+    dnet128 = qaoa.edge_network(dn, de, 1, de[0], dtype=qtn.TN_C128, lightcone=False)
+    dnet128.set_order(dnet128.order_linegraph(trials=8, seed=0))
+    dbatch128 = qtn.Batch([dnet128], max_sets=1)
+    dbatch128.autotune(dpar, reps=2, stream=st)
+    dout3 = torch.empty_like(dout)
+    f_ms = timed(lambda: dbatch128.contract(dpar, out=dout3, stream=st))
+    zz_ref = ref["zz_edge0"]
+    mfma = {"workload": f"whole-circuit folded network of one edge, QAOA p=1, {dd}-regular n={dn} "
+                        f"(no light cone), line-graph order, complex64, 4M FP32 matrix-core products",
+            "peak_bits": dinfo["peak_bits"], "flops_per_pass": dinfo["flops"], "pass_ms": d_ms,
+            "tflops": dinfo["flops"] / (d_ms * 1e-3) / 1e12,
+            "frac_of_fp32_matrix_peak": dinfo["flops"] / (d_ms * 1e-3) / FP32_MFMA_PEAK,
+            "abs_err_zz_vs_closed_form": abs(v32 - zz_ref),
+            "fwd_grad": {"pass_ms": g_ms, "flops_per_pass": g_flops, "tflops": g_flops / (g_ms * 1e-3) / 1e12,
+                         "frac_of_fp32_matrix_peak": g_flops / (g_ms * 1e-3) / FP32_MFMA_PEAK,
+                         "abs_err_grad_vs_closed_form": g_err},
+            "split_bf16": {"pass_ms": b_ms, "tflops_fp32_equivalent": dinfo["flops"] / (b_ms * 1e-3) / 1e12,
+                           "executed_bf16_frac_of_bf16_peak": 3 * dinfo["flops"] / (b_ms * 1e-3) / BF16_MFMA_PEAK,
+                           "abs_err_zz_vs_closed_form": abs(dout2[0, 0, 0].item() - zz_ref)},
+            "complex128_fp64": {"pass_ms": f_ms, "tflops": dinfo["flops"] / (f_ms * 1e-3) / 1e12,
+                                "frac_of_fp64_matrix_peak": dinfo["flops"] / (f_ms * 1e-3) / FP64_MFMA_PEAK,
+                                "abs_err_zz_vs_closed_form": abs(dout3[0, 0, 0].item() - zz_ref)}}
+    log(f"dense/MFMA: {mfma}")
+    return mfma
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-next", action="store_true", help="skip the optimisation / answer-string / noise lines")
-    ap.add_argument("--no-grid", action="store_true", help="skip the 4-/5-regular batching grid")
+    ap.add_argument("--no-grid", action="store_true", help="skip the batching grid, differentiation and crossover")
+    ap.add_argument("--headline-only", action="store_true", help="only the headline measurement (for profiling)")
     ap.add_argument("--extras", action="store_true",
                     help="only the batching grid, differentiation and crossover rows, as one JSON line")
     ap.add_argument("--grid-case", action="append", default=None,
@@ -496,217 +828,47 @@ def main():
         return
 
     import torch
-    import workloads
-    from paper_1709_03636_amd import qtn, qaoa
 
     dev = torch.device("cuda:0")
+    refs = load_refs()
     if args.grid_case:
         cases = {tuple(int(x) for x in c.split(",")) for c in args.grid_case}
-        print(json.dumps(batching_grid(torch.cuda.Stream(), dev, cases=cases)), flush=True)
+        print(json.dumps(batching_grid(torch.cuda.Stream(), dev, refs, cases=cases)), flush=True)
         return
     if args.extras:
         st = torch.cuda.Stream()
-        print(json.dumps({"batching_grid": batching_grid(st, dev), "differentiation_p2_n60": differentiation(st, dev),
-                          "crossover_in_degree": crossover(st, dev)}), flush=True)
+        print(json.dumps({"batching_grid": batching_grid(st, dev, refs),
+                          "differentiation_p2_n60": differentiation(st, dev, refs),
+                          "crossover_in_degree": crossover(st, dev, refs)}), flush=True)
         return
-    edges = workloads.random_regular_graph(D, N_VERT, GRAPH_SEED)
-    angles = np.array(workloads.qaoa_angles(ANGLE_SEED, N_SETS, P_LAYERS))
-    n_nets = len(edges)
-    log(f"workload d={D} n={N_VERT} p={P_LAYERS} edges={n_nets} sets={N_SETS}")
-
-    t0 = time.perf_counter()
-    model = qaoa.MaxCut(N_VERT, edges, P_LAYERS, qtn.TN_C64, order="linegraph", max_sets=N_SETS, trials=4)
-    info = model.batch.info()
-    log(f"plans compiled in {time.perf_counter() - t0:.2f}s: {info}")
-    params = torch.tensor(angles, dtype=torch.float64, device=dev)
-    out = torch.empty((n_nets, N_SETS, 2), dtype=torch.float64, device=dev)
-    obj = torch.empty(N_SETS, dtype=torch.float64, device=dev)
-    grad = torch.empty((N_SETS, 2 * P_LAYERS), dtype=torch.float64, device=dev)
-    gnet = torch.empty((n_nets, N_SETS, 2 * P_LAYERS), dtype=torch.float64, device=dev)
     st = torch.cuda.Stream()
-
-    # --- accuracy against the closed-form p=1 oracle ---------------------------------
-    from oracle import closed_form
-    model.batch.grad(params, out=out, obj=obj, grad=grad, grad_net=gnet, stream=st)
-    st.synchronize()
-    o, ob, gr = out.cpu().numpy(), obj.cpu().numpy(), grad.cpu().numpy()
-    err_zz = err_c = err_g = 0.0
-    for s in range(N_SETS):
-        zz = closed_form.zz_p1(N_VERT, edges, angles[s, 0], angles[s, 1])
-        dg, db = closed_form.zz_p1_grad(N_VERT, edges, angles[s, 0], angles[s, 1])
-        err_zz = max(err_zz, float(np.max(np.abs(o[:, s, 0] - zz))))
-        c_ref = float(np.sum((1 - zz) / 2))
-        err_c = max(err_c, abs(ob[s] - c_ref) / max(1.0, abs(c_ref)))
-        g_ref = np.array([-0.5 * dg.sum(), -0.5 * db.sum()])
-        err_g = max(err_g, float(np.max(np.abs(gr[s] - g_ref)) / max(1.0, np.abs(g_ref).max())))
-    log(f"error vs FP64 closed form: zz {err_zz:.2e}  <C> rel {err_c:.2e}  grad rel {err_g:.2e}")
-
-    # plan-time kernel choices (autotuner), outside the timed region
-    t0 = time.perf_counter()
-    model.batch.autotune(params, reps=10, stream=st)
-    st.synchronize()
-    info = model.batch.info()
-    log(f"autotuned in {time.perf_counter() - t0:.2f}s: {info}")
-    if info["sets_per_wave_grad"] > 1:
-        kname = f"fused_sets_kernel<float, true, {6 - info['sets_per_wave_grad'] // 2}>"
+    h = headline(args, st, dev, refs)
+    lvl = h["kernels"].get("level")
+    dom_name = max(h["kernels"], key=lambda k: h["kernels"][k]["kernel_ms"])
+    dom = h["kernels"][dom_name]
+    roofline = {k: dom[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+    roofline.update({"kernel": {"level": "task_kernel<2> (task executor, split-BF16)",
+                                "global_arena": "fused_exec_kernel<float, 256, true, false, true>",
+                                "lds_fused": "fused executor"}[dom_name],
+                     "executor": dom_name, "kernel_ms": dom["kernel_ms"], "launches_timed": dom["launches_timed"],
+                     "algorithmic_flops_per_launch": dom["algorithmic_flops_per_launch"],
+                     "algorithmic_bytes_per_launch": dom["algorithmic_bytes_per_launch"],
+                     "traffic": traffic_from_profile(f"{dom_name}.qaoa_d5_n100_p2_s64",
+                                                     roofline_kernel_symbol(dom_name))})
+    extra = {k: v for k, v in dom.items() if k not in roofline}
+    roofline.update({"detail": extra, "all_executors": h["kernels"]})
+    if not args.headline_only:
+        p1_model, p1_params, p1_edges, p1_angles, batched, plain = p1_rows(args, st, dev, refs)
+        mfma = None if args.no_dense else dense_row(st, dev, refs, p1_angles)
+        nxt = None if args.no_next else next_rows(p1_model, p1_params, p1_edges, st, dev, refs)
     else:
-        kname = (f"fused_exec_kernel<float, {info['fused_block']}, true, "
-                 f"{'true' if info['rec_only'] & 2 else 'false'}, false>")
-
-    # --- timed: fwd+grad steps from the captured graph ----------------------------------
-    def replay(with_grad):
-        model.batch.run_graph(with_grad, params, obj=obj, grad=grad if with_grad else None, stream=st)
-
-    for _ in range(args.warmup):
-        replay(True)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    ev0.record(st)
-    for _ in range(args.steps):
-        replay(True)
-    ev1.record(st)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    value = n_nets * N_SETS / (ms_step * 1e-3)
-    log(f"fwd+grad: {ms_step * 1e3:.1f} us/step, {value:.3e} networks/s (wall {wall:.3f}s)")
-
-    # forward only
-    for _ in range(args.warmup):
-        replay(False)
-    ev0.record(st)
-    for _ in range(args.steps):
-        replay(False)
-    ev1.record(st)
-    torch.cuda.synchronize()
-    ms_fwd = ev0.elapsed_time(ev1) / args.steps
-    log(f"fwd: {ms_fwd * 1e3:.1f} us/step")
-
-    # dominant kernel alone (fused executor, adjoint program): HIP events the
-    # library records on the launch stream right around each fused launch
-    for _ in range(args.warmup):
-        model.batch.grad(params, out=out, grad_net=gnet, stream=st)
-    model.batch.kernel_timing(True)
-    for _ in range(args.steps):
-        model.batch.grad(params, out=out, grad_net=gnet, stream=st)
-    n_timed, total_ms = model.batch.kernel_time()
-    model.batch.kernel_timing(False)
-    k_ms = total_ms / max(1, n_timed)
-    alg_bytes = (info["bytes_fwd"] + info["bytes_grad"]) * N_SETS
-    alg_flops = (info["flops_fwd"] + info["flops_grad"]) * N_SETS
-    achieved = alg_bytes / (k_ms * 1e-3)
-    log(f"fused kernel: {k_ms * 1e3:.1f} us, {achieved / 1e9:.1f} GB/s algorithmic, "
-        f"{alg_flops / (k_ms * 1e-3) / 1e12:.3f} TFLOP/s")
-
-    # plain path: one network per launch, complex64 and complex128 (host sync per network)
-    plain = {}
-    for name, dt in (("c64", qtn.TN_C64), ("c128", qtn.TN_C128)):
-        nets = qaoa.edge_networks(N_VERT, edges, P_LAYERS, dt, order="linegraph", trials=4)
-        a0 = angles[0]
-        for net in nets:  # plan-time device set-up of every network, outside the timed loops
-            net.contract(a0, stream=st)
-            net.grad(a0, stream=st)
-        t0 = time.perf_counter()
-        vals = [net.contract(a0, stream=st) for net in nets]
-        dtp = time.perf_counter() - t0
-        zz = closed_form.zz_p1(N_VERT, edges, a0[0], a0[1])
-        # forward plus adjoint gradient, one network per call (tn_grad)
-        t0 = time.perf_counter()
-        grads = [net.grad(a0, stream=st) for net in nets]
-        dtg = time.perf_counter() - t0
-        dg, db = closed_form.zz_p1_grad(N_VERT, edges, a0[0], a0[1])
-        gerr = max(float(np.max(np.abs(g - np.array([dg[i], db[i]])))) for i, (_, g) in enumerate(grads))
-        plain[name] = {"networks_per_s": len(nets) / dtp,
-                       "max_abs_err_zz": float(np.max(np.abs(np.array(vals).real - zz))),
-                       "fwd_grad_networks_per_s": len(nets) / dtg, "max_abs_err_grad": gerr}
-        log(f"plain {name}: {plain[name]}")
-
-    # dense regime (MFMA path): whole-circuit network of one edge, 6-regular n=20, p=1
-    mfma = None
-    if not args.no_dense:
-        dd, dn = 6, 20
-        de = workloads.random_regular_graph(dd, dn, GRAPH_SEED)
-        dnet = qaoa.edge_network(dn, de, 1, de[0], dtype=qtn.TN_C64, lightcone=False)
-        dnet.set_order(dnet.order_linegraph(trials=8, seed=0))
-        dinfo = dnet.plan_info()
-        dbatch = qtn.Batch([dnet], max_sets=1)
-        dpar = torch.tensor([angles[0]], dtype=torch.float64, device=dev)
-        dbatch.autotune(dpar, reps=2, stream=st)
-        dout = torch.empty((1, 1, 2), dtype=torch.float64, device=dev)
-        dbatch.contract(dpar, out=dout, stream=st)
-        st.synchronize()
-        reps = 5
-        ev0.record(st)
-        for _ in range(reps):
-            dbatch.contract(dpar, out=dout, stream=st)
-        ev1.record(st)
-        torch.cuda.synchronize()
-        d_ms = ev0.elapsed_time(ev1) / reps
-        zz_ref = closed_form.zz_p1(dn, de, angles[0, 0], angles[0, 1])[0]
-        # forward + adjoint gradient of the same network (FP32 products)
-        dgn = torch.empty((1, 1, 2), dtype=torch.float64, device=dev)
-        doutg = torch.empty_like(dout)
-        dbatch.grad(dpar, out=doutg, grad_net=dgn, stream=st)
-        st.synchronize()
-        ev0.record(st)
-        for _ in range(reps):
-            dbatch.grad(dpar, out=doutg, grad_net=dgn, stream=st)
-        ev1.record(st)
-        torch.cuda.synchronize()
-        g_ms = ev0.elapsed_time(ev1) / reps
-        dbi = dbatch.info()
-        g_flops = dbi["flops_fwd"] + dbi["flops_grad"]
-        dg_ref, db_ref = closed_form.zz_p1_grad(dn, de, angles[0, 0], angles[0, 1])
-        g_err = float(np.max(np.abs(dgn[0, 0].cpu().numpy() - np.array([dg_ref[0], db_ref[0]]))))
-        # split-BF16 products on the same network
-        dbatch.set_precision(qtn.TN_MFMA_BF16X3)
-        dbatch.autotune(dpar, reps=2, stream=st)
-        dout2 = torch.empty_like(dout)
-        dbatch.contract(dpar, out=dout2, stream=st)
-        ev0.record(st)
-        for _ in range(reps):
-            dbatch.contract(dpar, out=dout2, stream=st)
-        ev1.record(st)
-        torch.cuda.synchronize()
-        b_ms = ev0.elapsed_time(ev1) / reps
-        # complex128: FP64 matrix-core products on the same network
-        dnet128 = qaoa.edge_network(dn, de, 1, de[0], dtype=qtn.TN_C128, lightcone=False)
-        dnet128.set_order(dnet128.order_linegraph(trials=8, seed=0))
-        dbatch128 = qtn.Batch([dnet128], max_sets=1)
-        dbatch128.autotune(dpar, reps=2, stream=st)
-        dout3 = torch.empty_like(dout)
-        dbatch128.contract(dpar, out=dout3, stream=st)
-        ev0.record(st)
-        for _ in range(reps):
-            dbatch128.contract(dpar, out=dout3, stream=st)
-        ev1.record(st)
-        torch.cuda.synchronize()
-        f_ms = ev0.elapsed_time(ev1) / reps
-        mfma = {"workload": f"whole-circuit folded network of one edge, QAOA p=1, {dd}-regular n={dn} "
-                            f"(no light cone), line-graph order, complex64, 4M FP32 MFMA",
-                "peak_bits": dinfo["peak_bits"], "flops_per_pass": dinfo["flops"], "pass_ms": d_ms,
-                "tflops": dinfo["flops"] / (d_ms * 1e-3) / 1e12,
-                "frac_of_fp32_matrix_peak": dinfo["flops"] / (d_ms * 1e-3) / FP32_MFMA_PEAK,
-                "abs_err_zz_vs_closed_form": abs(dout[0, 0, 0].item() - zz_ref),
-                "fwd_grad": {"pass_ms": g_ms, "flops_per_pass": g_flops,
-                             "tflops": g_flops / (g_ms * 1e-3) / 1e12,
-                             "frac_of_fp32_matrix_peak": g_flops / (g_ms * 1e-3) / FP32_MFMA_PEAK,
-                             "abs_err_grad_vs_closed_form": g_err},
-                "split_bf16": {"pass_ms": b_ms, "tflops_fp32_equivalent": dinfo["flops"] / (b_ms * 1e-3) / 1e12,
-                               "abs_err_zz_vs_closed_form": abs(dout2[0, 0, 0].item() - zz_ref)},
-                "complex128_fp64": {"pass_ms": f_ms, "tflops": dinfo["flops"] / (f_ms * 1e-3) / 1e12,
-                                    "frac_of_fp64_matrix_peak": dinfo["flops"] / (f_ms * 1e-3) / FP64_MFMA_PEAK,
-                                    "abs_err_zz_vs_closed_form": abs(dout3[0, 0, 0].item() - zz_ref)}}
-        log(f"dense/MFMA: {mfma}")
-
-    nxt = None if args.no_next else next_rows(model, params, edges, st, dev)
+        p1_edges = p1_angles = batched = plain = mfma = nxt = None
     grid = diff = cross = None
-    if not args.no_grid:
+    if not args.no_grid and not args.headline_only:
         # the other configurations run in a child process (its own GPU context): a failure there is
         # recorded in their entries and does not take the headline measurement with it
         import subprocess
+        status = None
         try:
             r = subprocess.run([sys.executable, os.path.abspath(__file__), "--extras"], stdout=subprocess.PIPE,
                                text=True, timeout=1200)
@@ -720,45 +882,64 @@ def main():
             grid = diff = cross = {"error": f"child process exited with status {status}"}
             log(f"extras failed: exit status {status}")
 
-    cpu = None
+    cpu = cpu_p1 = None
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle) ...")
-        cpu = cpu_baseline(edges, angles)
+        cpu = cpu_baseline(HEAD_N, h["edges"], HEAD_P, h["angles"], 20.0,
+                           f"the headline batch (5-regular n={HEAD_N}, p={HEAD_P}, 64 angle sets)")
+        cpu["gpu_over_cpu"] = h["value"] / cpu["value"]
         log(f"cpu baseline: {cpu}")
+        if p1_edges is not None:
+            cpu_p1 = cpu_baseline(P1_N, p1_edges, 1, p1_angles, 6.0,
+                                  f"the 3-regular n={P1_N} p=1 batch (64 angle sets)")
+            log(f"cpu baseline p=1: {cpu_p1}")
 
+    check = h["check"]
     rec = {
-        "metric": "QAOA <ZZ> networks contracted/s (fwd+grad)",
-        "value": value,
-        "unit": "networks/s",
+        "metric": "QAOA <ZZ> networks contracted/s (fwd, fwd+grad), FP32 vs FP64 oracle err",
+        "value": h["value"],
+        "unit": "networks/s (fwd+grad)",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": h["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 (fp32 complex), fp64 final scalars and gradient sums",
-        "data": "synthetic",
-        "config": {"workload": f"QAOA Max-Cut p={P_LAYERS}, random {D}-regular graph n={N_VERT} "
-                               f"({n_nets} edge light-cone networks) x {N_SETS} angle sets, fwd + adjoint grad, "
-                               "line-graph order, one hipGraph replay per step",
-                   "networks_per_step": n_nets * N_SETS, "parallelism": "single GPU"},
-        "fwd_networks_per_s": n_nets * N_SETS / (ms_fwd * 1e-3),
-        "ms_per_step_fwd": ms_fwd,
-        "plain_one_network_per_launch": plain,
-        "error_vs_fp64_oracle": {"max_abs_zz": err_zz, "max_rel_cost": err_c, "max_rel_grad": err_g},
-        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK, "traffic": traffic_from_profile(kname),
-                     "kernel": kname, "kernel_us": k_ms * 1e3, "kernel_launches_timed": n_timed,
-                     "algorithmic_bytes_per_launch": alg_bytes, "algorithmic_flops_per_launch": alg_flops},
+        "dtype": "c64 (FP32 complex; split-BF16 matrix-core products, FP32 accumulation), FP64 final scalars and "
+                 "gradient sums",
+        "data": "synthetic (seeded random regular graphs and angle sets)",
+        "config": {"workload": f"QAOA Max-Cut p={HEAD_P}, random {HEAD_D}-regular graph n={HEAD_N} "
+                               f"({h['n_nets']} edge light-cone networks) x {N_SETS} angle sets, fwd + adjoint grad, "
+                               "line-graph order (best of 128 restarts), split-BF16 matrix-core products, "
+                               "one hipGraph replay per step",
+                   "networks_per_step": h["n_nets"] * N_SETS, "parallelism": "single GPU"},
+        "fwd_networks_per_s": h["fwd_networks_per_s"],
+        "ms_per_step_fwd": h["ms_per_step_fwd"],
+        "error_vs_fp64_oracle": check,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "executors": {"lds_fused": h["info"]["n_fused"], "global_arena": h["info"]["n_global"],
+                      "level": h["info"]["n_level"], "level_task_groups": h["info"]["n_level_tasked"]},
+        "plan_s": h["plan_s"], "autotune_s": h["autotune_s"],
+        "p1_batch_3regular_n100": batched,
+        "plain_one_network_per_launch_3regular_n100_p1": plain,
+        "cpu_baseline_p1_batch": cpu_p1,
         "mfma_path": mfma,
         "next_rows": nxt,
         "batching_grid": grid,
         "differentiation_p2_n60": diff,
         "crossover_in_degree": cross,
-        "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
+    if not check["ok"]:
+        log("headline results outside the oracle tolerance")
+        sys.exit(1)
+
+
+def roofline_kernel_symbol(executor):
+    return {"level": "task_kernel<2>", "global_arena": "fused_exec_kernel<float, 256, true, false, true>",
+            "lds_fused": "fused_exec_kernel"}[executor]
 
 
 if __name__ == "__main__":

@@ -271,6 +271,10 @@ typedef struct {
   int32_t level_split_grad;           /* index is split over workgroups: forward / forward+adjoint */
   double flops_fwd, bytes_fwd;        /* algorithmic, one parameter vector, all networks */
   double flops_grad, bytes_grad;      /* algorithmic, adjoint sweep only */
+  double exec_flops[3], exec_bytes[3];/* algorithmic forward + adjoint, one parameter vector, of the networks on
+                                         each executor (TN_EXEC_FUSED, TN_EXEC_LEVEL, TN_EXEC_GLOBAL) */
+  double level_mfma_flops;            /* of those on the level executor: the ops on the matrix cores with the
+                                         current precision and tuning (real flops, 8 per complex multiply-add) */
 } tn_batch_stats;
 
 int tn_batch_info(const tn_batch *b, tn_batch_stats *out);

@@ -159,6 +159,7 @@ struct tn_batch {
   std::map<std::string, int> use_mfma; // autotuner: shape class of a large op -> 1 MFMA, 0 thin
   int mfma_prec = TN_MFMA_FP32;        // matrix-core precision of large steps (complex128: TN_MFMA_FP64)
   double flops_fwd = 0, bytes_fwd = 0, flops_grad = 0, bytes_grad = 0;
+  double exec_flops[3] = {0, 0, 0}, exec_bytes[3] = {0, 0, 0};  // per executor (fused, level, global), fwd + adjoint
   int64_t level_bytes = 0;
   qtn::WsLayout ws;
   // device state (runtime.hip)

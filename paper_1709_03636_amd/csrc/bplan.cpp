@@ -1043,14 +1043,17 @@ int plan_batch(tn_net *const *nets, int n_nets, const double *coef, double offse
   std::vector<double> cost(n_nets);
   std::vector<int> fused_ids, gmem_ids;
   int maxbits = 0;
+  // executor of each network: the LDS fused executor when its memory fits
+  // LDS, the global-arena fused executor when its steps are small enough for
+  // one workgroup, else the level executor. When the level networks are many
+  // enough for the task executor anyway, the global-arena ones join them
+  // there (one launch, LDS-resident small tensors, matrix cores for the few
+  // large steps; measured faster on the 5-regular p=2 batches).
+  std::vector<int> cls(n_nets);
+  int n_level = 0, n_gmem = 0;
   for (int i = 0; i < n_nets; ++i) {
     const Net *n = reinterpret_cast<const Net *>(nets[i]);
     NetLayout lay = make_layout(*n);
-    cost[i] = n->gplan.flops + n->gplan.flops_grad + 1e3 * n->gplan.ops.size();
-    b->flops_fwd += n->gplan.flops;
-    b->bytes_fwd += n->gplan.bytes;
-    b->flops_grad += n->gplan.flops_grad;
-    b->bytes_grad += n->gplan.bytes_grad;
     double max_macs = 0, tot_macs = 0;
     for (const Op &op : n->gplan.ops)
       if (op.type == OP_CONTRACT || op.type == OP_SCALAR) {
@@ -1059,18 +1062,44 @@ int plan_batch(tn_net *const *nets, int n_nets, const double *coef, double offse
         tot_macs += m;
       }
     const int64_t mem_elems = lay.leaf_region + std::max(lay.arena[0], lay.arena[1]);
-    if (fused_lds_need(*n, lay, eb, b->n_params) <= fused_max) {
+    if (fused_lds_need(*n, lay, eb, b->n_params) <= fused_max)
+      cls[i] = 0;
+    else if (tot_macs <= (double)gmem_max && max_macs <= (double)gmem_max / 16 && mem_elems < kMaxArenaElems &&
+             mem_elems * eb <= kGmemBudget / 256)
+      cls[i] = 2;
+    else
+      cls[i] = 1;
+    n_level += cls[i] == 1;
+    n_gmem += cls[i] == 2;
+  }
+  bool join = true;  // QTN_GMEM_JOIN=0 keeps them on the global-arena executor
+  if (const char *env = std::getenv("QTN_GMEM_JOIN")) join = std::atoi(env) != 0;
+  if (join && n_gmem > 0 && (int64_t)n_level * max_sets >= b->task_min)
+    for (int &c : cls)
+      if (c == 2) c = 1;
+  for (int i = 0; i < n_nets; ++i) {
+    const Net *n = reinterpret_cast<const Net *>(nets[i]);
+    NetLayout lay = make_layout(*n);
+    cost[i] = n->gplan.flops + n->gplan.flops_grad + 1e3 * n->gplan.ops.size();
+    int ex = -1;  // executor: 0 LDS fused, 1 level, 2 global arena
+    b->flops_fwd += n->gplan.flops;
+    b->bytes_fwd += n->gplan.bytes;
+    b->flops_grad += n->gplan.flops_grad;
+    b->bytes_grad += n->gplan.bytes_grad;
+    if (cls[i] == 0) {
       append_fused(*n, lay, b->hp, false);
       fused_ids.push_back(i);
+      ex = 0;
       maxbits = std::max(maxbits, n->gplan.peak_bits);
-    } else if (tot_macs <= (double)gmem_max && max_macs <= (double)gmem_max / 16 && mem_elems < kMaxArenaElems &&
-               mem_elems * eb <= kGmemBudget / 256) {
+    } else if (cls[i] == 2) {
       append_fused(*n, lay, b->hp, true);
       gmem_ids.push_back(i);
+      ex = 2;
     } else {
       b->hp.nets_fwd.push_back(DNet{});
       b->hp.nets_grad.push_back(DNet{});
       b->level.push_back(append_level(*n, lay, b->hp, i, eb, level_budget, max_sets));
+      ex = 1;
       if (b->level.back().stride[0] >= kMaxArenaElems) {
         set_error("tn_batch_create: network " + std::to_string(i) + " needs " +
                   std::to_string(b->level.back().stride[0]) +
@@ -1078,6 +1107,8 @@ int plan_batch(tn_net *const *nets, int n_nets, const double *coef, double offse
         return TN_ENOMEM;
       }
     }
+    b->exec_flops[ex] += n->gplan.flops + n->gplan.flops_grad;
+    b->exec_bytes[ex] += n->gplan.bytes + n->gplan.bytes_grad;
   }
   // fused networks, expensive first (longest processing time first)
   b->task_net = fused_ids;
@@ -1246,6 +1277,17 @@ int batch_info(const tn_batch *b, tn_batch_stats *s) {
   s->rec_only = (b->block == kRecLanes && !b->hp.generic[0] ? 1 : 0) | (b->block == kRecLanes && !b->hp.generic[1] ? 2 : 0);
   s->lds_bytes_fwd = b->lds_fwd;
   s->lds_bytes_grad = b->lds_grad;
+  for (int x = 0; x < 3; ++x) {
+    s->exec_flops[x] = b->exec_flops[x];
+    s->exec_bytes[x] = b->exec_bytes[x];
+  }
+  // level ops on the matrix cores with the current choices (forward + adjoint)
+  for (const LevelNet &ln : b->level)
+    for (int k = 0; k < ln.n_ops[1]; ++k) {
+      const DOp &op = b->hp.ops[ln.op_begin[1] + k];
+      if (op.type == OP_CONTRACT && level_prec(b, op) != 0)
+        s->level_mfma_flops += 8.0 * std::ldexp(1.0, op.nFX + op.nB + op.nS + op.nFY);
+    }
   s->flops_fwd = b->flops_fwd;
   s->bytes_fwd = b->bytes_fwd;
   s->flops_grad = b->flops_grad;

@@ -54,7 +54,9 @@ class tn_batch_stats(ctypes.Structure):
                                                "sets_per_wave_fwd", "sets_per_wave_grad", "n_global",
                                                "n_level_groups", "n_level_tasked", "n_level_chunked", "level_launches_fwd",
                                                "level_launches_grad", "level_split_fwd", "level_split_grad")] + \
-               [(n, ctypes.c_double) for n in ("flops_fwd", "bytes_fwd", "flops_grad", "bytes_grad")]
+               [(n, ctypes.c_double) for n in ("flops_fwd", "bytes_fwd", "flops_grad", "bytes_grad")] + \
+               [("exec_flops", ctypes.c_double * 3), ("exec_bytes", ctypes.c_double * 3),
+                ("level_mfma_flops", ctypes.c_double)]
 
 
 _lib = None
@@ -364,7 +366,7 @@ class Batch:
     def info(self):
         s = tn_batch_stats()
         _check(lib().tn_batch_info(self.h, ctypes.byref(s)))
-        return {n: getattr(s, n) for n, _ in s._fields_}
+        return {n: (list(getattr(s, n)) if n.startswith("exec_") else getattr(s, n)) for n, _ in s._fields_}
 
     def autotune(self, params, reps=3, cache_path=None, stream=None):
         """Pick fused workgroup size and MFMA/thin per large-op shape (tn_batch_autotune)."""

@@ -251,6 +251,7 @@ def test_kernel_timing_hook(monkeypatch):
     monkeypatch.setenv("QTN_FUSED_LDS_MAX", "32768")
     monkeypatch.setenv("QTN_GMEM_MAX_MACS", str(1 << 18))
     monkeypatch.setenv("QTN_TASK_MIN", "1")
+    monkeypatch.setenv("QTN_GMEM_JOIN", "0")
     model = qaoa.MaxCut(n, e, 2, qtn.TN_C64, order="linegraph", max_sets=S, trials=2)
     info = model.batch.info()
     assert info["n_fused"] > 0 and info["n_global"] > 0 and info["n_level_tasked"] == info["n_level_groups"] == 1
@@ -815,3 +816,35 @@ def test_task_executor_lds_residency_is_exact(monkeypatch):
     obj, grad = res["default"]
     assert np.max(np.abs(obj - ref)) <= 1e-5 * np.abs(ref).max()
     assert np.max(np.abs(grad - ps)) <= 1e-4 * np.abs(ps).max()
+
+
+def test_global_arena_networks_join_task_executor(monkeypatch):
+    """When a batch's level networks are many enough for the task executor,
+    the networks the global-arena executor would take run there too: the
+    3-way split batch (3-regular n=24 p=2 under lowered executor limits)
+    with the task threshold at one pair puts every non-LDS network on the
+    level executor, and matches the same batch with the global-arena
+    executor kept."""
+    qtn, qaoa = _qtn(), _qaoa()
+    n = 24
+    e = workloads.random_regular_graph(3, n, 2)
+    S = 4
+    ang = torch.tensor(workloads.qaoa_angles(13, S, 2), device="cuda", dtype=torch.float64)
+    monkeypatch.setenv("QTN_FUSED_LDS_MAX", "32768")
+    monkeypatch.setenv("QTN_GMEM_MAX_MACS", str(1 << 18))
+    monkeypatch.setenv("QTN_TASK_MIN", "1")
+    res = {}
+    for join in ("0", "1"):
+        monkeypatch.setenv("QTN_GMEM_JOIN", join)
+        model = qaoa.MaxCut(n, e, 2, qtn.TN_C64, order="linegraph", max_sets=S, trials=2)
+        info = model.batch.info()
+        if join == "1":
+            assert info["n_global"] == 0 and info["n_level"] == len(e) - info["n_fused"]
+        else:
+            assert info["n_global"] > 0
+        _say(f"global-arena join {join}: fused={info['n_fused']} global={info['n_global']} level={info['n_level']}")
+        obj, grad = model.value_and_grad(ang)
+        torch.cuda.synchronize()
+        res[join] = (obj.cpu().numpy(), grad.cpu().numpy())
+    assert np.max(np.abs(res["0"][0] - res["1"][0])) <= 1e-5 * np.abs(res["0"][0]).max()
+    assert np.max(np.abs(res["0"][1] - res["1"][1])) <= 1e-4 * np.abs(res["0"][1]).max()

@@ -51,12 +51,16 @@ def test_binding_structs_match_header(qtn):
             m = re.match(r"(const\s+)?(\w+)\s*(\*?)\s*(.*)", decl)
             ctype, ptr = m.group(2), m.group(3)
             for nm in (x.strip().lstrip("*").strip() for x in m.group(4).split(",")):
-                fields.append((nm, ctype, bool(ptr) or m.group(4).lstrip().startswith("*")))
+                arr = re.match(r"(\w+)\[(\d+)\]$", nm)
+                fields.append((arr.group(1) if arr else nm, ctype, bool(ptr) or m.group(4).lstrip().startswith("*"),
+                               int(arr.group(2)) if arr else 0))
         py = getattr(qtn, name)._fields_
         assert [f[0] for f in fields] == [f[0] for f in py], name
-        for (nm, ctype, ptr), (_, pt) in zip(fields, py):
+        for (nm, ctype, ptr, n_arr), (_, pt) in zip(fields, py):
             if ptr:
                 assert issubclass(pt, ctypes._Pointer), (name, nm)
+            elif n_arr:
+                assert issubclass(pt, ctypes.Array) and pt._length_ == n_arr and pt._type_ is cmap[ctype], (name, nm)
             else:
                 assert pt is cmap[ctype], (name, nm)
 

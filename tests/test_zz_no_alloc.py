@@ -59,8 +59,9 @@ def test_noalloc_matches_batch_grad(monkeypatch):
     monkeypatch.setenv("QTN_FUSED_LDS_MAX", "32768")
     monkeypatch.setenv("QTN_GMEM_MAX_MACS", str(1 << 18))
     monkeypatch.setenv("QTN_TASK_MIN", "1")
+    monkeypatch.setenv("QTN_GMEM_JOIN", "0")
     model_a = qaoa.MaxCut(n_a, e_a, 2, qtn.TN_C64, order="linegraph", max_sets=4, trials=2)
-    for var in ("QTN_FUSED_LDS_MAX", "QTN_GMEM_MAX_MACS", "QTN_TASK_MIN"):
+    for var in ("QTN_FUSED_LDS_MAX", "QTN_GMEM_MAX_MACS", "QTN_TASK_MIN", "QTN_GMEM_JOIN"):
         monkeypatch.delenv(var)
     info = model_a.batch.info()
     assert info["n_fused"] > 0 and info["n_global"] > 0 and info["n_level"] > 0 and info["n_level_tasked"] > 0
