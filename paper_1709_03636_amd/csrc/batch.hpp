@@ -121,7 +121,7 @@ constexpr int kTaskMin = 512;  // (network, vector) pairs a group needs for the 
 struct WsLayout {
   enum {
     NETS_FWD, NETS_GRAD, OPS, TABS, RECS, SRECS0, SRECS1, TASK_NET, GTASK_NET, CONSTS, PTENS, SLOTS, COEF, BOUND,
-    DBOUND, VAL, GNET, GARENA, LARENA, LSCAL, LPART, LSPLIT, TITEMS0, TITEMS1, TNETS0, TNETS1, CTRL, N
+    DBOUND, VAL, GNET, GARENA, LARENA, LSCAL, LPART, LSPLIT, TITEMS0, TITEMS1, TNETS0, TNETS1, TRECS, CTRL, N
   };
   int64_t off[N] = {};
   int64_t size[N] = {};
@@ -153,6 +153,8 @@ struct tn_batch {
   std::vector<qtn::PItem> solo_items[2];  // items of the networks run alone (one launch each)
   std::vector<int> solo_begin[2];      // first solo item of each lsolo network, plus an end marker
   int64_t cap_titems[2] = {0, 0};      // workspace room for task-executor items
+  std::vector<int32_t> trecs;          // task-executor lane records (both variants), 4 ints x 64 lanes each
+  int64_t cap_trecs = 0;               // workspace room for them (ints)
   int task_min = qtn::kTaskMin;        // pairs a group needs for the task executor (QTN_TASK_MIN)
   int64_t larena_elems = 0, lscal_doubles = 0, lpart_doubles = 0, lsplit_elems = 0;
   int64_t split_target = 0;            // tasks a split matrix-core item aims at (0: no splits)
@@ -199,6 +201,7 @@ struct ItemCtx {
   bool one_wg = false;  // items for one workgroup and one vector (task executor): no split sums, one
                         // workgroup per rank-0 sum and set-up
   int lds_elems = 0;    // one_wg: elements of the workgroup's LDS arena for small tensors (0: none)
+  std::vector<int32_t> *trecs = nullptr;  // one_wg: lane records of PK_TREC items are appended here
   const std::vector<DOp> *ops = nullptr;
   const std::vector<int32_t> *tabs = nullptr;
 };

@@ -194,31 +194,32 @@ static uint32_t host_pdep(uint32_t v, uint32_t mask) {
 
 // Operand offsets (X, Y) of output c of a contraction: c = (i, b, j) with i
 // the X-only bits, b the batch bits (offset table), j the Y-only bits.
-static void out_offsets(const HostProgram &loc, const DOp &op, uint32_t c, int32_t &ox, int32_t &oy) {
+static void out_offsets(const std::vector<int32_t> &tabs, const DOp &op, uint32_t c, int32_t &ox, int32_t &oy) {
   const uint32_t rest = c >> op.nFY;
   ox = op.x + (int32_t)host_pdep(rest >> op.nB, op.maskX);
   oy = op.y + (int32_t)host_pdep(c & ((1u << op.nFY) - 1u), op.maskY);
   if (op.nB) {
     const uint32_t b = rest & ((1u << op.nB) - 1u);
-    ox += loc.tabs[op.tabB + 2 * b];
-    oy += loc.tabs[op.tabB + 2 * b + 1];
+    ox += tabs[op.tabB + 2 * b];
+    oy += tabs[op.tabB + 2 * b + 1];
   }
 }
 
-// Lane records (see kRecLanes) of ops [first, first + n) of `loc`;
-// `pt` are the network's parametric tensors (for leaf-gradient ops).
-static void build_records(const HostProgram &loc, const std::vector<DParam> &pt, int first, int n,
-                          std::vector<int32_t> &recs) {
+// Lane record (see kRecLanes) of one op whose operands all sit in one
+// memory at the op's offsets (below 2^16): 64 int4 appended to `recs`;
+// returns its type (0: the op has no record form). `pt` are the network's
+// parametric tensors (for leaf-gradient ops).
+static int build_record(const std::vector<int32_t> &tabs, const std::vector<DParam> &pt, const DOp &op,
+                        std::vector<int32_t> &recs) {
   auto pack = [](int32_t a, int32_t b) { return (a & 0xffff) | (b << 16); };
-  for (int o = first; o < first + n; ++o) {
-    const DOp &op = loc.ops[o];
+  {
     const int lgOut = op.nFX + op.nB + op.nFY;
     // LDS offsets of output c's X and Y rows
-    auto offs = [&](uint32_t c, int32_t &ox, int32_t &oy) { out_offsets(loc, op, c, ox, oy); };
+    auto offs = [&](uint32_t c, int32_t &ox, int32_t &oy) { out_offsets(tabs, op, c, ox, oy); };
     // (X, Y) offsets of summed entry k (tables of at most 2^12 entries)
     auto tab = [&](int k, int32_t &tx, int32_t &ty) {
-      tx = loc.tabs[op.tab + 2 * k];
-      ty = loc.tabs[op.tab + 2 * k + 1];
+      tx = tabs[op.tab + 2 * k];
+      ty = tabs[op.tab + 2 * k + 1];
     };
     int type = 0, A = 0, B = 0, C = 0, zf = 0;
     int lgG = 0;
@@ -307,7 +308,7 @@ static void build_records(const HostProgram &loc, const std::vector<DParam> &pt,
       } else if (type == kRecLeafGrad) {
         a0 = op.x + l;
         for (int q = 0; q < 4; ++q)
-          if (l + (q << 6) < (1 << op.nFX)) a1 |= (loc.tabs[op.tab + l + (q << 6)] & 0xff) << (8 * q);
+          if (l + (q << 6) < (1 << op.nFX)) a1 |= (tabs[op.tab + l + (q << 6)] & 0xff) << (8 * q);
         const DParam &d = pt[op.aux0];
         int64_t bits;
         std::memcpy(&bits, &d.coeff, sizeof(bits));
@@ -321,7 +322,14 @@ static void build_records(const HostProgram &loc, const std::vector<DParam> &pt,
       recs.push_back(a2);
       recs.push_back(a3);
     }
+    return type;
   }
+}
+
+// Lane records of ops [first, first + n) of `loc` (LDS offsets).
+static void build_records(const HostProgram &loc, const std::vector<DParam> &pt, int first, int n,
+                          std::vector<int32_t> &recs) {
+  for (int o = first; o < first + n; ++o) build_record(loc.tabs, pt, loc.ops[o], recs);
 }
 
 // Set-packed records (see kSetContract), 2^lgW lanes per set, of the ops of
@@ -334,7 +342,7 @@ static bool build_set_records(const HostProgram &loc, const std::vector<DParam> 
   bool all = true;
   for (const DOp &op : loc.ops) {
     std::vector<std::array<int32_t, 4>> f(W, std::array<int32_t, 4>{0, 0, 0, 0});
-    auto offs = [&](uint32_t c, int32_t &ox, int32_t &oy) { out_offsets(loc, op, c, ox, oy); };
+    auto offs = [&](uint32_t c, int32_t &ox, int32_t &oy) { out_offsets(loc.tabs, op, c, ox, oy); };
     auto tab = [&](int k, int32_t &tx, int32_t &ty) {
       tx = loc.tabs[op.tab + 2 * k];
       ty = loc.tabs[op.tab + 2 * k + 1];
@@ -767,6 +775,13 @@ static bool packed_tab(const ItemCtx &c, const DOp &op, int32_t &px, int32_t &py
 
 // --- level items ------------------------------------------------------------------------------
 
+// Contraction shapes with a lane-record form: at most 64 outputs (summed
+// index up to 12 bits), or an outer product of at most 256 outputs.
+static bool record_shape(const DOp &op) {
+  const int lgOut = op.nFX + op.nB + op.nFY;
+  return op.type == OP_CONTRACT && ((lgOut <= 6 && op.nS <= 12) || (op.nS == 0 && lgOut <= 8));
+}
+
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Items of one network's program variant v over n_sets parameter vectors:
@@ -780,6 +795,7 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
   while ((int64_t(1) << lgs) < n_sets) ++lgs;
   auto base_item = [&](int kind) {
     PItem it{};
+    it.rec = it.nrec = -1;
     it.kind = kind;
     it.base = abase;
     it.stride = ln.stride[v];
@@ -787,6 +803,7 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
     it.n_comp = std::max(1, ln.n_comp);
     return it;
   };
+  const size_t first_item = out.size();
   auto push = [&](const PItem &it) { out.push_back(it); };
   const std::vector<LdsOp> lds = lds_assign(c, ln, v);
   {
@@ -842,17 +859,33 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
         if (r.flags & kLdsY) it.op.y = r.y;
         if (r.flags & kLdsZ) it.op.z = r.z;
         if (thin && packed_tab(c, op, it.a1, it.a2)) it.a0 |= kPackedTab;
+        // a small contraction with every operand in LDS: one wave runs it
+        // from a lane record (offsets precomputed here). Measured: with an
+        // operand in the region the vector-unit path is faster.
+        if (thin && c.trecs && (r.flags & (kLdsX | kLdsY | kLdsZ)) == (kLdsX | kLdsY | kLdsZ) &&
+            record_shape(it.op)) {
+          const size_t at = c.trecs->size();
+          const int type = build_record(*c.tabs, {}, it.op, *c.trecs);
+          if (type == kRecLite || type == kRecWide || type == kRecNarrow) {
+            it.kind = PK_TREC;
+            it.rec = (int32_t)(at / (4 * kRecLanes));
+          } else {
+            c.trecs->resize(at);
+          }
+        }
       }
       const int lg = thin ? op.nFX + op.nB + op.nFY : op.nFX;
       int64_t work = ((int64_t)1 << lg) * n_sets;
       it.lgl = 0;
       if (thin) {
         // lanes per output: at least 8 summed entries each, up to 64, while
-        // the step has fewer than 2^20 (output, lane) pairs
-        it.lgl = std::max(0, std::min({6, op.nS - 3, 20 - lg - lgs}));
+        // the step has fewer than 2^20 (output, lane) pairs (one workgroup:
+        // 2^10, four per thread)
+        const int lg_fill = c.one_wg ? 10 : 20, lg_four = c.one_wg ? 10 : 16;
+        it.lgl = std::max(0, std::min({6, op.nS - 3, lg_fill - lg - lgs}));
         work <<= it.lgl;
         // many outputs: four per lane instead (shared operand reads)
-        if (it.lgl == 0 && lg + lgs >= 16 && (op.nFY >= 2 || (op.nFY == 0 && op.nB == 0 && op.nFX >= 8))) {
+        if (it.lgl == 0 && lg + lgs >= lg_four && (op.nFY >= 2 || (op.nFY == 0 && op.nB == 0 && op.nFX >= 8))) {
           // 64 apart along Y (>= 8 Y-only bits) or X (X-only output bits), else consecutive
           it.lgl = op.nFY >= 8 ? -2 : op.nFY == 0 ? -3 : -1;
           work >>= 2;
@@ -889,12 +922,14 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
   f.a1 = ln.ptens_begin;
   f.a2 = ln.n_ptens;
   push(f);
+  for (size_t i = first_item; i + 1 < out.size(); ++i) out[i].nrec = out[i + 1].rec;
 }
 
 // Items of every group (item mode) or its task-executor items and networks,
 // and the items of the networks run alone, for the current matrix-core
 // choices.
 int plan_level(tn_batch *b) {
+  b->trecs.clear();
   for (int v = 0; v < 2; ++v) {
     b->items[v].clear();
     b->titems[v].clear();
@@ -924,6 +959,7 @@ int plan_level(tn_batch *b) {
       c.one_wg = true;
       c.lds_elems = b->dtype == TN_C128 ? kLdsArenaBytes<TN_MFMA_FP64> / 16 : kLdsArenaBytes<TN_MFMA_FP32> / 8;
       if (const char *env = std::getenv("QTN_TASK_LDS")) c.lds_elems = std::min(c.lds_elems, std::max(0, std::atoi(env)));
+      c.trecs = &b->trecs;
       for (int j : order) {
         const LevelNet &ln = b->level[g.lv[j]];
         TNet tn{};
@@ -960,10 +996,15 @@ void plan_workspace(tn_batch *b) {
   const HostProgram &hp = b->hp;
   b->cap_titems[0] = b->cap_titems[1] = 0;
   int64_t n_tnets = 0;
+  b->cap_trecs = 0;
   for (const LevelGroup &g : b->groups) {
     n_tnets += (int64_t)g.lv.size();
     for (int v = 0; v < 2; ++v)
-      for (int l : g.lv) b->cap_titems[v] += titem_count(b->level[l], v);
+      for (int l : g.lv) {
+        b->cap_titems[v] += titem_count(b->level[l], v);
+        const LevelNet &ln = b->level[l];
+        for (int k = 0; k < ln.n_ops[v]; ++k) b->cap_trecs += record_shape(hp.ops[ln.op_begin[v] + k]) ? 4 * kRecLanes : 0;
+      }
   }
   WsLayout &w = b->ws;
   auto sz = [&](int k, int64_t bytes) { w.size[k] = std::max<int64_t>(bytes, 0); };
@@ -993,6 +1034,7 @@ void plan_workspace(tn_batch *b) {
   sz(WsLayout::TITEMS1, b->cap_titems[1] * (int64_t)sizeof(PItem));
   sz(WsLayout::TNETS0, n_tnets * (int64_t)sizeof(TNet));
   sz(WsLayout::TNETS1, n_tnets * (int64_t)sizeof(TNet));
+  sz(WsLayout::TRECS, b->cap_trecs * (int64_t)sizeof(int32_t));
   sz(WsLayout::CTRL, 64);
   int64_t off = 0;
   for (int k = 0; k < WsLayout::N; ++k) {

@@ -33,6 +33,7 @@ struct FusedArgs {
 struct LvlArgs {
   const PItem *items;
   const TNet *tnets;
+  const int4 *trecs;   // task executor: lane records of PK_TREC items (64 per record)
   int n_tnets;         // tasks = n_tnets * max_sets (network, parameter vector) pairs
   int max_sets;
   int32_t *ctrl;

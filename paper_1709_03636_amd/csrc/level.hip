@@ -15,6 +15,7 @@
 #include "device.hpp"
 #include "internal.hpp"
 #include "kargs.hpp"
+#include "lrec.hpp"
 #include "task.hpp"
 
 namespace qtn {
@@ -52,6 +53,27 @@ __global__ __launch_bounds__(256, kMinWaves<PREC>) void item_kernel(PItem it, Lv
 // memory round trip per descriptor field. Every thread takes part (indices
 // clamped; threads past the descriptor rewrite its padding word), keeping
 // the loop free of per-thread branches.
+// A PK_TREC item: wave 0 forms the small contraction from its lane record
+// (loaded while the item before it ran); its operands are in the LDS arena.
+template <typename V>
+__device__ __forceinline__ void run_rec(const V *xm, const V *ym, V *zm, const int4 &rec) {
+  const uint32_t hdr = (uint32_t)__builtin_amdgcn_readfirstlane(rec.w);
+  const uint32_t type = hdr & 7u;
+  if (type == kRecLite) {
+    switch ((hdr >> 3) & 15u) {
+      case 0: contract_lite<V, 0>(xm, ym, zm, rec, hdr); break;
+      case 1: contract_lite<V, 1>(xm, ym, zm, rec, hdr); break;
+      default: contract_lite<V, 2>(xm, ym, zm, rec, hdr); break;
+    }
+  } else if (type == kRecWide) {
+    contract_wide<V>(xm, ym, zm, rec, hdr);
+  } else if (type == kRecNarrow) {
+    contract_narrow<V>(xm, ym, zm, rec, hdr);
+  }
+}
+
+
+
 constexpr int kItemWords = (int)(sizeof(PItem) / 4);
 constexpr int kItemRow = (kItemWords + 4 + 3) & ~3;  // 16-byte rows with padding
 static_assert(sizeof(PItem) % 4 == 0, "item descriptors are copied in whole words");
@@ -63,6 +85,7 @@ __global__ __launch_bounds__(256, kTaskWaves<PREC>) void task_kernel(LvlArgs a) 
   __shared__ __align__(16) int32_t s_item[2][kItemRow];     // current and next item descriptor
   __shared__ int s_task;
   constexpr int eb = PREC == TN_MFMA_FP64 ? 16 : 8;
+  using V = typename std::conditional<PREC == TN_MFMA_FP64, double2, float2>::type;
   const int total = a.n_tnets * a.max_sets;
   const int word = min((int)threadIdx.x, kItemWords - 1), slot = min((int)threadIdx.x, kItemRow - 1);
   for (;;) {
@@ -83,15 +106,26 @@ __global__ __launch_bounds__(256, kTaskWaves<PREC>) void task_kernel(LvlArgs a) 
       const int32_t *src = reinterpret_cast<const int32_t *>(a.items + i0);
       if (n > 0) s_item[0][slot] = src[word];
       __syncthreads();
+      int4 rcur = make_int4(0, 0, 0, 0);  // this item's lane record (PK_TREC), loaded during the last one
+      const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
       for (int i = 0; i < n; ++i) {
         const bool more = i + 1 < n;  // uniform
         int32_t next = 0;
         if (more) next = src[(int64_t)(i + 1) * kItemWords + word];
         const PItem &it = *reinterpret_cast<const PItem *>(s_item[i & 1]);
-        const int cnt = __builtin_amdgcn_readfirstlane(it.kind == PK_MFMA ? it.count : 1);
-        for (int r = 0; r < cnt; ++r) run_item<PREC, true>(lds, lar, it, r, cnt, v);
+        const int nr = __builtin_amdgcn_readfirstlane(it.nrec);
+        int4 rnext = make_int4(0, 0, 0, 0);
+        if (nr >= 0) rnext = a.trecs[(int64_t)nr * kRecLanes + (threadIdx.x & (kRecLanes - 1))];
+        const int kind = __builtin_amdgcn_readfirstlane(it.kind);
+        if (kind == PK_TREC) {
+          if (wave == 0) run_rec<V>(reinterpret_cast<V *>(lar), reinterpret_cast<V *>(lar), reinterpret_cast<V *>(lar), rcur);
+        } else {
+          const int cnt = __builtin_amdgcn_readfirstlane(kind == PK_MFMA ? it.count : 1);
+          for (int r = 0; r < cnt; ++r) run_item<PREC, true>(lds, lar, it, r, cnt, v);
+        }
         if (more) s_item[(i + 1) & 1][slot] = next;
         __syncthreads();  // the next item reads what this one wrote (same workgroup) and its descriptor
+        rcur = rnext;
       }
     }
     __syncthreads();  // every thread has read s_task before it is rewritten

@@ -276,6 +276,13 @@ static int upload_items(tn_batch *b) {
       HIPCHK(hipMemcpy(ws_ptr<char>(b, v ? WsLayout::TNETS1 : WsLayout::TNETS0), b->tnets[v].data(),
                        b->tnets[v].size() * sizeof(TNet), hipMemcpyHostToDevice));
   }
+  if ((int64_t)b->trecs.size() > b->cap_trecs) {
+    set_error("task-executor lane records larger than their workspace room");
+    return TN_EINVAL;
+  }
+  if (!b->trecs.empty())
+    HIPCHK(hipMemcpy(ws_ptr<char>(b, WsLayout::TRECS), b->trecs.data(), b->trecs.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice));
   b->items_dirty = false;
   graph_clear(b);
   return TN_OK;
@@ -359,6 +366,7 @@ static int upload_tables(tn_batch *b, char *ws, hipStream_t st, bool async, bool
       {WsLayout::TITEMS1, b->titems[1].data(), with_items ? b->titems[1].size() * sizeof(PItem) : 0},
       {WsLayout::TNETS0, b->tnets[0].data(), with_items ? b->tnets[0].size() * sizeof(TNet) : 0},
       {WsLayout::TNETS1, b->tnets[1].data(), with_items ? b->tnets[1].size() * sizeof(TNet) : 0},
+      {WsLayout::TRECS, b->trecs.data(), with_items ? b->trecs.size() * sizeof(int32_t) : 0},
   };
   for (auto &u : ups) {
     if (!u.n) continue;
@@ -478,6 +486,7 @@ static int run_batch(tn_batch *b, char *ws, bool grad, const double *params, int
     la.n_sets = n_sets;
     la.max_sets = b->max_sets;
     la.ctrl = wsp<int32_t>(ws, b, WsLayout::CTRL);
+    la.trecs = wsp<int4>(ws, b, WsLayout::TRECS);
     la.arena = wsp<void>(ws, b, WsLayout::LARENA);
     la.split = wsp<void>(ws, b, WsLayout::LSPLIT);
     la.scal = wsp<double>(ws, b, WsLayout::LSCAL);

@@ -785,12 +785,14 @@ def test_task_executor_matches_item_mode(monkeypatch):
     assert np.max(np.abs(res["task"][0] - res["item"][0])) < 1e-5
 
 
-def test_task_executor_lds_residency_is_exact(monkeypatch):
+def test_task_executor_lds_residency(monkeypatch):
     """The task executor keeps a program's small tensors (and a mirror of its
-    leaves) in LDS and takes small summed-index offsets from packed bit
-    positions: 4-regular n=14 p=2 light-cone networks, forward + adjoint,
-    give bit-identical values and gradients with that arena switched off
-    (every tensor in the region, every offset from its table), and match the
+    leaves) in LDS, takes small summed-index offsets from packed bit
+    positions, and runs small contractions whose operands are all in LDS
+    from lane records on one wave: 4-regular n=14 p=2 light-cone networks,
+    forward + adjoint, agree with that arena switched off (every tensor in
+    the region, every offset from its table; the lane records sum some
+    entries in another order, so to complex64 rounding) and match the
     state-vector cost and parameter-shift gradient."""
     qtn, qaoa = _qtn(), _qaoa()
     monkeypatch.setenv("QTN_FUSED_LDS_MAX", "0")
@@ -812,7 +814,8 @@ def test_task_executor_lds_residency_is_exact(monkeypatch):
         obj, grad = model.value_and_grad(ang)
         torch.cuda.synchronize()
         res[lds] = (obj.cpu().numpy(), grad.cpu().numpy())
-    assert np.array_equal(res["default"][0], res["0"][0]) and np.array_equal(res["default"][1], res["0"][1])
+    assert np.max(np.abs(res["default"][0] - res["0"][0])) <= 1e-6 * np.abs(res["0"][0]).max()
+    assert np.max(np.abs(res["default"][1] - res["0"][1])) <= 1e-5 * np.abs(res["0"][1]).max()
     obj, grad = res["default"]
     assert np.max(np.abs(obj - ref)) <= 1e-5 * np.abs(ref).max()
     assert np.max(np.abs(grad - ps)) <= 1e-4 * np.abs(ps).max()
