@@ -775,6 +775,47 @@ static bool packed_tab(const ItemCtx &c, const DOp &op, int32_t &px, int32_t &py
 
 // --- level items ------------------------------------------------------------------------------
 
+// Runs of up to four consecutive record items whose contractions touch
+// disjoint LDS ranges where one of them writes (no read-after-write,
+// write-after-read or write-after-write between them) become one item: wave w
+// runs the w-th (their records are consecutive), one barrier for all.
+static void group_records(std::vector<PItem> &items, size_t first) {
+  struct Rng {
+    int64_t lo, hi;
+  };
+  auto ranges = [](const DOp &op, Rng &x, Rng &y, Rng &z) {
+    x = {op.x, op.x + ((int64_t)1 << (op.nFX + op.nB + op.nS))};
+    y = {op.y, op.y + ((int64_t)1 << (op.nS + op.nB + op.nFY))};
+    z = {op.z, op.z + ((int64_t)1 << (op.nFX + op.nB + op.nFY))};
+  };
+  auto overlap = [](const Rng &a, const Rng &b) { return a.lo < b.hi && b.lo < a.hi; };
+  std::vector<PItem> outv(items.begin(), items.begin() + first);
+  for (size_t i = first; i < items.size();) {
+    PItem head = items[i];
+    size_t j = i + 1;
+    if (head.kind == PK_TREC) {
+      std::vector<std::array<Rng, 3>> grp(1);
+      ranges(head.op, grp[0][0], grp[0][1], grp[0][2]);
+      while (j < items.size() && grp.size() < 4 && items[j].kind == PK_TREC &&
+             items[j].rec == head.rec + (int32_t)grp.size()) {
+        std::array<Rng, 3> r;
+        ranges(items[j].op, r[0], r[1], r[2]);
+        bool ok = true;
+        for (const auto &g : grp)
+          ok = ok && !overlap(g[2], r[0]) && !overlap(g[2], r[1]) && !overlap(g[2], r[2]) && !overlap(r[2], g[0]) &&
+               !overlap(r[2], g[1]);
+        if (!ok) break;
+        grp.push_back(r);
+        ++j;
+      }
+      head.count = (int32_t)grp.size();
+    }
+    outv.push_back(head);
+    i = j;
+  }
+  items.swap(outv);
+}
+
 // Contraction shapes with a lane-record form: at most 64 outputs (summed
 // index up to 12 bits), or an outer product of at most 256 outputs.
 static bool record_shape(const DOp &op) {
@@ -796,6 +837,7 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
   auto base_item = [&](int kind) {
     PItem it{};
     it.rec = it.nrec = -1;
+    it.nrec_n = 0;
     it.kind = kind;
     it.base = abase;
     it.stride = ln.stride[v];
@@ -869,6 +911,7 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
           if (type == kRecLite || type == kRecWide || type == kRecNarrow) {
             it.kind = PK_TREC;
             it.rec = (int32_t)(at / (4 * kRecLanes));
+            it.count = 1;
           } else {
             c.trecs->resize(at);
           }
@@ -922,7 +965,11 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
   f.a1 = ln.ptens_begin;
   f.a2 = ln.n_ptens;
   push(f);
-  for (size_t i = first_item; i + 1 < out.size(); ++i) out[i].nrec = out[i + 1].rec;
+  if (c.one_wg) group_records(out, first_item);
+  for (size_t i = first_item; i + 1 < out.size(); ++i) {
+    out[i].nrec = out[i + 1].rec;
+    out[i].nrec_n = out[i + 1].kind == PK_TREC ? out[i + 1].count : 0;
+  }
 }
 
 // Items of every group (item mode) or its task-executor items and networks,

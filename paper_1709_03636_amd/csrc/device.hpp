@@ -142,8 +142,9 @@ enum PKind : int32_t {
   PK_SCALAR_SUM = 5,  // rank-0 result: sum of the partial sums in index order (FP64)
   PK_SEED = 6,        // adjoint seed: product of the other component scalars
   PK_FINISH = 7,      // value and gradient of the network into the outputs
-  PK_TREC = 8         // task executor: small thin contraction from a lane record (rec), one wave,
-                      // operands in the workgroup's LDS arena
+  PK_TREC = 8         // task executor: count (1-4) small independent thin contractions from lane
+                      // records rec, rec + 1, ... (wave w runs record rec + w), operands in the
+                      // workgroup's LDS arena
 };
 
 struct PItem {
@@ -162,8 +163,9 @@ struct PItem {
   int32_t n_comp;  // component scalars of the network
   int32_t a0, a1, a2, a3, a4, a5;  // SETUP: const_begin, n_const, ptens_begin, n_pt, zero_begin, zero_n;
                                    // FINISH: network index, ptens_begin, n_pt; THIN: see kLdsX
-  int32_t rec;     // task executor: this item's lane record (PK_TREC), else -1
-  int32_t nrec;    // task executor: the next item's lane record (loaded while this item runs), else -1
+  int32_t rec;     // task executor: this item's first lane record (PK_TREC), else -1
+  int32_t nrec;    // task executor: the next item's first lane record (loaded while this item runs), else -1
+  int32_t nrec_n;  // and how many it has (PK_TREC: up to 4 independent contractions, one per wave)
 };
 
 // Task executor: a workgroup keeps the small tensors of its program in an

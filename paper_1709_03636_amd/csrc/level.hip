@@ -53,8 +53,9 @@ __global__ __launch_bounds__(256, kMinWaves<PREC>) void item_kernel(PItem it, Lv
 // memory round trip per descriptor field. Every thread takes part (indices
 // clamped; threads past the descriptor rewrite its padding word), keeping
 // the loop free of per-thread branches.
-// A PK_TREC item: wave 0 forms the small contraction from its lane record
-// (loaded while the item before it ran); its operands are in the LDS arena.
+// A PK_TREC item: wave w forms the w-th of the item's small independent
+// contractions from its lane record (loaded while the item before it ran);
+// the operands are in the LDS arena.
 template <typename V>
 __device__ __forceinline__ void run_rec(const V *xm, const V *ym, V *zm, const int4 &rec) {
   const uint32_t hdr = (uint32_t)__builtin_amdgcn_readfirstlane(rec.w);
@@ -106,19 +107,21 @@ __global__ __launch_bounds__(256, kTaskWaves<PREC>) void task_kernel(LvlArgs a) 
       const int32_t *src = reinterpret_cast<const int32_t *>(a.items + i0);
       if (n > 0) s_item[0][slot] = src[word];
       __syncthreads();
-      int4 rcur = make_int4(0, 0, 0, 0);  // this item's lane record (PK_TREC), loaded during the last one
+      int4 rcur = make_int4(0, 0, 0, 0);  // this wave's lane record of the item (PK_TREC), loaded during the last one
       const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
       for (int i = 0; i < n; ++i) {
         const bool more = i + 1 < n;  // uniform
         int32_t next = 0;
         if (more) next = src[(int64_t)(i + 1) * kItemWords + word];
         const PItem &it = *reinterpret_cast<const PItem *>(s_item[i & 1]);
-        const int nr = __builtin_amdgcn_readfirstlane(it.nrec);
+        // wave w loads the w-th lane record of the next item
+        const int nr = __builtin_amdgcn_readfirstlane(it.nrec), nn = __builtin_amdgcn_readfirstlane(it.nrec_n);
         int4 rnext = make_int4(0, 0, 0, 0);
-        if (nr >= 0) rnext = a.trecs[(int64_t)nr * kRecLanes + (threadIdx.x & (kRecLanes - 1))];
+        if (wave < nn) rnext = a.trecs[(int64_t)(nr + wave) * kRecLanes + (threadIdx.x & (kRecLanes - 1))];
         const int kind = __builtin_amdgcn_readfirstlane(it.kind);
         if (kind == PK_TREC) {
-          if (wave == 0) run_rec<V>(reinterpret_cast<V *>(lar), reinterpret_cast<V *>(lar), reinterpret_cast<V *>(lar), rcur);
+          V *m = reinterpret_cast<V *>(lar);
+          if (wave < __builtin_amdgcn_readfirstlane(it.count)) run_rec<V>(m, m, m, rcur);
         } else {
           const int cnt = __builtin_amdgcn_readfirstlane(kind == PK_MFMA ? it.count : 1);
           for (int r = 0; r < cnt; ++r) run_item<PREC, true>(lds, lar, it, r, cnt, v);
