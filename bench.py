@@ -118,7 +118,14 @@ def cpu_baseline(n, edges, p, angles, budget_s, label):
         t0 = time.perf_counter()
         pool.map(_oracle_worker, sample, chunksize=1)
         dt = time.perf_counter() - t0
+    # one core: a short sample in this process
+    n1 = int(max(1, min(len(tasks), 3.0 / max(one, 1e-4))))
+    t0 = time.perf_counter()
+    for t in tasks[:n1]:
+        _oracle_worker(t)
+    dt1 = time.perf_counter() - t0
     return {"value": n_sample / dt, "unit": "networks/s (fwd+grad)", "cores": workers, "kind": "oracle",
+            "value_1core": n1 / dt1, "sample_1core": n1,
             "sample": f"{n_sample} of the {len(tasks)} (edge, angle set) networks of {label}, each forward plus "
                       f"central finite-difference gradient ({1 + 4 * p} FP64 light-cone contractions), "
                       f"{workers} worker processes with one BLAS thread each",
@@ -572,15 +579,25 @@ def executor_rooflines(model, params, st, steps, n_sets, prec_name):
         r = {"launches_timed": n_t, "kernel_ms": ms, "algorithmic_flops_per_launch": flops,
              "algorithmic_bytes_per_launch": byts, "fp32_equiv_tflops": flops / (ms * 1e-3) / 1e12}
         if ex == qtn.TN_EXEC_LEVEL:
+            # the binding roofline: the larger of the HBM time of the algorithmic bytes and the
+            # matrix-core time of the executed products (split-BF16: three per real product)
             mf = info["level_mfma_flops"] * n_sets
             mult, peak = (3.0, BF16_MFMA_PEAK) if prec_name == "bf16x3" else (1.0, FP32_MFMA_PEAK)
             if prec_name == "fp64":
                 peak = FP64_MFMA_PEAK
-            ach = mult * mf / (ms * 1e-3)
-            r.update({"bound": "mfma", "matrix_core_share_of_flops": mf / max(flops, 1.0),
-                      "executed_precision": prec_name, "achieved": ach / 1e12, "peak": peak / 1e12,
-                      "unit": "TFLOP/s", "frac": ach / peak,
+            t_hbm, t_mfma = byts / HBM_PEAK, mult * mf / peak
+            ach_m = mult * mf / (ms * 1e-3)
+            r.update({"matrix_core_share_of_flops": mf / max(flops, 1.0), "executed_precision": prec_name,
+                      "ideal_ms_hbm": t_hbm * 1e3, "ideal_ms_mfma": t_mfma * 1e3,
+                      "mfma_executed_tflops": ach_m / 1e12, "mfma_frac": ach_m / peak,
+                      "hbm_frac": byts / (ms * 1e-3) / HBM_PEAK,
                       "fp32_equiv_frac_of_fp32_matrix_peak": flops / (ms * 1e-3) / FP32_MFMA_PEAK})
+            if t_hbm >= t_mfma:
+                r.update({"bound": "hbm", "achieved": byts / (ms * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
+                          "unit": "GB/s", "frac": byts / (ms * 1e-3) / HBM_PEAK})
+            else:
+                r.update({"bound": "mfma", "achieved": ach_m / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                          "frac": ach_m / peak})
         else:
             ach = flops / (ms * 1e-3)
             r.update({"bound": "alu", "achieved": ach / 1e12, "peak": FP32_VALU_PEAK / 1e12, "unit": "TFLOP/s",
