@@ -53,8 +53,8 @@ enum {
   TN_CZ = 9,
   TN_U1 = 10,  /* custom 2x2 matrix (row-major, interleaved re/im) */
   TN_U2 = 11,  /* custom 4x4 matrix (row-major, interleaved re/im) */
-  /* Quantum channel rho -> sum_k E_k rho E_k^dagger (e.g. noise, Sec. on
-   * noise: Kraus operators as superoperators), given as its folded
+  /* Quantum channel rho -> sum_k E_k rho E_k^dagger (e.g. noise, Sec. "A note
+   * on noise": Kraus operators as superoperators), given as its folded
    * superoperator S: entry [(2a+b)*4 + (2c+d)] maps rho_cd to rho'_ab, i.e.
    * sum_k E_k[a][c] conj(E_k[b][d]) (16 entries, 32 doubles); for two qubits
    * entry [((2a0+b0)*4 + (2a1+b1))*16 + (2c0+d0)*4 + (2c1+d1)] with qubit q0
@@ -63,7 +63,14 @@ enum {
    * cone off for the network (it does not reduce to the identity outside
    * the cone). */
   TN_SUPER1 = 12,
-  TN_SUPER2 = 13
+  TN_SUPER2 = 13,
+  /* The same channels given by their Kraus operators E_k (Sec. "A note on noise": a
+   * channel is a set of Kraus operators), folded into the superoperator above
+   * by tn_build: matrix holds n_matrices operators one after another, each
+   * 2x2 (TN_KRAUS1, 8 doubles) or 4x4 (TN_KRAUS2, 32 doubles, basis index
+   * 2*x_q0 + x_q1), row-major, interleaved re/im. */
+  TN_KRAUS1 = 14,
+  TN_KRAUS2 = 15
 };
 
 typedef struct {
@@ -71,7 +78,9 @@ typedef struct {
   int32_t q0, q1;        /* q1 = -1 for one-qubit gates */
   int32_t param;         /* index into params[], or -1 for a fixed angle */
   double coeff;          /* theta = coeff * params[param] (or coeff when param == -1) */
-  const double *matrix;  /* TN_U1 / TN_U2: 8 or 32 doubles; TN_SUPER1 / TN_SUPER2: 32 or 512 doubles; copied */
+  const double *matrix;  /* TN_U1 / TN_U2: 8 or 32 doubles; TN_SUPER1 / TN_SUPER2: 32 or 512 doubles;
+                            TN_KRAUS1 / TN_KRAUS2: n_matrices x 8 or 32 doubles; copied */
+  int32_t n_matrices;    /* TN_KRAUS1 / TN_KRAUS2: number of Kraus operators (>= 1); ignored otherwise */
 } tn_gate;
 
 /* What the network computes (Sec. Preliminaries and Sec. "Estimating the
@@ -170,16 +179,28 @@ int tn_plan_steps(const tn_net *net, int32_t *dims);
 
 /* Contract one network for one parameter vector (host params, n_params
  * doubles) on the given HIP stream (NULL = default); writes the complex
- * scalar to out[0..1] (host) and synchronises the stream. One network per
- * launch sequence: the plain path. */
+ * scalar to out[0..1] (host) and synchronises the stream. The closed network
+ * contracts to one scalar (Sec. Preliminaries): the amplitude <x|C|psi0>,
+ * the probability Tr(Pi rho), or the expectation <psi|M|psi> of a Pauli
+ * string (Sec. "Estimating the answer string"), by the pairwise
+ * contractions of eq. (1) in the order fixed by tn_set_order. One network
+ * per launch sequence: the plain path. */
 int tn_contract(tn_net *net, const double *params, double *out, void *stream);
 
 /* Value and gradient of Re(scalar) with respect to params (host buffers;
- * grad has n_params entries) by reverse-mode (adjoint) contraction. */
+ * grad has n_params entries) by reverse-mode (adjoint) contraction. Not in
+ * the paper: the adjoint of each pairwise contraction of eq. (1) is again a
+ * contraction of that form (the result's adjoint with the other operand),
+ * run over the same order in reverse with the forward intermediates kept;
+ * the adjoint of a parametric gate tensor is contracted with its angle
+ * derivative. */
 int tn_grad(tn_net *net, const double *params, double *value, double *grad, void *stream);
 
 /* Batched execution of many networks (each with an order set) over many
- * parameter vectors. All networks must share n_params and dtype.
+ * parameter vectors. Not in the paper (its networks run one at a time, with
+ * the nodes of one network split over CPU threads, Sec. "Threading"): every
+ * (network, parameter vector) pair is independent, and a batch runs them all
+ * in a few launches. All networks must share n_params and dtype.
  * coef[i] weights network i in the combined objective
  *   obj[s] = offset + sum_i coef[i] * Re(scalar_i(params_s))
  * (QAOA Max-Cut: coef = -1/2, offset = |E|/2). coef may be NULL (all 0).
@@ -314,7 +335,8 @@ enum {
 int tn_batch_kernel_timing(tn_batch *b, int32_t enable);
 int tn_batch_kernel_time(tn_batch *b, int32_t executor, int32_t *n_launches, double *total_ms);
 
-/* One-shot conveniences: create a transient batch, run, free. Device pointers. */
+/* One-shot conveniences: create a transient batch, run, free (tn_batch_contract /
+ * tn_batch_grad semantics, not in the paper). Device pointers. */
 int tn_contract_batch(tn_net *const *nets, int32_t n_nets, const double *params, int32_t n_sets,
                       double *out, void *stream);
 int tn_grad_batch(tn_net *const *nets, int32_t n_nets, const double *params, int32_t n_sets,

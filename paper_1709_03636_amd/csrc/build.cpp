@@ -230,10 +230,59 @@ struct Builder {
 
 }  // namespace
 
-int build_network(const tn_gate *gates, int n_gates, int n_qubits, const double *init,
+// Folded superoperator of a channel given by Kraus operators E_k (d x d,
+// d = 2 or 4, row-major interleaved re/im): one qubit, entry
+// [(2a+b)*4 + (2c+d)] = sum_k E_k[a][c] conj(E_k[b][d]); two qubits, with
+// each of a, b, c, d split into (qubit q0 bit, qubit q1 bit), entry
+// [((2a0+b0)*4 + (2a1+b1))*16 + (2c0+d0)*4 + (2c1+d1)] =
+// sum_k E_k[2a0+a1][2c0+c1] conj(E_k[2b0+b1][2d0+d1]).
+static std::vector<double> fold_kraus(const double *m, int n_k, bool two) {
+  const int dim = two ? 4 : 2, q = two ? 2 : 1, sdim = 1 << (2 * q);
+  std::vector<cd> S((size_t)sdim * sdim, cd(0.0, 0.0));
+  for (int k = 0; k < n_k; ++k) {
+    const double *e = m + (size_t)k * 2 * dim * dim;
+    auto E = [&](int r, int c) { return cd(e[2 * (r * dim + c)], e[2 * (r * dim + c) + 1]); };
+    for (int a = 0; a < dim; ++a)
+      for (int b = 0; b < dim; ++b)
+        for (int c = 0; c < dim; ++c)
+          for (int d = 0; d < dim; ++d) {
+            // folded wire value of qubit j: 2 * (ket bit) + (bra bit)
+            int row = 0, col = 0;
+            for (int j = 0; j < q; ++j) {
+              const int sh = q - 1 - j;  // qubit q0 is the most significant bit
+              row = row * 4 + 2 * ((a >> sh) & 1) + ((b >> sh) & 1);
+              col = col * 4 + 2 * ((c >> sh) & 1) + ((d >> sh) & 1);
+            }
+            S[(size_t)row * sdim + col] += E(a, c) * std::conj(E(b, d));
+          }
+  }
+  std::vector<double> out(2 * S.size());
+  for (size_t i = 0; i < S.size(); ++i) {
+    out[2 * i] = S[i].real();
+    out[2 * i + 1] = S[i].imag();
+  }
+  return out;
+}
+
+int build_network(const tn_gate *gates_in, int n_gates, int n_qubits, const double *init,
                   const tn_target *target, int n_params, int dtype, Net &net) {
   if (n_qubits < 1 || n_qubits > 4096) { set_error("tn_build: n_qubits out of range"); return TN_EINVAL; }
-  if (n_gates < 0 || (n_gates > 0 && !gates)) { set_error("tn_build: bad gate list"); return TN_EINVAL; }
+  if (n_gates < 0 || (n_gates > 0 && !gates_in)) { set_error("tn_build: bad gate list"); return TN_EINVAL; }
+  // channels given by Kraus operators become superoperator gates here
+  std::vector<tn_gate> gate_copy(gates_in, gates_in + n_gates);
+  std::vector<std::vector<double>> folded_store;
+  for (int i = 0; i < n_gates; ++i) {
+    tn_gate &g = gate_copy[i];
+    if (g.kind != TN_KRAUS1 && g.kind != TN_KRAUS2) continue;
+    if (!g.matrix || g.n_matrices < 1 || g.n_matrices > 4096) {
+      set_error("tn_build: Kraus gate without operators at gate " + std::to_string(i));
+      return TN_EINVAL;
+    }
+    folded_store.push_back(fold_kraus(g.matrix, g.n_matrices, g.kind == TN_KRAUS2));
+    g.kind = g.kind == TN_KRAUS1 ? TN_SUPER1 : TN_SUPER2;
+    g.matrix = folded_store.back().data();
+  }
+  const tn_gate *gates = gate_copy.data();
   if (!target) { set_error("tn_build: target is NULL"); return TN_EINVAL; }
   if (dtype != TN_C64 && dtype != TN_C128) { set_error("tn_build: bad dtype"); return TN_EINVAL; }
   if (n_params < 0) { set_error("tn_build: n_params < 0"); return TN_EINVAL; }

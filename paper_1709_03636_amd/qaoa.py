@@ -42,8 +42,7 @@ def _channel(noise):
     after every gate, on each qubit the gate acts on."""
     if noise is None:
         return None
-    S = noise_mod.superop(noise)
-    return lambda q: ("SUPER1", q, -1, -1, 0.0, S)
+    return lambda q: noise_mod.channel_gate(noise, q)
 
 
 def qaoa_gates(n, edges, p, noise=None):

@@ -14,13 +14,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("QTN_LIB", os.path.join(HERE, "libqtn.so"))
 
 TN_OK, TN_EINVAL, TN_ENOMEM, TN_EORDER, TN_EDEVICE, TN_ESTATE = 0, -1, -2, -3, -4, -5
-TN_H, TN_X, TN_Y, TN_Z, TN_RX, TN_RY, TN_RZ, TN_ZZ, TN_CNOT, TN_CZ, TN_U1, TN_U2, TN_SUPER1, TN_SUPER2 = range(14)
+TN_H, TN_X, TN_Y, TN_Z, TN_RX, TN_RY, TN_RZ, TN_ZZ, TN_CNOT, TN_CZ, TN_U1, TN_U2, TN_SUPER1, TN_SUPER2, \
+    TN_KRAUS1, TN_KRAUS2 = range(16)
 TN_AMPLITUDE, TN_PROBABILITY, TN_EXPECTATION = 0, 1, 2
 TN_EXEC_FUSED, TN_EXEC_LEVEL, TN_EXEC_GLOBAL = 0, 1, 2
 TN_C64, TN_C128 = 0, 1
 TN_MFMA_FP32, TN_MFMA_BF16X3, TN_MFMA_FP64 = 1, 2, 3
 GATE_KINDS = {"H": TN_H, "X": TN_X, "Y": TN_Y, "Z": TN_Z, "RX": TN_RX, "RY": TN_RY, "RZ": TN_RZ, "ZZ": TN_ZZ,
-              "CNOT": TN_CNOT, "CZ": TN_CZ, "U1": TN_U1, "U2": TN_U2, "SUPER1": TN_SUPER1, "SUPER2": TN_SUPER2}
+              "CNOT": TN_CNOT, "CZ": TN_CZ, "U1": TN_U1, "U2": TN_U2, "SUPER1": TN_SUPER1, "SUPER2": TN_SUPER2,
+              "KRAUS1": TN_KRAUS1, "KRAUS2": TN_KRAUS2}
 ERR_NAMES = {TN_EINVAL: "TN_EINVAL", TN_ENOMEM: "TN_ENOMEM", TN_EORDER: "TN_EORDER", TN_EDEVICE: "TN_EDEVICE",
              TN_ESTATE: "TN_ESTATE"}
 
@@ -33,7 +35,8 @@ class QtnError(RuntimeError):
 
 class tn_gate(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("q0", ctypes.c_int32), ("q1", ctypes.c_int32),
-                ("param", ctypes.c_int32), ("coeff", ctypes.c_double), ("matrix", ctypes.POINTER(ctypes.c_double))]
+                ("param", ctypes.c_int32), ("coeff", ctypes.c_double), ("matrix", ctypes.POINTER(ctypes.c_double)),
+                ("n_matrices", ctypes.c_int32)]
 
 
 class tn_target(ctypes.Structure):
@@ -190,19 +193,25 @@ def sv_maxcut_p1(n, edges, gamma, beta, workspace=None, stream=None):
 
 
 def make_gates(gates):
-    """Gate tuples (kind, q0, q1, param, coeff[, matrix]) -> tn_gate array (+ keep-alive list)."""
+    """Gate tuples (kind, q0, q1, param, coeff[, matrix]) -> tn_gate array (+ keep-alive list). For
+    KRAUS1 / KRAUS2 the matrix entry is the list of Kraus operators (folded by tn_build)."""
     arr = (tn_gate * max(1, len(gates)))()
     keep = []
     for i, g in enumerate(gates):
         kind, q0, q1, param, coeff = g[:5]
         mat = g[5] if len(g) > 5 else None
         k = GATE_KINDS[kind] if isinstance(kind, str) else int(kind)
-        mp = None
+        mp, nm = None, 0
         if mat is not None:
-            m = np.ascontiguousarray(np.asarray(mat, dtype=np.complex128).ravel().view(np.float64))
+            a = np.asarray(mat, dtype=np.complex128)
+            if k in (TN_KRAUS1, TN_KRAUS2):
+                d = 2 if k == TN_KRAUS1 else 4
+                a = a.reshape(-1, d, d)
+                nm = a.shape[0]
+            m = np.ascontiguousarray(a.ravel().view(np.float64))
             keep.append(m)
             mp = m.ctypes.data_as(_PD)
-        arr[i] = tn_gate(k, q0, q1, param, coeff, mp)
+        arr[i] = tn_gate(k, q0, q1, param, coeff, mp, nm)
     return arr, keep
 
 

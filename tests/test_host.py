@@ -253,21 +253,48 @@ def test_channel_gates_light_cone_and_errors(qtn):
         qtn.Network(3, base + [("SUPER1", 1, -1, -1, 0.0)], qtn.TN_EXPECTATION, pauli)
 
 
-def test_superoperator_layout(qtn):
-    """noise.superop follows the documented folded layout: for one Kraus
-    operator E, entry (2a+b, 2c+d) is E[a, c] conj(E[b, d]); two-qubit
-    entries are indexed (q0 out, q1 out, q0 in, q1 in)."""
+def _fold(kraus):
+    """The documented folded layout, restated here: for Kraus operators E_k,
+    entry (2a+b, 2c+d) is sum_k E_k[a, c] conj(E_k[b, d]); two-qubit entries
+    are indexed (q0 out, q1 out, q0 in, q1 in), each wire value 2*ket + bra."""
+    d = kraus[0].shape[0]
+    q = 1 if d == 2 else 2
+    S = np.zeros((4 ** q, 4 ** q), dtype=complex)
+    for E in kraus:
+        for a, b, c, dd in itertools.product(range(d), repeat=4):
+            row = col = 0
+            for j in range(q):
+                sh = q - 1 - j
+                row = row * 4 + 2 * ((a >> sh) & 1) + ((b >> sh) & 1)
+                col = col * 4 + 2 * ((c >> sh) & 1) + ((dd >> sh) & 1)
+            S[row, col] += E[a, c] * np.conj(E[b, dd])
+    return S
+
+
+def test_kraus_gates_fold_like_superoperators(qtn):
+    """Channels given by Kraus operators (folded by tn_build) build the same
+    networks as their superoperators in the documented layout: the same
+    tensors and wires, the same light-cone decisions (trace preserving or
+    not); malformed Kraus gates are refused."""
     from paper_1709_03636_amd import noise
     rng = np.random.default_rng(1)
-    E = rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2))
-    S = noise.superop([E])
-    for a, b, c, d in itertools.product((0, 1), repeat=4):
-        assert S[2 * a + b, 2 * c + d] == E[a, c] * np.conj(E[b, d])
-    F = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
-    S2 = noise.superop([F])
-    for a0, b0, a1, b1, c0, d0, c1, d1 in itertools.product((0, 1), repeat=8):
-        row, col = (2 * a0 + b0) * 4 + 2 * a1 + b1, (2 * c0 + d0) * 4 + 2 * c1 + d1
-        assert S2[row, col] == F[2 * a0 + a1, 2 * c0 + c1] * np.conj(F[2 * b0 + b1, 2 * d0 + d1])
+    base = [("H", 0, -1, -1, 0.0), ("CNOT", 0, 1, -1, 0.0), ("H", 2, -1, -1, 0.0), ("CZ", 1, 2, -1, 0.0)]
+    chans = [(noise.depolarizing(0.2), 2, -1), ([np.diag([1.0, 0.0])], 2, -1),
+             ([np.kron(E, F) for E in noise.dephasing(0.2) for F in noise.amplitude_damping(0.3)], 1, 2),
+             ([rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))], 0, 1)]
+    for kraus, q0, q1 in chans:
+        ks = [np.asarray(k, dtype=complex) for k in kraus]
+        gk = base + [noise.channel_gate(ks, q0, q1)]
+        gs = base + [("SUPER1" if q1 < 0 else "SUPER2", q0, q1, -1, 0.0, _fold(ks))]
+        for lc in (True, False):
+            nk = qtn.Network(3, gk, qtn.TN_EXPECTATION, [3, 3, 1], lightcone=lc)
+            ns = qtn.Network(3, gs, qtn.TN_EXPECTATION, [3, 3, 1], lightcone=lc)
+            wk, ws = nk.wires(), ns.wires()
+            assert wk[:2] == ws[:2] and np.array_equal(wk[2], ws[2])
+    for bad in (("KRAUS1", 0, -1, -1, 0.0, np.zeros((0, 2, 2))), ("KRAUS1", 0, -1, -1, 0.0)):
+        with pytest.raises(qtn.QtnError) as ei:
+            qtn.Network(3, base + [bad], qtn.TN_EXPECTATION, [3, 3, 1])
+        assert ei.value.code == qtn.TN_EINVAL
 
 
 @pytest.mark.parametrize("noisy", [False, True])
