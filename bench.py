@@ -481,9 +481,12 @@ def crossover(st, dev, refs):
     crossover in degree): time per <C> (all edges) of the full complex64 state
     vector on this GPU, of the batched light-cone networks (one angle set),
     and of the whole-circuit folded networks (dense and diagonal gates) where
-    their largest intermediate fits (edge 0 timed, times |E|); n = 40 for the
-    light-cone networks, where the state vector (8 TiB) does not fit.
-    Errors against the stored closed-form values."""
+    their largest intermediate stays within 2^30 entries (edge 0 timed, times
+    |E|; line-graph orders from 1024 restarts for the dense networks at
+    n = 30, 256 otherwise; forward + gradient too at 2^26 entries and up);
+    n = 40 for the light-cone networks, where the state vector (8 TiB) does
+    not fit, and the order search of the whole-circuit ones. Errors against
+    the stored closed-form values."""
     import torch
     import workloads
     from paper_1709_03636_amd import qaoa, qtn
@@ -520,28 +523,59 @@ def crossover(st, dev, refs):
             ev1.record(st)
             torch.cuda.synchronize()
             row["tn_lightcone"] = {"ms_per_cost": ev0.elapsed_time(ev1) / 20, "abs_err": abs(obj.item() - ref)}
-            if n <= 30:
-                for mode in ("dense", "diagonal"):
-                    net = qaoa.edge_network(n, e, 1, e[0], dtype=qtn.TN_C64, lightcone=False,
-                                            diagonal=mode == "diagonal")
-                    try:
-                        net.set_order(net.order_linegraph(trials=4, seed=0))
-                    except qtn.QtnError as ex:  # the order's largest intermediate passes the memory limit
-                        row[f"tn_whole_circuit_{mode}"] = {"infeasible": str(ex)}
-                        continue
-                    pi = net.plan_info()
-                    r = {"peak_bits": pi["peak_bits"], "flops_per_edge": pi["flops"]}
-                    if pi["peak_bits"] <= 28 and pi["flops"] <= 2e13:
-                        net.contract([g0, b0], stream=st)
-                        t0 = time.perf_counter()
-                        z = net.contract([g0, b0], stream=st)
-                        r["ms_per_edge"] = (time.perf_counter() - t0) * 1e3
-                        r["ms_per_cost_estimate"] = r["ms_per_edge"] * len(e)
-                        r["abs_err_zz_edge0"] = abs(z.real - cr["zz_edge0"])
-                    else:
-                        r["infeasible"] = "largest intermediate beyond 2^28 entries or work beyond 2e13 flops"
-                    row[f"tn_whole_circuit_{mode}"] = r
-                    del net
+            # whole-circuit networks (config 5): line-graph order, best of 1024 restarts at n=30 and of 256
+            # at n=40 (the order search is anytime; the paper ran QuickBB for 3000 s per circuit)
+            for mode in ("dense", "diagonal"):
+                trials = 1024 if n <= 30 and mode == "dense" else 256
+                net = qaoa.edge_network(n, e, 1, e[0], dtype=qtn.TN_C64, lightcone=False,
+                                        diagonal=mode == "diagonal")
+                t0 = time.perf_counter()
+                pi_order = net.order_linegraph(trials=trials, seed=0)
+                search_s = time.perf_counter() - t0
+                try:
+                    net.set_order(pi_order)
+                except qtn.QtnError as ex:  # the order's largest intermediate passes the 2^31-entry cap
+                    row[f"tn_whole_circuit_{mode}"] = {"order_restarts": trials, "order_search_s": search_s,
+                                                       "infeasible": str(ex)}
+                    continue
+                pi = net.plan_info()
+                r = {"order_restarts": trials, "order_search_s": search_s, "peak_bits": pi["peak_bits"],
+                     "flops_per_edge": pi["flops"]}
+                if n <= 30 and pi["peak_bits"] <= 30 and pi["flops"] <= 1e14:
+                    b = qtn.Batch([net], max_sets=1)
+                    prm = torch.tensor([[g0, b0]], dtype=torch.float64, device=dev)
+                    out = torch.empty((1, 1, 2), dtype=torch.float64, device=dev)
+                    b.contract(prm, out=out, stream=st)
+                    torch.cuda.synchronize()
+                    ev0.record(st)
+                    b.contract(prm, out=out, stream=st)
+                    ev1.record(st)
+                    torch.cuda.synchronize()
+                    ms = ev0.elapsed_time(ev1)
+                    r.update({"ms_per_edge": ms, "ms_per_cost_estimate": ms * len(e),
+                              "tflops": pi["flops"] / (ms * 1e-3) / 1e12,
+                              "frac_of_fp32_matrix_peak": pi["flops"] / (ms * 1e-3) / FP32_MFMA_PEAK,
+                              "abs_err_zz_edge0": abs(out[0, 0, 0].item() - cr["zz_edge0"])})
+                    if pi["peak_bits"] >= 26 and mode == "dense":
+                        gn = torch.empty((1, 1, 2), dtype=torch.float64, device=dev)
+                        ev0.record(st)
+                        b.grad(prm, out=out, grad_net=gn, stream=st)
+                        ev1.record(st)
+                        torch.cuda.synchronize()
+                        gms = ev0.elapsed_time(ev1)
+                        bi = b.info()
+                        r["fwd_grad"] = {"ms_per_edge": gms,
+                                         "tflops": (bi["flops_fwd"] + bi["flops_grad"]) / (gms * 1e-3) / 1e12,
+                                         "grad": gn[0, 0].cpu().numpy().tolist(),
+                                         "abs_err_zz_edge0": abs(out[0, 0, 0].item() - cr["zz_edge0"])}
+                    del b
+                    torch.cuda.empty_cache()
+                elif n > 30:
+                    r["not_run"] = "n=40 rows report the order search only"
+                else:
+                    r["infeasible"] = "largest intermediate beyond 2^30 entries or work beyond 1e14 flops"
+                row[f"tn_whole_circuit_{mode}"] = r
+                del net
             rows.append(row)
             log(f"crossover: {row}")
     return {"workload": "QAOA p=1 Max-Cut <C>, random d-regular graphs, gamma=0.4, beta=0.3; time per <C> over all "

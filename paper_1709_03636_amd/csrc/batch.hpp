@@ -28,7 +28,8 @@ constexpr int64_t kFusedLdsMax = 48 * 1024;
 // launch, fewer groups one after another); a network alone
 // processes its parameter vectors in chunks that fit. 32 GiB of the 288 GB.
 constexpr int64_t kLevelBudget = 32ll << 30;
-constexpr int64_t kMaxArenaElems = int64_t(1) << 31;  // 32-bit element offsets per set
+constexpr int64_t kMaxArenaElems = int64_t(1) << 31;  // global-arena executor: 32-bit element offsets per slot
+constexpr int64_t kMaxLevelElems = int64_t(1) << 40;  // level executor: elements of one set's region
 // Global-arena fused executor: networks too large for LDS whose whole task
 // (forward + adjoint program of one parameter vector) has at most this many
 // complex multiply-adds, and no step above a sixteenth of it.

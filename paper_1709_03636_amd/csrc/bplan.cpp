@@ -564,7 +564,7 @@ static LevelNet append_level(const Net &net, const NetLayout &lay, HostProgram &
     d.diag = pt.diag;
     d.bits = pt.bits;
     d.off = (int32_t)lay.poff[t];
-    d.goff = (int32_t)(ln.gbar_begin + lay.poff[t] - lay.n_const);
+    d.goff = ln.gbar_begin + lay.poff[t] - lay.n_const;
     d.coeff = pt.coeff;
     d.slot = slot_for(hp, pt);
     hp.ptens.push_back(d);
@@ -573,16 +573,16 @@ static LevelNet append_level(const Net &net, const NetLayout &lay, HostProgram &
     ln.op_begin[variant] = (int)hp.ops.size();
     ln.n_ops[variant] = variant == 0 ? p.n_fwd_ops : (int)p.ops.size();
     emit_ops(
-        p, ln.n_ops[variant], hp, [&](int v) { return (int32_t)abs_off(net, lay, variant, v); },
+        p, ln.n_ops[variant], hp, [&](int v) { return abs_off(net, lay, variant, v); },
         [&](const Op &op, DOp &d) {
-          d.y = (int32_t)(ln.gbar_begin + lay.poff[op.aux0] - lay.n_const);
+          d.y = ln.gbar_begin + lay.poff[op.aux0] - lay.n_const;
           d.aux0 = ln.ptens_begin + op.aux0;
           d.aux1 = op.aux1;
         });
   }
-  // element offsets inside a set's arena are 32-bit: an adjoint arena past
-  // 2^31 elements leaves the network usable for forward passes only
-  ln.grad_ok = ln.stride[1] < kMaxArenaElems;
+  // a set's region past kMaxLevelElems elements leaves the network usable
+  // for forward passes only
+  ln.grad_ok = ln.stride[1] < kMaxLevelElems;
   int64_t per = ln.stride[ln.grad_ok ? 1 : 0] * eb;
   ln.chunk = (int)std::max<int64_t>(1, std::min<int64_t>(max_sets, budget_bytes / std::max<int64_t>(1, per)));
   ln.cost = p.flops + p.flops_grad;
@@ -687,7 +687,7 @@ static std::vector<LdsOp> lds_assign(const ItemCtx &c, const LevelNet &ln, int v
     const DOp &op = (*c.ops)[ln.op_begin[v] + k];
     const bool thin = op.type == OP_CONTRACT && level_prec(c, op) == 0;
     const bool vector_read = thin || op.type == OP_LEAFGRAD;
-    auto read = [&](int32_t off, int slot) {
+    auto read = [&](int64_t off, int slot) {
       if (off < leaf) return;
       auto it = cur.find(off);
       if (it == cur.end()) return;
@@ -728,7 +728,7 @@ static std::vector<LdsOp> lds_assign(const ItemCtx &c, const LevelNet &ln, int v
     LdsOp &r = res[k];
     const bool thin = op.type == OP_CONTRACT && level_prec(c, op) == 0;
     if (thin || op.type == OP_LEAFGRAD) {
-      const int32_t offs[2] = {op.x, op.y};
+      const int64_t offs[2] = {op.x, op.y};
       for (int s = 0; s < (thin ? 2 : 1); ++s) {
         const int t = uses[k][s];
         const int32_t flag = s == 0 ? kLdsX : kLdsY;
@@ -859,7 +859,7 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
     it.a1 = ln.n_const;
     it.a2 = ln.ptens_begin;
     it.a3 = ln.n_ptens;
-    it.a4 = (int32_t)ln.gbar_begin;
+    it.zs = ln.gbar_begin;
     it.a5 = (int32_t)zero_n;
     push(it);
   }
@@ -1189,10 +1189,10 @@ int plan_batch(tn_net *const *nets, int n_nets, const double *coef, double offse
       b->hp.nets_grad.push_back(DNet{});
       b->level.push_back(append_level(*n, lay, b->hp, i, eb, level_budget, max_sets));
       ex = 1;
-      if (b->level.back().stride[0] >= kMaxArenaElems) {
+      if (b->level.back().stride[0] >= kMaxLevelElems) {
         set_error("tn_batch_create: network " + std::to_string(i) + " needs " +
                   std::to_string(b->level.back().stride[0]) +
-                  " elements of working memory per parameter vector; the executor addresses at most 2^31");
+                  " elements of working memory per parameter vector; the executor addresses at most 2^40");
         return TN_ENOMEM;
       }
     }

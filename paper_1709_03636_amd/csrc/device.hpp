@@ -14,7 +14,8 @@ namespace qtn {
 // (deposited at maskY in Y).
 struct DOp {
   int32_t type;      // OpType
-  int32_t x, y, z;   // operand / result offsets (OP_SCALAR: z = scalar slot)
+  int64_t x, y, z;   // operand / result offsets (OP_SCALAR: z = scalar slot); 64-bit: a level
+                     // network's region may pass 2^31 elements (2^30-entry intermediates)
   int32_t nFX, nS, nFY;
   uint32_t maskX, maskY;
   int32_t tab;       // offset into the int32 table array (summed index)
@@ -56,7 +57,8 @@ inline void pack_runs(uint32_t mask, int32_t out[4]) {
 // bound-tensor slice.
 struct DParam {
   int32_t kind, param, folded, bits;
-  int32_t off, goff, slot, diag;  // diag: only the diagonal of the gate (2^bits entries)
+  int32_t off, slot, diag, pad;  // diag: only the diagonal of the gate (2^bits entries)
+  int64_t goff;                  // 64-bit: a level network's adjoint accumulators may sit past 2^31
   double coeff;
 };
 
@@ -161,7 +163,7 @@ struct PItem {
                    // summed-index ranges; SCALAR: workgroups per parameter vector (1: writes the scalar)
   int32_t mv;      // MFMA: kernel variant (tile shape, operand layouts)
   int32_t n_comp;  // component scalars of the network
-  int32_t a0, a1, a2, a3, a4, a5;  // SETUP: const_begin, n_const, ptens_begin, n_pt, zero_begin, zero_n;
+  int32_t a0, a1, a2, a3, a4, a5;  // SETUP: const_begin, n_const, ptens_begin, n_pt, -, zero_n (zero_begin: zs);
                                    // FINISH: network index, ptens_begin, n_pt; THIN: see kLdsX
   int32_t rec;     // task executor: this item's first lane record (PK_TREC), else -1
   int32_t nrec;    // task executor: the next item's first lane record (loaded while this item runs), else -1

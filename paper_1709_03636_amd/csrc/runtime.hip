@@ -414,7 +414,7 @@ static int run_batch(tn_batch *b, char *ws, bool grad, const double *params, int
     for (const LevelNet &ln : b->level)
       if (!ln.grad_ok) {
         set_error("batch gradient: network " + std::to_string(ln.net) +
-                  " needs more than 2^31 elements of adjoint working memory per parameter vector");
+                  " needs more than 2^40 elements of adjoint working memory per parameter vector");
         return TN_ENOMEM;
       }
   const bool own_ws = ws != nullptr;

@@ -478,7 +478,7 @@ __device__ __forceinline__ void task_seed(const PItem &it, int rank, const LvlAr
 // PK_SETUP: task (set, chunk) of G = lgl chunks per parameter vector copies
 // the constants (a1 entries from a0) and the bound parametric tensors
 // (DParams a2 .. a2 + a3) into the vector's slice and clears the a5 adjoint
-// accumulator entries from a4.
+// accumulator entries from zs.
 template <typename V>
 __device__ __forceinline__ void task_setup(const PItem &it, int rank, const LvlArgs &a, V *lar) {
   const int G = it.lgl;
@@ -506,7 +506,7 @@ __device__ __forceinline__ void task_setup(const PItem &it, int rank, const LvlA
     V z;
     z.x = 0;
     z.y = 0;
-    base[it.a4 + e] = z;
+    base[it.zs + e] = z;
   }
 }
 

@@ -244,3 +244,43 @@ def test_autograd_function_backward():
         dg, db = closed_form.zz_p1_grad(n, e, ang[s, 0], ang[s, 1])
         g = np.array([-0.5 * dg.sum(), -0.5 * db.sum()])
         assert np.max(np.abs(x.grad[s].cpu().numpy() / w[s].item() - g)) <= 1e-4 * max(1.0, np.abs(g).max())
+
+
+def test_config5_whole_circuit_2p30():
+    """The dense regime at its stated size: the whole-circuit folded network
+    of edge 0 of the seeded 5-regular n=30 graph at p=1 (no light cone),
+    line-graph order from 1024 restarts (largest intermediate 2^30 entries,
+    8 GiB complex64; 4.5e13 flops forward), on the level executor with FP32
+    and split-BF16 matrix-core products. <Z_u Z_v> and its gradient against
+    the p=1 closed form: 1e-6 / 1e-5 absolute (FP32), 1e-5 / 1e-4 (split
+    BF16). Exercises element offsets past 2^31 in the set's region."""
+    from paper_1709_03636_amd import qtn, qaoa
+    d, n = 5, 30
+    e = workloads.random_regular_graph(d, n, 0)
+    a0 = np.array(workloads.qaoa_angles(0, 64, 1))[0]
+    zz = closed_form.zz_p1(n, e, a0[0], a0[1])[0]
+    dg, db = closed_form.zz_p1_grad(n, e, a0[0], a0[1])
+    net = qaoa.edge_network(n, e, 1, e[0], dtype=qtn.TN_C64, lightcone=False)
+    net.set_order(net.order_linegraph(trials=1024, seed=0))
+    info = net.plan_info()
+    assert info["peak_bits"] == 30
+    prm = torch.tensor([a0], dtype=torch.float64, device="cuda")
+    for prec, tz, tg in ((qtn.TN_MFMA_FP32, 1e-6, 1e-5), (qtn.TN_MFMA_BF16X3, 1e-5, 1e-4)):
+        b = qtn.Batch([net], max_sets=1)
+        b.set_precision(prec)
+        assert b.workspace_bytes() > 8 << 31  # the region passes 2^31 elements
+        out = torch.empty((1, 1, 2), dtype=torch.float64, device="cuda")
+        gn = torch.empty((1, 1, 2), dtype=torch.float64, device="cuda")
+        _say(f"config 5 whole circuit d={d} n={n} 2^30, precision {prec}: forward")
+        b.contract(prm, out=out)
+        torch.cuda.synchronize()
+        v = out[0, 0].cpu().numpy()
+        assert abs(v[0] - zz) <= tz and abs(v[1]) <= tz
+        _say(f"config 5 precision {prec}: forward + gradient")
+        b.grad(prm, out=out, grad_net=gn)
+        torch.cuda.synchronize()
+        g = gn[0, 0].cpu().numpy()
+        assert abs(out[0, 0, 0].item() - zz) <= tz
+        assert abs(g[0] - dg[0]) <= tg and abs(g[1] - db[0]) <= tg
+        del b
+        torch.cuda.empty_cache()
