@@ -658,7 +658,10 @@ ItemCtx item_ctx(const tn_batch *b) {
 // write global memory. Candidates take arena space first-fit when written
 // and give it back after their last read; one that does not fit stays in
 // the region. Tensors are told apart by their region offset (a write at an
-// offset starts a new tensor there).
+// offset starts a new tensor there). With gradients (v = 1) the adjoint
+// accumulators of the parametric tensors take a fixed block after the
+// mirror, for the whole program (*acc_at: its LDS offset, else -1), so
+// leaf adjoints add into LDS.
 struct LdsOp {
   int32_t flags = 0, x = 0, y = 0, z = 0;
 };
@@ -667,9 +670,10 @@ static bool lds_mirror(const ItemCtx &c, const LevelNet &ln) {
   return c.one_wg && c.lds_elems > 0 && ln.leaf_region > 0 && 2 * ln.leaf_region <= c.lds_elems;
 }
 
-static std::vector<LdsOp> lds_assign(const ItemCtx &c, const LevelNet &ln, int v) {
+static std::vector<LdsOp> lds_assign(const ItemCtx &c, const LevelNet &ln, int v, int64_t *acc_at) {
   const int n = ln.n_ops[v];
   std::vector<LdsOp> res(n);
+  *acc_at = -1;
   if (!c.one_wg || c.lds_elems <= 0) return res;
   const bool mirror = lds_mirror(c, ln);
   const int64_t leaf = ln.leaf_region;
@@ -712,7 +716,11 @@ static std::vector<LdsOp> lds_assign(const ItemCtx &c, const LevelNet &ln, int v
       inst.push_back(t);
     }
   }
-  const int64_t base = mirror ? ((leaf + 31) & ~int64_t(31)) : 0;
+  int64_t base = mirror ? ((leaf + 31) & ~int64_t(31)) : 0;
+  if (v == 1 && ln.ptens_elems > 0 && 2 * (base + ln.ptens_elems) <= c.lds_elems) {
+    *acc_at = base;
+    base = (base + ln.ptens_elems + 31) & ~int64_t(31);
+  }
   const int64_t cap = c.lds_elems - base;
   Arena ar;
   for (int k = 0; k < n; ++k) {
@@ -743,6 +751,10 @@ static std::vector<LdsOp> lds_assign(const ItemCtx &c, const LevelNet &ln, int v
       if (thin && w >= 0 && inst[w].lds >= 0) {
         r.flags |= kLdsZ;
         r.z = (int32_t)inst[w].lds;
+      }
+      if (!thin && *acc_at >= 0 && op.y >= ln.gbar_begin && op.y + (int64_t(1) << op.nFX) <= ln.gbar_begin + ln.ptens_elems) {
+        r.flags |= kLdsY;  // the accumulator
+        r.y = (int32_t)(*acc_at + op.y - ln.gbar_begin);
       }
     }
     // give back what this op read for the last time, and a result nobody reads
@@ -775,8 +787,8 @@ static bool packed_tab(const ItemCtx &c, const DOp &op, int32_t &px, int32_t &py
 
 // --- level items ------------------------------------------------------------------------------
 
-// Runs of up to four consecutive record items whose contractions touch
-// disjoint LDS ranges where one of them writes (no read-after-write,
+// Runs of up to four consecutive record items whose contractions (or leaf
+// adjoint additions) touch disjoint LDS ranges where one of them writes (no read-after-write,
 // write-after-read or write-after-write between them) become one item: wave w
 // runs the w-th (their records are consecutive), one barrier for all.
 static void group_records(std::vector<PItem> &items, size_t first) {
@@ -787,6 +799,7 @@ static void group_records(std::vector<PItem> &items, size_t first) {
     x = {op.x, op.x + ((int64_t)1 << (op.nFX + op.nB + op.nS))};
     y = {op.y, op.y + ((int64_t)1 << (op.nS + op.nB + op.nFY))};
     z = {op.z, op.z + ((int64_t)1 << (op.nFX + op.nB + op.nFY))};
+    if (op.type == OP_LEAFGRAD) y = z = {op.y, op.y + ((int64_t)1 << op.nFX)};  // adds into its accumulator
   };
   auto overlap = [](const Rng &a, const Rng &b) { return a.lo < b.hi && b.lo < a.hi; };
   std::vector<PItem> outv(items.begin(), items.begin() + first);
@@ -847,10 +860,12 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
   };
   const size_t first_item = out.size();
   auto push = [&](const PItem &it) { out.push_back(it); };
-  const std::vector<LdsOp> lds = lds_assign(c, ln, v);
+  int64_t acc_at = -1;
+  const std::vector<LdsOp> lds = lds_assign(c, ln, v, &acc_at);
   {
     PItem it = base_item(PK_SETUP);
-    it.mv = lds_mirror(c, ln) ? 1 : 0;
+    it.mv = (lds_mirror(c, ln) ? 1 : 0) | (acc_at >= 0 ? 2 : 0);
+    it.a4 = (int32_t)std::max<int64_t>(acc_at, 0);
     const int64_t zero_n = v == 1 ? ln.ptens_elems : 0;
     const int64_t per = ln.n_const + ln.ptens_elems + zero_n;
     it.lgl = c.one_wg ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>(64, ceil_div(per, 1024)));
@@ -916,6 +931,23 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
             c.trecs->resize(at);
           }
         }
+        // a leaf adjoint with its adjoint and accumulator in LDS: one wave
+        // adds it from a record
+        if (!thin && c.trecs && (r.flags & (kLdsX | kLdsY)) == (kLdsX | kLdsY) && op.nFX <= 8 &&
+            it.op.y < (1 << 17)) {
+          it.kind = PK_TREC;
+          it.rec = (int32_t)(c.trecs->size() / (4 * kRecLanes));
+          it.count = 1;
+          for (int l = 0; l < kRecLanes; ++l) {
+            int32_t cy = 0;
+            for (int q = 0; q < 4; ++q)
+              if (l + (q << 6) < (1 << op.nFX)) cy |= ((*c.tabs)[op.tab + l + (q << 6)] & 0xff) << (8 * q);
+            c.trecs->push_back((int32_t)it.op.x + l);
+            c.trecs->push_back(cy);
+            c.trecs->push_back(0);
+            c.trecs->push_back(l == 0 ? (int32_t)(kRecAcc | (op.nFX << 7) | ((uint32_t)it.op.y << 15)) : 0);
+          }
+        }
       }
       const int lg = thin ? op.nFX + op.nB + op.nFY : op.nFX;
       int64_t work = ((int64_t)1 << lg) * n_sets;
@@ -964,6 +996,9 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
   f.a0 = ln.net;
   f.a1 = ln.ptens_begin;
   f.a2 = ln.n_ptens;
+  f.mv = acc_at >= 0 ? 1 : 0;  // adjoint accumulators in LDS from a3
+  f.a3 = (int32_t)std::max<int64_t>(acc_at, 0);
+  f.zs = ln.gbar_begin;
   push(f);
   if (c.one_wg) group_records(out, first_item);
   for (size_t i = first_item; i + 1 < out.size(); ++i) {
@@ -1050,7 +1085,10 @@ void plan_workspace(tn_batch *b) {
       for (int l : g.lv) {
         b->cap_titems[v] += titem_count(b->level[l], v);
         const LevelNet &ln = b->level[l];
-        for (int k = 0; k < ln.n_ops[v]; ++k) b->cap_trecs += record_shape(hp.ops[ln.op_begin[v] + k]) ? 4 * kRecLanes : 0;
+        for (int k = 0; k < ln.n_ops[v]; ++k) {
+          const DOp &op = hp.ops[ln.op_begin[v] + k];
+          b->cap_trecs += record_shape(op) || (op.type == OP_LEAFGRAD && op.nFX <= 8) ? 4 * kRecLanes : 0;
+        }
       }
   }
   WsLayout &w = b->ws;

@@ -97,9 +97,13 @@ struct DNet {
 //  kRecLeafGrad adjoint of a parametric leaf, 2^B <= 256 entries: x =
 //               offset of entry l, y = canonical indices of entries
 //               l + 64 q (8 bits each), z of lane 0 the bound-tensor slot,
-//               of lanes 1-2 the FP64 coefficient.
+//               of lanes 1-2 the FP64 coefficient;
+//  kRecAcc      (task executor) adjoint of a parametric leaf, 2^B <= 256
+//               entries, added into its accumulator at the header's
+//               offset: x = offset of entry l, y = canonical indices of
+//               entries l + 64 q (8 bits each).
 // Type 0: the op runs from its DOp descriptor.
-constexpr int kRecLite = 1, kRecWide = 2, kRecNarrow = 3, kRecScalar = 4, kRecSeed = 5, kRecLeafGrad = 6;
+constexpr int kRecLite = 1, kRecWide = 2, kRecNarrow = 3, kRecScalar = 4, kRecSeed = 5, kRecLeafGrad = 6, kRecAcc = 7;
 constexpr int kRecLanes = 64;
 
 // Set-packed records: one 64-lane wave runs S = 2 or 4 angle sets of one
@@ -144,9 +148,9 @@ enum PKind : int32_t {
   PK_SCALAR_SUM = 5,  // rank-0 result: sum of the partial sums in index order (FP64)
   PK_SEED = 6,        // adjoint seed: product of the other component scalars
   PK_FINISH = 7,      // value and gradient of the network into the outputs
-  PK_TREC = 8         // task executor: count (1-4) small independent thin contractions from lane
-                      // records rec, rec + 1, ... (wave w runs record rec + w), operands in the
-                      // workgroup's LDS arena
+  PK_TREC = 8         // task executor: count (1-4) small independent thin contractions or leaf
+                      // adjoint additions from lane records rec, rec + 1, ... (wave w runs record
+                      // rec + w), operands in the workgroup's LDS arena
 };
 
 struct PItem {
@@ -174,9 +178,13 @@ struct PItem {
 // LDS arena of kLdsArenaBytes. SETUP with mv = 1 also copies the leaf
 // region (constants and bound parametric tensors) to LDS [0, leaf region).
 // A THIN item's a0 says which operands live there: kLdsX / kLdsY / kLdsZ
-// (op.x / op.y / op.z are then LDS element offsets); kPackedTab: the
-// summed-index offsets come from the bit positions in a1 (X) and a2 (Y), 5
-// bits per summed bit, lowest first, instead of the table (nS <= 6).
+// (op.x / op.y / op.z are then LDS element offsets; a leaf adjoint's
+// accumulator is its Y); kPackedTab: the summed-index offsets come from the
+// bit positions in a1 (X) and a2 (Y), 5 bits per summed bit, lowest first,
+// instead of the table (nS <= 6). With gradients the adjoint accumulators
+// may live in LDS too, as one block at LDS element a4 of SETUP (mv bit 1),
+// which clears it there instead of in the region; FINISH (mv = 1) then reads
+// the accumulator of region offset goff at LDS a3 + goff - zs.
 constexpr int kLdsX = 1, kLdsY = 2, kLdsZ = 4, kPackedTab = 8;
 constexpr int kPackedTabBits = 6;
 template <int PREC>

@@ -53,9 +53,9 @@ __global__ __launch_bounds__(256, kMinWaves<PREC>) void item_kernel(PItem it, Lv
 // memory round trip per descriptor field. Every thread takes part (indices
 // clamped; threads past the descriptor rewrite its padding word), keeping
 // the loop free of per-thread branches.
-// A PK_TREC item: wave w forms the w-th of the item's small independent
-// contractions from its lane record (loaded while the item before it ran);
-// the operands are in the LDS arena.
+// A PK_TREC item: wave w runs the w-th of the item's small independent
+// contractions (or leaf adjoint additions) from its lane record (loaded
+// while the item before it ran); the operands are in the LDS arena.
 template <typename V>
 __device__ __forceinline__ void run_rec(const V *xm, const V *ym, V *zm, const int4 &rec) {
   const uint32_t hdr = (uint32_t)__builtin_amdgcn_readfirstlane(rec.w);
@@ -70,6 +70,8 @@ __device__ __forceinline__ void run_rec(const V *xm, const V *ym, V *zm, const i
     contract_wide<V>(xm, ym, zm, rec, hdr);
   } else if (type == kRecNarrow) {
     contract_narrow<V>(xm, ym, zm, rec, hdr);
+  } else if (type == kRecAcc) {
+    acc_rec<V>(xm, zm, rec, hdr);
   }
 }
 

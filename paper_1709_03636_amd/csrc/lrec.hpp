@@ -178,4 +178,26 @@ __device__ __forceinline__ void contract_narrow(V *mem, const int4 &rec, uint32_
   contract_narrow<V>(mem, mem, mem, rec, hdr);
 }
 
+// kRecAcc (task executor): a leaf adjoint of 2^B <= 256 entries added into
+// its parametric tensor's accumulator in canonical layout: lane l adds
+// entries l + 64 q (offset x of entry l, canonical indices packed 8 bits
+// each in y) to the accumulator at the header's offset. The canonical map
+// is a permutation, so no two lanes write the same entry.
+template <typename V>
+__device__ __forceinline__ void acc_rec(const V *xm, V *zm, const int4 &rec, uint32_t hdr) {
+  const int cnt = 1 << ((hdr >> 7) & 15u);
+  const int z = (int)(hdr >> 15);
+  const int l = (int)(threadIdx.x & 63);
+  V xv[4], zv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (l + 64 * q < cnt) {
+      xv[q] = xm[rec.x + 64 * q];
+      zv[q] = zm[z + (((uint32_t)rec.y >> (8 * q)) & 0xffu)];
+    }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (l + 64 * q < cnt) zm[z + (((uint32_t)rec.y >> (8 * q)) & 0xffu)] = cadd(zv[q], xv[q]);
+}
+
 }  // namespace qtn

@@ -276,11 +276,12 @@ __device__ __forceinline__ void task_thin(const PItem &it, int rank, int count, 
       const int64_t set = g >> op.nFX;
       const int i = (int)(g & (m - 1));
       V *base = reg + set * it.stride;
-      V v = base[op.y + tab[i]];
+      V *acc = pick(base, kLdsY);
+      V v = acc[op.y + tab[i]];
       const V x = pick(base, kLdsX)[op.x + i];
       v.x += x.x;
       v.y += x.y;
-      base[op.y + tab[i]] = v;
+      acc[op.y + tab[i]] = v;
     }
     return;
   }
@@ -502,11 +503,12 @@ __device__ __forceinline__ void task_setup(const PItem &it, int rank, const LvlA
       if (mirror) lar[d.off + e] = v;
     }
   }
+  V *zdst = lar && (it.mv & 2) ? lar + it.a4 : base + it.zs;  // adjoint accumulators in LDS or the region
   for (int e = first; e < it.a5; e += step) {
     V z;
     z.x = 0;
     z.y = 0;
-    base[it.zs + e] = z;
+    zdst[e] = z;
   }
 }
 
@@ -514,12 +516,15 @@ __device__ __forceinline__ void task_setup(const PItem &it, int rank, const LvlA
 // component scalars) and, with gradients, sum over its parametric tensors of
 // coeff * Re <Gbar, dG/dtheta> per parameter, in FP64.
 template <typename V>
-__device__ __forceinline__ void task_finish(char *lds, const PItem &it, int rank, const LvlArgs &a) {
+__device__ __forceinline__ void task_finish(char *lds, const PItem &it, int rank, const LvlArgs &a, const V *lar) {
   const int set = rank;
   if (set >= a.n_sets) return;
   double *red = reinterpret_cast<double *>(lds);
   double *gacc = red + 8;
   const V *base = reinterpret_cast<const V *>(a.arena) + it.base + set * it.stride;
+  const bool gl = lar && it.mv;  // adjoint accumulators (offsets goff) in LDS from a3
+  const V *gb = gl ? lar : base;
+  const int64_t g0 = gl ? it.a3 - it.zs : 0;
   const int gs = a.set0 + set, net = it.a0;
   if (threadIdx.x == 0) {
     const double *sc = a.scal + it.sbase + (int64_t)set * it.n_comp * 2;
@@ -542,7 +547,7 @@ __device__ __forceinline__ void task_finish(char *lds, const PItem &it, int rank
       if (d.param < p0 || d.param >= p0 + 64) continue;
       double acc = 0.0;
       for (int e = threadIdx.x; e < (1 << d.bits); e += 256) {
-        const double2 g = l_d2(base[d.goff + e]);
+        const double2 g = l_d2(gb[g0 + d.goff + e]);
         const double2 dv = l_d2(dset[d.slot + e]);
         acc += g.x * dv.x - g.y * dv.y;
       }
@@ -571,7 +576,7 @@ __device__ __forceinline__ void run_item(char *lds, char *lar, const PItem &it, 
     case PK_SCALAR: task_scalar<V>(lds, it, rank, a); break;
     case PK_SCALAR_SUM: task_scalar_sum(it, rank, a); break;
     case PK_SEED: task_seed<V>(it, rank, a); break;
-    default: task_finish<V>(lds, it, rank, a); break;
+    default: task_finish<V>(lds, it, rank, a, larv); break;
   }
 }
 

@@ -264,7 +264,7 @@ def test_config5_whole_circuit_2p30():
     net.set_order(net.order_linegraph(trials=1024, seed=0))
     info = net.plan_info()
     assert info["peak_bits"] == 30
-    prm = torch.tensor([a0], dtype=torch.float64, device="cuda")
+    prm = torch.tensor(np.array([a0]), dtype=torch.float64, device="cuda")
     for prec, tz, tg in ((qtn.TN_MFMA_FP32, 1e-6, 1e-5), (qtn.TN_MFMA_BF16X3, 1e-5, 1e-4)):
         b = qtn.Batch([net], max_sets=1)
         b.set_precision(prec)
