@@ -592,17 +592,21 @@ static LevelNet append_level(const Net &net, const NetLayout &lay, HostProgram &
 // --- matrix-core eligibility and tile shapes --------------------------------------------------
 
 // True when the matrix-core path takes this op: no batch bits, at least 16
-// summed entries; complex64: one free index at least 64 wide, the other at
-// least 4 (tiles 64 x 64, 16 x 64 or 64 x 16; a 4- or 8-wide index is one
-// padded 16-wide tile); complex128: both at least 64 wide (64 x 64 tiles).
+// summed entries; complex64: both free indices at least 4 wide and one at
+// least 64 wide (tiles 64 x 64, 16 x 64 or 64 x 16; a 4- or 8-wide index is
+// one padded 16-wide tile), or both narrower than 64 with at least 64
+// summed entries (one 16 x 64 tile whose columns past the Y index read
+// aliased entries and are not written: a long sum on few outputs is
+// latency-bound on the vector units); complex128: both at least 64 wide
+// (64 x 64 tiles).
 bool mfma_eligible(int dtype, const DOp &op) {
   if (op.type != OP_CONTRACT || op.nB != 0 || op.nS < 4) return false;
   if (dtype == TN_C128) return op.nFX >= 6 && op.nFY >= 6;
-  return dtype == TN_C64 && op.nFX >= 2 && op.nFY >= 2 && (op.nFX >= 6 || op.nFY >= 6);
+  return dtype == TN_C64 && op.nFX >= 2 && op.nFY >= 2 && (op.nFX >= 6 || op.nFY >= 6 || op.nS >= 6);
 }
 
 static inline int tile_m(const DOp &op) { return op.nFX >= 6 ? 64 : 16; }
-static inline int tile_n(const DOp &op) { return op.nFY >= 6 ? 64 : 16; }
+static inline int tile_n(const DOp &op) { return op.nFY >= 6 || op.nFX < 6 ? 64 : 16; }
 
 // Output tiles of an eligible op per parameter vector.
 int mfma_tiles(const DOp &op) {
@@ -1039,6 +1043,9 @@ int plan_level(tn_batch *b) {
                        [&](int x, int y) { return b->level[g.lv[x]].cost > b->level[g.lv[y]].cost; });
       ItemCtx c = item_ctx(b);
       c.one_wg = true;
+      // every eligible product on the matrix cores: the tuner's per-class
+      // choices are timed on chip-wide item launches, not on one workgroup
+      c.use_mfma = nullptr;
       c.lds_elems = b->dtype == TN_C128 ? kLdsArenaBytes<TN_MFMA_FP64> / 16 : kLdsArenaBytes<TN_MFMA_FP32> / 8;
       if (const char *env = std::getenv("QTN_TASK_LDS")) c.lds_elems = std::min(c.lds_elems, std::max(0, std::atoi(env)));
       c.trecs = &b->trecs;

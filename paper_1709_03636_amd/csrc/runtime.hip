@@ -854,14 +854,23 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
     found["sets_per_wave_fwd:" + suffix] = b->spw[0];
   }
   // (2) large level ops: matrix cores vs thin per shape class, each timed as
-  // an item of the pass's parameter-vector count on scratch operands
+  // an item of the pass's parameter-vector count on scratch operands (item
+  // mode only: the task executor puts every eligible product on the matrix
+  // cores)
   std::map<std::string, DOp> classes;
-  for (const LevelNet &ln : b->level)
-    for (int v = 0; v < 2; ++v)
+  std::vector<char> tasked(b->level.size(), 0);
+  for (const LevelGroup &g : b->groups)
+    if (g.tasked)
+      for (int l : g.lv) tasked[l] = 1;
+  for (size_t l = 0; l < b->level.size(); ++l)
+    for (int v = 0; v < 2; ++v) {
+      if (tasked[l]) continue;
+      const LevelNet &ln = b->level[l];
       for (int o = 0; o < ln.n_ops[v]; ++o) {
         const DOp &op = b->hp.ops[ln.op_begin[v] + o];
         if (mfma_eligible(b->dtype, op)) classes.emplace(shape_class(b->dtype, op, b->mfma_prec), op);
       }
+    }
   const int eb = b->dtype == TN_C128 ? 16 : 8;
   const int prec = b->dtype == TN_C128 ? TN_MFMA_FP64 : b->mfma_prec;
   for (auto &kv : classes) {

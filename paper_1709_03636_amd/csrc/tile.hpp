@@ -165,8 +165,8 @@ __device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs,
   using R = typename Acc4<V>::R;
   using A4 = typename Acc4<V>::type;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // a free index narrower than its tile side (2-3 bits) is one padded tile:
-  // rows / columns past it read aliased operand entries and are not written
+  // a free index narrower than its tile side is one padded tile: rows /
+  // columns past it read aliased operand entries and are not written
   const int sy = op.nFY > T::LN ? op.nFY - T::LN : 0;
   const int n0 = (tile & ((1 << sy) - 1)) * BN, m0 = (tile >> sy) * BM;
   const V *X = base + op.x;
@@ -270,8 +270,8 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
                                             int kb, int ke, float2 *__restrict__ Z) {
   using T = TileT<BM, BN>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // a free index narrower than its tile side (2-3 bits) is one padded tile:
-  // rows / columns past it read aliased operand entries and are not written
+  // a free index narrower than its tile side is one padded tile: rows /
+  // columns past it read aliased operand entries and are not written
   const int sy = op.nFY > T::LN ? op.nFY - T::LN : 0;
   const int n0 = (tile & ((1 << sy) - 1)) * BN, m0 = (tile >> sy) * BM;
   const float2 *X = base + op.x;

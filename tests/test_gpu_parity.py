@@ -623,7 +623,8 @@ def test_split_summed_index(monkeypatch):
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_level_mfma_tile_shapes(prec, mode, monkeypatch):
     """Matrix-core products of every tile shape (64 x 64, and 16 x 64 / 64 x 16
-    where one free index has 2 to 5 bits, padded below 4), forward and adjoint,
+    where one free index has 2 to 5 bits, padded below 4; 16 x 64 with both
+    narrower than 64 and a long sum, aliased columns), forward and adjoint,
     one launch per item over the networks of a group (item mode: products
     spread over many workgroups) or within one workgroup's whole program (task
     executor): 4-regular n=14 p=2 light-cone networks on the level executor,
@@ -644,9 +645,9 @@ def test_level_mfma_tile_shapes(prec, mode, monkeypatch):
     for net in model.nets:
         for fx, s, fy in net.plan_steps():
             for a, ss, c in ((fx, s, fy), (fx, fy, s), (s, fx, fy)):  # the step and its two adjoints
-                if ss >= 4 and min(a, c) >= 2 and max(a, c) >= 6:
-                    shapes.add((64 if a >= 6 else 16, 64 if c >= 6 else 16))
-                    padded += min(a, c) < 4  # a 4- or 8-wide index in a padded 16-wide tile
+                if ss >= 4 and min(a, c) >= 2 and (max(a, c) >= 6 or ss >= 6):
+                    shapes.add((64 if a >= 6 else 16, 64 if c >= 6 or a < 6 else 16))
+                    padded += min(a, c) < 4 or max(a, c) < 6  # an index narrower than its tile side
     assert shapes == {(64, 64), (16, 64), (64, 16)} and padded > 0
     model.batch.set_precision(qtn.TN_MFMA_FP32 if prec == "fp32" else qtn.TN_MFMA_BF16X3)
     info = model.batch.info()
