@@ -87,69 +87,91 @@ __device__ __forceinline__ uint32_t g_deposit(uint32_t v, const int32_t runs[4],
   return r;
 }
 
-__device__ __forceinline__ int2 g_tab(const int32_t *__restrict__ tb, int nS, int k) {
-  if (nS <= kTabLoBits) return make_int2(tb[2 * k], tb[2 * k + 1]);
-  const int lo = k & ((1 << kTabLoBits) - 1), hi = k >> kTabLoBits;
-  const int32_t *h = tb + (2 << kTabLoBits);
-  return make_int2(tb[2 * lo] + h[2 * hi], tb[2 * lo + 1] + h[2 * hi + 1]);
-}
-
 // Staging assignment: each thread moves NX X and NY Y entries per stage.
-// Summed-index offsets add over disjoint bits, so the offset of k0 + k (k0
-// a multiple of BK, k < BK) is t(k0) + t(k): the per-thread parts t(k) are
-// fixed, and t(k0) is one workgroup-uniform lookup per stage.
+// Summed-index offsets are sums over the set bits of k of one (X, Y) offset
+// per summed bit (the offset table is built that way), so they are formed
+// from those per-bit offsets, one bit per lane, read from the table once
+// per tile: the offset of k0 + k (k0 a multiple of BK, k < BK) is the
+// thread's fixed part t(k) plus the workgroup-uniform t(k0), formed in
+// scalar registers, and no stage waits on a table read.
 // XK: X's lowest address bit is summed (stage X with k fastest), else m
 // fastest; YK likewise for Y. BLK (split-BF16 tiles, whose LDS rows are
 // [row][k] with a 20-dword stride): with m (n) fastest, a wave stages a
 // 16 x 4 block (16 consecutive rows, 128 contiguous bytes each, at 4 summed
 // entries) instead of 64 rows at one summed entry, so its LDS writes fall
 // on 64 different banks instead of 16.
-template <bool XK, bool YK, int BM, int BN, typename V = float2, bool BLK = false>
+// LDS element offsets: X entry (row m, summed k) at m * XM + k * XKS, Y
+// entry (k, column n) at k * YKS + n * YN.
+template <bool XK, bool YK, int BM, int BN, typename V, bool BLK, int XM, int XKS, int YKS, int YN>
 struct Stager {
   using T = TileT<BM, BN>;
-  int xr[T::NX], xk[T::NX], yk[T::NY], yn[T::NY];
+  int xs[T::NX], ys[T::NY];  // LDS offsets of this thread's entries
   uint32_t xrow[T::NX], ycol[T::NY];
   V xv[T::NX], yv[T::NY];
+  int bx, by;  // lane t < nS: the X / Y offset of summed bit t
   __device__ __forceinline__ Stager(const DOp &op, const DRuns &ru, const int32_t *tab, int m0, int n0) {
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    bx = by = 0;
+    if (lane < op.nS) {
+      const int lo = op.nS < kTabLoBits ? op.nS : kTabLoBits;
+      const int32_t *e = lane < kTabLoBits ? tab + (2 << lane) : tab + (2 << lo) + (2 << (lane - kTabLoBits));
+      bx = e[0];
+      by = e[1];
+    }
+    int lx[4], ly[4];  // offsets of summed bits 0-3 (zero past nS)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      lx[b] = __builtin_amdgcn_readlane(bx, b);
+      ly[b] = __builtin_amdgcn_readlane(by, b);
+    }
+    auto low = [&](int k, const int *l) { return (k & 1 ? l[0] : 0) + (k & 2 ? l[1] : 0) + (k & 4 ? l[2] : 0) + (k & 8 ? l[3] : 0); };
 #pragma unroll
     for (int i = 0; i < T::NX; ++i) {
       const int e = tid + 256 * i;
+      int xr, xk;
       if (XK) {
-        xk[i] = e & (BK - 1);
-        xr[i] = e >> 4;
+        xk = e & (BK - 1);
+        xr = e >> 4;
       } else if (BLK) {
-        xr[i] = (e & 15) + 16 * ((e >> 6) & (BM / 16 - 1));
-        xk[i] = ((e >> 4) & 3) + 4 * (e >> (T::LM + 2));
+        xr = (e & 15) + 16 * ((e >> 6) & (BM / 16 - 1));
+        xk = ((e >> 4) & 3) + 4 * (e >> (T::LM + 2));
       } else {
-        xr[i] = e & (BM - 1);
-        xk[i] = e >> T::LM;
+        xr = e & (BM - 1);
+        xk = e >> T::LM;
       }
-      xrow[i] = g_deposit((uint32_t)(m0 + xr[i]), ru.runsX, op.maskX) + (uint32_t)g_tab(tab, op.nS, xk[i]).x;
+      xs[i] = xr * XM + xk * XKS;
+      xrow[i] = g_deposit((uint32_t)(m0 + xr), ru.runsX, op.maskX) + (uint32_t)low(xk, lx);
     }
 #pragma unroll
     for (int i = 0; i < T::NY; ++i) {
       const int e = tid + 256 * i;
+      int yk, yn;
       if (YK) {
-        yk[i] = e & (BK - 1);
-        yn[i] = e >> 4;
+        yk = e & (BK - 1);
+        yn = e >> 4;
       } else if (BLK) {
-        yn[i] = (e & 15) + 16 * ((e >> 6) & (BN / 16 - 1));
-        yk[i] = ((e >> 4) & 3) + 4 * (e >> (T::LN + 2));
+        yn = (e & 15) + 16 * ((e >> 6) & (BN / 16 - 1));
+        yk = ((e >> 4) & 3) + 4 * (e >> (T::LN + 2));
       } else {
-        yn[i] = e & (BN - 1);
-        yk[i] = e >> T::LN;
+        yn = e & (BN - 1);
+        yk = e >> T::LN;
       }
-      ycol[i] = g_deposit((uint32_t)(n0 + yn[i]), ru.runsY, op.maskY) + (uint32_t)g_tab(tab, op.nS, yk[i]).y;
+      ys[i] = yk * YKS + yn * YN;
+      ycol[i] = g_deposit((uint32_t)(n0 + yn), ru.runsY, op.maskY) + (uint32_t)low(yk, ly);
     }
   }
-  __device__ __forceinline__ void fetch(const V *X, const V *Y, const DOp &op, const int32_t *tab, int k0) {
-    const int2 t0 = g_tab(tab, op.nS, k0);
-    const int bx = __builtin_amdgcn_readfirstlane(t0.x), by = __builtin_amdgcn_readfirstlane(t0.y);
+  // loads of stage k0 (a multiple of BK)
+  __device__ __forceinline__ void fetch(const V *X, const V *Y, int k0) {
+    int ox = 0, oy = 0;
+    for (int t = 4; (k0 >> t) != 0; ++t)
+      if ((k0 >> t) & 1) {
+        ox += __builtin_amdgcn_readlane(bx, t);
+        oy += __builtin_amdgcn_readlane(by, t);
+      }
 #pragma unroll
-    for (int i = 0; i < T::NX; ++i) xv[i] = X[xrow[i] + bx];
+    for (int i = 0; i < T::NX; ++i) xv[i] = X[xrow[i] + ox];
 #pragma unroll
-    for (int i = 0; i < T::NY; ++i) yv[i] = Y[by + ycol[i]];
+    for (int i = 0; i < T::NY; ++i) yv[i] = Y[oy + ycol[i]];
   }
 };
 
@@ -171,7 +193,7 @@ __device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs,
   const int n0 = (tile & ((1 << sy) - 1)) * BN, m0 = (tile >> sy) * BM;
   const V *X = base + op.x;
   const V *Y = base + op.y;
-  Stager<XK, YK, BM, BN, V> sg(op, ru, tab, m0, n0);
+  Stager<XK, YK, BM, BN, V, false, T::AS, 1, T::BS, 1> sg(op, ru, tab, m0, n0);
   A4 cre[T::WM][T::WN], cim[T::WM][T::WN];
 #pragma unroll
   for (int i = 0; i < T::WM; ++i)
@@ -184,15 +206,15 @@ __device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs,
   const int lr = lane & 15, lk = lane >> 4;  // MFMA operand row/col and real-k index
   const int part = lk & 1;
 
-  sg.fetch(X, Y, op, tab, kb);
+  sg.fetch(X, Y, kb);
   for (int k0 = kb; k0 < ke; k0 += BK) {
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < T::NX; ++i) As[sg.xr[i] * T::AS + sg.xk[i]] = sg.xv[i];
+    for (int i = 0; i < T::NX; ++i) As[sg.xs[i]] = sg.xv[i];
 #pragma unroll
-    for (int i = 0; i < T::NY; ++i) Bs[sg.yk[i] * T::BS + sg.yn[i]] = sg.yv[i];
+    for (int i = 0; i < T::NY; ++i) Bs[sg.ys[i]] = sg.yv[i];
     __syncthreads();
-    if (k0 + BK < ke) sg.fetch(X, Y, op, tab, k0 + BK);
+    if (k0 + BK < ke) sg.fetch(X, Y, k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 2) {
       const int kc = kk + (lk >> 1);
@@ -276,7 +298,7 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
   const int n0 = (tile & ((1 << sy) - 1)) * BN, m0 = (tile >> sy) * BM;
   const float2 *X = base + op.x;
   const float2 *Y = base + op.y;
-  Stager<XK, YK, BM, BN, float2, true> sg(op, ru, tab, m0, n0);
+  Stager<XK, YK, BM, BN, float2, true, T::PS, 1, 1, T::PS> sg(op, ru, tab, m0, n0);
   mf4 cre[T::WM][T::WN], cim[T::WM][T::WN];
 #pragma unroll
   for (int i = 0; i < T::WM; ++i)
@@ -288,25 +310,25 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
   const int wr = (wave / T::GN) * 16 * T::WM, wc = (wave % T::GN) * 16 * T::WN;
   const int lr = lane & 15, lg = lane >> 4;  // operand row/col, group of 4 complex summed entries
 
-  sg.fetch(X, Y, op, tab, kb);
+  sg.fetch(X, Y, kb);
   for (int k0 = kb; k0 < ke; k0 += BK) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < T::NX; ++i) {
       uint32_t h, l;
       split_pack(sg.xv[i], h, l);
-      Ah[sg.xr[i] * T::PS + sg.xk[i]] = h;
-      Al[sg.xr[i] * T::PS + sg.xk[i]] = l;
+      Ah[sg.xs[i]] = h;
+      Al[sg.xs[i]] = l;
     }
 #pragma unroll
     for (int i = 0; i < T::NY; ++i) {
       uint32_t h, l;
       split_pack(sg.yv[i], h, l);
-      Bh[sg.yn[i] * T::PS + sg.yk[i]] = h;
-      Bl[sg.yn[i] * T::PS + sg.yk[i]] = l;
+      Bh[sg.ys[i]] = h;
+      Bl[sg.ys[i]] = l;
     }
     __syncthreads();
-    if (k0 + BK < ke) sg.fetch(X, Y, op, tab, k0 + BK);
+    if (k0 + BK < ke) sg.fetch(X, Y, k0 + BK);
     u32x4 ah[T::WM], al[T::WM], bh[T::WN], bl[T::WN];
 #pragma unroll
     for (int i = 0; i < T::WM; ++i) {
