@@ -833,6 +833,37 @@ static void group_records(std::vector<PItem> &items, size_t first) {
   items.swap(outv);
 }
 
+// Runs of consecutive record items (after grouping) become one item of up
+// to kMaxRunSteps steps: step t runs 1-4 records on waves 0.. (the counts,
+// less one, packed 2 bits per step into a0 .. a5), lgl = the number of
+// steps, count = the first step's count. Their records are consecutive.
+static void run_records(std::vector<PItem> &items, size_t first) {
+  std::vector<PItem> outv(items.begin(), items.begin() + first);
+  for (size_t i = first; i < items.size();) {
+    PItem head = items[i];
+    size_t j = i + 1;
+    if (head.kind == PK_TREC) {
+      int32_t packed[6] = {0, 0, 0, 0, 0, 0};
+      int steps = 0, next_rec = head.rec;
+      for (j = i; j < items.size() && items[j].kind == PK_TREC && steps < kMaxRunSteps && items[j].rec == next_rec; ++j) {
+        packed[steps >> 4] |= (items[j].count - 1) << (2 * (steps & 15));
+        next_rec += items[j].count;
+        ++steps;
+      }
+      head.lgl = steps;
+      head.a0 = packed[0];
+      head.a1 = packed[1];
+      head.a2 = packed[2];
+      head.a3 = packed[3];
+      head.a4 = packed[4];
+      head.a5 = packed[5];
+    }
+    outv.push_back(head);
+    i = j;
+  }
+  items.swap(outv);
+}
+
 // Contraction shapes with a lane-record form: at most 64 outputs (summed
 // index up to 12 bits), or an outer product of at most 256 outputs.
 static bool record_shape(const DOp &op) {
@@ -1004,7 +1035,10 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
   f.a3 = (int32_t)std::max<int64_t>(acc_at, 0);
   f.zs = ln.gbar_begin;
   push(f);
-  if (c.one_wg) group_records(out, first_item);
+  if (c.one_wg) {
+    group_records(out, first_item);
+    run_records(out, first_item);
+  }
   for (size_t i = first_item; i + 1 < out.size(); ++i) {
     out[i].nrec = out[i + 1].rec;
     out[i].nrec_n = out[i + 1].kind == PK_TREC ? out[i + 1].count : 0;

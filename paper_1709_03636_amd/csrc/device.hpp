@@ -148,9 +148,11 @@ enum PKind : int32_t {
   PK_SCALAR_SUM = 5,  // rank-0 result: sum of the partial sums in index order (FP64)
   PK_SEED = 6,        // adjoint seed: product of the other component scalars
   PK_FINISH = 7,      // value and gradient of the network into the outputs
-  PK_TREC = 8         // task executor: count (1-4) small independent thin contractions or leaf
-                      // adjoint additions from lane records rec, rec + 1, ... (wave w runs record
-                      // rec + w), operands in the workgroup's LDS arena
+  PK_TREC = 8         // task executor: lgl steps of small thin contractions or leaf adjoint
+                      // additions from lane records rec, rec + 1, ..., operands in the
+                      // workgroup's LDS arena; step t runs 1-4 independent records (wave w the
+                      // w-th), its count less one in bits 2(t mod 16) of a(t / 16); count: the
+                      // first step's
 };
 
 struct PItem {
@@ -186,6 +188,7 @@ struct PItem {
 // which clears it there instead of in the region; FINISH (mv = 1) then reads
 // the accumulator of region offset goff at LDS a3 + goff - zs.
 constexpr int kLdsX = 1, kLdsY = 2, kLdsZ = 4, kPackedTab = 8;
+constexpr int kMaxRunSteps = 96;  // steps of one PK_TREC item (2 bits each in a0 .. a5)
 constexpr int kPackedTabBits = 6;
 template <int PREC>
 constexpr int kLdsArenaBytes = PREC == TN_MFMA_FP64 ? 24576 : 32768;  // complex128: its tiles take more LDS

@@ -53,9 +53,10 @@ __global__ __launch_bounds__(256, kMinWaves<PREC>) void item_kernel(PItem it, Lv
 // memory round trip per descriptor field. Every thread takes part (indices
 // clamped; threads past the descriptor rewrite its padding word), keeping
 // the loop free of per-thread branches.
-// A PK_TREC item: wave w runs the w-th of the item's small independent
-// contractions (or leaf adjoint additions) from its lane record (loaded
-// while the item before it ran); the operands are in the LDS arena.
+// A PK_TREC item: a run of steps, wave w running the w-th of a step's small
+// independent contractions (or leaf adjoint additions) from its lane record
+// (the first step's loaded while the item before it ran, each later one
+// while the step before it runs); the operands are in the LDS arena.
 template <typename V>
 __device__ __forceinline__ void run_rec(const V *xm, const V *ym, V *zm, const int4 &rec) {
   const uint32_t hdr = (uint32_t)__builtin_amdgcn_readfirstlane(rec.w);
@@ -123,7 +124,25 @@ __global__ __launch_bounds__(256, kTaskWaves<PREC>) void task_kernel(LvlArgs a) 
         const int kind = __builtin_amdgcn_readfirstlane(it.kind);
         if (kind == PK_TREC) {
           V *m = reinterpret_cast<V *>(lar);
-          if (wave < __builtin_amdgcn_readfirstlane(it.count)) run_rec<V>(m, m, m, rcur);
+          const int steps = __builtin_amdgcn_readfirstlane(it.lgl);
+          const int32_t pk[6] = {__builtin_amdgcn_readfirstlane(it.a0), __builtin_amdgcn_readfirstlane(it.a1),
+                                 __builtin_amdgcn_readfirstlane(it.a2), __builtin_amdgcn_readfirstlane(it.a3),
+                                 __builtin_amdgcn_readfirstlane(it.a4), __builtin_amdgcn_readfirstlane(it.a5)};
+          auto count = [&](int t) { return ((pk[t >> 4] >> (2 * (t & 15))) & 3) + 1; };
+          int r = __builtin_amdgcn_readfirstlane(it.rec);
+          int4 cur = rcur;
+          for (int t = 0; t < steps; ++t) {
+            const int c = count(t), cn = t + 1 < steps ? count(t + 1) : 0;
+            // the next step's record of this wave is loaded while this step runs
+            int4 nx = make_int4(0, 0, 0, 0);
+            if (wave < cn) nx = a.trecs[(int64_t)(r + c + wave) * kRecLanes + (threadIdx.x & (kRecLanes - 1))];
+            if (wave < c) run_rec<V>(m, m, m, cur);
+            // steps on wave 0 alone follow each other without a barrier (a
+            // wave's LDS accesses complete in order)
+            if (cn > 0 && (c > 1 || cn > 1)) __syncthreads();
+            cur = nx;
+            r += c;
+          }
         } else {
           const int cnt = __builtin_amdgcn_readfirstlane(kind == PK_MFMA ? it.count : 1);
           for (int r = 0; r < cnt; ++r) run_item<PREC, true>(lds, lar, it, r, cnt, v);
