@@ -155,7 +155,13 @@ int tn_order_linegraph(const tn_net *net, int32_t trials, double budget_s, uint6
  * Compiles the plan; TN_ENOMEM if its peak exceeds the memory limit. */
 int tn_set_order(tn_net *net, const int32_t *pi, int32_t n);
 
-/* Device-memory limit for one network and one angle set (default 64 GiB). */
+/* Device-memory limit for one network and one angle set (default 64 GiB),
+ * applied by the next tn_set_order: an order whose forward intermediates
+ * exceed it is refused (TN_ENOMEM); when the gradient program, which keeps
+ * every forward intermediate for the adjoint steps, would exceed it, the
+ * forward steps are cut into runs whose intermediates are recomputed just
+ * before their adjoint steps (not in the paper; tn_plan_stats.recompute_runs
+ * and grad_bytes report the result). */
 int tn_set_memory_limit(tn_net *net, uint64_t bytes);
 
 typedef struct {
@@ -170,6 +176,9 @@ typedef struct {
   double flops;             /* algorithmic: 8 * 2^(|F_A|+|S|+|F_B|) per step, one angle set */
   double bytes;             /* algorithmic: e*(|A|+|B|+|C|) per step, one angle set */
   double peak_live_bytes;   /* largest sum of live intermediates, one angle set */
+  double grad_bytes;        /* gradient program: leaves plus the most intermediates and adjoints held at once */
+  int32_t recompute_runs;   /* gradient program: forward runs recomputed before their adjoints (1: none) */
+  int32_t reserved;
 } tn_plan_stats;
 
 int tn_plan_info(const tn_net *net, tn_plan_stats *out);

@@ -1,5 +1,6 @@
 // C ABI entry points (declared in include/qtn.h). Host-only calls never
 // touch the GPU; device calls forward to the batch runtime.
+#include <cmath>
 #include <cstring>
 #include <exception>
 #include <memory>
@@ -173,6 +174,15 @@ int tn_plan_info(const tn_net *net, tn_plan_stats *out) {
   out->flops = p.flops;
   out->bytes = p.bytes;
   out->peak_live_bytes = p.peak_live_bytes;
+  {
+    const qtn::Plan &g = net->gplan;
+    std::vector<int64_t> off;
+    double leaves = 0;
+    for (auto &c : net->consts) leaves += (double)c.size();
+    for (auto &t : net->ptensors) leaves += std::ldexp(1.0, t.bits);
+    out->grad_bytes = (leaves + (double)qtn::layout_buffers(g, (int)g.ops.size(), off)) * net->elem_bytes();
+    out->recompute_runs = g.recompute_runs;
+  }
   // fused-executor fit: leaves + live intermediates (forward) in 160 KiB
   double leaf = 0;
   for (auto &c : net->consts) leaf += (double)c.size();

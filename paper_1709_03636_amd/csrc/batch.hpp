@@ -45,13 +45,6 @@ constexpr int64_t kItemMaxTasks = 65536;
 constexpr int64_t kSplitTarget = 1024;
 constexpr int64_t kSplitItemBytes = int64_t(512) << 20;
 
-// First-fit arena allocator over element offsets.
-struct Arena {
-  std::vector<std::pair<int64_t, int64_t>> free_;  // (offset, size), sorted by offset
-  int64_t top = 0;
-  int64_t alloc(int64_t n);
-  void release(int64_t off, int64_t n);
-};
 
 // Layout of one network's buffers in executor memory: constant leaves,
 // parametric leaves, then the arena of intermediates/adjoints for each

@@ -14,71 +14,6 @@
 
 namespace qtn {
 
-int64_t Arena::alloc(int64_t n) {
-  for (size_t i = 0; i < free_.size(); ++i) {
-    if (free_[i].second >= n) {
-      int64_t off = free_[i].first;
-      free_[i].first += n;
-      free_[i].second -= n;
-      if (free_[i].second == 0) free_.erase(free_.begin() + i);
-      return off;
-    }
-  }
-  // extend: merge with a trailing free block
-  if (!free_.empty() && free_.back().first + free_.back().second == top) {
-    int64_t off = free_.back().first;
-    top = off + n;
-    free_.pop_back();
-    return off;
-  }
-  int64_t off = top;
-  top += n;
-  return off;
-}
-
-void Arena::release(int64_t off, int64_t n) {
-  auto it = std::lower_bound(free_.begin(), free_.end(), std::make_pair(off, (int64_t)0));
-  it = free_.insert(it, {off, n});
-  size_t i = it - free_.begin();
-  if (i + 1 < free_.size() && free_[i].first + free_[i].second == free_[i + 1].first) {
-    free_[i].second += free_[i + 1].second;
-    free_.erase(free_.begin() + i + 1);
-  }
-  if (i > 0 && free_[i - 1].first + free_[i - 1].second == free_[i].first) {
-    free_[i - 1].second += free_[i].second;
-    free_.erase(free_.begin() + i);
-  }
-}
-
-// Offsets of the buffers >= n_leaves of ops [0, n_ops) by liveness.
-static int64_t layout_buffers(const Plan &p, int n_ops, std::vector<int64_t> &off) {
-  const int NB = (int)p.labels.size();
-  const int L = p.n_leaves;
-  std::vector<int> last(NB, -1), def(NB, -1);
-  for (int i = 0; i < n_ops; ++i) {
-    const Op &op = p.ops[i];
-    if (op.type == OP_CONTRACT || op.type == OP_SEED) def[op.z] = i;
-    if (op.x >= 0) last[op.x] = std::max(last[op.x], i);
-    if (op.type != OP_LEAFGRAD && op.y >= 0) last[op.y] = std::max(last[op.y], i);
-  }
-  off.assign(NB, -1);
-  Arena ar;
-  for (int i = 0; i < n_ops; ++i) {
-    const Op &op = p.ops[i];
-    if ((op.type == OP_CONTRACT || op.type == OP_SEED) && op.z >= L) {
-      off[op.z] = ar.alloc((int64_t)1 << p.buf_bits[op.z]);
-      if (last[op.z] < 0) ar.release(off[op.z], (int64_t)1 << p.buf_bits[op.z]);
-    }
-    int reads[2] = {op.x, op.type == OP_LEAFGRAD ? -1 : op.y};
-    for (int v : reads)
-      if (v >= L && last[v] == i) {
-        ar.release(off[v], (int64_t)1 << p.buf_bits[v]);
-        last[v] = -2;  // released once even when x == y
-      }
-  }
-  return ar.top;
-}
-
 NetLayout make_layout(const Net &net) {
   NetLayout lay;
   lay.coff.resize(net.consts.size());

@@ -16,6 +16,7 @@
 #include <complex>
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/qtn.h"
@@ -85,6 +86,7 @@ struct Plan {
   double flops = 0, bytes = 0;               // forward, one angle set
   double flops_grad = 0, bytes_grad = 0;     // reverse ops only
   double peak_live_bytes = 0;
+  int recompute_runs = 1;                    // grad: forward runs recomputed before their adjoints (1: none)
   std::vector<std::array<int, 3>> step_dims; // forward (nFX, nS, nFY)
 };
 
@@ -139,6 +141,19 @@ struct OrderCost {
   double flops = 0;
 };
 OrderCost order_cost(const Net &net, const std::vector<int> &pi);
+
+// First-fit arena allocator over element offsets.
+struct Arena {
+  std::vector<std::pair<int64_t, int64_t>> free_;  // (offset, size), sorted by offset
+  int64_t top = 0;
+  int64_t alloc(int64_t n);
+  void release(int64_t off, int64_t n);
+};
+
+// Offsets of the buffers >= n_leaves written by ops [0, n_ops) of a plan,
+// reusing memory by liveness; returns the elements needed.
+int64_t layout_buffers(const Plan &p, int n_ops, std::vector<int64_t> &off);
+
 int compile_plan(const Net &net, const std::vector<int> &pi, bool with_grad, Plan &plan);
 
 }  // namespace qtn

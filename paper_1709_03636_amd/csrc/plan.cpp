@@ -15,6 +15,7 @@
 //   Ybar = X . Zbar  (sums the free labels of X, keeps the batch labels),
 // and at a parametric leaf G, d s / d theta += sum Gbar * dG/dtheta.
 #include <algorithm>
+#include <cmath>
 #include <map>
 
 #include "internal.hpp"
@@ -193,6 +194,8 @@ OrderCost order_cost(const Net &net, const std::vector<int> &pi) {
   return c;
 }
 
+static void emit_adjoint(Plan &plan, const Net &net, int segs);
+
 int compile_plan(const Net &net, const std::vector<int> &pi, bool with_grad, Plan &plan) {
   const int W = (int)net.wire_holders.size();
   if ((int)pi.size() != W) {
@@ -290,17 +293,49 @@ int compile_plan(const Net &net, const std::vector<int> &pi, bool with_grad, Pla
   }
 
   if (!with_grad) return TN_OK;
+  // the adjoint program keeps every forward intermediate; when that needs
+  // more than the network's memory limit, the forward steps are cut into
+  // segments whose intermediates are recomputed before their adjoints run
+  const Plan fwd = plan;
+  double leaf = 0;
+  for (auto &c : net.consts) leaf += (double)c.size();
+  for (auto &t : net.ptensors) leaf += std::ldexp(1.0, t.bits);
+  auto mem = [&](const Plan &q) {
+    std::vector<int64_t> off;
+    return (leaf + (double)layout_buffers(q, (int)q.ops.size(), off)) * net.elem_bytes();
+  };
+  emit_adjoint(plan, net, 1);
+  double best = mem(plan);
+  for (int segs = 2; best > (double)net.mem_limit && segs <= fwd.n_fwd_ops; segs += std::max(1, segs / 4)) {
+    Plan q = fwd;
+    emit_adjoint(q, net, segs);
+    const double m = mem(q);
+    if (m < best) {
+      best = m;
+      plan = std::move(q);
+    }
+  }
+  return TN_OK;
+}
 
-  // --- adjoint program ---------------------------------------------------------
+// Reverse-mode program after the forward ops of `plan`. With segs > 1 the
+// forward ops are cut into segs runs of about equal length; before the
+// adjoints of a run, its forward steps whose results those adjoints read
+// (directly or through another such step) are emitted again on new
+// buffers, so the forward pass keeps only the results that leave a run.
+static void emit_adjoint(Plan &plan, const Net &net, int segs) {
+  Emitter em(plan, net);
+  const int L = plan.n_leaves;
+  const int nf = plan.n_fwd_ops;
   const int NB = (int)plan.labels.size();
   std::vector<char> needs(NB, 0);
   for (int v = 0; v < L; ++v) needs[v] = net.leaves[v].src < 0;
-  for (int i = 0; i < plan.n_fwd_ops; ++i) {
+  for (int i = 0; i < nf; ++i) {
     const Op &op = plan.ops[i];
     if (op.type == OP_CONTRACT) needs[op.z] = needs[op.x] || needs[op.y];
   }
   // seeds: d(prod_j s_j)/d s_j = prod_{i != j} s_i, one rank-0 buffer each
-  for (int j = 0; j < n_comp; ++j) {
+  for (int j = 0; j < plan.n_components; ++j) {
     Op op;
     op.type = OP_SEED;
     op.x = op.y = -1;
@@ -337,27 +372,134 @@ int compile_plan(const Net &net, const std::vector<int> &pi, bool with_grad, Pla
     }
     plan.ops.push_back(std::move(op));
   };
-  for (int i = plan.n_fwd_ops - 1; i >= 0; --i) {
+  // recomputation: run of each forward op, producer of each buffer, and the
+  // buffer that replaces a forward result in the adjoints of its run
+  segs = std::max(1, std::min(segs, nf));
+  auto run_of = [&](int i) { return (int)((int64_t)i * segs / nf); };
+  std::vector<int> prod(NB, -1), rep(NB, -1), lastc(NB, -1);
+  for (int i = 0; i < nf; ++i) {
+    const Op &op = plan.ops[i];
+    if (op.type == OP_CONTRACT) prod[op.z] = i;
+    for (int v : {op.x, op.y}) lastc[v] = std::max(lastc[v], i);
+  }
+  auto rd = [&](int v) { return v >= 0 && v < NB && rep[v] >= 0 ? rep[v] : v; };
+  for (int i = nf - 1; i >= 0; --i) {
+    if (segs > 1 && (i == nf - 1 || run_of(i) != run_of(i + 1))) {
+      int first = i;
+      while (first > 0 && run_of(first - 1) == run_of(i)) --first;
+      // results read only inside the run (one read later is kept instead)
+      auto inside = [&](int v) { return v >= L && v < NB && prod[v] >= first && lastc[v] <= i; };
+      std::vector<char> again(NB, 0);
+      for (int j = i; j >= first; --j) {
+        const Op &op = plan.ops[j];
+        const bool adjoint = op.type == OP_SCALAR || (op.type == OP_CONTRACT && needs[op.z]);
+        if (!(adjoint || (op.type == OP_CONTRACT && again[op.z]))) continue;
+        for (int v : {op.x, op.y})
+          if (inside(v)) again[v] = 1;
+      }
+      for (int j = first; j <= i; ++j) {
+        const Op &f = plan.ops[j];
+        if (f.type != OP_CONTRACT || !again[f.z]) continue;
+        Op r = f;  // same labels, so the same masks and tables
+        r.x = rd(f.x);
+        r.y = rd(f.y);
+        r.z = em.new_buf(plan.labels[f.z]);
+        r.fwd = false;
+        gflops += 8.0 * std::ldexp(1.0, r.nFX + r.nB + r.nS + r.nFY);
+        gbytes += em.eb * (std::ldexp(1.0, plan.buf_bits[r.x]) + std::ldexp(1.0, plan.buf_bits[r.y]) +
+                           std::ldexp(1.0, plan.buf_bits[r.z]));
+        rep[f.z] = r.z;
+        plan.ops.push_back(std::move(r));
+      }
+    }
     const Op fop = plan.ops[i];  // copy: ops grows below
     if (fop.type == OP_CONTRACT && !needs[fop.z]) continue;  // no parameter below this result
     int zbar = fop.type == OP_SCALAR ? plan.seed_buf[fop.z] : adj.at(fop.z);
     // adjoints keep the batch labels of the forward step: exactly the shared
     // labels that belong to the operand whose adjoint is formed
     const std::vector<int> lx = plan.labels[fop.x], ly = plan.labels[fop.y];
+    const int fx = rd(fop.x), fy = rd(fop.y);
     if (needs[fop.x]) {
-      int xb = em.contract(zbar, fop.y, false, -1, gflops, gbytes, [&](int l) { return find_label(lx, l) >= 0; });
+      int xb = em.contract(zbar, fy, false, -1, gflops, gbytes, [&](int l) { return find_label(lx, l) >= 0; });
       adj[fop.x] = xb;
       if (fop.x < L) leafgrad(fop.x, xb);
     }
     if (needs[fop.y]) {
-      int yb = em.contract(fop.x, zbar, false, -1, gflops, gbytes, [&](int l) { return find_label(ly, l) >= 0; });
+      int yb = em.contract(fx, zbar, false, -1, gflops, gbytes, [&](int l) { return find_label(ly, l) >= 0; });
       adj[fop.y] = yb;
       if (fop.y < L) leafgrad(fop.y, yb);
     }
   }
   plan.flops_grad = gflops;
   plan.bytes_grad = gbytes;
-  return TN_OK;
+  plan.recompute_runs = segs;
+}
+
+// --- memory layout by liveness ---------------------------------------------------
+
+int64_t Arena::alloc(int64_t n) {
+  for (size_t i = 0; i < free_.size(); ++i) {
+    if (free_[i].second >= n) {
+      int64_t off = free_[i].first;
+      free_[i].first += n;
+      free_[i].second -= n;
+      if (free_[i].second == 0) free_.erase(free_.begin() + i);
+      return off;
+    }
+  }
+  // extend: merge with a trailing free block
+  if (!free_.empty() && free_.back().first + free_.back().second == top) {
+    int64_t off = free_.back().first;
+    top = off + n;
+    free_.pop_back();
+    return off;
+  }
+  int64_t off = top;
+  top += n;
+  return off;
+}
+
+void Arena::release(int64_t off, int64_t n) {
+  auto it = std::lower_bound(free_.begin(), free_.end(), std::make_pair(off, (int64_t)0));
+  it = free_.insert(it, {off, n});
+  size_t i = it - free_.begin();
+  if (i + 1 < free_.size() && free_[i].first + free_[i].second == free_[i + 1].first) {
+    free_[i].second += free_[i + 1].second;
+    free_.erase(free_.begin() + i + 1);
+  }
+  if (i > 0 && free_[i - 1].first + free_[i - 1].second == free_[i].first) {
+    free_[i - 1].second += free_[i].second;
+    free_.erase(free_.begin() + i);
+  }
+}
+
+// Offsets of the buffers >= n_leaves of ops [0, n_ops) by liveness.
+int64_t layout_buffers(const Plan &p, int n_ops, std::vector<int64_t> &off) {
+  const int NB = (int)p.labels.size();
+  const int L = p.n_leaves;
+  std::vector<int> last(NB, -1), def(NB, -1);
+  for (int i = 0; i < n_ops; ++i) {
+    const Op &op = p.ops[i];
+    if (op.type == OP_CONTRACT || op.type == OP_SEED) def[op.z] = i;
+    if (op.x >= 0) last[op.x] = std::max(last[op.x], i);
+    if (op.type != OP_LEAFGRAD && op.y >= 0) last[op.y] = std::max(last[op.y], i);
+  }
+  off.assign(NB, -1);
+  Arena ar;
+  for (int i = 0; i < n_ops; ++i) {
+    const Op &op = p.ops[i];
+    if ((op.type == OP_CONTRACT || op.type == OP_SEED) && op.z >= L) {
+      off[op.z] = ar.alloc((int64_t)1 << p.buf_bits[op.z]);
+      if (last[op.z] < 0) ar.release(off[op.z], (int64_t)1 << p.buf_bits[op.z]);
+    }
+    int reads[2] = {op.x, op.type == OP_LEAFGRAD ? -1 : op.y};
+    for (int v : reads)
+      if (v >= L && last[v] == i) {
+        ar.release(off[v], (int64_t)1 << p.buf_bits[v]);
+        last[v] = -2;  // released once even when x == y
+      }
+  }
+  return ar.top;
 }
 
 }  // namespace qtn

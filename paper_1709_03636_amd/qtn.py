@@ -48,7 +48,8 @@ class tn_target(ctypes.Structure):
 class tn_plan_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("n_steps", "n_tensors", "n_wires", "peak_bits", "max_rank_wires",
                                                "n_components", "fused", "lds_bytes")] + \
-               [(n, ctypes.c_double) for n in ("flops", "bytes", "peak_live_bytes")]
+               [(n, ctypes.c_double) for n in ("flops", "bytes", "peak_live_bytes", "grad_bytes")] + \
+               [(n, ctypes.c_int32) for n in ("recompute_runs", "reserved")]
 
 
 class tn_batch_stats(ctypes.Structure):

@@ -159,6 +159,36 @@ def test_linegraph_restarts_and_threads(qtn, qaoa):
         assert np.array_equal(a.plan_steps(), b.plan_steps())
 
 
+def test_gradient_recompute_plan_under_memory_limit(qtn, qaoa):
+    """A memory limit below what the gradient program needs (it keeps every
+    forward intermediate) makes tn_set_order cut the forward steps into runs
+    that are recomputed before their adjoints: the gradient program then fits
+    the limit, the forward program is unchanged, and a generous limit leaves
+    the plan without recomputation."""
+    n, p = 10, 2
+    e = workloads.random_regular_graph(4, n, 0)
+    net = qaoa.edge_network(n, e, p, e[0], dtype=qtn.TN_C128, lightcone=False)
+    pi = net.order_linegraph(trials=8, seed=0)
+    net.set_order(pi)
+    full = net.plan_info()
+    assert full["recompute_runs"] == 1 and full["grad_bytes"] > full["peak_live_bytes"]
+    for frac, expect_runs in ((0.8, True), (1.5, False)):
+        limit = int(full["grad_bytes"] * frac)
+        small = qaoa.edge_network(n, e, p, e[0], dtype=qtn.TN_C128, lightcone=False)
+        small.set_memory_limit(limit)
+        small.set_order(pi)
+        info = small.plan_info()
+        assert (info["recompute_runs"] > 1) == expect_runs, (frac, info["recompute_runs"])
+        assert info["grad_bytes"] <= limit
+        for k in ("flops", "bytes", "peak_live_bytes", "n_steps", "peak_bits"):
+            assert info[k] == full[k], k
+    # below what any cut reaches, the order still stands (the forward fits)
+    tight = qaoa.edge_network(n, e, p, e[0], dtype=qtn.TN_C128, lightcone=False)
+    tight.set_memory_limit(int(full["peak_live_bytes"] * 1.01))
+    tight.set_order(pi)
+    assert tight.plan_info()["recompute_runs"] > 1
+
+
 def test_plan_shapes_and_flops(qtn, qaoa):
     """Eq. (1): C has rank x+z and costs m^(x+y+z) multiply-adds (m = 4 per wire = 2 bits)."""
     e = workloads.random_regular_graph(3, 12, 0)
