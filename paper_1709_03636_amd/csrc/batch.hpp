@@ -105,6 +105,7 @@ struct LevelNet {
 struct LevelGroup {
   std::vector<int> lv;                              // indices into tn_batch::level
   std::vector<int64_t> abase, sbase, pbase, zbase;  // elements, doubles, doubles, elements
+  std::vector<int64_t> zsize;                       // split scratch elements of each network
   int item0[2] = {0, 0}, n_items[2] = {0, 0};       // item mode: into tn_batch::items[variant]
   bool tasked = false;
   int tnet0 = 0;                                    // task executor: into tn_batch::tnets[variant]
@@ -152,7 +153,8 @@ struct tn_batch {
   int task_min = qtn::kTaskMin;        // pairs a group needs for the task executor (QTN_TASK_MIN)
   int64_t larena_elems = 0, lscal_doubles = 0, lpart_doubles = 0, lsplit_elems = 0;
   int64_t split_target = 0;            // tasks a split matrix-core item aims at (0: no splits)
-  std::map<std::string, int> use_mfma; // autotuner: shape class of a large op -> 1 MFMA, 0 thin
+  std::map<std::string, int> use_mfma; // autotuner: shape class of a large op -> 0 thin, 1 matrix cores
+                                       // (tile by widths), 2-4 matrix cores on 64 x 64 / 16 x 64 / 64 x 16 tiles
   int mfma_prec = TN_MFMA_FP32;        // matrix-core precision of large steps (complex128: TN_MFMA_FP64)
   double flops_fwd = 0, bytes_fwd = 0, flops_grad = 0, bytes_grad = 0;
   double exec_flops[3] = {0, 0, 0}, exec_bytes[3] = {0, 0, 0};  // per executor (fused, level, global), fwd + adjoint
@@ -192,6 +194,7 @@ struct ItemCtx {
   int64_t split_target = 0;
   const std::map<std::string, int> *use_mfma = nullptr;
   bool all_thin = false;
+  int force_tile = -1;  // >= 0: every matrix-core op takes this tile shape (scratch sizing)
   bool one_wg = false;  // items for one workgroup and one vector (task executor): no split sums, one
                         // workgroup per rank-0 sum and set-up
   int lds_elems = 0;    // one_wg: elements of the workgroup's LDS arena for small tensors (0: none)
@@ -211,8 +214,9 @@ int level_prec(const tn_batch *b, const DOp &op);
 int level_prec(const ItemCtx &c, const DOp &op);
 ItemCtx item_ctx(const tn_batch *b);
 bool mfma_eligible(int dtype, const DOp &op);
-int mfma_tiles(const DOp &op);
-int mfma_variant(const DOp &op, int prec);
+int level_tile(const ItemCtx &c, const DOp &op);
+int mfma_tiles(const DOp &op, int shape);
+int mfma_variant(const DOp &op, int prec, int shape);
 // Items of one level network over n_sets parameter vectors (region offsets
 // as given); appends to `out`.
 void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int64_t abase, int64_t sbase,

@@ -540,20 +540,26 @@ bool mfma_eligible(int dtype, const DOp &op) {
   return dtype == TN_C64 && op.nFX >= 2 && op.nFY >= 2 && (op.nFX >= 6 || op.nFY >= 6 || op.nS >= 6);
 }
 
-static inline int tile_m(const DOp &op) { return op.nFX >= 6 ? 64 : 16; }
-static inline int tile_n(const DOp &op) { return op.nFY >= 6 || op.nFX < 6 ? 64 : 16; }
+// Tile of an eligible op: shape 0 by its free-index widths (above), else
+// the tuner's choice, 1 = 64 x 64, 2 = 16 x 64, 3 = 64 x 16 (any of them
+// covers any eligible op: a side wider than its index reads aliased
+// entries and does not write them).
+static inline int tile_m(const DOp &op, int shape) { return shape ? (shape == 2 ? 16 : 64) : op.nFX >= 6 ? 64 : 16; }
+static inline int tile_n(const DOp &op, int shape) {
+  return shape ? (shape == 3 ? 16 : 64) : op.nFY >= 6 || op.nFX < 6 ? 64 : 16;
+}
 
 // Output tiles of an eligible op per parameter vector.
-int mfma_tiles(const DOp &op) {
-  const int lm = tile_m(op) == 64 ? 6 : 4, ln = tile_n(op) == 64 ? 6 : 4;
+int mfma_tiles(const DOp &op, int shape) {
+  const int lm = tile_m(op, shape) == 64 ? 6 : 4, ln = tile_n(op, shape) == 64 ? 6 : 4;
   return 1 << ((op.nFX > lm ? op.nFX - lm : 0) + (op.nFY > ln ? op.nFY - ln : 0));
 }
 
 // Kernel variant of an op: bit 0 XK (X's lowest address bit is summed), bit 1
 // YK, bit 2 BM = 16, bit 3 BN = 16, bit 4 split-BF16, bit 5 FP64.
-int mfma_variant(const DOp &op, int prec) {
-  return (!(op.maskX & 1u) ? 1 : 0) | (!(op.maskY & 1u) ? 2 : 0) | (tile_m(op) == 16 ? 4 : 0) |
-         (tile_n(op) == 16 ? 8 : 0) | (prec == TN_MFMA_BF16X3 ? 16 : 0) | (prec == TN_MFMA_FP64 ? 32 : 0);
+int mfma_variant(const DOp &op, int prec, int shape) {
+  return (!(op.maskX & 1u) ? 1 : 0) | (!(op.maskY & 1u) ? 2 : 0) | (tile_m(op, shape) == 16 ? 4 : 0) |
+         (tile_n(op, shape) == 16 ? 8 : 0) | (prec == TN_MFMA_BF16X3 ? 16 : 0) | (prec == TN_MFMA_FP64 ? 32 : 0);
 }
 
 // Key of a large op for the autotuner: dtype, precision, free/summed bit
@@ -573,6 +579,17 @@ int level_prec(const ItemCtx &c, const DOp &op) {
 }
 
 int level_prec(const tn_batch *b, const DOp &op) { return level_prec(item_ctx(b), op); }
+
+// Tile shape of a matrix-core level op: the tuner's choice (its class's
+// value 2-4 is shape 1-3), else by the op's widths (0). complex128 has 64 x
+// 64 tiles only.
+int level_tile(const ItemCtx &c, const DOp &op) {
+  if (c.dtype == TN_C128) return 0;
+  if (c.force_tile >= 0) return c.force_tile;
+  if (!c.use_mfma) return 0;
+  auto it = c.use_mfma->find(shape_class(c.dtype, op, c.mfma_prec));
+  return it != c.use_mfma->end() && it->second >= 2 && it->second <= 4 ? it->second - 1 : 0;
+}
 
 ItemCtx item_ctx(const tn_batch *b) {
   ItemCtx c;
@@ -857,8 +874,9 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
     const int prec = op.type == OP_CONTRACT ? level_prec(c, op) : 0;
     if (prec) {
       it.kind = PK_MFMA;
-      it.mv = mfma_variant(op, prec);
-      const int64_t wg = (int64_t)mfma_tiles(op) * n_sets;
+      const int shape = level_tile(c, op);
+      it.mv = mfma_variant(op, prec, shape);
+      const int64_t wg = (int64_t)mfma_tiles(op, shape) * n_sets;
       const int64_t part = (int64_t)n_sets << (op.nFX + op.nFY);  // elements per range
       int ls = 0;
       while (allow_split && ls < 6 && op.nS - ls > 9 && (wg << ls) < c.split_target &&
@@ -998,8 +1016,14 @@ int plan_level(tn_batch *b) {
       if (!g.tasked) {
         for (size_t j = 0; j < g.lv.size(); ++j) {
           int64_t sn = 0, pn = 0;
+          const size_t at = b->items[v].size();
           network_items(item_ctx(b), b->level[g.lv[j]], v, b->max_sets, g.abase[j], g.sbase[j], g.pbase[j],
                         g.zbase[j], true, b->items[v], &sn, &pn);
+          if (sn > g.zsize[j]) {  // more split scratch than planned: no split sums for this network
+            b->items[v].resize(at);
+            network_items(item_ctx(b), b->level[g.lv[j]], v, b->max_sets, g.abase[j], g.sbase[j], g.pbase[j],
+                          g.zbase[j], false, b->items[v], &sn, &pn);
+          }
         }
         g.n_items[v] = (int)b->items[v].size() - g.item0[v];
         continue;
@@ -1260,12 +1284,14 @@ int plan_batch(tn_net *const *nets, int n_nets, const double *coef, double offse
     }
     // this network's rank-0 partial sums and split partial tiles, both variants
     int64_t sn = 0, pn = 0;
-    for (int v = 0; v < 2; ++v) {
-      std::vector<PItem> tmp;
-      ItemCtx c = item_ctx(b);
-      c.use_mfma = nullptr;  // every eligible op on the matrix cores: the most scratch
-      network_items(c, ln, v, max_sets, 0, 0, 0, 0, true, tmp, &sn, &pn);
-    }
+    for (int v = 0; v < 2; ++v)
+      for (int shape = 0; shape < 4; ++shape) {  // whichever tile shape the tuner picks
+        std::vector<PItem> tmp;
+        ItemCtx c = item_ctx(b);
+        c.use_mfma = nullptr;  // every eligible op on the matrix cores: the most scratch
+        c.force_tile = shape;
+        network_items(c, ln, v, max_sets, 0, 0, 0, 0, true, tmp, &sn, &pn);
+      }
     const int64_t need = (per * max_sets + 63) / 64 * 64;
     if (b->groups.empty() || (g_elems + need) * eb > level_budget) {
       b->groups.emplace_back();
@@ -1277,6 +1303,7 @@ int plan_batch(tn_net *const *nets, int n_nets, const double *coef, double offse
     g.sbase.push_back(g_scal);
     g.pbase.push_back(g_part);
     g.zbase.push_back(g_split);
+    g.zsize.push_back(sn);
     g_elems += need;
     g_scal += (int64_t)max_sets * std::max(1, ln.n_comp) * 2;
     g_part += pn;

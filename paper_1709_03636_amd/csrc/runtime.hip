@@ -853,10 +853,10 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
     found["sets_per_wave:" + suffix] = b->spw[1];
     found["sets_per_wave_fwd:" + suffix] = b->spw[0];
   }
-  // (2) large level ops: matrix cores vs thin per shape class, each timed as
-  // an item of the pass's parameter-vector count on scratch operands (item
-  // mode only: the task executor puts every eligible product on the matrix
-  // cores)
+  // (2) large level ops: per shape class, each tile shape of the matrix-core
+  // item and the thin item, timed as an item of the pass's parameter-vector
+  // count on scratch operands (item mode only: the task executor puts every
+  // eligible product on the matrix cores, tiled by its widths)
   std::map<std::string, DOp> classes;
   std::vector<char> tasked(b->level.size(), 0);
   for (const LevelGroup &g : b->groups)
@@ -892,35 +892,51 @@ int batch_autotune(tn_batch *b, const double *params, int n_sets, int reps, cons
     std::vector<DOp> one{op};
     c.ops = &one;
     c.split_target = 0;
-    std::vector<PItem> mi, ti;
+    std::vector<PItem> ti;
     int64_t sn = 0, pn = 0;
-    c.use_mfma = nullptr;
-    network_items(c, ln, 0, sets_t, 0, 0, 0, 0, false, mi, &sn, &pn);
     c.all_thin = true;
     network_items(c, ln, 0, sets_t, 0, 0, 0, 0, false, ti, &sn, &pn);
+    c.all_thin = false;
     LvlArgs la{};
     la.arena = buf;
     la.n_sets = sets_t;
     la.tabs = ws_ptr<int32_t>(b, WsLayout::TABS);
-    int rc1 = TN_OK, rc2 = TN_OK;
-    // item 1 of each list is the op (item 0 sets up, the last writes outputs)
-    float t_mfma = time_ms(st, reps, [&] { return item_launch(prec, mi[1], la, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rc1);
+    int rcl = TN_OK;
+    // candidates: the tile shapes (complex128: 64 x 64 only), then the thin
+    // item; item 1 of each list is the op (item 0 sets up, the last writes
+    // outputs)
+    int best_v = 1;
+    float best_t = 1e30f;
+    std::map<std::string, int> force;
+    c.use_mfma = &force;
+    for (int v : b->dtype == TN_C128 ? std::vector<int>{2} : std::vector<int>{2, 3, 4}) {
+      force[kv.first] = v;
+      std::vector<PItem> mi;
+      network_items(c, ln, 0, sets_t, 0, 0, 0, 0, false, mi, &sn, &pn);
+      const float t = time_ms(st, reps, [&] { return item_launch(prec, mi[1], la, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rcl);
+      if (rcl != TN_OK) break;
+      found["time_ns_tile" + std::to_string(v - 1) + ":" + kv.first + ":sets" + std::to_string(sets_t)] =
+          (int)std::min(2e9f, t * 1e6f);
+      if (t < best_t) {
+        best_t = t;
+        best_v = v;
+      }
+    }
     // the thin kernel is not a candidate for large products (2^24 and more
     // complex multiply-adds per parameter vector): the matrix cores win there
     float t_thin = 1e30f;
-    if (op.nFX + op.nS + op.nFY < 24)
-      t_thin = time_ms(st, reps, [&] { return item_launch(prec, ti[1], la, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rc2);
+    if (rcl == TN_OK && op.nFX + op.nS + op.nFY < 24)
+      t_thin = time_ms(st, reps, [&] { return item_launch(prec, ti[1], la, st) == hipSuccess ? TN_OK : TN_EDEVICE; }, rcl);
     (void)hipStreamSynchronize(st);
     dev_free(buf);
-    if (rc1 != TN_OK || rc2 != TN_OK) {
+    if (rcl != TN_OK) {
       b->poisoned = true;
       set_error("tn_batch_autotune: launch failed");
       return TN_EDEVICE;
     }
-    b->use_mfma[kv.first] = t_mfma <= t_thin ? 1 : 0;
+    b->use_mfma[kv.first] = best_t <= t_thin ? best_v : 0;
     found["mfma:" + kv.first] = b->use_mfma[kv.first];
     // measured times (ns, at sets_t angle sets), recorded for inspection only
-    found["time_ns_mfma:" + kv.first + ":sets" + std::to_string(sets_t)] = (int)std::min(2e9f, t_mfma * 1e6f);
     if (t_thin < 1e29f)
       found["time_ns_thin:" + kv.first + ":sets" + std::to_string(sets_t)] = (int)std::min(2e9f, t_thin * 1e6f);
   }
@@ -986,7 +1002,7 @@ int batch_apply_cache(tn_batch *b, const char *cache_path) {
     }
   }
   for (auto &kv : m)
-    if (kv.first.rfind("mfma:", 0) == 0) b->use_mfma[kv.first.substr(5)] = kv.second;
+    if (kv.first.rfind("mfma:", 0) == 0 && kv.second >= 0 && kv.second <= 4) b->use_mfma[kv.first.substr(5)] = kv.second;
   graph_clear(b);
   return plan_level(b);
 }

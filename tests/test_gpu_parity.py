@@ -524,6 +524,57 @@ def test_autotune_keeps_results(tmp_path):
         assert np.max(np.abs(out1.cpu().numpy()[:, s, 0] - zz)) < 1e-5
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_level_tile_shape_choices(prec, tmp_path, monkeypatch):
+    """Every tile shape the tuner can choose (64 x 64, 16 x 64, 64 x 16, for
+    any eligible product: a side wider than its index reads aliased entries
+    and does not write them) gives the oracle's values and gradients: the
+    tuner's cache is rewritten to force each shape on every matrix-core
+    class of whole-circuit 6-regular n=12 p=1 networks (level executor, one
+    launch per item), against the p=1 closed form and its derivative."""
+    qtn, qaoa = _qtn(), _qaoa()
+    monkeypatch.setenv("QTN_FUSED_LDS_MAX", "0")
+    monkeypatch.setenv("QTN_GMEM_MAX_MACS", "0")
+    monkeypatch.setenv("QTN_TASK_MIN", "1000000000")
+    n = 12
+    e = workloads.random_regular_graph(6, n, 0)
+    ang = torch.tensor(workloads.qaoa_angles(4, 2, 1), device="cuda", dtype=torch.float64)
+    nets = []
+    for ed in e[:2]:
+        net = qaoa.edge_network(n, e, 1, ed, dtype=qtn.TN_C64, lightcone=False)
+        net.set_order(net.order_linegraph(trials=4, seed=0))
+        nets.append(net)
+    p_code = qtn.TN_MFMA_FP32 if prec == "fp32" else qtn.TN_MFMA_BF16X3
+    batch = qtn.Batch(nets, max_sets=2)
+    batch.set_precision(p_code)
+    cache = str(tmp_path / "tune.txt")
+    batch.autotune(ang, reps=1, cache_path=cache)
+    lines = open(cache).read().splitlines()
+    classes = [ln.split()[0] for ln in lines if ln.startswith("mfma:")]
+    assert classes
+    a = ang.cpu().numpy()
+    tol_v, tol_g = (1e-5, 1e-4) if prec == "fp32" else (5e-5, 5e-4)
+    for v in (2, 3, 4):
+        forced = str(tmp_path / f"tile{v}.txt")
+        with open(forced, "w") as f:
+            for c in classes:
+                f.write(f"{c} {v}\n")
+        b = qtn.Batch(nets, max_sets=2)
+        b.set_precision(p_code)
+        b.apply_tuning(forced)
+        out = torch.empty((2, 2, 2), dtype=torch.float64, device="cuda")
+        gn = torch.empty((2, 2, 2), dtype=torch.float64, device="cuda")
+        b.grad(ang, out=out, grad_net=gn)
+        torch.cuda.synchronize()
+        for s in range(2):
+            zz = closed_form.zz_p1(n, e, a[s, 0], a[s, 1])[:2]
+            dg, db = closed_form.zz_p1_grad(n, e, a[s, 0], a[s, 1])
+            g_ref = np.stack([dg[:2], db[:2]], axis=1)
+            assert np.max(np.abs(out.cpu().numpy()[:, s, 0] - zz)) < tol_v, (v, s)
+            assert np.max(np.abs(gn.cpu().numpy()[:, s] - g_ref)) <= tol_g * max(1.0, np.abs(g_ref).max()), (v, s)
+        _say(f"tile shape {v - 1} {prec}: ok over {len(classes)} classes")
+
+
 def test_dense_split_bf16_precision():
     """Split-BF16 MFMA products on the dense whole-circuit networks: error
     against the state vector within the split's bound (at most 3 * 2^-18
