@@ -258,7 +258,10 @@ __device__ __forceinline__ void thin_output4s(const V *xb, const V *yb, V *zb, c
 // are read from / written to the workgroup's LDS arena `lar` instead of the
 // region, and kPackedTab items take their summed-index offsets from packed
 // bit positions instead of the table.
-template <typename V, bool LDSOK>
+// FL: the item's operands in LDS (kLdsX / kLdsY / kLdsZ, the item's a0 &
+// 7) as a compile-time set, so every access is an LDS or a global access
+// rather than a generic one.
+template <typename V, bool LDSOK, int FL>
 __device__ __forceinline__ void task_thin(const PItem &it, int rank, int count, V *arena, V *lar, int n_sets,
                                           const int32_t *__restrict__ tabs) {
   const DOp &op = it.op;
@@ -268,7 +271,7 @@ __device__ __forceinline__ void task_thin(const PItem &it, int rank, int count, 
   const int fl = LDSOK ? it.a0 : 0;
   const int3 pk = make_int3(it.a1, it.a2, fl & kPackedTab);
   V *reg = arena + it.base;
-  auto pick = [&](V *base, int bit) { return LDSOK && (fl & bit) ? lar : base; };
+  auto pick = [&](V *base, int bit) { return LDSOK && (FL & bit) ? lar : base; };
   if (op.type == OP_LEAFGRAD) {
     const int m = 1 << op.nFX;
     const int64_t tot = (int64_t)m * n_sets;
@@ -570,7 +573,20 @@ __device__ __forceinline__ void run_item(char *lds, char *lar, const PItem &it, 
   V *larv = LDSOK ? reinterpret_cast<V *>(lar) : nullptr;
   switch (it.kind) {
     case PK_SETUP: task_setup<V>(it, rank, a, larv); break;
-    case PK_THIN: task_thin<V, LDSOK>(it, rank, count, reinterpret_cast<V *>(a.arena), larv, a.n_sets, a.tabs); break;
+    case PK_THIN: {
+      V *ar = reinterpret_cast<V *>(a.arena);
+      switch (LDSOK ? it.a0 & 7 : 0) {
+        case 0: task_thin<V, LDSOK, 0>(it, rank, count, ar, larv, a.n_sets, a.tabs); break;
+        case 1: task_thin<V, LDSOK, 1>(it, rank, count, ar, larv, a.n_sets, a.tabs); break;
+        case 2: task_thin<V, LDSOK, 2>(it, rank, count, ar, larv, a.n_sets, a.tabs); break;
+        case 3: task_thin<V, LDSOK, 3>(it, rank, count, ar, larv, a.n_sets, a.tabs); break;
+        case 4: task_thin<V, LDSOK, 4>(it, rank, count, ar, larv, a.n_sets, a.tabs); break;
+        case 5: task_thin<V, LDSOK, 5>(it, rank, count, ar, larv, a.n_sets, a.tabs); break;
+        case 6: task_thin<V, LDSOK, 6>(it, rank, count, ar, larv, a.n_sets, a.tabs); break;
+        default: task_thin<V, LDSOK, 7>(it, rank, count, ar, larv, a.n_sets, a.tabs); break;
+      }
+      break;
+    }
     case PK_MFMA: task_mfma<PREC>(lds, it, rank, a); break;
     case PK_SPLITSUM: task_splitsum<V>(it, rank, count, a); break;
     case PK_SCALAR: task_scalar<V>(lds, it, rank, a); break;
