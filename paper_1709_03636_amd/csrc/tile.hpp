@@ -160,18 +160,39 @@ struct Stager {
       ycol[i] = g_deposit((uint32_t)(n0 + yn), ru.runsY, op.maskY) + (uint32_t)low(yk, ly);
     }
   }
-  // loads of stage k0 (a multiple of BK)
-  __device__ __forceinline__ void fetch(const V *X, const V *Y, int k0) {
-    int ox = 0, oy = 0;
-    for (int t = 4; (k0 >> t) != 0; ++t)
-      if ((k0 >> t) & 1) {
+  // Stages are taken in Gray-code order over a power-of-two range of them,
+  // so consecutive stages differ in one summed bit and the next stage's
+  // offset is the current one plus or minus that bit's: stage s covers
+  // summed entries kb + BK * (s ^ (s >> 1)). ox, oy: the offsets of the
+  // stage fetched last.
+  int ox, oy;
+  __device__ __forceinline__ void load() {
+#pragma unroll
+    for (int i = 0; i < T::NX; ++i) xv[i] = X_[xrow[i] + ox];
+#pragma unroll
+    for (int i = 0; i < T::NY; ++i) yv[i] = Y_[oy + ycol[i]];
+  }
+  const V *X_, *Y_;
+  // loads of stage 0 (summed entries from kb, a multiple of BK)
+  __device__ __forceinline__ void first(const V *X, const V *Y, int kb) {
+    X_ = X;
+    Y_ = Y;
+    ox = oy = 0;
+    for (int t = 4; (kb >> t) != 0; ++t)
+      if ((kb >> t) & 1) {
         ox += __builtin_amdgcn_readlane(bx, t);
         oy += __builtin_amdgcn_readlane(by, t);
       }
-#pragma unroll
-    for (int i = 0; i < T::NX; ++i) xv[i] = X[xrow[i] + ox];
-#pragma unroll
-    for (int i = 0; i < T::NY; ++i) yv[i] = Y[oy + ycol[i]];
+    load();
+  }
+  // loads of stage s >= 1: stage s - 1 with summed bit 4 + ctz(s) flipped
+  __device__ __forceinline__ void next(int s) {
+    const int b = __builtin_ctz((unsigned)s);
+    const int dx = __builtin_amdgcn_readlane(bx, 4 + b), dy = __builtin_amdgcn_readlane(by, 4 + b);
+    const bool set = ((s ^ (s >> 1)) >> b) & 1;
+    ox += set ? dx : -dx;
+    oy += set ? dy : -dy;
+    load();
   }
 };
 
@@ -206,15 +227,16 @@ __device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs,
   const int lr = lane & 15, lk = lane >> 4;  // MFMA operand row/col and real-k index
   const int part = lk & 1;
 
-  sg.fetch(X, Y, kb);
-  for (int k0 = kb; k0 < ke; k0 += BK) {
+  const int S = (ke - kb) / BK;  // a power of two
+  sg.first(X, Y, kb);
+  for (int st = 0; st < S; ++st) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < T::NX; ++i) As[sg.xs[i]] = sg.xv[i];
 #pragma unroll
     for (int i = 0; i < T::NY; ++i) Bs[sg.ys[i]] = sg.yv[i];
     __syncthreads();
-    if (k0 + BK < ke) sg.fetch(X, Y, k0 + BK);
+    if (st + 1 < S) sg.next(st + 1);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 2) {
       const int kc = kk + (lk >> 1);
@@ -310,8 +332,9 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
   const int wr = (wave / T::GN) * 16 * T::WM, wc = (wave % T::GN) * 16 * T::WN;
   const int lr = lane & 15, lg = lane >> 4;  // operand row/col, group of 4 complex summed entries
 
-  sg.fetch(X, Y, kb);
-  for (int k0 = kb; k0 < ke; k0 += BK) {
+  const int S = (ke - kb) / BK;  // a power of two
+  sg.first(X, Y, kb);
+  for (int st = 0; st < S; ++st) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < T::NX; ++i) {
@@ -328,7 +351,7 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
       Bl[sg.ys[i]] = l;
     }
     __syncthreads();
-    if (k0 + BK < ke) sg.fetch(X, Y, k0 + BK);
+    if (st + 1 < S) sg.next(st + 1);
     u32x4 ah[T::WM], al[T::WM], bh[T::WN], bl[T::WN];
 #pragma unroll
     for (int i = 0; i < T::WM; ++i) {
