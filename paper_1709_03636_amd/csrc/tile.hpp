@@ -286,19 +286,15 @@ __device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs,
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint32_t f2bf(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
-}
-__device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-// (hi, lo) packed pairs of a complex value: low half re, high half im.
+// (hi, lo) packed pairs of a complex value: low half re, high half im. The
+// conversions round to nearest even (one v_cvt_pk_bf16_f32 per pair).
 __device__ __forceinline__ void split_pack(float2 v, uint32_t &hi, uint32_t &lo) {
-  const uint32_t hr = f2bf(v.x), hm = f2bf(v.y);
-  const uint32_t lr = f2bf(v.x - bf2f(hr)), lm = f2bf(v.y - bf2f(hm));
-  hi = hr | (hm << 16);
-  lo = lr | (lm << 16);
+  hi = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){v.x, v.y}, bf16x2));
+  const float rr = v.x - __uint_as_float(hi << 16), ri = v.y - __uint_as_float(hi & 0xffff0000u);
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){rr, ri}, bf16x2));
 }
 
 __device__ __forceinline__ bf16x8 as_bf(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
