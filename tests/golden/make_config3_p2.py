@@ -3,9 +3,9 @@ configuration (seeded random 4- and 5-regular graphs, n in {50, 70, 100}, 64
 seeded angle sets), where no closed form exists and the light cones (17-42
 qubits) are too wide for state vectors.
 
-For each graph: <Z_u Z_v> on 32 sampled (edge, angle set) pairs by the
+For each graph: <Z_u Z_v> on 64 sampled (edge, angle set) pairs by the
 oracle's plain tensor-network contraction of the edge's light cone, and
-d<Z_u Z_v>/d(gamma_1, gamma_2, beta_1, beta_2) on 2 of those pairs by the
+d<Z_u Z_v>/d(gamma_1, gamma_2, beta_1, beta_2) on 4 of those pairs by the
 parameter-shift rule on the same contraction. Calls only oracle/ and the
 seeded input generators in workloads/.
 
@@ -25,7 +25,7 @@ import workloads  # noqa: E402
 from oracle import gates, gradients, tensornet  # noqa: E402
 
 GRAPHS = [(4, 50), (4, 70), (4, 100), (5, 50), (5, 70), (5, 100)]
-P, N_SETS, N_VALUES, N_GRADS = 2, 64, 32, 2
+P, N_SETS, N_VALUES, N_GRADS = 2, 64, 64, 4
 
 
 def sample_pairs(d, n, n_edges):

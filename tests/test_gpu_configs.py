@@ -66,8 +66,8 @@ def test_config3_timed_path(d, n, p):
     split-BF16 matrix-core products, autotuned, forward + adjoint gradient
     replayed twice from the captured graph. The replayed values and gradients
     are checked: p = 1 against the closed form and its derivative on every
-    edge and set; p = 2 against the oracle's light-cone contraction on 32
-    sampled (edge, set) pairs and the parameter-shift rule on 2 of them
+    edge and set; p = 2 against the oracle's light-cone contraction on 64
+    sampled (edge, set) pairs and the parameter-shift rule on 4 of them
     (tests/golden/config3_p2.json); both replays agree bit for bit."""
     from paper_1709_03636_amd import qtn, qaoa
     e = workloads.random_regular_graph(d, n, 0)
