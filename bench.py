@@ -137,7 +137,7 @@ def kernel_src_sha():
     import hashlib
     h = hashlib.sha256()
     for f in sorted(os.listdir(os.path.join(ROOT, "paper_1709_03636_amd", "csrc"))):
-        if f.endswith((".hip", ".hpp")):
+        if f.endswith((".hip", ".hpp", ".cpp")):  # kernels and the planner that writes their programs
             h.update(open(os.path.join(ROOT, "paper_1709_03636_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -198,6 +198,7 @@ struct ItemCtx {
   bool one_wg = false;  // items for one workgroup and one vector (task executor): no split sums, one
                         // workgroup per rank-0 sum and set-up
   int lds_elems = 0;    // one_wg: elements of the workgroup's LDS arena for small tensors (0: none)
+  int tile_elems = 0;   // one_wg: elements of the tile staging usable between the items that need it
   std::vector<int32_t> *trecs = nullptr;  // one_wg: lane records of PK_TREC items are appended here
   const std::vector<DOp> *ops = nullptr;
   const std::vector<int32_t> *tabs = nullptr;

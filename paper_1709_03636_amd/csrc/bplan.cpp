@@ -612,8 +612,9 @@ ItemCtx item_ctx(const tn_batch *b) {
 // or reads it runs on the vector units (a thin contraction, or a leaf
 // adjoint reading it); the matrix-core tiles, rank-0 sums and seeds read and
 // write global memory. Candidates take arena space first-fit when written
-// and give it back after their last read; one that does not fit stays in
-// the region. Tensors are told apart by their region offset (a write at an
+// and give it back after their last read; one that does not fit goes to the
+// tile staging after the arena (c.tile_elems elements) when no matrix-core
+// product runs while it lives, else stays in the region. Tensors are told apart by their region offset (a write at an
 // offset starts a new tensor there). With gradients (v = 1) the adjoint
 // accumulators of the parametric tensors take a fixed block after the
 // mirror, for the whole program (*acc_at: its LDS offset, else -1), so
@@ -678,7 +679,16 @@ static std::vector<LdsOp> lds_assign(const ItemCtx &c, const LevelNet &ln, int v
     base = (base + ln.ptens_elems + 31) & ~int64_t(31);
   }
   const int64_t cap = c.lds_elems - base;
-  Arena ar;
+  // the tile staging after the arena, past the reserve that rank-0 sums and
+  // outputs use: for tensors whose whole life has no matrix-core product
+  const int64_t tbase = c.lds_elems + kTileReserve / (c.dtype == TN_C128 ? 16 : 8), tcap = c.tile_elems;
+  std::vector<int> tile_use(n + 1, 0);  // prefix counts of the matrix-core products
+  for (int k = 0; k < n; ++k) {
+    const DOp &op = (*c.ops)[ln.op_begin[v] + k];
+    tile_use[k + 1] = tile_use[k] + (op.type == OP_CONTRACT && level_prec(c, op) != 0);
+  }
+  std::vector<char> in_tile(inst.size(), 0);
+  Arena ar, at;
   for (int k = 0; k < n; ++k) {
     const int w = uses[k][2];
     if (w >= 0 && !inst[w].banned && inst[w].size <= cap) {
@@ -687,6 +697,16 @@ static std::vector<LdsOp> lds_assign(const ItemCtx &c, const LevelNet &ln, int v
         inst[w].lds = base + off;
       else
         ar.release(off, inst[w].size);
+    }
+    if (w >= 0 && !inst[w].banned && inst[w].lds < 0 && inst[w].last > k && inst[w].size <= tcap &&
+        tile_use[inst[w].last + 1] == tile_use[k]) {
+      const int64_t off = at.alloc(inst[w].size);
+      if (off + inst[w].size <= tcap) {
+        inst[w].lds = tbase + off;
+        in_tile[w] = 1;
+      } else {
+        at.release(off, inst[w].size);
+      }
     }
     const DOp &op = (*c.ops)[ln.op_begin[v] + k];
     LdsOp &r = res[k];
@@ -718,7 +738,10 @@ static std::vector<LdsOp> lds_assign(const ItemCtx &c, const LevelNet &ln, int v
       const int t = uses[k][s];
       if (t < 0 || inst[t].lds < 0) continue;
       if ((s < 2 && inst[t].last == k) || (s == 2 && inst[t].last < 0)) {
-        ar.release(inst[t].lds - base, inst[t].size);
+        if (in_tile[t])
+          at.release(inst[t].lds - tbase, inst[t].size);
+        else
+          ar.release(inst[t].lds - base, inst[t].size);
         inst[t].lds = -2;  // released
       }
     }
@@ -1040,7 +1063,15 @@ int plan_level(tn_batch *b) {
       // choices are timed on chip-wide item launches, not on one workgroup
       c.use_mfma = nullptr;
       c.lds_elems = b->dtype == TN_C128 ? kLdsArenaBytes<TN_MFMA_FP64> / 16 : kLdsArenaBytes<TN_MFMA_FP32> / 8;
-      if (const char *env = std::getenv("QTN_TASK_LDS")) c.lds_elems = std::min(c.lds_elems, std::max(0, std::atoi(env)));
+      {
+        const int tb = b->dtype == TN_C128 ? kTileLdsBytes<TN_MFMA_FP64>
+                       : b->mfma_prec == TN_MFMA_BF16X3 ? kTileLdsBytes<TN_MFMA_BF16X3> : kTileLdsBytes<TN_MFMA_FP32>;
+        c.tile_elems = (tb - kTileReserve) / (b->dtype == TN_C128 ? 16 : 8);
+      }
+      if (const char *env = std::getenv("QTN_TASK_LDS")) {
+        c.lds_elems = std::min(c.lds_elems, std::max(0, std::atoi(env)));
+        if (c.lds_elems == 0) c.tile_elems = 0;
+      }
       c.trecs = &b->trecs;
       for (int j : order) {
         const LevelNet &ln = b->level[g.lv[j]];

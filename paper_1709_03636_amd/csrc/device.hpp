@@ -189,6 +189,16 @@ struct PItem {
 // the accumulator of region offset goff at LDS a3 + goff - zs.
 constexpr int kLdsX = 1, kLdsY = 2, kLdsZ = 4, kPackedTab = 8;
 constexpr int kMaxRunSteps = 96;  // steps of one PK_TREC item (2 bits each in a0 .. a5)
+// LDS of a matrix-core tile (the largest, 64 x 64, with 16 summed entries
+// per stage): split-BF16 four 64-row planes of 20 dwords; FP32 / FP64 the
+// X tile (64 rows of 17 entries) and the Y tile (16 rows of 66). The task
+// executor lays it after its arena; between the items that use it (matrix
+// cores; rank-0 sums and outputs use its first kTileReserve bytes) the
+// planner may place tensors there, from element kLdsArenaBytes / e +
+// kTileReserve / e.
+template <int PREC>
+constexpr int kTileLdsBytes = PREC == TN_MFMA_BF16X3 ? 4 * 64 * 20 * 4 : (64 * 17 + 16 * 66) * (PREC == TN_MFMA_FP64 ? 16 : 8);
+constexpr int kTileReserve = 1024;
 constexpr int kPackedTabBits = 6;
 template <int PREC>
 constexpr int kLdsArenaBytes = PREC == TN_MFMA_FP64 ? 24576 : 32768;  // complex128: its tiles take more LDS

@@ -84,9 +84,11 @@ static_assert(sizeof(PItem) % 4 == 0, "item descriptors are copied in whole word
 
 template <int PREC>
 __global__ __launch_bounds__(256, kTaskWaves<PREC>) void task_kernel(LvlArgs a) {
-  __shared__ __align__(16) char lds[kItemLds<PREC>];
-  __shared__ __align__(16) char lar[kLdsArenaBytes<PREC>];  // the program's small tensors
-  __shared__ __align__(16) int32_t s_item[2][kItemRow];     // current and next item descriptor
+  // the program's small tensors (arena), then the tile staging, which holds
+  // small tensors too between the items that use it
+  __shared__ __align__(16) char lsm[kLdsArenaBytes<PREC> + kItemLds<PREC>];
+  char *const lar = lsm, *const lds = lsm + kLdsArenaBytes<PREC>;
+  __shared__ __align__(16) int32_t s_item[2][kItemRow];  // current and next item descriptor
   __shared__ int s_task;
   constexpr int eb = PREC == TN_MFMA_FP64 ? 16 : 8;
   using V = typename std::conditional<PREC == TN_MFMA_FP64, double2, float2>::type;

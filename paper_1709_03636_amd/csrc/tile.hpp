@@ -416,6 +416,10 @@ constexpr int kTileLds = PREC == TN_MFMA_BF16X3 ? 4 * 64 * TileT<64, 64>::PS * 4
                          : PREC == TN_MFMA_FP64 ? (64 * TileT<64, 64>::AS + BK * TileT<64, 64>::BS) * 16
                                                 : (64 * TileT<64, 64>::AS + BK * TileT<64, 64>::BS) * 8;
 
+static_assert(kTileLds<TN_MFMA_BF16X3> == kTileLdsBytes<TN_MFMA_BF16X3> && kTileLds<TN_MFMA_FP32> == kTileLdsBytes<TN_MFMA_FP32> &&
+                  kTileLds<TN_MFMA_FP64> == kTileLdsBytes<TN_MFMA_FP64>,
+              "the planner's tile LDS sizes");
+
 // Bytes of one complex element of a precision's operands.
 constexpr int elem_bytes(int prec) { return prec == TN_MFMA_FP64 ? 16 : 8; }
 
