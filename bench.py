@@ -364,8 +364,8 @@ def batching_grid(st, dev, refs, cases=None):
     with split-BF16 matrix-core products (FP32 accumulation). Also the same
     batches with the diagonal gates on hyperedge wires. Error against the FP64
     oracle (stored values): closed form on every edge of 4 angle sets at p = 1,
-    the oracle's light-cone contraction on 32 sampled (edge, set) pairs and the
-    parameter-shift gradient on 2 of them at p = 2, checked on the last
+    the oracle's light-cone contraction on 64 sampled (edge, set) pairs and the
+    parameter-shift gradient on 4 of them at p = 2, checked on the last
     replay."""
     import torch
     import workloads
@@ -424,7 +424,7 @@ def batching_grid(st, dev, refs, cases=None):
     return {"workload": "all edge light-cone networks x 64 angle sets, fwd + adjoint grad, graph replay, complex64 "
                         "with split-BF16 matrix-core products; diagonal: ZZ gates on hyperedge wires",
             "oracle_check": "stored FP64 oracle values: closed form on every edge of 4 angle sets (p=1); light-cone "
-                            "contraction on 32 sampled (edge, set) pairs and parameter shift on 2 (p=2); last replay",
+                            "contraction on 64 sampled (edge, set) pairs and parameter shift on 4 (p=2); last replay",
             "rows": rows}
 
 
