@@ -31,13 +31,15 @@ constexpr int kMinWaves = PREC == TN_MFMA_BF16X3 ? 4 : 1;
 template <int PREC>
 constexpr int kTaskWaves = PREC == TN_MFMA_FP64 ? 1 : 3;
 // LDS of a workgroup: the largest tile, and at least the 72 doubles of the
-// FP64 sums.
+// FP64 sums; the item kernel double-buffers split-BF16 tiles.
 template <int PREC>
 constexpr int kItemLds = kTileLds<PREC> > 576 ? kTileLds<PREC> : 576;
+template <int PREC>
+constexpr int kItemKernelLds = PREC == TN_MFMA_BF16X3 ? 2 * kItemLds<PREC> : kItemLds<PREC>;
 
 template <int PREC>
 __global__ __launch_bounds__(256, kMinWaves<PREC>) void item_kernel(PItem it, LvlArgs a) {
-  __shared__ __align__(16) char lds[kItemLds<PREC>];
+  __shared__ __align__(16) char lds[kItemKernelLds<PREC>];
   run_item<PREC, false>(lds, nullptr, it, (int)blockIdx.x, (int)gridDim.x, a);
 }
 

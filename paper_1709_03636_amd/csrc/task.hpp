@@ -337,7 +337,7 @@ __device__ __forceinline__ void task_thin(const PItem &it, int rank, int count, 
 // vector: rank = (set, range, tile) with the tile fastest. An item with
 // lgl > 0 (split summed index) writes partial tiles to the split scratch
 // ([set][range][M x N] from element zs), else the result tile in place.
-template <int PREC, bool XK, bool YK, int BM, int BN>
+template <int PREC, bool XK, bool YK, int BM, int BN, bool DB>
 __device__ __forceinline__ void task_mfma_t(char *lds, const PItem &it, int rank, const LvlArgs &a) {
   using T = TileT<BM, BN>;
   constexpr int eb = elem_bytes(PREC);
@@ -350,17 +350,18 @@ __device__ __forceinline__ void task_mfma_t(char *lds, const PItem &it, int rank
   const int kl = op.nS - ls;
   char *z = ls == 0 ? base + (int64_t)op.z * eb
                     : (char *)a.split + (it.zs + ((((int64_t)set << ls) + part) << (op.nFX + op.nFY))) * eb;
-  any_tile<PREC, XK, YK, BM, BN>(lds, base, op, it.ru, a.tabs + op.tab, tile, part << kl, (part + 1) << kl, z);
+  // one-item launches (the item kernel) have LDS for two tile buffers
+  any_tile<PREC, XK, YK, BM, BN, DB>(lds, base, op, it.ru, a.tabs + op.tab, tile, part << kl, (part + 1) << kl, z);
 }
 
 // Kernel variant of a matrix-core item: bit 0 XK (X's lowest address bit is
 // summed), bit 1 YK, bit 2 BM = 16, bit 3 BN = 16 (the precision is the
 // kernel's).
-template <int PREC>
+template <int PREC, bool DB>
 __device__ __forceinline__ void task_mfma(char *lds, const PItem &it, int rank, const LvlArgs &a) {
 #define QTN_TV(XK, YK, BM, BN) \
   case (XK ? 1 : 0) | (YK ? 2 : 0) | (BM == 16 ? 4 : 0) | (BN == 16 ? 8 : 0): \
-    task_mfma_t<PREC, XK, YK, BM, BN>(lds, it, rank, a);                       \
+    task_mfma_t<PREC, XK, YK, BM, BN, DB>(lds, it, rank, a);                   \
     return;
 #define QTN_TV4(BM, BN) QTN_TV(false, false, BM, BN) QTN_TV(true, false, BM, BN) QTN_TV(false, true, BM, BN) \
   QTN_TV(true, true, BM, BN)
@@ -565,7 +566,9 @@ __device__ __forceinline__ void task_finish(char *lds, const PItem &it, int rank
 
 // Task `rank` of `count` of an item; PREC: the matrix-core precision
 // (TN_MFMA_FP32 or TN_MFMA_BF16X3 for complex64, TN_MFMA_FP64 for
-// complex128). lds: at least max(kTileLds<PREC>, 72 doubles), 16-byte aligned.
+// complex128). lds: at least max(kTileLds<PREC>, 72 doubles), 16-byte aligned;
+// twice kTileLds for split-BF16 items unless LDSOK (item kernel: double
+// buffered tiles).
 // lar: the task executor's LDS arena for small tensors (LDSOK), else unused.
 template <int PREC, bool LDSOK>
 __device__ __forceinline__ void run_item(char *lds, char *lar, const PItem &it, int rank, int count, const LvlArgs &a) {
@@ -587,7 +590,7 @@ __device__ __forceinline__ void run_item(char *lds, char *lar, const PItem &it, 
       }
       break;
     }
-    case PK_MFMA: task_mfma<PREC>(lds, it, rank, a); break;
+    case PK_MFMA: task_mfma<PREC, !LDSOK>(lds, it, rank, a); break;
     case PK_SPLITSUM: task_splitsum<V>(it, rank, count, a); break;
     case PK_SCALAR: task_scalar<V>(lds, it, rank, a); break;
     case PK_SCALAR_SUM: task_scalar_sum(it, rank, a); break;

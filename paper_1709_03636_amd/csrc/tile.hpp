@@ -302,13 +302,18 @@ __device__ __forceinline__ u32x4 neg_im(u32x4 v) { return v ^ (u32x4){0x80000000
 __device__ __forceinline__ u32x4 swap_ri(u32x4 v) { return (v >> 16) | (v << 16); }
 
 // LDS of the split-BF16 tile: X as [m][k] and Y as [n][k] (transposed)
-// packed pairs, hi and lo parts.
-template <bool XK, bool YK, int BM, int BN>
+// packed pairs, hi and lo parts. DB (one-item launches, whose workgroups
+// have the LDS): two such buffers, stage s + 1 written into one while stage
+// s is read from the other, one barrier per stage and the split of the next
+// stage overlapping the matrix-core work of the current one; else one
+// buffer and two barriers per stage.
+template <bool XK, bool YK, int BM, int BN, bool DB>
 __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t *__restrict__ Al,
                                             uint32_t *__restrict__ Bh, uint32_t *__restrict__ Bl, const float2 *base,
                                             const DOp &op, const DRuns &ru, const int32_t *__restrict__ tab, int tile,
                                             int kb, int ke, float2 *__restrict__ Z) {
   using T = TileT<BM, BN>;
+  constexpr int BUF = (2 * BM + 2 * BN) * T::PS;  // words of one buffer (the four planes)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // a free index narrower than its tile side is one padded tile: rows /
   // columns past it read aliased operand entries and are not written
@@ -328,36 +333,35 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
   const int wr = (wave / T::GN) * 16 * T::WM, wc = (wave % T::GN) * 16 * T::WN;
   const int lr = lane & 15, lg = lane >> 4;  // operand row/col, group of 4 complex summed entries
 
-  const int S = (ke - kb) / BK;  // a power of two
-  sg.first(X, Y, kb);
-  for (int st = 0; st < S; ++st) {
-    __syncthreads();
+  // the staged stage (registers) split into buffer b
+  auto write = [&](int b) {
 #pragma unroll
     for (int i = 0; i < T::NX; ++i) {
       uint32_t h, l;
       split_pack(sg.xv[i], h, l);
-      Ah[sg.xs[i]] = h;
-      Al[sg.xs[i]] = l;
+      Ah[b * BUF + sg.xs[i]] = h;
+      Al[b * BUF + sg.xs[i]] = l;
     }
 #pragma unroll
     for (int i = 0; i < T::NY; ++i) {
       uint32_t h, l;
       split_pack(sg.yv[i], h, l);
-      Bh[sg.ys[i]] = h;
-      Bl[sg.ys[i]] = l;
+      Bh[b * BUF + sg.ys[i]] = h;
+      Bl[b * BUF + sg.ys[i]] = l;
     }
-    __syncthreads();
-    if (st + 1 < S) sg.next(st + 1);
+  };
+  // the products of the stage in buffer b
+  auto compute = [&](int b) {
     u32x4 ah[T::WM], al[T::WM], bh[T::WN], bl[T::WN];
 #pragma unroll
     for (int i = 0; i < T::WM; ++i) {
-      ah[i] = *reinterpret_cast<const u32x4 *>(&Ah[(wr + 16 * i + lr) * T::PS + 4 * lg]);
-      al[i] = *reinterpret_cast<const u32x4 *>(&Al[(wr + 16 * i + lr) * T::PS + 4 * lg]);
+      ah[i] = *reinterpret_cast<const u32x4 *>(&Ah[b * BUF + (wr + 16 * i + lr) * T::PS + 4 * lg]);
+      al[i] = *reinterpret_cast<const u32x4 *>(&Al[b * BUF + (wr + 16 * i + lr) * T::PS + 4 * lg]);
     }
 #pragma unroll
     for (int j = 0; j < T::WN; ++j) {
-      bh[j] = *reinterpret_cast<const u32x4 *>(&Bh[(wc + 16 * j + lr) * T::PS + 4 * lg]);
-      bl[j] = *reinterpret_cast<const u32x4 *>(&Bl[(wc + 16 * j + lr) * T::PS + 4 * lg]);
+      bh[j] = *reinterpret_cast<const u32x4 *>(&Bh[b * BUF + (wc + 16 * j + lr) * T::PS + 4 * lg]);
+      bl[j] = *reinterpret_cast<const u32x4 *>(&Bl[b * BUF + (wc + 16 * j + lr) * T::PS + 4 * lg]);
     }
 #pragma unroll
     for (int i = 0; i < T::WM; ++i) {
@@ -375,6 +379,31 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
         cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, bih, cim[i][j], 0, 0, 0);
       }
     }
+  };
+
+  const int S = (ke - kb) / BK;  // a power of two
+  sg.first(X, Y, kb);
+  if constexpr (DB) {
+    write(0);
+    if (S > 1) sg.next(1);
+    __syncthreads();
+    for (int st = 0; st < S; ++st) {
+      const int b = st & 1;
+      compute(b);
+      if (st + 1 < S) {
+        write(b ^ 1);  // the other buffer's last readers passed the barrier that ended stage st - 1
+        if (st + 2 < S) sg.next(st + 2);
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int st = 0; st < S; ++st) {
+      __syncthreads();
+      write(0);
+      __syncthreads();
+      if (st + 1 < S) sg.next(st + 1);
+      compute(0);
+    }
   }
   const int N = 1 << op.nFY, M = 1 << op.nFX;
 #pragma unroll
@@ -390,17 +419,18 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
 }
 
 // One tile of any precision over summed entries [kb, ke), staged through
-// the LDS at `lds` (kTileLds bytes, 16-byte aligned); base: the parameter
+// the LDS at `lds` (kTileLds bytes, 16-byte aligned; twice that with DB,
+// which double-buffers the split-BF16 tile); base: the parameter
 // vector's arena slice (complex128 for TN_MFMA_FP64, else complex64); z:
 // where the M x N result goes.
-template <int PREC, bool XK, bool YK, int BM, int BN>
+template <int PREC, bool XK, bool YK, int BM, int BN, bool DB = false>
 __device__ __forceinline__ void any_tile(char *lds, const void *base, const DOp &op, const DRuns &ru,
                                          const int32_t *__restrict__ tab, int tile, int kb, int ke, void *z) {
   using T = TileT<BM, BN>;
   if constexpr (PREC == TN_MFMA_BF16X3) {
     uint32_t *Ah = reinterpret_cast<uint32_t *>(lds), *Al = Ah + BM * T::PS;
     uint32_t *Bh = Al + BM * T::PS, *Bl = Bh + BN * T::PS;
-    bf16x3_tile<XK, YK, BM, BN>(Ah, Al, Bh, Bl, (const float2 *)base, op, ru, tab, tile, kb, ke, (float2 *)z);
+    bf16x3_tile<XK, YK, BM, BN, DB>(Ah, Al, Bh, Bl, (const float2 *)base, op, ru, tab, tile, kb, ke, (float2 *)z);
   } else if constexpr (PREC == TN_MFMA_FP64) {
     double2 *As = reinterpret_cast<double2 *>(lds), *Bs = As + BM * T::AS;
     c4m_tile<double2, XK, YK, BM, BN>(As, Bs, (const double2 *)base, op, ru, tab, tile, kb, ke, (double2 *)z);
