@@ -764,6 +764,25 @@ static bool packed_tab(const ItemCtx &c, const DOp &op, int32_t &px, int32_t &py
   return true;
 }
 
+// Bit positions of a matrix-core op's per-summed-bit offsets (the table
+// entries of the single bits, as the tiles read them) into w[0..5] (X in
+// w[0..2], Y in w[3..5], 5 bits each, six per word), when every one is a
+// power of two and nS <= 18.
+static bool mfma_packed_bits(const ItemCtx &c, const DOp &op, int32_t *w) {
+  if (!c.tabs || op.nS > 18) return false;
+  int32_t v[6] = {0, 0, 0, 0, 0, 0};
+  const int lo = std::min(op.nS, kTabLoBits);
+  for (int t = 0; t < op.nS; ++t) {
+    const int64_t e = t < kTabLoBits ? (int64_t)2 << t : ((int64_t)2 << lo) + ((int64_t)2 << (t - kTabLoBits));
+    const int32_t ox = (*c.tabs)[op.tab + e], oy = (*c.tabs)[op.tab + e + 1];
+    if (ox <= 0 || oy <= 0 || (ox & (ox - 1)) || (oy & (oy - 1))) return false;
+    v[t / 6] |= __builtin_ctz((uint32_t)ox) << (5 * (t % 6));
+    v[3 + t / 6] |= __builtin_ctz((uint32_t)oy) << (5 * (t % 6));
+  }
+  std::copy(v, v + 6, w);
+  return true;
+}
+
 // --- level items ------------------------------------------------------------------------------
 
 // Runs of up to four consecutive record items whose contractions (or leaf
@@ -899,6 +918,7 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
       it.kind = PK_MFMA;
       const int shape = level_tile(c, op);
       it.mv = mfma_variant(op, prec, shape);
+      if (mfma_packed_bits(c, op, &it.a0)) it.mv |= kMfmaPacked;
       const int64_t wg = (int64_t)mfma_tiles(op, shape) * n_sets;
       const int64_t part = (int64_t)n_sets << (op.nFX + op.nFY);  // elements per range
       int ls = 0;

@@ -188,6 +188,11 @@ struct PItem {
 // which clears it there instead of in the region; FINISH (mv = 1) then reads
 // the accumulator of region offset goff at LDS a3 + goff - zs.
 constexpr int kLdsX = 1, kLdsY = 2, kLdsZ = 4, kPackedTab = 8;
+// A MFMA item's mv bit kMfmaPacked (bits 0-3: tile variant, 4-5:
+// precision): every summed bit's X and Y offset is a power of two, and a0 ..
+// a5 hold their bit positions (5 bits each, six per word; X in a0 .. a2, Y
+// in a3 .. a5), read instead of the offset table; nS <= 18.
+constexpr int kMfmaPacked = 64;
 constexpr int kMaxRunSteps = 96;  // steps of one PK_TREC item (2 bits each in a0 .. a5)
 // LDS of a matrix-core tile (the largest, 64 x 64, with 16 summed entries
 // per stage): split-BF16 four 64-row planes of 20 dwords; FP32 / FP64 the

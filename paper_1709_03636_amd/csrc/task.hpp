@@ -351,7 +351,8 @@ __device__ __forceinline__ void task_mfma_t(char *lds, const PItem &it, int rank
   char *z = ls == 0 ? base + (int64_t)op.z * eb
                     : (char *)a.split + (it.zs + ((((int64_t)set << ls) + part) << (op.nFX + op.nFY))) * eb;
   // one-item launches (the item kernel) have LDS for two tile buffers
-  any_tile<PREC, XK, YK, BM, BN, DB>(lds, base, op, it.ru, a.tabs + op.tab, tile, part << kl, (part + 1) << kl, z);
+  const int32_t *pk = (it.mv & kMfmaPacked) ? &it.a0 : nullptr;  // a0 .. a5: packed summed-bit positions
+  any_tile<PREC, XK, YK, BM, BN, DB>(lds, base, op, it.ru, a.tabs + op.tab, pk, tile, part << kl, (part + 1) << kl, z);
 }
 
 // Kernel variant of a matrix-core item: bit 0 XK (X's lowest address bit is

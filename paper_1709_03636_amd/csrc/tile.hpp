@@ -109,10 +109,24 @@ struct Stager {
   uint32_t xrow[T::NX], ycol[T::NY];
   V xv[T::NX], yv[T::NY];
   int bx, by;  // lane t < nS: the X / Y offset of summed bit t
-  __device__ __forceinline__ Stager(const DOp &op, const DRuns &ru, const int32_t *tab, int m0, int n0) {
+  // pk: null, or the bit positions of those offsets (each a power of two),
+  // 5 bits per summed bit, six per word, X in pk[0..2] and Y in pk[3..5]:
+  // no table read before the first stage's loads
+  __device__ __forceinline__ Stager(const DOp &op, const DRuns &ru, const int32_t *tab, const int32_t *pk, int m0,
+                                    int n0) {
     const int tid = threadIdx.x, lane = tid & 63;
     bx = by = 0;
-    if (lane < op.nS) {
+    if (pk) {
+      int w[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) w[i] = __builtin_amdgcn_readfirstlane(pk[i]);
+      const int q = lane / 6, r = 5 * (lane - 6 * q);
+      const int wx = q == 0 ? w[0] : q == 1 ? w[1] : w[2], wy = q == 0 ? w[3] : q == 1 ? w[4] : w[5];
+      if (lane < op.nS) {
+        bx = 1 << ((wx >> r) & 31);
+        by = 1 << ((wy >> r) & 31);
+      }
+    } else if (lane < op.nS) {
       const int lo = op.nS < kTabLoBits ? op.nS : kTabLoBits;
       const int32_t *e = lane < kTabLoBits ? tab + (2 << lane) : tab + (2 << lo) + (2 << (lane - kTabLoBits));
       bx = e[0];
@@ -202,8 +216,8 @@ struct Stager {
 // (row-major M x N).
 template <typename V, bool XK, bool YK, int BM, int BN>
 __device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs, const V *base, const DOp &op,
-                                         const DRuns &ru, const int32_t *__restrict__ tab, int tile, int kb, int ke,
-                                         V *__restrict__ Z) {
+                                         const DRuns &ru, const int32_t *__restrict__ tab, const int32_t *pk, int tile,
+                                         int kb, int ke, V *__restrict__ Z) {
   using T = TileT<BM, BN>;
   using R = typename Acc4<V>::R;
   using A4 = typename Acc4<V>::type;
@@ -214,7 +228,7 @@ __device__ __forceinline__ void c4m_tile(V *__restrict__ As, V *__restrict__ Bs,
   const int n0 = (tile & ((1 << sy) - 1)) * BN, m0 = (tile >> sy) * BM;
   const V *X = base + op.x;
   const V *Y = base + op.y;
-  Stager<XK, YK, BM, BN, V, false, T::AS, 1, T::BS, 1> sg(op, ru, tab, m0, n0);
+  Stager<XK, YK, BM, BN, V, false, T::AS, 1, T::BS, 1> sg(op, ru, tab, pk, m0, n0);
   A4 cre[T::WM][T::WN], cim[T::WM][T::WN];
 #pragma unroll
   for (int i = 0; i < T::WM; ++i)
@@ -310,8 +324,8 @@ __device__ __forceinline__ u32x4 swap_ri(u32x4 v) { return (v >> 16) | (v << 16)
 template <bool XK, bool YK, int BM, int BN, bool DB>
 __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t *__restrict__ Al,
                                             uint32_t *__restrict__ Bh, uint32_t *__restrict__ Bl, const float2 *base,
-                                            const DOp &op, const DRuns &ru, const int32_t *__restrict__ tab, int tile,
-                                            int kb, int ke, float2 *__restrict__ Z) {
+                                            const DOp &op, const DRuns &ru, const int32_t *__restrict__ tab,
+                                            const int32_t *pk, int tile, int kb, int ke, float2 *__restrict__ Z) {
   using T = TileT<BM, BN>;
   constexpr int BUF = (2 * BM + 2 * BN) * T::PS;  // words of one buffer (the four planes)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -321,7 +335,7 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
   const int n0 = (tile & ((1 << sy) - 1)) * BN, m0 = (tile >> sy) * BM;
   const float2 *X = base + op.x;
   const float2 *Y = base + op.y;
-  Stager<XK, YK, BM, BN, float2, true, T::PS, 1, 1, T::PS> sg(op, ru, tab, m0, n0);
+  Stager<XK, YK, BM, BN, float2, true, T::PS, 1, 1, T::PS> sg(op, ru, tab, pk, m0, n0);
   mf4 cre[T::WM][T::WN], cim[T::WM][T::WN];
 #pragma unroll
   for (int i = 0; i < T::WM; ++i)
@@ -420,23 +434,25 @@ __device__ __forceinline__ void bf16x3_tile(uint32_t *__restrict__ Ah, uint32_t 
 
 // One tile of any precision over summed entries [kb, ke), staged through
 // the LDS at `lds` (kTileLds bytes, 16-byte aligned; twice that with DB,
-// which double-buffers the split-BF16 tile); base: the parameter
+// which double-buffers the split-BF16 tile); pk: the packed summed-bit
+// positions, or null for the offset table; base: the parameter
 // vector's arena slice (complex128 for TN_MFMA_FP64, else complex64); z:
 // where the M x N result goes.
 template <int PREC, bool XK, bool YK, int BM, int BN, bool DB = false>
 __device__ __forceinline__ void any_tile(char *lds, const void *base, const DOp &op, const DRuns &ru,
-                                         const int32_t *__restrict__ tab, int tile, int kb, int ke, void *z) {
+                                         const int32_t *__restrict__ tab, const int32_t *pk, int tile, int kb, int ke,
+                                         void *z) {
   using T = TileT<BM, BN>;
   if constexpr (PREC == TN_MFMA_BF16X3) {
     uint32_t *Ah = reinterpret_cast<uint32_t *>(lds), *Al = Ah + BM * T::PS;
     uint32_t *Bh = Al + BM * T::PS, *Bl = Bh + BN * T::PS;
-    bf16x3_tile<XK, YK, BM, BN, DB>(Ah, Al, Bh, Bl, (const float2 *)base, op, ru, tab, tile, kb, ke, (float2 *)z);
+    bf16x3_tile<XK, YK, BM, BN, DB>(Ah, Al, Bh, Bl, (const float2 *)base, op, ru, tab, pk, tile, kb, ke, (float2 *)z);
   } else if constexpr (PREC == TN_MFMA_FP64) {
     double2 *As = reinterpret_cast<double2 *>(lds), *Bs = As + BM * T::AS;
-    c4m_tile<double2, XK, YK, BM, BN>(As, Bs, (const double2 *)base, op, ru, tab, tile, kb, ke, (double2 *)z);
+    c4m_tile<double2, XK, YK, BM, BN>(As, Bs, (const double2 *)base, op, ru, tab, pk, tile, kb, ke, (double2 *)z);
   } else {
     float2 *As = reinterpret_cast<float2 *>(lds), *Bs = As + BM * T::AS;
-    c4m_tile<float2, XK, YK, BM, BN>(As, Bs, (const float2 *)base, op, ru, tab, tile, kb, ke, (float2 *)z);
+    c4m_tile<float2, XK, YK, BM, BN>(As, Bs, (const float2 *)base, op, ru, tab, pk, tile, kb, ke, (float2 *)z);
   }
 }
 
