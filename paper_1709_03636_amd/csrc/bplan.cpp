@@ -986,8 +986,8 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
       if (thin) {
         // lanes per output: at least 8 summed entries each, up to 64, while
         // the step has fewer than 2^20 (output, lane) pairs (one workgroup:
-        // 2^10, four per thread)
-        const int lg_fill = c.one_wg ? 10 : 20, lg_four = c.one_wg ? 10 : 16;
+        // 2^8, one per thread; measured against 2^6 .. 2^11)
+        const int lg_fill = c.one_wg ? 8 : 20, lg_four = c.one_wg ? 10 : 16;
         it.lgl = std::max(0, std::min({6, op.nS - 3, lg_fill - lg - lgs}));
         work <<= it.lgl;
         // many outputs: four per lane instead (shared operand reads)
