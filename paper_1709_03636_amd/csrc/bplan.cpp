@@ -986,9 +986,10 @@ void network_items(const ItemCtx &c, const LevelNet &ln, int v, int n_sets, int6
       if (thin) {
         // lanes per output: at least 8 summed entries each, up to 64, while
         // the step has fewer than 2^20 (output, lane) pairs (one workgroup:
-        // 2^8, one per thread; measured against 2^6 .. 2^11)
+        // at least 2 entries each and 2^8 pairs, one per thread; measured
+        // against 1 .. 16 entries and 2^6 .. 2^11 pairs)
         const int lg_fill = c.one_wg ? 8 : 20, lg_four = c.one_wg ? 10 : 16;
-        it.lgl = std::max(0, std::min({6, op.nS - 3, lg_fill - lg - lgs}));
+        it.lgl = std::max(0, std::min({6, op.nS - (c.one_wg ? 1 : 3), lg_fill - lg - lgs}));
         work <<= it.lgl;
         // many outputs: four per lane instead (shared operand reads)
         if (it.lgl == 0 && lg + lgs >= lg_four && (op.nFY >= 2 || (op.nFY == 0 && op.nB == 0 && op.nFX >= 8))) {
