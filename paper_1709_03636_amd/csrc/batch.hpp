@@ -111,6 +111,7 @@ struct LevelGroup {
   int tnet0 = 0;                                    // task executor: into tn_batch::tnets[variant]
 };
 constexpr int kTaskMin = 512;  // (network, vector) pairs a group needs for the task executor
+constexpr double kGmemJoinMacs = 6e6;  // global-arena work (per vector) that joins the task executor alone
 
 // Workspace layout: byte offsets of every device array of the batch.
 struct WsLayout {

@@ -1224,12 +1224,19 @@ int plan_batch(tn_net *const *nets, int n_nets, const double *coef, double offse
   int maxbits = 0;
   // executor of each network: the LDS fused executor when its memory fits
   // LDS, the global-arena fused executor when its steps are small enough for
-  // one workgroup, else the level executor. When the level networks are many
-  // enough for the task executor anyway, the global-arena ones join them
-  // there (one launch, LDS-resident small tensors, matrix cores for the few
-  // large steps; measured faster on the 5-regular p=2 batches).
+  // one workgroup, else the level executor. The global-arena networks join
+  // the level ones on the task executor (one launch, LDS-resident small
+  // tensors, matrix cores for the few large steps) when the level networks
+  // are enough for it anyway (measured faster on the 5-regular p=2 batches),
+  // or when the global-arena ones are enough for it and hold at least
+  // kGmemJoinMacs multiply-adds per parameter vector in all (measured on the
+  // p=2 batches: 4-regular n=70 and n=100 6.4 -> 3.1 and 6.7 -> 4.1 ms, the
+  // 5-regular n=50 diagonal one 5.1 -> 3.8 ms; below it the global-arena
+  // executor stayed faster, e.g. 4.0 against 5.6 ms on the 5-regular n=100
+  // diagonal batch, 3.4e6 multiply-adds).
   std::vector<int> cls(n_nets);
   int n_level = 0, n_gmem = 0;
+  double gmem_macs = 0;  // multiply-adds of the global-arena networks, one parameter vector
   for (int i = 0; i < n_nets; ++i) {
     const Net *n = reinterpret_cast<const Net *>(nets[i]);
     NetLayout lay = make_layout(*n);
@@ -1250,10 +1257,13 @@ int plan_batch(tn_net *const *nets, int n_nets, const double *coef, double offse
       cls[i] = 1;
     n_level += cls[i] == 1;
     n_gmem += cls[i] == 2;
+    if (cls[i] == 2) gmem_macs += tot_macs;
   }
   bool join = true;  // QTN_GMEM_JOIN=0 keeps them on the global-arena executor
   if (const char *env = std::getenv("QTN_GMEM_JOIN")) join = std::atoi(env) != 0;
-  if (join && n_gmem > 0 && (int64_t)n_level * max_sets >= b->task_min)
+  if (join && n_gmem > 0 &&
+      ((int64_t)n_level * max_sets >= b->task_min ||
+       ((int64_t)n_gmem * max_sets >= b->task_min && gmem_macs >= kGmemJoinMacs)))
     for (int &c : cls)
       if (c == 2) c = 1;
   for (int i = 0; i < n_nets; ++i) {
