@@ -22,8 +22,12 @@ namespace qtn {
 constexpr int kLdsCap = 160 * 1024;
 // Networks whose fused adjoint program needs more LDS than this run on the
 // global-arena or level executor, so one large network does not lower the
-// occupancy of all: at most 48 KiB keeps three workgroups per CU.
-constexpr int64_t kFusedLdsMax = 48 * 1024;
+// occupancy of all (the fused launch takes the largest program's LDS).
+// Measured on the p=2 batches of 64 angle sets against 48 and 24 KiB: 32
+// KiB was fastest on all but the 5-regular n=100 diagonal one (4-regular
+// n=70 dense 3.1 -> 2.7 ms and diagonal 2.3 -> 1.0 ms; 3-regular n=60
+// 0.68 -> 0.55 ms; 5-regular n=100 diagonal 4.1 -> 5.0 ms).
+constexpr int64_t kFusedLdsMax = 32 * 1024;
 // Level arena budget: the networks of one group share it (more networks per
 // launch, fewer groups one after another); a network alone
 // processes its parameter vectors in chunks that fit. 32 GiB of the 288 GB.
