@@ -28,6 +28,7 @@ constexpr int kLdsCap = 160 * 1024;
 // n=70 dense 3.1 -> 2.7 ms and diagonal 2.3 -> 1.0 ms; 3-regular n=60
 // 0.68 -> 0.55 ms; 5-regular n=100 diagonal 4.1 -> 5.0 ms).
 constexpr int64_t kFusedLdsMax = 32 * 1024;
+constexpr int64_t kFusedLdsMaxHi = 48 * 1024;  // kept for some batches (plan_batch): three workgroups per CU
 // Level arena budget: the networks of one group share it (more networks per
 // launch, fewer groups one after another); a network alone
 // processes its parameter vectors in chunks that fit. 32 GiB of the 288 GB.

@@ -1211,7 +1211,9 @@ int plan_batch(tn_net *const *nets, int n_nets, const double *coef, double offse
   // QTN_FUSED_LDS_MAX (bytes) overrides the LDS-fused limit, e.g. 0 sends
   // every network to the global-arena or level executor
   int64_t fused_max = kFusedLdsMax;
-  if (const char *env = std::getenv("QTN_FUSED_LDS_MAX")) fused_max = std::atoll(env);
+  const char *fused_env = std::getenv("QTN_FUSED_LDS_MAX");
+  const bool fused_max_set = fused_env != nullptr;
+  if (fused_env) fused_max = std::atoll(fused_env);
   int64_t gmem_max = kGmemMaxMacs;  // QTN_GMEM_MAX_MACS=0 turns the global-arena executor off
   if (const char *env = std::getenv("QTN_GMEM_MAX_MACS")) gmem_max = std::atoll(env);
   int64_t level_budget = kLevelBudget;  // QTN_LEVEL_BUDGET (bytes): level arena limit
@@ -1234,36 +1236,60 @@ int plan_batch(tn_net *const *nets, int n_nets, const double *coef, double offse
   // 5-regular n=50 diagonal one 5.1 -> 3.8 ms; below it the global-arena
   // executor stayed faster, e.g. 4.0 against 5.6 ms on the 5-regular n=100
   // diagonal batch, 3.4e6 multiply-adds).
-  std::vector<int> cls(n_nets);
-  int n_level = 0, n_gmem = 0;
-  double gmem_macs = 0;  // multiply-adds of the global-arena networks, one parameter vector
-  for (int i = 0; i < n_nets; ++i) {
-    const Net *n = reinterpret_cast<const Net *>(nets[i]);
-    NetLayout lay = make_layout(*n);
-    double max_macs = 0, tot_macs = 0;
-    for (const Op &op : n->gplan.ops)
-      if (op.type == OP_CONTRACT || op.type == OP_SCALAR) {
-        const double m = std::ldexp(1.0, op.nFX + op.nB + op.nS + op.nFY);
-        max_macs = std::max(max_macs, m);
-        tot_macs += m;
-      }
-    const int64_t mem_elems = lay.leaf_region + std::max(lay.arena[0], lay.arena[1]);
-    if (fused_lds_need(*n, lay, eb, b->n_params) <= fused_max)
-      cls[i] = 0;
-    else if (tot_macs <= (double)gmem_max && max_macs <= (double)gmem_max / 16 && mem_elems < kMaxArenaElems &&
-             mem_elems * eb <= kGmemBudget / 256)
-      cls[i] = 2;
-    else
-      cls[i] = 1;
-    n_level += cls[i] == 1;
-    n_gmem += cls[i] == 2;
-    if (cls[i] == 2) gmem_macs += tot_macs;
-  }
+  struct Classes {
+    std::vector<int> cls;
+    int n_level = 0, n_gmem = 0;
+    double gmem_macs = 0;  // multiply-adds of the global-arena networks, one parameter vector
+  };
+  auto classify = [&](int64_t fmax) {
+    Classes k;
+    k.cls.resize(n_nets);
+    for (int i = 0; i < n_nets; ++i) {
+      const Net *n = reinterpret_cast<const Net *>(nets[i]);
+      NetLayout lay = make_layout(*n);
+      double max_macs = 0, tot_macs = 0;
+      for (const Op &op : n->gplan.ops)
+        if (op.type == OP_CONTRACT || op.type == OP_SCALAR) {
+          const double m = std::ldexp(1.0, op.nFX + op.nB + op.nS + op.nFY);
+          max_macs = std::max(max_macs, m);
+          tot_macs += m;
+        }
+      const int64_t mem_elems = lay.leaf_region + std::max(lay.arena[0], lay.arena[1]);
+      int &c = k.cls[i];
+      if (fused_lds_need(*n, lay, eb, b->n_params) <= fmax)
+        c = 0;
+      else if (tot_macs <= (double)gmem_max && max_macs <= (double)gmem_max / 16 && mem_elems < kMaxArenaElems &&
+               mem_elems * eb <= kGmemBudget / 256)
+        c = 2;
+      else
+        c = 1;
+      k.n_level += c == 1;
+      k.n_gmem += c == 2;
+      if (c == 2) k.gmem_macs += tot_macs;
+    }
+    return k;
+  };
   bool join = true;  // QTN_GMEM_JOIN=0 keeps them on the global-arena executor
   if (const char *env = std::getenv("QTN_GMEM_JOIN")) join = std::atoi(env) != 0;
-  if (join && n_gmem > 0 &&
-      ((int64_t)n_level * max_sets >= b->task_min ||
-       ((int64_t)n_gmem * max_sets >= b->task_min && gmem_macs >= kGmemJoinMacs)))
+  // the global-arena networks join the task executor because the level ones are enough
+  // for it (1), or because they hold enough work themselves (2)
+  auto joins = [&](const Classes &k) {
+    if (!join || k.n_gmem == 0) return 0;
+    if ((int64_t)k.n_level * max_sets >= b->task_min) return 1;
+    return (int64_t)k.n_gmem * max_sets >= b->task_min && k.gmem_macs >= kGmemJoinMacs ? 2 : 0;
+  };
+  Classes k = classify(fused_max);
+  // Networks between the fused limit and kFusedLdsMaxHi stay on the fused
+  // executor when moving them only sends light global-arena networks to the
+  // task executor (measured: the 5-regular n=100 p=2 diagonal batch 5.4 ms
+  // with them moved, 4.1 ms kept; the batches whose networks move to the
+  // level or global-arena executor otherwise run faster moved)
+  if (!fused_max_set && fused_max < kFusedLdsMaxHi && joins(k) == 2) {
+    Classes hi = classify(kFusedLdsMaxHi);
+    if (joins(hi) == 0) k = std::move(hi);
+  }
+  std::vector<int> &cls = k.cls;
+  if (joins(k))
     for (int &c : cls)
       if (c == 2) c = 1;
   for (int i = 0; i < n_nets; ++i) {
